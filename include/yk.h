@@ -1,0 +1,188 @@
+/*
+ * yk.h -- C ABI of libyk, an MI355X (gfx950) implementation of one implicit
+ * time step of the 2-D heat equation done as a modified Helmholtz (Yukawa)
+ * solve, after Kropinski & Quaife, "Fast integral equation methods for the
+ * heat equation and the modified Helmholtz equation in two dimensions"
+ * (arXiv 1007.5335).
+ *
+ * General conventions
+ *  - Every array argument is a DEVICE pointer to FP64 data unless marked
+ *    HOST.  The caller owns all arrays; the library owns only its context,
+ *    its cached trees/operator tables and its workspace.  Inputs and outputs
+ *    must not alias.
+ *  - Points are interleaved [n][2] (x, y).  Curve 0 of a boundary is the outer
+ *    curve, traversed counter-clockwise; holes are traversed clockwise; the
+ *    unit normals point out of the domain on every curve; the curvature is
+ *    signed (+1/R on a counter-clockwise circle).
+ *  - Kernel normalisation of the sums (Sec. 2): the library sums carry
+ *    K0(|x-y|/alpha)/(2 pi), i.e. the Green's function G = K0/(2 pi alpha^2)
+ *    without its 1/alpha^2; the heat step applies that factor itself.
+ *  - Errors are returned as status codes; no C++ exception crosses the ABI.
+ *    Arguments are checked before any work; on YK_ERR_ARG outputs are left
+ *    untouched.  yk_last_error() returns a per-context message.
+ *  - All work is ordered on the context's stream (yk_set_stream).  The two
+ *    sum entry points are asynchronous; the solver entry points synchronise
+ *    the stream, because GMRES reads residual scalars on the host.
+ *  - A context is not thread-safe; use one per host thread.
+ *  - Trees and operator tables are cached per context, keyed by the point
+ *    arrays' addresses and sizes and by alpha.  After changing point
+ *    coordinates in place, call yk_invalidate_geometry().
+ */
+#ifndef YK_H
+#define YK_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct yk_ctx_s *yk_ctx;
+
+typedef enum {
+    YK_OK = 0,
+    YK_ERR_ARG = -1,        /* invalid argument (null pointer, n <= 0, alpha <= 0, ...) */
+    YK_ERR_HIP = -2,        /* a HIP runtime call failed */
+    YK_ERR_NOMEM = -3,      /* device or host allocation failed */
+    YK_ERR_NOCONV = -4,     /* GMRES hit max_iter; the best iterate is written */
+    YK_ERR_NONFINITE = -5,  /* a residual or a result became NaN/Inf */
+    YK_ERR_INTERNAL = -6
+} yk_status;
+
+enum {
+    YK_PREC_FP64 = 0,       /* every sum in FP64 */
+    YK_PREC_MIXED = 1,      /* FP32 sums inside GMRES, FP64 outer residual and volume pass */
+    YK_PREC_FP32 = 2        /* as MIXED, and the volume pass in FP32 too */
+};
+
+typedef struct {
+    int precision;          /* YK_PREC_* */
+    double fmm_tol;         /* target relative accuracy of the sums; picks p when p == 0 */
+    int p;                  /* expansion order (terms -p..p); 0 = derived from fmm_tol */
+    int leaf_size;          /* target mean number of points per leaf box */
+    int direct;             /* 1 = all sums by O(N^2) direct summation */
+    int gmres_m;            /* Krylov dimension before a restart */
+    int debug_flags;        /* bit0: synchronise and check after every kernel */
+} yk_options;
+
+typedef struct {
+    int32_t n_curves;             /* >= 1; curve 0 outer, 1.. holes */
+    const int64_t *offset;        /* HOST [n_curves + 1]; N_k = offset[k+1] - offset[k] */
+    const double *xy;             /* [N][2] nodes y_j, N equispaced in each curve's parameter */
+    const double *normal;         /* [N][2] unit normals, outward from the domain */
+    const double *speed;          /* [N] |y'(theta_j)|; weights w_j = (2 pi / N_k) speed_j */
+    const double *curvature;      /* [N] signed curvature kappa_j */
+} yk_boundary;
+
+typedef struct {
+    int iters;               /* total GMRES iterations (inner ones in mixed precision) */
+    int outer_iters;         /* refinement sweeps (mixed precision), else 0 */
+    int guess_used;          /* 0 zero, 1 caller's guess, 2 learned guess */
+    int matvecs;             /* operator applications */
+    double res0;             /* ||b - A x0|| / ||b|| */
+    double res_final;        /* ||b - A x|| / ||b|| (true residual, FP64) */
+    double ms[8];            /* stage times: 0 tree, 1 volume->nodes, 2 solve,
+                                3 volume+layer->volume, 4 guess, 5-7 spare */
+} yk_stats;
+
+/* Fills *opt with defaults: FP64, fmm_tol 1e-10, p 0, leaf_size 64,
+ * direct 0, gmres_m 60, debug_flags 0. */
+void yk_default_options(yk_options *opt);
+
+/* Creates a context on the current HIP device.  opt may be NULL (defaults). */
+yk_status yk_create(const yk_options *opt, yk_ctx *out);
+yk_status yk_destroy(yk_ctx ctx);
+/* Binds the context to a hipStream_t (NULL = the null stream). */
+yk_status yk_set_stream(yk_ctx ctx, void *hip_stream);
+/* Replaces the options; cached trees are dropped when p/leaf_size change. */
+yk_status yk_set_options(yk_ctx ctx, const yk_options *opt);
+const char *yk_last_error(yk_ctx ctx);
+/* Drops every cached tree and operator table. */
+yk_status yk_invalidate_geometry(yk_ctx ctx);
+
+/*
+ * Volume potential as a weighted point sum (Sec. 2, eq. vol_potential; Sec. 3.1
+ * evaluates it with an FMM):
+ *   out[i] = sum_{j : |t_i - s_j| > 0} q[j] K0(|t_i - s_j| / alpha) / (2 pi).
+ * tgt_xy == NULL means targets are the sources (n_tgt ignored); the self pair
+ * is then skipped, and so is any pair of coincident points.
+ * src_xy [n_src][2], q [n_src], tgt_xy [n_tgt][2], out [n_tgt or n_src].
+ */
+yk_status yk_volume_potential(yk_ctx ctx, int64_t n_src, const double *src_xy, const double *q,
+                              int64_t n_tgt, const double *tgt_xy, double alpha, double *out);
+
+/*
+ * Double-layer potential (Sec. 2, the representation of U^h, without 1/alpha^2):
+ *   out[i] = sum_j w_j sigma_j D(t_i, y_j) / (2 pi),
+ *   D(x, y) = d/dnu_y K0(|x - y|/alpha) = (1/alpha) K1(r/alpha) (x - y).n_y / r,
+ *   w_j = (2 pi / N_k) speed_j.
+ * tgt_xy == NULL evaluates on the curve at the nodes (n_tgt ignored, out has
+ * N entries), with the diagonal term w_j (-kappa_j / 2) sigma_j / (2 pi) (the
+ * continuity of the kernel along the curve, Sec. 2); off the curve, pairs at
+ * distance zero are skipped.
+ */
+yk_status yk_double_layer_apply(yk_ctx ctx, const yk_boundary *bnd, const double *sigma,
+                                int64_t n_tgt, const double *tgt_xy, double alpha, double *out);
+
+/*
+ * Solves the trapezoid discretisation of the second-kind equation
+ * (eq. dirichlet:inteqn multiplied by -2 alpha^2; Sec. 3.2, eq. discrete_sys):
+ *   sigma_j - 2 * DL[w sigma](y_j) = -2 alpha^2 g_j
+ * by GMRES (restarted every gmres_m iterations), stopping when
+ * ||b - A sigma||_2 <= tol ||b||_2.  g [N] Dirichlet data of the homogeneous
+ * problem; sigma0 [N] initial guess or NULL (zero); sigma [N] output.
+ * On YK_ERR_NOCONV the best iterate is written.  stats may be NULL.
+ */
+yk_status yk_gmres_density(yk_ctx ctx, const yk_boundary *bnd, double alpha, const double *g,
+                           const double *sigma0, double tol, int max_iter, double *sigma,
+                           yk_stats *stats);
+
+/*
+ * One backward-Euler step (Sec. 2: alpha^2 = dt, B = u^N + dt F^N), split into
+ * U^p (eq. particular) and U^h (eq. mod_helm_hom):
+ *   q       = vol_w * B
+ *   U^p     = (V[q] + B * C_self) / alpha^2   on volume points and nodes
+ *   g       = f_next - U^p on the nodes
+ *   sigma   solves A sigma = -2 alpha^2 g     (GMRES to tol)
+ *   u_next  = U^p + DL[w sigma] / alpha^2     at every volume point
+ * B [n_vol] must already be extended to every volume point (values outside
+ * the domain are the caller's extension, Sec. 3.1).  vol_w [n_vol] quadrature
+ * weights.  flags bit0: volume points are centres of square cells of area
+ * vol_w, and each gets the integral of the kernel over its own cell,
+ * C_self = (1/2pi) int_cell K0(|y|/alpha) dA, instead of the skipped self pair.
+ * f_next [N] boundary data at t^{N+1}.  sigma_io [N]: in = initial guess,
+ * out = sigma^{N+1}.  flags bit1: ignore sigma_io on input (zero guess).
+ * u_next [n_vol] (meaningful at points inside the domain).
+ */
+yk_status yk_heat_step(yk_ctx ctx, const yk_boundary *bnd, int64_t n_vol, const double *vol_xy,
+                       const double *vol_w, const double *B, int flags, const double *f_next,
+                       double dt, double tol, double *sigma_io, double *u_next, yk_stats *stats);
+
+/*
+ * Right-hand side of the backward-Euler step with the constant extension of
+ * Sec. 3.1 (boundary data constant on each curve):
+ *   B_i = u_i + dt F_i       if region[i] < 0 (inside the domain)
+ *   B_i = c[region[i]]       otherwise (0 = outside the outer curve, k = inside hole k)
+ * u, F [n] device FP64 (F may be NULL = 0); region [n] device int32;
+ * c [n_const] HOST FP64.
+ */
+yk_status yk_rhs_backward_euler(yk_ctx ctx, int64_t n, const double *u, const double *F,
+                                const int32_t *region, int n_const, const double *c,
+                                double dt, double *B);
+
+/*
+ * One full FMM evaluation with charges on the volume points and dipoles on the
+ * nodes, every point a target (the throughput benchmark's pass):
+ *   out_vol[i] = V[q](x_i) + DL[d](x_i),   out_bnd[j] = V[q](y_j) + DL[d](y_j)
+ * with d_j the dipole strength at node j (normal from bnd), self pairs and
+ * coincident pairs skipped, no diagonal term.
+ */
+yk_status yk_fmm_potential(yk_ctx ctx, int64_t n_vol, const double *vol_xy, const double *q,
+                           const yk_boundary *bnd, const double *d, double alpha,
+                           double *out_vol, double *out_bnd);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* YK_H */

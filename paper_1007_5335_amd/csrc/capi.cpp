@@ -1,0 +1,448 @@
+// capi.cpp -- the C ABI of libyk: argument checks, status codes, and the
+// drivers of the solve and of the heat step (Kropinski & Quaife, Sec. 2-3).
+#include <chrono>
+#include <cmath>
+#include <new>
+
+#include "sums.h"
+#include "yk_internal.h"
+
+namespace yk {
+
+void check_launch(Context &ctx, const char *what) {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) throw Error{YK_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e)};
+    if (ctx.opt.debug_flags & 1) {
+        e = hipStreamSynchronize(ctx.stream);
+        if (e != hipSuccess) throw Error{YK_ERR_HIP, std::string(what) + " (sync): " + hipGetErrorString(e)};
+    }
+}
+
+BoundaryData &prepare_boundary(Context &ctx, const yk_boundary *b) {
+    YK_REQUIRE(b != nullptr, "boundary is NULL");
+    YK_REQUIRE(b->n_curves >= 1, "boundary needs at least one curve");
+    YK_REQUIRE(b->offset != nullptr, "boundary offsets are NULL");
+    YK_REQUIRE(b->xy && b->normal && b->speed && b->curvature, "a boundary array is NULL");
+    YK_REQUIRE(b->offset[0] == 0, "boundary offset[0] must be 0");
+    for (int k = 0; k < b->n_curves; ++k)
+        YK_REQUIRE(b->offset[k + 1] > b->offset[k], "boundary offsets must increase strictly");
+    const int64_t n = b->offset[b->n_curves];
+    YK_REQUIRE(n < (int64_t)1 << 31, "too many boundary nodes");
+    BoundaryData *cur = ctx.bnd.get();
+    bool same = cur && cur->xy == b->xy && cur->n == n && cur->n_curves == b->n_curves &&
+                cur->speed == b->speed && cur->normal == b->normal && cur->curvature == b->curvature;
+    if (same)
+        for (int k = 0; k <= b->n_curves; ++k) same = same && cur->offset[k] == b->offset[k];
+    if (same) return *cur;
+    auto nb = std::make_unique<BoundaryData>();
+    nb->xy = b->xy;
+    nb->n = n;
+    nb->n_curves = b->n_curves;
+    nb->offset.assign(b->offset, b->offset + b->n_curves + 1);
+    nb->normal = b->normal;
+    nb->curvature = b->curvature;
+    nb->speed = b->speed;
+    DevBuf<int64_t> off;
+    int64_t *doff = off.ensure(b->n_curves + 1);
+    YK_HIP(hipMemcpyAsync(doff, nb->offset.data(), (b->n_curves + 1) * sizeof(int64_t),
+                          hipMemcpyHostToDevice, ctx.stream));
+    launch_boundary_prep(ctx, n, b->n_curves, doff, b->speed, nb->w.ensure(n), nb->curve.ensure(n),
+                         nb->idx.ensure(n));
+    YK_HIP(hipStreamSynchronize(ctx.stream));
+    ctx.bnd = std::move(nb);
+    // trees that contain the nodes are stale
+    ctx.plan_vol.reset();
+    ctx.plan_bnd.reset();
+    return *ctx.bnd;
+}
+
+void evaluate_sums(Context &ctx, PlanSlot slot, const SumProblem &pb, const double *q,
+                   const double *dn, double *const out[3], SumPrec prec) {
+    if (!ctx.opt.direct) {
+        fmm_evaluate(ctx, slot, pb, q, dn, out, prec);
+        return;
+    }
+    for (int s = 0; s < 3; ++s) {
+        if (!out[s] || pb.n[s] == 0) continue;
+        launch_direct(ctx, pb.n[s], pb.xy[s], q ? pb.n[0] : 0, pb.xy[0], q, dn ? pb.n[1] : 0,
+                      pb.xy[1], dn, pb.alpha, out[s], false);
+    }
+}
+
+namespace {
+
+double ms_since(std::chrono::steady_clock::time_point t0) {
+    return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+}
+
+void check_alpha(double a) { YK_REQUIRE(std::isfinite(a) && a > 0.0, "alpha must be finite and > 0"); }
+
+// Operator of eq. discrete_sys (trapezoid rule): y = x - 2 (DL[w x] + diagonal).
+struct BieOperator {
+    Context &ctx;
+    BoundaryData &bd;
+    double alpha;
+    SumPrec prec;
+    void operator()(const double *x, double *y) const {
+        const int64_t n = bd.n;
+        double *dn = ctx.dn.ensure(2 * n);
+        double *dl = ctx.ws_a.ensure(n);
+        launch_dipole_vectors(ctx, n, bd.w.p, x, bd.normal, 1.0, dn);
+        SumProblem pb;
+        pb.n[1] = n;
+        pb.xy[1] = bd.xy;
+        pb.alpha = alpha;
+        double *const outs[3] = {nullptr, dl, nullptr};
+        evaluate_sums(ctx, SLOT_BND, pb, nullptr, dn, outs, prec);
+        launch_dl_diagonal(ctx, n, bd.w.p, bd.curvature, x, dl);
+        launch_bie_combine(ctx, n, x, dl, y);
+    }
+};
+
+// Solves A sigma = b in FP64, or (mixed) by refinement: FP64 residuals with an
+// FP32-operator GMRES for each correction.
+GmresResult solve_density(Context &ctx, BoundaryData &bd, double alpha, const double *b,
+                          double *sigma, bool zero_guess, double tol, int max_iter, int *outer) {
+    const int64_t n = bd.n;
+    BieOperator A64{ctx, bd, alpha, SUM_FP64};
+    *outer = 0;
+    if (ctx.opt.precision == YK_PREC_FP64 || ctx.opt.direct)
+        return gmres(ctx, A64, n, b, sigma, zero_guess, tol, max_iter, ctx.opt.gmres_m);
+    BieOperator A32{ctx, bd, alpha, SUM_FP32};
+    double *r = ctx.ws_b.ensure(n);
+    double *delta = ctx.ws_c.ensure(n);
+    double *tmp = ctx.ws_d.ensure(n);
+    double *dscal = ctx.scal.ensure(512);
+    auto norm = [&](const double *v) {
+        launch_multi_dot(ctx, n, 1, v, n, v, dscal + 400);
+        double h = 0;
+        YK_HIP(hipMemcpyAsync(&h, dscal + 400, sizeof(double), hipMemcpyDeviceToHost, ctx.stream));
+        YK_HIP(hipStreamSynchronize(ctx.stream));
+        return std::sqrt(h);
+    };
+    GmresResult tot;
+    const double bnorm = norm(b);
+    if (zero_guess) YK_HIP(hipMemsetAsync(sigma, 0, n * sizeof(double), ctx.stream));
+    for (int sweep = 0; sweep < 30; ++sweep) {
+        A64(sigma, tmp);
+        tot.matvecs++;
+        launch_axpby(ctx, n, 1.0, b, -1.0, tmp, r);
+        const double rn = norm(r);
+        if (!std::isfinite(rn)) throw Error{YK_ERR_NONFINITE, "refinement residual is not finite"};
+        if (sweep == 0) tot.res0 = bnorm > 0 ? rn / bnorm : 0.0;
+        tot.res_final = bnorm > 0 ? rn / bnorm : 0.0;
+        if (rn <= tol * bnorm || bnorm == 0.0) {
+            tot.converged = true;
+            break;
+        }
+        if (tot.iters >= max_iter) break;
+        // inner FP32-operator solve to a modest relative tolerance
+        GmresResult in = gmres(ctx, A32, n, r, delta, true, 1e-5, max_iter - tot.iters, ctx.opt.gmres_m);
+        tot.iters += in.iters;
+        tot.matvecs += in.matvecs;
+        launch_axpby(ctx, n, 1.0, sigma, 1.0, delta, sigma);
+        (*outer)++;
+    }
+    return tot;
+}
+
+}  // namespace
+
+}  // namespace yk
+
+using namespace yk;
+
+template <typename F>
+static yk_status guarded(yk_ctx ctx, F &&f) {
+    if (!ctx) return YK_ERR_ARG;
+    try {
+        yk_status s = f(ctx->c);
+        if (s == YK_OK) ctx->c.last_error.clear();
+        return s;
+    } catch (const Error &e) {
+        ctx->c.last_error = e.msg;
+        return e.code;
+    } catch (const std::bad_alloc &) {
+        ctx->c.last_error = "host allocation failed";
+        return YK_ERR_NOMEM;
+    } catch (const std::exception &e) {
+        ctx->c.last_error = e.what();
+        return YK_ERR_INTERNAL;
+    } catch (...) {
+        ctx->c.last_error = "unknown internal error";
+        return YK_ERR_INTERNAL;
+    }
+}
+
+extern "C" {
+
+void yk_default_options(yk_options *opt) {
+    if (!opt) return;
+    opt->precision = YK_PREC_FP64;
+    opt->fmm_tol = 1e-10;
+    opt->p = 0;
+    opt->leaf_size = 64;
+    opt->direct = 0;
+    opt->gmres_m = 60;
+    opt->debug_flags = 0;
+}
+
+static bool valid_options(const yk_options *o) {
+    return o->precision >= 0 && o->precision <= 2 && o->p >= 0 && o->p <= 80 &&
+           o->leaf_size >= 1 && o->leaf_size <= 4096 && o->gmres_m >= 1 && o->gmres_m <= 120 &&
+           (o->p > 0 || (o->fmm_tol > 0 && o->fmm_tol < 1));
+}
+
+yk_status yk_create(const yk_options *opt, yk_ctx *out) {
+    if (!out) return YK_ERR_ARG;
+    *out = nullptr;
+    yk_options o;
+    yk_default_options(&o);
+    if (opt) o = *opt;
+    if (!valid_options(&o)) return YK_ERR_ARG;
+    yk_ctx c = new (std::nothrow) yk_ctx_s();
+    if (!c) return YK_ERR_NOMEM;
+    c->c.opt = o;
+    if (hipGetDevice(&c->c.device) != hipSuccess) {
+        delete c;
+        return YK_ERR_HIP;
+    }
+    *out = c;
+    return YK_OK;
+}
+
+yk_status yk_destroy(yk_ctx ctx) {
+    if (!ctx) return YK_ERR_ARG;
+    (void)hipStreamSynchronize(ctx->c.stream);
+    delete ctx;
+    return YK_OK;
+}
+
+yk_status yk_set_stream(yk_ctx ctx, void *stream) {
+    if (!ctx) return YK_ERR_ARG;
+    ctx->c.stream = (hipStream_t)stream;
+    return YK_OK;
+}
+
+yk_status yk_set_options(yk_ctx ctx, const yk_options *opt) {
+    if (!ctx || !opt || !valid_options(opt)) return YK_ERR_ARG;
+    const yk_options old = ctx->c.opt;
+    ctx->c.opt = *opt;
+    if (old.p != opt->p || old.leaf_size != opt->leaf_size || old.fmm_tol != opt->fmm_tol) {
+        ctx->c.plan_vol.reset();
+        ctx->c.plan_bnd.reset();
+        ctx->c.plan_misc.reset();
+    }
+    return YK_OK;
+}
+
+const char *yk_last_error(yk_ctx ctx) {
+    if (!ctx) return "null context";
+    return ctx->c.last_error.c_str();
+}
+
+yk_status yk_invalidate_geometry(yk_ctx ctx) {
+    return guarded(ctx, [&](Context &c) {
+        YK_HIP(hipStreamSynchronize(c.stream));
+        c.plan_vol.reset();
+        c.plan_bnd.reset();
+        c.plan_misc.reset();
+        c.bnd.reset();
+        return YK_OK;
+    });
+}
+
+yk_status yk_volume_potential(yk_ctx ctx, int64_t n_src, const double *src_xy, const double *q,
+                              int64_t n_tgt, const double *tgt_xy, double alpha, double *out) {
+    return guarded(ctx, [&](Context &c) {
+        YK_REQUIRE(n_src > 0 && src_xy && q && out, "invalid source arguments");
+        YK_REQUIRE(!tgt_xy || n_tgt > 0, "n_tgt must be > 0 when targets are given");
+        check_alpha(alpha);
+        SumProblem pb;
+        pb.n[0] = n_src;
+        pb.xy[0] = src_xy;
+        pb.alpha = alpha;
+        double *outs[3] = {nullptr, nullptr, nullptr};
+        if (tgt_xy) {
+            pb.n[2] = n_tgt;
+            pb.xy[2] = tgt_xy;
+            outs[2] = out;
+        } else {
+            outs[0] = out;
+        }
+        evaluate_sums(c, SLOT_MISC, pb, q, nullptr, outs, SUM_FP64);
+        return YK_OK;
+    });
+}
+
+yk_status yk_double_layer_apply(yk_ctx ctx, const yk_boundary *bnd, const double *sigma,
+                                int64_t n_tgt, const double *tgt_xy, double alpha, double *out) {
+    return guarded(ctx, [&](Context &c) {
+        YK_REQUIRE(sigma && out, "sigma/out are NULL");
+        YK_REQUIRE(!tgt_xy || n_tgt > 0, "n_tgt must be > 0 when targets are given");
+        check_alpha(alpha);
+        BoundaryData &bd = prepare_boundary(c, bnd);
+        double *dn = c.dn.ensure(2 * bd.n);
+        launch_dipole_vectors(c, bd.n, bd.w.p, sigma, bd.normal, 1.0, dn);
+        SumProblem pb;
+        pb.n[1] = bd.n;
+        pb.xy[1] = bd.xy;
+        pb.alpha = alpha;
+        double *outs[3] = {nullptr, nullptr, nullptr};
+        if (tgt_xy) {
+            pb.n[2] = n_tgt;
+            pb.xy[2] = tgt_xy;
+            outs[2] = out;
+            evaluate_sums(c, SLOT_MISC, pb, nullptr, dn, outs, SUM_FP64);
+        } else {
+            outs[1] = out;
+            evaluate_sums(c, SLOT_BND, pb, nullptr, dn, outs, SUM_FP64);
+            launch_dl_diagonal(c, bd.n, bd.w.p, bd.curvature, sigma, out);
+        }
+        return YK_OK;
+    });
+}
+
+static void fill_stats(yk_stats *st, const GmresResult &r, int outer, int guess) {
+    if (!st) return;
+    st->iters = r.iters;
+    st->outer_iters = outer;
+    st->guess_used = guess;
+    st->matvecs = r.matvecs;
+    st->res0 = r.res0;
+    st->res_final = r.res_final;
+}
+
+yk_status yk_gmres_density(yk_ctx ctx, const yk_boundary *bnd, double alpha, const double *g,
+                           const double *sigma0, double tol, int max_iter, double *sigma,
+                           yk_stats *stats) {
+    return guarded(ctx, [&](Context &c) {
+        YK_REQUIRE(g && sigma, "g/sigma are NULL");
+        YK_REQUIRE(std::isfinite(tol) && tol >= 0.0, "tol must be finite and >= 0");
+        YK_REQUIRE(max_iter >= 1, "max_iter must be >= 1");
+        check_alpha(alpha);
+        if (stats) std::memset(stats, 0, sizeof(*stats));
+        BoundaryData &bd = prepare_boundary(c, bnd);
+        const int64_t n = bd.n;
+        double *b = c.ws_f.ensure(n);
+        launch_axpby(c, n, -2.0 * alpha * alpha, g, 0.0, nullptr, b);
+        if (sigma0 && sigma0 != sigma)
+            YK_HIP(hipMemcpyAsync(sigma, sigma0, n * sizeof(double), hipMemcpyDeviceToDevice, c.stream));
+        auto t0 = std::chrono::steady_clock::now();
+        int outer = 0;
+        GmresResult r = solve_density(c, bd, alpha, b, sigma, sigma0 == nullptr, tol, max_iter, &outer);
+        YK_HIP(hipStreamSynchronize(c.stream));
+        fill_stats(stats, r, outer, sigma0 ? 1 : 0);
+        if (stats) stats->ms[2] = ms_since(t0);
+        if (!r.converged) {
+            c.last_error = "GMRES did not reach the tolerance within max_iter";
+            return YK_ERR_NOCONV;
+        }
+        return YK_OK;
+    });
+}
+
+yk_status yk_heat_step(yk_ctx ctx, const yk_boundary *bnd, int64_t n_vol, const double *vol_xy,
+                       const double *vol_w, const double *B, int flags, const double *f_next,
+                       double dt, double tol, double *sigma_io, double *u_next, yk_stats *stats) {
+    return guarded(ctx, [&](Context &c) {
+        YK_REQUIRE(n_vol > 0 && vol_xy && vol_w && B && f_next && sigma_io && u_next,
+                   "invalid heat-step arguments");
+        YK_REQUIRE(std::isfinite(dt) && dt > 0.0, "dt must be finite and > 0");
+        YK_REQUIRE(std::isfinite(tol) && tol >= 0.0, "tol must be finite and >= 0");
+        if (stats) std::memset(stats, 0, sizeof(*stats));
+        BoundaryData &bd = prepare_boundary(c, bnd);
+        const int64_t nb = bd.n;
+        const double alpha = std::sqrt(dt), a2 = dt;
+        const SumPrec vprec = c.opt.precision == YK_PREC_FP32 ? SUM_FP32 : SUM_FP64;
+        // q = W B
+        double *q = c.ws_d.ensure(n_vol);   // ws_d is free until the solve
+        auto t0 = std::chrono::steady_clock::now();
+        launch_mul(c, n_vol, vol_w, B, q);
+        SumProblem pb;
+        pb.n[0] = n_vol;
+        pb.xy[0] = vol_xy;
+        pb.n[1] = nb;
+        pb.xy[1] = bd.xy;
+        pb.alpha = alpha;
+        // U^p on the nodes: b = -2 alpha^2 (f - V[q]/alpha^2) = -2 alpha^2 f + 2 V[q]
+        double *vb = c.ws_e.ensure(nb);
+        {
+            double *outs[3] = {nullptr, vb, nullptr};
+            evaluate_sums(c, SLOT_VOL, pb, q, nullptr, outs, vprec);
+        }
+        double *b = c.ws_f.ensure(nb);
+        launch_axpby(c, nb, -2.0 * a2, f_next, 2.0, vb, b);
+        YK_HIP(hipStreamSynchronize(c.stream));
+        if (stats) {
+            stats->ms[0] = fmm_last_build_ms(c);
+            stats->ms[1] = ms_since(t0);
+        }
+        // sigma
+        auto t1 = std::chrono::steady_clock::now();
+        // the solver's operators use ws_a..ws_d, so q is formed again afterwards
+        int outer = 0;
+        GmresResult r = solve_density(c, bd, alpha, b, sigma_io, (flags & 2) != 0, tol, 1000, &outer);
+        if (stats) stats->ms[2] = ms_since(t1);
+        // u = (V[q] + DL[w sigma] + B C_self) / alpha^2 at the volume points
+        auto t2 = std::chrono::steady_clock::now();
+        launch_mul(c, n_vol, vol_w, B, q);   // q again (ws_d was used by the solver)
+        double *dn = c.dn.ensure(2 * nb);
+        launch_dipole_vectors(c, nb, bd.w.p, sigma_io, bd.normal, 1.0, dn);
+        {
+            double *outs[3] = {u_next, nullptr, nullptr};
+            evaluate_sums(c, SLOT_VOL, pb, q, dn, outs, vprec);
+        }
+        if (flags & 1) launch_self_cell(c, n_vol, vol_w, B, alpha, u_next);
+        launch_axpby(c, n_vol, 1.0 / a2, u_next, 0.0, nullptr, u_next);
+        YK_HIP(hipStreamSynchronize(c.stream));
+        if (stats) stats->ms[3] = ms_since(t2);
+        fill_stats(stats, r, outer, (flags & 2) ? 0 : 1);
+        if (!r.converged) {
+            c.last_error = "GMRES did not reach the tolerance";
+            return YK_ERR_NOCONV;
+        }
+        return YK_OK;
+    });
+}
+
+yk_status yk_rhs_backward_euler(yk_ctx ctx, int64_t n, const double *u, const double *F,
+                                const int32_t *region, int n_const, const double *cvals,
+                                double dt, double *B) {
+    return guarded(ctx, [&](Context &c) {
+        YK_REQUIRE(n > 0 && u && region && B, "invalid arguments");
+        YK_REQUIRE(n_const >= 0 && n_const <= 4096 && (n_const == 0 || cvals), "invalid constants");
+        YK_REQUIRE(std::isfinite(dt) && dt > 0.0, "dt must be finite and > 0");
+        double *cdev = c.ws_c.ensure(n_const > 0 ? n_const : 1);
+        if (n_const > 0)
+            YK_HIP(hipMemcpyAsync(cdev, cvals, n_const * sizeof(double), hipMemcpyHostToDevice, c.stream));
+        launch_rhs_be(c, n, u, F, region, n_const, cdev, dt, B);
+        YK_HIP(hipStreamSynchronize(c.stream));
+        return YK_OK;
+    });
+}
+
+yk_status yk_fmm_potential(yk_ctx ctx, int64_t n_vol, const double *vol_xy, const double *q,
+                           const yk_boundary *bnd, const double *d, double alpha,
+                           double *out_vol, double *out_bnd) {
+    return guarded(ctx, [&](Context &c) {
+        YK_REQUIRE(n_vol > 0 && vol_xy && q && d && out_vol && out_bnd, "invalid arguments");
+        check_alpha(alpha);
+        BoundaryData &bd = prepare_boundary(c, bnd);
+        double *dn = c.dn.ensure(2 * bd.n);
+        // dn_j = d_j n_j  (no quadrature weight: d is the full dipole strength)
+        launch_dipole_vectors(c, bd.n, nullptr, d, bd.normal, 1.0, dn);
+        SumProblem pb;
+        pb.n[0] = n_vol;
+        pb.xy[0] = vol_xy;
+        pb.n[1] = bd.n;
+        pb.xy[1] = bd.xy;
+        pb.alpha = alpha;
+        double *outs[3] = {out_vol, out_bnd, nullptr};
+        evaluate_sums(c, SLOT_VOL, pb, q, dn, outs,
+                      c.opt.precision == YK_PREC_FP32 ? SUM_FP32 : SUM_FP64);
+        return YK_OK;
+    });
+}
+
+}  // extern "C"

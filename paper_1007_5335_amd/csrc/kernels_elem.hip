@@ -1,0 +1,251 @@
+// kernels_elem.hip -- direct sums and elementwise kernels (FP64).
+#include "yk_bessel.h"
+#include "yk_internal.h"
+
+namespace yk {
+
+namespace {
+
+constexpr int kDirectBlock = 256;
+
+// All-pairs sum: one target per thread, sources staged through LDS in tiles.
+// Charges contribute q K0(z)/(2pi); dipoles contribute (x - y).dn K1(z)/(alpha^2 z)/(2pi),
+// z = r/alpha.  Pairs at distance zero are skipped (self pairs included).
+__global__ __launch_bounds__(kDirectBlock) void k_direct(
+    int64_t nt, const double *__restrict__ txy, int64_t ns, const double *__restrict__ sxy,
+    const double *__restrict__ q, int64_t nb, const double *__restrict__ bxy,
+    const double *__restrict__ dn, double inv4a2, double inva2, double *__restrict__ out,
+    int accumulate) {
+    __shared__ double sx[kDirectBlock], sy[kDirectBlock], sq[kDirectBlock], sn[kDirectBlock];
+    const int64_t i = (int64_t)blockIdx.x * kDirectBlock + threadIdx.x;
+    const bool live = i < nt;
+    const double x = live ? txy[2 * i] : 0.0;
+    const double y = live ? txy[2 * i + 1] : 0.0;
+    double acc = 0.0;
+    for (int64_t s0 = 0; s0 < ns; s0 += kDirectBlock) {
+        const int64_t j = s0 + threadIdx.x;
+        if (j < ns) {
+            sx[threadIdx.x] = sxy[2 * j];
+            sy[threadIdx.x] = sxy[2 * j + 1];
+            sq[threadIdx.x] = q[j];
+        }
+        __syncthreads();
+        const int cnt = (int)min<int64_t>(kDirectBlock, ns - s0);
+        for (int k = 0; k < cnt; ++k) {
+            const double dx = x - sx[k], dy = y - sy[k];
+            const double r2 = dx * dx + dy * dy;
+            if (r2 > 0.0) acc += sq[k] * k0_of_t(r2 * inv4a2);
+        }
+        __syncthreads();
+    }
+    for (int64_t s0 = 0; s0 < nb; s0 += kDirectBlock) {
+        const int64_t j = s0 + threadIdx.x;
+        if (j < nb) {
+            sx[threadIdx.x] = bxy[2 * j];
+            sy[threadIdx.x] = bxy[2 * j + 1];
+            sq[threadIdx.x] = dn[2 * j];
+            sn[threadIdx.x] = dn[2 * j + 1];
+        }
+        __syncthreads();
+        const int cnt = (int)min<int64_t>(kDirectBlock, nb - s0);
+        for (int k = 0; k < cnt; ++k) {
+            const double dx = x - sx[k], dy = y - sy[k];
+            const double r2 = dx * dx + dy * dy;
+            if (r2 > 0.0) acc += (dx * sq[k] + dy * sn[k]) * inva2 * k1oz_of_t(r2 * inv4a2);
+        }
+        __syncthreads();
+    }
+    if (live) {
+        const double v = acc * kInv2Pi;
+        out[i] = accumulate ? out[i] + v : v;
+    }
+}
+
+__global__ void k_dipole_vectors(int64_t n, const double *__restrict__ w,
+                                 const double *__restrict__ sigma,
+                                 const double *__restrict__ normal, double scale,
+                                 double *__restrict__ dn) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double s = scale * (w ? w[i] : 1.0) * sigma[i];
+    dn[2 * i] = s * normal[2 * i];
+    dn[2 * i + 1] = s * normal[2 * i + 1];
+}
+
+__global__ void k_dl_diagonal(int64_t n, const double *__restrict__ w,
+                              const double *__restrict__ kappa, const double *__restrict__ sigma,
+                              double *__restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    out[i] += w[i] * (-0.5 * kappa[i]) * sigma[i] * kInv2Pi;
+}
+
+__global__ void k_bie_combine(int64_t n, const double *__restrict__ x,
+                              const double *__restrict__ dl, double *__restrict__ y) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    y[i] = x[i] - 2.0 * dl[i];
+}
+
+__global__ void k_mul(int64_t n, const double *__restrict__ a, const double *__restrict__ b,
+                      double *__restrict__ o) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    o[i] = a[i] * b[i];
+}
+
+__global__ void k_axpby(int64_t n, double ca, const double *__restrict__ a, double cb,
+                        const double *__restrict__ b, double *__restrict__ o) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    o[i] = b ? ca * a[i] + cb * b[i] : ca * a[i];
+}
+
+// 32-point Gauss-Legendre rule on [-1, 1] (nodes and weights filled on the host).
+__constant__ double c_gl_x[32];
+__constant__ double c_gl_w[32];
+
+// out[i] += B[i] * (1/2pi) * 8 * int_0^{pi/4} (alpha^2 - alpha R K1(R/alpha)) dtheta,
+// R = (h/2)/cos(theta), h = sqrt(vol_w[i]): the kernel integrated over the
+// target's own square cell (8 right triangles with apex at the centre).
+__global__ void k_self_cell(int64_t n, const double *__restrict__ vol_w,
+                            const double *__restrict__ B, double alpha,
+                            double *__restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double h = sqrt(vol_w[i]);
+    const double q8 = kPi / 8.0;
+    double s = 0.0;
+    for (int k = 0; k < 32; ++k) {
+        const double th = (c_gl_x[k] + 1.0) * q8;
+        const double R = 0.5 * h / cos(th);
+        const double z = R / alpha;
+        s += c_gl_w[k] * (alpha * alpha - alpha * R * k1(z));
+    }
+    out[i] += B[i] * 8.0 * q8 * s * kInv2Pi;
+}
+
+__global__ void k_rhs_be(int64_t n, const double *__restrict__ u, const double *__restrict__ F,
+                         const int32_t *__restrict__ region, int n_const,
+                         const double *__restrict__ c, double dt, double *__restrict__ B) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int r = region[i];
+    if (r < 0)
+        B[i] = u[i] + (F ? dt * F[i] : 0.0);
+    else
+        B[i] = (r < n_const) ? c[r] : 0.0;
+}
+
+__global__ void k_boundary_prep(int64_t n, int n_curves, const int64_t *__restrict__ off,
+                                const double *__restrict__ speed, double *__restrict__ w,
+                                int32_t *__restrict__ curve, int32_t *__restrict__ idx) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int lo = 0, hi = n_curves - 1;
+    while (lo < hi) {   // last curve k with off[k] <= i
+        const int mid = (lo + hi + 1) >> 1;
+        if (off[mid] <= i) lo = mid; else hi = mid - 1;
+    }
+    const int64_t nk = off[lo + 1] - off[lo];
+    w[i] = (2.0 * kPi / (double)nk) * speed[i];
+    curve[i] = lo;
+    idx[i] = (int32_t)(i - off[lo]);
+}
+
+inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+
+}  // namespace
+
+void launch_direct(Context &ctx, int64_t nt, const double *txy, int64_t ns, const double *sxy,
+                   const double *q, int64_t nb, const double *bxy, const double *dn, double alpha,
+                   double *out, bool accumulate) {
+    if (nt <= 0) return;
+    const double inv4a2 = 1.0 / (4.0 * alpha * alpha), inva2 = 1.0 / (alpha * alpha);
+    hipLaunchKernelGGL(k_direct, dim3(nblk(nt, kDirectBlock)), dim3(kDirectBlock), 0, ctx.stream,
+                       nt, txy, ns, sxy, q, nb, bxy, dn, inv4a2, inva2, out, accumulate ? 1 : 0);
+    check_launch(ctx, "k_direct");
+}
+
+void launch_dipole_vectors(Context &ctx, int64_t n, const double *w, const double *sigma,
+                           const double *normal, double scale, double *dn) {
+    hipLaunchKernelGGL(k_dipole_vectors, dim3(nblk(n, 256)), dim3(256), 0, ctx.stream, n, w, sigma,
+                       normal, scale, dn);
+    check_launch(ctx, "k_dipole_vectors");
+}
+
+void launch_dl_diagonal(Context &ctx, int64_t n, const double *w, const double *kappa,
+                        const double *sigma, double *out) {
+    hipLaunchKernelGGL(k_dl_diagonal, dim3(nblk(n, 256)), dim3(256), 0, ctx.stream, n, w, kappa,
+                       sigma, out);
+    check_launch(ctx, "k_dl_diagonal");
+}
+
+void launch_bie_combine(Context &ctx, int64_t n, const double *x, const double *dl, double *y) {
+    hipLaunchKernelGGL(k_bie_combine, dim3(nblk(n, 256)), dim3(256), 0, ctx.stream, n, x, dl, y);
+    check_launch(ctx, "k_bie_combine");
+}
+
+void launch_mul(Context &ctx, int64_t n, const double *a, const double *b, double *out) {
+    hipLaunchKernelGGL(k_mul, dim3(nblk(n, 256)), dim3(256), 0, ctx.stream, n, a, b, out);
+    check_launch(ctx, "k_mul");
+}
+
+void launch_axpby(Context &ctx, int64_t n, double ca, const double *a, double cb, const double *b,
+                  double *out) {
+    hipLaunchKernelGGL(k_axpby, dim3(nblk(n, 256)), dim3(256), 0, ctx.stream, n, ca, a, cb, b, out);
+    check_launch(ctx, "k_axpby");
+}
+
+static void gauss_legendre32(double *x, double *w) {
+    // Newton iteration on P_32 from the asymptotic initial guesses.
+    const int n = 32;
+    for (int i = 0; i < n; ++i) {
+        double z = cos(kPi * (i + 0.75) / (n + 0.5)), pp = 0.0;
+        for (int it = 0; it < 100; ++it) {
+            double p1 = 1.0, p2 = 0.0;
+            for (int j = 1; j <= n; ++j) {
+                const double p3 = p2;
+                p2 = p1;
+                p1 = ((2.0 * j - 1.0) * z * p2 - (j - 1.0) * p3) / j;
+            }
+            pp = n * (z * p1 - p2) / (z * z - 1.0);
+            const double dz = p1 / pp;
+            z -= dz;
+            if (fabs(dz) < 1e-16) break;
+        }
+        x[i] = z;
+        w[i] = 2.0 / ((1.0 - z * z) * pp * pp);
+    }
+}
+
+void launch_self_cell(Context &ctx, int64_t n, const double *vol_w, const double *B, double alpha,
+                      double *out_accum) {
+    static bool ready = false;
+    static double gx[32], gw[32];
+    if (!ready) {
+        gauss_legendre32(gx, gw);
+        ready = true;
+    }
+    YK_HIP(hipMemcpyToSymbolAsync(HIP_SYMBOL(c_gl_x), gx, sizeof(gx), 0, hipMemcpyHostToDevice, ctx.stream));
+    YK_HIP(hipMemcpyToSymbolAsync(HIP_SYMBOL(c_gl_w), gw, sizeof(gw), 0, hipMemcpyHostToDevice, ctx.stream));
+    hipLaunchKernelGGL(k_self_cell, dim3(nblk(n, 256)), dim3(256), 0, ctx.stream, n, vol_w, B,
+                       alpha, out_accum);
+    check_launch(ctx, "k_self_cell");
+}
+
+void launch_rhs_be(Context &ctx, int64_t n, const double *u, const double *F, const int32_t *region,
+                   int n_const, const double *c_dev, double dt, double *B) {
+    hipLaunchKernelGGL(k_rhs_be, dim3(nblk(n, 256)), dim3(256), 0, ctx.stream, n, u, F, region,
+                       n_const, c_dev, dt, B);
+    check_launch(ctx, "k_rhs_be");
+}
+
+void launch_boundary_prep(Context &ctx, int64_t n, int n_curves, const int64_t *off_dev,
+                          const double *speed, double *w, int32_t *curve, int32_t *idx) {
+    hipLaunchKernelGGL(k_boundary_prep, dim3(nblk(n, 256)), dim3(256), 0, ctx.stream, n, n_curves,
+                       off_dev, speed, w, curve, idx);
+    check_launch(ctx, "k_boundary_prep");
+}
+
+}  // namespace yk

@@ -1,0 +1,34 @@
+// sums.h -- one interface for the kernel sums, with a direct and an FMM backend.
+#pragma once
+
+#include "yk_internal.h"
+
+namespace yk {
+
+// Up to three point sets, each a target set:
+//   0: charge sources (volume points),  strengths q
+//   1: dipole sources (boundary nodes), dipole vectors dn = strength * normal
+//   2: target-only points
+// out[s] (if non-null) receives, at every point of set s,
+//   sum_q q_j K0(r/alpha)/(2pi) + sum_d (x - y_j).dn_j K1(r/alpha)/(alpha r)/(2pi)
+// with pairs at distance zero skipped.
+struct SumProblem {
+    int64_t n[3] = {0, 0, 0};
+    const double *xy[3] = {nullptr, nullptr, nullptr};
+    double alpha = 0.0;
+};
+
+enum PlanSlot { SLOT_VOL = 0, SLOT_BND = 1, SLOT_MISC = 2 };
+
+enum SumPrec { SUM_FP64 = 0, SUM_FP32 = 1 };
+
+void evaluate_sums(Context &ctx, PlanSlot slot, const SumProblem &pb, const double *q,
+                   const double *dn, double *const out[3], SumPrec prec);
+
+// FMM backend (fmm.hip)
+void fmm_evaluate(Context &ctx, PlanSlot slot, const SumProblem &pb, const double *q,
+                  const double *dn, double *const out[3], SumPrec prec);
+// Time spent building the last tree, in ms (0 when reused).
+double fmm_last_build_ms(Context &ctx);
+
+}  // namespace yk

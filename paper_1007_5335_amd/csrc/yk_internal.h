@@ -1,0 +1,172 @@
+// yk_internal.h -- shared declarations of libyk's host layer and kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstring>
+#include <functional>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "yk.h"
+
+namespace yk {
+
+constexpr double kPi = 3.14159265358979323846;
+constexpr double kInv2Pi = 1.0 / (2.0 * kPi);
+
+// Internal error: thrown inside the library, converted to a status at the ABI.
+struct Error {
+    yk_status code;
+    std::string msg;
+};
+
+#define YK_HIP(call)                                                                       \
+    do {                                                                                   \
+        hipError_t e_ = (call);                                                            \
+        if (e_ != hipSuccess)                                                              \
+            throw ::yk::Error{YK_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(e_)}; \
+    } while (0)
+
+#define YK_REQUIRE(cond, msg)                                      \
+    do {                                                           \
+        if (!(cond)) throw ::yk::Error{YK_ERR_ARG, std::string(msg)}; \
+    } while (0)
+
+// Device buffer owned by the library (grow-only).
+template <typename T>
+struct DevBuf {
+    T *p = nullptr;
+    size_t n = 0;
+    DevBuf() = default;
+    DevBuf(const DevBuf &) = delete;
+    DevBuf &operator=(const DevBuf &) = delete;
+    ~DevBuf() { release(); }
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        n = 0;
+    }
+    T *ensure(size_t count) {
+        if (count <= n && p) return p;
+        release();
+        size_t c = count ? count : 1;
+        if (hipMalloc(&p, c * sizeof(T)) != hipSuccess) {
+            p = nullptr;
+            throw Error{YK_ERR_NOMEM, "device allocation of " + std::to_string(c * sizeof(T)) + " bytes failed"};
+        }
+        n = c;
+        return p;
+    }
+};
+
+struct Context;
+
+// Launch-time check (and optional synchronous check in debug mode).
+void check_launch(Context &ctx, const char *what);
+
+// Boundary geometry prepared once per boundary (weights, curve ids).
+struct BoundaryData {
+    const double *xy = nullptr;
+    int64_t n = 0;
+    int n_curves = 0;
+    std::vector<int64_t> offset;      // host copy
+    DevBuf<double> w;                 // (2 pi / N_k) speed_j
+    DevBuf<int32_t> curve;            // curve id per node
+    DevBuf<int32_t> idx;              // node index within its curve
+    const double *normal = nullptr;
+    const double *curvature = nullptr;
+    const double *speed = nullptr;
+};
+
+struct FmmPlan;   // tree + lists + operator tables (fmm.hip)
+void destroy_plan(FmmPlan *p);
+struct PlanDeleter {
+    void operator()(FmmPlan *p) const { destroy_plan(p); }
+};
+using PlanPtr = std::unique_ptr<FmmPlan, PlanDeleter>;
+
+struct Context {
+    yk_options opt{};
+    hipStream_t stream = nullptr;
+    std::string last_error;
+    int device = 0;
+
+    std::unique_ptr<BoundaryData> bnd;     // cached boundary preparation
+    PlanPtr plan_vol;                      // tree over volume points and nodes
+    PlanPtr plan_bnd;                      // tree over the nodes only (solver)
+    PlanPtr plan_misc;                     // tree for the stand-alone sum calls
+
+    // workspaces
+    DevBuf<double> ws_a, ws_b, ws_c, ws_d, ws_e, ws_f;
+    DevBuf<double> krylov;                 // (m+1) x N
+    DevBuf<double> gm_w, gm_r;             // GMRES-private vectors
+    DevBuf<double> partial;                // reduction partials
+    DevBuf<double> scal;                   // small device scalars
+    DevBuf<double> dn;                     // dipole vectors [N][2]
+    std::vector<double> host_scal;
+};
+
+// ---------------------------------------------------------------- kernels ---
+// Direct sums (FP64): out[i] (+)= sum_j q_j K0/(2pi) + sum_j (x_i - y_j).dn_j K1(z)/(alpha^2 z)/(2pi)
+void launch_direct(Context &ctx, int64_t nt, const double *txy, int64_t ns, const double *sxy,
+                   const double *q, int64_t nb, const double *bxy, const double *dn, double alpha,
+                   double *out, bool accumulate);
+// dn_j = scale * w_j * sigma_j * n_j  (w == nullptr: unit weights)
+void launch_dipole_vectors(Context &ctx, int64_t n, const double *w, const double *sigma,
+                           const double *normal, double scale, double *dn);
+// out_j += w_j (-kappa_j/2) sigma_j / (2 pi)
+void launch_dl_diagonal(Context &ctx, int64_t n, const double *w, const double *kappa,
+                        const double *sigma, double *out);
+// y = x - 2 * dl  (dl already includes 1/(2pi) and the diagonal)
+void launch_bie_combine(Context &ctx, int64_t n, const double *x, const double *dl, double *y);
+void launch_mul(Context &ctx, int64_t n, const double *a, const double *b, double *out);
+// out = ca * a + cb * b  (b may be null -> out = ca * a)
+void launch_axpby(Context &ctx, int64_t n, double ca, const double *a, double cb, const double *b,
+                  double *out);
+void launch_self_cell(Context &ctx, int64_t n, const double *vol_w, const double *B, double alpha,
+                      double *out_accum);
+void launch_rhs_be(Context &ctx, int64_t n, const double *u, const double *F, const int32_t *region,
+                   int n_const, const double *c_dev, double dt, double *B);
+void launch_boundary_prep(Context &ctx, int64_t n, int n_curves, const int64_t *off_dev,
+                          const double *speed, double *w, int32_t *curve, int32_t *idx);
+
+// BLAS for GMRES (deterministic reductions)
+// h[k] = sum_i V[k*ld + i] * x[i], k < nv  (result on device at h)
+void launch_multi_dot(Context &ctx, int64_t n, int nv, const double *V, int64_t ld,
+                      const double *x, double *h);
+// x -= sum_k h[k] V[k*ld + i]
+void launch_multi_axpy(Context &ctx, int64_t n, int nv, const double *V, int64_t ld,
+                       const double *h, double *x);
+// y = x / *s  (s on device)
+void launch_scale_div(Context &ctx, int64_t n, const double *x, const double *s, double *y);
+// x += sum_k y[k] V[k*ld+i] with y on device
+void launch_add_combination(Context &ctx, int64_t n, int nv, const double *V, int64_t ld,
+                            const double *y, double *x);
+// flag = any non-finite in x  (writes 0/1 to *flag as double)
+void launch_nonfinite(Context &ctx, int64_t n, const double *x, double *flag);
+
+// ------------------------------------------------------------------ GMRES ---
+using Apply = std::function<void(const double *x, double *y)>;
+struct GmresResult {
+    int iters = 0;
+    int matvecs = 0;
+    double res0 = 0, res_final = 0;   // relative to ||b||
+    bool converged = false;
+};
+// Solves A x = b; x holds the initial guess on entry (zero if zero_guess).
+GmresResult gmres(Context &ctx, const Apply &A, int64_t n, const double *b, double *x,
+                  bool zero_guess, double tol, int max_iter, int m);
+
+// -------------------------------------------------------------------- FMM ---
+// Evaluate V[q] + DL[dn] at targets with the cached plan.
+struct FmmRequest;
+BoundaryData &prepare_boundary(Context &ctx, const yk_boundary *b);
+
+}  // namespace yk
+
+struct yk_ctx_s {
+    yk::Context c;
+};

@@ -1,0 +1,264 @@
+"""Thin ctypes binding of libyk (include/yk.h), same names as the C ABI.
+
+Only argument marshalling happens here: every array is a contiguous FP64 (or
+int32) torch tensor on the GPU, passed to the library by its device address.
+Every computation runs in the library's HIP kernels.  If the built library is
+missing, loading fails loudly; there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libyk.so")
+
+YK_OK = 0
+YK_ERR_ARG = -1
+YK_ERR_HIP = -2
+YK_ERR_NOMEM = -3
+YK_ERR_NOCONV = -4
+YK_ERR_NONFINITE = -5
+YK_ERR_INTERNAL = -6
+
+YK_PREC_FP64 = 0
+YK_PREC_MIXED = 1
+YK_PREC_FP32 = 2
+
+HEAT_GRID_SELF_CELL = 1
+HEAT_ZERO_GUESS = 2
+
+EXPORTS = (
+    "yk_default_options", "yk_create", "yk_destroy", "yk_set_stream", "yk_set_options",
+    "yk_last_error", "yk_invalidate_geometry", "yk_volume_potential", "yk_double_layer_apply",
+    "yk_gmres_density", "yk_heat_step", "yk_rhs_backward_euler", "yk_fmm_potential",
+)
+
+
+class yk_options(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int), ("fmm_tol", ctypes.c_double), ("p", ctypes.c_int),
+                ("leaf_size", ctypes.c_int), ("direct", ctypes.c_int), ("gmres_m", ctypes.c_int),
+                ("debug_flags", ctypes.c_int)]
+
+
+class yk_boundary(ctypes.Structure):
+    _fields_ = [("n_curves", ctypes.c_int32), ("offset", ctypes.POINTER(ctypes.c_int64)),
+                ("xy", ctypes.c_void_p), ("normal", ctypes.c_void_p),
+                ("speed", ctypes.c_void_p), ("curvature", ctypes.c_void_p)]
+
+
+class yk_stats(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int), ("outer_iters", ctypes.c_int),
+                ("guess_used", ctypes.c_int), ("matvecs", ctypes.c_int),
+                ("res0", ctypes.c_double), ("res_final", ctypes.c_double),
+                ("ms", ctypes.c_double * 8)]
+
+    def as_dict(self):
+        return dict(iters=self.iters, outer_iters=self.outer_iters, guess_used=self.guess_used,
+                    matvecs=self.matvecs, res0=self.res0, res_final=self.res_final,
+                    ms=list(self.ms))
+
+
+class YkError(RuntimeError):
+    def __init__(self, status, msg, stats=None):
+        super().__init__(f"libyk status {status}: {msg}")
+        self.status = status
+        self.stats = stats
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libyk.so (built in-tree by paper_1007_5335_amd.build)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"libyk.so not found at {path}; build it with "
+                          f"`python -m paper_1007_5335_amd.build` (no fallback exists)")
+    lib = ctypes.CDLL(path)
+    vp, i64, dbl, ip = ctypes.c_void_p, ctypes.c_int64, ctypes.c_double, ctypes.c_int
+    P = ctypes.POINTER
+    sig = {
+        "yk_default_options": (None, [P(yk_options)]),
+        "yk_create": (ip, [P(yk_options), P(vp)]),
+        "yk_destroy": (ip, [vp]),
+        "yk_set_stream": (ip, [vp, vp]),
+        "yk_set_options": (ip, [vp, P(yk_options)]),
+        "yk_last_error": (ctypes.c_char_p, [vp]),
+        "yk_invalidate_geometry": (ip, [vp]),
+        "yk_volume_potential": (ip, [vp, i64, vp, vp, i64, vp, dbl, vp]),
+        "yk_double_layer_apply": (ip, [vp, P(yk_boundary), vp, i64, vp, dbl, vp]),
+        "yk_gmres_density": (ip, [vp, P(yk_boundary), dbl, vp, vp, dbl, ip, vp, P(yk_stats)]),
+        "yk_heat_step": (ip, [vp, P(yk_boundary), i64, vp, vp, vp, ip, vp, dbl, dbl, vp, vp,
+                              P(yk_stats)]),
+        "yk_rhs_backward_euler": (ip, [vp, i64, vp, vp, vp, ip, P(dbl), dbl, vp]),
+        "yk_fmm_potential": (ip, [vp, i64, vp, vp, P(yk_boundary), vp, dbl, vp, vp]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+# ---------------------------------------------------------------------------
+# argument helpers
+# ---------------------------------------------------------------------------
+def _dev(t, name, dtype="float64", shape_last=None):
+    import torch
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor on the GPU")
+    want = torch.float64 if dtype == "float64" else torch.int32
+    if t.dtype != want:
+        raise TypeError(f"{name} must be {want}, got {t.dtype}")
+    if not t.is_cuda:
+        raise ValueError(f"{name} must live on the GPU")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if shape_last is not None and (t.dim() != 2 or t.shape[1] != shape_last):
+        raise ValueError(f"{name} must have shape [n, {shape_last}]")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _check(ctx, status, stats=None):
+    if status != YK_OK:
+        msg = load_library().yk_last_error(ctx)
+        raise YkError(status, msg.decode() if msg else "", stats)
+
+
+class Boundary:
+    """Device-resident boundary (curve 0 outer, holes after) and its C view."""
+
+    def __init__(self, xy, normal, speed, curvature, offset):
+        import torch
+        dev = "cuda"
+        f = lambda a: torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64), device=dev)
+        self.xy = f(xy) if not isinstance(xy, torch.Tensor) else xy
+        self.normal = f(normal) if not isinstance(normal, torch.Tensor) else normal
+        self.speed = f(speed) if not isinstance(speed, torch.Tensor) else speed
+        self.curvature = f(curvature) if not isinstance(curvature, torch.Tensor) else curvature
+        self.offset = np.ascontiguousarray(offset, dtype=np.int64)
+        self.n = int(self.offset[-1])
+        self.n_curves = len(self.offset) - 1
+        self._c = yk_boundary(self.n_curves,
+                              self.offset.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                              _dev(self.xy, "xy", shape_last=2), _dev(self.normal, "normal", shape_last=2),
+                              _dev(self.speed, "speed"), _dev(self.curvature, "curvature"))
+
+    @classmethod
+    def from_workload(cls, bnd):
+        return cls(bnd.xy, bnd.normal, bnd.speed, bnd.curvature, bnd.offset)
+
+    @property
+    def struct(self):
+        return self._c
+
+
+# ---------------------------------------------------------------------------
+# C ABI, same names
+# ---------------------------------------------------------------------------
+def yk_default_options() -> yk_options:
+    o = yk_options()
+    load_library().yk_default_options(ctypes.byref(o))
+    return o
+
+
+def yk_create(opt: yk_options | None = None, **kw):
+    if opt is None:
+        opt = yk_default_options()
+    for k, v in kw.items():
+        setattr(opt, k, v)
+    h = ctypes.c_void_p()
+    st = load_library().yk_create(ctypes.byref(opt), ctypes.byref(h))
+    if st != YK_OK:
+        raise YkError(st, "yk_create failed")
+    import torch
+    yk_set_stream(h, torch.cuda.current_stream())
+    return h
+
+
+def yk_destroy(ctx):
+    load_library().yk_destroy(ctx)
+
+
+def yk_set_stream(ctx, stream=None):
+    ptr = None if stream is None else ctypes.c_void_p(stream.cuda_stream)
+    _check(ctx, load_library().yk_set_stream(ctx, ptr))
+
+
+def yk_set_options(ctx, opt: yk_options):
+    _check(ctx, load_library().yk_set_options(ctx, ctypes.byref(opt)))
+
+
+def yk_last_error(ctx) -> str:
+    m = load_library().yk_last_error(ctx)
+    return m.decode() if m else ""
+
+
+def yk_invalidate_geometry(ctx):
+    _check(ctx, load_library().yk_invalidate_geometry(ctx))
+
+
+def yk_volume_potential(ctx, src_xy, q, tgt_xy, alpha, out):
+    n_tgt = 0 if tgt_xy is None else tgt_xy.shape[0]
+    _check(ctx, load_library().yk_volume_potential(
+        ctx, src_xy.shape[0], _dev(src_xy, "src_xy", shape_last=2), _dev(q, "q"), n_tgt,
+        _dev(tgt_xy, "tgt_xy", shape_last=2), float(alpha), _dev(out, "out")))
+    return out
+
+
+def yk_double_layer_apply(ctx, bnd: Boundary, sigma, tgt_xy, alpha, out):
+    n_tgt = 0 if tgt_xy is None else tgt_xy.shape[0]
+    _check(ctx, load_library().yk_double_layer_apply(
+        ctx, ctypes.byref(bnd.struct), _dev(sigma, "sigma"), n_tgt,
+        _dev(tgt_xy, "tgt_xy", shape_last=2), float(alpha), _dev(out, "out")))
+    return out
+
+
+def yk_gmres_density(ctx, bnd: Boundary, alpha, g, sigma0, tol, max_iter, sigma,
+                     raise_on_noconv=True):
+    st = yk_stats()
+    s = load_library().yk_gmres_density(ctx, ctypes.byref(bnd.struct), float(alpha), _dev(g, "g"),
+                                        _dev(sigma0, "sigma0"), float(tol), int(max_iter),
+                                        _dev(sigma, "sigma"), ctypes.byref(st))
+    if s == YK_ERR_NOCONV and not raise_on_noconv:
+        return st
+    _check(ctx, s, st)
+    return st
+
+
+def yk_heat_step(ctx, bnd: Boundary, vol_xy, vol_w, B, flags, f_next, dt, tol, sigma_io, u_next,
+                 raise_on_noconv=True):
+    st = yk_stats()
+    s = load_library().yk_heat_step(ctx, ctypes.byref(bnd.struct), vol_xy.shape[0],
+                                    _dev(vol_xy, "vol_xy", shape_last=2), _dev(vol_w, "vol_w"),
+                                    _dev(B, "B"), int(flags), _dev(f_next, "f_next"), float(dt),
+                                    float(tol), _dev(sigma_io, "sigma_io"), _dev(u_next, "u_next"),
+                                    ctypes.byref(st))
+    if s == YK_ERR_NOCONV and not raise_on_noconv:
+        return st
+    _check(ctx, s, st)
+    return st
+
+
+def yk_rhs_backward_euler(ctx, u, F, region, consts, dt, B):
+    c = np.ascontiguousarray(consts, dtype=np.float64)
+    _check(ctx, load_library().yk_rhs_backward_euler(
+        ctx, u.shape[0], _dev(u, "u"), _dev(F, "F"), _dev(region, "region", dtype="int32"),
+        int(c.size), c.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), float(dt), _dev(B, "B")))
+    return B
+
+
+def yk_fmm_potential(ctx, vol_xy, q, bnd: Boundary, d, alpha, out_vol, out_bnd):
+    _check(ctx, load_library().yk_fmm_potential(
+        ctx, vol_xy.shape[0], _dev(vol_xy, "vol_xy", shape_last=2), _dev(q, "q"),
+        ctypes.byref(bnd.struct), _dev(d, "d"), float(alpha), _dev(out_vol, "out_vol"),
+        _dev(out_bnd, "out_bnd")))
+    return out_vol, out_bnd

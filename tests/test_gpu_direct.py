@@ -1,0 +1,159 @@
+"""GPU parity of the direct-sum path against the CPU oracle (through the C ABI)."""
+import math
+
+import numpy as np
+import pytest
+
+import workloads as W
+from gpu_util import dev, host, rel_max
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def yk():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1007_5335_amd.yk as yk
+    yk.load_library()
+    return yk
+
+
+@pytest.fixture
+def ctx(yk):
+    c = yk.yk_create(direct=1)
+    yield c
+    yk.yk_destroy(c)
+
+
+def test_device_k0_through_single_source(yk, ctx, oracle_lib):
+    import torch
+    alpha = 0.37
+    r = np.concatenate([np.logspace(-6, math.log10(40.0 * alpha), 400), [2 * alpha, 2 * alpha * (1 + 1e-12)]])
+    tgt = np.stack([0.3 + r, np.full_like(r, -0.2)], axis=1)
+    out = torch.empty(len(r), dtype=torch.float64, device="cuda")
+    yk.yk_volume_potential(ctx, dev([[0.3, -0.2]]), dev([2 * math.pi]), dev(tgt), alpha, out)
+    got = host(out)
+    r = tgt[:, 0] - 0.3            # the separation the kernel actually sees (exact subtraction)
+    ref = oracle_lib.k0(r / alpha)
+    rel = np.abs(got - ref) / ref
+    assert np.max(rel * (r / alpha < 2)) < 4e-15
+    assert np.max(rel) < 2e-14
+
+
+def test_device_dl_kernel_through_single_dipole(yk, ctx, oracle_lib):
+    import torch
+    alpha = 0.21
+    cv = W.circle((0.0, 0.0), 0.5, 1, ccw=True)   # one node at (0.5, 0), normal (1, 0)
+    bd = yk.Boundary(cv.xy, cv.normal, np.ones(1) / (2 * math.pi), cv.curvature, [0, 1])
+    ang = np.linspace(0.1, 6.0, 50)
+    rr = np.logspace(-5, math.log10(30 * alpha), 50)
+    tgt = np.stack([0.5 + rr * np.cos(ang), rr * np.sin(ang)], axis=1)
+    out = torch.empty(50, dtype=torch.float64, device="cuda")
+    # weight w = (2 pi / 1) * speed = 1, sigma = 2 pi -> out = D(t, y)
+    yk.yk_double_layer_apply(ctx, bd, dev([2 * math.pi]), dev(tgt), alpha, out)
+    ref = np.array([oracle_lib.dl_kernel(t, cv.xy[0], cv.normal[0], alpha) for t in tgt])
+    assert np.max(np.abs(host(out) - ref) / np.abs(ref)) < 1e-13
+
+
+def test_volume_potential_direct(yk, ctx, oracle_lib):
+    import torch
+    c = W.small_fmm_case(n_vol=3000, n_nodes=64, alpha=0.05, seed=3)
+    src, q = c["vol"], c["q"]
+    tgt = np.random.default_rng(9).random((777, 2))
+    out = torch.empty(777, dtype=torch.float64, device="cuda")
+    yk.yk_volume_potential(ctx, dev(src), dev(q), dev(tgt), 0.05, out)
+    assert rel_max(host(out), oracle_lib.volume_sum(src, q, 0.05, tgt_xy=tgt)) < 1e-13
+    out2 = torch.empty(3000, dtype=torch.float64, device="cuda")
+    yk.yk_volume_potential(ctx, dev(src), dev(q), None, 0.05, out2)
+    assert rel_max(host(out2), oracle_lib.volume_sum(src, q, 0.05)) < 1e-13
+
+
+def test_double_layer_on_and_off_surface(yk, ctx, oracle_lib):
+    import torch
+    cfg = W.config_c0(n_nodes=128, m=8)
+    b = cfg["bnd"]
+    bd = yk.Boundary.from_workload(b)
+    sig = np.cos(3 * np.arange(b.n)) + 0.1
+    out = torch.empty(b.n, dtype=torch.float64, device="cuda")
+    yk.yk_double_layer_apply(ctx, bd, dev(sig), None, 0.1, out)
+    ref = oracle_lib.dl_on_surface(b.xy, b.normal, b.weights(), b.curvature, sig, 0.1)
+    assert rel_max(host(out), ref) < 1e-13
+    tgt = cfg["vol"]
+    out2 = torch.empty(tgt.shape[0], dtype=torch.float64, device="cuda")
+    yk.yk_double_layer_apply(ctx, bd, dev(sig), dev(tgt), 0.1, out2)
+    ref2 = oracle_lib.dl_sum(b.xy, b.normal, b.weights() * sig, 0.1, tgt)
+    assert rel_max(host(out2), ref2) < 1e-13
+
+
+@pytest.mark.parametrize("alpha", [0.01, 0.1, 0.2])
+def test_gmres_density_vs_dense_lu(yk, ctx, oracle_lib, alpha):
+    import torch
+    cfg = W.config_c0(n_nodes=256, m=8)
+    b = cfg["bnd"]
+    bd = yk.Boundary.from_workload(b)
+    g = np.sin(b.xy[:, 0] * 3) + b.xy[:, 1] ** 2
+    sig = torch.empty(b.n, dtype=torch.float64, device="cuda")
+    st = yk.yk_gmres_density(ctx, bd, alpha, dev(g), None, 1e-13, 200, sig)
+    ref = oracle_lib.DenseBIE(b.xy, b.normal, b.weights(), b.curvature, alpha).solve(g)
+    assert st.res_final <= 1e-13
+    assert rel_max(host(sig), ref) < 1e-11
+    assert 2 <= st.iters <= 40
+
+
+def test_heat_step_c0_direct(yk, ctx, oracle_lib):
+    import torch
+    cfg = W.config_c0()
+    b = cfg["bnd"]
+    bd = yk.Boundary.from_workload(b)
+    n = cfg["vol"].shape[0]
+    sig = torch.zeros(b.n, dtype=torch.float64, device="cuda")
+    u = torch.empty(n, dtype=torch.float64, device="cuda")
+    st = yk.yk_heat_step(ctx, bd, dev(cfg["vol"]), dev(cfg["vol_w"]), dev(cfg["B"]),
+                         yk.HEAT_GRID_SELF_CELL | yk.HEAT_ZERO_GUESS, dev(cfg["f_next"]),
+                         cfg["dt"], 1e-13, sig, u)
+    u_ref, s_ref, _ = oracle_lib.heat_step(b.xy, b.normal, b.weights(), b.curvature, cfg["vol"],
+                                           cfg["vol_w"], cfg["B"], cfg["f_next"], cfg["dt"],
+                                           grid_h=cfg["h"])
+    assert rel_max(host(u), u_ref) < 1e-10
+    assert rel_max(host(sig), s_ref) < 1e-10
+    # and the physics: close to the manufactured solution inside the domain, away from the boundary
+    inside = (cfg["region"] < 0) & (b.distance_to_boundary(cfg["vol"]) > 0.12)
+    assert np.max(np.abs(host(u)[inside] - cfg["u_exact_next"][inside])) < 1e-2
+
+
+def test_rhs_backward_euler(yk, ctx):
+    import torch
+    rng = np.random.default_rng(1)
+    u = rng.standard_normal(1000); F = rng.standard_normal(1000)
+    reg = rng.integers(-1, 4, size=1000).astype(np.int32)
+    c = np.array([0.0, 1.0, -0.5, 0.25])
+    B = torch.empty(1000, dtype=torch.float64, device="cuda")
+    yk.yk_rhs_backward_euler(ctx, dev(u), dev(F), dev(reg), c, 0.01, B)
+    ref = np.where(reg < 0, u + 0.01 * F, c[np.maximum(reg, 0)])
+    assert np.array_equal(host(B), ref)
+
+
+def test_error_paths(yk, ctx):
+    import torch
+    cfg = W.config_c0(n_nodes=64, m=8)
+    b = cfg["bnd"]
+    bd = yk.Boundary.from_workload(b)
+    g = dev(np.ones(b.n))
+    sig = torch.zeros(b.n, dtype=torch.float64, device="cuda")
+    # max_iter = 1 with tol = 0 cannot converge: NOCONV, iterate still written
+    st = yk.yk_gmres_density(ctx, bd, 0.1, g, None, 0.0, 1, sig, raise_on_noconv=False)
+    assert st.iters == 1 and np.all(np.isfinite(host(sig))) and np.any(host(sig) != 0)
+    with pytest.raises(yk.YkError) as e:
+        yk.yk_gmres_density(ctx, bd, 0.1, g, None, 0.0, 1, sig)
+    assert e.value.status == yk.YK_ERR_NOCONV
+    # non-finite data
+    gbad = np.ones(b.n); gbad[5] = np.nan
+    with pytest.raises(yk.YkError) as e:
+        yk.yk_gmres_density(ctx, bd, 0.1, dev(gbad), None, 1e-10, 50, sig)
+    assert e.value.status == yk.YK_ERR_NONFINITE
+    # invalid alpha
+    with pytest.raises(yk.YkError) as e:
+        yk.yk_gmres_density(ctx, bd, -1.0, g, None, 1e-10, 50, sig)
+    assert e.value.status == yk.YK_ERR_ARG
