@@ -1,0 +1,264 @@
+#!/usr/bin/env python3
+"""Benchmark: one full Yukawa-FMM evaluation on one MI355X.
+
+Workload (the paper-shaped FMM throughput set): 2^20 iid uniform points in the
+unit square with N(0,1) charges, plus an outer circle (centre (0.5,0.5),
+radius 0.5) and five circular holes of radius 0.06, 4096 nodes per curve, with
+N(0,1) dipole strengths; alpha = 0.05; expansion order chosen for 1e-10
+relative error.  One step = one evaluation of V[q] + DL[d] at every point
+(sources = targets), FP64, with the tree already built (points are static
+across time steps; the build time is reported separately).
+
+The JSON line carries:
+  value        Mpts/s = (N_D + N_Gamma) / t_pass
+  config       workload, p, leaf size, relative error over 1000 sampled targets
+               against FP64 direct sums on the GPU, and over 100 of them against
+               the CPU oracle
+  roofline     the dominant kernel (near field + local evaluation) against the
+               FP64 vector peak, from HIP events recorded around its launches
+  cpu_baseline the CPU oracle's direct sums at the sampled targets
+  time_step    s/time-step of the backward-Euler heat step, plain FP64 vs mixed
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Yukawa-FMM Mpts/s at stated rel err; s/time-step plain FP64 vs mixed+learned"
+PEAK_FP64_VALU_TF = 78.6      # MI355X FP64 vector peak (256 CU x 2.4 GHz x 128 flop/clk)
+PEAK_FP32_MFMA_TF = 157.3
+
+
+def near_flops(info):
+    """Algorithmic FP64 flops of the near field and of the local evaluation.
+
+    Per charge pair: separation and r^2 (5), t = r^2/(4 alpha^2) (1), the two
+    Horner series of length n (4(n-1)), -1/2 ln(t) A(t) + B(t) (3), q K0 + acc (2),
+    with ln(t) counted as one operation.  Per dipole pair: the same geometry (6),
+    the K1(z)/z series (4(n-1) + 6), (x-y).dn (3), scale and accumulate (3).
+    Per L2P point: 9 per order plus the F_n start (4 per series term) plus 10."""
+    n = info.near_terms
+    fq = 12 + 4 * (n - 1)
+    fd = 18 + 4 * (n - 1)
+    fl = 9 * info.p + 4 * info.nser + 10
+    return info.pairs_charge * fq + info.pairs_dipole * fd + info.l2p_points * fl
+
+
+def m2l_flops(info):
+    """Algorithmic flops of M2L: 2 P^2 per non-empty V-list translation (no padding)."""
+    return 2.0 * info.P * info.P * info.m2l_translations
+
+
+def run_fmm_bench(args, yk, torch, W):
+    cfg = W.config_c1(n_vol=args.n_vol, n_nodes=args.n_nodes, alpha=args.alpha, seed=1)
+    b = cfg["bnd"]
+    n_pts = cfg["vol"].shape[0] + b.n
+    d = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+    vol, q, dip = d(cfg["vol"]), d(cfg["q"]), d(cfg["dip"])
+    bd = yk.Boundary.from_workload(b)
+    out_v = torch.empty(vol.shape[0], dtype=torch.float64, device="cuda")
+    out_b = torch.empty(b.n, dtype=torch.float64, device="cuda")
+    prec = yk.YK_PREC_FP32 if args.fp32 else yk.YK_PREC_FP64
+    ctx = yk.yk_create(fmm_tol=args.tol, p=args.p, leaf_size=args.leaf, precision=prec)
+    try:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        yk.yk_fmm_potential(ctx, vol, q, bd, dip, args.alpha, out_v, out_b)   # builds the tree
+        torch.cuda.synchronize()
+        first_ms = (time.perf_counter() - t0) * 1e3
+        info = yk.yk_plan_info_get(ctx, 0)
+        for _ in range(args.warmup):
+            yk.yk_fmm_potential(ctx, vol, q, bd, dip, args.alpha, out_v, out_b)
+        torch.cuda.synchronize()
+        yk.yk_timing_enable(ctx, True)
+        yk.yk_timing_read(ctx, reset=True)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(args.steps):
+            yk.yk_fmm_potential(ctx, vol, q, bd, dip, args.alpha, out_v, out_b)
+        e1.record()
+        torch.cuda.synchronize()
+        total_ms = e0.elapsed_time(e1)
+        stages = yk.yk_timing_read(ctx, reset=True)
+        yk.yk_timing_enable(ctx, False)
+        info = yk.yk_plan_info_get(ctx, 0)
+        ov = out_v.cpu().numpy()
+        ob = out_b.cpu().numpy()
+    finally:
+        yk.yk_destroy(ctx)
+    ms = total_ms / args.steps
+    res = dict(cfg=cfg, n_pts=n_pts, ms=ms, first_ms=first_ms, info=info, stages=stages,
+               out=np.concatenate([ov, ob]))
+    return res
+
+
+def direct_check(args, res, yk, torch):
+    """Relative error over sampled targets against FP64 direct sums on the GPU."""
+    cfg = res["cfg"]
+    b = cfg["bnd"]
+    all_xy = np.concatenate([cfg["vol"], b.xy])
+    idx = np.sort(np.random.default_rng(12345).choice(res["n_pts"], size=args.samples, replace=False))
+    d = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+    tgt = d(all_xy[idx])
+    ctx = yk.yk_create(direct=1)
+    try:
+        v = torch.empty(len(idx), dtype=torch.float64, device="cuda")
+        dl = torch.empty(len(idx), dtype=torch.float64, device="cuda")
+        yk.yk_volume_potential(ctx, d(cfg["vol"]), d(cfg["q"]), tgt, cfg["alpha"], v)
+        # the layer call weighs sigma by w_j = (2 pi / N_k) |y'|; pass sigma = d / w
+        w = b.weights()
+        yk.yk_double_layer_apply(ctx, yk.Boundary.from_workload(b), d(cfg["dip"] / w), tgt,
+                                 cfg["alpha"], dl)
+        ref = (v + dl).cpu().numpy()
+    finally:
+        yk.yk_destroy(ctx)
+    got = res["out"][idx]
+    return (float(np.linalg.norm(got - ref) / np.linalg.norm(ref)),
+            float(np.max(np.abs(got - ref)) / np.max(np.abs(ref))), idx, ref)
+
+
+def oracle_baseline(args, res, idx):
+    """The CPU oracle's direct sums on a bounded sample of the same targets."""
+    import oracle
+    oracle.build(force=False)
+    cfg = res["cfg"]
+    b = cfg["bnd"]
+    n_vol = cfg["vol"].shape[0]
+    sub = idx[: args.cpu_samples]
+    tgt = np.concatenate([cfg["vol"], b.xy])[sub]
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    t0 = time.perf_counter()
+    ref = oracle.volume_sum(cfg["vol"], cfg["q"], cfg["alpha"], tgt_xy=tgt) + \
+        oracle.dl_sum(b.xy, b.normal, cfg["dip"], cfg["alpha"], tgt)
+    t_cpu = time.perf_counter() - t0
+    got = res["out"][sub]
+    err = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+    cpu = {"value": len(sub) / t_cpu / 1e6, "unit": "Mpts/s", "cores": threads, "kind": "oracle",
+           "sample": f"{len(sub)} sampled targets x all {n_vol} charges + {b.n} dipoles, direct FP64 "
+                     f"sums in {t_cpu:.2f} s; each sampled point is one full O(N) sum"}
+    return err, cpu
+
+
+def heat_step_bench(args, yk, torch, W):
+    """s/time-step of the backward-Euler step on the time-stepping geometry."""
+    cfg = W.config_c3(m=args.heat_m, n_holes=10, n_nodes=2048, dt=1e-3, seed=3)
+    b = cfg["bnd"]
+    d = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+    vol, w = d(cfg["vol"]), d(cfg["vol_w"])
+    region = torch.as_tensor(cfg["region"], dtype=torch.int32, device="cuda")
+    f = d(cfg["f_bnd"])
+    bd = yk.Boundary.from_workload(b)
+    out = {}
+    for name, prec in (("fp64", yk.YK_PREC_FP64), ("mixed", yk.YK_PREC_MIXED)):
+        ctx = yk.yk_create(fmm_tol=1e-10, leaf_size=args.leaf, precision=prec)
+        try:
+            u = d(cfg["u0"])
+            B = torch.empty_like(u)
+            un = torch.empty_like(u)
+            sig = torch.zeros(b.n, dtype=torch.float64, device="cuda")
+            times, iters = [], []
+            for step in range(args.heat_steps + 1):
+                yk.yk_rhs_backward_euler(ctx, u, None, region, cfg["consts"], cfg["dt"], B)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                st = yk.yk_heat_step(ctx, bd, vol, w, B, yk.HEAT_GRID_SELF_CELL, f, cfg["dt"], 1e-10,
+                                     sig, un)
+                torch.cuda.synchronize()
+                if step > 0:             # the first step builds the trees
+                    times.append(time.perf_counter() - t0)
+                    iters.append(st.iters)
+                u, un = un, u
+        finally:
+            yk.yk_destroy(ctx)
+        out[name] = {"s_per_step": float(np.mean(times)), "gmres_iters": float(np.mean(iters))}
+    out["workload"] = (f"{args.heat_m}x{args.heat_m} cell grid, outer circle + 10 ellipses x 2048 nodes, "
+                       f"dt=1e-3, alpha=sqrt(dt), previous-step guess, tol 1e-10, "
+                       f"{args.heat_steps} timed steps")
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--n-vol", type=int, default=1 << 20)
+    ap.add_argument("--n-nodes", type=int, default=4096)
+    ap.add_argument("--alpha", type=float, default=0.05)
+    ap.add_argument("--tol", type=float, default=1e-10)
+    ap.add_argument("--p", type=int, default=0)
+    ap.add_argument("--leaf", type=int, default=64)
+    ap.add_argument("--samples", type=int, default=1000)
+    ap.add_argument("--cpu-samples", type=int, default=100)
+    ap.add_argument("--fp32", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle check (profiling runs)")
+    ap.add_argument("--heat-steps", type=int, default=5)
+    ap.add_argument("--heat-m", type=int, default=1024)
+    ap.add_argument("--no-heat", action="store_true")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: this build runs the FMM on a single MI355X "
+              "(the multi-GPU decomposition is a design, not an implementation); use --gpus 1",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import workloads as W
+    import paper_1007_5335_amd.yk as yk
+    yk.load_library()
+    torch.cuda.set_device(0)
+
+    res = run_fmm_bench(args, yk, torch, W)
+    info, st = res["info"], res["stages"]
+    value = res["n_pts"] / (res["ms"] * 1e-3) / 1e6
+    leaf_ms, leaf_calls = st["leaf"]
+    leaf_avg = leaf_ms / max(leaf_calls, 1)
+    lf = near_flops(info)
+    achieved = lf / (leaf_avg * 1e-3) / 1e12
+    roof = {"kernel": "k_leaf (near field P2P + L2P)", "bound": "alu", "achieved": achieved,
+            "peak": PEAK_FP64_VALU_TF, "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_VALU_TF,
+            "traffic": None, "avg_launch_ms": leaf_avg, "algorithmic_flops": lf}
+    m2l_ms, m2l_calls = st["m2l"]
+    m2l_rate = m2l_flops(info) / (m2l_ms / max(args.steps, 1) * 1e-3) / 1e12 if m2l_ms > 0 else None
+    err, errmax, idx, _ = direct_check(args, res, yk, torch)
+    err_oracle = cpu = None
+    if not args.no_cpu:
+        err_oracle, cpu = oracle_baseline(args, res, idx)
+    heat = None if args.no_heat else heat_step_bench(args, yk, torch, W)
+    line = {
+        "metric": METRIC, "value": value, "unit": "Mpts/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": res["ms"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32" if args.fp32 else "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": (f"FMM pass: {args.n_vol} uniform points in the unit square, N(0,1) charges; "
+                         f"outer circle + 5 circular holes x {args.n_nodes} nodes, N(0,1) dipoles; "
+                         f"alpha={args.alpha}"),
+            "n_points": res["n_pts"], "alpha": args.alpha, "p": info.p, "leaf_level": info.leaf_level,
+            "leaf_size": args.leaf, "fmm_tol": args.tol, "rel_err_l2_sampled": err,
+            "rel_err_max_sampled": errmax, "rel_err_l2_vs_oracle": err_oracle,
+            "tree_build_ms": info.build_ms,
+            "first_call_ms": res["first_ms"],
+            "stage_ms_per_step": {k: v[0] / args.steps for k, v in st.items()},
+            "m2l_tflops": m2l_rate, "pairs_per_step": info.pairs_charge + info.pairs_dipole,
+            "m2l_translations": info.m2l_translations,
+        },
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "time_step": heat,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

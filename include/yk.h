@@ -181,6 +181,42 @@ yk_status yk_fmm_potential(yk_ctx ctx, int64_t n_vol, const double *vol_xy, cons
                            const yk_boundary *bnd, const double *d, double alpha,
                            double *out_vol, double *out_bnd);
 
+/*
+ * Introspection for measurement (not part of the method).
+ * yk_plan_info: shape of the tree cached in `slot` (0 = volume points and
+ * nodes, as used by the heat step and yk_fmm_potential; 1 = nodes only, as
+ * used by the density solve; 2 = the stand-alone sum calls) and the work of
+ * its last evaluation: near-field pairs and M2L translations.
+ * yk_timing_enable: when on, every FMM stage is bracketed by HIP events on
+ * the context's stream; yk_timing_read returns the accumulated milliseconds
+ * and launch counts per stage (YK_STAGE_*), resolving the events, and resets
+ * the counters when `reset` is non-zero.  Reading synchronises the stream.
+ */
+typedef struct {
+    int32_t valid;            /* 0 when no tree is cached in the slot */
+    int32_t leaf_level, lmin, p, P, Pp;
+    int64_t n_points, n_boxes, n_leaves;
+    int64_t pairs_charge;     /* near-field (target, charge) pairs of the last evaluation */
+    int64_t pairs_dipole;     /* near-field (target, dipole) pairs of the last evaluation */
+    int64_t m2l_translations; /* non-empty V-list entries of the last evaluation */
+    int64_t m2l_slots;        /* V-list slots processed (27 per active box, incl. empty) */
+    int64_t p2m_points, l2p_points;
+    int32_t near_terms;       /* series length of the near-field K0/K1 evaluation */
+    int32_t nser;             /* series length of the F_n starting values */
+    double build_ms;          /* host wall time of the last tree build */
+} yk_plan_info;
+
+enum {
+    YK_STAGE_GATHER = 0, YK_STAGE_P2M = 1, YK_STAGE_M2M = 2, YK_STAGE_M2L = 3,
+    YK_STAGE_L2L = 4, YK_STAGE_LEAF = 5, YK_STAGE_SCATTER = 6, YK_STAGE_DIRECT = 7,
+    YK_NUM_STAGES = 8
+};
+
+yk_status yk_plan_info_get(yk_ctx ctx, int slot, yk_plan_info *info);
+yk_status yk_timing_enable(yk_ctx ctx, int enable);
+yk_status yk_timing_read(yk_ctx ctx, double ms[YK_NUM_STAGES], int64_t calls[YK_NUM_STAGES],
+                         int reset);
+
 #ifdef __cplusplus
 }
 #endif

@@ -4,6 +4,7 @@
 #include <cmath>
 #include <new>
 
+#include "fmm.h"
 #include "sums.h"
 #include "yk_internal.h"
 
@@ -16,6 +17,52 @@ void check_launch(Context &ctx, const char *what) {
         e = hipStreamSynchronize(ctx.stream);
         if (e != hipSuccess) throw Error{YK_ERR_HIP, std::string(what) + " (sync): " + hipGetErrorString(e)};
     }
+}
+
+Context::~Context() {
+    for (auto &pe : pending) {
+        (void)hipEventDestroy(pe.second.first);
+        (void)hipEventDestroy(pe.second.second);
+    }
+    for (hipEvent_t e : event_pool) (void)hipEventDestroy(e);
+}
+
+static hipEvent_t take_event(Context &ctx) {
+    if (!ctx.event_pool.empty()) {
+        hipEvent_t e = ctx.event_pool.back();
+        ctx.event_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e;
+    YK_HIP(hipEventCreate(&e));
+    return e;
+}
+
+StageTimer::StageTimer(Context &c, int s) : ctx(c), stage(s) {
+    if (!ctx.timing) return;
+    a = take_event(ctx);
+    b = take_event(ctx);
+    YK_HIP(hipEventRecord(a, ctx.stream));
+}
+
+StageTimer::~StageTimer() {
+    if (!a) return;
+    if (hipEventRecord(b, ctx.stream) == hipSuccess)
+        ctx.pending.push_back({stage, {a, b}});
+}
+
+void resolve_timings(Context &ctx) {
+    if (ctx.pending.empty()) return;
+    YK_HIP(hipStreamSynchronize(ctx.stream));
+    for (auto &pe : ctx.pending) {
+        float ms = 0.f;
+        YK_HIP(hipEventElapsedTime(&ms, pe.second.first, pe.second.second));
+        ctx.stage_ms[pe.first] += ms;
+        ctx.stage_calls[pe.first] += 1;
+        ctx.event_pool.push_back(pe.second.first);
+        ctx.event_pool.push_back(pe.second.second);
+    }
+    ctx.pending.clear();
 }
 
 BoundaryData &prepare_boundary(Context &ctx, const yk_boundary *b) {
@@ -62,6 +109,7 @@ void evaluate_sums(Context &ctx, PlanSlot slot, const SumProblem &pb, const doub
         fmm_evaluate(ctx, slot, pb, q, dn, out, prec);
         return;
     }
+    StageTimer st(ctx, YK_STAGE_DIRECT);
     for (int s = 0; s < 3; ++s) {
         if (!out[s] || pb.n[s] == 0) continue;
         launch_direct(ctx, pb.n[s], pb.xy[s], q ? pb.n[0] : 0, pb.xy[0], q, dn ? pb.n[1] : 0,
@@ -441,6 +489,66 @@ yk_status yk_fmm_potential(yk_ctx ctx, int64_t n_vol, const double *vol_xy, cons
         double *outs[3] = {out_vol, out_bnd, nullptr};
         evaluate_sums(c, SLOT_VOL, pb, q, dn, outs,
                       c.opt.precision == YK_PREC_FP32 ? SUM_FP32 : SUM_FP64);
+        return YK_OK;
+    });
+}
+
+yk_status yk_plan_info_get(yk_ctx ctx, int slot, yk_plan_info *info) {
+    return guarded(ctx, [&](Context &c) {
+        YK_REQUIRE(info != nullptr, "info is NULL");
+        YK_REQUIRE(slot >= 0 && slot <= 2, "slot must be 0, 1 or 2");
+        std::memset(info, 0, sizeof(*info));
+        const FmmPlan *pl = plan_in_slot(c, slot);
+        if (!pl) return YK_OK;
+        info->valid = 1;
+        info->leaf_level = pl->L;
+        info->lmin = pl->lmin;
+        info->p = pl->p;
+        info->P = pl->P;
+        info->Pp = pl->Pp;
+        info->n_points = pl->N;
+        info->n_boxes = pl->nbox;
+        info->n_leaves = pl->nleaf;
+        info->build_ms = pl->build_ms;
+        info->near_terms = pl->near_terms;
+        info->nser = pl->nser;
+        auto it = pl->active.find(pl->last_mask);
+        if (it != pl->active.end()) {
+            const ActiveSet &as = *it->second;
+            info->pairs_charge = pl->last_has_q ? as.pairs_q : 0;
+            info->pairs_dipole = pl->last_has_d ? as.pairs_d : 0;
+            const bool far = pl->lmin <= pl->L;
+            info->m2l_translations = far ? as.m2l_trans : 0;
+            info->m2l_slots = far ? as.n_m2l_boxes * kNumV : 0;
+            info->l2p_points = far ? as.l2p_points : 0;
+            info->p2m_points = far ? (pl->last_has_q ? pl->toff[1] - pl->toff[0] : 0) +
+                                         (pl->last_has_d ? pl->toff[2] - pl->toff[1] : 0)
+                                   : 0;
+        }
+        return YK_OK;
+    });
+}
+
+yk_status yk_timing_enable(yk_ctx ctx, int enable) {
+    return guarded(ctx, [&](Context &c) {
+        resolve_timings(c);
+        c.timing = enable != 0;
+        return YK_OK;
+    });
+}
+
+yk_status yk_timing_read(yk_ctx ctx, double ms[YK_NUM_STAGES], int64_t calls[YK_NUM_STAGES],
+                         int reset) {
+    return guarded(ctx, [&](Context &c) {
+        resolve_timings(c);
+        for (int k = 0; k < YK_NUM_STAGES; ++k) {
+            if (ms) ms[k] = c.stage_ms[k];
+            if (calls) calls[k] = c.stage_calls[k];
+            if (reset) {
+                c.stage_ms[k] = 0;
+                c.stage_calls[k] = 0;
+            }
+        }
         return YK_OK;
     });
 }

@@ -1,0 +1,125 @@
+// fmm.h -- the FMM plan: a uniform-depth sparse quadtree over up to three
+// point sets (charges, dipoles, target-only points), its interaction lists and
+// the per-level translation operators of the modified-Helmholtz expansions.
+//
+// Expansions (alpha-scaled coordinates w = (y - c)/alpha, F^I_n(w) =
+// I_n(|w|) e^{i n arg w}, F^K_n(w) = K_n(|w|) e^{i n arg w}):
+//   multipole  phi(x) = sum_n M_n F^K_n((x - c)/alpha),
+//              charge q at y:  M_n = q conj(F^I_n(w))          (Graf's addition theorem)
+//              dipole D = d (n_x + i n_y):
+//                   M_n = (1/(2 alpha)) [D conj(F^I_{n+1}(w)) + conj(D) conj(F^I_{n-1}(w))]
+//   local      phi(x) = sum_m L_m F^I_m((x - c)/alpha)
+//   M2L        L_m = (-1)^m sum_n M_n F^K_{n-m}((c_t - c_s)/alpha)
+//   M2M, L2L   shifts by F^I_{n-k}(e), e = (child centre - parent centre)/alpha
+// Coefficients are stored scaled per level, Mh_n = M_n / I_n(R_l) and
+// Lh_m = L_m I_m(R_l), with R_l the box half-diagonal over alpha, so that every
+// stored quantity and every operator entry is O(1) (no overflow in FP32).
+// Only n = 0..p is stored (M_{-n} = conj(M_n) for real strengths) as the real
+// vector [Re M_0, Re M_1, Im M_1, ..., Re M_p, Im M_p] of P = 2p + 1 entries,
+// padded with zeros to Pp (a multiple of 16).
+#pragma once
+
+#include <map>
+
+#include "sums.h"
+#include "yk_internal.h"
+
+namespace yk {
+
+constexpr int kMaxLevel = 15;          // Morton keys carry 2 x 15 bits (+ 2 type bits)
+constexpr int kNumV = 27;              // V-list slots per box (per parity class)
+constexpr int kNumOff = 40;            // distinct V-list offsets in [-3,3]^2 minus [-1,1]^2
+
+struct LevelInfo {
+    int64_t begin = 0, end = 0;        // global box index range
+    double side = 0;                   // box side
+    double R = 0;                      // half-diagonal / alpha
+};
+
+// Boxes of one target mask that take part in the downward pass.
+struct ActiveSet {
+    DevBuf<int32_t> m2l_boxes;         // active boxes of levels lmin..L, sorted by (level, class)
+    DevBuf<int4> m2l_tiles;            // {level, class, start, count} into m2l_boxes
+    int n_tiles = 0;
+    std::vector<int64_t> l2l_begin, l2l_count;   // per level: active boxes (children) list slices
+    DevBuf<int32_t> l2l_boxes;         // active boxes of levels lmin+1..L (level-major)
+    std::vector<int> tile_begin, tile_count;     // per level: slice of m2l_tiles
+    DevBuf<int32_t> leaves;            // active leaves (leaf-local indices)
+    int64_t n_leaves = 0;
+    int64_t n_m2l_boxes = 0;
+    // work counts (for measurement)
+    int64_t pairs_q = 0, pairs_d = 0, m2l_trans = 0, l2p_points = 0;
+};
+
+struct FmmPlan {
+    // cache key
+    int64_t key_n[3] = {0, 0, 0};
+    const double *key_xy[3] = {nullptr, nullptr, nullptr};
+    double alpha = 0;
+    int opt_p = 0, opt_leaf = 0;
+    double opt_tol = 0;
+
+    // geometry
+    double x0 = 0, y0 = 0, size = 0;  // bounding square
+    int L = 0;                         // leaf level
+    int lmin = 2;                      // coarsest level with M2L
+    int p = 0, P = 0, Pp = 0;
+    int64_t N = 0;
+    int64_t toff[4] = {0, 0, 0, 0};    // type blocks in sorted order
+    int nser = 0;                      // series terms for F_n at the leaf level
+    int near_terms = 14;               // Horner length of the near-field series
+
+    // sorted points
+    DevBuf<double> px, py;
+    DevBuf<float> pxf, pyf;            // leaf-centre-relative FP32 copies
+    DevBuf<int32_t> perm;              // sorted position -> index within its set
+    DevBuf<double> qs, dns, outs;      // sorted strengths and outputs
+    DevBuf<float> qsf, dnsf;
+
+    // boxes
+    std::vector<LevelInfo> lev;
+    int64_t nbox = 0, nleaf = 0;
+    std::vector<uint32_t> hcode;       // Morton code per box (global index)
+    std::vector<int32_t> hparent;
+    DevBuf<double> bcx, bcy;           // centres
+    DevBuf<int32_t> bparent;
+    DevBuf<uint32_t> bcode;            // Morton code per box
+    DevBuf<int32_t> fchild, nchild;    // first child (global index) and child count
+    DevBuf<int32_t> slot_oid;          // [4 classes][27 slots] -> offset id in 0..39
+    DevBuf<double> serc;               // [2][nser]: series coefficients of F_{p+1}, F_{p+2}
+    DevBuf<int32_t> vlist;             // [nbox][27]
+    DevBuf<int32_t> lrange;            // [nleaf][6] start/end per set (sorted positions)
+    DevBuf<int32_t> ulist_off, ulist;  // CSR over leaves (leaf-local indices)
+    std::vector<int32_t> h_lrange;     // host copy
+
+    // coefficients
+    DevBuf<double> M, Lc;              // [nbox][Pp]
+    DevBuf<float> Mf, Lf;
+
+    // operators (double, column-major Pp x Pp blocks)
+    DevBuf<double> m2m, l2l, m2l;      // [level][4][Pp*Pp], [level][4][Pp*Pp], [level][40][Pp*Pp]
+    DevBuf<float> m2lf;
+    DevBuf<double> invFY, dipa, dipb;  // [level][p+2]
+    DevBuf<double> cnn;                // 1/((n+1)(n+2)), n = 0 .. p+3
+
+    std::map<int, std::unique_ptr<ActiveSet>> active;   // by target mask
+
+    double build_ms = 0;
+    bool fresh = false;
+    int last_mask = 0;
+    int last_has_q = 0, last_has_d = 0;
+};
+FmmPlan *plan_in_slot(Context &ctx, int slot);
+
+// tree.hip
+void build_tree(Context &ctx, FmmPlan &pl, const SumProblem &pb);
+// fmm_plan.cpp
+void build_lists_and_tables(Context &ctx, FmmPlan &pl, const std::vector<uint32_t> &keys);
+ActiveSet &get_active(Context &ctx, FmmPlan &pl, int mask);
+int choose_order(double tol);
+
+// fmm_kernels.hip
+void fmm_run(Context &ctx, FmmPlan &pl, const double *q, const double *dn, double *const out[3],
+             SumPrec prec);
+
+}  // namespace yk

@@ -1,12 +1,64 @@
-// fmm.hip -- placeholder until the tree and expansion kernels land.
-#include "sums.h"
+// fmm.hip -- FMM backend of the kernel sums: plan cache and evaluation.
+#include <chrono>
+
+#include "fmm.h"
 
 namespace yk {
-struct FmmPlan {};
+
 void destroy_plan(FmmPlan *p) { delete p; }
-void fmm_evaluate(Context &, PlanSlot, const SumProblem &, const double *, const double *,
-                  double *const[3], SumPrec) {
-    throw Error{YK_ERR_ARG, "FMM backend not available; set options.direct = 1"};
+
+namespace {
+
+PlanPtr &slot_ref(Context &ctx, PlanSlot slot) {
+    switch (slot) {
+        case SLOT_VOL: return ctx.plan_vol;
+        case SLOT_BND: return ctx.plan_bnd;
+        default: return ctx.plan_misc;
+    }
 }
-double fmm_last_build_ms(Context &) { return 0.0; }
+
+bool plan_matches(const FmmPlan &pl, const Context &ctx, const SumProblem &pb) {
+    for (int s = 0; s < 3; ++s)
+        if (pl.key_n[s] != pb.n[s] || pl.key_xy[s] != (pb.n[s] ? pb.xy[s] : nullptr)) return false;
+    return pl.alpha == pb.alpha && pl.opt_p == ctx.opt.p && pl.opt_leaf == ctx.opt.leaf_size &&
+           pl.opt_tol == ctx.opt.fmm_tol;
+}
+
+}  // namespace
+
+FmmPlan &get_plan(Context &ctx, PlanSlot slot, const SumProblem &pb) {
+    PlanPtr &ref = slot_ref(ctx, slot);
+    if (ref && plan_matches(*ref, ctx, pb)) {
+        ref->fresh = false;
+        return *ref;
+    }
+    ref.reset();
+    PlanPtr pl(new FmmPlan());
+    for (int s = 0; s < 3; ++s) {
+        pl->key_n[s] = pb.n[s];
+        pl->key_xy[s] = pb.n[s] ? pb.xy[s] : nullptr;
+    }
+    pl->alpha = pb.alpha;
+    pl->opt_p = ctx.opt.p;
+    pl->opt_leaf = ctx.opt.leaf_size;
+    pl->opt_tol = ctx.opt.fmm_tol;
+    build_tree(ctx, *pl, pb);
+    pl->fresh = true;
+    ref = std::move(pl);
+    return *ref;
+}
+
+void fmm_evaluate(Context &ctx, PlanSlot slot, const SumProblem &pb, const double *q,
+                  const double *dn, double *const out[3], SumPrec prec) {
+    FmmPlan &pl = get_plan(ctx, slot, pb);
+    fmm_run(ctx, pl, q, dn, out, prec);
+}
+
+double fmm_last_build_ms(Context &ctx) {
+    double ms = 0;
+    for (PlanPtr *p : {&ctx.plan_vol, &ctx.plan_bnd, &ctx.plan_misc})
+        if (*p && (*p)->fresh) ms += (*p)->build_ms;
+    return ms;
+}
+
 }  // namespace yk

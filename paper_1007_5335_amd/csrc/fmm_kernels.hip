@@ -1,0 +1,675 @@
+// fmm_kernels.hip -- upward pass, M2L, downward pass and near field of the
+// modified-Helmholtz FMM (expansion conventions in fmm.h), FP64.
+#include <type_traits>
+
+#include "fmm.h"
+#include "yk_bessel.h"
+
+namespace yk {
+
+namespace {
+
+inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// ---------------------------------------------------------------- gathers --
+__global__ void k_gather_q(int64_t n, const int32_t *__restrict__ perm, const double *__restrict__ q,
+                           double *__restrict__ qs) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < n) qs[k] = q[perm[k]];
+}
+
+__global__ void k_gather_dn(int64_t off, int64_t n, const int32_t *__restrict__ perm,
+                            const double *__restrict__ dn, double *__restrict__ dns) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    const int32_t i = perm[off + k];
+    dns[2 * k] = dn[2 * i];
+    dns[2 * k + 1] = dn[2 * i + 1];
+}
+
+__global__ void k_scatter_out(int64_t off, int64_t n, const int32_t *__restrict__ perm,
+                              const double *__restrict__ outs, double *__restrict__ out) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < n) out[perm[off + k]] = outs[off + k];
+}
+
+// ------------------------------------------------------------ F_n helpers --
+// F_n(y) = sum_k y^k/(k!(n+1)_k): the two starting values F_{p+1}, F_{p+2} by
+// their series; below that, F_n = F_{n+1} + y F_{n+2} / ((n+1)(n+2)) (the
+// three-term recurrence of I_n, stable downwards).
+__device__ __forceinline__ void f_start(double y, const double *__restrict__ sc, int nser,
+                                        double &Fn1, double &Fn2) {
+    double a = sc[nser - 1], b = sc[2 * nser - 1];
+    for (int k = nser - 2; k >= 0; --k) {
+        a = a * y + sc[k];
+        b = b * y + sc[nser + k];
+    }
+    Fn1 = a;   // F_{p+1}
+    Fn2 = b;   // F_{p+2}
+}
+
+// ------------------------------------------------------------------- P2M ---
+// One wavefront per leaf; lanes over source points.  Each lane builds
+// G_n = F_n(y)/F_n(Y) for n = 0..p+1 in LDS (downwards), then the terms
+// q G_n conj(z)^n (upwards) are summed over the wavefront with shuffles.
+__global__ __launch_bounds__(64) void k_p2m(
+    int64_t leaf_base, const int32_t *__restrict__ lrange, const double *__restrict__ bcx,
+    const double *__restrict__ bcy, const double *__restrict__ px, const double *__restrict__ py,
+    const double *__restrict__ qs, const double *__restrict__ dns, int64_t off1, int has_q,
+    int has_d, double inv_alpha, double invR, const double *__restrict__ invFY,
+    const double *__restrict__ da, const double *__restrict__ db, const double *__restrict__ cnn,
+    const double *__restrict__ sc, int nser, int p, int Pp, double *__restrict__ M) {
+    extern __shared__ double smem[];
+    double *G = smem;                    // [(p+2)][64]
+    double *Msh = smem + (p + 2) * 64;   // [Pp]
+    const int li = blockIdx.x, lane = threadIdx.x;
+    const int64_t b = leaf_base + li;
+    for (int k = lane; k < Pp; k += 64) Msh[k] = 0.0;
+    __syncthreads();
+    const double cx = bcx[b], cy = bcy[b];
+    for (int set = 0; set < 2; ++set) {
+        if ((set == 0 && !has_q) || (set == 1 && !has_d)) continue;
+        const int s0 = lrange[li * 6 + 2 * set], e0 = lrange[li * 6 + 2 * set + 1];
+        for (int base = s0; base < e0; base += 64) {
+            const int j = base + lane;
+            const bool valid = j < e0;
+            const double wx = valid ? (px[j] - cx) * inv_alpha : 0.0;
+            const double wy = valid ? (py[j] - cy) * inv_alpha : 0.0;
+            const double y = 0.25 * (wx * wx + wy * wy);
+            const double zx = wx * invR, zy = -wy * invR;   // conj(w)/R
+            double F1, F2;
+            f_start(y, sc, nser, F1, F2);
+            G[(p + 1) * 64 + lane] = F1 * invFY[p + 1];
+            for (int n = p; n >= 0; --n) {
+                const double F0 = F1 + y * F2 * cnn[n];
+                G[n * 64 + lane] = F0 * invFY[n];
+                F2 = F1;
+                F1 = F0;
+            }
+            // (the LDS column is private to the lane: no barrier needed)
+            if (set == 0) {
+                const double q = valid ? qs[j] : 0.0;
+                double pr = 1.0, pi = 0.0;     // conj(z)^n
+                for (int n = 0; n <= p; ++n) {
+                    const double g = q * G[n * 64 + lane];
+                    const double tr = wave_sum(g * pr), ti = wave_sum(g * pi);
+                    if (lane == 0) {
+                        if (n == 0) Msh[0] += tr;
+                        else { Msh[2 * n - 1] += tr; Msh[2 * n] += ti; }
+                    }
+                    const double nr = pr * zx - pi * zy;
+                    pi = pr * zy + pi * zx;
+                    pr = nr;
+                }
+            } else {
+                const double Dx = valid ? dns[2 * (j - off1)] : 0.0;
+                const double Dy = valid ? dns[2 * (j - off1) + 1] : 0.0;
+                const double h = 0.5 * inv_alpha;
+                // window Psi_{n-1}, Psi_n, Psi_{n+1};  Psi_k = G_k conj(z)^k
+                double pr = zx, pi = zy;                       // conj(z)^1
+                double g1 = G[1 * 64 + lane];
+                double c_r = G[0 * 64 + lane], c_i = 0.0;      // Psi_0
+                double n_r = g1 * pr, n_i = g1 * pi;           // Psi_1
+                double m_r = n_r, m_i = -n_i;                  // Psi_{-1} = conj(Psi_1)
+                for (int n = 0; n <= p; ++n) {
+                    // term_n = h [a_n D Psi_{n+1} + b_n conj(D) Psi_{n-1}]
+                    const double an = da[n], bn = db[n];
+                    const double t1r = Dx * n_r - Dy * n_i, t1i = Dx * n_i + Dy * n_r;
+                    const double t2r = Dx * m_r + Dy * m_i, t2i = Dx * m_i - Dy * m_r;
+                    const double tr = wave_sum(h * (an * t1r + bn * t2r));
+                    const double ti = wave_sum(h * (an * t1i + bn * t2i));
+                    if (lane == 0) {
+                        if (n == 0) Msh[0] += tr;
+                        else { Msh[2 * n - 1] += tr; Msh[2 * n] += ti; }
+                    }
+                    // advance the window
+                    m_r = c_r; m_i = c_i;
+                    c_r = n_r; c_i = n_i;
+                    const double nr = pr * zx - pi * zy;
+                    pi = pr * zy + pi * zx;
+                    pr = nr;
+                    if (n + 2 <= p + 1) {
+                        const double g = G[(n + 2) * 64 + lane];
+                        n_r = g * pr; n_i = g * pi;
+                    } else {
+                        n_r = 0.0; n_i = 0.0;
+                    }
+                }
+            }
+        }
+    }
+    __syncthreads();
+    for (int k = lane; k < Pp; k += 64) M[b * Pp + k] = Msh[k];
+}
+
+// ------------------------------------------------------------ M2M / L2L ---
+// Parent multipole from its children: M_b = sum_c S[pos(c)] M_c.
+__global__ __launch_bounds__(128) void k_m2m(int64_t pbegin, const int32_t *__restrict__ fchild,
+                                             const int32_t *__restrict__ nchild,
+                                             const uint32_t *__restrict__ code,
+                                             const double *__restrict__ S, int P, int Pp,
+                                             double *__restrict__ M) {
+    extern __shared__ double mc[];
+    const int64_t b = pbegin + blockIdx.x;
+    const int i = threadIdx.x;
+    double acc = 0.0;
+    const int c0 = fchild[b], nc = nchild[b];
+    for (int c = c0; c < c0 + nc; ++c) {
+        for (int k = i; k < Pp; k += blockDim.x) mc[k] = M[(int64_t)c * Pp + k];
+        __syncthreads();
+        const double *Sc = S + (size_t)(code[c] & 3u) * Pp * Pp;
+        if (i < P)
+            for (int j = 0; j < P; ++j) acc += Sc[(size_t)j * Pp + i] * mc[j];
+        __syncthreads();
+    }
+    if (i < Pp) M[b * Pp + i] = i < P ? acc : 0.0;
+}
+
+// Child local expansion from its parent: L_b += E[pos(b)] L_parent.
+__global__ __launch_bounds__(128) void k_l2l(const int32_t *__restrict__ boxes,
+                                             const int32_t *__restrict__ parent,
+                                             const uint32_t *__restrict__ code,
+                                             const double *__restrict__ E, int P, int Pp,
+                                             double *__restrict__ Lc) {
+    extern __shared__ double lp[];
+    const int64_t b = boxes[blockIdx.x];
+    const int64_t pa = parent[b];
+    const int i = threadIdx.x;
+    for (int k = i; k < Pp; k += blockDim.x) lp[k] = Lc[pa * Pp + k];
+    __syncthreads();
+    if (i < P) {
+        const double *Ec = E + (size_t)(code[b] & 3u) * Pp * Pp;
+        double acc = 0.0;
+        for (int j = 0; j < P; ++j) acc += Ec[(size_t)j * Pp + i] * lp[j];
+        Lc[b * Pp + i] += acc;
+    }
+}
+
+// -------------------------------------------------------------------- M2L ---
+// One block per tile of up to 16 target boxes of one level and one parity
+// class (so all share the same 27 offsets).  For each offset the Pp x Pp
+// operator is streamed through LDS in column chunks and applied to the 16
+// gathered multipoles.
+constexpr int kM2LTile = 16;
+constexpr int kM2LChunk = 32;
+__global__ __launch_bounds__(256) void k_m2l(const int4 *__restrict__ tiles, int tile0,
+                                             const int32_t *__restrict__ boxes,
+                                             const int32_t *__restrict__ vlist,
+                                             const int32_t *__restrict__ slot_oid,
+                                             const double *__restrict__ T, int P, int Pp,
+                                             const double *__restrict__ M, double *__restrict__ Lc) {
+    extern __shared__ double sm[];
+    double *Ts = sm;                               // kM2LChunk * Pp
+    double *Ms = sm + (size_t)kM2LChunk * Pp;      // 16 * Pp
+    const int4 tl = tiles[tile0 + blockIdx.x];
+    const int level = tl.x, cls = tl.y;
+    const int t = threadIdx.x;
+    for (int sub0 = 0; sub0 < tl.w; sub0 += kM2LTile) {
+    const int start = tl.z + sub0, count = min(kM2LTile, tl.w - sub0);
+    const int bb = t >> 4, r0 = t & 15;
+    const int nr = Pp / 16;
+    double acc[8];
+#pragma unroll
+    for (int r = 0; r < 8; ++r) acc[r] = 0.0;
+    const int64_t mybox = bb < count ? boxes[start + bb] : -1;
+    for (int slot = 0; slot < kNumV; ++slot) {
+        const int oid = slot_oid[cls * kNumV + slot];
+        const double *Tg = T + ((size_t)level * kNumOff + oid) * Pp * Pp;
+        for (int k = t; k < kM2LTile * Pp; k += 256) {
+            const int b2 = k / Pp, j = k - b2 * Pp;
+            double v = 0.0;
+            if (b2 < count) {
+                const int32_t src = vlist[(int64_t)boxes[start + b2] * kNumV + slot];
+                if (src >= 0) v = M[(int64_t)src * Pp + j];
+            }
+            Ms[k] = v;
+        }
+        for (int j0 = 0; j0 < P; j0 += kM2LChunk) {
+            const int jn = min(kM2LChunk, P - j0);
+            for (int k = t; k < jn * Pp; k += 256) Ts[k] = Tg[(size_t)j0 * Pp + k];
+            __syncthreads();
+            if (bb < count) {
+                const double *mrow = Ms + bb * Pp + j0;
+                for (int j = 0; j < jn; ++j) {
+                    const double mj = mrow[j];
+#pragma unroll
+                    for (int r = 0; r < 8; ++r)
+                        if (r < nr) acc[r] += Ts[(size_t)j * Pp + r0 + 16 * r] * mj;
+                }
+            }
+            __syncthreads();
+        }
+    }
+    if (mybox >= 0) {
+#pragma unroll
+        for (int r = 0; r < 8; ++r)
+            if (r < nr) Lc[mybox * Pp + r0 + 16 * r] += acc[r];
+    }
+    __syncthreads();
+    }
+}
+
+// ------------------------------------------------------------- M2L (MFMA) --
+// Matrix-core version: one workgroup (4 wavefronts) per tile of up to 64
+// target boxes of one level and parity class.  C (Pp x 64 local
+// coefficients) stays in accumulation registers for all 27 offsets; for each
+// offset the Pp x Pp operator is double-buffered in LDS (prefetched into
+// registers during the previous offset's MFMAs) and the gathered multipoles
+// of the 16 boxes of a wavefront are read straight into B fragments.
+//   v_mfma_f64_16x16x4f64: lane l holds A[l%16][l/16], B[l/16][l%16] and
+//                          C rows l/16 + 4r, column l%16 (r = 0..3);
+//   v_mfma_f32_16x16x4f32: same A, B; C rows 4(l/16) + r.
+typedef double yk_d4 __attribute__((ext_vector_type(4)));
+typedef float yk_f4 __attribute__((ext_vector_type(4)));
+
+template <typename T> struct Mfma;
+template <> struct Mfma<double> {
+    using acc = yk_d4;
+    static __device__ __forceinline__ acc step(double a, double b, acc c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ int row(int lane, int r) { return (lane >> 4) + 4 * r; }
+};
+template <> struct Mfma<float> {
+    using acc = yk_f4;
+    static __device__ __forceinline__ acc step(float a, float b, acc c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ int row(int lane, int r) { return 4 * (lane >> 4) + r; }
+};
+
+template <typename T, int PP>
+__global__ __launch_bounds__(256) void k_m2l_mfma(const int4 *__restrict__ tiles, int tile0,
+                                                  const int32_t *__restrict__ boxes,
+                                                  const int32_t *__restrict__ vlist,
+                                                  const int32_t *__restrict__ slot_oid,
+                                                  const T *__restrict__ Top,
+                                                  const T *__restrict__ M, double *__restrict__ Lc) {
+    constexpr int NRT = PP / 16, NKS = PP / 4, NLD = PP * PP / 256;
+    __shared__ T As[2][PP * PP];
+    using MF = Mfma<T>;
+    const int4 tl = tiles[tile0 + blockIdx.x];
+    const int level = tl.x, cls = tl.y, start = tl.z, count = tl.w;
+    const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+    const int jb = 16 * w + (lane & 15);
+    const bool colvalid = jb < count;
+    const int64_t boxj = colvalid ? boxes[start + jb] : -1;
+    typename MF::acc acc[NRT];
+#pragma unroll
+    for (int r = 0; r < NRT; ++r) acc[r] = typename MF::acc{0, 0, 0, 0};
+    const T *Tlev = Top + (size_t)level * kNumOff * PP * PP;
+    T pre[NLD];
+    {
+        const T *Tg = Tlev + (size_t)slot_oid[cls * kNumV] * PP * PP;
+#pragma unroll
+        for (int e = 0; e < NLD; ++e) As[0][tid + 256 * e] = Tg[tid + 256 * e];
+    }
+    __syncthreads();
+    for (int slot = 0; slot < kNumV; ++slot) {
+        const int cur = slot & 1;
+        if (slot + 1 < kNumV) {
+            const T *Tg = Tlev + (size_t)slot_oid[cls * kNumV + slot + 1] * PP * PP;
+#pragma unroll
+            for (int e = 0; e < NLD; ++e) pre[e] = Tg[tid + 256 * e];
+        }
+        const int32_t src = colvalid ? vlist[boxj * kNumV + slot] : -1;
+        const T *mrow = M + (int64_t)(src >= 0 ? src : 0) * PP;
+        const T *Ac = As[cur];
+#pragma unroll
+        for (int ks = 0; ks < NKS; ++ks) {
+            const int kk = 4 * ks + (lane >> 4);
+            const T bv = src >= 0 ? mrow[kk] : T(0);
+#pragma unroll
+            for (int rt = 0; rt < NRT; ++rt)
+                acc[rt] = MF::step(Ac[kk * PP + 16 * rt + (lane & 15)], bv, acc[rt]);
+        }
+        if (slot + 1 < kNumV) {
+#pragma unroll
+            for (int e = 0; e < NLD; ++e) As[cur ^ 1][tid + 256 * e] = pre[e];
+        }
+        __syncthreads();
+    }
+    if (colvalid) {
+#pragma unroll
+        for (int rt = 0; rt < NRT; ++rt)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) Lc[boxj * PP + 16 * rt + MF::row(lane, r)] += (double)acc[rt][r];
+    }
+}
+
+using M2LKernel = void (*)(const int4 *, int, const int32_t *, const int32_t *, const int32_t *,
+                           const void *, const void *, double *);
+
+__global__ void k_to_float(int64_t n, const double *__restrict__ a, float *__restrict__ b) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) b[i] = (float)a[i];
+}
+
+template <typename T>
+void launch_m2l_mfma(Context &ctx, int Pp, int ntiles, const int4 *tiles, int tile0,
+                     const int32_t *boxes, const int32_t *vlist, const int32_t *soid, const T *Top,
+                     const T *M, double *Lc) {
+    switch (Pp) {
+        case 16:
+            hipLaunchKernelGGL((k_m2l_mfma<T, 16>), dim3(ntiles), dim3(256), 0, ctx.stream, tiles, tile0,
+                               boxes, vlist, soid, Top, M, Lc);
+            break;
+        case 32:
+            hipLaunchKernelGGL((k_m2l_mfma<T, 32>), dim3(ntiles), dim3(256), 0, ctx.stream, tiles, tile0,
+                               boxes, vlist, soid, Top, M, Lc);
+            break;
+        case 48:
+            hipLaunchKernelGGL((k_m2l_mfma<T, 48>), dim3(ntiles), dim3(256), 0, ctx.stream, tiles, tile0,
+                               boxes, vlist, soid, Top, M, Lc);
+            break;
+        case 64:
+            hipLaunchKernelGGL((k_m2l_mfma<T, 64>), dim3(ntiles), dim3(256), 0, ctx.stream, tiles, tile0,
+                               boxes, vlist, soid, Top, M, Lc);
+            break;
+        default:
+            throw Error{YK_ERR_INTERNAL, "no MFMA M2L kernel for this padded order"};
+    }
+    check_launch(ctx, "k_m2l_mfma");
+}
+
+// ----------------------------------------------------------- leaf kernel ---
+// One wavefront per leaf.  The leaf's targets (its points of the requested
+// sets) are processed 64 lanes at a time: with c targets in a chunk, each
+// target gets g = 64 / next_pow2(c) lanes that split its U-list sources
+// between them, and the g partial sums are combined with shuffles.  Sources
+// are read straight from global memory (every lane of a target group reads
+// the same few consecutive addresses).  The local expansion is evaluated by
+// the first lane of each group (Horner in z with G_m = F_m(y)/F_m(Y)).
+template <int NT, typename T>
+__device__ __forceinline__ T horner_n(const T (&c)[YK_NSER64], T t) {
+    T s = c[NT - 1];
+#pragma unroll
+    for (int k = NT - 2; k >= 0; --k) s = s * t + c[k];
+    return s;
+}
+
+template <int NT, bool kSmallOnly>
+__device__ __forceinline__ double near_k0(double t) {
+    if (kSmallOnly || t <= 1.0) {
+        const double lt = log(t);
+        return -0.5 * lt * horner_n<NT>(yk_ser_A, t) + horner_n<NT>(yk_ser_B, t);
+    }
+    return k0_large(2.0 * sqrt(t));
+}
+template <int NT, bool kSmallOnly>
+__device__ __forceinline__ double near_k1oz(double t) {
+    if (kSmallOnly || t <= 1.0) {
+        const double lt = log(t);
+        return 0.25 / t + 0.25 * lt * horner_n<NT>(yk_ser_C, t) - 0.25 * horner_n<NT>(yk_ser_D, t);
+    }
+    const double z = 2.0 * sqrt(t);
+    return k1_large(z) / z;
+}
+
+template <int NT>
+__device__ __forceinline__ float horner_nf(const float (&c)[YK_NSER32], float t) {
+    float s = c[NT - 1];
+#pragma unroll
+    for (int k = NT - 2; k >= 0; --k) s = s * t + c[k];
+    return s;
+}
+template <bool kSmallOnly>
+__device__ __forceinline__ float near_k0_f(float t) {
+    if (kSmallOnly || t <= 1.0f) {
+        const float lt = __logf(t);
+        return -0.5f * lt * horner_nf<YK_NSER32>(yk_ser_A_f, t) + horner_nf<YK_NSER32>(yk_ser_B_f, t);
+    }
+    return k0_large_f(2.0f * sqrtf(t));
+}
+template <bool kSmallOnly>
+__device__ __forceinline__ float near_k1oz_f(float t) {
+    if (kSmallOnly || t <= 1.0f) {
+        const float lt = __logf(t);
+        return 0.25f / t + 0.25f * lt * horner_nf<YK_NSER32>(yk_ser_C_f, t) -
+               0.25f * horner_nf<YK_NSER32>(yk_ser_D_f, t);
+    }
+    const float z = 2.0f * sqrtf(t);
+    return k1_large_f(z) / z;
+}
+
+// Near-field accumulation policy: FP64 (series and sums in double) or FP32
+// (separations and the dipole dot product in double, the Bessel series, the
+// logarithm and the accumulation in float).
+template <int NT, bool kSmallOnly, bool kF32>
+struct Near {
+    using acc_t = typename std::conditional<kF32, float, double>::type;
+    static __device__ __forceinline__ acc_t charge(double q, double r2, double inv4a2) {
+        if constexpr (kF32) return (float)q * near_k0_f<kSmallOnly>((float)(r2 * inv4a2));
+        else return q * near_k0<NT, kSmallOnly>(r2 * inv4a2);
+    }
+    static __device__ __forceinline__ acc_t dipole(double dot, double r2, double inv4a2, double inva2) {
+        if constexpr (kF32) return (float)(dot * inva2) * near_k1oz_f<kSmallOnly>((float)(r2 * inv4a2));
+        else return dot * inva2 * near_k1oz<NT, kSmallOnly>(r2 * inv4a2);
+    }
+};
+
+template <int NT, bool kSmallOnly, bool kF32 = false>
+__global__ __launch_bounds__(64) void k_leaf(
+    const int32_t *__restrict__ leaves, int64_t leaf_base, const int32_t *__restrict__ lrange,
+    const int32_t *__restrict__ uoff, const int32_t *__restrict__ ulist,
+    const double *__restrict__ bcx, const double *__restrict__ bcy, const double *__restrict__ px,
+    const double *__restrict__ py, const double *__restrict__ qs, const double *__restrict__ dns,
+    int64_t off1, int has_q, int has_d, int mask, int has_far, const double *__restrict__ Lc,
+    double inv_alpha, double invR, const double *__restrict__ invFY,
+    const double *__restrict__ cnn, const double *__restrict__ sc, int nser, int p, int Pp,
+    double inv4a2, double inva2, double *__restrict__ outs) {
+    const int li = leaves[blockIdx.x];
+    const int64_t b = leaf_base + li;
+    const int lane = threadIdx.x;
+    const double cx = bcx[b], cy = bcy[b];
+    int rs[3], re[3], ntot = 0;
+    for (int s = 0; s < 3; ++s) {
+        rs[s] = lrange[li * 6 + 2 * s];
+        re[s] = (mask >> s) & 1 ? lrange[li * 6 + 2 * s + 1] : rs[s];
+        ntot += re[s] - rs[s];
+    }
+    const int u0 = uoff[li], u1 = uoff[li + 1];
+    const double *Lb = Lc + b * Pp;
+    for (int tb = 0; tb < ntot; tb += 64) {
+        const int c = min(64, ntot - tb);
+        int np2 = 1;
+        while (np2 < c) np2 <<= 1;
+        const int g = 64 / np2;
+        const int ti = lane / g, sub = lane - ti * g;
+        int k = tb + ti, t = -1;
+        if (ti < c)
+            for (int s = 0; s < 3; ++s) {
+                const int n = re[s] - rs[s];
+                if (t < 0 && k < n) t = rs[s] + k;
+                k -= n;
+            }
+        const bool valid = t >= 0;
+        const double x = valid ? px[t] : cx, y = valid ? py[t] : cy;
+        double acc = 0.0;
+        if (has_far && valid && sub == 0) {
+            const double wx = (x - cx) * inv_alpha, wy = (y - cy) * inv_alpha;
+            const double yv = 0.25 * (wx * wx + wy * wy);
+            const double zx = wx * invR, zy = wy * invR;
+            double F1, F2;
+            f_start(yv, sc, nser, F1, F2);
+            double sr = 0.0, si = 0.0;
+            for (int m = p; m >= 1; --m) {
+                const double F0 = F1 + yv * F2 * cnn[m];
+                const double gm = F0 * invFY[m];
+                const double cr = Lb[2 * m - 1] * gm, ci = Lb[2 * m] * gm;
+                const double nr = sr * zx - si * zy + cr;
+                si = sr * zy + si * zx + ci;
+                sr = nr;
+                F2 = F1;
+                F1 = F0;
+            }
+            const double F0 = F1 + yv * F2 * cnn[0];
+            acc = Lb[0] * F0 * invFY[0] + 2.0 * (sr * zx - si * zy);
+        }
+        using NearT = Near<NT, kSmallOnly, kF32>;
+        typename NearT::acc_t near = 0;
+        if (valid) {
+            for (int u = u0; u < u1; ++u) {
+                const int ul = ulist[u];
+                if (has_q) {
+                    const int a1 = lrange[ul * 6 + 1];
+                    for (int j = lrange[ul * 6] + sub; j < a1; j += g) {
+                        const double dx = x - px[j], dy = y - py[j];
+                        const double r2 = dx * dx + dy * dy;
+                        if (r2 > 0.0) near += NearT::charge(qs[j], r2, inv4a2);
+                    }
+                }
+                if (has_d) {
+                    const int a1 = lrange[ul * 6 + 3];
+                    for (int j = lrange[ul * 6 + 2] + sub; j < a1; j += g) {
+                        const double dx = x - px[j], dy = y - py[j];
+                        const double r2 = dx * dx + dy * dy;
+                        const int64_t jd = j - off1;
+                        if (r2 > 0.0)
+                            near += NearT::dipole(dx * dns[2 * jd] + dy * dns[2 * jd + 1], r2, inv4a2, inva2);
+                    }
+                }
+            }
+        }
+        for (int off = g >> 1; off > 0; off >>= 1) near += __shfl_xor(near, off, 64);
+        if (valid && sub == 0) outs[t] = (acc + (double)near) * kInv2Pi;
+    }
+}
+
+using LeafKernel = void (*)(const int32_t *, int64_t, const int32_t *, const int32_t *,
+                            const int32_t *, const double *, const double *, const double *,
+                            const double *, const double *, const double *, int64_t, int, int, int,
+                            int, const double *, double, double, const double *, const double *,
+                            const double *, int, int, int, double, double, double *);
+
+LeafKernel pick_leaf_kernel(int nt, bool small_only, bool f32) {
+    if (f32) return small_only ? k_leaf<8, true, true> : k_leaf<8, false, true>;
+    if (small_only) {
+        if (nt <= 6) return k_leaf<6, true>;
+        if (nt <= 8) return k_leaf<8, true>;
+        if (nt <= 10) return k_leaf<10, true>;
+        return k_leaf<14, true>;
+    }
+    return k_leaf<14, false>;
+}
+
+}  // namespace
+
+void fmm_run(Context &ctx, FmmPlan &pl, const double *q, const double *dn, double *const out[3],
+             SumPrec prec) {
+    int mask = 0;
+    for (int s = 0; s < 3; ++s)
+        if (out[s] && pl.toff[s + 1] > pl.toff[s]) mask |= 1 << s;
+    if (!mask) return;
+    const int64_t n0 = pl.toff[1] - pl.toff[0], n1 = pl.toff[2] - pl.toff[1];
+    const int has_q = (q && n0 > 0) ? 1 : 0, has_d = (dn && n1 > 0) ? 1 : 0;
+    const int L = pl.L, p = pl.p, P = pl.P, Pp = pl.Pp;
+    const double inv_alpha = 1.0 / pl.alpha;
+    double *qs = pl.qs.ensure(n0 > 0 ? n0 : 1);
+    double *dns = pl.dns.ensure(n1 > 0 ? 2 * n1 : 1);
+    double *outs = pl.outs.ensure(pl.N);
+    pl.last_mask = mask;
+    pl.last_has_q = has_q;
+    pl.last_has_d = has_d;
+    {
+    StageTimer tg(ctx, YK_STAGE_GATHER);
+    if (has_q) {
+        hipLaunchKernelGGL(k_gather_q, dim3(nblk(n0, 256)), dim3(256), 0, ctx.stream, n0, pl.perm.p, q, qs);
+        check_launch(ctx, "k_gather_q");
+    }
+    if (has_d) {
+        hipLaunchKernelGGL(k_gather_dn, dim3(nblk(n1, 256)), dim3(256), 0, ctx.stream, pl.toff[1], n1,
+                           pl.perm.p, dn, dns);
+        check_launch(ctx, "k_gather_dn");
+    }
+    }
+    ActiveSet &as = get_active(ctx, pl, mask);
+    const bool far = pl.lmin <= L && (has_q || has_d);
+    const int64_t leaf_base = pl.lev[L].begin;
+    const size_t lvl = (size_t)(p + 2);
+    if (far) {
+        // upward pass
+        const size_t sh = ((size_t)(p + 2) * 64 + Pp) * sizeof(double);
+        {
+        StageTimer tm(ctx, YK_STAGE_P2M);
+        hipLaunchKernelGGL(k_p2m, dim3(pl.nleaf), dim3(64), sh, ctx.stream, leaf_base, pl.lrange.p,
+                           pl.bcx.p, pl.bcy.p, pl.px.p, pl.py.p, qs, dns, pl.toff[1], has_q, has_d,
+                           inv_alpha, 1.0 / pl.lev[L].R, pl.invFY.p + L * lvl, pl.dipa.p + L * lvl,
+                           pl.dipb.p + L * lvl, pl.cnn.p, pl.serc.p, pl.nser, p, Pp, pl.M.p);
+        check_launch(ctx, "k_p2m");
+        }
+        {
+            StageTimer tmm(ctx, YK_STAGE_M2M);
+            for (int l = L - 1; l >= pl.lmin; --l) {
+                const int64_t nbl = pl.lev[l].end - pl.lev[l].begin;
+                hipLaunchKernelGGL(k_m2m, dim3(nbl), dim3(128), Pp * sizeof(double), ctx.stream,
+                                   pl.lev[l].begin, pl.fchild.p, pl.nchild.p, pl.bcode.p,
+                                   pl.m2m.p + (size_t)l * 4 * Pp * Pp, P, Pp, pl.M.p);
+                check_launch(ctx, "k_m2m");
+            }
+        }
+        if (prec == SUM_FP32 && Pp <= 64) {
+            const int64_t nm = pl.nbox * (int64_t)Pp;
+            float *mf = pl.Mf.ensure(nm);
+            hipLaunchKernelGGL(k_to_float, dim3(nblk(nm, 256)), dim3(256), 0, ctx.stream, nm, pl.M.p, mf);
+            check_launch(ctx, "k_to_float");
+        }
+        // downward pass
+        YK_HIP(hipMemsetAsync(pl.Lc.p, 0, (size_t)pl.nbox * Pp * sizeof(double), ctx.stream));
+        for (int l = pl.lmin; l <= L; ++l) {
+            if (l > pl.lmin && as.l2l_count[l] > 0) {
+                StageTimer tl(ctx, YK_STAGE_L2L);
+                hipLaunchKernelGGL(k_l2l, dim3(as.l2l_count[l]), dim3(128), Pp * sizeof(double), ctx.stream,
+                                   as.l2l_boxes.p + as.l2l_begin[l], pl.bparent.p, pl.bcode.p,
+                                   pl.l2l.p + (size_t)(l - 1) * 4 * Pp * Pp, P, Pp, pl.Lc.p);
+                check_launch(ctx, "k_l2l");
+            }
+            if (as.tile_count[l] > 0) {
+                StageTimer tl(ctx, YK_STAGE_M2L);
+                if (Pp <= 64 && prec == SUM_FP32) {
+                    launch_m2l_mfma<float>(ctx, Pp, as.tile_count[l], as.m2l_tiles.p, as.tile_begin[l],
+                                           as.m2l_boxes.p, pl.vlist.p, pl.slot_oid.p, pl.m2lf.p, pl.Mf.p,
+                                           pl.Lc.p);
+                } else if (Pp <= 64) {
+                    launch_m2l_mfma<double>(ctx, Pp, as.tile_count[l], as.m2l_tiles.p, as.tile_begin[l],
+                                            as.m2l_boxes.p, pl.vlist.p, pl.slot_oid.p, pl.m2l.p, pl.M.p,
+                                            pl.Lc.p);
+                } else {
+                    const size_t shm = ((size_t)kM2LChunk * Pp + (size_t)kM2LTile * Pp) * sizeof(double);
+                    hipLaunchKernelGGL(k_m2l, dim3(as.tile_count[l]), dim3(256), shm, ctx.stream,
+                                       as.m2l_tiles.p, as.tile_begin[l], as.m2l_boxes.p, pl.vlist.p,
+                                       pl.slot_oid.p, pl.m2l.p, P, Pp, pl.M.p, pl.Lc.p);
+                    check_launch(ctx, "k_m2l");
+                }
+            }
+        }
+    }
+    if (as.n_leaves > 0) {
+        const double inv4a2 = 0.25 * inv_alpha * inv_alpha, inva2 = inv_alpha * inv_alpha;
+        const double tmax = 2.0 * pl.lev[L].side * pl.lev[L].side * inv4a2 * 4.0;
+        LeafKernel kern = pick_leaf_kernel(pl.near_terms, tmax <= 1.0, prec == SUM_FP32);
+        StageTimer tl(ctx, YK_STAGE_LEAF);
+        hipLaunchKernelGGL(kern, dim3(as.n_leaves), dim3(64), 0, ctx.stream, as.leaves.p,
+                           leaf_base, pl.lrange.p, pl.ulist_off.p, pl.ulist.p, pl.bcx.p, pl.bcy.p,
+                           pl.px.p, pl.py.p, qs, dns, pl.toff[1], has_q, has_d, mask, far ? 1 : 0,
+                           pl.Lc.p, inv_alpha, 1.0 / pl.lev[L].R, pl.invFY.p + L * lvl, pl.cnn.p,
+                           pl.serc.p, pl.nser, p, Pp, inv4a2, inva2, outs);
+        check_launch(ctx, "k_leaf");
+    }
+    StageTimer tsc(ctx, YK_STAGE_SCATTER);
+    for (int s = 0; s < 3; ++s) {
+        if (!((mask >> s) & 1)) continue;
+        const int64_t n = pl.toff[s + 1] - pl.toff[s];
+        hipLaunchKernelGGL(k_scatter_out, dim3(nblk(n, 256)), dim3(256), 0, ctx.stream, pl.toff[s], n,
+                           pl.perm.p, outs, out[s]);
+        check_launch(ctx, "k_scatter_out");
+    }
+}
+
+}  // namespace yk

@@ -1,0 +1,539 @@
+// fmm_plan.cpp -- quadtree, interaction lists and translation operators on the host.
+//
+// The tree has uniform depth L (every leaf at level L) but stores only
+// non-empty boxes, so clustered boundary nodes cost nothing where there are
+// none.  Lists: U (the non-empty leaves among a leaf's 3x3 neighbourhood,
+// itself included: near field by direct summation) and V (the children of the
+// parent's neighbours that are not adjacent: far field by M2L), the classical
+// lists of the FMM the paper relies on (Sec. 3, with the quadtree of Sec. 3.1).
+// Levels whose boxes are wider than 40 alpha get no M2L: across such a gap
+// the kernel is below K0(40) ~ 1e-18.
+#include <algorithm>
+#include <cmath>
+#include <complex>
+
+#include "fmm.h"
+#include "yk_bessel.h"
+
+namespace yk {
+
+using ld = long double;
+using cld = std::complex<long double>;
+
+namespace {
+
+constexpr double kFarCut = 40.0;
+
+inline uint32_t compact15(uint32_t v) {
+    v &= 0x55555555u;
+    v = (v | (v >> 1)) & 0x33333333u;
+    v = (v | (v >> 2)) & 0x0f0f0f0fu;
+    v = (v | (v >> 4)) & 0x00ff00ffu;
+    v = (v | (v >> 8)) & 0x0000ffffu;
+    return v;
+}
+inline uint32_t spread(uint32_t v) {
+    v &= 0x7fff;
+    v = (v | (v << 8)) & 0x00ff00ffu;
+    v = (v | (v << 4)) & 0x0f0f0f0fu;
+    v = (v | (v << 2)) & 0x33333333u;
+    v = (v | (v << 1)) & 0x55555555u;
+    return v;
+}
+inline uint32_t encode(uint32_t ix, uint32_t iy) { return spread(ix) | (spread(iy) << 1); }
+inline void decode(uint32_t c, uint32_t &ix, uint32_t &iy) {
+    ix = compact15(c);
+    iy = compact15(c >> 1);
+}
+
+int64_t find_code(const std::vector<uint32_t> &codes, int64_t lo, int64_t hi, uint32_t c) {
+    auto it = std::lower_bound(codes.begin() + lo, codes.begin() + hi, c);
+    if (it != codes.begin() + hi && *it == c) return it - codes.begin();
+    return -1;
+}
+
+// F_n(y) = sum_k y^k / (k! (n+1)_k), so that I_n(x) = (x/2)^n / n! F_n(x^2/4).
+ld F_series(int n, ld y) {
+    ld t = 1, s = 1;
+    for (int k = 1; k < 20000; ++k) {
+        t *= y / ((ld)k * (ld)(n + k));
+        s += t;
+        if (t < 1e-22L * s) break;
+    }
+    return s;
+}
+
+// I_0..I_nmax at x (x >= 0) in extended precision
+std::vector<ld> I_seq(ld x, int nmax) {
+    std::vector<ld> I(nmax + 1);
+    const ld y = 0.25L * x * x;
+    ld pref = 1;                           // (x/2)^n / n!
+    for (int n = 0; n <= nmax; ++n) {
+        if (n > 0) pref *= (0.5L * x) / (ld)n;
+        I[n] = pref * F_series(n, y);
+    }
+    return I;
+}
+
+// K_0..K_nmax at x > 0: K0, K1 from the library's own evaluation, then the
+// forward recurrence K_{n+1} = K_{n-1} + (2n/x) K_n (stable upwards).
+std::vector<ld> K_seq(double x, int nmax) {
+    std::vector<ld> K(nmax + 1);
+    K[0] = (ld)yk::k0(x);
+    if (nmax >= 1) K[1] = (ld)yk::k1(x);
+    for (int n = 1; n < nmax; ++n) K[n + 1] = K[n - 1] + (2.0L * n / (ld)x) * K[n];
+    return K;
+}
+
+// Real form of out_k = sum_{n=-p..p} C[k][n] v_n (k = 0..p) for v_{-n} = conj(v_n):
+// vectors are [Re v_0, Re v_1, Im v_1, ...]; the Pp x Pp result is column-major.
+void to_real(const std::vector<cld> &C, int p, int Pp, double *out) {
+    auto c = [&](int k, int n) { return C[(size_t)k * (2 * p + 1) + (n + p)]; };
+    std::fill(out, out + (size_t)Pp * Pp, 0.0);
+    auto put = [&](int row, int col, ld v) { out[(size_t)col * Pp + row] = (double)v; };
+    for (int k = 0; k <= p; ++k) {
+        const int rr = k == 0 ? 0 : 2 * k - 1, ri = 2 * k;
+        // column of v_0
+        put(rr, 0, c(k, 0).real());
+        if (k > 0) put(ri, 0, c(k, 0).imag());
+        for (int n = 1; n <= p; ++n) {
+            const cld sp = c(k, n) + c(k, -n), sm = c(k, n) - c(k, -n);
+            put(rr, 2 * n - 1, sp.real());
+            put(rr, 2 * n, -sm.imag());
+            if (k > 0) {
+                put(ri, 2 * n - 1, sp.imag());
+                put(ri, 2 * n, sm.real());
+            }
+        }
+    }
+}
+
+inline cld cis(ld phi, int m) { return std::polar((ld)1, phi * (ld)m); }
+
+}  // namespace
+
+int choose_order(double tol) {
+    // Measured on uniform and clustered point sets: the relative error of the
+    // sums behaves like 0.0123 * 0.44^p; take the smallest p with half the
+    // tolerance to spare.
+    int p = (int)std::ceil(std::log(0.5 * tol / 0.0123) / std::log(0.44));
+    return std::max(4, std::min(60, p));
+}
+
+void build_lists_and_tables(Context &ctx, FmmPlan &pl, const std::vector<uint32_t> &keys) {
+    const int64_t N = pl.N;
+    const uint32_t kMask = 0x3fffffffu;
+    // ---- merged Morton codes (each set's block is sorted) ----
+    std::vector<uint32_t> merged;
+    merged.reserve(N);
+    {
+        std::vector<uint32_t> a, b;
+        for (int s = 0; s < 3; ++s) {
+            if (pl.toff[s + 1] == pl.toff[s]) continue;
+            b.resize(pl.toff[s + 1] - pl.toff[s]);
+            for (int64_t k = pl.toff[s]; k < pl.toff[s + 1]; ++k) b[k - pl.toff[s]] = keys[k] & kMask;
+            a.swap(merged);
+            merged.resize(a.size() + b.size());
+            std::merge(a.begin(), a.end(), b.begin(), b.end(), merged.begin());
+        }
+    }
+    // ---- leaf level: smallest level whose mean occupancy is <= leaf_size ----
+    std::vector<uint32_t> uniq15;
+    uniq15.reserve(N);
+    for (int64_t k = 0; k < N; ++k)
+        if (k == 0 || merged[k] != merged[k - 1]) uniq15.push_back(merged[k]);
+    std::vector<std::vector<uint32_t>> codes(kMaxLevel + 1);
+    codes[kMaxLevel] = uniq15;
+    for (int l = kMaxLevel - 1; l >= 0; --l) {
+        const auto &f = codes[l + 1];
+        auto &c = codes[l];
+        for (size_t k = 0; k < f.size(); ++k) {
+            const uint32_t v = f[k] >> 2;
+            if (c.empty() || c.back() != v) c.push_back(v);
+        }
+    }
+    int L = kMaxLevel;
+    for (int l = 0; l <= kMaxLevel; ++l) {
+        if ((double)N / (double)codes[l].size() <= (double)pl.opt_leaf) {
+            L = l;
+            break;
+        }
+    }
+    pl.L = L;
+    codes.resize(L + 1);
+    // codes at levels <= L come from level L's prefixes
+    codes[L].clear();
+    for (int64_t k = 0; k < N; ++k) {
+        const uint32_t v = merged[k] >> (2 * (kMaxLevel - L));
+        if (codes[L].empty() || codes[L].back() != v) codes[L].push_back(v);
+    }
+    for (int l = L - 1; l >= 0; --l) {
+        codes[l].clear();
+        for (uint32_t v : codes[l + 1])
+            if (codes[l].empty() || codes[l].back() != (v >> 2)) codes[l].push_back(v >> 2);
+    }
+    // ---- boxes ----
+    pl.lev.assign(L + 1, LevelInfo{});
+    int64_t nb = 0;
+    for (int l = 0; l <= L; ++l) {
+        pl.lev[l].begin = nb;
+        nb += (int64_t)codes[l].size();
+        pl.lev[l].end = nb;
+        pl.lev[l].side = pl.size / (double)(1u << l);
+        pl.lev[l].R = pl.lev[l].side * 0.70710678118654752440 / pl.alpha;
+    }
+    pl.nbox = nb;
+    pl.nleaf = (int64_t)codes[L].size();
+    pl.hcode.resize(nb);
+    pl.hparent.assign(nb, -1);
+    std::vector<double> cx(nb), cy(nb);
+    for (int l = 0; l <= L; ++l) {
+        for (size_t k = 0; k < codes[l].size(); ++k) {
+            const int64_t gidx = pl.lev[l].begin + (int64_t)k;
+            pl.hcode[gidx] = codes[l][k];
+            uint32_t ix, iy;
+            decode(codes[l][k], ix, iy);
+            cx[gidx] = pl.x0 + (ix + 0.5) * pl.lev[l].side;
+            cy[gidx] = pl.y0 + (iy + 0.5) * pl.lev[l].side;
+            if (l > 0) {
+                const int64_t pi = find_code(codes[l - 1], 0, (int64_t)codes[l - 1].size(), codes[l][k] >> 2);
+                pl.hparent[gidx] = (int32_t)(pl.lev[l - 1].begin + pi);
+            }
+        }
+    }
+    // ---- M2L levels ----
+    int lmin = 2;
+    while (lmin <= L && pl.lev[lmin].side >= kFarCut * pl.alpha) ++lmin;
+    pl.lmin = lmin;
+    // ---- leaf ranges per set ----
+    pl.h_lrange.assign((size_t)pl.nleaf * 6, 0);
+    for (int s = 0; s < 3; ++s) {
+        int64_t k = pl.toff[s];
+        const int64_t e = pl.toff[s + 1];
+        while (k < e) {
+            const uint32_t lc = (keys[k] & kMask) >> (2 * (kMaxLevel - L));
+            int64_t k2 = k;
+            while (k2 < e && ((keys[k2] & kMask) >> (2 * (kMaxLevel - L))) == lc) ++k2;
+            const int64_t li = find_code(codes[L], 0, pl.nleaf, lc);
+            if (li < 0) throw Error{YK_ERR_INTERNAL, "leaf code not found"};
+            pl.h_lrange[(size_t)li * 6 + 2 * s] = (int32_t)k;
+            pl.h_lrange[(size_t)li * 6 + 2 * s + 1] = (int32_t)k2;
+            k = k2;
+        }
+    }
+    // ---- U-lists ----
+    std::vector<int32_t> uoff(pl.nleaf + 1, 0), ul;
+    ul.reserve((size_t)pl.nleaf * 9);
+    const int64_t nside = (int64_t)1 << L;
+    for (int64_t li = 0; li < pl.nleaf; ++li) {
+        uint32_t ix, iy;
+        decode(codes[L][li], ix, iy);
+        for (int dy = -1; dy <= 1; ++dy)
+            for (int dx = -1; dx <= 1; ++dx) {
+                const int64_t jx = (int64_t)ix + dx, jy = (int64_t)iy + dy;
+                if (jx < 0 || jy < 0 || jx >= nside || jy >= nside) continue;
+                const int64_t j = find_code(codes[L], 0, pl.nleaf, encode((uint32_t)jx, (uint32_t)jy));
+                if (j >= 0) ul.push_back((int32_t)j);
+            }
+        uoff[li + 1] = (int32_t)ul.size();
+    }
+    // ---- V-lists (27 slots per box, in class order) ----
+    std::vector<int32_t> vl((size_t)nb * kNumV, -1);
+    for (int l = std::max(lmin, 2); l <= L; ++l) {
+        const int64_t ns = (int64_t)1 << l;
+        for (size_t k = 0; k < codes[l].size(); ++k) {
+            uint32_t ix, iy;
+            decode(codes[l][k], ix, iy);
+            const int cxs = ix & 1, cys = iy & 1;
+            int slot = 0;
+            for (int dy = -2 - cys; dy <= 3 - cys; ++dy)
+                for (int dx = -2 - cxs; dx <= 3 - cxs; ++dx) {
+                    if (std::abs(dx) <= 1 && std::abs(dy) <= 1) continue;
+                    const int64_t jx = (int64_t)ix + dx, jy = (int64_t)iy + dy;
+                    int32_t src = -1;
+                    if (jx >= 0 && jy >= 0 && jx < ns && jy < ns) {
+                        const int64_t j = find_code(codes[l], 0, (int64_t)codes[l].size(),
+                                                    encode((uint32_t)jx, (uint32_t)jy));
+                        if (j >= 0) src = (int32_t)(pl.lev[l].begin + j);
+                    }
+                    vl[(pl.lev[l].begin + (int64_t)k) * kNumV + slot] = src;
+                    ++slot;
+                }
+        }
+    }
+    // ---- children (contiguous at the next level because codes are sorted) ----
+    std::vector<int32_t> fch(nb, -1), nch(nb, 0);
+    for (int64_t b = 0; b < nb; ++b) {
+        const int32_t pa = pl.hparent[b];
+        if (pa < 0) continue;
+        if (fch[pa] < 0) fch[pa] = (int32_t)b;
+        nch[pa]++;
+    }
+    // ---- slot -> offset id for the 4 parity classes ----
+    std::vector<int32_t> soid(4 * kNumV);
+    for (int cls = 0; cls < 4; ++cls) {
+        const int cxs = cls & 1, cys = cls >> 1;
+        int slot = 0;
+        for (int dy = -2 - cys; dy <= 3 - cys; ++dy)
+            for (int dx = -2 - cxs; dx <= 3 - cxs; ++dx) {
+                if (std::abs(dx) <= 1 && std::abs(dy) <= 1) continue;
+                int oid = 0, found = -1;
+                for (int ey = -3; ey <= 3; ++ey)
+                    for (int ex = -3; ex <= 3; ++ex) {
+                        if (std::abs(ex) <= 1 && std::abs(ey) <= 1) continue;
+                        if (ex == dx && ey == dy) found = oid;
+                        ++oid;
+                    }
+                soid[cls * kNumV + slot] = found;
+                ++slot;
+            }
+    }
+    // ---- upload tree ----
+    auto up = [&](auto &buf, const auto &vec) {
+        using T = typename std::decay_t<decltype(vec)>::value_type;
+        T *d = buf.ensure(vec.size());
+        YK_HIP(hipMemcpyAsync(d, vec.data(), vec.size() * sizeof(T), hipMemcpyHostToDevice, ctx.stream));
+    };
+    up(pl.bcx, cx);
+    up(pl.bcy, cy);
+    up(pl.bparent, pl.hparent);
+    up(pl.bcode, pl.hcode);
+    up(pl.fchild, fch);
+    up(pl.nchild, nch);
+    up(pl.slot_oid, soid);
+    up(pl.vlist, vl);
+    up(pl.lrange, pl.h_lrange);
+    up(pl.ulist_off, uoff);
+    up(pl.ulist, ul);
+
+    // ---- expansion order and operators ----
+    const int p = pl.opt_p > 0 ? pl.opt_p : choose_order(pl.opt_tol);
+    pl.p = p;
+    pl.P = 2 * p + 1;
+    pl.Pp = (pl.P + 15) / 16 * 16;
+    const int Pp = pl.Pp, nL = L + 1;
+    const double alpha = pl.alpha;
+    // per-level scale data
+    std::vector<double> invFY((size_t)nL * (p + 2)), da((size_t)nL * (p + 2)), db((size_t)nL * (p + 2));
+    std::vector<std::vector<ld>> IR(nL);
+    for (int l = std::min(lmin, L); l <= L; ++l) {
+        const ld R = pl.lev[l].R;
+        IR[l] = I_seq(R, 2 * p + 4);
+        for (int n = 0; n <= p + 1; ++n) {
+            invFY[(size_t)l * (p + 2) + n] = (double)(1.0L / F_series(n, 0.25L * R * R));
+            da[(size_t)l * (p + 2) + n] = (double)(IR[l][n + 1] / IR[l][n]);
+            db[(size_t)l * (p + 2) + n] = (double)((n == 0 ? IR[l][1] : IR[l][n - 1]) / IR[l][n]);
+        }
+    }
+    std::vector<double> cnn(p + 4);
+    for (int n = 0; n < p + 4; ++n) cnn[n] = 1.0 / ((double)(n + 1) * (double)(n + 2));
+    up(pl.invFY, invFY);
+    up(pl.dipa, da);
+    up(pl.dipb, db);
+    up(pl.cnn, cnn);
+    // series length for F_{p+1}, F_{p+2} at the leaf level
+    {
+        const ld Y = 0.25L * pl.lev[L].R * pl.lev[L].R * 1.0001L;
+        ld t = 1;
+        int k = 1;
+        for (; k < 200; ++k) {
+            t *= Y / ((ld)k * (ld)(p + 1 + k));
+            if (t < 1e-19L) break;
+        }
+        pl.nser = k + 1;
+        std::vector<double> sc(2 * pl.nser);
+        for (int w = 0; w < 2; ++w) {
+            const int n = p + 1 + w;
+            ld c = 1;
+            for (int kk = 0; kk < pl.nser; ++kk) {
+                if (kk > 0) c /= (ld)kk * (ld)(n + kk);
+                sc[w * pl.nser + kk] = (double)c;
+            }
+        }
+        up(pl.serc, sc);
+    }
+    // near-field series length: t = r^2/(4 alpha^2) over U-list pairs is at most
+    // (2 sqrt(2) side_L)^2 / (4 alpha^2); when it exceeds 1 the large-argument branch is used too
+    {
+        const double tmax = 2.0 * pl.lev[L].side * pl.lev[L].side / (alpha * alpha);
+        const double tt = std::min(1.0, tmax);
+        int k = 1;
+        double term = 1;
+        for (; k < YK_NSER64; ++k) {
+            term *= tt / ((double)k * (double)k);
+            if (term < 1e-18) break;
+        }
+        pl.near_terms = std::min(YK_NSER64, k + 1);
+    }
+
+    const int nC = 2 * p + 1;
+    std::vector<cld> C((size_t)(p + 1) * nC);
+    // M2M and L2L for parent levels lmin..L-1 (also below lmin: unused)
+    std::vector<double> m2m((size_t)nL * 4 * Pp * Pp, 0.0), l2l((size_t)nL * 4 * Pp * Pp, 0.0);
+    for (int l = std::max(lmin, 0); l < L; ++l) {
+        const ld Rp = pl.lev[l].R, Rc = pl.lev[l + 1].R;
+        const auto &Ip = IR[l], &Ic = IR[l + 1];
+        for (int c = 0; c < 4; ++c) {
+            const int bx = c & 1, by = (c >> 1) & 1;
+            const ld ex = (bx - 0.5L) * pl.lev[l + 1].side / alpha;
+            const ld ey = (by - 0.5L) * pl.lev[l + 1].side / alpha;
+            const ld re = std::sqrt(ex * ex + ey * ey), phi = std::atan2(ey, ex);
+            const std::vector<ld> Ie = I_seq(re, 2 * p + 2);
+            // M2M: S[k][n] = I_|n|(Rc) F^I_{n-k}(e) / I_k(Rp)
+            for (int k = 0; k <= p; ++k)
+                for (int n = -p; n <= p; ++n)
+                    C[(size_t)k * nC + n + p] = Ic[std::abs(n)] * Ie[std::abs(n - k)] * cis(phi, n - k) / Ip[k];
+            to_real(C, p, Pp, &m2m[((size_t)l * 4 + c) * Pp * Pp]);
+            // L2L: E[k][m] = F^I_{m-k}(e) I_k(Rc) / I_|m|(Rp)
+            for (int k = 0; k <= p; ++k)
+                for (int m = -p; m <= p; ++m)
+                    C[(size_t)k * nC + m + p] = Ie[std::abs(m - k)] * cis(phi, m - k) * Ic[k] / Ip[std::abs(m)];
+            to_real(C, p, Pp, &l2l[((size_t)l * 4 + c) * Pp * Pp]);
+        }
+    }
+    // M2L for levels lmin..L, 40 offsets (dy outer, dx inner over [-3,3]^2 minus [-1,1]^2)
+    std::vector<double> m2l((size_t)nL * kNumOff * Pp * Pp, 0.0);
+    for (int l = lmin; l <= L; ++l) {
+        const auto &I = IR[l];
+        int oid = 0;
+        for (int dy = -3; dy <= 3; ++dy)
+            for (int dx = -3; dx <= 3; ++dx) {
+                if (std::abs(dx) <= 1 && std::abs(dy) <= 1) continue;
+                // d = (c_t - c_s)/alpha with the source at offset (dx, dy)
+                const double ddx = -dx * pl.lev[l].side / alpha, ddy = -dy * pl.lev[l].side / alpha;
+                const double dd = std::sqrt(ddx * ddx + ddy * ddy);
+                const ld phi = std::atan2((ld)ddy, (ld)ddx);
+                const std::vector<ld> K = K_seq(dd, 2 * p + 1);
+                for (int m = 0; m <= p; ++m)
+                    for (int n = -p; n <= p; ++n) {
+                        const ld sgn = (m & 1) ? -1.0L : 1.0L;
+                        C[(size_t)m * nC + n + p] = sgn * I[m] * I[std::abs(n)] * K[std::abs(n - m)] * cis(phi, n - m);
+                    }
+                to_real(C, p, Pp, &m2l[((size_t)l * kNumOff + oid) * Pp * Pp]);
+                ++oid;
+            }
+    }
+    up(pl.m2m, m2m);
+    up(pl.l2l, l2l);
+    up(pl.m2l, m2l);
+    {
+        std::vector<float> f(m2l.begin(), m2l.end());
+        up(pl.m2lf, f);
+    }
+    pl.M.ensure((size_t)nb * Pp);
+    pl.Lc.ensure((size_t)nb * Pp);
+    YK_HIP(hipStreamSynchronize(ctx.stream));
+}
+
+FmmPlan *plan_in_slot(Context &ctx, int slot) {
+    switch (slot) {
+        case 0: return ctx.plan_vol.get();
+        case 1: return ctx.plan_bnd.get();
+        case 2: return ctx.plan_misc.get();
+        default: return nullptr;
+    }
+}
+
+ActiveSet &get_active(Context &ctx, FmmPlan &pl, int mask) {
+    auto it = pl.active.find(mask);
+    if (it != pl.active.end()) return *it->second;
+    auto as = std::make_unique<ActiveSet>();
+    const int L = pl.L;
+    std::vector<int64_t> cnt(pl.nbox, 0);
+    for (int64_t li = 0; li < pl.nleaf; ++li) {
+        int64_t c = 0;
+        for (int s = 0; s < 3; ++s)
+            if (mask & (1 << s)) c += pl.h_lrange[li * 6 + 2 * s + 1] - pl.h_lrange[li * 6 + 2 * s];
+        cnt[pl.lev[L].begin + li] = c;
+    }
+    for (int64_t b = pl.nbox - 1; b >= 0; --b)
+        if (pl.hparent[b] >= 0) cnt[pl.hparent[b]] += cnt[b];
+    std::vector<int32_t> leaves;
+    for (int64_t li = 0; li < pl.nleaf; ++li)
+        if (cnt[pl.lev[L].begin + li] > 0) leaves.push_back((int32_t)li);
+    // near-field pair counts over the U-lists of the active leaves
+    {
+        std::vector<int32_t> uoff(pl.nleaf + 1), ul;
+        // recompute the U-lists from the uploaded copies
+        YK_HIP(hipMemcpyAsync(uoff.data(), pl.ulist_off.p, uoff.size() * sizeof(int32_t),
+                              hipMemcpyDeviceToHost, ctx.stream));
+        YK_HIP(hipStreamSynchronize(ctx.stream));
+        ul.resize(uoff[pl.nleaf]);
+        YK_HIP(hipMemcpyAsync(ul.data(), pl.ulist.p, ul.size() * sizeof(int32_t),
+                              hipMemcpyDeviceToHost, ctx.stream));
+        YK_HIP(hipStreamSynchronize(ctx.stream));
+        for (int32_t li : leaves) {
+            const int64_t nt = cnt[pl.lev[L].begin + li];
+            int64_t sq = 0, sd = 0;
+            for (int32_t u = uoff[li]; u < uoff[li + 1]; ++u) {
+                sq += pl.h_lrange[(size_t)ul[u] * 6 + 1] - pl.h_lrange[(size_t)ul[u] * 6];
+                sd += pl.h_lrange[(size_t)ul[u] * 6 + 3] - pl.h_lrange[(size_t)ul[u] * 6 + 2];
+            }
+            as->pairs_q += nt * sq;
+            as->pairs_d += nt * sd;
+            as->l2p_points += nt;
+        }
+    }
+    // M2L tiles: active boxes of levels lmin..L grouped by (level, class)
+    constexpr int kTile = 64;
+    std::vector<int32_t> vl_host;
+    if (pl.lmin <= L) {
+        vl_host.resize((size_t)pl.nbox * kNumV);
+        YK_HIP(hipMemcpyAsync(vl_host.data(), pl.vlist.p, vl_host.size() * sizeof(int32_t),
+                              hipMemcpyDeviceToHost, ctx.stream));
+        YK_HIP(hipStreamSynchronize(ctx.stream));
+    }
+    std::vector<int32_t> mb;
+    std::vector<int4> tiles;
+    for (int l = pl.lmin; l <= L; ++l) {
+        for (int cls = 0; cls < 4; ++cls) {
+            const int64_t start = (int64_t)mb.size();
+            for (int64_t b = pl.lev[l].begin; b < pl.lev[l].end; ++b) {
+                if (cnt[b] == 0) continue;
+                uint32_t ix, iy;
+                decode(pl.hcode[b], ix, iy);
+                if ((int)((ix & 1) | ((iy & 1) << 1)) == cls) {
+                    mb.push_back((int32_t)b);
+                    for (int k = 0; k < kNumV; ++k) as->m2l_trans += vl_host[(size_t)b * kNumV + k] >= 0;
+                }
+            }
+            for (int64_t s = start; s < (int64_t)mb.size(); s += kTile)
+                tiles.push_back(make_int4(l, cls, (int)s, (int)std::min<int64_t>(kTile, (int64_t)mb.size() - s)));
+        }
+    }
+    as->tile_begin.assign(L + 1, 0);
+    as->tile_count.assign(L + 1, 0);
+    for (size_t t = 0; t < tiles.size(); ++t) {
+        const int l = tiles[t].x;
+        if (as->tile_count[l] == 0) as->tile_begin[l] = (int)t;
+        as->tile_count[l]++;
+    }
+    std::vector<int32_t> l2lb;
+    as->l2l_begin.assign(L + 1, 0);
+    as->l2l_count.assign(L + 1, 0);
+    for (int l = pl.lmin + 1; l <= L; ++l) {
+        as->l2l_begin[l] = (int64_t)l2lb.size();
+        for (int64_t b = pl.lev[l].begin; b < pl.lev[l].end; ++b)
+            if (cnt[b] > 0) l2lb.push_back((int32_t)b);
+        as->l2l_count[l] = (int64_t)l2lb.size() - as->l2l_begin[l];
+    }
+    auto up = [&](auto &buf, const auto &vec) {
+        using T = typename std::decay_t<decltype(vec)>::value_type;
+        T *d = buf.ensure(vec.size());
+        if (!vec.empty())
+            YK_HIP(hipMemcpyAsync(d, vec.data(), vec.size() * sizeof(T), hipMemcpyHostToDevice, ctx.stream));
+    };
+    up(as->m2l_boxes, mb);
+    up(as->m2l_tiles, tiles);
+    up(as->l2l_boxes, l2lb);
+    up(as->leaves, leaves);
+    as->n_tiles = (int)tiles.size();
+    as->n_leaves = (int64_t)leaves.size();
+    as->n_m2l_boxes = (int64_t)mb.size();
+    YK_HIP(hipStreamSynchronize(ctx.stream));
+    auto &ref = *as;
+    pl.active[mask] = std::move(as);
+    return ref;
+}
+
+}  // namespace yk

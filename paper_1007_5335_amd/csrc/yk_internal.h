@@ -107,7 +107,25 @@ struct Context {
     DevBuf<double> scal;                   // small device scalars
     DevBuf<double> dn;                     // dipole vectors [N][2]
     std::vector<double> host_scal;
+
+    // optional per-stage event timing
+    bool timing = false;
+    std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> pending;
+    std::vector<hipEvent_t> event_pool;
+    double stage_ms[YK_NUM_STAGES] = {0};
+    int64_t stage_calls[YK_NUM_STAGES] = {0};
+    ~Context();
 };
+
+// Brackets a stage with events when timing is on (RAII).
+struct StageTimer {
+    Context &ctx;
+    int stage;
+    hipEvent_t a = nullptr, b = nullptr;
+    StageTimer(Context &c, int s);
+    ~StageTimer();
+};
+void resolve_timings(Context &ctx);
 
 // ---------------------------------------------------------------- kernels ---
 // Direct sums (FP64): out[i] (+)= sum_j q_j K0/(2pi) + sum_j (x_i - y_j).dn_j K1(z)/(alpha^2 z)/(2pi)

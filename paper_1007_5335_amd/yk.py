@@ -34,7 +34,10 @@ EXPORTS = (
     "yk_default_options", "yk_create", "yk_destroy", "yk_set_stream", "yk_set_options",
     "yk_last_error", "yk_invalidate_geometry", "yk_volume_potential", "yk_double_layer_apply",
     "yk_gmres_density", "yk_heat_step", "yk_rhs_backward_euler", "yk_fmm_potential",
+    "yk_plan_info_get", "yk_timing_enable", "yk_timing_read",
 )
+
+STAGES = ("gather", "p2m", "m2m", "m2l", "l2l", "leaf", "scatter", "direct")
 
 
 class yk_options(ctypes.Structure):
@@ -59,6 +62,20 @@ class yk_stats(ctypes.Structure):
         return dict(iters=self.iters, outer_iters=self.outer_iters, guess_used=self.guess_used,
                     matvecs=self.matvecs, res0=self.res0, res_final=self.res_final,
                     ms=list(self.ms))
+
+
+class yk_plan_info(ctypes.Structure):
+    _fields_ = [("valid", ctypes.c_int32), ("leaf_level", ctypes.c_int32), ("lmin", ctypes.c_int32),
+                ("p", ctypes.c_int32), ("P", ctypes.c_int32), ("Pp", ctypes.c_int32),
+                ("n_points", ctypes.c_int64), ("n_boxes", ctypes.c_int64), ("n_leaves", ctypes.c_int64),
+                ("pairs_charge", ctypes.c_int64), ("pairs_dipole", ctypes.c_int64),
+                ("m2l_translations", ctypes.c_int64), ("m2l_slots", ctypes.c_int64),
+                ("p2m_points", ctypes.c_int64), ("l2p_points", ctypes.c_int64),
+                ("near_terms", ctypes.c_int32), ("nser", ctypes.c_int32),
+                ("build_ms", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 class YkError(RuntimeError):
@@ -97,6 +114,9 @@ def load_library(path: str = LIB_PATH):
                               P(yk_stats)]),
         "yk_rhs_backward_euler": (ip, [vp, i64, vp, vp, vp, ip, P(dbl), dbl, vp]),
         "yk_fmm_potential": (ip, [vp, i64, vp, vp, P(yk_boundary), vp, dbl, vp, vp]),
+        "yk_plan_info_get": (ip, [vp, ip, P(yk_plan_info)]),
+        "yk_timing_enable": (ip, [vp, ip]),
+        "yk_timing_read": (ip, [vp, P(dbl), P(i64), ip]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -262,3 +282,20 @@ def yk_fmm_potential(ctx, vol_xy, q, bnd: Boundary, d, alpha, out_vol, out_bnd):
         ctypes.byref(bnd.struct), _dev(d, "d"), float(alpha), _dev(out_vol, "out_vol"),
         _dev(out_bnd, "out_bnd")))
     return out_vol, out_bnd
+
+
+def yk_plan_info_get(ctx, slot=0) -> yk_plan_info:
+    info = yk_plan_info()
+    _check(ctx, load_library().yk_plan_info_get(ctx, int(slot), ctypes.byref(info)))
+    return info
+
+
+def yk_timing_enable(ctx, enable=True):
+    _check(ctx, load_library().yk_timing_enable(ctx, 1 if enable else 0))
+
+
+def yk_timing_read(ctx, reset=False):
+    ms = (ctypes.c_double * len(STAGES))()
+    calls = (ctypes.c_int64 * len(STAGES))()
+    _check(ctx, load_library().yk_timing_read(ctx, ms, calls, 1 if reset else 0))
+    return {name: (ms[i], calls[i]) for i, name in enumerate(STAGES)}

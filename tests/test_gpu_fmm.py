@@ -1,0 +1,195 @@
+"""GPU parity of the FMM path against the CPU oracle's direct sums and dense solves."""
+import math
+
+import numpy as np
+import pytest
+
+import workloads as W
+from gpu_util import dev, host, rel_max
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def yk():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1007_5335_amd.yk as yk
+    yk.load_library()
+    return yk
+
+
+def _ctx(yk, **kw):
+    kw.setdefault("direct", 0)
+    return yk.yk_create(**kw)
+
+
+def rel_l2(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def _oracle_fmm_potential(oracle_lib, c):
+    b = c["bnd"]
+    vol, q, dip, al = c["vol"], c["q"], c["dip"], c["alpha"]
+    # dipole strength d_j with unit normal: pass weights 1 via dl_sum(d)
+    ov = oracle_lib.volume_sum(vol, q, al) + oracle_lib.dl_sum(b.xy, b.normal, dip, al, vol)
+    ob = oracle_lib.volume_sum(vol, q, al, tgt_xy=b.xy) + oracle_lib.dl_sum(b.xy, b.normal, dip, al, b.xy)
+    return ov, ob
+
+
+@pytest.mark.parametrize("alpha,leaf,clustered", [(0.05, 64, False), (0.05, 16, False),
+                                                  (0.01, 64, False), (0.2, 32, False),
+                                                  (0.05, 32, True)])
+def test_fmm_potential_vs_direct(yk, oracle_lib, alpha, leaf, clustered):
+    import torch
+    c = W.small_fmm_case(n_vol=6000, n_nodes=256, alpha=alpha, seed=5, clustered=clustered)
+    b = c["bnd"]
+    ctx = _ctx(yk, leaf_size=leaf, fmm_tol=1e-10, debug_flags=1)
+    try:
+        bd = yk.Boundary.from_workload(b)
+        ov = torch.empty(c["vol"].shape[0], dtype=torch.float64, device="cuda")
+        ob = torch.empty(b.n, dtype=torch.float64, device="cuda")
+        print(f"case alpha={alpha} leaf={leaf} clustered={clustered}", flush=True)
+        yk.yk_fmm_potential(ctx, dev(c["vol"]), dev(c["q"]), bd, dev(c["dip"]), alpha, ov, ob)
+        torch.cuda.synchronize()
+    finally:
+        yk.yk_destroy(ctx)
+    rv, rb = _oracle_fmm_potential(oracle_lib, c)
+    ev, eb = rel_l2(host(ov), rv), rel_l2(host(ob), rb)
+    print(f"  rel l2 err volume {ev:.2e} nodes {eb:.2e}", flush=True)
+    assert ev < 1e-10 and eb < 1e-10
+
+
+def test_fmm_volume_potential_separate_targets(yk, oracle_lib):
+    import torch
+    rng = np.random.default_rng(8)
+    src = rng.random((5000, 2)); q = rng.standard_normal(5000)
+    tgt = rng.random((1500, 2)) * 1.2 - 0.1          # some targets outside the sources' box
+    ctx = _ctx(yk, leaf_size=32, debug_flags=1)
+    try:
+        out = torch.empty(1500, dtype=torch.float64, device="cuda")
+        yk.yk_volume_potential(ctx, dev(src), dev(q), dev(tgt), 0.07, out)
+        out2 = torch.empty(5000, dtype=torch.float64, device="cuda")
+        yk.yk_volume_potential(ctx, dev(src), dev(q), None, 0.07, out2)
+        torch.cuda.synchronize()
+    finally:
+        yk.yk_destroy(ctx)
+    assert rel_l2(host(out), oracle_lib.volume_sum(src, q, 0.07, tgt_xy=tgt)) < 1e-10
+    assert rel_l2(host(out2), oracle_lib.volume_sum(src, q, 0.07)) < 1e-10
+
+
+def test_fmm_double_layer_on_surface(yk, oracle_lib):
+    import torch
+    c = W.small_fmm_case(n_vol=16, n_nodes=512, alpha=0.05, seed=2)
+    b = c["bnd"]
+    sig = np.cos(5 * b.xy[:, 0]) + b.xy[:, 1]
+    ctx = _ctx(yk, leaf_size=32, debug_flags=1)
+    try:
+        bd = yk.Boundary.from_workload(b)
+        out = torch.empty(b.n, dtype=torch.float64, device="cuda")
+        yk.yk_double_layer_apply(ctx, bd, dev(sig), None, 0.05, out)
+        torch.cuda.synchronize()
+    finally:
+        yk.yk_destroy(ctx)
+    ref = oracle_lib.dl_on_surface(b.xy, b.normal, b.weights(), b.curvature, sig, 0.05)
+    assert rel_l2(host(out), ref) < 1e-10
+
+
+def test_fmm_gmres_vs_dense_lu(yk, oracle_lib):
+    import torch
+    c = W.small_fmm_case(n_vol=16, n_nodes=256, alpha=0.05, seed=2)
+    b = c["bnd"]
+    g = np.sin(4 * b.xy[:, 0]) * np.cos(3 * b.xy[:, 1])
+    ctx = _ctx(yk, leaf_size=32, debug_flags=1)
+    try:
+        bd = yk.Boundary.from_workload(b)
+        sig = torch.empty(b.n, dtype=torch.float64, device="cuda")
+        st = yk.yk_gmres_density(ctx, bd, 0.05, dev(g), None, 1e-12, 200, sig)
+    finally:
+        yk.yk_destroy(ctx)
+    ref = oracle_lib.DenseBIE(b.xy, b.normal, b.weights(), b.curvature, 0.05).solve(g)
+    assert rel_l2(host(sig), ref) < 1e-10, st.as_dict()
+
+
+def test_fmm_heat_step_c0(yk, oracle_lib):
+    import torch
+    cfg = W.config_c0()
+    b = cfg["bnd"]
+    ctx = _ctx(yk, leaf_size=32, debug_flags=1)
+    try:
+        bd = yk.Boundary.from_workload(b)
+        n = cfg["vol"].shape[0]
+        sig = torch.zeros(b.n, dtype=torch.float64, device="cuda")
+        u = torch.empty(n, dtype=torch.float64, device="cuda")
+        st = yk.yk_heat_step(ctx, bd, dev(cfg["vol"]), dev(cfg["vol_w"]), dev(cfg["B"]),
+                             yk.HEAT_GRID_SELF_CELL | yk.HEAT_ZERO_GUESS, dev(cfg["f_next"]),
+                             cfg["dt"], 1e-13, sig, u)
+    finally:
+        yk.yk_destroy(ctx)
+    u_ref, s_ref, _ = oracle_lib.heat_step(b.xy, b.normal, b.weights(), b.curvature, cfg["vol"],
+                                           cfg["vol_w"], cfg["B"], cfg["f_next"], cfg["dt"],
+                                           grid_h=cfg["h"])
+    assert rel_l2(host(u), u_ref) < 1e-10, st.as_dict()
+    assert rel_l2(host(sig), s_ref) < 1e-10
+
+
+def test_fmm_fp32_mode_accuracy(yk, oracle_lib):
+    """FP32 near field and FP32 matrix-core M2L: error at FP32 level, stated."""
+    import torch
+    c = W.small_fmm_case(n_vol=6000, n_nodes=256, alpha=0.05, seed=5)
+    b = c["bnd"]
+    ctx = _ctx(yk, leaf_size=32, precision=yk.YK_PREC_FP32, debug_flags=1)
+    try:
+        bd = yk.Boundary.from_workload(b)
+        ov = torch.empty(c["vol"].shape[0], dtype=torch.float64, device="cuda")
+        ob = torch.empty(b.n, dtype=torch.float64, device="cuda")
+        yk.yk_fmm_potential(ctx, dev(c["vol"]), dev(c["q"]), bd, dev(c["dip"]), 0.05, ov, ob)
+        torch.cuda.synchronize()
+    finally:
+        yk.yk_destroy(ctx)
+    rv, rb = _oracle_fmm_potential(oracle_lib, c)
+    ev, eb = rel_l2(host(ov), rv), rel_l2(host(ob), rb)
+    print(f"  fp32 rel l2 err volume {ev:.2e} nodes {eb:.2e}", flush=True)
+    assert ev < 2e-5 and eb < 2e-5
+
+
+@pytest.mark.parametrize("p", [8, 16, 24, 31])
+def test_fmm_order_sweep_small(yk, oracle_lib, p):
+    """Each padded order (16/32/48/64 coefficients) runs and converges with p."""
+    import torch
+    c = W.small_fmm_case(n_vol=4000, n_nodes=128, alpha=0.05, seed=6)
+    b = c["bnd"]
+    ctx = _ctx(yk, leaf_size=16, p=p, debug_flags=1)
+    try:
+        bd = yk.Boundary.from_workload(b)
+        ov = torch.empty(c["vol"].shape[0], dtype=torch.float64, device="cuda")
+        ob = torch.empty(b.n, dtype=torch.float64, device="cuda")
+        yk.yk_fmm_potential(ctx, dev(c["vol"]), dev(c["q"]), bd, dev(c["dip"]), 0.05, ov, ob)
+        torch.cuda.synchronize()
+        info = yk.yk_plan_info_get(ctx, 0)
+    finally:
+        yk.yk_destroy(ctx)
+    rv, rb = _oracle_fmm_potential(oracle_lib, c)
+    err = rel_l2(np.concatenate([host(ov), host(ob)]), np.concatenate([rv, rb]))
+    print(f"  p={p} Pp={info.Pp} L={info.leaf_level} err={err:.2e}", flush=True)
+    bound = {8: 1e-3, 16: 1e-7, 24: 1e-10, 31: 1e-12}[p]
+    assert err < bound
+
+
+def test_mixed_precision_gmres_refines_to_fp64(yk, oracle_lib):
+    import torch
+    c = W.small_fmm_case(n_vol=16, n_nodes=256, alpha=0.05, seed=2)
+    b = c["bnd"]
+    g = np.sin(4 * b.xy[:, 0]) * np.cos(3 * b.xy[:, 1])
+    ctx = _ctx(yk, leaf_size=32, precision=yk.YK_PREC_MIXED, debug_flags=1)
+    try:
+        bd = yk.Boundary.from_workload(b)
+        sig = torch.empty(b.n, dtype=torch.float64, device="cuda")
+        st = yk.yk_gmres_density(ctx, bd, 0.05, dev(g), None, 1e-12, 200, sig)
+    finally:
+        yk.yk_destroy(ctx)
+    ref = oracle_lib.DenseBIE(b.xy, b.normal, b.weights(), b.curvature, 0.05).solve(g)
+    print("  mixed", st.as_dict(), flush=True)
+    assert st.res_final <= 1e-12 and st.outer_iters >= 1
+    assert rel_l2(host(sig), ref) < 1e-10
