@@ -86,6 +86,11 @@ struct FmmPlan {
     DevBuf<uint32_t> bcode;            // Morton code per box
     DevBuf<int32_t> fchild, nchild;    // first child (global index) and child count
     DevBuf<int32_t> slot_oid;          // [4 classes][27 slots] -> offset id in 0..39
+    DevBuf<int32_t> child4;            // [nbox][4] child at each position, -1 if none
+    DevBuf<int32_t> iota4;             // {0,1,2,3}: slot -> operator for M2M and L2L
+    DevBuf<int4> up_tiles;             // M2M tiles: parents of levels lmin..L-1, 64 per tile
+    DevBuf<int32_t> up_boxes;
+    std::vector<int> up_tile_begin, up_tile_count;
     DevBuf<double> serc;               // [2][nser]: series coefficients of F_{p+1}, F_{p+2}
     DevBuf<int32_t> vlist;             // [nbox][27]
     DevBuf<int32_t> lrange;            // [nleaf][6] start/end per set (sorted positions)
@@ -98,7 +103,7 @@ struct FmmPlan {
 
     // operators (double, column-major Pp x Pp blocks)
     DevBuf<double> m2m, l2l, m2l;      // [level][4][Pp*Pp], [level][4][Pp*Pp], [level][40][Pp*Pp]
-    DevBuf<float> m2lf;
+    DevBuf<float> m2lf, l2lf;
     DevBuf<double> invFY, dipa, dipb;  // [level][p+2]
     DevBuf<double> cnn;                // 1/((n+1)(n+2)), n = 0 .. p+3
 

@@ -55,29 +55,45 @@ __device__ __forceinline__ void f_start(double y, const double *__restrict__ sc,
 }
 
 // ------------------------------------------------------------------- P2M ---
-// One wavefront per leaf; lanes over source points.  Each lane builds
-// G_n = F_n(y)/F_n(Y) for n = 0..p+1 in LDS (downwards), then the terms
-// q G_n conj(z)^n (upwards) are summed over the wavefront with shuffles.
+// One wavefront serves four leaves, 16 lanes each; lanes over source points.
+// Each lane builds G_n = F_n(y)/F_n(Y) for n = 0..p+1 in its own LDS column
+// (downwards), then the terms q G_n conj(z)^n (upwards) are summed over the
+// 16 lanes of the leaf with shuffles.
+__device__ __forceinline__ double group16_sum(double v) {
+#pragma unroll
+    for (int off = 8; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
 __global__ __launch_bounds__(64) void k_p2m(
-    int64_t leaf_base, const int32_t *__restrict__ lrange, const double *__restrict__ bcx,
-    const double *__restrict__ bcy, const double *__restrict__ px, const double *__restrict__ py,
-    const double *__restrict__ qs, const double *__restrict__ dns, int64_t off1, int has_q,
-    int has_d, double inv_alpha, double invR, const double *__restrict__ invFY,
-    const double *__restrict__ da, const double *__restrict__ db, const double *__restrict__ cnn,
-    const double *__restrict__ sc, int nser, int p, int Pp, double *__restrict__ M) {
+    int64_t leaf_base, int64_t nleaf, const int32_t *__restrict__ lrange,
+    const double *__restrict__ bcx, const double *__restrict__ bcy, const double *__restrict__ px,
+    const double *__restrict__ py, const double *__restrict__ qs, const double *__restrict__ dns,
+    int64_t off1, int has_q, int has_d, double inv_alpha, double invR,
+    const double *__restrict__ invFY, const double *__restrict__ da, const double *__restrict__ db,
+    const double *__restrict__ cnn, const double *__restrict__ sc, int nser, int p, int Pp,
+    double *__restrict__ M) {
     extern __shared__ double smem[];
     double *G = smem;                    // [(p+2)][64]
-    double *Msh = smem + (p + 2) * 64;   // [Pp]
-    const int li = blockIdx.x, lane = threadIdx.x;
-    const int64_t b = leaf_base + li;
-    for (int k = lane; k < Pp; k += 64) Msh[k] = 0.0;
+    double *Msh = smem + (p + 2) * 64;   // [4][Pp]
+    const int lane = threadIdx.x, grp = lane >> 4, gl = lane & 15;
+    const int64_t li = (int64_t)blockIdx.x * 4 + grp;
+    const bool leaf_ok = li < nleaf;
+    const int64_t b = leaf_base + (leaf_ok ? li : 0);
+    double *Mg = Msh + grp * Pp;
+    for (int k = gl; k < Pp; k += 16) Mg[k] = 0.0;
     __syncthreads();
     const double cx = bcx[b], cy = bcy[b];
     for (int set = 0; set < 2; ++set) {
         if ((set == 0 && !has_q) || (set == 1 && !has_d)) continue;
-        const int s0 = lrange[li * 6 + 2 * set], e0 = lrange[li * 6 + 2 * set + 1];
-        for (int base = s0; base < e0; base += 64) {
-            const int j = base + lane;
+        const int s0 = leaf_ok ? lrange[li * 6 + 2 * set] : 0;
+        const int e0 = leaf_ok ? lrange[li * 6 + 2 * set + 1] : 0;
+        // uniform trip count over the four groups
+        int nmax = e0 - s0;
+        nmax = max(nmax, __shfl_xor(nmax, 16, 64));
+        nmax = max(nmax, __shfl_xor(nmax, 32, 64));
+        for (int base = 0; base < nmax; base += 16) {
+            const int j = s0 + base + gl;
             const bool valid = j < e0;
             const double wx = valid ? (px[j] - cx) * inv_alpha : 0.0;
             const double wy = valid ? (py[j] - cy) * inv_alpha : 0.0;
@@ -92,16 +108,15 @@ __global__ __launch_bounds__(64) void k_p2m(
                 F2 = F1;
                 F1 = F0;
             }
-            // (the LDS column is private to the lane: no barrier needed)
             if (set == 0) {
                 const double q = valid ? qs[j] : 0.0;
                 double pr = 1.0, pi = 0.0;     // conj(z)^n
                 for (int n = 0; n <= p; ++n) {
                     const double g = q * G[n * 64 + lane];
-                    const double tr = wave_sum(g * pr), ti = wave_sum(g * pi);
-                    if (lane == 0) {
-                        if (n == 0) Msh[0] += tr;
-                        else { Msh[2 * n - 1] += tr; Msh[2 * n] += ti; }
+                    const double tr = group16_sum(g * pr), ti = group16_sum(g * pi);
+                    if (gl == 0) {
+                        if (n == 0) Mg[0] += tr;
+                        else { Mg[2 * n - 1] += tr; Mg[2 * n] += ti; }
                     }
                     const double nr = pr * zx - pi * zy;
                     pi = pr * zy + pi * zx;
@@ -113,7 +128,7 @@ __global__ __launch_bounds__(64) void k_p2m(
                 const double h = 0.5 * inv_alpha;
                 // window Psi_{n-1}, Psi_n, Psi_{n+1};  Psi_k = G_k conj(z)^k
                 double pr = zx, pi = zy;                       // conj(z)^1
-                double g1 = G[1 * 64 + lane];
+                const double g1 = G[1 * 64 + lane];
                 double c_r = G[0 * 64 + lane], c_i = 0.0;      // Psi_0
                 double n_r = g1 * pr, n_i = g1 * pi;           // Psi_1
                 double m_r = n_r, m_i = -n_i;                  // Psi_{-1} = conj(Psi_1)
@@ -122,13 +137,12 @@ __global__ __launch_bounds__(64) void k_p2m(
                     const double an = da[n], bn = db[n];
                     const double t1r = Dx * n_r - Dy * n_i, t1i = Dx * n_i + Dy * n_r;
                     const double t2r = Dx * m_r + Dy * m_i, t2i = Dx * m_i - Dy * m_r;
-                    const double tr = wave_sum(h * (an * t1r + bn * t2r));
-                    const double ti = wave_sum(h * (an * t1i + bn * t2i));
-                    if (lane == 0) {
-                        if (n == 0) Msh[0] += tr;
-                        else { Msh[2 * n - 1] += tr; Msh[2 * n] += ti; }
+                    const double tr = group16_sum(h * (an * t1r + bn * t2r));
+                    const double ti = group16_sum(h * (an * t1i + bn * t2i));
+                    if (gl == 0) {
+                        if (n == 0) Mg[0] += tr;
+                        else { Mg[2 * n - 1] += tr; Mg[2 * n] += ti; }
                     }
-                    // advance the window
                     m_r = c_r; m_i = c_i;
                     c_r = n_r; c_i = n_i;
                     const double nr = pr * zx - pi * zy;
@@ -145,7 +159,8 @@ __global__ __launch_bounds__(64) void k_p2m(
         }
     }
     __syncthreads();
-    for (int k = lane; k < Pp; k += 64) M[b * Pp + k] = Msh[k];
+    if (leaf_ok)
+        for (int k = gl; k < Pp; k += 16) M[b * Pp + k] = Mg[k];
 }
 
 // ------------------------------------------------------------ M2M / L2L ---
@@ -284,13 +299,19 @@ template <> struct Mfma<float> {
     static __device__ __forceinline__ int row(int lane, int r) { return 4 * (lane >> 4) + r; }
 };
 
-template <typename T, int PP>
-__global__ __launch_bounds__(256) void k_m2l_mfma(const int4 *__restrict__ tiles, int tile0,
-                                                  const int32_t *__restrict__ boxes,
-                                                  const int32_t *__restrict__ vlist,
-                                                  const int32_t *__restrict__ slot_oid,
-                                                  const T *__restrict__ Top,
-                                                  const T *__restrict__ M, double *__restrict__ Lc) {
+// Generic form used for M2L (27 V-list slots per box), M2M (4 child slots per
+// parent) and L2L (1 parent slot per child):
+//   out[box] (+)= sum_s Op[level + level_shift][slot_op[cls][s]] * X[src[box][s]]
+// Every box of a tile has the same level and parity class (so the same
+// operator per slot).  X is read in its own type TS and converted to T.
+template <typename T, typename TS, int PP>
+__global__ __launch_bounds__(256) void k_tile_gemm(const int4 *__restrict__ tiles, int tile0,
+                                                   const int32_t *__restrict__ boxes, int nslot,
+                                                   const int32_t *__restrict__ src,
+                                                   const int32_t *__restrict__ slot_op,
+                                                   const T *__restrict__ Op, int64_t op_stride,
+                                                   int level_shift, const TS *__restrict__ X,
+                                                   int assign, double *__restrict__ out) {
     constexpr int NRT = PP / 16, NKS = PP / 4, NLD = PP * PP / 256;
     __shared__ T As[2][PP * PP];
     using MF = Mfma<T>;
@@ -303,79 +324,85 @@ __global__ __launch_bounds__(256) void k_m2l_mfma(const int4 *__restrict__ tiles
     typename MF::acc acc[NRT];
 #pragma unroll
     for (int r = 0; r < NRT; ++r) acc[r] = typename MF::acc{0, 0, 0, 0};
-    const T *Tlev = Top + (size_t)level * kNumOff * PP * PP;
-    T pre[NLD];
+    const T *Olev = Op + (int64_t)(level + level_shift) * op_stride;
+    auto op_of = [&](int sl) -> const T * { return Olev + (size_t)slot_op[cls * nslot + sl] * PP * PP; };
+    auto load_b = [&](int sl, T (&bf)[NKS]) {
+        const int32_t sj = colvalid ? src[boxj * nslot + sl] : -1;
+        const TS *row = X + (int64_t)(sj >= 0 ? sj : 0) * PP + (lane >> 4);
+#pragma unroll
+        for (int ks = 0; ks < NKS; ++ks) bf[ks] = sj >= 0 ? (T)row[4 * ks] : T(0);
+    };
+    T bcur[NKS], bnxt[NKS], pre[NLD];
+    load_b(0, bcur);
     {
-        const T *Tg = Tlev + (size_t)slot_oid[cls * kNumV] * PP * PP;
+        const T *Tg = op_of(0);
 #pragma unroll
         for (int e = 0; e < NLD; ++e) As[0][tid + 256 * e] = Tg[tid + 256 * e];
     }
     __syncthreads();
-    for (int slot = 0; slot < kNumV; ++slot) {
+    for (int slot = 0; slot < nslot; ++slot) {
         const int cur = slot & 1;
-        if (slot + 1 < kNumV) {
-            const T *Tg = Tlev + (size_t)slot_oid[cls * kNumV + slot + 1] * PP * PP;
+        const bool more = slot + 1 < nslot;
+        if (more) {
+            load_b(slot + 1, bnxt);
+            const T *Tg = op_of(slot + 1);
 #pragma unroll
             for (int e = 0; e < NLD; ++e) pre[e] = Tg[tid + 256 * e];
         }
-        const int32_t src = colvalid ? vlist[boxj * kNumV + slot] : -1;
-        const T *mrow = M + (int64_t)(src >= 0 ? src : 0) * PP;
-        const T *Ac = As[cur];
+        const T *Ac = As[cur] + (lane >> 4) * PP + (lane & 15);
 #pragma unroll
         for (int ks = 0; ks < NKS; ++ks) {
-            const int kk = 4 * ks + (lane >> 4);
-            const T bv = src >= 0 ? mrow[kk] : T(0);
 #pragma unroll
             for (int rt = 0; rt < NRT; ++rt)
-                acc[rt] = MF::step(Ac[kk * PP + 16 * rt + (lane & 15)], bv, acc[rt]);
+                acc[rt] = MF::step(Ac[4 * ks * PP + 16 * rt], bcur[ks], acc[rt]);
         }
-        if (slot + 1 < kNumV) {
+        if (more) {
 #pragma unroll
             for (int e = 0; e < NLD; ++e) As[cur ^ 1][tid + 256 * e] = pre[e];
+#pragma unroll
+            for (int ks = 0; ks < NKS; ++ks) bcur[ks] = bnxt[ks];
         }
         __syncthreads();
     }
     if (colvalid) {
+        double *o = out + boxj * PP;
 #pragma unroll
         for (int rt = 0; rt < NRT; ++rt)
 #pragma unroll
-            for (int r = 0; r < 4; ++r) Lc[boxj * PP + 16 * rt + MF::row(lane, r)] += (double)acc[rt][r];
+            for (int r = 0; r < 4; ++r) {
+                const int i = 16 * rt + MF::row(lane, r);
+                o[i] = assign ? (double)acc[rt][r] : o[i] + (double)acc[rt][r];
+            }
     }
 }
 
-using M2LKernel = void (*)(const int4 *, int, const int32_t *, const int32_t *, const int32_t *,
-                           const void *, const void *, double *);
+template <typename T, typename TS>
+void launch_tile_gemm(Context &ctx, int Pp, int ntiles, const int4 *tiles, int tile0,
+                      const int32_t *boxes, int nslot, const int32_t *src, const int32_t *slot_op,
+                      const T *Op, int64_t op_stride, int level_shift, const TS *X, int assign,
+                      double *out) {
+    if (ntiles <= 0) return;
+#define YK_TILE_CASE(PPV)                                                                          \
+    case PPV:                                                                                      \
+        hipLaunchKernelGGL((k_tile_gemm<T, TS, PPV>), dim3(ntiles), dim3(256), 0, ctx.stream, tiles, \
+                           tile0, boxes, nslot, src, slot_op, Op, op_stride, level_shift, X, assign,  \
+                           out);                                                                   \
+        break;
+    switch (Pp) {
+        YK_TILE_CASE(16)
+        YK_TILE_CASE(32)
+        YK_TILE_CASE(48)
+        YK_TILE_CASE(64)
+        default:
+            throw Error{YK_ERR_INTERNAL, "no matrix-core kernel for this padded order"};
+    }
+#undef YK_TILE_CASE
+    check_launch(ctx, "k_tile_gemm");
+}
 
 __global__ void k_to_float(int64_t n, const double *__restrict__ a, float *__restrict__ b) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) b[i] = (float)a[i];
-}
-
-template <typename T>
-void launch_m2l_mfma(Context &ctx, int Pp, int ntiles, const int4 *tiles, int tile0,
-                     const int32_t *boxes, const int32_t *vlist, const int32_t *soid, const T *Top,
-                     const T *M, double *Lc) {
-    switch (Pp) {
-        case 16:
-            hipLaunchKernelGGL((k_m2l_mfma<T, 16>), dim3(ntiles), dim3(256), 0, ctx.stream, tiles, tile0,
-                               boxes, vlist, soid, Top, M, Lc);
-            break;
-        case 32:
-            hipLaunchKernelGGL((k_m2l_mfma<T, 32>), dim3(ntiles), dim3(256), 0, ctx.stream, tiles, tile0,
-                               boxes, vlist, soid, Top, M, Lc);
-            break;
-        case 48:
-            hipLaunchKernelGGL((k_m2l_mfma<T, 48>), dim3(ntiles), dim3(256), 0, ctx.stream, tiles, tile0,
-                               boxes, vlist, soid, Top, M, Lc);
-            break;
-        case 64:
-            hipLaunchKernelGGL((k_m2l_mfma<T, 64>), dim3(ntiles), dim3(256), 0, ctx.stream, tiles, tile0,
-                               boxes, vlist, soid, Top, M, Lc);
-            break;
-        default:
-            throw Error{YK_ERR_INTERNAL, "no MFMA M2L kernel for this padded order"};
-    }
-    check_launch(ctx, "k_m2l_mfma");
 }
 
 // ----------------------------------------------------------- leaf kernel ---
@@ -397,7 +424,7 @@ __device__ __forceinline__ T horner_n(const T (&c)[YK_NSER64], T t) {
 template <int NT, bool kSmallOnly>
 __device__ __forceinline__ double near_k0(double t) {
     if (kSmallOnly || t <= 1.0) {
-        const double lt = log(t);
+        const double lt = fast_log(t);
         return -0.5 * lt * horner_n<NT>(yk_ser_A, t) + horner_n<NT>(yk_ser_B, t);
     }
     return k0_large(2.0 * sqrt(t));
@@ -405,8 +432,8 @@ __device__ __forceinline__ double near_k0(double t) {
 template <int NT, bool kSmallOnly>
 __device__ __forceinline__ double near_k1oz(double t) {
     if (kSmallOnly || t <= 1.0) {
-        const double lt = log(t);
-        return 0.25 / t + 0.25 * lt * horner_n<NT>(yk_ser_C, t) - 0.25 * horner_n<NT>(yk_ser_D, t);
+        const double lt = fast_log(t);
+        return 0.25 * fast_rcp(t) + 0.25 * lt * horner_n<NT>(yk_ser_C, t) - 0.25 * horner_n<NT>(yk_ser_D, t);
     }
     const double z = 2.0 * sqrt(t);
     return k1_large(z) / z;
@@ -454,6 +481,10 @@ struct Near {
     }
 };
 
+// Sources of the U-list are staged into LDS in chunks of kLeafStage (a single
+// wavefront, so the barriers are cheap), then every lane group walks the chunk.
+constexpr int kLeafStage = 512;
+
 template <int NT, bool kSmallOnly, bool kF32 = false>
 __global__ __launch_bounds__(64) void k_leaf(
     const int32_t *__restrict__ leaves, int64_t leaf_base, const int32_t *__restrict__ lrange,
@@ -464,6 +495,7 @@ __global__ __launch_bounds__(64) void k_leaf(
     double inv_alpha, double invR, const double *__restrict__ invFY,
     const double *__restrict__ cnn, const double *__restrict__ sc, int nser, int p, int Pp,
     double inv4a2, double inva2, double *__restrict__ outs) {
+    __shared__ double s_x[kLeafStage], s_y[kLeafStage], s_a[kLeafStage], s_b[kLeafStage];
     const int li = leaves[blockIdx.x];
     const int64_t b = leaf_base + li;
     const int lane = threadIdx.x;
@@ -474,7 +506,21 @@ __global__ __launch_bounds__(64) void k_leaf(
         re[s] = (mask >> s) & 1 ? lrange[li * 6 + 2 * s + 1] : rs[s];
         ntot += re[s] - rs[s];
     }
-    const int u0 = uoff[li], u1 = uoff[li + 1];
+    const int u0 = uoff[li], nu = uoff[li + 1] - u0;
+    // U-list source ranges (at most 9 neighbours) of the two source sets
+    int qa[9], qn[9], da[9], dn_[9], nq = 0, nd = 0;
+    for (int u = 0; u < 9; ++u) {
+        qa[u] = qn[u] = da[u] = dn_[u] = 0;
+        if (u < nu) {
+            const int ul = ulist[u0 + u];
+            qa[u] = lrange[ul * 6];
+            qn[u] = has_q ? lrange[ul * 6 + 1] - qa[u] : 0;
+            da[u] = lrange[ul * 6 + 2];
+            dn_[u] = has_d ? lrange[ul * 6 + 3] - da[u] : 0;
+            nq += qn[u];
+            nd += dn_[u];
+        }
+    }
     const double *Lb = Lc + b * Pp;
     for (int tb = 0; tb < ntot; tb += 64) {
         const int c = min(64, ntot - tb);
@@ -514,25 +560,41 @@ __global__ __launch_bounds__(64) void k_leaf(
         }
         using NearT = Near<NT, kSmallOnly, kF32>;
         typename NearT::acc_t near = 0;
-        if (valid) {
-            for (int u = u0; u < u1; ++u) {
-                const int ul = ulist[u];
-                if (has_q) {
-                    const int a1 = lrange[ul * 6 + 1];
-                    for (int j = lrange[ul * 6] + sub; j < a1; j += g) {
-                        const double dx = x - px[j], dy = y - py[j];
-                        const double r2 = dx * dx + dy * dy;
-                        if (r2 > 0.0) near += NearT::charge(qs[j], r2, inv4a2);
+        for (int set = 0; set < 2; ++set) {
+            const int ntot_s = set == 0 ? nq : nd;
+            for (int c0 = 0; c0 < ntot_s; c0 += kLeafStage) {
+                const int cn = min(kLeafStage, ntot_s - c0);
+                __syncthreads();
+                // cooperative gather of flat source indices [c0, c0 + cn) into LDS
+                for (int f = lane; f < cn; f += 64) {
+                    int r = c0 + f, u = 0;
+                    const int *cnt = set == 0 ? qn : dn_;
+                    while (u < 8 && r >= cnt[u]) { r -= cnt[u]; ++u; }
+                    const int j = (set == 0 ? qa[u] : da[u]) + r;
+                    s_x[f] = px[j];
+                    s_y[f] = py[j];
+                    if (set == 0) {
+                        s_a[f] = qs[j];
+                    } else {
+                        const int64_t jd = j - off1;
+                        s_a[f] = dns[2 * jd];
+                        s_b[f] = dns[2 * jd + 1];
                     }
                 }
-                if (has_d) {
-                    const int a1 = lrange[ul * 6 + 3];
-                    for (int j = lrange[ul * 6 + 2] + sub; j < a1; j += g) {
-                        const double dx = x - px[j], dy = y - py[j];
-                        const double r2 = dx * dx + dy * dy;
-                        const int64_t jd = j - off1;
-                        if (r2 > 0.0)
-                            near += NearT::dipole(dx * dns[2 * jd] + dy * dns[2 * jd + 1], r2, inv4a2, inva2);
+                __syncthreads();
+                if (valid) {
+                    if (set == 0) {
+                        for (int j = sub; j < cn; j += g) {
+                            const double dx = x - s_x[j], dy = y - s_y[j];
+                            const double r2 = dx * dx + dy * dy;
+                            if (r2 > 0.0) near += NearT::charge(s_a[j], r2, inv4a2);
+                        }
+                    } else {
+                        for (int j = sub; j < cn; j += g) {
+                            const double dx = x - s_x[j], dy = y - s_y[j];
+                            const double r2 = dx * dx + dy * dy;
+                            if (r2 > 0.0) near += NearT::dipole(dx * s_a[j] + dy * s_b[j], r2, inv4a2, inva2);
+                        }
                     }
                 }
             }
@@ -595,10 +657,11 @@ void fmm_run(Context &ctx, FmmPlan &pl, const double *q, const double *dn, doubl
     const size_t lvl = (size_t)(p + 2);
     if (far) {
         // upward pass
-        const size_t sh = ((size_t)(p + 2) * 64 + Pp) * sizeof(double);
+        const size_t sh = ((size_t)(p + 2) * 64 + 4 * Pp) * sizeof(double);
         {
         StageTimer tm(ctx, YK_STAGE_P2M);
-        hipLaunchKernelGGL(k_p2m, dim3(pl.nleaf), dim3(64), sh, ctx.stream, leaf_base, pl.lrange.p,
+        hipLaunchKernelGGL(k_p2m, dim3((unsigned)((pl.nleaf + 3) / 4)), dim3(64), sh, ctx.stream, leaf_base,
+                           pl.nleaf, pl.lrange.p,
                            pl.bcx.p, pl.bcy.p, pl.px.p, pl.py.p, qs, dns, pl.toff[1], has_q, has_d,
                            inv_alpha, 1.0 / pl.lev[L].R, pl.invFY.p + L * lvl, pl.dipa.p + L * lvl,
                            pl.dipb.p + L * lvl, pl.cnn.p, pl.serc.p, pl.nser, p, Pp, pl.M.p);
@@ -607,14 +670,23 @@ void fmm_run(Context &ctx, FmmPlan &pl, const double *q, const double *dn, doubl
         {
             StageTimer tmm(ctx, YK_STAGE_M2M);
             for (int l = L - 1; l >= pl.lmin; --l) {
-                const int64_t nbl = pl.lev[l].end - pl.lev[l].begin;
-                hipLaunchKernelGGL(k_m2m, dim3(nbl), dim3(128), Pp * sizeof(double), ctx.stream,
-                                   pl.lev[l].begin, pl.fchild.p, pl.nchild.p, pl.bcode.p,
-                                   pl.m2m.p + (size_t)l * 4 * Pp * Pp, P, Pp, pl.M.p);
-                check_launch(ctx, "k_m2m");
+                if (Pp <= 64) {
+                    // M2M on matrix cores: 4 child slots, operators S[l][position]
+                    launch_tile_gemm<double, double>(ctx, Pp, pl.up_tile_count[l], pl.up_tiles.p,
+                                                     pl.up_tile_begin[l], pl.up_boxes.p, 4, pl.child4.p,
+                                                     pl.iota4.p, pl.m2m.p, (int64_t)4 * Pp * Pp, 0, pl.M.p,
+                                                     1, pl.M.p);
+                } else {
+                    const int64_t nbl = pl.lev[l].end - pl.lev[l].begin;
+                    hipLaunchKernelGGL(k_m2m, dim3(nbl), dim3(128), Pp * sizeof(double), ctx.stream,
+                                       pl.lev[l].begin, pl.fchild.p, pl.nchild.p, pl.bcode.p,
+                                       pl.m2m.p + (size_t)l * 4 * Pp * Pp, P, Pp, pl.M.p);
+                    check_launch(ctx, "k_m2m");
+                }
             }
         }
-        if (prec == SUM_FP32 && Pp <= 64) {
+        const bool f32 = prec == SUM_FP32 && Pp <= 64;
+        if (f32) {
             const int64_t nm = pl.nbox * (int64_t)Pp;
             float *mf = pl.Mf.ensure(nm);
             hipLaunchKernelGGL(k_to_float, dim3(nblk(nm, 256)), dim3(256), 0, ctx.stream, nm, pl.M.p, mf);
@@ -622,25 +694,44 @@ void fmm_run(Context &ctx, FmmPlan &pl, const double *q, const double *dn, doubl
         }
         // downward pass
         YK_HIP(hipMemsetAsync(pl.Lc.p, 0, (size_t)pl.nbox * Pp * sizeof(double), ctx.stream));
-        for (int l = pl.lmin; l <= L; ++l) {
-            if (l > pl.lmin && as.l2l_count[l] > 0) {
-                StageTimer tl(ctx, YK_STAGE_L2L);
-                hipLaunchKernelGGL(k_l2l, dim3(as.l2l_count[l]), dim3(128), Pp * sizeof(double), ctx.stream,
-                                   as.l2l_boxes.p + as.l2l_begin[l], pl.bparent.p, pl.bcode.p,
-                                   pl.l2l.p + (size_t)(l - 1) * 4 * Pp * Pp, P, Pp, pl.Lc.p);
-                check_launch(ctx, "k_l2l");
-            }
-            if (as.tile_count[l] > 0) {
+        if (Pp <= 64) {
+            {
+                // M2L of every level at once (levels are independent given the multipoles)
                 StageTimer tl(ctx, YK_STAGE_M2L);
-                if (Pp <= 64 && prec == SUM_FP32) {
-                    launch_m2l_mfma<float>(ctx, Pp, as.tile_count[l], as.m2l_tiles.p, as.tile_begin[l],
-                                           as.m2l_boxes.p, pl.vlist.p, pl.slot_oid.p, pl.m2lf.p, pl.Mf.p,
-                                           pl.Lc.p);
-                } else if (Pp <= 64) {
-                    launch_m2l_mfma<double>(ctx, Pp, as.tile_count[l], as.m2l_tiles.p, as.tile_begin[l],
-                                            as.m2l_boxes.p, pl.vlist.p, pl.slot_oid.p, pl.m2l.p, pl.M.p,
-                                            pl.Lc.p);
-                } else {
+                if (f32)
+                    launch_tile_gemm<float, float>(ctx, Pp, as.n_tiles, as.m2l_tiles.p, 0, as.m2l_boxes.p,
+                                                   kNumV, pl.vlist.p, pl.slot_oid.p, pl.m2lf.p,
+                                                   (int64_t)kNumOff * Pp * Pp, 0, pl.Mf.p, 0, pl.Lc.p);
+                else
+                    launch_tile_gemm<double, double>(ctx, Pp, as.n_tiles, as.m2l_tiles.p, 0, as.m2l_boxes.p,
+                                                     kNumV, pl.vlist.p, pl.slot_oid.p, pl.m2l.p,
+                                                     (int64_t)kNumOff * Pp * Pp, 0, pl.M.p, 0, pl.Lc.p);
+            }
+            StageTimer tl2(ctx, YK_STAGE_L2L);
+            for (int l = pl.lmin + 1; l <= L; ++l) {
+                // L2L top-down: one parent slot, operator E[l-1][position]
+                if (f32)
+                    launch_tile_gemm<float, double>(ctx, Pp, as.tile_count[l], as.m2l_tiles.p,
+                                                    as.tile_begin[l], as.m2l_boxes.p, 1, pl.bparent.p,
+                                                    pl.iota4.p, pl.l2lf.p, (int64_t)4 * Pp * Pp, -1, pl.Lc.p,
+                                                    0, pl.Lc.p);
+                else
+                    launch_tile_gemm<double, double>(ctx, Pp, as.tile_count[l], as.m2l_tiles.p,
+                                                     as.tile_begin[l], as.m2l_boxes.p, 1, pl.bparent.p,
+                                                     pl.iota4.p, pl.l2l.p, (int64_t)4 * Pp * Pp, -1, pl.Lc.p,
+                                                     0, pl.Lc.p);
+            }
+        } else {
+            for (int l = pl.lmin; l <= L; ++l) {
+                if (l > pl.lmin && as.l2l_count[l] > 0) {
+                    StageTimer tl(ctx, YK_STAGE_L2L);
+                    hipLaunchKernelGGL(k_l2l, dim3(as.l2l_count[l]), dim3(128), Pp * sizeof(double), ctx.stream,
+                                       as.l2l_boxes.p + as.l2l_begin[l], pl.bparent.p, pl.bcode.p,
+                                       pl.l2l.p + (size_t)(l - 1) * 4 * Pp * Pp, P, Pp, pl.Lc.p);
+                    check_launch(ctx, "k_l2l");
+                }
+                if (as.tile_count[l] > 0) {
+                    StageTimer tl(ctx, YK_STAGE_M2L);
                     const size_t shm = ((size_t)kM2LChunk * Pp + (size_t)kM2LTile * Pp) * sizeof(double);
                     hipLaunchKernelGGL(k_m2l, dim3(as.tile_count[l]), dim3(256), shm, ctx.stream,
                                        as.m2l_tiles.p, as.tile_begin[l], as.m2l_boxes.p, pl.vlist.p,

@@ -269,6 +269,24 @@ void build_lists_and_tables(Context &ctx, FmmPlan &pl, const std::vector<uint32_
         if (fch[pa] < 0) fch[pa] = (int32_t)b;
         nch[pa]++;
     }
+    // ---- children by position, and M2M tiles (64 parents of one level) ----
+    std::vector<int32_t> ch4((size_t)nb * 4, -1);
+    for (int64_t b = 0; b < nb; ++b)
+        if (pl.hparent[b] >= 0) ch4[(size_t)pl.hparent[b] * 4 + (pl.hcode[b] & 3u)] = (int32_t)b;
+    std::vector<int4> utiles;
+    std::vector<int32_t> uboxes;
+    pl.up_tile_begin.assign(L + 1, 0);
+    pl.up_tile_count.assign(L + 1, 0);
+    for (int l = lmin; l < L; ++l) {
+        pl.up_tile_begin[l] = (int)utiles.size();
+        for (int64_t b = pl.lev[l].begin; b < pl.lev[l].end; b += 64) {
+            const int cnt = (int)std::min<int64_t>(64, pl.lev[l].end - b);
+            utiles.push_back(make_int4(l, 0, (int)uboxes.size(), cnt));
+            for (int k = 0; k < cnt; ++k) uboxes.push_back((int32_t)(b + k));
+        }
+        pl.up_tile_count[l] = (int)utiles.size() - pl.up_tile_begin[l];
+    }
+    const std::vector<int32_t> iota4 = {0, 1, 2, 3};
     // ---- slot -> offset id for the 4 parity classes ----
     std::vector<int32_t> soid(4 * kNumV);
     for (int cls = 0; cls < 4; ++cls) {
@@ -301,6 +319,12 @@ void build_lists_and_tables(Context &ctx, FmmPlan &pl, const std::vector<uint32_
     up(pl.fchild, fch);
     up(pl.nchild, nch);
     up(pl.slot_oid, soid);
+    up(pl.child4, ch4);
+    up(pl.iota4, iota4);
+    if (!utiles.empty()) {
+        up(pl.up_tiles, utiles);
+        up(pl.up_boxes, uboxes);
+    }
     up(pl.vlist, vl);
     up(pl.lrange, pl.h_lrange);
     up(pl.ulist_off, uoff);
@@ -419,6 +443,8 @@ void build_lists_and_tables(Context &ctx, FmmPlan &pl, const std::vector<uint32_
     {
         std::vector<float> f(m2l.begin(), m2l.end());
         up(pl.m2lf, f);
+        std::vector<float> g(l2l.begin(), l2l.end());
+        up(pl.l2lf, g);
     }
     pl.M.ensure((size_t)nb * Pp);
     pl.Lc.ensure((size_t)nb * Pp);

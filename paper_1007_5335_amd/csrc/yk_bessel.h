@@ -66,6 +66,47 @@ YK_HD double k1oz_of_t(double t) {
 YK_HD double k0(double z) { return k0_of_t(0.25 * z * z); }
 YK_HD double k1(double z) { return z * k1oz_of_t(0.25 * z * z); }
 
+// ------------------------------------------------------- fast FP64 log ---
+// Natural logarithm for the near-field series (t > 0, finite).  With
+// t = m 2^e and m in [sqrt(1/2), sqrt(2)), ln t = e ln 2 + 2 atanh(s),
+// s = (m - 1)/(m + 1), |s| <= 0.1716, and 2 atanh(s) = 2 sum s^(2k+1)/(2k+1);
+// eleven terms leave a truncation below 1e-17 relative.  ln 2 is split in a
+// high part with trailing zero bits and a low part.  About 30 operations
+// instead of a double-double library logarithm.
+__device__ __forceinline__ double fast_rcp(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    r = fma(fma(-x, r, 1.0), r, r);
+    r = fma(fma(-x, r, 1.0), r, r);
+    return r;
+}
+
+__device__ __forceinline__ double fast_log(double t) {
+    int e = __builtin_amdgcn_frexp_exp(t);
+    double m = __builtin_amdgcn_frexp_mant(t);         // [0.5, 1)
+    if (m < 0.70710678118654752440) {
+        m += m;
+        e -= 1;
+    }
+    const double f = m - 1.0;                          // exact
+    const double s = f * fast_rcp(2.0 + f);
+    const double s2 = s * s;
+    double p = 2.0 / 21.0;
+    p = fma(p, s2, 2.0 / 19.0);
+    p = fma(p, s2, 2.0 / 17.0);
+    p = fma(p, s2, 2.0 / 15.0);
+    p = fma(p, s2, 2.0 / 13.0);
+    p = fma(p, s2, 2.0 / 11.0);
+    p = fma(p, s2, 2.0 / 9.0);
+    p = fma(p, s2, 2.0 / 7.0);
+    p = fma(p, s2, 2.0 / 5.0);
+    p = fma(p, s2, 2.0 / 3.0);
+    const double ln_m = fma(s * s2, p, 2.0 * s);
+    const double de = (double)e;
+    constexpr double ln2_hi = 6.93147180369123816490e-01;   // 0x3FE62E42FEE00000
+    constexpr double ln2_lo = 1.90821492927058770002e-10;
+    return fma(de, ln2_hi, fma(de, ln2_lo, ln_m));
+}
+
 // ---------------------------------------------------------------- FP32 ---
 YK_HD float k0_small_f(float t, float lnt) {
     return -0.5f * lnt * horner(yk_ser_A_f, t) + horner(yk_ser_B_f, t);

@@ -193,3 +193,22 @@ def test_mixed_precision_gmres_refines_to_fp64(yk, oracle_lib):
     print("  mixed", st.as_dict(), flush=True)
     assert st.res_final <= 1e-12 and st.outer_iters >= 1
     assert rel_l2(host(sig), ref) < 1e-10
+
+
+def test_fmm_near_field_accuracy_tight(yk, oracle_lib):
+    """Points packed so every near pair has t = r^2/(4 alpha^2) <= 1, and p = 31:
+    the near field (own logarithm and series) and the far field agree with the
+    direct sums to ~1e-13."""
+    import torch
+    rng = np.random.default_rng(21)
+    src = rng.random((6000, 2)) * 0.05
+    q = rng.standard_normal(6000)
+    ctx = _ctx(yk, leaf_size=16, p=31, debug_flags=1)
+    try:
+        out = torch.empty(6000, dtype=torch.float64, device="cuda")
+        yk.yk_volume_potential(ctx, dev(src), dev(q), None, 0.2, out)
+        torch.cuda.synchronize()
+    finally:
+        yk.yk_destroy(ctx)
+    ref = oracle_lib.volume_sum(src, q, 0.2)
+    assert rel_l2(host(out), ref) < 5e-13
