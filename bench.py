@@ -166,7 +166,7 @@ def heat_step_bench(args, yk, torch, W):
             B = torch.empty_like(u)
             un = torch.empty_like(u)
             sig = torch.zeros(b.n, dtype=torch.float64, device="cuda")
-            times, iters = [], []
+            times, iters, stage = [], [], []
             for step in range(args.heat_steps + 1):
                 yk.yk_rhs_backward_euler(ctx, u, None, region, cfg["consts"], cfg["dt"], B)
                 torch.cuda.synchronize()
@@ -177,10 +177,13 @@ def heat_step_bench(args, yk, torch, W):
                 if step > 0:             # the first step builds the trees
                     times.append(time.perf_counter() - t0)
                     iters.append(st.iters)
+                    stage.append(list(st.ms[:4]))
                 u, un = un, u
         finally:
             yk.yk_destroy(ctx)
-        out[name] = {"s_per_step": float(np.mean(times)), "gmres_iters": float(np.mean(iters))}
+        sm = np.mean(np.array(stage), axis=0)
+        out[name] = {"s_per_step": float(np.mean(times)), "gmres_iters": float(np.mean(iters)),
+                     "ms_tree_vol2nodes_solve_final": [round(float(v), 3) for v in sm]}
     out["workload"] = (f"{args.heat_m}x{args.heat_m} cell grid, outer circle + 10 ellipses x 2048 nodes, "
                        f"dt=1e-3, alpha=sqrt(dt), previous-step guess, tol 1e-10, "
                        f"{args.heat_steps} timed steps")

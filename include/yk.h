@@ -182,6 +182,55 @@ yk_status yk_fmm_potential(yk_ctx ctx, int64_t n_vol, const double *vol_xy, cons
                            double *out_vol, double *out_bnd);
 
 /*
+ * Learned warm start for the density solve (an addition to the method: it
+ * only seeds GMRES).  A per-node network (features: sigma^N,
+ * sigma^N - sigma^{N-1}, g^{N+1} - g^N, g^N - g^{N-1} and kappa at 13 offsets
+ * along the curve) predicts the correction of sigma^{N+1} to the linear
+ * extrapolation 2 sigma^N - sigma^{N-1}.  It is trained on the GPU, with the
+ * library's own FP32 matrix-core forward/backward kernels and Adam, on the
+ * densities the solver produced.  Attached to a context (yk_set_warm_start),
+ * yk_heat_step evaluates ||b - A sigma|| for the learned guess and for the
+ * previous-step density and starts GMRES from the smaller one (stats
+ * guess_used = 2 when the learned guess wins); every step still stops at the
+ * same tolerance.  Attached, yk_heat_step also records each solved step
+ * (yk_ws_observe).  All arrays are device FP64 of the boundary's N nodes.
+ */
+typedef struct yk_ws_s *yk_ws;
+typedef struct {
+    int hidden;            /* width of the two hidden layers */
+    int batch;             /* rows (nodes x steps) per Adam step */
+    int steps;             /* Adam steps per yk_ws_train call */
+    double lr;             /* Adam learning rate */
+    int max_obs;           /* observed steps kept (training triples = max_obs - 2) */
+    uint64_t seed;         /* weight initialisation and shuffling */
+} yk_ws_options;
+
+/* Defaults: hidden 256, batch 32768, steps 600, lr 1e-3, max_obs 64, seed 1. */
+void yk_ws_default_options(yk_ws_options *opt);
+/* The boundary must stay the same (same arrays) for the life of the network. */
+yk_status yk_ws_create(yk_ctx ctx, const yk_boundary *bnd, const yk_ws_options *opt, yk_ws *out);
+yk_status yk_ws_destroy(yk_ws ws);
+/* Records one solved step: g [N] = f^{N+1} - U^p on the nodes, sigma [N] = sigma^{N+1}. */
+yk_status yk_ws_observe(yk_ws ws, const double *g, const double *sigma);
+/* Trains on every (N-1, N, N+1) triple recorded; *loss = last mini-batch MSE
+ * in units of the target's RMS (may be NULL). */
+yk_status yk_ws_train(yk_ws ws, double *loss);
+/* sigma_out [N] = the network's prediction of sigma^{N+1} from the last two
+ * recorded steps and g_next [N]. */
+yk_status yk_ws_predict(yk_ws ws, const double *g_next, double *sigma_out);
+/* Attaches (ws != NULL) or detaches the warm start used by yk_heat_step. */
+yk_status yk_set_warm_start(yk_ctx ctx, yk_ws ws);
+/* Parameter access and one loss/gradient evaluation, for checking the
+ * training kernels: params/grad are DEVICE FP32 arrays of yk_ws_num_params
+ * entries (W1 [H][Fp], b1 [H], W2 [H][H], b2 [H], w3 [H], b3), X [rows][Fp]
+ * device FP32 features, t [rows] device FP32 targets. */
+int64_t yk_ws_num_params(yk_ws ws, int *hidden, int *fp);
+yk_status yk_ws_get_params(yk_ws ws, float *params);
+yk_status yk_ws_set_params(yk_ws ws, const float *params);
+yk_status yk_ws_loss_grad(yk_ws ws, int64_t rows, const float *X, const float *t, float *grad,
+                          double *loss);
+
+/*
  * Introspection for measurement (not part of the method).
  * yk_plan_info: shape of the tree cached in `slot` (0 = volume points and
  * nodes, as used by the heat step and yk_fmm_potential; 1 = nodes only, as

@@ -5,6 +5,7 @@
 #include <new>
 
 #include "fmm.h"
+#include "mlp.h"
 #include "sums.h"
 #include "yk_internal.h"
 
@@ -426,11 +427,40 @@ yk_status yk_heat_step(yk_ctx ctx, const yk_boundary *bnd, int64_t n_vol, const 
             stats->ms[0] = fmm_last_build_ms(c);
             stats->ms[1] = ms_since(t0);
         }
+        // g = f - U^p on the nodes (recorded for the learned warm start)
+        double *gN = c.ws_g.ensure(nb);
+        launch_axpby(c, nb, 1.0, f_next, -1.0 / a2, vb, gN);
+        // initial guess: the caller's (previous-step) density, or the learned
+        // prediction when its residual is smaller
+        int guess = (flags & 2) ? 0 : 1;
+        if (c.warm && c.warm->trained && c.warm->obs.size() >= 2 && guess == 1) {
+            auto tg = std::chrono::steady_clock::now();
+            double *sml = c.ws_ml.ensure(nb), *tmp = c.ws_t.ensure(nb);
+            c.warm->predict(gN, sml);
+            BieOperator A64{c, bd, alpha, SUM_FP64};
+            auto resid = [&](const double *x) {
+                A64(x, tmp);
+                launch_axpby(c, nb, 1.0, b, -1.0, tmp, tmp);
+                double *ds = c.scal.ensure(512) + 450;
+                launch_multi_dot(c, nb, 1, tmp, nb, tmp, ds);
+                double h = 0;
+                YK_HIP(hipMemcpyAsync(&h, ds, sizeof(double), hipMemcpyDeviceToHost, c.stream));
+                YK_HIP(hipStreamSynchronize(c.stream));
+                return h;
+            };
+            const double r_ml = resid(sml), r_prev = resid(sigma_io);
+            if (std::isfinite(r_ml) && r_ml < r_prev) {
+                YK_HIP(hipMemcpyAsync(sigma_io, sml, nb * sizeof(double), hipMemcpyDeviceToDevice, c.stream));
+                guess = 2;
+            }
+            if (stats) stats->ms[4] = ms_since(tg);
+        }
         // sigma
         auto t1 = std::chrono::steady_clock::now();
         // the solver's operators use ws_a..ws_d, so q is formed again afterwards
         int outer = 0;
-        GmresResult r = solve_density(c, bd, alpha, b, sigma_io, (flags & 2) != 0, tol, 1000, &outer);
+        GmresResult r = solve_density(c, bd, alpha, b, sigma_io, guess == 0, tol, 1000, &outer);
+        if (c.warm) c.warm->observe(gN, sigma_io);
         if (stats) stats->ms[2] = ms_since(t1);
         // u = (V[q] + DL[w sigma] + B C_self) / alpha^2 at the volume points
         auto t2 = std::chrono::steady_clock::now();
@@ -445,7 +475,7 @@ yk_status yk_heat_step(yk_ctx ctx, const yk_boundary *bnd, int64_t n_vol, const 
         launch_axpby(c, n_vol, 1.0 / a2, u_next, 0.0, nullptr, u_next);
         YK_HIP(hipStreamSynchronize(c.stream));
         if (stats) stats->ms[3] = ms_since(t2);
-        fill_stats(stats, r, outer, (flags & 2) ? 0 : 1);
+        fill_stats(stats, r, outer, guess);
         if (!r.converged) {
             c.last_error = "GMRES did not reach the tolerance";
             return YK_ERR_NOCONV;
@@ -489,6 +519,119 @@ yk_status yk_fmm_potential(yk_ctx ctx, int64_t n_vol, const double *vol_xy, cons
         double *outs[3] = {out_vol, out_bnd, nullptr};
         evaluate_sums(c, SLOT_VOL, pb, q, dn, outs,
                       c.opt.precision == YK_PREC_FP32 ? SUM_FP32 : SUM_FP64);
+        return YK_OK;
+    });
+}
+
+void yk_ws_default_options(yk_ws_options *o) {
+    if (!o) return;
+    o->hidden = 256;
+    o->batch = 32768;
+    o->steps = 600;
+    o->lr = 1e-3;
+    o->max_obs = 64;
+    o->seed = 1;
+}
+
+yk_status yk_ws_create(yk_ctx ctx, const yk_boundary *bnd, const yk_ws_options *opt, yk_ws *out) {
+    return guarded(ctx, [&](Context &c) {
+        YK_REQUIRE(out != nullptr, "out is NULL");
+        *out = nullptr;
+        yk_ws_options o;
+        yk_ws_default_options(&o);
+        if (opt) o = *opt;
+        YK_REQUIRE(o.hidden >= 16 && o.hidden <= 1024 && o.hidden % 16 == 0, "hidden must be a multiple of 16 in [16, 1024]");
+        YK_REQUIRE(o.batch >= 64 && o.steps >= 0 && o.lr > 0 && o.max_obs >= 3, "invalid warm-start options");
+        BoundaryData &bd = prepare_boundary(c, bnd);
+        auto w = std::make_unique<WarmStart>(c, bd, o);
+        yk_ws h = new yk_ws_s{ctx, std::move(w)};
+        *out = h;
+        return YK_OK;
+    });
+}
+
+yk_status yk_ws_destroy(yk_ws ws) {
+    if (!ws) return YK_ERR_ARG;
+    if (ws->owner) {
+        (void)hipStreamSynchronize(ws->owner->c.stream);
+        if (ws->owner->c.warm == ws->w.get()) ws->owner->c.warm = nullptr;
+    }
+    delete ws;
+    return YK_OK;
+}
+
+yk_status yk_ws_observe(yk_ws ws, const double *g, const double *sigma) {
+    if (!ws) return YK_ERR_ARG;
+    return guarded(ws->owner, [&](Context &) {
+        YK_REQUIRE(g && sigma, "g/sigma are NULL");
+        ws->w->observe(g, sigma);
+        return YK_OK;
+    });
+}
+
+yk_status yk_ws_train(yk_ws ws, double *loss) {
+    if (!ws) return YK_ERR_ARG;
+    return guarded(ws->owner, [&](Context &c) {
+        const double l = ws->w->train();
+        YK_HIP(hipStreamSynchronize(c.stream));
+        if (loss) *loss = l;
+        return YK_OK;
+    });
+}
+
+yk_status yk_ws_predict(yk_ws ws, const double *g_next, double *sigma_out) {
+    if (!ws) return YK_ERR_ARG;
+    return guarded(ws->owner, [&](Context &) {
+        YK_REQUIRE(g_next && sigma_out, "g_next/sigma_out are NULL");
+        ws->w->predict(g_next, sigma_out);
+        return YK_OK;
+    });
+}
+
+yk_status yk_set_warm_start(yk_ctx ctx, yk_ws ws) {
+    return guarded(ctx, [&](Context &c) {
+        YK_REQUIRE(!ws || ws->owner == ctx, "the warm start belongs to another context");
+        c.warm = ws ? ws->w.get() : nullptr;
+        return YK_OK;
+    });
+}
+
+int64_t yk_ws_num_params(yk_ws ws, int *hidden, int *fp) {
+    if (!ws) return -1;
+    if (hidden) *hidden = ws->w->H;
+    if (fp) *fp = ws->w->Fp;
+    return ws->w->n_params;
+}
+
+yk_status yk_ws_get_params(yk_ws ws, float *params) {
+    if (!ws) return YK_ERR_ARG;
+    return guarded(ws->owner, [&](Context &c) {
+        YK_REQUIRE(params != nullptr, "params is NULL");
+        YK_HIP(hipMemcpyAsync(params, ws->w->params.p, ws->w->n_params * sizeof(float), hipMemcpyDeviceToDevice,
+                              c.stream));
+        YK_HIP(hipStreamSynchronize(c.stream));
+        return YK_OK;
+    });
+}
+
+yk_status yk_ws_set_params(yk_ws ws, const float *params) {
+    if (!ws) return YK_ERR_ARG;
+    return guarded(ws->owner, [&](Context &c) {
+        YK_REQUIRE(params != nullptr, "params is NULL");
+        YK_HIP(hipMemcpyAsync(ws->w->params.p, params, ws->w->n_params * sizeof(float), hipMemcpyDeviceToDevice,
+                              c.stream));
+        YK_HIP(hipStreamSynchronize(c.stream));
+        return YK_OK;
+    });
+}
+
+yk_status yk_ws_loss_grad(yk_ws ws, int64_t rows, const float *X, const float *t, float *grad, double *loss) {
+    if (!ws) return YK_ERR_ARG;
+    return guarded(ws->owner, [&](Context &c) {
+        YK_REQUIRE(rows > 0 && rows < ((int64_t)1 << 31) && X && t && grad, "invalid arguments");
+        const double l = ws->w->loss_grad(rows, X, t, grad);
+        YK_HIP(hipStreamSynchronize(c.stream));
+        if (loss) *loss = l;
         return YK_OK;
     });
 }

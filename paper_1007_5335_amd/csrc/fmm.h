@@ -46,6 +46,8 @@ struct ActiveSet {
     std::vector<int> tile_begin, tile_count;     // per level: slice of m2l_tiles
     DevBuf<int32_t> leaves;            // active leaves (leaf-local indices)
     int64_t n_leaves = 0;
+    DevBuf<int2> leaf_items;           // {leaf, first target} work items of <= 64 targets
+    int64_t n_items = 0;
     int64_t n_m2l_boxes = 0;
     // work counts (for measurement)
     int64_t pairs_q = 0, pairs_d = 0, m2l_trans = 0, l2p_points = 0;

@@ -487,7 +487,7 @@ constexpr int kLeafStage = 512;
 
 template <int NT, bool kSmallOnly, bool kF32 = false>
 __global__ __launch_bounds__(64) void k_leaf(
-    const int32_t *__restrict__ leaves, int64_t leaf_base, const int32_t *__restrict__ lrange,
+    const int2 *__restrict__ items, int64_t leaf_base, const int32_t *__restrict__ lrange,
     const int32_t *__restrict__ uoff, const int32_t *__restrict__ ulist,
     const double *__restrict__ bcx, const double *__restrict__ bcy, const double *__restrict__ px,
     const double *__restrict__ py, const double *__restrict__ qs, const double *__restrict__ dns,
@@ -496,7 +496,8 @@ __global__ __launch_bounds__(64) void k_leaf(
     const double *__restrict__ cnn, const double *__restrict__ sc, int nser, int p, int Pp,
     double inv4a2, double inva2, double *__restrict__ outs) {
     __shared__ double s_x[kLeafStage], s_y[kLeafStage], s_a[kLeafStage], s_b[kLeafStage];
-    const int li = leaves[blockIdx.x];
+    const int2 item = items[blockIdx.x];
+    const int li = item.x;
     const int64_t b = leaf_base + li;
     const int lane = threadIdx.x;
     const double cx = bcx[b], cy = bcy[b];
@@ -522,7 +523,8 @@ __global__ __launch_bounds__(64) void k_leaf(
         }
     }
     const double *Lb = Lc + b * Pp;
-    for (int tb = 0; tb < ntot; tb += 64) {
+    {
+        const int tb = item.y;
         const int c = min(64, ntot - tb);
         int np2 = 1;
         while (np2 < c) np2 <<= 1;
@@ -604,7 +606,7 @@ __global__ __launch_bounds__(64) void k_leaf(
     }
 }
 
-using LeafKernel = void (*)(const int32_t *, int64_t, const int32_t *, const int32_t *,
+using LeafKernel = void (*)(const int2 *, int64_t, const int32_t *, const int32_t *,
                             const int32_t *, const double *, const double *, const double *,
                             const double *, const double *, const double *, int64_t, int, int, int,
                             int, const double *, double, double, const double *, const double *,
@@ -746,7 +748,7 @@ void fmm_run(Context &ctx, FmmPlan &pl, const double *q, const double *dn, doubl
         const double tmax = 2.0 * pl.lev[L].side * pl.lev[L].side * inv4a2 * 4.0;
         LeafKernel kern = pick_leaf_kernel(pl.near_terms, tmax <= 1.0, prec == SUM_FP32);
         StageTimer tl(ctx, YK_STAGE_LEAF);
-        hipLaunchKernelGGL(kern, dim3(as.n_leaves), dim3(64), 0, ctx.stream, as.leaves.p,
+        hipLaunchKernelGGL(kern, dim3(as.n_items), dim3(64), 0, ctx.stream, as.leaf_items.p,
                            leaf_base, pl.lrange.p, pl.ulist_off.p, pl.ulist.p, pl.bcx.p, pl.bcy.p,
                            pl.px.p, pl.py.p, qs, dns, pl.toff[1], has_q, has_d, mask, far ? 1 : 0,
                            pl.Lc.p, inv_alpha, 1.0 / pl.lev[L].R, pl.invFY.p + L * lvl, pl.cnn.p,

@@ -137,24 +137,48 @@ void build_lists_and_tables(Context &ctx, FmmPlan &pl, const std::vector<uint32_
             std::merge(a.begin(), a.end(), b.begin(), b.end(), merged.begin());
         }
     }
-    // ---- leaf level: smallest level whose mean occupancy is <= leaf_size ----
+    // ---- leaf level: smallest level whose point-weighted occupancy
+    //      sum_i n_i^2 / N (the leaf size seen by an average point, which sets
+    //      the near-field work per target) is <= leaf_size ----
     std::vector<uint32_t> uniq15;
+    std::vector<int64_t> cnt15;
     uniq15.reserve(N);
-    for (int64_t k = 0; k < N; ++k)
-        if (k == 0 || merged[k] != merged[k - 1]) uniq15.push_back(merged[k]);
+    cnt15.reserve(N);
+    for (int64_t k = 0; k < N; ++k) {
+        if (k == 0 || merged[k] != merged[k - 1]) {
+            uniq15.push_back(merged[k]);
+            cnt15.push_back(0);
+        }
+        cnt15.back()++;
+    }
     std::vector<std::vector<uint32_t>> codes(kMaxLevel + 1);
-    codes[kMaxLevel] = uniq15;
-    for (int l = kMaxLevel - 1; l >= 0; --l) {
-        const auto &f = codes[l + 1];
-        auto &c = codes[l];
-        for (size_t k = 0; k < f.size(); ++k) {
-            const uint32_t v = f[k] >> 2;
-            if (c.empty() || c.back() != v) c.push_back(v);
+    std::vector<double> occ(kMaxLevel + 1, 0.0);
+    {
+        std::vector<uint32_t> c = uniq15;
+        std::vector<int64_t> n = cnt15;
+        for (int l = kMaxLevel; l >= 0; --l) {
+            double s2 = 0;
+            for (int64_t v : n) s2 += (double)v * (double)v;
+            occ[l] = s2 / (double)N;
+            codes[l] = c;
+            if (l == 0) break;
+            std::vector<uint32_t> c2;
+            std::vector<int64_t> n2;
+            for (size_t k = 0; k < c.size(); ++k) {
+                const uint32_t v = c[k] >> 2;
+                if (c2.empty() || c2.back() != v) {
+                    c2.push_back(v);
+                    n2.push_back(0);
+                }
+                n2.back() += n[k];
+            }
+            c.swap(c2);
+            n.swap(n2);
         }
     }
     int L = kMaxLevel;
     for (int l = 0; l <= kMaxLevel; ++l) {
-        if ((double)N / (double)codes[l].size() <= (double)pl.opt_leaf) {
+        if (occ[l] <= (double)pl.opt_leaf) {
             L = l;
             break;
         }
@@ -475,8 +499,12 @@ ActiveSet &get_active(Context &ctx, FmmPlan &pl, int mask) {
     for (int64_t b = pl.nbox - 1; b >= 0; --b)
         if (pl.hparent[b] >= 0) cnt[pl.hparent[b]] += cnt[b];
     std::vector<int32_t> leaves;
-    for (int64_t li = 0; li < pl.nleaf; ++li)
-        if (cnt[pl.lev[L].begin + li] > 0) leaves.push_back((int32_t)li);
+    std::vector<int2> items;
+    for (int64_t li = 0; li < pl.nleaf; ++li) {
+        const int64_t c = cnt[pl.lev[L].begin + li];
+        if (c > 0) leaves.push_back((int32_t)li);
+        for (int64_t tb = 0; tb < c; tb += 64) items.push_back(make_int2((int)li, (int)tb));
+    }
     // near-field pair counts over the U-lists of the active leaves
     {
         std::vector<int32_t> uoff(pl.nleaf + 1), ul;
@@ -553,6 +581,8 @@ ActiveSet &get_active(Context &ctx, FmmPlan &pl, int mask) {
     up(as->m2l_tiles, tiles);
     up(as->l2l_boxes, l2lb);
     up(as->leaves, leaves);
+    up(as->leaf_items, items);
+    as->n_items = (int64_t)items.size();
     as->n_tiles = (int)tiles.size();
     as->n_leaves = (int64_t)leaves.size();
     as->n_m2l_boxes = (int64_t)mb.size();

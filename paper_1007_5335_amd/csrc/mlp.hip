@@ -1,0 +1,479 @@
+// mlp.hip -- learned warm start for the density solve.
+//
+// A small per-node network predicts the next step's double-layer density from
+// the last two densities and the boundary data; it only seeds GMRES.  The
+// previous-step density is the fallback, and the residual of the second-kind
+// system decides which of the two seeds is used, so every step still reaches
+// the same tolerance.
+//
+// Network: x (F features, zero-padded to Fp) -> tanh(W1 x + b1) (H) ->
+// tanh(W2 h + b2) (H) -> w3 . h + b3, FP32, trained with Adam on the mean
+// squared error.  Features of node j on curve k, at curve offsets
+// o in {0, +-1, +-2, +-4, +-8, +-16, +-32} (periodic within the curve):
+//   sigma^N, sigma^N - sigma^{N-1}, g^{N+1} - g^N, g^N - g^{N-1}, kappa,
+// each divided by its RMS over the training set.  Target: the correction to
+// linear extrapolation, sigma^{N+1} - (2 sigma^N - sigma^{N-1}).
+// Scaling is per step, so that one network serves early transients and later
+// slow decay alike: sigma^N over its RMS, the density difference over its RMS
+// r_s, both boundary-data differences over the RMS r_g of g^{N+1} - g^N (their
+// ratio is kept), kappa over its RMS; the target is in units of r_s.  Two
+// more features carry the step's scales: r_g / r_s and
+// rms(g^N - g^{N-1}) / r_g.
+#include <cmath>
+#include <random>
+
+#include "mlp.h"
+
+namespace yk {
+
+namespace {
+
+constexpr int kOffsets[13] = {0, 1, -1, 2, -2, 4, -4, 8, -8, 16, -16, 32, -32};
+constexpr int kChannels = 5;
+constexpr int kFeat = kChannels * 13 + 2;
+
+inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+
+typedef float f4v __attribute__((ext_vector_type(4)));
+
+// ------------------------------------------------------------------ GEMM ---
+// C[z][m][n] = sum_{k in chunk z} A(m,k) B(k,n), A(m,k) = A[m*sam + k*sak],
+// B(k,n) = B[k*sbk + n*sbn].  64 x 64 tiles, 4 wavefronts each owning a
+// 32 x 32 quarter (2 x 2 tiles of v_mfma_f32_16x16x4f32), K staged in LDS in
+// steps of 16.  gridDim.z > 1 splits K; the partial sums are added afterwards
+// in a fixed order.
+constexpr int kLdsPad = 80;   // row stride of the LDS tiles (keeps the four lane groups on distinct banks)
+
+__global__ __launch_bounds__(256) void k_sgemm(int M, int N, int K, const float *__restrict__ A,
+                                               int64_t sam, int64_t sak, const float *__restrict__ B,
+                                               int64_t sbk, int64_t sbn, float *__restrict__ C,
+                                               int64_t ldc, int64_t ldz, int kchunk) {
+    __shared__ float As[16][kLdsPad];
+    __shared__ float Bs[16][kLdsPad];
+    const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+    const int m0 = blockIdx.y * 64, n0 = blockIdx.x * 64;
+    const int kbeg = blockIdx.z * kchunk, kend = min(K, kbeg + kchunk);
+    const int wm = (w >> 1) * 32, wn = (w & 1) * 32;
+    f4v acc[2][2];
+    for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j) acc[i][j] = f4v{0.f, 0.f, 0.f, 0.f};
+    const bool a_kfast = sak == 1, b_nfast = sbn == 1;
+    for (int k0 = kbeg; k0 < kend; k0 += 16) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int idx = tid + 256 * e;
+            int mm, kk;
+            if (a_kfast) { mm = idx >> 4; kk = idx & 15; } else { kk = idx >> 6; mm = idx & 63; }
+            const int gm = m0 + mm, gk = k0 + kk;
+            As[kk][mm] = (gm < M && gk < kend) ? A[(int64_t)gm * sam + (int64_t)gk * sak] : 0.f;
+            int nn, kb;
+            if (b_nfast) { kb = idx >> 6; nn = idx & 63; } else { nn = idx >> 4; kb = idx & 15; }
+            const int gn = n0 + nn, gkb = k0 + kb;
+            Bs[kb][nn] = (gn < N && gkb < kend) ? B[(int64_t)gkb * sbk + (int64_t)gn * sbn] : 0.f;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kq = 0; kq < 4; ++kq) {
+            const int kk = 4 * kq + (lane >> 4);
+            const float a0 = As[kk][wm + (lane & 15)], a1 = As[kk][wm + 16 + (lane & 15)];
+            const float b0 = Bs[kk][wn + (lane & 15)], b1 = Bs[kk][wn + 16 + (lane & 15)];
+            acc[0][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b0, acc[0][0], 0, 0, 0);
+            acc[0][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b1, acc[0][1], 0, 0, 0);
+            acc[1][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b0, acc[1][0], 0, 0, 0);
+            acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b1, acc[1][1], 0, 0, 0);
+        }
+        __syncthreads();
+    }
+    float *Cz = C + (int64_t)blockIdx.z * ldz;
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int gm = m0 + wm + 16 * i + 4 * (lane >> 4) + r;
+                const int gn = n0 + wn + 16 * j + (lane & 15);
+                if (gm < M && gn < N) Cz[(int64_t)gm * ldc + gn] = acc[i][j][r];
+            }
+}
+
+__global__ void k_sum_partials(int64_t n, int nz, const float *__restrict__ part, int64_t ldz,
+                               float *__restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    float s = 0.f;
+    for (int z = 0; z < nz; ++z) s += part[z * ldz + i];
+    out[i] = s;
+}
+
+// H = tanh(Z + b[col]) in place
+__global__ void k_bias_tanh(int64_t rows, int cols, float *__restrict__ Z, const float *__restrict__ b) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= rows * cols) return;
+    Z[i] = tanhf(Z[i] + b[i % cols]);
+}
+
+// y[r] = sum_c H[r][c] w[c] + b0   (one wavefront per row)
+__global__ void k_rowdot(int64_t rows, int cols, const float *__restrict__ H, const float *__restrict__ w,
+                         const float *__restrict__ b0, float *__restrict__ y) {
+    const int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (r >= rows) return;
+    float s = 0.f;
+    for (int c = lane; c < cols; c += 64) s += H[r * cols + c] * w[c];
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+    if (lane == 0) y[r] = s + b0[0];
+}
+
+// dy = 2 (y - t) / n ; partial loss sums per block (fixed-order reduction later)
+__global__ __launch_bounds__(256) void k_mse(int64_t n, const float *__restrict__ y, const float *__restrict__ t,
+                                             float *__restrict__ dy, float *__restrict__ part) {
+    __shared__ float sh[256];
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    float e = 0.f;
+    if (i < n) {
+        const float d = y[i] - t[i];
+        dy[i] = 2.f * d / (float)n;
+        e = d * d;
+    }
+    sh[threadIdx.x] = e;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if (threadIdx.x < off) sh[threadIdx.x] += sh[threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
+// D[r][c] = dy[r] * w[c] * (1 - H[r][c]^2)
+__global__ void k_back_out(int64_t rows, int cols, const float *__restrict__ dy, const float *__restrict__ w,
+                           const float *__restrict__ H, float *__restrict__ D) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= rows * cols) return;
+    const float h = H[i];
+    D[i] = dy[i / cols] * w[i % cols] * (1.f - h * h);
+}
+
+// D *= (1 - H^2)
+__global__ void k_back_tanh(int64_t n, const float *__restrict__ H, float *__restrict__ D) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float h = H[i];
+    D[i] *= 1.f - h * h;
+}
+
+// column sums over row blocks: part[blk][c]
+__global__ void k_colsum_part(int64_t rows, int cols, const float *__restrict__ D, int rows_per_blk,
+                              float *__restrict__ part) {
+    const int c = threadIdx.x + blockIdx.y * blockDim.x;
+    if (c >= cols) return;
+    const int64_t r0 = (int64_t)blockIdx.x * rows_per_blk;
+    const int64_t r1 = min<int64_t>(rows, r0 + rows_per_blk);
+    float s = 0.f;
+    for (int64_t r = r0; r < r1; ++r) s += D[r * cols + c];
+    part[(int64_t)blockIdx.x * cols + c] = s;
+}
+
+__global__ void k_adam(int64_t n, float *__restrict__ p, const float *__restrict__ g, float *__restrict__ m,
+                       float *__restrict__ v, float lr, float b1, float b2, float eps, float c1, float c2) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.f - b1) * gi;
+    const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    p[i] -= lr * (mi * c1) / (sqrtf(vi * c2) + eps);
+}
+
+// Features of every node for one (N-1, N, N+1) triple; scale[0..4] are the
+// per-channel factors, extra0/extra1 the two per-step scalar features.
+__global__ void k_features(int64_t n, const double *__restrict__ sm1, const double *__restrict__ s0,
+                           const double *__restrict__ gm1, const double *__restrict__ g0,
+                           const double *__restrict__ gp1, const double *__restrict__ kappa,
+                           const int32_t *__restrict__ curve, const int32_t *__restrict__ idx,
+                           const int64_t *__restrict__ off, float sc0, float sc1, float sc2, float sc4,
+                           float extra0, float extra1, int Fp, float *__restrict__ X) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    const int k = curve[j];
+    const int64_t base = off[k], nk = off[k + 1] - off[k];
+    const int64_t jl = idx[j];
+    float *row = X + j * Fp;
+    for (int o = 0; o < 13; ++o) {
+        int64_t q = (jl + kOffsets[o]) % nk;
+        if (q < 0) q += nk;
+        const int64_t jj = base + q;
+        row[0 * 13 + o] = (float)(s0[jj] * sc0);
+        row[1 * 13 + o] = (float)((s0[jj] - sm1[jj]) * sc1);
+        row[2 * 13 + o] = (float)((gp1[jj] - g0[jj]) * sc2);
+        row[3 * 13 + o] = (float)((g0[jj] - gm1[jj]) * sc2);
+        row[4 * 13 + o] = (float)(kappa[jj] * sc4);
+    }
+    row[65] = extra0;
+    row[66] = extra1;
+    for (int f = kFeat; f < Fp; ++f) row[f] = 0.f;
+}
+
+// target (sigma^{N+1} - 2 sigma^N + sigma^{N-1}) * inv_sy, inv_sy = 1 / r_s
+__global__ void k_target(int64_t n, const double *__restrict__ sm1, const double *__restrict__ s0,
+                         const double *__restrict__ sp1, float inv_sy, float *__restrict__ t) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    t[j] = (float)((sp1[j] - 2.0 * s0[j] + sm1[j]) * inv_sy);
+}
+
+// sigma = 2 sigma^N - sigma^{N-1} + sy * y
+__global__ void k_apply_pred(int64_t n, const double *__restrict__ sm1, const double *__restrict__ s0,
+                             const float *__restrict__ y, double sy, double *__restrict__ out) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    out[j] = 2.0 * s0[j] - sm1[j] + sy * (double)y[j];
+}
+
+// sum of squares partials (double)
+__global__ __launch_bounds__(256) void k_sumsq(int64_t n, const double *__restrict__ a,
+                                               const double *__restrict__ b, double *__restrict__ part) {
+    __shared__ double sh[256];
+    double s = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+        const double v = b ? a[i] - b[i] : a[i];
+        s += v * v;
+    }
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if (threadIdx.x < off) sh[threadIdx.x] += sh[threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
+__global__ void k_gather_rows(int64_t nb, int Fp, const int32_t *__restrict__ rows,
+                              const float *__restrict__ X, const float *__restrict__ T,
+                              float *__restrict__ Xb, float *__restrict__ Tb) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nb * Fp) return;
+    const int64_t r = i / Fp, f = i - r * Fp;
+    const int64_t src = rows[r];
+    Xb[i] = X[src * Fp + f];
+    if (f == 0) Tb[r] = T[src];
+}
+
+}  // namespace
+
+// --------------------------------------------------------------- host side --
+void sgemm(Context &ctx, int M, int N, int K, const float *A, int64_t sam, int64_t sak, const float *B,
+           int64_t sbk, int64_t sbn, float *C, int64_t ldc, DevBuf<float> &part) {
+    if (M <= 0 || N <= 0) return;
+    const int gm = (M + 63) / 64, gn = (N + 63) / 64;
+    // split K when the output has few tiles and K is long
+    int nz = 1;
+    if ((int64_t)gm * gn < 256 && K > 1024) nz = (int)std::min<int64_t>(64, std::max<int64_t>(1, 512 / ((int64_t)gm * gn)));
+    int kchunk = (K + nz - 1) / nz;
+    kchunk = (kchunk + 15) / 16 * 16;
+    nz = (K + kchunk - 1) / kchunk;
+    if (nz <= 1) {
+        hipLaunchKernelGGL(k_sgemm, dim3(gn, gm, 1), dim3(256), 0, ctx.stream, M, N, K, A, sam, sak, B, sbk, sbn,
+                           C, ldc, (int64_t)0, K);
+        check_launch(ctx, "k_sgemm");
+        return;
+    }
+    const int64_t ldz = (int64_t)M * ldc;
+    float *p = part.ensure((size_t)nz * ldz);
+    hipLaunchKernelGGL(k_sgemm, dim3(gn, gm, nz), dim3(256), 0, ctx.stream, M, N, K, A, sam, sak, B, sbk, sbn,
+                       p, ldc, ldz, kchunk);
+    check_launch(ctx, "k_sgemm");
+    hipLaunchKernelGGL(k_sum_partials, dim3(nblk(ldz, 256)), dim3(256), 0, ctx.stream, ldz, nz, p, ldz, C);
+    check_launch(ctx, "k_sum_partials");
+}
+
+WarmStart::WarmStart(Context &c, BoundaryData &b, const yk_ws_options &o) : ctx(c), opt(o) {
+    n = b.n;
+    H = o.hidden;
+    Fp = (kFeat + 15) / 16 * 16;
+    offsets = b.offset;
+    int64_t *d = off.ensure(offsets.size());
+    YK_HIP(hipMemcpyAsync(d, offsets.data(), offsets.size() * sizeof(int64_t), hipMemcpyHostToDevice, ctx.stream));
+    curve = curve_buf.ensure(n);
+    idx = idx_buf.ensure(n);
+    YK_HIP(hipMemcpyAsync(curve_buf.p, b.curve.p, n * sizeof(int32_t), hipMemcpyDeviceToDevice, ctx.stream));
+    YK_HIP(hipMemcpyAsync(idx_buf.p, b.idx.p, n * sizeof(int32_t), hipMemcpyDeviceToDevice, ctx.stream));
+    kappa = b.curvature;
+    // parameters: W1 [H x Fp], b1 [H], W2 [H x H], b2 [H], w3 [H], b3 [1]
+    o_W1 = 0;
+    o_b1 = o_W1 + (int64_t)H * Fp;
+    o_W2 = o_b1 + H;
+    o_b2 = o_W2 + (int64_t)H * H;
+    o_w3 = o_b2 + H;
+    o_b3 = o_w3 + H;
+    n_params = o_b3 + 1;
+    std::vector<float> p(n_params, 0.f);
+    std::mt19937_64 rng(o.seed);
+    auto fill = [&](int64_t o0, int64_t cnt, int fan_in, int fan_out, float gain) {
+        const float a = gain * std::sqrt(6.f / (float)(fan_in + fan_out));
+        std::uniform_real_distribution<float> u(-a, a);
+        for (int64_t i = 0; i < cnt; ++i) p[o0 + i] = u(rng);
+    };
+    fill(o_W1, (int64_t)H * Fp, kFeat, H, 1.f);
+    for (int r = 0; r < H; ++r)
+        for (int f = kFeat; f < Fp; ++f) p[o_W1 + (int64_t)r * Fp + f] = 0.f;
+    fill(o_W2, (int64_t)H * H, H, H, 1.f);
+    fill(o_w3, H, H, 1, 0.1f);
+    float *dp = params.ensure(n_params);
+    YK_HIP(hipMemcpyAsync(dp, p.data(), n_params * sizeof(float), hipMemcpyHostToDevice, ctx.stream));
+    YK_HIP(hipMemsetAsync(adam_m.ensure(n_params), 0, n_params * sizeof(float), ctx.stream));
+    YK_HIP(hipMemsetAsync(adam_v.ensure(n_params), 0, n_params * sizeof(float), ctx.stream));
+    YK_HIP(hipStreamSynchronize(ctx.stream));
+}
+
+void WarmStart::observe(const double *g, const double *sigma) {
+    auto slot = std::make_unique<Obs>();
+    YK_HIP(hipMemcpyAsync(slot->g.ensure(n), g, n * sizeof(double), hipMemcpyDeviceToDevice, ctx.stream));
+    YK_HIP(hipMemcpyAsync(slot->s.ensure(n), sigma, n * sizeof(double), hipMemcpyDeviceToDevice, ctx.stream));
+    obs.push_back(std::move(slot));
+    // bounded history: the oldest observation is dropped beyond max_obs
+    if ((int)obs.size() > opt.max_obs) obs.erase(obs.begin());
+}
+
+double WarmStart::rms_dev(const double *a, const double *b, int64_t cnt) {
+    double *part = scal.ensure(256);
+    hipLaunchKernelGGL(k_sumsq, dim3(256), dim3(256), 0, ctx.stream, cnt, a, b, part);
+    check_launch(ctx, "k_sumsq");
+    std::vector<double> h(256);
+    YK_HIP(hipMemcpyAsync(h.data(), part, 256 * sizeof(double), hipMemcpyDeviceToHost, ctx.stream));
+    YK_HIP(hipStreamSynchronize(ctx.stream));
+    double s = 0;
+    for (double v : h) s += v;
+    return std::sqrt(s / (double)std::max<int64_t>(1, cnt));
+}
+
+double WarmStart::features(const double *sm1, const double *s0, const double *gm1, const double *g0,
+                           const double *gp1, float *X) {
+    const double tiny = 1e-300;
+    const double r0 = std::max(tiny, rms_dev(s0, nullptr, n));
+    const double rs = std::max(tiny, rms_dev(s0, sm1, n));
+    const double rg = std::max(tiny, rms_dev(gp1, g0, n));
+    const double rg0 = rms_dev(g0, gm1, n);
+    if (kappa_rms <= 0) kappa_rms = std::max(tiny, rms_dev(kappa, nullptr, n));
+    hipLaunchKernelGGL(k_features, dim3(nblk(n, 256)), dim3(256), 0, ctx.stream, n, sm1, s0, gm1, g0, gp1,
+                       kappa, curve, idx, off.p, (float)(1.0 / r0), (float)(1.0 / rs), (float)(1.0 / rg),
+                       (float)(1.0 / kappa_rms), (float)std::log(rg / rs), (float)(rg0 / rg), Fp, X);
+    check_launch(ctx, "k_features");
+    return rs;
+}
+
+void WarmStart::forward(int64_t rows, const float *X, float *y) {
+    float *P = params.p;
+    float *H1 = h1.ensure((size_t)rows * H), *H2 = h2.ensure((size_t)rows * H);
+    sgemm(ctx, (int)rows, H, Fp, X, Fp, 1, P + o_W1, 1, Fp, H1, H, part);
+    hipLaunchKernelGGL(k_bias_tanh, dim3(nblk(rows * H, 256)), dim3(256), 0, ctx.stream, rows, H, H1, P + o_b1);
+    check_launch(ctx, "k_bias_tanh");
+    sgemm(ctx, (int)rows, H, H, H1, H, 1, P + o_W2, 1, H, H2, H, part);
+    hipLaunchKernelGGL(k_bias_tanh, dim3(nblk(rows * H, 256)), dim3(256), 0, ctx.stream, rows, H, H2, P + o_b2);
+    check_launch(ctx, "k_bias_tanh");
+    hipLaunchKernelGGL(k_rowdot, dim3(nblk(rows, 4)), dim3(256), 0, ctx.stream, rows, H, H2, P + o_w3, P + o_b3, y);
+    check_launch(ctx, "k_rowdot");
+}
+
+double WarmStart::loss_grad(int64_t rows, const float *X, const float *T, float *G) {
+    float *P = params.p;
+    float *y = yb.ensure(rows), *dy = dyb.ensure(rows);
+    forward(rows, X, y);
+    const int nb = (int)nblk(rows, 256);
+    float *lp = lpart.ensure(nb);
+    hipLaunchKernelGGL(k_mse, dim3(nb), dim3(256), 0, ctx.stream, rows, y, T, dy, lp);
+    check_launch(ctx, "k_mse");
+    float *H1 = h1.p, *H2 = h2.p;
+    float *D2 = d2.ensure((size_t)rows * H), *D1 = d1.ensure((size_t)rows * H);
+    // output layer: g_w3 = H2^T dy (1 x H), g_b3 = sum dy
+    sgemm(ctx, 1, H, (int)rows, dy, 0, 1, H2, H, 1, G + o_w3, H, part);
+    // D2 = dy w3^T (1 - H2^2)
+    hipLaunchKernelGGL(k_back_out, dim3(nblk(rows * H, 256)), dim3(256), 0, ctx.stream, rows, H, dy, P + o_w3, H2, D2);
+    check_launch(ctx, "k_back_out");
+    // g_W2 = D2^T H1 (H x H);  D1 = (D2 W2) (1 - H1^2);  g_W1 = D1^T X (H x Fp)
+    sgemm(ctx, H, H, (int)rows, D2, 1, H, H1, H, 1, G + o_W2, H, part);
+    sgemm(ctx, (int)rows, H, H, D2, H, 1, P + o_W2, H, 1, D1, H, part);
+    hipLaunchKernelGGL(k_back_tanh, dim3(nblk(rows * H, 256)), dim3(256), 0, ctx.stream, rows * H, H1, D1);
+    check_launch(ctx, "k_back_tanh");
+    sgemm(ctx, H, Fp, (int)rows, D1, 1, H, X, Fp, 1, G + o_W1, Fp, part);
+    // bias gradients: column sums of D1, D2 and of dy
+    colsum(rows, H, D1, G + o_b1);
+    colsum(rows, H, D2, G + o_b2);
+    colsum(rows, 1, dy, G + o_b3);
+    std::vector<float> hl(nb);
+    YK_HIP(hipMemcpyAsync(hl.data(), lp, nb * sizeof(float), hipMemcpyDeviceToHost, ctx.stream));
+    YK_HIP(hipStreamSynchronize(ctx.stream));
+    double s = 0;
+    for (float v : hl) s += v;
+    return s / (double)rows;
+}
+
+void WarmStart::colsum(int64_t rows, int cols, const float *D, float *out) {
+    const int rpb = 512;
+    const int nbr = (int)nblk(rows, rpb);
+    float *p = cpart.ensure((size_t)nbr * cols);
+    hipLaunchKernelGGL(k_colsum_part, dim3(nbr, nblk(cols, 256)), dim3(256), 0, ctx.stream, rows, cols, D, rpb, p);
+    check_launch(ctx, "k_colsum_part");
+    // fixed-order reduction of the row-block partials
+    hipLaunchKernelGGL(k_sum_partials, dim3(nblk(cols, 256)), dim3(256), 0, ctx.stream, (int64_t)cols, nbr, p,
+                       (int64_t)cols, out);
+    check_launch(ctx, "k_sum_partials");
+}
+
+double WarmStart::train() {
+    const int ns = (int)obs.size() - 2;   // (N-1, N, N+1) triples
+    if (ns < 1) throw Error{YK_ERR_ARG, "warm start needs at least three observed steps to train"};
+    // features and targets of every triple (per-step scaling)
+    const int64_t rows = (int64_t)ns * n;
+    float *X = Xall.ensure((size_t)rows * Fp), *T = Tall.ensure(rows);
+    for (int s = 0; s < ns; ++s) {
+        const double rs = features(obs[s]->s.p, obs[s + 1]->s.p, obs[s]->g.p, obs[s + 1]->g.p,
+                                   obs[s + 2]->g.p, X + (int64_t)s * n * Fp);
+        hipLaunchKernelGGL(k_target, dim3(nblk(n, 256)), dim3(256), 0, ctx.stream, n, obs[s]->s.p,
+                           obs[s + 1]->s.p, obs[s + 2]->s.p, (float)(1.0 / rs), T + (int64_t)s * n);
+        check_launch(ctx, "k_target");
+    }
+    // Adam on shuffled mini-batches
+    const int64_t B = std::min<int64_t>(opt.batch, rows);
+    float *Xb = Xbat.ensure((size_t)B * Fp), *Tb = Tbat.ensure(B), *G = grad.ensure(n_params);
+    int32_t *rowsd = brows.ensure(B);
+    std::mt19937_64 rng(opt.seed ^ 0x9e3779b97f4a7c15ull);
+    std::vector<int32_t> perm(rows);
+    for (int64_t i = 0; i < rows; ++i) perm[i] = (int32_t)i;
+    int64_t pos = rows;
+    double loss = 0;
+    const float b1 = 0.9f, b2 = 0.999f;
+    for (int it = 0; it < opt.steps; ++it) {
+        if (pos + B > rows) {
+            std::shuffle(perm.begin(), perm.end(), rng);
+            pos = 0;
+        }
+        YK_HIP(hipMemcpyAsync(rowsd, perm.data() + pos, B * sizeof(int32_t), hipMemcpyHostToDevice, ctx.stream));
+        pos += B;
+        hipLaunchKernelGGL(k_gather_rows, dim3(nblk(B * Fp, 256)), dim3(256), 0, ctx.stream, B, Fp, rowsd, X, T,
+                           Xb, Tb);
+        check_launch(ctx, "k_gather_rows");
+        loss = loss_grad(B, Xb, Tb, G);
+        ++adam_t;
+        const float c1 = 1.f / (1.f - std::pow(b1, (float)adam_t)), c2 = 1.f / (1.f - std::pow(b2, (float)adam_t));
+        hipLaunchKernelGGL(k_adam, dim3(nblk(n_params, 256)), dim3(256), 0, ctx.stream, n_params, params.p, G,
+                           adam_m.p, adam_v.p, (float)opt.lr, b1, b2, 1e-8f, c1, c2);
+        check_launch(ctx, "k_adam");
+    }
+    trained = true;
+    return loss;
+}
+
+void WarmStart::predict(const double *g_next, double *out) {
+    if (obs.size() < 2) throw Error{YK_ERR_ARG, "warm start needs two observed steps to predict"};
+    const Obs &a = *obs[obs.size() - 2], &b = *obs[obs.size() - 1];
+    float *X = Xbat.ensure((size_t)std::max<int64_t>(n, (int64_t)opt.batch) * Fp);
+    const double rs = features(a.s.p, b.s.p, a.g.p, b.g.p, g_next, X);
+    float *y = yb.ensure(std::max<int64_t>(n, (int64_t)opt.batch));
+    forward(n, X, y);
+    hipLaunchKernelGGL(k_apply_pred, dim3(nblk(n, 256)), dim3(256), 0, ctx.stream, n, a.s.p, b.s.p, y, rs, out);
+    check_launch(ctx, "k_apply_pred");
+}
+
+}  // namespace yk

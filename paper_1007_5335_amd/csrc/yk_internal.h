@@ -63,6 +63,7 @@ struct DevBuf {
 };
 
 struct Context;
+struct WarmStart;
 
 // Launch-time check (and optional synchronous check in debug mode).
 void check_launch(Context &ctx, const char *what);
@@ -107,6 +108,9 @@ struct Context {
     DevBuf<double> scal;                   // small device scalars
     DevBuf<double> dn;                     // dipole vectors [N][2]
     std::vector<double> host_scal;
+
+    struct WarmStart *warm = nullptr;       // attached learned warm start (not owned)
+    DevBuf<double> ws_g, ws_ml, ws_t;       // heat-step buffers of the guess selection
 
     // optional per-stage event timing
     bool timing = false;

@@ -35,6 +35,9 @@ EXPORTS = (
     "yk_last_error", "yk_invalidate_geometry", "yk_volume_potential", "yk_double_layer_apply",
     "yk_gmres_density", "yk_heat_step", "yk_rhs_backward_euler", "yk_fmm_potential",
     "yk_plan_info_get", "yk_timing_enable", "yk_timing_read",
+    "yk_ws_default_options", "yk_ws_create", "yk_ws_destroy", "yk_ws_observe", "yk_ws_train",
+    "yk_ws_predict", "yk_set_warm_start", "yk_ws_num_params", "yk_ws_get_params",
+    "yk_ws_set_params", "yk_ws_loss_grad",
 )
 
 STAGES = ("gather", "p2m", "m2m", "m2l", "l2l", "leaf", "scatter", "direct")
@@ -78,6 +81,11 @@ class yk_plan_info(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class yk_ws_options(ctypes.Structure):
+    _fields_ = [("hidden", ctypes.c_int), ("batch", ctypes.c_int), ("steps", ctypes.c_int),
+                ("lr", ctypes.c_double), ("max_obs", ctypes.c_int), ("seed", ctypes.c_uint64)]
+
+
 class YkError(RuntimeError):
     def __init__(self, status, msg, stats=None):
         super().__init__(f"libyk status {status}: {msg}")
@@ -117,6 +125,17 @@ def load_library(path: str = LIB_PATH):
         "yk_plan_info_get": (ip, [vp, ip, P(yk_plan_info)]),
         "yk_timing_enable": (ip, [vp, ip]),
         "yk_timing_read": (ip, [vp, P(dbl), P(i64), ip]),
+        "yk_ws_default_options": (None, [P(yk_ws_options)]),
+        "yk_ws_create": (ip, [vp, P(yk_boundary), P(yk_ws_options), P(vp)]),
+        "yk_ws_destroy": (ip, [vp]),
+        "yk_ws_observe": (ip, [vp, vp, vp]),
+        "yk_ws_train": (ip, [vp, P(dbl)]),
+        "yk_ws_predict": (ip, [vp, vp, vp]),
+        "yk_set_warm_start": (ip, [vp, vp]),
+        "yk_ws_num_params": (i64, [vp, P(ip), P(ip)]),
+        "yk_ws_get_params": (ip, [vp, vp]),
+        "yk_ws_set_params": (ip, [vp, vp]),
+        "yk_ws_loss_grad": (ip, [vp, i64, vp, vp, vp, P(dbl)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -135,7 +154,7 @@ def _dev(t, name, dtype="float64", shape_last=None):
         return None
     if not isinstance(t, torch.Tensor):
         raise TypeError(f"{name} must be a torch tensor on the GPU")
-    want = torch.float64 if dtype == "float64" else torch.int32
+    want = {"float64": torch.float64, "float32": torch.float32, "int32": torch.int32}[dtype]
     if t.dtype != want:
         raise TypeError(f"{name} must be {want}, got {t.dtype}")
     if not t.is_cuda:
@@ -299,3 +318,76 @@ def yk_timing_read(ctx, reset=False):
     calls = (ctypes.c_int64 * len(STAGES))()
     _check(ctx, load_library().yk_timing_read(ctx, ms, calls, 1 if reset else 0))
     return {name: (ms[i], calls[i]) for i, name in enumerate(STAGES)}
+
+
+# ---------------------------------------------------------------------------
+# learned warm start
+# ---------------------------------------------------------------------------
+class WarmStartHandle:
+    """A yk_ws together with the context that owns it (destroy it first)."""
+
+    def __init__(self, ctx, h):
+        self.ctx = ctx
+        self.h = h
+
+
+def yk_ws_default_options() -> yk_ws_options:
+    o = yk_ws_options()
+    load_library().yk_ws_default_options(ctypes.byref(o))
+    return o
+
+
+def yk_ws_create(ctx, bnd: Boundary, opt: yk_ws_options | None = None, **kw) -> WarmStartHandle:
+    if opt is None:
+        opt = yk_ws_default_options()
+    for k, v in kw.items():
+        setattr(opt, k, v)
+    h = ctypes.c_void_p()
+    _check(ctx, load_library().yk_ws_create(ctx, ctypes.byref(bnd.struct), ctypes.byref(opt), ctypes.byref(h)))
+    return WarmStartHandle(ctx, h)
+
+
+def yk_ws_destroy(ws: WarmStartHandle):
+    load_library().yk_ws_destroy(ws.h)
+
+
+def yk_ws_observe(ws: WarmStartHandle, g, sigma):
+    _check(ws.ctx, load_library().yk_ws_observe(ws.h, _dev(g, "g"), _dev(sigma, "sigma")))
+
+
+def yk_ws_train(ws: WarmStartHandle) -> float:
+    loss = ctypes.c_double()
+    _check(ws.ctx, load_library().yk_ws_train(ws.h, ctypes.byref(loss)))
+    return loss.value
+
+
+def yk_ws_predict(ws: WarmStartHandle, g_next, sigma_out):
+    _check(ws.ctx, load_library().yk_ws_predict(ws.h, _dev(g_next, "g_next"), _dev(sigma_out, "sigma_out")))
+    return sigma_out
+
+
+def yk_set_warm_start(ctx, ws: WarmStartHandle | None):
+    _check(ctx, load_library().yk_set_warm_start(ctx, ws.h if ws is not None else None))
+
+
+def yk_ws_num_params(ws: WarmStartHandle):
+    H, Fp = ctypes.c_int(), ctypes.c_int()
+    n = load_library().yk_ws_num_params(ws.h, ctypes.byref(H), ctypes.byref(Fp))
+    return int(n), H.value, Fp.value
+
+
+def yk_ws_get_params(ws: WarmStartHandle, out):
+    _check(ws.ctx, load_library().yk_ws_get_params(ws.h, _dev(out, "params", dtype="float32")))
+    return out
+
+
+def yk_ws_set_params(ws: WarmStartHandle, params):
+    _check(ws.ctx, load_library().yk_ws_set_params(ws.h, _dev(params, "params", dtype="float32")))
+
+
+def yk_ws_loss_grad(ws: WarmStartHandle, X, t, grad) -> float:
+    loss = ctypes.c_double()
+    _check(ws.ctx, load_library().yk_ws_loss_grad(ws.h, X.shape[0], _dev(X, "X", dtype="float32"),
+                                                  _dev(t, "t", dtype="float32"),
+                                                  _dev(grad, "grad", dtype="float32"), ctypes.byref(loss)))
+    return loss.value

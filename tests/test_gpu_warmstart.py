@@ -1,0 +1,113 @@
+"""Learned warm start: training kernels against the FP64 reference, and the
+time loop with the learned guess (safety: every step reaches the tolerance)."""
+import numpy as np
+import pytest
+
+import workloads as W
+from gpu_util import dev, host
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def yk():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1007_5335_amd.yk as yk
+    yk.load_library()
+    return yk
+
+
+def test_mlp_loss_and_gradients_vs_fp64(yk):
+    import torch
+    from oracle import mlp
+    cfg = W.config_c0(n_nodes=64, m=8)
+    ctx = yk.yk_create()
+    bd = yk.Boundary.from_workload(cfg["bnd"])
+    ws = yk.yk_ws_create(ctx, bd, hidden=256)
+    try:
+        n, H, Fp = yk.yk_ws_num_params(ws)
+        rng = np.random.default_rng(7)
+        p = (rng.standard_normal(n) * 0.08).astype(np.float32)
+        X = rng.standard_normal((700, Fp)).astype(np.float32)
+        X[:, 65:] = 0.0
+        t = rng.standard_normal(700).astype(np.float32)
+        yk.yk_ws_set_params(ws, dev(p, torch.float32))
+        g = torch.empty(n, dtype=torch.float32, device="cuda")
+        loss = yk.yk_ws_loss_grad(ws, dev(X, torch.float32), dev(t, torch.float32), g)
+    finally:
+        yk.yk_ws_destroy(ws)
+        yk.yk_destroy(ctx)
+    ref_loss, ref_g = mlp.loss_grad(p.astype(np.float64), H, Fp, X.astype(np.float64), t.astype(np.float64))
+    assert abs(loss - ref_loss) < 1e-5 * ref_loss
+    gg = host(g).astype(np.float64)
+    blocks = [(0, H * Fp), (H * Fp, H * Fp + H), (H * Fp + H, H * Fp + H + H * H),
+              (H * Fp + H + H * H, H * Fp + 2 * H + H * H), (H * Fp + 2 * H + H * H, n - 1), (n - 1, n)]
+    for a, b in blocks:
+        err = np.max(np.abs(gg[a:b] - ref_g[a:b])) / np.max(np.abs(ref_g[a:b]))
+        assert err < 2e-4, (a, b, err)
+
+
+def _run_loop(yk, cfg, n_steps, train_at=None, ws_opts=None, garbage=False, precision=0):
+    import torch
+    b = cfg["bnd"]
+    d = dev
+    vol, w = d(cfg["vol"]), d(cfg["vol_w"])
+    region = d(cfg["region"])
+    f = d(cfg["f_bnd"])
+    ctx = yk.yk_create(precision=precision)
+    bd = yk.Boundary.from_workload(b)
+    ws = None
+    if train_at is not None:
+        ws = yk.yk_ws_create(ctx, bd, **(ws_opts or {}))
+        yk.yk_set_warm_start(ctx, ws)
+    u = d(cfg["u0"]); B = torch.empty_like(u); un = torch.empty_like(u)
+    sig = torch.zeros(b.n, dtype=torch.float64, device="cuda")
+    recs = []
+    try:
+        for step in range(1, n_steps + 1):
+            if ws is not None and step == train_at:
+                loss = yk.yk_ws_train(ws)
+                assert np.isfinite(loss)
+                if garbage:
+                    nparam, _, _ = yk.yk_ws_num_params(ws)
+                    yk.yk_ws_set_params(ws, torch.full((nparam,), float("nan"), dtype=torch.float32,
+                                                       device="cuda"))
+            yk.yk_rhs_backward_euler(ctx, u, None, region, cfg["consts"], cfg["dt"], B)
+            st = yk.yk_heat_step(ctx, bd, vol, w, B, yk.HEAT_GRID_SELF_CELL, f, cfg["dt"], 1e-10, sig, un)
+            recs.append(st.as_dict())
+            u, un = un, u
+        out = host(u)
+    finally:
+        if ws is not None:
+            yk.yk_ws_destroy(ws)
+        yk.yk_destroy(ctx)
+    return recs, out
+
+
+def test_time_loop_with_learned_guess(yk):
+    cfg = W.config_c3(m=256, n_holes=10, n_nodes=256, dt=1e-3, seed=3)
+    base, u_base = _run_loop(yk, cfg, 30)
+    opts = dict(hidden=256, batch=4096, steps=400)
+    learn, u_learn = _run_loop(yk, cfg, 30, train_at=21, ws_opts=opts)
+    for r in base + learn:
+        assert r["res_final"] <= 1e-10
+    assert np.max(np.abs(u_learn - u_base)) < 1e-7 * np.max(np.abs(u_base))
+    it_b = np.mean([r["iters"] for r in base[20:]])
+    it_l = np.mean([r["iters"] for r in learn[20:]])
+    r0_b = np.mean([r["res0"] for r in base[20:]])
+    r0_l = np.mean([r["res0"] for r in learn[20:]])
+    used = sum(r["guess_used"] == 2 for r in learn[20:])
+    print(f"steps 21-30: iters {it_b:.1f} -> {it_l:.1f}, initial residual {r0_b:.2e} -> {r0_l:.2e}, "
+          f"learned guess used {used}/10", flush=True)
+    assert r0_l <= r0_b * 1.0001
+    assert used >= 1
+
+
+def test_warm_start_falls_back_on_garbage_network(yk):
+    cfg = W.config_c3(m=128, n_holes=4, n_nodes=128, dt=1e-3, seed=5)
+    recs, _ = _run_loop(yk, cfg, 8, train_at=5, ws_opts=dict(hidden=64, batch=1024, steps=5), garbage=True)
+    for r in recs:
+        assert r["res_final"] <= 1e-10
+    assert all(r["guess_used"] == 1 for r in recs[4:])

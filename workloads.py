@@ -239,13 +239,19 @@ def _random_ellipses(rng, n_holes, n_nodes, amin, amax, gap, rmax=0.4, cen=(0.5,
     return [ellipse(c, a, b, n_nodes, rot, ccw=False) for (c, R, a, b, rot) in placed]
 
 
-def config_c3(m=1024, n_holes=10, n_nodes=2048, dt=1e-3, seed=3):
-    """Time-stepping set: unit square, outer circle of radius 0.5 at (0.5,0.5)
-    with n_nodes nodes, n_holes random ellipses (semi-axes U[0.02,0.08],
-    rotation U[0,pi)) with n_nodes nodes each; an m x m cell-centred grid;
-    u_0 = 0 in the domain, u = 0 on the outer curve and u = c_k on hole k."""
+def config_c3(m=1024, n_holes=10, n_nodes=2048, dt=1e-3, seed=3, n_outer=None):
+    """Time-stepping set: unit square, n_holes random ellipses (semi-axes
+    U[0.02,0.08], rotation U[0,pi)) with n_nodes nodes each inside an outer
+    circle of radius 0.5 at (0.5,0.5); an m x m cell-centred grid;
+    u_0 = 0 in the domain, u = 0 on the outer curve and u = c_k on hole k.
+    The outer circle gets n_outer nodes, by default the power of two that makes
+    its node spacing at most 0.4 grid cells, so that no curve is coarser than
+    the grid (the trapezoid double layer is inaccurate within about two node
+    spacings of its curve)."""
     rng = np.random.default_rng(seed)
-    curves = [circle((0.5, 0.5), 0.5, n_nodes, ccw=True)]
+    if n_outer is None:
+        n_outer = 1 << int(math.ceil(math.log2(2 * math.pi * 0.5 / (0.4 / m))))
+    curves = [circle((0.5, 0.5), 0.5, n_outer, ccw=True)]
     curves += _random_ellipses(rng, n_holes, n_nodes, 0.02, 0.08, 0.02)
     bnd = make_boundary(curves)
     vol, h = _cell_grid(0.0, 1.0, m)
