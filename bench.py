@@ -150,7 +150,10 @@ def oracle_baseline(args, res, idx):
 
 
 def heat_step_bench(args, yk, torch, W):
-    """s/time-step of the backward-Euler step on the time-stepping geometry."""
+    """s/time-step of the backward-Euler step on the time-stepping geometry:
+    plain FP64 with the previous-step guess against mixed precision with the
+    learned warm start (trained on the first half of the steps), averaged over
+    the second half; every step is solved to the same GMRES tolerance."""
     cfg = W.config_c3(m=args.heat_m, n_holes=10, n_nodes=2048, dt=1e-3, seed=3)
     b = cfg["bnd"]
     d = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
@@ -158,35 +161,57 @@ def heat_step_bench(args, yk, torch, W):
     region = torch.as_tensor(cfg["region"], dtype=torch.int32, device="cuda")
     f = d(cfg["f_bnd"])
     bd = yk.Boundary.from_workload(b)
-    out = {}
-    for name, prec in (("fp64", yk.YK_PREC_FP64), ("mixed", yk.YK_PREC_MIXED)):
+    n_steps, half = args.heat_steps, args.heat_steps // 2
+    runs = (("fp64", yk.YK_PREC_FP64, False), ("fp64_learned", yk.YK_PREC_FP64, True),
+            ("mixed_learned", yk.YK_PREC_MIXED, True))
+    out, finals = {}, {}
+    for name, prec, learned in runs:
         ctx = yk.yk_create(fmm_tol=1e-10, leaf_size=args.leaf, precision=prec)
+        ws = None
         try:
+            if learned:
+                ws = yk.yk_ws_create(ctx, bd)
+                yk.yk_set_warm_start(ctx, ws)
             u = d(cfg["u0"])
             B = torch.empty_like(u)
             un = torch.empty_like(u)
             sig = torch.zeros(b.n, dtype=torch.float64, device="cuda")
-            times, iters, stage = [], [], []
-            for step in range(args.heat_steps + 1):
+            times, iters, res0, used, train_s = [], [], [], [], None
+            for step in range(1, n_steps + 1):
+                if ws is not None and step == half + 1:
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    yk.yk_ws_train(ws)
+                    train_s = time.perf_counter() - t0
                 yk.yk_rhs_backward_euler(ctx, u, None, region, cfg["consts"], cfg["dt"], B)
                 torch.cuda.synchronize()
                 t0 = time.perf_counter()
                 st = yk.yk_heat_step(ctx, bd, vol, w, B, yk.HEAT_GRID_SELF_CELL, f, cfg["dt"], 1e-10,
                                      sig, un)
                 torch.cuda.synchronize()
-                if step > 0:             # the first step builds the trees
+                if step > half:
                     times.append(time.perf_counter() - t0)
                     iters.append(st.iters)
-                    stage.append(list(st.ms[:4]))
+                    res0.append(st.res0)
+                    used.append(st.guess_used == 2)
                 u, un = un, u
+            finals[name] = u.cpu().numpy()
         finally:
+            if ws is not None:
+                yk.yk_ws_destroy(ws)
             yk.yk_destroy(ctx)
-        sm = np.mean(np.array(stage), axis=0)
         out[name] = {"s_per_step": float(np.mean(times)), "gmres_iters": float(np.mean(iters)),
-                     "ms_tree_vol2nodes_solve_final": [round(float(v), 3) for v in sm]}
-    out["workload"] = (f"{args.heat_m}x{args.heat_m} cell grid, outer circle + 10 ellipses x 2048 nodes, "
-                       f"dt=1e-3, alpha=sqrt(dt), previous-step guess, tol 1e-10, "
-                       f"{args.heat_steps} timed steps")
+                     "initial_rel_residual": float(np.mean(res0)),
+                     "learned_guess_used": float(np.mean(used)) if learned else None,
+                     "train_s": train_s}
+    ref = finals["fp64"]
+    for name in finals:
+        out[name]["u_rel_diff_vs_fp64"] = float(np.max(np.abs(finals[name] - ref)) / np.max(np.abs(ref)))
+    out["speedup_mixed_learned_vs_fp64"] = out["fp64"]["s_per_step"] / out["mixed_learned"]["s_per_step"]
+    out["workload"] = (f"{n_steps} backward-Euler steps, dt=1e-3, alpha=sqrt(dt), {args.heat_m}^2 cell grid "
+                       f"in the unit square, outer circle ({b.curves[0].n} nodes) + 10 random ellipses x "
+                       f"2048 nodes, GMRES tol 1e-10; network trained on steps 1-{half}, timing and "
+                       f"iterations averaged over steps {half + 1}-{n_steps}")
     return out
 
 
@@ -205,9 +230,11 @@ def main():
     ap.add_argument("--cpu-samples", type=int, default=100)
     ap.add_argument("--fp32", action="store_true")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle check (profiling runs)")
-    ap.add_argument("--heat-steps", type=int, default=5)
+    ap.add_argument("--heat-steps", type=int, default=100)
     ap.add_argument("--heat-m", type=int, default=1024)
     ap.add_argument("--no-heat", action="store_true")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="also run a plain 256 MiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -221,6 +248,14 @@ def main():
     yk.load_library()
     torch.cuda.set_device(0)
 
+    if args.calib_copy:
+        # a fill (writes 256 MiB) and an elementwise multiply (reads 256 MiB,
+        # writes 256 MiB): reference dispatches for the HBM byte counters
+        xs = torch.ones(1 << 25, dtype=torch.float64, device="cuda")
+        ys = torch.empty_like(xs)
+        torch.mul(xs, 2.0, out=ys)
+        torch.cuda.synchronize()
+        del xs, ys
     res = run_fmm_bench(args, yk, torch, W)
     info, st = res["info"], res["stages"]
     value = res["n_pts"] / (res["ms"] * 1e-3) / 1e6

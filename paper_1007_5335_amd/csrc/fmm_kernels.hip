@@ -11,6 +11,17 @@ namespace {
 
 inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
+// Consecutive workgroups are dealt round-robin to the 8 XCDs, each with its
+// own L2.  Remapping block b so that every XCD walks one contiguous range of
+// the (Morton-ordered) work list keeps neighbouring boxes' data in one L2.
+// The map is a bijection on [0, n).
+__device__ __forceinline__ int xcd_remap(int b, int n) {
+    constexpr int kXcd = 8;
+    const int x = b % kXcd, i = b / kXcd;
+    const int q = n / kXcd, r = n % kXcd;
+    return x * q + min(x, r) + i;
+}
+
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
@@ -315,7 +326,7 @@ __global__ __launch_bounds__(256) void k_tile_gemm(const int4 *__restrict__ tile
     constexpr int NRT = PP / 16, NKS = PP / 4, NLD = PP * PP / 256;
     __shared__ T As[2][PP * PP];
     using MF = Mfma<T>;
-    const int4 tl = tiles[tile0 + blockIdx.x];
+    const int4 tl = tiles[tile0 + xcd_remap(blockIdx.x, gridDim.x)];
     const int level = tl.x, cls = tl.y, start = tl.z, count = tl.w;
     const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
     const int jb = 16 * w + (lane & 15);
@@ -496,7 +507,8 @@ __global__ __launch_bounds__(64) void k_leaf(
     const double *__restrict__ cnn, const double *__restrict__ sc, int nser, int p, int Pp,
     double inv4a2, double inva2, double *__restrict__ outs) {
     __shared__ double s_x[kLeafStage], s_y[kLeafStage], s_a[kLeafStage], s_b[kLeafStage];
-    const int2 item = items[blockIdx.x];
+    __shared__ int qa[9], qn[9], da[9], dn_[9];
+    const int2 item = items[xcd_remap(blockIdx.x, gridDim.x)];
     const int li = item.x;
     const int64_t b = leaf_base + li;
     const int lane = threadIdx.x;
@@ -508,19 +520,25 @@ __global__ __launch_bounds__(64) void k_leaf(
         ntot += re[s] - rs[s];
     }
     const int u0 = uoff[li], nu = uoff[li + 1] - u0;
-    // U-list source ranges (at most 9 neighbours) of the two source sets
-    int qa[9], qn[9], da[9], dn_[9], nq = 0, nd = 0;
-    for (int u = 0; u < 9; ++u) {
-        qa[u] = qn[u] = da[u] = dn_[u] = 0;
+    // U-list source ranges (at most 9 neighbours) of the two source sets, in
+    // LDS (indexed per lane below; a private array would live in scratch)
+    if (lane < 9) {
+        const int u = lane;
+        int a = 0, an = 0, b2 = 0, bn = 0;
         if (u < nu) {
             const int ul = ulist[u0 + u];
-            qa[u] = lrange[ul * 6];
-            qn[u] = has_q ? lrange[ul * 6 + 1] - qa[u] : 0;
-            da[u] = lrange[ul * 6 + 2];
-            dn_[u] = has_d ? lrange[ul * 6 + 3] - da[u] : 0;
-            nq += qn[u];
-            nd += dn_[u];
+            a = lrange[ul * 6];
+            an = has_q ? lrange[ul * 6 + 1] - a : 0;
+            b2 = lrange[ul * 6 + 2];
+            bn = has_d ? lrange[ul * 6 + 3] - b2 : 0;
         }
+        qa[u] = a; qn[u] = an; da[u] = b2; dn_[u] = bn;
+    }
+    __syncthreads();
+    int nq = 0, nd = 0;
+    for (int u = 0; u < 9; ++u) {
+        nq += qn[u];
+        nd += dn_[u];
     }
     const double *Lb = Lc + b * Pp;
     {
