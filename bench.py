@@ -38,19 +38,44 @@ PEAK_FP64_VALU_TF = 78.6      # MI355X FP64 vector peak (256 CU x 2.4 GHz x 128 
 PEAK_FP32_MFMA_TF = 157.3
 
 
+LOG_FLOPS = 40   # FP64 logarithm: 9 for the reciprocal with two Newton steps, 31 for the
+                 # reduction, the degree-10 atanh series and the exponent recombination
+
+
 def near_flops(info):
     """Algorithmic FP64 flops of the near field and of the local evaluation.
 
     Per charge pair: separation and r^2 (5), t = r^2/(4 alpha^2) (1), the two
     Horner series of length n (4(n-1)), -1/2 ln(t) A(t) + B(t) (3), q K0 + acc (2),
-    with ln(t) counted as one operation.  Per dipole pair: the same geometry (6),
-    the K1(z)/z series (4(n-1) + 6), (x-y).dn (3), scale and accumulate (3).
-    Per L2P point: 9 per order plus the F_n start (4 per series term) plus 10."""
+    plus the logarithm counted at the cost of its evaluation (LOG_FLOPS, an FMA
+    being 2 flops), as N-body codes count a reciprocal square root.  Per dipole
+    pair: the same geometry (6), the K1(z)/z series (4(n-1) + 6), (x-y).dn (3),
+    scale and accumulate (3), plus the logarithm.  Per L2P point: 9 per order
+    plus the F_n start (4 per series term) plus 10."""
     n = info.near_terms
-    fq = 12 + 4 * (n - 1)
-    fd = 18 + 4 * (n - 1)
+    fq = 12 + 4 * (n - 1) + LOG_FLOPS
+    fd = 18 + 4 * (n - 1) + LOG_FLOPS
     fl = 9 * info.p + 4 * info.nser + 10
     return info.pairs_charge * fq + info.pairs_dipole * fd + info.l2p_points * fl
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary, or None when the kernel source changed since it was taken."""
+    import hashlib
+    prof = os.path.join(ROOT, "profiles", "hbm_traffic_fmm_pass_c1_fp64.md")
+    src = os.path.join(ROOT, "paper_1007_5335_amd", "csrc", "fmm_kernels.hip")
+    try:
+        h = hashlib.sha256(open(src, "rb").read()).hexdigest()
+        for ln in open(prof):
+            f = ln.split()
+            if len(f) == 4 and f[0] == "traffic" and f[1] == kernel:
+                kv = dict(x.split("=", 1) for x in f[2:])
+                if kv.get("source_sha256") == h:
+                    return float(kv["bytes_per_launch"])
+    except OSError:
+        pass
+    return None
 
 
 def m2l_flops(info):
@@ -265,7 +290,8 @@ def main():
     achieved = lf / (leaf_avg * 1e-3) / 1e12
     roof = {"kernel": "k_leaf (near field P2P + L2P)", "bound": "alu", "achieved": achieved,
             "peak": PEAK_FP64_VALU_TF, "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_VALU_TF,
-            "traffic": None, "avg_launch_ms": leaf_avg, "algorithmic_flops": lf}
+            "traffic": measured_traffic("k_leaf"), "avg_launch_ms": leaf_avg,
+            "algorithmic_flops": lf, "log_counted_as_flops": LOG_FLOPS}
     m2l_ms, m2l_calls = st["m2l"]
     m2l_rate = m2l_flops(info) / (m2l_ms / max(args.steps, 1) * 1e-3) / 1e12 if m2l_ms > 0 else None
     err, errmax, idx, _ = direct_check(args, res, yk, torch)
