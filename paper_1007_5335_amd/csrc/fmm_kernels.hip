@@ -417,37 +417,56 @@ __global__ void k_to_float(int64_t n, const double *__restrict__ a, float *__res
 }
 
 // ----------------------------------------------------------- leaf kernel ---
-// One wavefront per leaf.  The leaf's targets (its points of the requested
-// sets) are processed 64 lanes at a time: with c targets in a chunk, each
-// target gets g = 64 / next_pow2(c) lanes that split its U-list sources
-// between them, and the g partial sums are combined with shuffles.  Sources
-// are read straight from global memory (every lane of a target group reads
-// the same few consecutive addresses).  The local expansion is evaluated by
-// the first lane of each group (Horner in z with G_m = F_m(y)/F_m(Y)).
+// Near field in scaled coordinates: points are multiplied by 1/(2 alpha), so
+// the squared distance of two scaled points is t = r^2/(4 alpha^2) itself and
+//     K0(r/alpha)            = h(t) A(t) + B(t),           h = -(1/2) ln t,
+//     4 K1(r/alpha)/(r/alpha) = 1/t - 2 h(t) C(t) - D(t)
+// for t <= 1 (series in bessel_tables.h); larger t use the Chebyshev forms.
 template <int NT, typename T>
 __device__ __forceinline__ T horner_n(const T (&c)[YK_NSER64], T t) {
     T s = c[NT - 1];
 #pragma unroll
-    for (int k = NT - 2; k >= 0; --k) s = s * t + c[k];
+    for (int k = NT - 2; k >= 0; --k) s = __builtin_fma(s, t, c[k]);
     return s;
 }
 
+// h(t) = -(1/2) ln t for a positive normal t.  With t = m 2^e, m in [1/2, 1),
+// piece i of [1/2, 1) is given by the top eight fraction bits of m; the table
+// holds rc_i ~ 1/c_i (c_i the piece's centre) and (1/2) ln rc_i, and
+// -(1/2) ln m = (1/2) ln rc_i - (1/2) log1p(m rc_i - 1) with |m rc_i - 1| < 2^-9,
+// where five terms of the log1p series leave an error below r^6/12 < 2^-57.
+// ln 2 is split so that e * ln2_hi is exact.
+__device__ __forceinline__ double neg_half_log(double t, const double2 *__restrict__ tab) {
+    const int e = __builtin_amdgcn_frexp_exp(t);
+    const double m = __builtin_amdgcn_frexp_mant(t);
+    const int i = (__double2hiint(m) >> 12) & (YK_LOG_TAB - 1);
+    const double2 c = tab[i];
+    const double r = __builtin_fma(m, c.x, -1.0);
+    double s = __builtin_fma(r, -0.1, 0.125);
+    s = __builtin_fma(s, r, -1.0 / 6.0);
+    s = __builtin_fma(s, r, 0.25);
+    s = __builtin_fma(s, r, -0.5);
+    const double de = (double)e;
+    constexpr double h2_hi = -0.5 * 6.93147180369123816490e-01;   // -(1/2) 0x3FE62E42FEE00000
+    constexpr double h2_lo = -0.5 * 1.90821492927058770002e-10;
+    return __builtin_fma(de, h2_hi, c.y + __builtin_fma(de, h2_lo, s * r));
+}
+
 template <int NT, bool kSmallOnly>
-__device__ __forceinline__ double near_k0(double t) {
-    if (kSmallOnly || t <= 1.0) {
-        const double lt = fast_log(t);
-        return -0.5 * lt * horner_n<NT>(yk_ser_A, t) + horner_n<NT>(yk_ser_B, t);
-    }
+__device__ __forceinline__ double near_k0(double t, const double2 *__restrict__ tab) {
+    if (kSmallOnly || t <= 1.0)
+        return __builtin_fma(neg_half_log(t, tab), horner_n<NT>(yk_ser_A, t), horner_n<NT>(yk_ser_B, t));
     return k0_large(2.0 * sqrt(t));
 }
+// 4 K1(z)/z with t = z^2/4
 template <int NT, bool kSmallOnly>
-__device__ __forceinline__ double near_k1oz(double t) {
+__device__ __forceinline__ double near_k1oz4(double t, const double2 *__restrict__ tab) {
     if (kSmallOnly || t <= 1.0) {
-        const double lt = fast_log(t);
-        return 0.25 * fast_rcp(t) + 0.25 * lt * horner_n<NT>(yk_ser_C, t) - 0.25 * horner_n<NT>(yk_ser_D, t);
+        const double h2 = 2.0 * neg_half_log(t, tab);
+        return fast_rcp(t) - __builtin_fma(h2, horner_n<NT>(yk_ser_C, t), horner_n<NT>(yk_ser_D, t));
     }
     const double z = 2.0 * sqrt(t);
-    return k1_large(z) / z;
+    return 4.0 * k1_large(z) / z;
 }
 
 template <int NT>
@@ -466,14 +485,13 @@ __device__ __forceinline__ float near_k0_f(float t) {
     return k0_large_f(2.0f * sqrtf(t));
 }
 template <bool kSmallOnly>
-__device__ __forceinline__ float near_k1oz_f(float t) {
+__device__ __forceinline__ float near_k1oz4_f(float t) {
     if (kSmallOnly || t <= 1.0f) {
         const float lt = __logf(t);
-        return 0.25f / t + 0.25f * lt * horner_nf<YK_NSER32>(yk_ser_C_f, t) -
-               0.25f * horner_nf<YK_NSER32>(yk_ser_D_f, t);
+        return 1.0f / t + lt * horner_nf<YK_NSER32>(yk_ser_C_f, t) - horner_nf<YK_NSER32>(yk_ser_D_f, t);
     }
     const float z = 2.0f * sqrtf(t);
-    return k1_large_f(z) / z;
+    return 4.0f * k1_large_f(z) / z;
 }
 
 // Near-field accumulation policy: FP64 (series and sums in double) or FP32
@@ -482,19 +500,26 @@ __device__ __forceinline__ float near_k1oz_f(float t) {
 template <int NT, bool kSmallOnly, bool kF32>
 struct Near {
     using acc_t = typename std::conditional<kF32, float, double>::type;
-    static __device__ __forceinline__ acc_t charge(double q, double r2, double inv4a2) {
-        if constexpr (kF32) return (float)q * near_k0_f<kSmallOnly>((float)(r2 * inv4a2));
-        else return q * near_k0<NT, kSmallOnly>(r2 * inv4a2);
+    static __device__ __forceinline__ acc_t charge(double q, double t, const double2 *tab) {
+        if constexpr (kF32) return (float)q * near_k0_f<kSmallOnly>((float)t);
+        else return q * near_k0<NT, kSmallOnly>(t, tab);
     }
-    static __device__ __forceinline__ acc_t dipole(double dot, double r2, double inv4a2, double inva2) {
-        if constexpr (kF32) return (float)(dot * inva2) * near_k1oz_f<kSmallOnly>((float)(r2 * inv4a2));
-        else return dot * inva2 * near_k1oz<NT, kSmallOnly>(r2 * inv4a2);
+    // dot = (x - y).(d n_y) in scaled coordinates; the caller multiplies the
+    // sum by 1/(2 alpha), which turns dot * 4K1(z)/z into (1/alpha) K1(z) (x-y).(d n)/r
+    static __device__ __forceinline__ acc_t dipole(double dot, double t, const double2 *tab) {
+        if constexpr (kF32) return (float)dot * near_k1oz4_f<kSmallOnly>((float)t);
+        else return dot * near_k1oz4<NT, kSmallOnly>(t, tab);
     }
 };
 
-// Sources of the U-list are staged into LDS in chunks of kLeafStage (a single
-// wavefront, so the barriers are cheap), then every lane group walks the chunk.
-constexpr int kLeafStage = 512;
+// One wavefront per item: up to 64 targets of one leaf.  With c targets, the
+// 64 lanes form g = floor(64/c) groups of c lanes; lane l serves target l mod c
+// and walks every g-th source of the leaf's U list, so at most c - 1 lanes
+// idle.  U-list sources are staged into LDS (scaled coordinates and strengths)
+// in chunks of kLeafStage; the group partial sums are combined through LDS at
+// the end.  The local expansion is evaluated by the first group (Horner in z
+// with G_m = F_m(y)/F_m(Y)).
+constexpr int kLeafStage = 192;
 
 template <int NT, bool kSmallOnly, bool kF32 = false>
 __global__ __launch_bounds__(64) void k_leaf(
@@ -505,13 +530,16 @@ __global__ __launch_bounds__(64) void k_leaf(
     int64_t off1, int has_q, int has_d, int mask, int has_far, const double *__restrict__ Lc,
     double inv_alpha, double invR, const double *__restrict__ invFY,
     const double *__restrict__ cnn, const double *__restrict__ sc, int nser, int p, int Pp,
-    double inv4a2, double inva2, double *__restrict__ outs) {
+    double inv2a, double dip_scale, double *__restrict__ outs) {
     __shared__ double s_x[kLeafStage], s_y[kLeafStage], s_a[kLeafStage], s_b[kLeafStage];
+    __shared__ double2 s_log[YK_LOG_TAB];
     __shared__ int qa[9], qn[9], da[9], dn_[9];
     const int2 item = items[xcd_remap(blockIdx.x, gridDim.x)];
     const int li = item.x;
     const int64_t b = leaf_base + li;
     const int lane = threadIdx.x;
+    if constexpr (!kF32)
+        for (int i = lane; i < YK_LOG_TAB; i += 64) s_log[i] = make_double2(yk_log_tab[2 * i], yk_log_tab[2 * i + 1]);
     const double cx = bcx[b], cy = bcy[b];
     int rs[3], re[3], ntot = 0;
     for (int s = 0; s < 3; ++s) {
@@ -541,86 +569,96 @@ __global__ __launch_bounds__(64) void k_leaf(
         nd += dn_[u];
     }
     const double *Lb = Lc + b * Pp;
-    {
-        const int tb = item.y;
-        const int c = min(64, ntot - tb);
-        int np2 = 1;
-        while (np2 < c) np2 <<= 1;
-        const int g = 64 / np2;
-        const int ti = lane / g, sub = lane - ti * g;
-        int k = tb + ti, t = -1;
-        if (ti < c)
-            for (int s = 0; s < 3; ++s) {
-                const int n = re[s] - rs[s];
-                if (t < 0 && k < n) t = rs[s] + k;
-                k -= n;
-            }
-        const bool valid = t >= 0;
-        const double x = valid ? px[t] : cx, y = valid ? py[t] : cy;
-        double acc = 0.0;
-        if (has_far && valid && sub == 0) {
-            const double wx = (x - cx) * inv_alpha, wy = (y - cy) * inv_alpha;
-            const double yv = 0.25 * (wx * wx + wy * wy);
-            const double zx = wx * invR, zy = wy * invR;
-            double F1, F2;
-            f_start(yv, sc, nser, F1, F2);
-            double sr = 0.0, si = 0.0;
-            for (int m = p; m >= 1; --m) {
-                const double F0 = F1 + yv * F2 * cnn[m];
-                const double gm = F0 * invFY[m];
-                const double cr = Lb[2 * m - 1] * gm, ci = Lb[2 * m] * gm;
-                const double nr = sr * zx - si * zy + cr;
-                si = sr * zy + si * zx + ci;
-                sr = nr;
-                F2 = F1;
-                F1 = F0;
-            }
-            const double F0 = F1 + yv * F2 * cnn[0];
-            acc = Lb[0] * F0 * invFY[0] + 2.0 * (sr * zx - si * zy);
+    const int tb = item.y;
+    const int c = min(64, ntot - tb);          // >= 1 by construction of the items
+    const int g = 64 / c;
+    const int ti = lane % c, sub = lane / c;
+    const bool valid = sub < g;
+    int k = tb + ti, t = -1;
+    for (int s = 0; s < 3; ++s) {
+        const int n = re[s] - rs[s];
+        if (t < 0 && k < n) t = rs[s] + k;
+        k -= n;
+    }
+    const double x = px[t], y = py[t];
+    const double xs = x * inv2a, ys = y * inv2a;
+    double acc = 0.0;
+    if (has_far && sub == 0) {
+        const double wx = (x - cx) * inv_alpha, wy = (y - cy) * inv_alpha;
+        const double yv = 0.25 * (wx * wx + wy * wy);
+        const double zx = wx * invR, zy = wy * invR;
+        double F1, F2;
+        f_start(yv, sc, nser, F1, F2);
+        double sr = 0.0, si = 0.0;
+        for (int m = p; m >= 1; --m) {
+            const double F0 = F1 + yv * F2 * cnn[m];
+            const double gm = F0 * invFY[m];
+            const double cr = Lb[2 * m - 1] * gm, ci = Lb[2 * m] * gm;
+            const double nr = sr * zx - si * zy + cr;
+            si = sr * zy + si * zx + ci;
+            sr = nr;
+            F2 = F1;
+            F1 = F0;
         }
-        using NearT = Near<NT, kSmallOnly, kF32>;
-        typename NearT::acc_t near = 0;
-        for (int set = 0; set < 2; ++set) {
-            const int ntot_s = set == 0 ? nq : nd;
-            for (int c0 = 0; c0 < ntot_s; c0 += kLeafStage) {
-                const int cn = min(kLeafStage, ntot_s - c0);
-                __syncthreads();
-                // cooperative gather of flat source indices [c0, c0 + cn) into LDS
-                for (int f = lane; f < cn; f += 64) {
-                    int r = c0 + f, u = 0;
-                    const int *cnt = set == 0 ? qn : dn_;
-                    while (u < 8 && r >= cnt[u]) { r -= cnt[u]; ++u; }
-                    const int j = (set == 0 ? qa[u] : da[u]) + r;
-                    s_x[f] = px[j];
-                    s_y[f] = py[j];
-                    if (set == 0) {
-                        s_a[f] = qs[j];
-                    } else {
-                        const int64_t jd = j - off1;
-                        s_a[f] = dns[2 * jd];
-                        s_b[f] = dns[2 * jd + 1];
-                    }
-                }
-                __syncthreads();
-                if (valid) {
-                    if (set == 0) {
-                        for (int j = sub; j < cn; j += g) {
-                            const double dx = x - s_x[j], dy = y - s_y[j];
-                            const double r2 = dx * dx + dy * dy;
-                            if (r2 > 0.0) near += NearT::charge(s_a[j], r2, inv4a2);
-                        }
-                    } else {
-                        for (int j = sub; j < cn; j += g) {
-                            const double dx = x - s_x[j], dy = y - s_y[j];
-                            const double r2 = dx * dx + dy * dy;
-                            if (r2 > 0.0) near += NearT::dipole(dx * s_a[j] + dy * s_b[j], r2, inv4a2, inva2);
-                        }
-                    }
+        const double F0 = F1 + yv * F2 * cnn[0];
+        acc = Lb[0] * F0 * invFY[0] + 2.0 * (sr * zx - si * zy);
+    }
+    using NearT = Near<NT, kSmallOnly, kF32>;
+    typename NearT::acc_t near_q = 0, near_d = 0;
+    for (int set = 0; set < 2; ++set) {
+        const int ntot_s = set == 0 ? nq : nd;
+        for (int c0 = 0; c0 < ntot_s; c0 += kLeafStage) {
+            const int cn = min(kLeafStage, ntot_s - c0);
+            __syncthreads();
+            // cooperative gather of flat source indices [c0, c0 + cn) into LDS
+            for (int f = lane; f < cn; f += 64) {
+                int r = c0 + f, u = 0;
+                const int *cnt = set == 0 ? qn : dn_;
+                while (u < 8 && r >= cnt[u]) { r -= cnt[u]; ++u; }
+                const int j = (set == 0 ? qa[u] : da[u]) + r;
+                s_x[f] = px[j] * inv2a;
+                s_y[f] = py[j] * inv2a;
+                if (set == 0) {
+                    s_a[f] = qs[j];
+                } else {
+                    const int64_t jd = j - off1;
+                    s_a[f] = dns[2 * jd];
+                    s_b[f] = dns[2 * jd + 1];
                 }
             }
+            __syncthreads();
+            if (valid) {
+                // full passes (every lane's source index in range), then the tail
+                const int nfull = cn - cn % g;
+                if (set == 0) {
+                    auto pair = [&](int j) {
+                        const double dx = xs - s_x[j], dy = ys - s_y[j];
+                        const double tt = __builtin_fma(dx, dx, dy * dy);
+                        if (tt > 0.0) near_q += NearT::charge(s_a[j], tt, s_log);
+                    };
+#pragma unroll 2
+                    for (int jj = 0; jj < nfull; jj += g) pair(jj + sub);
+                    if (nfull + sub < cn) pair(nfull + sub);
+                } else {
+                    auto pair = [&](int j) {
+                        const double dx = xs - s_x[j], dy = ys - s_y[j];
+                        const double tt = __builtin_fma(dx, dx, dy * dy);
+                        if (tt > 0.0) near_d += NearT::dipole(__builtin_fma(dx, s_a[j], dy * s_b[j]), tt, s_log);
+                    };
+#pragma unroll 2
+                    for (int jj = 0; jj < nfull; jj += g) pair(jj + sub);
+                    if (nfull + sub < cn) pair(nfull + sub);
+                }
+            }
         }
-        for (int off = g >> 1; off > 0; off >>= 1) near += __shfl_xor(near, off, 64);
-        if (valid && sub == 0) outs[t] = (acc + (double)near) * kInv2Pi;
+    }
+    __syncthreads();
+    s_x[lane] = valid ? (double)near_q + dip_scale * (double)near_d : 0.0;
+    __syncthreads();
+    if (sub == 0) {
+        double tot = acc;
+        for (int gi = 0; gi < g; ++gi) tot += s_x[ti + gi * c];
+        outs[t] = tot * kInv2Pi;
     }
 }
 
@@ -633,6 +671,7 @@ using LeafKernel = void (*)(const int2 *, int64_t, const int32_t *, const int32_
 LeafKernel pick_leaf_kernel(int nt, bool small_only, bool f32) {
     if (f32) return small_only ? k_leaf<8, true, true> : k_leaf<8, false, true>;
     if (small_only) {
+        if (nt <= 5) return k_leaf<5, true>;
         if (nt <= 6) return k_leaf<6, true>;
         if (nt <= 8) return k_leaf<8, true>;
         if (nt <= 10) return k_leaf<10, true>;
@@ -762,15 +801,14 @@ void fmm_run(Context &ctx, FmmPlan &pl, const double *q, const double *dn, doubl
         }
     }
     if (as.n_leaves > 0) {
-        const double inv4a2 = 0.25 * inv_alpha * inv_alpha, inva2 = inv_alpha * inv_alpha;
-        const double tmax = 2.0 * pl.lev[L].side * pl.lev[L].side * inv4a2 * 4.0;
+        const double tmax = 2.0 * pl.lev[L].side * pl.lev[L].side * inv_alpha * inv_alpha;
         LeafKernel kern = pick_leaf_kernel(pl.near_terms, tmax <= 1.0, prec == SUM_FP32);
         StageTimer tl(ctx, YK_STAGE_LEAF);
         hipLaunchKernelGGL(kern, dim3(as.n_items), dim3(64), 0, ctx.stream, as.leaf_items.p,
                            leaf_base, pl.lrange.p, pl.ulist_off.p, pl.ulist.p, pl.bcx.p, pl.bcy.p,
                            pl.px.p, pl.py.p, qs, dns, pl.toff[1], has_q, has_d, mask, far ? 1 : 0,
                            pl.Lc.p, inv_alpha, 1.0 / pl.lev[L].R, pl.invFY.p + L * lvl, pl.cnn.p,
-                           pl.serc.p, pl.nser, p, Pp, inv4a2, inva2, outs);
+                           pl.serc.p, pl.nser, p, Pp, 0.5 * inv_alpha, 0.5 * inv_alpha, outs);
         check_launch(ctx, "k_leaf");
     }
     StageTimer tsc(ctx, YK_STAGE_SCATTER);

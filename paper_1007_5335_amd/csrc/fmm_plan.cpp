@@ -401,17 +401,23 @@ void build_lists_and_tables(Context &ctx, FmmPlan &pl, const std::vector<uint32_
         up(pl.serc, sc);
     }
     // near-field series length: t = r^2/(4 alpha^2) over U-list pairs is at most
-    // (2 sqrt(2) side_L)^2 / (4 alpha^2); when it exceeds 1 the large-argument branch is used too
+    // (2 sqrt(2) side_L)^2 / (4 alpha^2); when it exceeds 1 the large-argument
+    // branch is used too.  The series are cut at the first power whose term,
+    // weighted by the largest factor it meets ((1/2)|ln t| for A, about 3 for
+    // the digamma weights of B and D), is below half an ulp of the smallest
+    // K0 on the range (K0(z) > -(1/2) ln t - 0.58, and K0(2) > 0.11).
     {
         const double tmax = 2.0 * pl.lev[L].side * pl.lev[L].side / (alpha * alpha);
         const double tt = std::min(1.0, tmax);
+        const double weight = 0.5 * std::fabs(std::log(tt)) + 3.0;
+        const double k0min = std::max(0.11, -0.5 * std::log(tt) - 0.58);
         int k = 1;
         double term = 1;
         for (; k < YK_NSER64; ++k) {
             term *= tt / ((double)k * (double)k);
-            if (term < 1e-18) break;
+            if (term * weight < 0x1p-54 * k0min) break;
         }
-        pl.near_terms = std::min(YK_NSER64, k + 1);
+        pl.near_terms = std::min(YK_NSER64, k);
     }
 
     const int nC = 2 * p + 1;
