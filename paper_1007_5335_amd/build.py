@@ -24,6 +24,9 @@ COMMON = ["-O3", "-fPIC", "-std=c++17", f"--offload-arch={ARCH}",
           "-I", INCLUDE, "-I", CSRC,
           # no packed FP32 instructions in generated code
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+          # matrix-core accumulators in ordinary VGPRs: no per-iteration copies
+          # between VGPRs and AGPRs around the MFMA loops
+          "-mllvm", "-amdgpu-mfma-vgpr-form",
           "-Wno-unused-command-line-argument"]
 
 

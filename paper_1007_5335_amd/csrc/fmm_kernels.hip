@@ -315,7 +315,15 @@ template <> struct Mfma<float> {
 //   out[box] (+)= sum_s Op[level + level_shift][slot_op[cls][s]] * X[src[box][s]]
 // Every box of a tile has the same level and parity class (so the same
 // operator per slot).  X is read in its own type TS and converted to T.
-template <typename T, typename TS, int PP>
+//
+// A workgroup owns 64 boxes (4 wavefronts x 16 columns) and walks the slots;
+// the slot's Pp x Pp operator is double-buffered in LDS and the gathered
+// source coefficients of the next slot are loaded while the current slot runs.
+// With P = 16 NB + 1 real coefficients (p a multiple of 8), index 0 is split
+// off: the matrix cores take the 16 NB x 16 NB block of indices 1..16 NB and
+// the vector units add row 0 and column 0 (a 64 x 64 padded product would
+// spend 40% more matrix-core work on padding).
+template <typename T, typename TS, int PP, bool SPLIT_REQ>
 __global__ __launch_bounds__(256) void k_tile_gemm(const int4 *__restrict__ tiles, int tile0,
                                                    const int32_t *__restrict__ boxes, int nslot,
                                                    const int32_t *__restrict__ src,
@@ -323,81 +331,141 @@ __global__ __launch_bounds__(256) void k_tile_gemm(const int4 *__restrict__ tile
                                                    const T *__restrict__ Op, int64_t op_stride,
                                                    int level_shift, const TS *__restrict__ X,
                                                    int assign, double *__restrict__ out) {
-    constexpr int NRT = PP / 16, NKS = PP / 4, NLD = PP * PP / 256;
+    constexpr bool SPLIT = SPLIT_REQ && PP > 16;   // (the host never asks for PP = 16)
+    constexpr int NB = SPLIT ? PP / 16 - 1 : PP / 16;   // 16-row blocks on the matrix cores
+    constexpr int OFF = SPLIT ? 1 : 0;                  // first index of the matrix-core block
+    constexpr int NKS = 4 * NB, NLD = PP * PP / 256;
+    constexpr int kMaxSlot = 27;
     __shared__ T As[2][PP * PP];
+    __shared__ int32_t s_src[kMaxSlot * 64];
     using MF = Mfma<T>;
     const int4 tl = tiles[tile0 + xcd_remap(blockIdx.x, gridDim.x)];
     const int level = tl.x, cls = tl.y, start = tl.z, count = tl.w;
-    const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+    const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, g = lane >> 4;
     const int jb = 16 * w + (lane & 15);
     const bool colvalid = jb < count;
     const int64_t boxj = colvalid ? boxes[start + jb] : -1;
-    typename MF::acc acc[NRT];
+    // source box of every (slot, column) of the tile, -1 where empty
+    for (int e = tid; e < nslot * 64; e += 256) {
+        const int sl = e >> 6, j = e & 63;
+        s_src[e] = j < count ? src[(int64_t)boxes[start + j] * nslot + sl] : -1;
+    }
+    typename MF::acc acc[NB];
 #pragma unroll
-    for (int r = 0; r < NRT; ++r) acc[r] = typename MF::acc{0, 0, 0, 0};
+    for (int r = 0; r < NB; ++r) acc[r] = typename MF::acc{0, 0, 0, 0};
+    T rowacc = T(0), colacc[NB][4];
+#pragma unroll
+    for (int r = 0; r < NB; ++r)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) colacc[r][q] = T(0);
     const T *Olev = Op + (int64_t)(level + level_shift) * op_stride;
     auto op_of = [&](int sl) -> const T * { return Olev + (size_t)slot_op[cls * nslot + sl] * PP * PP; };
-    auto load_b = [&](int sl, T (&bf)[NKS]) {
-        const int32_t sj = colvalid ? src[boxj * nslot + sl] : -1;
-        const TS *row = X + (int64_t)(sj >= 0 ? sj : 0) * PP + (lane >> 4);
+    // B fragment of a slot: unconditional loads (row 0 stands in for an empty
+    // slot) and the empty slot's zeros selected when the fragment is consumed,
+    // so the loads of the next slot stay in flight during the current one (a
+    // select, not a product, so whatever row 0 holds never reaches the sums)
+    TS braw[NKS], b0raw = TS(0);
+    bool bvalid = false;
+    T bcur[NKS], b0 = T(0), pre[NLD];
+    auto load_b = [&](int sl) {
+        const int32_t sj = s_src[sl * 64 + jb];
+        const TS *row = X + (int64_t)(sj >= 0 ? sj : 0) * PP;
 #pragma unroll
-        for (int ks = 0; ks < NKS; ++ks) bf[ks] = sj >= 0 ? (T)row[4 * ks] : T(0);
+        for (int ks = 0; ks < NKS; ++ks) braw[ks] = row[OFF + 4 * ks + g];
+        if constexpr (SPLIT) b0raw = row[0];
+        bvalid = sj >= 0;
     };
-    T bcur[NKS], bnxt[NKS], pre[NLD];
-    load_b(0, bcur);
+    auto take_b = [&]() {
+#pragma unroll
+        for (int ks = 0; ks < NKS; ++ks) bcur[ks] = bvalid ? (T)braw[ks] : T(0);
+        if constexpr (SPLIT) b0 = bvalid ? (T)b0raw : T(0);
+    };
+    __syncthreads();
+    load_b(0);
     {
         const T *Tg = op_of(0);
 #pragma unroll
         for (int e = 0; e < NLD; ++e) As[0][tid + 256 * e] = Tg[tid + 256 * e];
     }
+    take_b();
     __syncthreads();
     for (int slot = 0; slot < nslot; ++slot) {
         const int cur = slot & 1;
         const bool more = slot + 1 < nslot;
         if (more) {
-            load_b(slot + 1, bnxt);
+            load_b(slot + 1);
             const T *Tg = op_of(slot + 1);
 #pragma unroll
             for (int e = 0; e < NLD; ++e) pre[e] = Tg[tid + 256 * e];
         }
-        const T *Ac = As[cur] + (lane >> 4) * PP + (lane & 15);
+        // operator column-major: A[i][k] = As[k * PP + i]
+        const T *Ac = As[cur] + (OFF + g) * PP + OFF + (lane & 15);
 #pragma unroll
         for (int ks = 0; ks < NKS; ++ks) {
 #pragma unroll
-            for (int rt = 0; rt < NRT; ++rt)
+            for (int rt = 0; rt < NB; ++rt)
                 acc[rt] = MF::step(Ac[4 * ks * PP + 16 * rt], bcur[ks], acc[rt]);
+        }
+        if constexpr (SPLIT) {
+            const T *A = As[cur];
+            // row 0: this lane's share of sum_k A[0][k] b[k]; column 0 into the
+            // rows this lane holds of the matrix-core result
+#pragma unroll
+            for (int ks = 0; ks < NKS; ++ks) rowacc += A[(OFF + 4 * ks + g) * PP] * bcur[ks];
+            if (g == 0) rowacc += A[0] * b0;
+#pragma unroll
+            for (int rt = 0; rt < NB; ++rt)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) colacc[rt][q] += A[OFF + 16 * rt + MF::row(lane, q)] * b0;
         }
         if (more) {
 #pragma unroll
             for (int e = 0; e < NLD; ++e) As[cur ^ 1][tid + 256 * e] = pre[e];
-#pragma unroll
-            for (int ks = 0; ks < NKS; ++ks) bcur[ks] = bnxt[ks];
+            take_b();
         }
         __syncthreads();
+    }
+    if constexpr (SPLIT) {
+        rowacc += __shfl_xor(rowacc, 16, 64);
+        rowacc += __shfl_xor(rowacc, 32, 64);
     }
     if (colvalid) {
         double *o = out + boxj * PP;
 #pragma unroll
-        for (int rt = 0; rt < NRT; ++rt)
+        for (int rt = 0; rt < NB; ++rt)
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int i = 16 * rt + MF::row(lane, r);
-                o[i] = assign ? (double)acc[rt][r] : o[i] + (double)acc[rt][r];
+            for (int q = 0; q < 4; ++q) {
+                const int i = OFF + 16 * rt + MF::row(lane, q);
+                const double v = SPLIT ? (double)acc[rt][q] + (double)colacc[rt][q] : (double)acc[rt][q];
+                o[i] = assign ? v : o[i] + v;
             }
+        if constexpr (SPLIT) {
+            if (g == 0) o[0] = assign ? (double)rowacc : o[0] + (double)rowacc;
+            // padding entries 16 NB + 1 .. PP - 1 stay zero for later readers
+            if (assign)
+                for (int i = OFF + 16 * NB + g; i < PP; i += 4) o[i] = 0.0;
+        }
     }
 }
 
 template <typename T, typename TS>
-void launch_tile_gemm(Context &ctx, int Pp, int ntiles, const int4 *tiles, int tile0,
+void launch_tile_gemm(Context &ctx, int P, int Pp, int ntiles, const int4 *tiles, int tile0,
                       const int32_t *boxes, int nslot, const int32_t *src, const int32_t *slot_op,
                       const T *Op, int64_t op_stride, int level_shift, const TS *X, int assign,
                       double *out) {
     if (ntiles <= 0) return;
+    if (nslot < 1 || nslot > 27) throw Error{YK_ERR_INTERNAL, "tile GEMM supports 1..27 slots"};
+    const bool split = Pp >= 32 && P == Pp - 15;
 #define YK_TILE_CASE(PPV)                                                                          \
     case PPV:                                                                                      \
-        hipLaunchKernelGGL((k_tile_gemm<T, TS, PPV>), dim3(ntiles), dim3(256), 0, ctx.stream, tiles, \
-                           tile0, boxes, nslot, src, slot_op, Op, op_stride, level_shift, X, assign,  \
-                           out);                                                                   \
+        if (split)                                                                                 \
+            hipLaunchKernelGGL((k_tile_gemm<T, TS, PPV, true>), dim3(ntiles), dim3(256), 0,       \
+                               ctx.stream, tiles, tile0, boxes, nslot, src, slot_op, Op, op_stride, \
+                               level_shift, X, assign, out);                                      \
+        else                                                                                       \
+            hipLaunchKernelGGL((k_tile_gemm<T, TS, PPV, false>), dim3(ntiles), dim3(256), 0,      \
+                               ctx.stream, tiles, tile0, boxes, nslot, src, slot_op, Op, op_stride, \
+                               level_shift, X, assign, out);                                      \
         break;
     switch (Pp) {
         YK_TILE_CASE(16)
@@ -731,7 +799,7 @@ void fmm_run(Context &ctx, FmmPlan &pl, const double *q, const double *dn, doubl
             for (int l = L - 1; l >= pl.lmin; --l) {
                 if (Pp <= 64) {
                     // M2M on matrix cores: 4 child slots, operators S[l][position]
-                    launch_tile_gemm<double, double>(ctx, Pp, pl.up_tile_count[l], pl.up_tiles.p,
+                    launch_tile_gemm<double, double>(ctx, P, Pp, pl.up_tile_count[l], pl.up_tiles.p,
                                                      pl.up_tile_begin[l], pl.up_boxes.p, 4, pl.child4.p,
                                                      pl.iota4.p, pl.m2m.p, (int64_t)4 * Pp * Pp, 0, pl.M.p,
                                                      1, pl.M.p);
@@ -758,11 +826,11 @@ void fmm_run(Context &ctx, FmmPlan &pl, const double *q, const double *dn, doubl
                 // M2L of every level at once (levels are independent given the multipoles)
                 StageTimer tl(ctx, YK_STAGE_M2L);
                 if (f32)
-                    launch_tile_gemm<float, float>(ctx, Pp, as.n_tiles, as.m2l_tiles.p, 0, as.m2l_boxes.p,
+                    launch_tile_gemm<float, float>(ctx, P, Pp, as.n_tiles, as.m2l_tiles.p, 0, as.m2l_boxes.p,
                                                    kNumV, pl.vlist.p, pl.slot_oid.p, pl.m2lf.p,
                                                    (int64_t)kNumOff * Pp * Pp, 0, pl.Mf.p, 0, pl.Lc.p);
                 else
-                    launch_tile_gemm<double, double>(ctx, Pp, as.n_tiles, as.m2l_tiles.p, 0, as.m2l_boxes.p,
+                    launch_tile_gemm<double, double>(ctx, P, Pp, as.n_tiles, as.m2l_tiles.p, 0, as.m2l_boxes.p,
                                                      kNumV, pl.vlist.p, pl.slot_oid.p, pl.m2l.p,
                                                      (int64_t)kNumOff * Pp * Pp, 0, pl.M.p, 0, pl.Lc.p);
             }
@@ -770,12 +838,12 @@ void fmm_run(Context &ctx, FmmPlan &pl, const double *q, const double *dn, doubl
             for (int l = pl.lmin + 1; l <= L; ++l) {
                 // L2L top-down: one parent slot, operator E[l-1][position]
                 if (f32)
-                    launch_tile_gemm<float, double>(ctx, Pp, as.tile_count[l], as.m2l_tiles.p,
+                    launch_tile_gemm<float, double>(ctx, P, Pp, as.tile_count[l], as.m2l_tiles.p,
                                                     as.tile_begin[l], as.m2l_boxes.p, 1, pl.bparent.p,
                                                     pl.iota4.p, pl.l2lf.p, (int64_t)4 * Pp * Pp, -1, pl.Lc.p,
                                                     0, pl.Lc.p);
                 else
-                    launch_tile_gemm<double, double>(ctx, Pp, as.tile_count[l], as.m2l_tiles.p,
+                    launch_tile_gemm<double, double>(ctx, P, Pp, as.tile_count[l], as.m2l_tiles.p,
                                                      as.tile_begin[l], as.m2l_boxes.p, 1, pl.bparent.p,
                                                      pl.iota4.p, pl.l2l.p, (int64_t)4 * Pp * Pp, -1, pl.Lc.p,
                                                      0, pl.Lc.p);
