@@ -66,16 +66,34 @@ __device__ __forceinline__ void f_start(double y, const double *__restrict__ sc,
 }
 
 // ------------------------------------------------------------------- P2M ---
-// One wavefront serves four leaves, 16 lanes each; lanes over source points.
-// Each lane builds G_n = F_n(y)/F_n(Y) for n = 0..p+1 in its own LDS column
-// (downwards), then the terms q G_n conj(z)^n (upwards) are summed over the
-// 16 lanes of the leaf with shuffles.
-__device__ __forceinline__ double group16_sum(double v) {
-#pragma unroll
-    for (int off = 8; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+// One wavefront serves four leaves, 16 lanes (one DPP row) each; lanes over
+// source points.  Each lane builds G_n = F_n(y)/F_n(Y) for n = 0..p+1 in its
+// own LDS column (downwards), then the terms of every order are summed over
+// the row with DPP (no LDS round trip); the lane whose index matches the
+// output's position mod 16 stores the batch sum, and the batch sums are then
+// accumulated in registers, output o = lane + 16 k.  The level's tables
+// (F-series coefficients, recurrence factors, normalisations, dipole weights)
+// are staged in LDS so the order loops read no scalar memory.
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double v) {
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+// sum over the 16 lanes of a row, in every lane of the row
+__device__ __forceinline__ double row16_sum(double v) {
+    v += dpp_d<0xB1>(v);    // quad_perm [1,0,3,2]
+    v += dpp_d<0x4E>(v);    // quad_perm [2,3,0,1]
+    v += dpp_d<0x124>(v);   // row_ror:4
+    v += dpp_d<0x128>(v);   // row_ror:8
     return v;
 }
 
+constexpr int kP2MSlots = 8;   // outputs per lane: Pp <= 128
+
+// NMAX > 0: orders known to be at most NMAX - 1 (Pp <= 2 NMAX), so G_n lives
+// in registers and the order loops unroll; NMAX = 0: G_n in LDS, any order.
+template <int NMAX>
 __global__ __launch_bounds__(64) void k_p2m(
     int64_t leaf_base, int64_t nleaf, const int32_t *__restrict__ lrange,
     const double *__restrict__ bcx, const double *__restrict__ bcy, const double *__restrict__ px,
@@ -84,17 +102,42 @@ __global__ __launch_bounds__(64) void k_p2m(
     const double *__restrict__ invFY, const double *__restrict__ da, const double *__restrict__ db,
     const double *__restrict__ cnn, const double *__restrict__ sc, int nser, int p, int Pp,
     double *__restrict__ M) {
+    constexpr bool kReg = NMAX > 0;
     extern __shared__ double smem[];
-    double *G = smem;                    // [(p+2)][64]
-    double *Msh = smem + (p + 2) * 64;   // [4][Pp]
+    double *G = smem;                                  // [(p+2)][64] (LDS form only)
+    double *s_out = G + (kReg ? 0 : (p + 2) * 64);     // [4][Pp] row sums of one batch
+    double *t_sc = s_out + 4 * Pp;                     // [2 nser] F_{p+1}, F_{p+2} series
+    double *t_cnn = t_sc + 2 * nser;                   // [p+2]
+    double *t_ify = t_cnn + (p + 2);                   // [p+2]
+    double *t_da = t_ify + (p + 2);                    // [p+1]
+    double *t_db = t_da + (p + 1);                     // [p+1]
     const int lane = threadIdx.x, grp = lane >> 4, gl = lane & 15;
     const int64_t li = (int64_t)blockIdx.x * 4 + grp;
     const bool leaf_ok = li < nleaf;
     const int64_t b = leaf_base + (leaf_ok ? li : 0);
-    double *Mg = Msh + grp * Pp;
-    for (int k = gl; k < Pp; k += 16) Mg[k] = 0.0;
+    const int P = 2 * p + 1, nk = Pp >> 4;
+    for (int k = lane; k < 2 * nser; k += 64) t_sc[k] = sc[k];
+    for (int k = lane; k < p + 2; k += 64) {
+        t_cnn[k] = cnn[k];
+        t_ify[k] = invFY[k];
+    }
+    if (has_d)
+        for (int k = lane; k < p + 1; k += 64) {
+            t_da[k] = da[k];
+            t_db[k] = db[k];
+        }
+    double *So = s_out + grp * Pp;
+    double macc[kP2MSlots];
+#pragma unroll
+    for (int k = 0; k < kP2MSlots; ++k) macc[k] = 0.0;
+    double Gr[kReg ? NMAX + 2 : 1];
     __syncthreads();
     const double cx = bcx[b], cy = bcy[b];
+    // G_n of this lane's point, register or LDS form
+    auto gget = [&](int n) -> double {
+        if constexpr (kReg) return Gr[n];
+        else return G[n * 64 + lane];
+    };
     for (int set = 0; set < 2; ++set) {
         if ((set == 0 && !has_q) || (set == 1 && !has_d)) continue;
         const int s0 = leaf_ok ? lrange[li * 6 + 2 * set] : 0;
@@ -106,53 +149,210 @@ __global__ __launch_bounds__(64) void k_p2m(
         for (int base = 0; base < nmax; base += 16) {
             const int j = s0 + base + gl;
             const bool valid = j < e0;
-            const double wx = valid ? (px[j] - cx) * inv_alpha : 0.0;
-            const double wy = valid ? (py[j] - cy) * inv_alpha : 0.0;
+            const int jc = valid ? j : (e0 > s0 ? s0 : (set == 0 ? 0 : (int)off1));   // weight 0 below
+            const double wx = valid ? (px[jc] - cx) * inv_alpha : 0.0;
+            const double wy = valid ? (py[jc] - cy) * inv_alpha : 0.0;
             const double y = 0.25 * (wx * wx + wy * wy);
             const double zx = wx * invR, zy = -wy * invR;   // conj(w)/R
             double F1, F2;
-            f_start(y, sc, nser, F1, F2);
-            G[(p + 1) * 64 + lane] = F1 * invFY[p + 1];
+            f_start(y, t_sc, nser, F1, F2);
+            if constexpr (kReg) {
+#pragma unroll
+                for (int n = NMAX + 1; n >= 0; --n) {
+                    if (n > p + 1) continue;
+                    if (n == p + 1) {
+                        Gr[n] = F1 * t_ify[n];
+                    } else {
+                        const double F0 = F1 + y * F2 * t_cnn[n];
+                        Gr[n] = F0 * t_ify[n];
+                        F2 = F1;
+                        F1 = F0;
+                    }
+                }
+            } else {
+                G[(p + 1) * 64 + lane] = F1 * t_ify[p + 1];
+                for (int n = p; n >= 0; --n) {
+                    const double F0 = F1 + y * F2 * t_cnn[n];
+                    G[n * 64 + lane] = F0 * t_ify[n];
+                    F2 = F1;
+                    F1 = F0;
+                }
+            }
+            // the row sum of order n goes to output 2n-1 (real) and 2n (imaginary)
+            auto emit = [&](int n, double tr, double ti) {
+                tr = row16_sum(tr);
+                ti = row16_sum(ti);
+                const int orr = n == 0 ? 0 : 2 * n - 1;
+                if (gl == (orr & 15)) So[orr] = tr;
+                if (n > 0 && gl == ((2 * n) & 15)) So[2 * n] = ti;
+            };
+            if (set == 0) {
+                const double q = valid ? qs[jc] : 0.0;
+                double pr = 1.0, pi = 0.0;     // conj(z)^n
+                auto body = [&](int n) {
+                    const double g = q * gget(n);
+                    emit(n, g * pr, g * pi);
+                    const double nr = pr * zx - pi * zy;
+                    pi = pr * zy + pi * zx;
+                    pr = nr;
+                };
+                if constexpr (kReg) {
+#pragma unroll
+                    for (int n = 0; n < NMAX; ++n)
+                        if (n <= p) body(n);
+                } else {
+                    for (int n = 0; n <= p; ++n) body(n);
+                }
+            } else {
+                const double Dx = valid ? dns[2 * (jc - off1)] : 0.0;
+                const double Dy = valid ? dns[2 * (jc - off1) + 1] : 0.0;
+                const double h = 0.5 * inv_alpha;
+                // window Psi_{n-1}, Psi_n, Psi_{n+1};  Psi_k = G_k conj(z)^k
+                double pr = zx, pi = zy;                       // conj(z)^1
+                const double g1 = gget(1);
+                double c_r = gget(0), c_i = 0.0;               // Psi_0
+                double n_r = g1 * pr, n_i = g1 * pi;           // Psi_1
+                double m_r = n_r, m_i = -n_i;                  // Psi_{-1} = conj(Psi_1)
+                auto body = [&](int n) {
+                    // term_n = h [a_n D Psi_{n+1} + b_n conj(D) Psi_{n-1}]
+                    const double an = t_da[n], bn = t_db[n];
+                    const double t1r = Dx * n_r - Dy * n_i, t1i = Dx * n_i + Dy * n_r;
+                    const double t2r = Dx * m_r + Dy * m_i, t2i = Dx * m_i - Dy * m_r;
+                    emit(n, h * (an * t1r + bn * t2r), h * (an * t1i + bn * t2i));
+                    m_r = c_r; m_i = c_i;
+                    c_r = n_r; c_i = n_i;
+                    const double nr = pr * zx - pi * zy;
+                    pi = pr * zy + pi * zx;
+                    pr = nr;
+                    if (n + 2 <= p + 1) {
+                        const double g = gget(n + 2);
+                        n_r = g * pr; n_i = g * pi;
+                    } else {
+                        n_r = 0.0; n_i = 0.0;
+                    }
+                };
+                if constexpr (kReg) {
+#pragma unroll
+                    for (int n = 0; n < NMAX; ++n)
+                        if (n <= p) body(n);
+                } else {
+                    for (int n = 0; n <= p; ++n) body(n);
+                }
+            }
+            __syncthreads();
+#pragma unroll
+            for (int k = 0; k < kP2MSlots; ++k)
+                if (k < nk && gl + 16 * k < P) macc[k] += So[gl + 16 * k];
+            __syncthreads();
+        }
+    }
+    if (leaf_ok)
+#pragma unroll
+        for (int k = 0; k < kP2MSlots; ++k)
+            if (k < nk) M[b * Pp + gl + 16 * k] = gl + 16 * k < P ? macc[k] : 0.0;
+}
+
+// P2M with four lanes per leaf (a DPP quad) for a compile-time order PO: each lane
+// takes every fourth point of its leaf and accumulates all 2p+1 outputs in
+// registers; the quad's partial sums are combined with two DPP steps at the
+// end.  Per point: F_n downwards (G_n = F_n(y)/F_n(Y) in registers), then the
+// terms with the powers of conj(z) upwards.
+template <int PO>
+__global__ __launch_bounds__(64) void k_p2m_quad(
+    int64_t leaf_base, int64_t nleaf, const int32_t *__restrict__ lrange,
+    const double *__restrict__ bcx, const double *__restrict__ bcy, const double *__restrict__ px,
+    const double *__restrict__ py, const double *__restrict__ qs, const double *__restrict__ dns,
+    int64_t off1, int has_q, int has_d, double inv_alpha, double invR,
+    const double *__restrict__ invFY, const double *__restrict__ da, const double *__restrict__ db,
+    const double *__restrict__ cnn, const double *__restrict__ sc, int nser, int /*p*/, int Pp,
+    double *__restrict__ M) {
+    constexpr int p = PO, P = 2 * PO + 1;
+    extern __shared__ double smem[];
+    double *t_sc = smem;                   // [2 nser] F_{p+1}, F_{p+2} series
+    double *t_cnn = t_sc + 2 * nser;       // [p+2]
+    double *t_ify = t_cnn + (p + 2);       // [p+2]
+    double *t_da = t_ify + (p + 2);        // [p+1]
+    double *t_db = t_da + (p + 1);         // [p+1]
+    const int lane = threadIdx.x, q4 = lane & 3;
+    const int64_t li = (int64_t)blockIdx.x * 16 + (lane >> 2);
+    const bool leaf_ok = li < nleaf;
+    const int64_t b = leaf_base + (leaf_ok ? li : 0);
+    for (int k = lane; k < 2 * nser; k += 64) t_sc[k] = sc[k];
+    for (int k = lane; k < p + 2; k += 64) {
+        t_cnn[k] = cnn[k];
+        t_ify[k] = invFY[k];
+    }
+    if (has_d)
+        for (int k = lane; k < p + 1; k += 64) {
+            t_da[k] = da[k];
+            t_db[k] = db[k];
+        }
+    double acc[P];
+#pragma unroll
+    for (int o = 0; o < P; ++o) acc[o] = 0.0;
+    double G[p + 2];
+    __syncthreads();
+    const double cx = bcx[b], cy = bcy[b];
+    for (int set = 0; set < 2; ++set) {
+        if ((set == 0 && !has_q) || (set == 1 && !has_d)) continue;
+        const int s0 = leaf_ok ? lrange[li * 6 + 2 * set] : 0;
+        const int e0 = leaf_ok ? lrange[li * 6 + 2 * set + 1] : 0;
+        for (int j0 = s0;; j0 += 4) {
+            const int j = j0 + q4;
+            const bool valid = j < e0;
+            if (!__any(valid)) break;
+            // a lane without a point reads a point of its own set (weight 0
+            // below): the leaf's first, else the set's first (index 0 or off1)
+            const int jc = valid ? j : (e0 > s0 ? s0 : (set == 0 ? 0 : (int)off1));
+            const double wx = (px[jc] - cx) * inv_alpha, wy = (py[jc] - cy) * inv_alpha;
+            const double y = 0.25 * (wx * wx + wy * wy);
+            const double zx = wx * invR, zy = -wy * invR;   // conj(w)/R
+            double F1, F2;
+            f_start(y, t_sc, nser, F1, F2);
+            // G_n for n = 0..p+1 (n = p+1 only for the dipole window)
+            G[p + 1] = F1 * t_ify[p + 1];
+#pragma unroll
             for (int n = p; n >= 0; --n) {
-                const double F0 = F1 + y * F2 * cnn[n];
-                G[n * 64 + lane] = F0 * invFY[n];
+                const double F0 = F1 + y * F2 * t_cnn[n];
+                G[n] = F0 * t_ify[n];
                 F2 = F1;
                 F1 = F0;
             }
             if (set == 0) {
-                const double q = valid ? qs[j] : 0.0;
+                const double qv = valid ? qs[jc] : 0.0;
                 double pr = 1.0, pi = 0.0;     // conj(z)^n
+#pragma unroll
                 for (int n = 0; n <= p; ++n) {
-                    const double g = q * G[n * 64 + lane];
-                    const double tr = group16_sum(g * pr), ti = group16_sum(g * pi);
-                    if (gl == 0) {
-                        if (n == 0) Mg[0] += tr;
-                        else { Mg[2 * n - 1] += tr; Mg[2 * n] += ti; }
+                    const double g = qv * G[n];
+                    if (n == 0) {
+                        acc[0] += g;
+                    } else {
+                        acc[2 * n - 1] = __builtin_fma(g, pr, acc[2 * n - 1]);
+                        acc[2 * n] = __builtin_fma(g, pi, acc[2 * n]);
                     }
                     const double nr = pr * zx - pi * zy;
                     pi = pr * zy + pi * zx;
                     pr = nr;
                 }
             } else {
-                const double Dx = valid ? dns[2 * (j - off1)] : 0.0;
-                const double Dy = valid ? dns[2 * (j - off1) + 1] : 0.0;
-                const double h = 0.5 * inv_alpha;
+                const double h = valid ? 0.5 * inv_alpha : 0.0;
+                const double Dx = h * dns[2 * (jc - off1)], Dy = h * dns[2 * (jc - off1) + 1];
                 // window Psi_{n-1}, Psi_n, Psi_{n+1};  Psi_k = G_k conj(z)^k
                 double pr = zx, pi = zy;                       // conj(z)^1
-                const double g1 = G[1 * 64 + lane];
-                double c_r = G[0 * 64 + lane], c_i = 0.0;      // Psi_0
-                double n_r = g1 * pr, n_i = g1 * pi;           // Psi_1
+                double c_r = G[0], c_i = 0.0;                  // Psi_0
+                double n_r = G[1] * pr, n_i = G[1] * pi;       // Psi_1
                 double m_r = n_r, m_i = -n_i;                  // Psi_{-1} = conj(Psi_1)
+#pragma unroll
                 for (int n = 0; n <= p; ++n) {
-                    // term_n = h [a_n D Psi_{n+1} + b_n conj(D) Psi_{n-1}]
-                    const double an = da[n], bn = db[n];
+                    // term_n = h [a_n D Psi_{n+1} + b_n conj(D) Psi_{n-1}]  (h folded into D)
+                    const double an = t_da[n], bn = t_db[n];
                     const double t1r = Dx * n_r - Dy * n_i, t1i = Dx * n_i + Dy * n_r;
                     const double t2r = Dx * m_r + Dy * m_i, t2i = Dx * m_i - Dy * m_r;
-                    const double tr = group16_sum(h * (an * t1r + bn * t2r));
-                    const double ti = group16_sum(h * (an * t1i + bn * t2i));
-                    if (gl == 0) {
-                        if (n == 0) Mg[0] += tr;
-                        else { Mg[2 * n - 1] += tr; Mg[2 * n] += ti; }
+                    if (n == 0) {
+                        acc[0] += an * t1r + bn * t2r;
+                    } else {
+                        acc[2 * n - 1] += an * t1r + bn * t2r;
+                        acc[2 * n] += an * t1i + bn * t2i;
                     }
                     m_r = c_r; m_i = c_i;
                     c_r = n_r; c_i = n_i;
@@ -160,8 +360,7 @@ __global__ __launch_bounds__(64) void k_p2m(
                     pi = pr * zy + pi * zx;
                     pr = nr;
                     if (n + 2 <= p + 1) {
-                        const double g = G[(n + 2) * 64 + lane];
-                        n_r = g * pr; n_i = g * pi;
+                        n_r = G[n + 2] * pr; n_i = G[n + 2] * pi;
                     } else {
                         n_r = 0.0; n_i = 0.0;
                     }
@@ -169,9 +368,16 @@ __global__ __launch_bounds__(64) void k_p2m(
             }
         }
     }
-    __syncthreads();
+    // quad sums; lane q4 of the quad writes outputs q4, q4 + 4, ...
+#pragma unroll
+    for (int o = 0; o < P; ++o) {
+        double v = acc[o];
+        v += dpp_d<0xB1>(v);    // quad_perm [1,0,3,2]
+        v += dpp_d<0x4E>(v);    // quad_perm [2,3,0,1]
+        if (leaf_ok && (o & 3) == q4) M[b * Pp + o] = v;
+    }
     if (leaf_ok)
-        for (int k = gl; k < Pp; k += 16) M[b * Pp + k] = Mg[k];
+        for (int o = P + q4; o < Pp; o += 4) M[b * Pp + o] = 0.0;
 }
 
 // ------------------------------------------------------------ M2M / L2L ---
@@ -602,6 +808,7 @@ __global__ __launch_bounds__(64) void k_leaf(
     __shared__ double s_x[kLeafStage], s_y[kLeafStage], s_a[kLeafStage], s_b[kLeafStage];
     __shared__ double2 s_log[YK_LOG_TAB];
     __shared__ int qa[9], qn[9], da[9], dn_[9];
+    extern __shared__ double dyn[];
     const int2 item = items[xcd_remap(blockIdx.x, gridDim.x)];
     const int li = item.x;
     const int64_t b = leaf_base + li;
@@ -636,7 +843,6 @@ __global__ __launch_bounds__(64) void k_leaf(
         nq += qn[u];
         nd += dn_[u];
     }
-    const double *Lb = Lc + b * Pp;
     const int tb = item.y;
     const int c = min(64, ntot - tb);          // >= 1 by construction of the items
     const int g = 64 / c;
@@ -651,25 +857,42 @@ __global__ __launch_bounds__(64) void k_leaf(
     const double x = px[t], y = py[t];
     const double xs = x * inv2a, ys = y * inv2a;
     double acc = 0.0;
-    if (has_far && sub == 0) {
-        const double wx = (x - cx) * inv_alpha, wy = (y - cy) * inv_alpha;
-        const double yv = 0.25 * (wx * wx + wy * wy);
-        const double zx = wx * invR, zy = wy * invR;
-        double F1, F2;
-        f_start(yv, sc, nser, F1, F2);
-        double sr = 0.0, si = 0.0;
-        for (int m = p; m >= 1; --m) {
-            const double F0 = F1 + yv * F2 * cnn[m];
-            const double gm = F0 * invFY[m];
-            const double cr = Lb[2 * m - 1] * gm, ci = Lb[2 * m] * gm;
-            const double nr = sr * zx - si * zy + cr;
-            si = sr * zy + si * zx + ci;
-            sr = nr;
-            F2 = F1;
-            F1 = F0;
+    if (has_far) {
+        // the box's local coefficients and the level's tables, staged in LDS
+        // (the order loop below would otherwise wait on a scalar load per order)
+        double *t_L = dyn;                 // [2p+1]
+        double *t_cnn = t_L + 2 * p + 1;   // [p+1]
+        double *t_ify = t_cnn + p + 1;     // [p+1]
+        double *t_sc = t_ify + p + 1;      // [2 nser]
+        const double *Lb = Lc + b * Pp;
+        for (int i = lane; i < 2 * p + 1; i += 64) t_L[i] = Lb[i];
+        for (int i = lane; i < p + 1; i += 64) {
+            t_cnn[i] = cnn[i];
+            t_ify[i] = invFY[i];
         }
-        const double F0 = F1 + yv * F2 * cnn[0];
-        acc = Lb[0] * F0 * invFY[0] + 2.0 * (sr * zx - si * zy);
+        for (int i = lane; i < 2 * nser; i += 64) t_sc[i] = sc[i];
+        __syncthreads();
+        if (sub == 0) {
+            const double wx = (x - cx) * inv_alpha, wy = (y - cy) * inv_alpha;
+            const double yv = 0.25 * (wx * wx + wy * wy);
+            const double zx = wx * invR, zy = wy * invR;
+            double F1, F2;
+            f_start(yv, t_sc, nser, F1, F2);
+            double sr = 0.0, si = 0.0;
+#pragma unroll 4
+            for (int m = p; m >= 1; --m) {
+                const double F0 = F1 + yv * F2 * t_cnn[m];
+                const double gm = F0 * t_ify[m];
+                const double cr = t_L[2 * m - 1] * gm, ci = t_L[2 * m] * gm;
+                const double nr = sr * zx - si * zy + cr;
+                si = sr * zy + si * zx + ci;
+                sr = nr;
+                F2 = F1;
+                F1 = F0;
+            }
+            const double F0 = F1 + yv * F2 * t_cnn[0];
+            acc = t_L[0] * F0 * t_ify[0] + 2.0 * (sr * zx - si * zy);
+        }
     }
     using NearT = Near<NT, kSmallOnly, kF32>;
     typename NearT::acc_t near_q = 0, near_d = 0;
@@ -784,14 +1007,26 @@ void fmm_run(Context &ctx, FmmPlan &pl, const double *q, const double *dn, doubl
     const size_t lvl = (size_t)(p + 2);
     if (far) {
         // upward pass
-        const size_t sh = ((size_t)(p + 2) * 64 + 4 * Pp) * sizeof(double);
         {
         StageTimer tm(ctx, YK_STAGE_P2M);
-        hipLaunchKernelGGL(k_p2m, dim3((unsigned)((pl.nleaf + 3) / 4)), dim3(64), sh, ctx.stream, leaf_base,
-                           pl.nleaf, pl.lrange.p,
-                           pl.bcx.p, pl.bcy.p, pl.px.p, pl.py.p, qs, dns, pl.toff[1], has_q, has_d,
-                           inv_alpha, 1.0 / pl.lev[L].R, pl.invFY.p + L * lvl, pl.dipa.p + L * lvl,
-                           pl.dipb.p + L * lvl, pl.cnn.p, pl.serc.p, pl.nser, p, Pp, pl.M.p);
+        const size_t tabs = (2 * (size_t)pl.nser + 4 * (size_t)(p + 2)) * sizeof(double);
+        auto quad = p == 8 ? k_p2m_quad<8> : p == 12 ? k_p2m_quad<12> : p == 16 ? k_p2m_quad<16>
+                  : p == 20 ? k_p2m_quad<20> : p == 24 ? k_p2m_quad<24> : p == 28 ? k_p2m_quad<28>
+                  : p == 31 ? k_p2m_quad<31> : nullptr;
+        if (quad) {
+            hipLaunchKernelGGL(quad, dim3((unsigned)((pl.nleaf + 15) / 16)), dim3(64), tabs, ctx.stream,
+                               leaf_base, pl.nleaf, pl.lrange.p, pl.bcx.p, pl.bcy.p, pl.px.p, pl.py.p, qs,
+                               dns, pl.toff[1], has_q, has_d, inv_alpha, 1.0 / pl.lev[L].R,
+                               pl.invFY.p + L * lvl, pl.dipa.p + L * lvl, pl.dipb.p + L * lvl, pl.cnn.p,
+                               pl.serc.p, pl.nser, p, Pp, pl.M.p);
+        } else {
+            const size_t shp = ((size_t)(p + 2) * 64 + 4 * Pp) * sizeof(double) + tabs;
+            hipLaunchKernelGGL(k_p2m<0>, dim3((unsigned)((pl.nleaf + 3) / 4)), dim3(64), shp, ctx.stream,
+                               leaf_base, pl.nleaf, pl.lrange.p, pl.bcx.p, pl.bcy.p, pl.px.p, pl.py.p, qs,
+                               dns, pl.toff[1], has_q, has_d, inv_alpha, 1.0 / pl.lev[L].R,
+                               pl.invFY.p + L * lvl, pl.dipa.p + L * lvl, pl.dipb.p + L * lvl, pl.cnn.p,
+                               pl.serc.p, pl.nser, p, Pp, pl.M.p);
+        }
         check_launch(ctx, "k_p2m");
         }
         {
@@ -872,7 +1107,8 @@ void fmm_run(Context &ctx, FmmPlan &pl, const double *q, const double *dn, doubl
         const double tmax = 2.0 * pl.lev[L].side * pl.lev[L].side * inv_alpha * inv_alpha;
         LeafKernel kern = pick_leaf_kernel(pl.near_terms, tmax <= 1.0, prec == SUM_FP32);
         StageTimer tl(ctx, YK_STAGE_LEAF);
-        hipLaunchKernelGGL(kern, dim3(as.n_items), dim3(64), 0, ctx.stream, as.leaf_items.p,
+        const size_t lsh = (size_t)(2 * p + 1 + 2 * (p + 1) + 2 * pl.nser) * sizeof(double);
+        hipLaunchKernelGGL(kern, dim3(as.n_items), dim3(64), lsh, ctx.stream, as.leaf_items.p,
                            leaf_base, pl.lrange.p, pl.ulist_off.p, pl.ulist.p, pl.bcx.p, pl.bcy.p,
                            pl.px.p, pl.py.p, qs, dns, pl.toff[1], has_q, has_d, mask, far ? 1 : 0,
                            pl.Lc.p, inv_alpha, 1.0 / pl.lev[L].R, pl.invFY.p + L * lvl, pl.cnn.p,
