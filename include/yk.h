@@ -62,7 +62,9 @@ typedef struct {
     int leaf_size;          /* target mean number of points per leaf box */
     int direct;             /* 1 = all sums by O(N^2) direct summation */
     int gmres_m;            /* Krylov dimension before a restart */
-    int debug_flags;        /* bit0: synchronise and check after every kernel */
+    int debug_flags;        /* bit0: synchronise and check after every kernel;
+                               bit1: run the near field on the context's stream
+                               (no overlap with the far field; for timing) */
 } yk_options;
 
 typedef struct {
@@ -237,7 +239,9 @@ yk_status yk_ws_loss_grad(yk_ws ws, int64_t rows, const float *X, const float *t
  * used by the density solve; 2 = the stand-alone sum calls) and the work of
  * its last evaluation: near-field pairs and M2L translations.
  * yk_timing_enable: when on, every FMM stage is bracketed by HIP events on
- * the context's stream; yk_timing_read returns the accumulated milliseconds
+ * the stream it runs on (the near field, YK_STAGE_LEAF, runs on a second
+ * stream of the context concurrently with the far-field stages, unless
+ * debug_flags bit 1 is set; its time then includes the sharing of the GPU); yk_timing_read returns the accumulated milliseconds
  * and launch counts per stage (YK_STAGE_*), resolving the events, and resets
  * the counters when `reset` is non-zero.  Reading synchronises the stream.
  */
@@ -258,7 +262,7 @@ typedef struct {
 enum {
     YK_STAGE_GATHER = 0, YK_STAGE_P2M = 1, YK_STAGE_M2M = 2, YK_STAGE_M2L = 3,
     YK_STAGE_L2L = 4, YK_STAGE_LEAF = 5, YK_STAGE_SCATTER = 6, YK_STAGE_DIRECT = 7,
-    YK_NUM_STAGES = 8
+    YK_STAGE_L2P = 8, YK_NUM_STAGES = 9
 };
 
 yk_status yk_plan_info_get(yk_ctx ctx, int slot, yk_plan_info *info);

@@ -15,7 +15,7 @@ void check_launch(Context &ctx, const char *what) {
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) throw Error{YK_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e)};
     if (ctx.opt.debug_flags & 1) {
-        e = hipStreamSynchronize(ctx.stream);
+        e = hipDeviceSynchronize();
         if (e != hipSuccess) throw Error{YK_ERR_HIP, std::string(what) + " (sync): " + hipGetErrorString(e)};
     }
 }
@@ -26,6 +26,16 @@ Context::~Context() {
         (void)hipEventDestroy(pe.second.second);
     }
     for (hipEvent_t e : event_pool) (void)hipEventDestroy(e);
+    if (ev_fork) (void)hipEventDestroy(ev_fork);
+    if (ev_join) (void)hipEventDestroy(ev_join);
+    if (side) (void)hipStreamDestroy(side);
+}
+
+void ensure_side_stream(Context &ctx) {
+    if (ctx.side) return;
+    YK_HIP(hipStreamCreateWithFlags(&ctx.side, hipStreamNonBlocking));
+    YK_HIP(hipEventCreateWithFlags(&ctx.ev_fork, hipEventDisableTiming));
+    YK_HIP(hipEventCreateWithFlags(&ctx.ev_join, hipEventDisableTiming));
 }
 
 static hipEvent_t take_event(Context &ctx) {
@@ -39,22 +49,23 @@ static hipEvent_t take_event(Context &ctx) {
     return e;
 }
 
-StageTimer::StageTimer(Context &c, int s) : ctx(c), stage(s) {
+StageTimer::StageTimer(Context &c, int s, hipStream_t on) : ctx(c), stage(s), st(on ? on : c.stream) {
     if (!ctx.timing) return;
     a = take_event(ctx);
     b = take_event(ctx);
-    YK_HIP(hipEventRecord(a, ctx.stream));
+    YK_HIP(hipEventRecord(a, st));
 }
 
 StageTimer::~StageTimer() {
     if (!a) return;
-    if (hipEventRecord(b, ctx.stream) == hipSuccess)
+    if (hipEventRecord(b, st) == hipSuccess)
         ctx.pending.push_back({stage, {a, b}});
 }
 
 void resolve_timings(Context &ctx) {
     if (ctx.pending.empty()) return;
     YK_HIP(hipStreamSynchronize(ctx.stream));
+    if (ctx.side) YK_HIP(hipStreamSynchronize(ctx.side));
     for (auto &pe : ctx.pending) {
         float ms = 0.f;
         YK_HIP(hipEventElapsedTime(&ms, pe.second.first, pe.second.second));

@@ -98,6 +98,7 @@ struct FmmPlan {
     DevBuf<int32_t> lrange;            // [nleaf][6] start/end per set (sorted positions)
     DevBuf<int32_t> ulist_off, ulist;  // CSR over leaves (leaf-local indices)
     std::vector<int32_t> h_lrange;     // host copy
+    DevBuf<int32_t> pleaf;             // [N] leaf (level-local index) of every sorted point
 
     // coefficients
     DevBuf<double> M, Lc;              // [nbox][Pp]

@@ -525,10 +525,21 @@ template <> struct Mfma<float> {
 // A workgroup owns 64 boxes (4 wavefronts x 16 columns) and walks the slots;
 // the slot's Pp x Pp operator is double-buffered in LDS and the gathered
 // source coefficients of the next slot are loaded while the current slot runs.
-// With P = 16 NB + 1 real coefficients (p a multiple of 8), index 0 is split
-// off: the matrix cores take the 16 NB x 16 NB block of indices 1..16 NB and
-// the vector units add row 0 and column 0 (a 64 x 64 padded product would
-// spend 40% more matrix-core work on padding).
+// With P = 16 NB + 1 real coefficients (p a multiple of 8), the last index
+// SP = 16 NB is split off: the matrix cores take the 16 NB x 16 NB block of
+// indices 0..SP-1 and the vector units add row SP and column SP (a padded
+// 16 (NB+1) product would spend 40% more matrix-core work on padding).
+//
+// Contraction order: lane group g (lane / 16) supplies, in the two matrix-core
+// steps of pair kp, the contraction indices 8 kp + 2 g and 8 kp + 2 g + 1, so
+// each lane loads its source coefficients as aligned pairs; the operator
+// fragments read from LDS follow the same order.
+typedef double yk_dpair __attribute__((ext_vector_type(2)));
+typedef float yk_fpair __attribute__((ext_vector_type(2)));
+template <typename TS> struct Pair2;
+template <> struct Pair2<double> { using type = yk_dpair; };
+template <> struct Pair2<float> { using type = yk_fpair; };
+
 template <typename T, typename TS, int PP, bool SPLIT_REQ>
 __global__ __launch_bounds__(256) void k_tile_gemm(const int4 *__restrict__ tiles, int tile0,
                                                    const int32_t *__restrict__ boxes, int nslot,
@@ -539,9 +550,14 @@ __global__ __launch_bounds__(256) void k_tile_gemm(const int4 *__restrict__ tile
                                                    int assign, double *__restrict__ out) {
     constexpr bool SPLIT = SPLIT_REQ && PP > 16;   // (the host never asks for PP = 16)
     constexpr int NB = SPLIT ? PP / 16 - 1 : PP / 16;   // 16-row blocks on the matrix cores
-    constexpr int OFF = SPLIT ? 1 : 0;                  // first index of the matrix-core block
-    constexpr int NKS = 4 * NB, NLD = PP * PP / 256;
+    constexpr int SP = 16 * NB;                         // split-off index (SPLIT only)
+    constexpr int NKP = 2 * NB;                         // contraction pairs
+    // operator pairs per thread (PP = 16: 128 pairs, half the threads load one)
+    constexpr int NL2 = PP * PP >= 512 ? PP * PP / 512 : 1;
+    constexpr int kPairs = PP * PP / 2;
     constexpr int kMaxSlot = 27;
+    using V2 = typename Pair2<TS>::type;
+    using T2 = typename Pair2<T>::type;
     __shared__ T As[2][PP * PP];
     __shared__ int32_t s_src[kMaxSlot * 64];
     using MF = Mfma<T>;
@@ -565,33 +581,43 @@ __global__ __launch_bounds__(256) void k_tile_gemm(const int4 *__restrict__ tile
 #pragma unroll
         for (int q = 0; q < 4; ++q) colacc[r][q] = T(0);
     const T *Olev = Op + (int64_t)(level + level_shift) * op_stride;
-    auto op_of = [&](int sl) -> const T * { return Olev + (size_t)slot_op[cls * nslot + sl] * PP * PP; };
+    auto op_of = [&](int sl) -> const T2 * {
+        return reinterpret_cast<const T2 *>(Olev + (size_t)slot_op[cls * nslot + sl] * PP * PP);
+    };
     // B fragment of a slot: unconditional loads (row 0 stands in for an empty
     // slot) and the empty slot's zeros selected when the fragment is consumed,
     // so the loads of the next slot stay in flight during the current one (a
     // select, not a product, so whatever row 0 holds never reaches the sums)
-    TS braw[NKS], b0raw = TS(0);
+    V2 braw[NKP];
+    TS bsraw = TS(0);
     bool bvalid = false;
-    T bcur[NKS], b0 = T(0), pre[NLD];
+    T bcur[2 * NKP], bs = T(0);
+    T2 pre[NL2];
     auto load_b = [&](int sl) {
         const int32_t sj = s_src[sl * 64 + jb];
         const TS *row = X + (int64_t)(sj >= 0 ? sj : 0) * PP;
+        const V2 *row2 = reinterpret_cast<const V2 *>(row) + g;
 #pragma unroll
-        for (int ks = 0; ks < NKS; ++ks) braw[ks] = row[OFF + 4 * ks + g];
-        if constexpr (SPLIT) b0raw = row[0];
+        for (int kp = 0; kp < NKP; ++kp) braw[kp] = row2[4 * kp];
+        if constexpr (SPLIT) bsraw = row[SP];
         bvalid = sj >= 0;
     };
     auto take_b = [&]() {
 #pragma unroll
-        for (int ks = 0; ks < NKS; ++ks) bcur[ks] = bvalid ? (T)braw[ks] : T(0);
-        if constexpr (SPLIT) b0 = bvalid ? (T)b0raw : T(0);
+        for (int kp = 0; kp < NKP; ++kp) {
+            bcur[2 * kp] = bvalid ? (T)braw[kp].x : T(0);
+            bcur[2 * kp + 1] = bvalid ? (T)braw[kp].y : T(0);
+        }
+        if constexpr (SPLIT) bs = bvalid ? (T)bsraw : T(0);
     };
     __syncthreads();
     load_b(0);
     {
-        const T *Tg = op_of(0);
+        const T2 *Tg = op_of(0);
+        T2 *Ad = reinterpret_cast<T2 *>(As[0]);
 #pragma unroll
-        for (int e = 0; e < NLD; ++e) As[0][tid + 256 * e] = Tg[tid + 256 * e];
+        for (int e = 0; e < NL2; ++e)
+            if (kPairs >= 256 * NL2 || tid + 256 * e < kPairs) Ad[tid + 256 * e] = Tg[tid + 256 * e];
     }
     take_b();
     __syncthreads();
@@ -600,33 +626,42 @@ __global__ __launch_bounds__(256) void k_tile_gemm(const int4 *__restrict__ tile
         const bool more = slot + 1 < nslot;
         if (more) {
             load_b(slot + 1);
-            const T *Tg = op_of(slot + 1);
+            const T2 *Tg = op_of(slot + 1);
 #pragma unroll
-            for (int e = 0; e < NLD; ++e) pre[e] = Tg[tid + 256 * e];
+            for (int e = 0; e < NL2; ++e)
+                if (kPairs >= 256 * NL2 || tid + 256 * e < kPairs) pre[e] = Tg[tid + 256 * e];
         }
-        // operator column-major: A[i][k] = As[k * PP + i]
-        const T *Ac = As[cur] + (OFF + g) * PP + OFF + (lane & 15);
+        // operator column-major: A[i][k] = As[k * PP + i]; step (kp, e) takes
+        // contraction index 8 kp + 2 g + e in lane group g
+        const T *Ac = As[cur] + 2 * g * PP + (lane & 15);
 #pragma unroll
-        for (int ks = 0; ks < NKS; ++ks) {
+        for (int kp = 0; kp < NKP; ++kp) {
 #pragma unroll
-            for (int rt = 0; rt < NB; ++rt)
-                acc[rt] = MF::step(Ac[4 * ks * PP + 16 * rt], bcur[ks], acc[rt]);
+            for (int e = 0; e < 2; ++e) {
+#pragma unroll
+                for (int rt = 0; rt < NB; ++rt)
+                    acc[rt] = MF::step(Ac[(8 * kp + e) * PP + 16 * rt], bcur[2 * kp + e], acc[rt]);
+            }
         }
         if constexpr (SPLIT) {
             const T *A = As[cur];
-            // row 0: this lane's share of sum_k A[0][k] b[k]; column 0 into the
-            // rows this lane holds of the matrix-core result
+            // row SP: this lane's share of sum_k A[SP][k] b[k]; column SP into
+            // the rows this lane holds of the matrix-core result
 #pragma unroll
-            for (int ks = 0; ks < NKS; ++ks) rowacc += A[(OFF + 4 * ks + g) * PP] * bcur[ks];
-            if (g == 0) rowacc += A[0] * b0;
+            for (int kp = 0; kp < NKP; ++kp)
+#pragma unroll
+                for (int e = 0; e < 2; ++e) rowacc += A[(8 * kp + 2 * g + e) * PP + SP] * bcur[2 * kp + e];
+            if (g == 0) rowacc += A[SP * PP + SP] * bs;
 #pragma unroll
             for (int rt = 0; rt < NB; ++rt)
 #pragma unroll
-                for (int q = 0; q < 4; ++q) colacc[rt][q] += A[OFF + 16 * rt + MF::row(lane, q)] * b0;
+                for (int q = 0; q < 4; ++q) colacc[rt][q] += A[SP * PP + 16 * rt + MF::row(lane, q)] * bs;
         }
         if (more) {
+            T2 *Ad = reinterpret_cast<T2 *>(As[cur ^ 1]);
 #pragma unroll
-            for (int e = 0; e < NLD; ++e) As[cur ^ 1][tid + 256 * e] = pre[e];
+            for (int e = 0; e < NL2; ++e)
+                if (kPairs >= 256 * NL2 || tid + 256 * e < kPairs) Ad[tid + 256 * e] = pre[e];
             take_b();
         }
         __syncthreads();
@@ -641,15 +676,15 @@ __global__ __launch_bounds__(256) void k_tile_gemm(const int4 *__restrict__ tile
         for (int rt = 0; rt < NB; ++rt)
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                const int i = OFF + 16 * rt + MF::row(lane, q);
+                const int i = 16 * rt + MF::row(lane, q);
                 const double v = SPLIT ? (double)acc[rt][q] + (double)colacc[rt][q] : (double)acc[rt][q];
                 o[i] = assign ? v : o[i] + v;
             }
         if constexpr (SPLIT) {
-            if (g == 0) o[0] = assign ? (double)rowacc : o[0] + (double)rowacc;
-            // padding entries 16 NB + 1 .. PP - 1 stay zero for later readers
+            if (g == 0) o[SP] = assign ? (double)rowacc : o[SP] + (double)rowacc;
+            // padding entries SP + 1 .. PP - 1 stay zero for later readers
             if (assign)
-                for (int i = OFF + 16 * NB + g; i < PP; i += 4) o[i] = 0.0;
+                for (int i = SP + 1 + g; i < PP; i += 4) o[i] = 0.0;
         }
     }
 }
@@ -684,6 +719,72 @@ void launch_tile_gemm(Context &ctx, int P, int Pp, int ntiles, const int4 *tiles
 #undef YK_TILE_CASE
     check_launch(ctx, "k_tile_gemm");
 }
+
+// Small levels of M2M (4 child slots) and L2L (1 parent slot): one wavefront
+// per box, all source rows staged in LDS at once and every operator load of a
+// thread issued from one unrolled loop.  (The tile GEMM chains one memory
+// round trip per slot, which dominates when a level has few boxes.)  Padding
+// rows and columns of the operators and of the coefficient vectors are zero.
+template <int PP, int NS>
+__global__ __launch_bounds__(64) void k_small_gemv(
+    const int32_t *__restrict__ boxes, int64_t box0, const int32_t *__restrict__ src,
+    const uint32_t *__restrict__ bcode, const double *__restrict__ Op, const double *__restrict__ X,
+    int P, int assign, double *__restrict__ out) {
+    __shared__ double xs[NS][PP];
+    const int64_t box = boxes ? (int64_t)boxes[blockIdx.x] : box0 + blockIdx.x;
+    const int i = threadIdx.x;
+    int sj[NS];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) sj[s] = src[box * NS + s];
+    const int cls = NS == 1 ? (int)(bcode[box] & 3u) : 0;
+#pragma unroll
+    for (int s = 0; s < NS; ++s)
+        for (int k = i; k < PP; k += 64) xs[s][k] = sj[s] >= 0 ? X[(int64_t)sj[s] * PP + k] : 0.0;
+    __syncthreads();
+    if (i >= PP) return;
+    double acc0 = 0.0, acc1 = 0.0;
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        if (sj[s] < 0) continue;
+        const double *A = Op + (size_t)(NS == 1 ? cls : s) * PP * PP + i;
+#pragma unroll
+        for (int k = 0; k < PP; k += 2) {
+            acc0 = __builtin_fma(A[(size_t)k * PP], xs[s][k], acc0);
+            acc1 = __builtin_fma(A[(size_t)(k + 1) * PP], xs[s][k + 1], acc1);
+        }
+    }
+    const double acc = i < P ? acc0 + acc1 : 0.0;
+    double *o = out + box * PP + i;
+    *o = assign ? acc : *o + acc;
+}
+
+void launch_small_gemv(Context &ctx, int Pp, int ns, int64_t nbox, const int32_t *boxes, int64_t box0,
+                       const int32_t *src, const uint32_t *bcode, const double *Op, const double *X,
+                       int P, int assign, double *out) {
+    if (nbox <= 0) return;
+#define YK_SMALL_CASE(PPV)                                                                         \
+    case PPV:                                                                                      \
+        if (ns == 1)                                                                               \
+            hipLaunchKernelGGL((k_small_gemv<PPV, 1>), dim3((unsigned)nbox), dim3(64), 0, ctx.stream, \
+                               boxes, box0, src, bcode, Op, X, P, assign, out);                    \
+        else                                                                                       \
+            hipLaunchKernelGGL((k_small_gemv<PPV, 4>), dim3((unsigned)nbox), dim3(64), 0, ctx.stream, \
+                               boxes, box0, src, bcode, Op, X, P, assign, out);                    \
+        break;
+    switch (Pp) {
+        YK_SMALL_CASE(16)
+        YK_SMALL_CASE(32)
+        YK_SMALL_CASE(48)
+        YK_SMALL_CASE(64)
+        default:
+            throw Error{YK_ERR_INTERNAL, "no small-level kernel for this padded order"};
+    }
+#undef YK_SMALL_CASE
+    check_launch(ctx, "k_small_gemv");
+}
+
+// levels with at most this many boxes take k_small_gemv for M2M and L2L
+constexpr int64_t kSmallLevel = 4096;
 
 __global__ void k_to_float(int64_t n, const double *__restrict__ a, float *__restrict__ b) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -791,31 +892,24 @@ struct Near {
 // and walks every g-th source of the leaf's U list, so at most c - 1 lanes
 // idle.  U-list sources are staged into LDS (scaled coordinates and strengths)
 // in chunks of kLeafStage; the group partial sums are combined through LDS at
-// the end.  The local expansion is evaluated by the first group (Horner in z
-// with G_m = F_m(y)/F_m(Y)).
+// the end.  The result is the near field alone (k_l2p adds the far field).
 constexpr int kLeafStage = 192;
 
 template <int NT, bool kSmallOnly, bool kF32 = false>
 __global__ __launch_bounds__(64) void k_leaf(
     const int2 *__restrict__ items, int64_t leaf_base, const int32_t *__restrict__ lrange,
     const int32_t *__restrict__ uoff, const int32_t *__restrict__ ulist,
-    const double *__restrict__ bcx, const double *__restrict__ bcy, const double *__restrict__ px,
-    const double *__restrict__ py, const double *__restrict__ qs, const double *__restrict__ dns,
-    int64_t off1, int has_q, int has_d, int mask, int has_far, const double *__restrict__ Lc,
-    double inv_alpha, double invR, const double *__restrict__ invFY,
-    const double *__restrict__ cnn, const double *__restrict__ sc, int nser, int p, int Pp,
-    double inv2a, double dip_scale, double *__restrict__ outs) {
+    const double *__restrict__ px, const double *__restrict__ py, const double *__restrict__ qs,
+    const double *__restrict__ dns, int64_t off1, int has_q, int has_d, int mask, double inv2a,
+    double dip_scale, double *__restrict__ outs) {
     __shared__ double s_x[kLeafStage], s_y[kLeafStage], s_a[kLeafStage], s_b[kLeafStage];
     __shared__ double2 s_log[YK_LOG_TAB];
     __shared__ int qa[9], qn[9], da[9], dn_[9];
-    extern __shared__ double dyn[];
     const int2 item = items[xcd_remap(blockIdx.x, gridDim.x)];
     const int li = item.x;
-    const int64_t b = leaf_base + li;
     const int lane = threadIdx.x;
     if constexpr (!kF32)
         for (int i = lane; i < YK_LOG_TAB; i += 64) s_log[i] = make_double2(yk_log_tab[2 * i], yk_log_tab[2 * i + 1]);
-    const double cx = bcx[b], cy = bcy[b];
     int rs[3], re[3], ntot = 0;
     for (int s = 0; s < 3; ++s) {
         rs[s] = lrange[li * 6 + 2 * s];
@@ -856,44 +950,6 @@ __global__ __launch_bounds__(64) void k_leaf(
     }
     const double x = px[t], y = py[t];
     const double xs = x * inv2a, ys = y * inv2a;
-    double acc = 0.0;
-    if (has_far) {
-        // the box's local coefficients and the level's tables, staged in LDS
-        // (the order loop below would otherwise wait on a scalar load per order)
-        double *t_L = dyn;                 // [2p+1]
-        double *t_cnn = t_L + 2 * p + 1;   // [p+1]
-        double *t_ify = t_cnn + p + 1;     // [p+1]
-        double *t_sc = t_ify + p + 1;      // [2 nser]
-        const double *Lb = Lc + b * Pp;
-        for (int i = lane; i < 2 * p + 1; i += 64) t_L[i] = Lb[i];
-        for (int i = lane; i < p + 1; i += 64) {
-            t_cnn[i] = cnn[i];
-            t_ify[i] = invFY[i];
-        }
-        for (int i = lane; i < 2 * nser; i += 64) t_sc[i] = sc[i];
-        __syncthreads();
-        if (sub == 0) {
-            const double wx = (x - cx) * inv_alpha, wy = (y - cy) * inv_alpha;
-            const double yv = 0.25 * (wx * wx + wy * wy);
-            const double zx = wx * invR, zy = wy * invR;
-            double F1, F2;
-            f_start(yv, t_sc, nser, F1, F2);
-            double sr = 0.0, si = 0.0;
-#pragma unroll 4
-            for (int m = p; m >= 1; --m) {
-                const double F0 = F1 + yv * F2 * t_cnn[m];
-                const double gm = F0 * t_ify[m];
-                const double cr = t_L[2 * m - 1] * gm, ci = t_L[2 * m] * gm;
-                const double nr = sr * zx - si * zy + cr;
-                si = sr * zy + si * zx + ci;
-                sr = nr;
-                F2 = F1;
-                F1 = F0;
-            }
-            const double F0 = F1 + yv * F2 * t_cnn[0];
-            acc = t_L[0] * F0 * t_ify[0] + 2.0 * (sr * zx - si * zy);
-        }
-    }
     using NearT = Near<NT, kSmallOnly, kF32>;
     typename NearT::acc_t near_q = 0, near_d = 0;
     for (int set = 0; set < 2; ++set) {
@@ -947,7 +1003,7 @@ __global__ __launch_bounds__(64) void k_leaf(
     s_x[lane] = valid ? (double)near_q + dip_scale * (double)near_d : 0.0;
     __syncthreads();
     if (sub == 0) {
-        double tot = acc;
+        double tot = 0.0;
         for (int gi = 0; gi < g; ++gi) tot += s_x[ti + gi * c];
         outs[t] = tot * kInv2Pi;
     }
@@ -955,9 +1011,53 @@ __global__ __launch_bounds__(64) void k_leaf(
 
 using LeafKernel = void (*)(const int2 *, int64_t, const int32_t *, const int32_t *,
                             const int32_t *, const double *, const double *, const double *,
-                            const double *, const double *, const double *, int64_t, int, int, int,
-                            int, const double *, double, double, const double *, const double *,
-                            const double *, int, int, int, double, double, double *);
+                            const double *, int64_t, int, int, int, double, double, double *);
+
+// L2P: one thread per target point, adding the local expansion of the
+// point's leaf (Horner in z with G_m = F_m(y)/F_m(Y), F_m downwards) to the
+// near-field sum already in outs.  The level's tables are staged in LDS.
+__global__ __launch_bounds__(256) void k_l2p(
+    int64_t n, int64_t toff1, int64_t toff2, int mask, const int32_t *__restrict__ pleaf,
+    int64_t leaf_base, const double *__restrict__ bcx, const double *__restrict__ bcy,
+    const double *__restrict__ px, const double *__restrict__ py, const double *__restrict__ Lc,
+    double inv_alpha, double invR, const double *__restrict__ invFY, const double *__restrict__ cnn,
+    const double *__restrict__ sc, int nser, int p, int Pp, double *__restrict__ outs) {
+    extern __shared__ double dyn[];
+    double *t_cnn = dyn;               // [p+1]
+    double *t_ify = t_cnn + p + 1;     // [p+1]
+    double *t_sc = t_ify + p + 1;      // [2 nser]
+    for (int i = threadIdx.x; i < p + 1; i += blockDim.x) {
+        t_cnn[i] = cnn[i];
+        t_ify[i] = invFY[i];
+    }
+    for (int i = threadIdx.x; i < 2 * nser; i += blockDim.x) t_sc[i] = sc[i];
+    __syncthreads();
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    const int set = (t >= toff1) + (t >= toff2);
+    if (!((mask >> set) & 1)) return;
+    const int64_t b = leaf_base + pleaf[t];
+    const double *Lb = Lc + b * Pp;
+    const double wx = (px[t] - bcx[b]) * inv_alpha, wy = (py[t] - bcy[b]) * inv_alpha;
+    const double yv = 0.25 * (wx * wx + wy * wy);
+    const double zx = wx * invR, zy = wy * invR;
+    double F1, F2;
+    f_start(yv, t_sc, nser, F1, F2);
+    double sr = 0.0, si = 0.0;
+#pragma unroll 4
+    for (int m = p; m >= 1; --m) {
+        const double F0 = F1 + yv * F2 * t_cnn[m];
+        const double gm = F0 * t_ify[m];
+        const double cr = Lb[2 * m - 1] * gm, ci = Lb[2 * m] * gm;
+        const double nr = sr * zx - si * zy + cr;
+        si = sr * zy + si * zx + ci;
+        sr = nr;
+        F2 = F1;
+        F1 = F0;
+    }
+    const double F0 = F1 + yv * F2 * t_cnn[0];
+    outs[t] += (Lb[0] * F0 * t_ify[0] + 2.0 * (sr * zx - si * zy)) * kInv2Pi;
+}
 
 LeafKernel pick_leaf_kernel(int nt, bool small_only, bool f32) {
     if (f32) return small_only ? k_leaf<8, true, true> : k_leaf<8, false, true>;
@@ -1004,6 +1104,31 @@ void fmm_run(Context &ctx, FmmPlan &pl, const double *q, const double *dn, doubl
     ActiveSet &as = get_active(ctx, pl, mask);
     const bool far = pl.lmin <= L && (has_q || has_d);
     const int64_t leaf_base = pl.lev[L].begin;
+
+    // near field: independent of the far field until L2P, so it runs on the
+    // side stream while M2M, M2L and L2L run on the main one (forked after P2M,
+    // which would otherwise be starved of compute units)
+    const bool overlap = !(ctx.opt.debug_flags & 2);
+    bool near_done = false;
+    auto launch_near = [&]() {
+        near_done = true;
+        if (overlap) {
+            ensure_side_stream(ctx);
+            YK_HIP(hipEventRecord(ctx.ev_fork, ctx.stream));
+            YK_HIP(hipStreamWaitEvent(ctx.side, ctx.ev_fork, 0));
+        }
+        hipStream_t near_stream = overlap ? ctx.side : ctx.stream;
+        if (as.n_leaves > 0) {
+            const double tmax = 2.0 * pl.lev[L].side * pl.lev[L].side * inv_alpha * inv_alpha;
+            LeafKernel kern = pick_leaf_kernel(pl.near_terms, tmax <= 1.0, prec == SUM_FP32);
+            StageTimer tl(ctx, YK_STAGE_LEAF, near_stream);
+            hipLaunchKernelGGL(kern, dim3(as.n_items), dim3(64), 0, near_stream, as.leaf_items.p,
+                               leaf_base, pl.lrange.p, pl.ulist_off.p, pl.ulist.p, pl.px.p, pl.py.p, qs,
+                               dns, pl.toff[1], has_q, has_d, mask, 0.5 * inv_alpha, 0.5 * inv_alpha, outs);
+            check_launch(ctx, "k_leaf");
+        }
+        if (overlap) YK_HIP(hipEventRecord(ctx.ev_join, ctx.side));
+    };
     const size_t lvl = (size_t)(p + 2);
     if (far) {
         // upward pass
@@ -1029,17 +1154,21 @@ void fmm_run(Context &ctx, FmmPlan &pl, const double *q, const double *dn, doubl
         }
         check_launch(ctx, "k_p2m");
         }
+        launch_near();
         {
             StageTimer tmm(ctx, YK_STAGE_M2M);
             for (int l = L - 1; l >= pl.lmin; --l) {
-                if (Pp <= 64) {
+                const int64_t nbl = pl.lev[l].end - pl.lev[l].begin;
+                if (Pp <= 64 && nbl <= kSmallLevel) {
+                    launch_small_gemv(ctx, Pp, 4, nbl, nullptr, pl.lev[l].begin, pl.child4.p, pl.bcode.p,
+                                      pl.m2m.p + (size_t)l * 4 * Pp * Pp, pl.M.p, P, 1, pl.M.p);
+                } else if (Pp <= 64) {
                     // M2M on matrix cores: 4 child slots, operators S[l][position]
                     launch_tile_gemm<double, double>(ctx, P, Pp, pl.up_tile_count[l], pl.up_tiles.p,
                                                      pl.up_tile_begin[l], pl.up_boxes.p, 4, pl.child4.p,
                                                      pl.iota4.p, pl.m2m.p, (int64_t)4 * Pp * Pp, 0, pl.M.p,
                                                      1, pl.M.p);
                 } else {
-                    const int64_t nbl = pl.lev[l].end - pl.lev[l].begin;
                     hipLaunchKernelGGL(k_m2m, dim3(nbl), dim3(128), Pp * sizeof(double), ctx.stream,
                                        pl.lev[l].begin, pl.fchild.p, pl.nchild.p, pl.bcode.p,
                                        pl.m2m.p + (size_t)l * 4 * Pp * Pp, P, Pp, pl.M.p);
@@ -1072,7 +1201,11 @@ void fmm_run(Context &ctx, FmmPlan &pl, const double *q, const double *dn, doubl
             StageTimer tl2(ctx, YK_STAGE_L2L);
             for (int l = pl.lmin + 1; l <= L; ++l) {
                 // L2L top-down: one parent slot, operator E[l-1][position]
-                if (f32)
+                if (as.l2l_count[l] <= kSmallLevel) {
+                    launch_small_gemv(ctx, Pp, 1, as.l2l_count[l], as.l2l_boxes.p + as.l2l_begin[l], 0,
+                                      pl.bparent.p, pl.bcode.p, pl.l2l.p + (size_t)(l - 1) * 4 * Pp * Pp,
+                                      pl.Lc.p, P, 0, pl.Lc.p);
+                } else if (f32)
                     launch_tile_gemm<float, double>(ctx, P, Pp, as.tile_count[l], as.m2l_tiles.p,
                                                     as.tile_begin[l], as.m2l_boxes.p, 1, pl.bparent.p,
                                                     pl.iota4.p, pl.l2lf.p, (int64_t)4 * Pp * Pp, -1, pl.Lc.p,
@@ -1103,17 +1236,16 @@ void fmm_run(Context &ctx, FmmPlan &pl, const double *q, const double *dn, doubl
             }
         }
     }
-    if (as.n_leaves > 0) {
-        const double tmax = 2.0 * pl.lev[L].side * pl.lev[L].side * inv_alpha * inv_alpha;
-        LeafKernel kern = pick_leaf_kernel(pl.near_terms, tmax <= 1.0, prec == SUM_FP32);
-        StageTimer tl(ctx, YK_STAGE_LEAF);
-        const size_t lsh = (size_t)(2 * p + 1 + 2 * (p + 1) + 2 * pl.nser) * sizeof(double);
-        hipLaunchKernelGGL(kern, dim3(as.n_items), dim3(64), lsh, ctx.stream, as.leaf_items.p,
-                           leaf_base, pl.lrange.p, pl.ulist_off.p, pl.ulist.p, pl.bcx.p, pl.bcy.p,
-                           pl.px.p, pl.py.p, qs, dns, pl.toff[1], has_q, has_d, mask, far ? 1 : 0,
+    if (!near_done) launch_near();
+    if (overlap) YK_HIP(hipStreamWaitEvent(ctx.stream, ctx.ev_join, 0));
+    if (far && as.n_leaves > 0) {
+        StageTimer tl(ctx, YK_STAGE_L2P);
+        const size_t lsh = (size_t)(2 * (p + 1) + 2 * pl.nser) * sizeof(double);
+        hipLaunchKernelGGL(k_l2p, dim3(nblk(pl.N, 256)), dim3(256), lsh, ctx.stream, pl.N, pl.toff[1],
+                           pl.toff[2], mask, pl.pleaf.p, leaf_base, pl.bcx.p, pl.bcy.p, pl.px.p, pl.py.p,
                            pl.Lc.p, inv_alpha, 1.0 / pl.lev[L].R, pl.invFY.p + L * lvl, pl.cnn.p,
-                           pl.serc.p, pl.nser, p, Pp, 0.5 * inv_alpha, 0.5 * inv_alpha, outs);
-        check_launch(ctx, "k_leaf");
+                           pl.serc.p, pl.nser, p, Pp, outs);
+        check_launch(ctx, "k_l2p");
     }
     StageTimer tsc(ctx, YK_STAGE_SCATTER);
     for (int s = 0; s < 3; ++s) {

@@ -351,6 +351,14 @@ void build_lists_and_tables(Context &ctx, FmmPlan &pl, const std::vector<uint32_
     }
     up(pl.vlist, vl);
     up(pl.lrange, pl.h_lrange);
+    {
+        std::vector<int32_t> hp((size_t)pl.N, 0);
+        for (int64_t li = 0; li < pl.nleaf; ++li)
+            for (int s = 0; s < 3; ++s)
+                for (int32_t t = pl.h_lrange[(size_t)li * 6 + 2 * s]; t < pl.h_lrange[(size_t)li * 6 + 2 * s + 1]; ++t)
+                    hp[(size_t)t] = (int32_t)li;
+        up(pl.pleaf, hp);
+    }
     up(pl.ulist_off, uoff);
     up(pl.ulist, ul);
 

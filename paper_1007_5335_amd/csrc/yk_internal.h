@@ -112,6 +112,11 @@ struct Context {
     struct WarmStart *warm = nullptr;       // attached learned warm start (not owned)
     DevBuf<double> ws_g, ws_ml, ws_t;       // heat-step buffers of the guess selection
 
+    // second stream for the near field (overlaps the far-field chain) and the
+    // fork/join events that order it against the context's stream
+    hipStream_t side = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+
     // optional per-stage event timing
     bool timing = false;
     std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> pending;
@@ -125,11 +130,14 @@ struct Context {
 struct StageTimer {
     Context &ctx;
     int stage;
+    hipStream_t st;
     hipEvent_t a = nullptr, b = nullptr;
-    StageTimer(Context &c, int s);
+    StageTimer(Context &c, int s, hipStream_t on = nullptr);
     ~StageTimer();
 };
 void resolve_timings(Context &ctx);
+// creates the side stream and its events on first use
+void ensure_side_stream(Context &ctx);
 
 // ---------------------------------------------------------------- kernels ---
 // Direct sums (FP64): out[i] (+)= sum_j q_j K0/(2pi) + sum_j (x_i - y_j).dn_j K1(z)/(alpha^2 z)/(2pi)

@@ -40,7 +40,7 @@ EXPORTS = (
     "yk_ws_set_params", "yk_ws_loss_grad",
 )
 
-STAGES = ("gather", "p2m", "m2m", "m2l", "l2l", "leaf", "scatter", "direct")
+STAGES = ("gather", "p2m", "m2m", "m2l", "l2l", "leaf", "scatter", "direct", "l2p")
 
 
 class yk_options(ctypes.Structure):
