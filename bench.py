@@ -212,7 +212,7 @@ def heat_step_bench(args, yk, torch, W):
             B = torch.empty_like(u)
             un = torch.empty_like(u)
             sig = torch.zeros(b.n, dtype=torch.float64, device="cuda")
-            times, iters, res0, used, train_s = [], [], [], [], None
+            times, iters, res0, used, train_s, phases = [], [], [], [], None, []
             for step in range(1, n_steps + 1):
                 if ws is not None and step == half + 1:
                     torch.cuda.synchronize()
@@ -230,6 +230,7 @@ def heat_step_bench(args, yk, torch, W):
                     iters.append(st.iters)
                     res0.append(st.res0)
                     used.append(st.guess_used == 2)
+                    phases.append([st.ms[1], st.ms[4], st.ms[2], st.ms[3]])
                 u, un = un, u
             finals[name] = u.cpu().numpy()
         finally:
@@ -239,7 +240,9 @@ def heat_step_bench(args, yk, torch, W):
         out[name] = {"s_per_step": float(np.mean(times)), "gmres_iters": float(np.mean(iters)),
                      "initial_rel_residual": float(np.mean(res0)),
                      "learned_guess_used": float(np.mean(used)) if learned else None,
-                     "train_s": train_s}
+                     "train_s": train_s,
+                     "phase_ms": dict(zip(("volume_to_nodes", "guess_selection", "density_solve",
+                                           "volume_assembly"), np.mean(phases, axis=0).tolist()))}
     ref = finals["fp64"]
     for name in finals:
         out[name]["u_rel_diff_vs_fp64"] = float(np.max(np.abs(finals[name] - ref)) / np.max(np.abs(ref)))

@@ -547,7 +547,7 @@ __global__ __launch_bounds__(256) void k_tile_gemm(const int4 *__restrict__ tile
                                                    const int32_t *__restrict__ slot_op,
                                                    const T *__restrict__ Op, int64_t op_stride,
                                                    int level_shift, const TS *__restrict__ X,
-                                                   int assign, double *__restrict__ out) {
+                                                   int assign, int nparts, double *__restrict__ out) {
     constexpr bool SPLIT = SPLIT_REQ && PP > 16;   // (the host never asks for PP = 16)
     constexpr int NB = SPLIT ? PP / 16 - 1 : PP / 16;   // 16-row blocks on the matrix cores
     constexpr int SP = 16 * NB;                         // split-off index (SPLIT only)
@@ -561,14 +561,19 @@ __global__ __launch_bounds__(256) void k_tile_gemm(const int4 *__restrict__ tile
     __shared__ T As[2][PP * PP];
     __shared__ int32_t s_src[kMaxSlot * 64];
     using MF = Mfma<T>;
-    const int4 tl = tiles[tile0 + xcd_remap(blockIdx.x, gridDim.x)];
+    // nparts > 1 (few tiles): the slots of a tile are shared among nparts
+    // workgroups, which add their partial sums atomically (assign must be 0)
+    const int bid = xcd_remap(blockIdx.x, gridDim.x);
+    const int part = bid % nparts;
+    const int4 tl = tiles[tile0 + bid / nparts];
     const int level = tl.x, cls = tl.y, start = tl.z, count = tl.w;
+    const int sl0 = part * nslot / nparts, sl1 = (part + 1) * nslot / nparts;
     const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, g = lane >> 4;
     const int jb = 16 * w + (lane & 15);
     const bool colvalid = jb < count;
     const int64_t boxj = colvalid ? boxes[start + jb] : -1;
     // source box of every (slot, column) of the tile, -1 where empty
-    for (int e = tid; e < nslot * 64; e += 256) {
+    for (int e = sl0 * 64 + tid; e < sl1 * 64; e += 256) {
         const int sl = e >> 6, j = e & 63;
         s_src[e] = j < count ? src[(int64_t)boxes[start + j] * nslot + sl] : -1;
     }
@@ -611,9 +616,9 @@ __global__ __launch_bounds__(256) void k_tile_gemm(const int4 *__restrict__ tile
         if constexpr (SPLIT) bs = bvalid ? (T)bsraw : T(0);
     };
     __syncthreads();
-    load_b(0);
+    load_b(sl0);
     {
-        const T2 *Tg = op_of(0);
+        const T2 *Tg = op_of(sl0);
         T2 *Ad = reinterpret_cast<T2 *>(As[0]);
 #pragma unroll
         for (int e = 0; e < NL2; ++e)
@@ -621,9 +626,9 @@ __global__ __launch_bounds__(256) void k_tile_gemm(const int4 *__restrict__ tile
     }
     take_b();
     __syncthreads();
-    for (int slot = 0; slot < nslot; ++slot) {
-        const int cur = slot & 1;
-        const bool more = slot + 1 < nslot;
+    for (int slot = sl0; slot < sl1; ++slot) {
+        const int cur = (slot - sl0) & 1;
+        const bool more = slot + 1 < sl1;
         if (more) {
             load_b(slot + 1);
             const T2 *Tg = op_of(slot + 1);
@@ -678,10 +683,14 @@ __global__ __launch_bounds__(256) void k_tile_gemm(const int4 *__restrict__ tile
             for (int q = 0; q < 4; ++q) {
                 const int i = 16 * rt + MF::row(lane, q);
                 const double v = SPLIT ? (double)acc[rt][q] + (double)colacc[rt][q] : (double)acc[rt][q];
-                o[i] = assign ? v : o[i] + v;
+                if (nparts > 1) atomicAdd(o + i, v);
+                else o[i] = assign ? v : o[i] + v;
             }
         if constexpr (SPLIT) {
-            if (g == 0) o[SP] = assign ? (double)rowacc : o[SP] + (double)rowacc;
+            if (g == 0) {
+                if (nparts > 1) atomicAdd(o + SP, (double)rowacc);
+                else o[SP] = assign ? (double)rowacc : o[SP] + (double)rowacc;
+            }
             // padding entries SP + 1 .. PP - 1 stay zero for later readers
             if (assign)
                 for (int i = SP + 1 + g; i < PP; i += 4) o[i] = 0.0;
@@ -697,16 +706,20 @@ void launch_tile_gemm(Context &ctx, int P, int Pp, int ntiles, const int4 *tiles
     if (ntiles <= 0) return;
     if (nslot < 1 || nslot > 27) throw Error{YK_ERR_INTERNAL, "tile GEMM supports 1..27 slots"};
     const bool split = Pp >= 32 && P == Pp - 15;
+    // fewer tiles than compute units: share each tile's slots among up to 7
+    // workgroups (about 4 slots each) that accumulate atomically
+    const int nparts = (!assign && nslot >= 8 && ntiles < 256) ? std::min(7, (512 + ntiles - 1) / ntiles) : 1;
+    const unsigned grid = (unsigned)ntiles * (unsigned)nparts;
 #define YK_TILE_CASE(PPV)                                                                          \
     case PPV:                                                                                      \
         if (split)                                                                                 \
-            hipLaunchKernelGGL((k_tile_gemm<T, TS, PPV, true>), dim3(ntiles), dim3(256), 0,       \
+            hipLaunchKernelGGL((k_tile_gemm<T, TS, PPV, true>), dim3(grid), dim3(256), 0,         \
                                ctx.stream, tiles, tile0, boxes, nslot, src, slot_op, Op, op_stride, \
-                               level_shift, X, assign, out);                                      \
+                               level_shift, X, assign, nparts, out);                              \
         else                                                                                       \
-            hipLaunchKernelGGL((k_tile_gemm<T, TS, PPV, false>), dim3(ntiles), dim3(256), 0,      \
+            hipLaunchKernelGGL((k_tile_gemm<T, TS, PPV, false>), dim3(grid), dim3(256), 0,        \
                                ctx.stream, tiles, tile0, boxes, nslot, src, slot_op, Op, op_stride, \
-                               level_shift, X, assign, out);                                      \
+                               level_shift, X, assign, nparts, out);                              \
         break;
     switch (Pp) {
         YK_TILE_CASE(16)
@@ -1135,7 +1148,10 @@ void fmm_run(Context &ctx, FmmPlan &pl, const double *q, const double *dn, doubl
         {
         StageTimer tm(ctx, YK_STAGE_P2M);
         const size_t tabs = (2 * (size_t)pl.nser + 4 * (size_t)(p + 2)) * sizeof(double);
-        auto quad = p == 8 ? k_p2m_quad<8> : p == 12 ? k_p2m_quad<12> : p == 16 ? k_p2m_quad<16>
+        // four lanes per leaf for many leaves; sixteen (more parallelism per
+        // leaf, shorter chains) when the leaves are too few to fill the GPU
+        auto quad = pl.nleaf < 8192 ? nullptr
+                  : p == 8 ? k_p2m_quad<8> : p == 12 ? k_p2m_quad<12> : p == 16 ? k_p2m_quad<16>
                   : p == 20 ? k_p2m_quad<20> : p == 24 ? k_p2m_quad<24> : p == 28 ? k_p2m_quad<28>
                   : p == 31 ? k_p2m_quad<31> : nullptr;
         if (quad) {
