@@ -35,7 +35,9 @@ sys.path.insert(0, ROOT)
 
 METRIC = "Yukawa-FMM Mpts/s at stated rel err; s/time-step plain FP64 vs mixed+learned"
 PEAK_FP64_VALU_TF = 78.6      # MI355X FP64 vector peak (256 CU x 2.4 GHz x 128 flop/clk)
-PEAK_FP32_MFMA_TF = 157.3
+PEAK_FP32_MFMA_TF = 157.3     # MI355X dense matrix-core peaks
+PEAK_FP64_MFMA_TF = 78.6
+PEAK_HBM_GBS = 8000.0
 
 
 LOG_FLOPS = 40   # FP64 logarithm: 9 for the reciprocal with two Newton steps, 31 for the
@@ -55,6 +57,37 @@ def near_flops(info):
     fq = 12 + 4 * (n - 1) + LOG_FLOPS
     fd = 18 + 4 * (n - 1) + LOG_FLOPS
     return info.pairs_charge * fq + info.pairs_dipole * fd
+
+
+def rooflines(info, st, steps, fp32):
+    """Per-kernel rooflines from the serialised per-stage event times.
+
+    Near field (cached): algorithmic bytes = the interaction values read once
+    per pass, 8 bytes per charge pair and 16 per dipole pair in FP64 (half in
+    FP32); source strengths and outputs add under 3% and are not counted.
+    M2L: 2 P^2 flops per non-empty V-list translation (padding not credited),
+    against the dense matrix-core peak of the arithmetic type."""
+    out = {}
+    leaf_ms, leaf_calls = st["leaf"]
+    if leaf_calls:
+        t = leaf_ms / leaf_calls
+        vb = 4 if fp32 else 8
+        nbytes = info.pairs_charge * vb + info.pairs_dipole * 2 * vb
+        ach = nbytes / (t * 1e-3) / 1e9
+        out["near"] = {"kernel": "k_near_apply (cached near field, P2P)", "bound": "hbm", "achieved": ach,
+                       "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": ach / PEAK_HBM_GBS,
+                       "traffic": measured_traffic("k_near_apply"), "avg_launch_ms": t,
+                       "launches_per_pass": leaf_calls / steps, "algorithmic_bytes": nbytes}
+    m2l_ms, m2l_calls = st["m2l"]
+    if m2l_calls:
+        t = m2l_ms / m2l_calls
+        peak = PEAK_FP32_MFMA_TF if fp32 else PEAK_FP64_MFMA_TF
+        ach = m2l_flops(info) / (t * 1e-3) / 1e12
+        out["m2l"] = {"kernel": "k_tile_gemm (M2L, all levels)", "bound": "mfma", "achieved": ach,
+                      "peak": peak, "unit": "TFLOP/s", "frac": ach / peak,
+                      "traffic": measured_traffic("k_tile_gemm_m2l"), "avg_launch_ms": t,
+                      "launches_per_pass": m2l_calls / steps, "algorithmic_flops": m2l_flops(info)}
+    return out
 
 
 def measured_traffic(kernel):
@@ -96,10 +129,13 @@ def run_fmm_bench(args, yk, torch, W):
     ctx = yk.yk_create(opt)
     try:
         torch.cuda.synchronize()
+        yk.yk_timing_enable(ctx, True)
         t0 = time.perf_counter()
         yk.yk_fmm_potential(ctx, vol, q, bd, dip, args.alpha, out_v, out_b)   # builds the tree
         torch.cuda.synchronize()
         first_ms = (time.perf_counter() - t0) * 1e3
+        near_build_ms = yk.yk_timing_read(ctx, reset=True)["near_build"][0]
+        yk.yk_timing_enable(ctx, False)
         info = yk.yk_plan_info_get(ctx, 0)
         for _ in range(args.warmup):
             yk.yk_fmm_potential(ctx, vol, q, bd, dip, args.alpha, out_v, out_b)
@@ -124,7 +160,16 @@ def run_fmm_bench(args, yk, torch, W):
                 yk.yk_fmm_potential(ctx, vol, q, bd, dip, args.alpha, out_v, out_b)
             dst.update(yk.yk_timing_read(ctx, reset=True))
             yk.yk_timing_enable(ctx, False)
-        opt.debug_flags = 0
+        # the near field evaluated on the fly (no cached values), serialised
+        opt.debug_flags, opt.near_cache_mb = 2, 0
+        yk.yk_set_options(ctx, opt)
+        yk.yk_timing_enable(ctx, True)
+        yk.yk_timing_read(ctx, reset=True)
+        for _ in range(args.steps):
+            yk.yk_fmm_potential(ctx, vol, q, bd, dip, args.alpha, out_v, out_b)
+        stages_otf = yk.yk_timing_read(ctx, reset=True)
+        yk.yk_timing_enable(ctx, False)
+        opt.debug_flags, opt.near_cache_mb = 0, yk.yk_default_options().near_cache_mb
         yk.yk_set_options(ctx, opt)
         info = yk.yk_plan_info_get(ctx, 0)
         ov = out_v.cpu().numpy()
@@ -133,7 +178,7 @@ def run_fmm_bench(args, yk, torch, W):
         yk.yk_destroy(ctx)
     ms = total_ms / args.steps
     res = dict(cfg=cfg, n_pts=n_pts, ms=ms, first_ms=first_ms, info=info, stages=stages,
-               stages_overlap=stages_overlap,
+               stages_overlap=stages_overlap, near_build_ms=near_build_ms, stages_otf=stages_otf,
                out=np.concatenate([ov, ob]))
     return res
 
@@ -298,16 +343,22 @@ def main():
     res = run_fmm_bench(args, yk, torch, W)
     info, st = res["info"], res["stages"]
     value = res["n_pts"] / (res["ms"] * 1e-3) / 1e6
-    leaf_ms, leaf_calls = st["leaf"]
-    leaf_avg = leaf_ms / max(leaf_calls, 1)
-    lf = near_flops(info)
-    achieved = lf / (leaf_avg * 1e-3) / 1e12
-    roof = {"kernel": "k_leaf (near field P2P)", "bound": "alu", "achieved": achieved,
-            "peak": PEAK_FP64_VALU_TF, "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_VALU_TF,
-            "traffic": measured_traffic("k_leaf"), "avg_launch_ms": leaf_avg,
+    roofs = rooflines(info, st, args.steps, args.fp32)
+    # the on-the-fly near-field kernel (Bessel series per pair), FP64 vector units
+    otf_ms, otf_calls = res["stages_otf"]["leaf"]
+    if otf_calls and not args.fp32:
+        t = otf_ms / otf_calls
+        lf = near_flops(info)
+        ach = lf / (t * 1e-3) / 1e12
+        roofs["near_on_the_fly"] = {
+            "kernel": "k_leaf (near field evaluated on the fly)", "bound": "alu", "achieved": ach,
+            "peak": PEAK_FP64_VALU_TF, "unit": "TFLOP/s", "frac": ach / PEAK_FP64_VALU_TF,
+            "traffic": measured_traffic("k_leaf"), "avg_launch_ms": t, "launches_per_pass": 0.0,
             "algorithmic_flops": lf, "log_counted_as_flops": LOG_FLOPS}
-    m2l_ms, m2l_calls = st["m2l"]
-    m2l_rate = m2l_flops(info) / (m2l_ms / max(args.steps, 1) * 1e-3) / 1e12 if m2l_ms > 0 else None
+    # the dominant kernel: largest time per pass
+    roof = max((r for k, r in roofs.items() if k != "near_on_the_fly"),
+               key=lambda r: r["avg_launch_ms"] * r["launches_per_pass"])
+    m2l_rate = roofs["m2l"]["achieved"] if "m2l" in roofs else None
     err, errmax, idx, _ = direct_check(args, res, yk, torch)
     err_oracle = cpu = None
     if not args.no_cpu:
@@ -329,7 +380,10 @@ def main():
             "first_call_ms": res["first_ms"],
             "stage_ms_per_step": {k: v[0] / args.steps for k, v in st.items()},
             "stage_ms_per_step_overlapped": {k: v[0] / args.steps for k, v in res["stages_overlap"].items()},
+            "stage_ms_per_step_near_on_the_fly": {k: v[0] / args.steps for k, v in res["stages_otf"].items()},
             "m2l_tflops": m2l_rate, "pairs_per_step": info.pairs_charge + info.pairs_dipole,
+            "near_cache_build_ms": res["near_build_ms"],
+            "rooflines": roofs,
             "m2l_translations": info.m2l_translations,
         },
         "roofline": roof,

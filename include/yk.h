@@ -65,6 +65,9 @@ typedef struct {
     int debug_flags;        /* bit0: synchronise and check after every kernel;
                                bit1: run the near field on the context's stream
                                (no overlap with the far field; for timing) */
+    int near_cache_mb;      /* device memory (MiB) a tree may spend on its cached
+                               near-field interaction values; 0 = evaluate the
+                               near-field kernels on every call */
 } yk_options;
 
 typedef struct {
@@ -88,7 +91,15 @@ typedef struct {
 } yk_stats;
 
 /* Fills *opt with defaults: FP64, fmm_tol 1e-10, p 0, leaf_size 64,
- * direct 0, gmres_m 60, debug_flags 0. */
+ * direct 0, gmres_m 60, debug_flags 0, near_cache_mb 16384.
+ *
+ * Cached near field: the near-field interaction values (K0 for charges, the
+ * double-layer kernel's two components for dipoles) depend only on the points
+ * and alpha, so a tree caches them on its first evaluation for each target
+ * set when they fit in near_cache_mb (8 bytes per charge pair and 16 per
+ * dipole pair in FP64, half in FP32); later evaluations on the same tree read
+ * them instead of evaluating Bessel series.  The cache lives and dies with
+ * the tree (new points, alpha, p, leaf_size or yk_invalidate_geometry). */
 void yk_default_options(yk_options *opt);
 
 /* Creates a context on the current HIP device.  opt may be NULL (defaults). */
@@ -262,7 +273,7 @@ typedef struct {
 enum {
     YK_STAGE_GATHER = 0, YK_STAGE_P2M = 1, YK_STAGE_M2M = 2, YK_STAGE_M2L = 3,
     YK_STAGE_L2L = 4, YK_STAGE_LEAF = 5, YK_STAGE_SCATTER = 6, YK_STAGE_DIRECT = 7,
-    YK_STAGE_L2P = 8, YK_NUM_STAGES = 9
+    YK_STAGE_L2P = 8, YK_STAGE_NEAR_BUILD = 9, YK_NUM_STAGES = 10
 };
 
 yk_status yk_plan_info_get(yk_ctx ctx, int slot, yk_plan_info *info);

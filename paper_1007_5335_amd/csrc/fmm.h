@@ -51,6 +51,14 @@ struct ActiveSet {
     int64_t n_m2l_boxes = 0;
     // work counts (for measurement)
     int64_t pairs_q = 0, pairs_d = 0, m2l_trans = 0, l2p_points = 0;
+    // cached near-field interactions (points and alpha only): per item, source
+    // major and target minor, in the U-list order of the near kernel; charge
+    // entries K0, dipole entries the pair (dx, dy) 4 K1(z)/z (scaled units)
+    DevBuf<int64_t> item_qoff, item_doff;   // entry offsets per item
+    int64_t near_q_len = 0, near_d_len = 0; // entries (dipole entries are pairs)
+    DevBuf<double> nq64, nd64;
+    DevBuf<float> nq32, nd32;
+    bool near64 = false, near32 = false;     // built
 };
 
 struct FmmPlan {

@@ -1022,6 +1022,207 @@ __global__ __launch_bounds__(64) void k_leaf(
     }
 }
 
+// ------------------------------------------------- cached near field ---
+// The near-field values depend on the points and alpha only, so a tree can
+// keep them: k_near_build writes them once per target set, k_near_apply then
+// forms the sums from them (an HBM-bound pass instead of Bessel series).
+// Both walk the items exactly as k_leaf does; entries are source-major and
+// target-minor per item, so a wavefront's loads are contiguous.
+struct ItemSetup {
+    int c, g, ti, sub, t, nq, nd;
+    bool valid;
+};
+
+// Leaf ranges and U-list source ranges of an item (into the LDS arrays qa, qn,
+// da, dn_, one entry per neighbour), and this lane's target.  q_on / d_on
+// select which source sets are counted.
+__device__ __forceinline__ ItemSetup item_setup(int2 item, const int32_t *__restrict__ lrange,
+                                                const int32_t *__restrict__ uoff,
+                                                const int32_t *__restrict__ ulist, int q_on, int d_on,
+                                                int mask, int *qa, int *qn, int *da, int *dn_) {
+    const int li = item.x, lane = threadIdx.x;
+    int rs[3], re[3], ntot = 0;
+    for (int s = 0; s < 3; ++s) {
+        rs[s] = lrange[li * 6 + 2 * s];
+        re[s] = (mask >> s) & 1 ? lrange[li * 6 + 2 * s + 1] : rs[s];
+        ntot += re[s] - rs[s];
+    }
+    const int u0 = uoff[li], nu = uoff[li + 1] - u0;
+    if (lane < 9) {
+        const int u = lane;
+        int a = 0, an = 0, b2 = 0, bn = 0;
+        if (u < nu) {
+            const int ul = ulist[u0 + u];
+            a = lrange[ul * 6];
+            an = q_on ? lrange[ul * 6 + 1] - a : 0;
+            b2 = lrange[ul * 6 + 2];
+            bn = d_on ? lrange[ul * 6 + 3] - b2 : 0;
+        }
+        qa[u] = a; qn[u] = an; da[u] = b2; dn_[u] = bn;
+    }
+    __syncthreads();
+    ItemSetup r;
+    r.nq = 0;
+    r.nd = 0;
+    for (int u = 0; u < 9; ++u) {
+        r.nq += qn[u];
+        r.nd += dn_[u];
+    }
+    r.c = min(64, ntot - item.y);
+    r.g = 64 / r.c;
+    r.ti = lane % r.c;
+    r.sub = lane / r.c;
+    r.valid = r.sub < r.g;
+    int k = item.y + r.ti;
+    r.t = -1;
+    for (int s = 0; s < 3; ++s) {
+        const int n = re[s] - rs[s];
+        if (r.t < 0 && k < n) r.t = rs[s] + k;
+        k -= n;
+    }
+    return r;
+}
+
+// sorted index of flat U-list source f of a set (counts cnt, starts st)
+__device__ __forceinline__ int flat_source(int f, const int *cnt, const int *st) {
+    int u = 0;
+    while (u < 8 && f >= cnt[u]) { f -= cnt[u]; ++u; }
+    return st[u] + f;
+}
+
+template <int NT, bool kSmallOnly, bool kF32>
+__global__ __launch_bounds__(64) void k_near_build(
+    const int2 *__restrict__ items, const int32_t *__restrict__ lrange,
+    const int32_t *__restrict__ uoff, const int32_t *__restrict__ ulist,
+    const double *__restrict__ px, const double *__restrict__ py, int q_on, int d_on, int mask,
+    double inv2a, const int64_t *__restrict__ qoff, const int64_t *__restrict__ doff,
+    typename std::conditional<kF32, float, double>::type *__restrict__ Mq,
+    typename std::conditional<kF32, float, double>::type *__restrict__ Md) {
+    using VT = typename std::conditional<kF32, float, double>::type;
+    __shared__ double s_x[kLeafStage], s_y[kLeafStage];
+    __shared__ double2 s_log[YK_LOG_TAB];
+    __shared__ int qa[9], qn[9], da[9], dn_[9];
+    const int ib = xcd_remap(blockIdx.x, gridDim.x);
+    const int lane = threadIdx.x;
+    if constexpr (!kF32)
+        for (int i = lane; i < YK_LOG_TAB; i += 64) s_log[i] = make_double2(yk_log_tab[2 * i], yk_log_tab[2 * i + 1]);
+    const ItemSetup it = item_setup(items[ib], lrange, uoff, ulist, q_on, d_on, mask, qa, qn, da, dn_);
+    const double xs = px[it.t] * inv2a, ys = py[it.t] * inv2a;
+    for (int set = 0; set < 2; ++set) {
+        const int ntot_s = set == 0 ? it.nq : it.nd;
+        VT *Mb = set == 0 ? Mq + qoff[ib] : Md + 2 * doff[ib];
+        for (int c0 = 0; c0 < ntot_s; c0 += kLeafStage) {
+            const int cn = min(kLeafStage, ntot_s - c0);
+            __syncthreads();
+            for (int f = lane; f < cn; f += 64) {
+                const int j = flat_source(c0 + f, set == 0 ? qn : dn_, set == 0 ? qa : da);
+                s_x[f] = px[j] * inv2a;
+                s_y[f] = py[j] * inv2a;
+            }
+            __syncthreads();
+            if (!it.valid) continue;
+            for (int j = it.sub; j < cn; j += it.g) {
+                const double dx = xs - s_x[j], dy = ys - s_y[j];
+                const double tt = __builtin_fma(dx, dx, dy * dy);
+                const int64_t e = (int64_t)(c0 + j) * it.c + it.ti;
+                if (set == 0) {
+                    double v = 0.0;
+                    if (tt > 0.0) {
+                        if constexpr (kF32) v = (double)near_k0_f<kSmallOnly>((float)tt);
+                        else v = near_k0<NT, kSmallOnly>(tt, s_log);
+                    }
+                    Mb[e] = (VT)v;
+                } else {
+                    double k = 0.0;
+                    if (tt > 0.0) {
+                        if constexpr (kF32) k = (double)near_k1oz4_f<kSmallOnly>((float)tt);
+                        else k = near_k1oz4<NT, kSmallOnly>(tt, s_log);
+                    }
+                    Mb[2 * e] = (VT)(dx * k);
+                    Mb[2 * e + 1] = (VT)(dy * k);
+                }
+            }
+        }
+    }
+}
+
+template <typename VT>
+__global__ __launch_bounds__(64) void k_near_apply(
+    const int2 *__restrict__ items, const int32_t *__restrict__ lrange,
+    const int32_t *__restrict__ uoff, const int32_t *__restrict__ ulist,
+    const double *__restrict__ qs, const double *__restrict__ dns, int64_t off1, int q_on, int d_on,
+    int has_q, int has_d, int mask, const int64_t *__restrict__ qoff, const int64_t *__restrict__ doff,
+    const VT *__restrict__ Mq, const VT *__restrict__ Md, double dip_scale, double *__restrict__ outs) {
+    using V2 = typename Pair2<VT>::type;
+    __shared__ double s_a[kLeafStage], s_b[kLeafStage];
+    __shared__ int qa[9], qn[9], da[9], dn_[9];
+    const int ib = xcd_remap(blockIdx.x, gridDim.x);
+    const int lane = threadIdx.x;
+    const ItemSetup it = item_setup(items[ib], lrange, uoff, ulist, q_on, d_on, mask, qa, qn, da, dn_);
+    double near_q = 0.0, near_d = 0.0;
+    for (int set = 0; set < 2; ++set) {
+        if ((set == 0 && !has_q) || (set == 1 && !has_d)) continue;
+        const int ntot_s = set == 0 ? it.nq : it.nd;
+        for (int c0 = 0; c0 < ntot_s; c0 += kLeafStage) {
+            const int cn = min(kLeafStage, ntot_s - c0);
+            __syncthreads();
+            for (int f = lane; f < cn; f += 64) {
+                const int j = flat_source(c0 + f, set == 0 ? qn : dn_, set == 0 ? qa : da);
+                if (set == 0) {
+                    s_a[f] = qs[j];
+                } else {
+                    const int64_t jd = j - off1;
+                    s_a[f] = dns[2 * jd];
+                    s_b[f] = dns[2 * jd + 1];
+                }
+            }
+            __syncthreads();
+            if (!it.valid) continue;
+            if (set == 0) {
+                const VT *Mb = Mq + qoff[ib] + (int64_t)c0 * it.c + it.ti;
+#pragma unroll 4
+                for (int j = it.sub; j < cn; j += it.g) near_q = __builtin_fma((double)Mb[(int64_t)j * it.c], s_a[j], near_q);
+            } else {
+                const V2 *Mb = reinterpret_cast<const V2 *>(Md) + doff[ib] + (int64_t)c0 * it.c + it.ti;
+#pragma unroll 4
+                for (int j = it.sub; j < cn; j += it.g) {
+                    const V2 m = Mb[(int64_t)j * it.c];
+                    near_d = __builtin_fma((double)m.x, s_a[j], __builtin_fma((double)m.y, s_b[j], near_d));
+                }
+            }
+        }
+    }
+    __syncthreads();
+    s_a[lane] = it.valid ? near_q + dip_scale * near_d : 0.0;
+    __syncthreads();
+    if (it.sub == 0) {
+        double tot = 0.0;
+        for (int gi = 0; gi < it.g; ++gi) tot += s_a[it.ti + gi * it.c];
+        outs[it.t] = tot * kInv2Pi;
+    }
+}
+
+using NearBuild64 = void (*)(const int2 *, const int32_t *, const int32_t *, const int32_t *,
+                             const double *, const double *, int, int, int, double, const int64_t *,
+                             const int64_t *, double *, double *);
+using NearBuild32 = void (*)(const int2 *, const int32_t *, const int32_t *, const int32_t *,
+                             const double *, const double *, int, int, int, double, const int64_t *,
+                             const int64_t *, float *, float *);
+
+NearBuild64 pick_near_build64(int nt, bool small_only) {
+    if (small_only) {
+        if (nt <= 5) return k_near_build<5, true, false>;
+        if (nt <= 6) return k_near_build<6, true, false>;
+        if (nt <= 8) return k_near_build<8, true, false>;
+        if (nt <= 10) return k_near_build<10, true, false>;
+        return k_near_build<14, true, false>;
+    }
+    return k_near_build<14, false, false>;
+}
+NearBuild32 pick_near_build32(bool small_only) {
+    return small_only ? k_near_build<8, true, true> : k_near_build<8, false, true>;
+}
+
 using LeafKernel = void (*)(const int2 *, int64_t, const int32_t *, const int32_t *,
                             const int32_t *, const double *, const double *, const double *,
                             const double *, int64_t, int, int, int, double, double, double *);
@@ -1133,12 +1334,53 @@ void fmm_run(Context &ctx, FmmPlan &pl, const double *q, const double *dn, doubl
         hipStream_t near_stream = overlap ? ctx.side : ctx.stream;
         if (as.n_leaves > 0) {
             const double tmax = 2.0 * pl.lev[L].side * pl.lev[L].side * inv_alpha * inv_alpha;
-            LeafKernel kern = pick_leaf_kernel(pl.near_terms, tmax <= 1.0, prec == SUM_FP32);
-            StageTimer tl(ctx, YK_STAGE_LEAF, near_stream);
-            hipLaunchKernelGGL(kern, dim3(as.n_items), dim3(64), 0, near_stream, as.leaf_items.p,
-                               leaf_base, pl.lrange.p, pl.ulist_off.p, pl.ulist.p, pl.px.p, pl.py.p, qs,
-                               dns, pl.toff[1], has_q, has_d, mask, 0.5 * inv_alpha, 0.5 * inv_alpha, outs);
-            check_launch(ctx, "k_leaf");
+            const bool f32 = prec == SUM_FP32, small_only = tmax <= 1.0;
+            const int q_on = n0 > 0 ? 1 : 0, d_on = n1 > 0 ? 1 : 0;
+            const int64_t entries = as.near_q_len + 2 * as.near_d_len;
+            const int64_t bytes = entries * (f32 ? 4 : 8);
+            const bool cache = ctx.opt.near_cache_mb > 0 && bytes <= ((int64_t)ctx.opt.near_cache_mb << 20);
+            if (cache) {
+                bool &built = f32 ? as.near32 : as.near64;
+                if (!built) {
+                    StageTimer tb(ctx, YK_STAGE_NEAR_BUILD, near_stream);
+                    if (f32) {
+                        float *mq = as.nq32.ensure(std::max<int64_t>(as.near_q_len, 1));
+                        float *md = as.nd32.ensure(std::max<int64_t>(2 * as.near_d_len, 1));
+                        hipLaunchKernelGGL(pick_near_build32(small_only), dim3(as.n_items), dim3(64), 0,
+                                           near_stream, as.leaf_items.p, pl.lrange.p, pl.ulist_off.p,
+                                           pl.ulist.p, pl.px.p, pl.py.p, q_on, d_on, mask, 0.5 * inv_alpha,
+                                           as.item_qoff.p, as.item_doff.p, mq, md);
+                    } else {
+                        double *mq = as.nq64.ensure(std::max<int64_t>(as.near_q_len, 1));
+                        double *md = as.nd64.ensure(std::max<int64_t>(2 * as.near_d_len, 1));
+                        hipLaunchKernelGGL(pick_near_build64(pl.near_terms, small_only), dim3(as.n_items),
+                                           dim3(64), 0, near_stream, as.leaf_items.p, pl.lrange.p,
+                                           pl.ulist_off.p, pl.ulist.p, pl.px.p, pl.py.p, q_on, d_on, mask,
+                                           0.5 * inv_alpha, as.item_qoff.p, as.item_doff.p, mq, md);
+                    }
+                    check_launch(ctx, "k_near_build");
+                    built = true;
+                }
+                StageTimer tl(ctx, YK_STAGE_LEAF, near_stream);
+                if (f32)
+                    hipLaunchKernelGGL(k_near_apply<float>, dim3(as.n_items), dim3(64), 0, near_stream,
+                                       as.leaf_items.p, pl.lrange.p, pl.ulist_off.p, pl.ulist.p, qs, dns,
+                                       pl.toff[1], q_on, d_on, has_q, has_d, mask, as.item_qoff.p,
+                                       as.item_doff.p, as.nq32.p, as.nd32.p, 0.5 * inv_alpha, outs);
+                else
+                    hipLaunchKernelGGL(k_near_apply<double>, dim3(as.n_items), dim3(64), 0, near_stream,
+                                       as.leaf_items.p, pl.lrange.p, pl.ulist_off.p, pl.ulist.p, qs, dns,
+                                       pl.toff[1], q_on, d_on, has_q, has_d, mask, as.item_qoff.p,
+                                       as.item_doff.p, as.nq64.p, as.nd64.p, 0.5 * inv_alpha, outs);
+                check_launch(ctx, "k_near_apply");
+            } else {
+                LeafKernel kern = pick_leaf_kernel(pl.near_terms, small_only, f32);
+                StageTimer tl(ctx, YK_STAGE_LEAF, near_stream);
+                hipLaunchKernelGGL(kern, dim3(as.n_items), dim3(64), 0, near_stream, as.leaf_items.p,
+                                   leaf_base, pl.lrange.p, pl.ulist_off.p, pl.ulist.p, pl.px.p, pl.py.p, qs,
+                                   dns, pl.toff[1], has_q, has_d, mask, 0.5 * inv_alpha, 0.5 * inv_alpha, outs);
+                check_launch(ctx, "k_leaf");
+            }
         }
         if (overlap) YK_HIP(hipEventRecord(ctx.ev_join, ctx.side));
     };

@@ -530,6 +530,7 @@ ActiveSet &get_active(Context &ctx, FmmPlan &pl, int mask) {
         YK_HIP(hipMemcpyAsync(ul.data(), pl.ulist.p, ul.size() * sizeof(int32_t),
                               hipMemcpyDeviceToHost, ctx.stream));
         YK_HIP(hipStreamSynchronize(ctx.stream));
+        std::vector<int64_t> sq_leaf(pl.nleaf, 0), sd_leaf(pl.nleaf, 0);
         for (int32_t li : leaves) {
             const int64_t nt = cnt[pl.lev[L].begin + li];
             int64_t sq = 0, sd = 0;
@@ -537,9 +538,31 @@ ActiveSet &get_active(Context &ctx, FmmPlan &pl, int mask) {
                 sq += pl.h_lrange[(size_t)ul[u] * 6 + 1] - pl.h_lrange[(size_t)ul[u] * 6];
                 sd += pl.h_lrange[(size_t)ul[u] * 6 + 3] - pl.h_lrange[(size_t)ul[u] * 6 + 2];
             }
+            sq_leaf[li] = sq;
+            sd_leaf[li] = sd;
             as->pairs_q += nt * sq;
             as->pairs_d += nt * sd;
             as->l2p_points += nt;
+        }
+        // entry offsets of the cached near field, item by item
+        std::vector<int64_t> qoff(items.size()), doff(items.size());
+        int64_t oq = 0, od = 0;
+        for (size_t i = 0; i < items.size(); ++i) {
+            const int li = items[i].x;
+            const int64_t c = std::min<int64_t>(64, cnt[pl.lev[L].begin + li] - items[i].y);
+            qoff[i] = oq;
+            doff[i] = od;
+            oq += c * sq_leaf[li];
+            od += c * sd_leaf[li];
+        }
+        as->near_q_len = oq;
+        as->near_d_len = od;
+        if (!items.empty()) {
+            int64_t *dq = as->item_qoff.ensure(items.size());
+            int64_t *dd = as->item_doff.ensure(items.size());
+            YK_HIP(hipMemcpyAsync(dq, qoff.data(), qoff.size() * sizeof(int64_t), hipMemcpyHostToDevice, ctx.stream));
+            YK_HIP(hipMemcpyAsync(dd, doff.data(), doff.size() * sizeof(int64_t), hipMemcpyHostToDevice, ctx.stream));
+            YK_HIP(hipStreamSynchronize(ctx.stream));
         }
     }
     // M2L tiles: active boxes of levels lmin..L grouped by (level, class)

@@ -40,13 +40,13 @@ EXPORTS = (
     "yk_ws_set_params", "yk_ws_loss_grad",
 )
 
-STAGES = ("gather", "p2m", "m2m", "m2l", "l2l", "leaf", "scatter", "direct", "l2p")
+STAGES = ("gather", "p2m", "m2m", "m2l", "l2l", "leaf", "scatter", "direct", "l2p", "near_build")
 
 
 class yk_options(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int), ("fmm_tol", ctypes.c_double), ("p", ctypes.c_int),
                 ("leaf_size", ctypes.c_int), ("direct", ctypes.c_int), ("gmres_m", ctypes.c_int),
-                ("debug_flags", ctypes.c_int)]
+                ("debug_flags", ctypes.c_int), ("near_cache_mb", ctypes.c_int)]
 
 
 class yk_boundary(ctypes.Structure):

@@ -245,3 +245,38 @@ def test_fmm_full_size_sampled_vs_oracle(yk, oracle_lib, precision):
     err = float(np.max(np.abs(got - ref)) / scale)
     print(f"  max err / rms {err:.2e}", flush=True)
     assert err < (1e-9 if precision == "fp64" else 2e-5)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_near_cache_matches_on_the_fly(yk, oracle_lib, precision):
+    """The cached near-field values give the same sums as evaluating the
+    kernels on the fly, also on a second call with new strengths (the cache
+    holds geometry only)."""
+    import torch
+    c = W.small_fmm_case(n_vol=6000, n_nodes=256, alpha=0.05, seed=21, clustered=False)
+    b = c["bnd"]
+    rng = np.random.default_rng(22)
+    strengths = ((c["q"], c["dip"]), (rng.standard_normal(c["q"].size), rng.standard_normal(b.n)))
+    prec = yk.YK_PREC_FP32 if precision == "fp32" else yk.YK_PREC_FP64
+    outs = {}
+    for cache_mb in (16384, 0):
+        ctx = _ctx(yk, leaf_size=32, fmm_tol=1e-10, precision=prec, near_cache_mb=cache_mb)
+        try:
+            bd = yk.Boundary.from_workload(b)
+            res = []
+            for q, dip in strengths:
+                ov = torch.empty(c["vol"].shape[0], dtype=torch.float64, device="cuda")
+                ob = torch.empty(b.n, dtype=torch.float64, device="cuda")
+                print(f"near cache {cache_mb} MiB {precision}", flush=True)
+                yk.yk_fmm_potential(ctx, dev(c["vol"]), dev(q), bd, dev(dip), c["alpha"], ov, ob)
+                torch.cuda.synchronize()
+                res.append(np.concatenate([host(ov), host(ob)]))
+        finally:
+            yk.yk_destroy(ctx)
+        outs[cache_mb] = res
+    tol = 1e-13 if precision == "fp64" else 2e-6
+    for a, bb in zip(outs[16384], outs[0]):
+        assert rel_l2(a, bb) < tol
+    rv, rb = _oracle_fmm_potential(oracle_lib, c)
+    ref = np.concatenate([rv, rb])
+    assert rel_l2(outs[16384][0], ref) < (1e-10 if precision == "fp64" else 2e-5)
