@@ -166,6 +166,10 @@ yk_status yk_gmres_density(yk_ctx ctx, const yk_boundary *bnd, double alpha, con
  * f_next [N] boundary data at t^{N+1}.  sigma_io [N]: in = initial guess,
  * out = sigma^{N+1}.  flags bit1: ignore sigma_io on input (zero guess).
  * u_next [n_vol] (meaningful at points inside the domain).
+ * The context keeps a copy of the density it returned and of A sigma; when the
+ * next call passes that same density (bitwise) for the same boundary, alpha
+ * and FMM options, its residual is formed from the kept A sigma instead of a
+ * new operator application.
  */
 yk_status yk_heat_step(yk_ctx ctx, const yk_boundary *bnd, int64_t n_vol, const double *vol_xy,
                        const double *vol_w, const double *B, int flags, const double *f_next,

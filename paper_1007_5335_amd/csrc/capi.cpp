@@ -161,13 +161,24 @@ struct BieOperator {
 
 // Solves A sigma = b in FP64, or (mixed) by refinement: FP64 residuals with an
 // FP32-operator GMRES for each correction.
+// r0: b - A sigma for the incoming sigma (optional); Asig_out (optional): set
+// to A sigma of the returned density when the solve converged (FP64 operator)
 GmresResult solve_density(Context &ctx, BoundaryData &bd, double alpha, const double *b,
-                          double *sigma, bool zero_guess, double tol, int max_iter, int *outer) {
+                          double *sigma, bool zero_guess, double tol, int max_iter, int *outer,
+                          const double *r0 = nullptr, double *Asig_out = nullptr,
+                          bool *asig_ok = nullptr) {
+    if (asig_ok) *asig_ok = false;
     const int64_t n = bd.n;
     BieOperator A64{ctx, bd, alpha, SUM_FP64};
     *outer = 0;
-    if (ctx.opt.precision == YK_PREC_FP64 || ctx.opt.direct)
-        return gmres(ctx, A64, n, b, sigma, zero_guess, tol, max_iter, ctx.opt.gmres_m);
+    if (ctx.opt.precision == YK_PREC_FP64 || ctx.opt.direct) {
+        GmresResult g = gmres(ctx, A64, n, b, sigma, zero_guess, tol, max_iter, ctx.opt.gmres_m, r0);
+        if (Asig_out && g.converged && g.res_final > 0) {   // A sigma = b - r
+            launch_axpby(ctx, n, 1.0, b, -1.0, ctx.gm_r.p, Asig_out);
+            if (asig_ok) *asig_ok = true;
+        }
+        return g;
+    }
     BieOperator A32{ctx, bd, alpha, SUM_FP32};
     double *r = ctx.ws_b.ensure(n);
     double *delta = ctx.ws_c.ensure(n);
@@ -184,15 +195,24 @@ GmresResult solve_density(Context &ctx, BoundaryData &bd, double alpha, const do
     const double bnorm = norm(b);
     if (zero_guess) YK_HIP(hipMemsetAsync(sigma, 0, n * sizeof(double), ctx.stream));
     for (int sweep = 0; sweep < 30; ++sweep) {
-        A64(sigma, tmp);
-        tot.matvecs++;
-        launch_axpby(ctx, n, 1.0, b, -1.0, tmp, r);
+        if (sweep == 0 && r0 && !zero_guess) {
+            YK_HIP(hipMemcpyAsync(r, r0, n * sizeof(double), hipMemcpyDeviceToDevice, ctx.stream));
+            launch_axpby(ctx, n, 1.0, b, -1.0, r0, tmp);   // A sigma, kept for the memo
+        } else {
+            A64(sigma, tmp);
+            tot.matvecs++;
+            launch_axpby(ctx, n, 1.0, b, -1.0, tmp, r);
+        }
         const double rn = norm(r);
         if (!std::isfinite(rn)) throw Error{YK_ERR_NONFINITE, "refinement residual is not finite"};
         if (sweep == 0) tot.res0 = bnorm > 0 ? rn / bnorm : 0.0;
         tot.res_final = bnorm > 0 ? rn / bnorm : 0.0;
         if (rn <= tol * bnorm || bnorm == 0.0) {
             tot.converged = true;
+            if (Asig_out && bnorm > 0.0) {
+                YK_HIP(hipMemcpyAsync(Asig_out, tmp, n * sizeof(double), hipMemcpyDeviceToDevice, ctx.stream));
+                if (asig_ok) *asig_ok = true;
+            }
             break;
         }
         if (tot.iters >= max_iter) break;
@@ -204,6 +224,37 @@ GmresResult solve_density(Context &ctx, BoundaryData &bd, double alpha, const do
         (*outer)++;
     }
     return tot;
+}
+
+// The memo of the last FP64 density solve applies to this operator and sigma?
+bool memo_matches(Context &ctx, BoundaryData &bd, double alpha, const double *sigma) {
+    const yk_options &o = ctx.opt;
+    if (!ctx.memo_valid || ctx.memo_xy != bd.xy || ctx.memo_n != bd.n || ctx.memo_alpha != alpha ||
+        ctx.memo_tol != o.fmm_tol || ctx.memo_p != o.p || ctx.memo_leaf != o.leaf_size ||
+        ctx.memo_direct != o.direct)
+        return false;
+    int *flag = ctx.memo_flag.ensure(1);
+    const int zero = 0;
+    YK_HIP(hipMemcpyAsync(flag, &zero, sizeof(int), hipMemcpyHostToDevice, ctx.stream));
+    launch_differs(ctx, bd.n, sigma, ctx.memo_sig.p, flag);
+    int h = 1;
+    YK_HIP(hipMemcpyAsync(&h, flag, sizeof(int), hipMemcpyDeviceToHost, ctx.stream));
+    YK_HIP(hipStreamSynchronize(ctx.stream));
+    return h == 0;
+}
+
+void memo_store(Context &ctx, BoundaryData &bd, double alpha, const double *sigma) {
+    const yk_options &o = ctx.opt;
+    YK_HIP(hipMemcpyAsync(ctx.memo_sig.ensure(bd.n), sigma, bd.n * sizeof(double), hipMemcpyDeviceToDevice,
+                          ctx.stream));
+    ctx.memo_valid = true;
+    ctx.memo_xy = bd.xy;
+    ctx.memo_n = bd.n;
+    ctx.memo_alpha = alpha;
+    ctx.memo_tol = o.fmm_tol;
+    ctx.memo_p = o.p;
+    ctx.memo_leaf = o.leaf_size;
+    ctx.memo_direct = o.direct;
 }
 
 }  // namespace
@@ -290,6 +341,7 @@ yk_status yk_set_options(yk_ctx ctx, const yk_options *opt) {
     if (!ctx || !opt || !valid_options(opt)) return YK_ERR_ARG;
     const yk_options old = ctx->c.opt;
     ctx->c.opt = *opt;
+    ctx->c.memo_valid = false;
     if (old.p != opt->p || old.leaf_size != opt->leaf_size || old.fmm_tol != opt->fmm_tol) {
         ctx->c.plan_vol.reset();
         ctx->c.plan_bnd.reset();
@@ -310,6 +362,7 @@ yk_status yk_invalidate_geometry(yk_ctx ctx) {
         c.plan_bnd.reset();
         c.plan_misc.reset();
         c.bnd.reset();
+        c.memo_valid = false;
         return YK_OK;
     });
 }
@@ -444,35 +497,55 @@ yk_status yk_heat_step(yk_ctx ctx, const yk_boundary *bnd, int64_t n_vol, const 
         double *gN = c.ws_g.ensure(nb);
         launch_axpby(c, nb, 1.0, f_next, -1.0 / a2, vb, gN);
         // initial guess: the caller's (previous-step) density, or the learned
-        // prediction when its residual is smaller
+        // prediction when its residual is smaller.  When the caller's density
+        // is the last solution of this same operator, its image A sigma is
+        // still held and its residual costs no operator application.
         int guess = (flags & 2) ? 0 : 1;
+        const double *r0 = nullptr;
+        double *rprev = c.memo_r1.ensure(nb), *rml = c.memo_r2.ensure(nb);
+        const bool memo = guess == 1 && memo_matches(c, bd, alpha, sigma_io);
+        BieOperator A64{c, bd, alpha, SUM_FP64};
+        // rv = b - A x (from the memo when from_memo); returns ||rv||^2
+        auto resid = [&](const double *x, double *rv, bool from_memo) {
+            if (from_memo) {
+                launch_axpby(c, nb, 1.0, b, -1.0, c.memo_Asig.p, rv);
+            } else {
+                A64(x, rv);
+                launch_axpby(c, nb, 1.0, b, -1.0, rv, rv);
+            }
+            double *ds = c.scal.ensure(512) + 450;
+            launch_multi_dot(c, nb, 1, rv, nb, rv, ds);
+            double h = 0;
+            YK_HIP(hipMemcpyAsync(&h, ds, sizeof(double), hipMemcpyDeviceToHost, c.stream));
+            YK_HIP(hipStreamSynchronize(c.stream));
+            return h;
+        };
         if (c.warm && c.warm->trained && c.warm->obs.size() >= 2 && guess == 1) {
             auto tg = std::chrono::steady_clock::now();
-            double *sml = c.ws_ml.ensure(nb), *tmp = c.ws_t.ensure(nb);
+            double *sml = c.ws_ml.ensure(nb);
             c.warm->predict(gN, sml);
-            BieOperator A64{c, bd, alpha, SUM_FP64};
-            auto resid = [&](const double *x) {
-                A64(x, tmp);
-                launch_axpby(c, nb, 1.0, b, -1.0, tmp, tmp);
-                double *ds = c.scal.ensure(512) + 450;
-                launch_multi_dot(c, nb, 1, tmp, nb, tmp, ds);
-                double h = 0;
-                YK_HIP(hipMemcpyAsync(&h, ds, sizeof(double), hipMemcpyDeviceToHost, c.stream));
-                YK_HIP(hipStreamSynchronize(c.stream));
-                return h;
-            };
-            const double r_ml = resid(sml), r_prev = resid(sigma_io);
+            const double r_ml = resid(sml, rml, false), r_prev = resid(sigma_io, rprev, memo);
             if (std::isfinite(r_ml) && r_ml < r_prev) {
                 YK_HIP(hipMemcpyAsync(sigma_io, sml, nb * sizeof(double), hipMemcpyDeviceToDevice, c.stream));
                 guess = 2;
+                r0 = rml;
+            } else {
+                r0 = rprev;
             }
             if (stats) stats->ms[4] = ms_since(tg);
+        } else if (memo) {
+            launch_axpby(c, nb, 1.0, b, -1.0, c.memo_Asig.p, rprev);
+            r0 = rprev;
         }
         // sigma
         auto t1 = std::chrono::steady_clock::now();
         // the solver's operators use ws_a..ws_d, so q is formed again afterwards
         int outer = 0;
-        GmresResult r = solve_density(c, bd, alpha, b, sigma_io, guess == 0, tol, 1000, &outer);
+        bool asig_ok = false;
+        GmresResult r = solve_density(c, bd, alpha, b, sigma_io, guess == 0, tol, 1000, &outer, r0,
+                                      c.memo_Asig.ensure(nb), &asig_ok);
+        if (asig_ok) memo_store(c, bd, alpha, sigma_io);
+        else c.memo_valid = false;
         if (c.warm) c.warm->observe(gN, sigma_io);
         if (stats) stats->ms[2] = ms_since(t1);
         // u = (V[q] + DL[w sigma] + B C_self) / alpha^2 at the volume points

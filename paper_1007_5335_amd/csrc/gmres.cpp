@@ -21,7 +21,7 @@ double dot_host(Context &ctx, int64_t n, const double *a, const double *b, doubl
 }  // namespace
 
 GmresResult gmres(Context &ctx, const Apply &A, int64_t n, const double *b, double *x,
-                  bool zero_guess, double tol, int max_iter, int m) {
+                  bool zero_guess, double tol, int max_iter, int m, const double *r0) {
     GmresResult res;
     if (m < 1) m = 1;
     if (m > 120) m = 120;
@@ -42,6 +42,8 @@ GmresResult gmres(Context &ctx, const Apply &A, int64_t n, const double *b, doub
     if (zero_guess) {
         YK_HIP(hipMemsetAsync(x, 0, n * sizeof(double), ctx.stream));
         YK_HIP(hipMemcpyAsync(r, b, n * sizeof(double), hipMemcpyDeviceToDevice, ctx.stream));
+    } else if (r0) {
+        YK_HIP(hipMemcpyAsync(r, r0, n * sizeof(double), hipMemcpyDeviceToDevice, ctx.stream));
     } else {
         A(x, w);
         res.matvecs++;

@@ -191,6 +191,18 @@ void launch_mul(Context &ctx, int64_t n, const double *a, const double *b, doubl
     check_launch(ctx, "k_mul");
 }
 
+__global__ void k_differs(int64_t n, const double *__restrict__ a, const double *__restrict__ b,
+                          int *__restrict__ flag) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n && __double_as_longlong(a[i]) != __double_as_longlong(b[i])) *flag = 1;
+}
+
+void launch_differs(Context &ctx, int64_t n, const double *a, const double *b, int *flag) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_differs, dim3(nblk(n, 256)), dim3(256), 0, ctx.stream, n, a, b, flag);
+    check_launch(ctx, "k_differs");
+}
+
 void launch_axpby(Context &ctx, int64_t n, double ca, const double *a, double cb, const double *b,
                   double *out) {
     hipLaunchKernelGGL(k_axpby, dim3(nblk(n, 256)), dim3(256), 0, ctx.stream, n, ca, a, cb, b, out);

@@ -110,6 +110,16 @@ struct Context {
     std::vector<double> host_scal;
 
     struct WarmStart *warm = nullptr;       // attached learned warm start (not owned)
+
+    // last solution of the FP64 density operator and its image A sigma, so the
+    // next heat step gets the residual of the previous-step density for free
+    DevBuf<double> memo_sig, memo_Asig, memo_r1, memo_r2;
+    DevBuf<int> memo_flag;
+    bool memo_valid = false;
+    const double *memo_xy = nullptr;
+    int64_t memo_n = 0;
+    double memo_alpha = 0, memo_tol = 0;
+    int memo_p = 0, memo_leaf = 0, memo_direct = 0;
     DevBuf<double> ws_g, ws_ml, ws_t;       // heat-step buffers of the guess selection
 
     // second stream for the near field (overlaps the far-field chain) and the
@@ -187,8 +197,13 @@ struct GmresResult {
     bool converged = false;
 };
 // Solves A x = b; x holds the initial guess on entry (zero if zero_guess).
+// r0, when given (and zero_guess is false), is b - A x for that guess, which
+// saves the first operator application.  On return ctx.gm_r holds the true
+// residual b - A x of the returned x, unless b was zero.
 GmresResult gmres(Context &ctx, const Apply &A, int64_t n, const double *b, double *x,
-                  bool zero_guess, double tol, int max_iter, int m);
+                  bool zero_guess, double tol, int max_iter, int m, const double *r0 = nullptr);
+// flag = 1 if a and b differ anywhere (bitwise), on the context's stream
+void launch_differs(Context &ctx, int64_t n, const double *a, const double *b, int *flag);
 
 // -------------------------------------------------------------------- FMM ---
 // Evaluate V[q] + DL[dn] at targets with the cached plan.

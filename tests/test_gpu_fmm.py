@@ -280,3 +280,46 @@ def test_near_cache_matches_on_the_fly(yk, oracle_lib, precision):
     rv, rb = _oracle_fmm_potential(oracle_lib, c)
     ref = np.concatenate([rv, rb])
     assert rel_l2(outs[16384][0], ref) < (1e-10 if precision == "fp64" else 2e-5)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_heat_steps_reuse_previous_residual(yk, precision):
+    """Three steps of the C0 problem: passing back the returned density lets the
+    context reuse A sigma for the next step's initial residual (one operator
+    application fewer per step) with the same results as recomputing it (the
+    memo is dropped by re-setting the options before every step)."""
+    import torch
+    cfg = W.config_c0()
+    b = cfg["bnd"]
+    prec = yk.YK_PREC_MIXED if precision == "mixed" else yk.YK_PREC_FP64
+    runs = {}
+    for reuse in (True, False):
+        opt = yk.yk_default_options()
+        opt.leaf_size, opt.precision = 32, prec
+        ctx = yk.yk_create(opt)
+        try:
+            bd = yk.Boundary.from_workload(b)
+            n = cfg["vol"].shape[0]
+            vol, w, f = dev(cfg["vol"]), dev(cfg["vol_w"]), dev(cfg["f_next"])
+            B = dev(cfg["B"])
+            sig = torch.zeros(b.n, dtype=torch.float64, device="cuda")
+            u = torch.empty(n, dtype=torch.float64, device="cuda")
+            mv, us = [], []
+            for step in range(3):
+                if not reuse:
+                    yk.yk_set_options(ctx, opt)
+                print(f"step {step} reuse={reuse} {precision}", flush=True)
+                st = yk.yk_heat_step(ctx, bd, vol, w, B, yk.HEAT_GRID_SELF_CELL, f, cfg["dt"], 1e-12, sig, u)
+                torch.cuda.synchronize()
+                mv.append(st.matvecs)
+                us.append(host(u).copy())
+                B = u.clone()
+        finally:
+            yk.yk_destroy(ctx)
+        runs[reuse] = (mv, us, host(sig))
+    (mv1, u1, s1), (mv0, u0, s0) = runs[True], runs[False]
+    for a, c in zip(u1, u0):
+        assert rel_l2(a, c) < 1e-11
+    assert rel_l2(s1, s0) < 1e-10
+    # steps after the first skip one application of the FP64 operator
+    assert sum(mv1[1:]) <= sum(mv0[1:]) - 2, (mv1, mv0)
