@@ -107,6 +107,9 @@ struct FmmPlan {
     DevBuf<int32_t> ulist_off, ulist;  // CSR over leaves (leaf-local indices)
     std::vector<int32_t> h_lrange;     // host copy
     DevBuf<int32_t> pleaf;             // [N] leaf (level-local index) of every sorted point
+    // cached P2M rows: per charge [Pp], per dipole [2][Pp] (built on first use)
+    DevBuf<double> p2m_rq, p2m_rd, p2m_gs;
+    bool p2m_rows_built = false;
 
     // coefficients
     DevBuf<double> M, Lc;              // [nbox][Pp]

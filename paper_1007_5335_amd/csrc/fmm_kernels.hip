@@ -380,6 +380,117 @@ __global__ __launch_bounds__(64) void k_p2m_quad(
         for (int o = P + q4; o < Pp; o += 4) M[b * Pp + o] = 0.0;
 }
 
+// Cached P2M: the map from a point's strength to its leaf's multipole depends
+// on the point and the tree only.  k_p2m_rows writes, per sorted point, the
+// Pp coefficients it contributes per unit charge (charges) or per unit dipole
+// component (dipoles: one row for each of d.n's two components); k_p2m_apply
+// then forms every leaf's multipole as a sum of rows (one wavefront per leaf,
+// lane = coefficient, contiguous loads).  Padding entries are zero.
+__global__ __launch_bounds__(256) void k_p2m_rows(
+    int64_t n0, int64_t n1, int64_t off1, const int32_t *__restrict__ pleaf, int64_t leaf_base,
+    const double *__restrict__ bcx, const double *__restrict__ bcy, const double *__restrict__ px,
+    const double *__restrict__ py, double inv_alpha, double invR, const double *__restrict__ invFY,
+    const double *__restrict__ da, const double *__restrict__ db, const double *__restrict__ cnn,
+    const double *__restrict__ sc, int nser, int p, int Pp, double *__restrict__ rq,
+    double *__restrict__ rd, double *__restrict__ Gs) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n0 + n1) return;
+    const bool dip = i >= n0;
+    const int64_t j = dip ? off1 + (i - n0) : i;   // sorted point index
+    const int64_t b = leaf_base + pleaf[j];
+    const double wx = (px[j] - bcx[b]) * inv_alpha, wy = (py[j] - bcy[b]) * inv_alpha;
+    const double y = 0.25 * (wx * wx + wy * wy);
+    const double zx = wx * invR, zy = -wy * invR;   // conj(w)/R
+    // G_n = F_n(y)/F_n(Y), n = 0..p+1, in this thread's scratch row of Gs
+    double *G = Gs + i * (int64_t)(p + 2);
+    double F1, F2;
+    f_start(y, sc, nser, F1, F2);
+    G[p + 1] = F1 * invFY[p + 1];
+    for (int n = p; n >= 0; --n) {
+        const double F0 = F1 + y * F2 * cnn[n];
+        G[n] = F0 * invFY[n];
+        F2 = F1;
+        F1 = F0;
+    }
+    if (!dip) {
+        double *row = rq + i * (int64_t)Pp;
+        double pr = 1.0, pi = 0.0;     // conj(z)^n
+        for (int n = 0; n <= p; ++n) {
+            if (n == 0) {
+                row[0] = G[0];
+            } else {
+                row[2 * n - 1] = G[n] * pr;
+                row[2 * n] = G[n] * pi;
+            }
+            const double nr = pr * zx - pi * zy;
+            pi = pr * zy + pi * zx;
+            pr = nr;
+        }
+        for (int o = 2 * p + 1; o < Pp; ++o) row[o] = 0.0;
+    } else {
+        // term_n = h [a_n D Psi_{n+1} + b_n conj(D) Psi_{n-1}], D = Dx + i Dy:
+        // the rows hold the coefficients of Dx and of Dy
+        double *rx = rd + (i - n0) * 2 * (int64_t)Pp, *ry = rx + Pp;
+        const double h = 0.5 * inv_alpha;
+        double pr = zx, pi = zy;                       // conj(z)^1
+        double c_r = G[0], c_i = 0.0;                  // Psi_0
+        double n_r = G[1] * pr, n_i = G[1] * pi;       // Psi_1
+        double m_r = n_r, m_i = -n_i;                  // Psi_{-1} = conj(Psi_1)
+        for (int n = 0; n <= p; ++n) {
+            const double an = h * da[n], bn = h * db[n];
+            const double xr = an * n_r + bn * m_r, yr = -an * n_i + bn * m_i;
+            const double xi = an * n_i + bn * m_i, yi = an * n_r - bn * m_r;
+            if (n == 0) {
+                rx[0] = xr;
+                ry[0] = yr;
+            } else {
+                rx[2 * n - 1] = xr; ry[2 * n - 1] = yr;
+                rx[2 * n] = xi;     ry[2 * n] = yi;
+            }
+            m_r = c_r; m_i = c_i;
+            c_r = n_r; c_i = n_i;
+            const double nr = pr * zx - pi * zy;
+            pi = pr * zy + pi * zx;
+            pr = nr;
+            if (n + 2 <= p + 1) {
+                n_r = G[n + 2] * pr; n_i = G[n + 2] * pi;
+            } else {
+                n_r = 0.0; n_i = 0.0;
+            }
+        }
+        for (int o = 2 * p + 1; o < Pp; ++o) rx[o] = ry[o] = 0.0;
+    }
+}
+
+// one wavefront per leaf, four leaves per block; lanes over coefficients
+__global__ __launch_bounds__(256) void k_p2m_apply(
+    int64_t leaf_base, int64_t nleaf, const int32_t *__restrict__ lrange, int64_t off1, int has_q,
+    int has_d, const double *__restrict__ qs, const double *__restrict__ dns,
+    const double *__restrict__ rq, const double *__restrict__ rd, int P, int Pp, double *__restrict__ M) {
+    const int64_t li = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (li >= nleaf) return;
+    const int lane = threadIdx.x & 63;
+    const int64_t b = leaf_base + li;
+    for (int o = lane; o < Pp; o += 64) {
+        double acc = 0.0;
+        if (has_q) {
+            const int s0 = lrange[li * 6], e0 = lrange[li * 6 + 1];
+#pragma unroll 4
+            for (int j = s0; j < e0; ++j) acc = __builtin_fma(rq[(int64_t)j * Pp + o], qs[j], acc);
+        }
+        if (has_d) {
+            const int s1 = lrange[li * 6 + 2], e1 = lrange[li * 6 + 3];
+#pragma unroll 2
+            for (int j = s1; j < e1; ++j) {
+                const int64_t jd = j - off1;
+                const double *r = rd + jd * 2 * (int64_t)Pp + o;
+                acc = __builtin_fma(r[0], dns[2 * jd], __builtin_fma(r[Pp], dns[2 * jd + 1], acc));
+            }
+        }
+        M[b * Pp + o] = o < P ? acc : 0.0;
+    }
+}
+
 // ------------------------------------------------------------ M2M / L2L ---
 // Parent multipole from its children: M_b = sum_c S[pos(c)] M_c.
 __global__ __launch_bounds__(128) void k_m2m(int64_t pbegin, const int32_t *__restrict__ fchild,
@@ -1388,7 +1499,33 @@ void fmm_run(Context &ctx, FmmPlan &pl, const double *q, const double *dn, doubl
     if (far) {
         // upward pass
         {
+        // cached rows for small trees (there the compute kernel's chains are
+        // latency-bound; for large ones it beats reading the rows) when they
+        // fit the cache budget (built on first use)
+        const int64_t rows_bytes = (n0 + 2 * n1) * (int64_t)Pp * (int64_t)sizeof(double);
+        const bool p2m_cache = ctx.opt.near_cache_mb > 0 && pl.nleaf < 8192 &&
+                               rows_bytes <= ((int64_t)ctx.opt.near_cache_mb << 20);
+        if (p2m_cache && !pl.p2m_rows_built) {
+            StageTimer tb(ctx, YK_STAGE_NEAR_BUILD);
+            double *rq = pl.p2m_rq.ensure(std::max<int64_t>(n0 * Pp, 1));
+            double *rd = pl.p2m_rd.ensure(std::max<int64_t>(2 * n1 * Pp, 1));
+            double *gs = pl.p2m_gs.ensure(std::max<int64_t>((n0 + n1) * (p + 2), 1));
+            hipLaunchKernelGGL(k_p2m_rows, dim3(nblk(n0 + n1, 256)), dim3(256), 0, ctx.stream, n0, n1,
+                               pl.toff[1], pl.pleaf.p, leaf_base, pl.bcx.p, pl.bcy.p, pl.px.p, pl.py.p,
+                               inv_alpha, 1.0 / pl.lev[L].R, pl.invFY.p + L * lvl, pl.dipa.p + L * lvl,
+                               pl.dipb.p + L * lvl, pl.cnn.p, pl.serc.p, pl.nser, p, Pp, rq, rd, gs);
+            check_launch(ctx, "k_p2m_rows");
+            YK_HIP(hipStreamSynchronize(ctx.stream));
+            pl.p2m_gs.release();
+            pl.p2m_rows_built = true;
+        }
         StageTimer tm(ctx, YK_STAGE_P2M);
+        if (p2m_cache) {
+            hipLaunchKernelGGL(k_p2m_apply, dim3((unsigned)((pl.nleaf + 3) / 4)), dim3(256), 0, ctx.stream,
+                               leaf_base, pl.nleaf, pl.lrange.p, pl.toff[1], has_q, has_d, qs, dns,
+                               pl.p2m_rq.p, pl.p2m_rd.p, P, Pp, pl.M.p);
+            check_launch(ctx, "k_p2m_apply");
+        } else {
         const size_t tabs = (2 * (size_t)pl.nser + 4 * (size_t)(p + 2)) * sizeof(double);
         // four lanes per leaf for many leaves; sixteen (more parallelism per
         // leaf, shorter chains) when the leaves are too few to fill the GPU
@@ -1411,6 +1548,7 @@ void fmm_run(Context &ctx, FmmPlan &pl, const double *q, const double *dn, doubl
                                pl.serc.p, pl.nser, p, Pp, pl.M.p);
         }
         check_launch(ctx, "k_p2m");
+        }
         }
         launch_near();
         {
