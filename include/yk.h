@@ -64,7 +64,10 @@ typedef struct {
     int gmres_m;            /* Krylov dimension before a restart */
     int debug_flags;        /* bit0: synchronise and check after every kernel;
                                bit1: run the near field on the context's stream
-                               (no overlap with the far field; for timing) */
+                               (no overlap with the far field; for timing);
+                               bit2: capture the density operator in a HIP
+                               graph and replay it (off by default: slower
+                               than eager launches here) */
     int near_cache_mb;      /* device memory (MiB) a tree may spend on its cached
                                near-field interaction values; 0 = evaluate the
                                near-field kernels on every call */

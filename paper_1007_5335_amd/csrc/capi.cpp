@@ -1,5 +1,6 @@
 // capi.cpp -- the C ABI of libyk: argument checks, status codes, and the
 // drivers of the solve and of the heat step (Kropinski & Quaife, Sec. 2-3).
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <new>
@@ -26,6 +27,8 @@ Context::~Context() {
         (void)hipEventDestroy(pe.second.second);
     }
     for (hipEvent_t e : event_pool) (void)hipEventDestroy(e);
+    bie_graphs.clear();
+    if (cap_stream) (void)hipStreamDestroy(cap_stream);
     if (ev_fork) (void)hipEventDestroy(ev_fork);
     if (ev_join) (void)hipEventDestroy(ev_join);
     if (side) (void)hipStreamDestroy(side);
@@ -50,7 +53,7 @@ static hipEvent_t take_event(Context &ctx) {
 }
 
 StageTimer::StageTimer(Context &c, int s, hipStream_t on) : ctx(c), stage(s), st(on ? on : c.stream) {
-    if (!ctx.timing) return;
+    if (!ctx.timing || ctx.capturing) return;
     a = take_event(ctx);
     b = take_event(ctx);
     YK_HIP(hipEventRecord(a, st));
@@ -143,10 +146,8 @@ struct BieOperator {
     BoundaryData &bd;
     double alpha;
     SumPrec prec;
-    void operator()(const double *x, double *y) const {
+    void apply_eager(const double *x, double *y, double *dn, double *dl) const {
         const int64_t n = bd.n;
-        double *dn = ctx.dn.ensure(2 * n);
-        double *dl = ctx.ws_a.ensure(n);
         launch_dipole_vectors(ctx, n, bd.w.p, x, bd.normal, 1.0, dn);
         SumProblem pb;
         pb.n[1] = n;
@@ -156,6 +157,80 @@ struct BieOperator {
         evaluate_sums(ctx, SLOT_BND, pb, nullptr, dn, outs, prec);
         launch_dl_diagonal(ctx, n, bd.w.p, bd.curvature, x, dl);
         launch_bie_combine(ctx, n, x, dl, y);
+    }
+    // With debug_flags bit 2 the operator, applied many times per solve with
+    // the same tree, is captured once (after one eager application) into a
+    // HIP graph, kernels and the near-field stream fork included, and
+    // replayed: one launch instead of ~20.  Input and output go through the
+    // graph's own buffers.  Measured on MI355X with ROCm 7 the replay was
+    // slower than eager launches for the 28,672-node boundary tree, so it is
+    // off by default.  Debug synchronisation, direct sums or a failed capture
+    // keep it eager.
+    BieGraph *graph_for_plan() const {
+        if (ctx.opt.direct || (ctx.opt.debug_flags & 1) || !(ctx.opt.debug_flags & 4)) return nullptr;
+        SumProblem pb;
+        pb.n[1] = bd.n;
+        pb.xy[1] = bd.xy;
+        pb.alpha = alpha;
+        FmmPlan &pl = get_plan(ctx, SLOT_BND, pb);
+        for (auto &g : ctx.bie_graphs)
+            if (g->plan_gen == pl.gen && g->alpha == alpha && g->prec == (int)prec) return g.get();
+        // entries of other trees are stale
+        ctx.bie_graphs.erase(std::remove_if(ctx.bie_graphs.begin(), ctx.bie_graphs.end(),
+                                            [&](const std::unique_ptr<BieGraph> &g) { return g->plan_gen != pl.gen; }),
+                             ctx.bie_graphs.end());
+        auto g = std::make_unique<BieGraph>();
+        g->plan_gen = pl.gen;
+        g->alpha = alpha;
+        g->prec = (int)prec;
+        ctx.bie_graphs.push_back(std::move(g));
+        return ctx.bie_graphs.back().get();
+    }
+    void capture(BieGraph &g) const {
+        const int64_t n = bd.n;
+        g.x.ensure(n);
+        g.y.ensure(n);
+        g.dn.ensure(2 * n);
+        g.dl.ensure(n);
+        YK_HIP(hipMemsetAsync(g.x.p, 0, n * sizeof(double), ctx.stream));
+        YK_HIP(hipStreamSynchronize(ctx.stream));
+        if (!ctx.cap_stream) YK_HIP(hipStreamCreateWithFlags(&ctx.cap_stream, hipStreamNonBlocking));
+        hipStream_t saved = ctx.stream;
+        ctx.stream = ctx.cap_stream;
+        ctx.capturing = true;
+        hipGraph_t graph = nullptr;
+        bool ok = hipStreamBeginCapture(ctx.stream, hipStreamCaptureModeThreadLocal) == hipSuccess;
+        if (ok) {
+            try {
+                apply_eager(g.x.p, g.y.p, g.dn.p, g.dl.p);
+            } catch (...) {
+                ok = false;
+            }
+            const hipError_t e = hipStreamEndCapture(ctx.stream, &graph);
+            ok = ok && e == hipSuccess && graph != nullptr;
+        }
+        ctx.stream = saved;
+        ctx.capturing = false;
+        if (ok) ok = hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0) == hipSuccess;
+        if (graph) (void)hipGraphDestroy(graph);
+        if (!ok) {
+            g.failed = true;
+            g.exec = nullptr;
+            (void)hipGetLastError();
+        }
+    }
+    void operator()(const double *x, double *y) const {
+        const int64_t n = bd.n;
+        BieGraph *g = graph_for_plan();
+        if (g && !g->failed && !g->exec && g->runs >= 1) capture(*g);
+        if (g && g->exec) {
+            YK_HIP(hipMemcpyAsync(g->x.p, x, n * sizeof(double), hipMemcpyDeviceToDevice, ctx.stream));
+            YK_HIP(hipGraphLaunch(g->exec, ctx.stream));
+            YK_HIP(hipMemcpyAsync(y, g->y.p, n * sizeof(double), hipMemcpyDeviceToDevice, ctx.stream));
+            return;
+        }
+        if (g) g->runs++;
+        apply_eager(x, y, ctx.dn.ensure(2 * n), ctx.ws_a.ensure(n));
     }
 };
 

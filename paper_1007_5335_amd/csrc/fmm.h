@@ -125,6 +125,7 @@ struct FmmPlan {
 
     double build_ms = 0;
     bool fresh = false;
+    uint64_t gen = 0;                  // unique per plan built in this process
     int last_mask = 0;
     int last_has_q = 0, last_has_d = 0;
 };
@@ -140,5 +141,8 @@ int choose_order(double tol);
 // fmm_kernels.hip
 void fmm_run(Context &ctx, FmmPlan &pl, const double *q, const double *dn, double *const out[3],
              SumPrec prec);
+
+// The tree of a slot for this problem (built, or rebuilt when stale).
+FmmPlan &get_plan(Context &ctx, PlanSlot slot, const SumProblem &pb);
 
 }  // namespace yk

@@ -1,6 +1,8 @@
 // fmm.hip -- FMM backend of the kernel sums: plan cache and evaluation.
 #include <chrono>
 
+#include <atomic>
+
 #include "fmm.h"
 
 namespace yk {
@@ -38,6 +40,8 @@ FmmPlan &get_plan(Context &ctx, PlanSlot slot, const SumProblem &pb) {
         pl->key_n[s] = pb.n[s];
         pl->key_xy[s] = pb.n[s] ? pb.xy[s] : nullptr;
     }
+    static std::atomic<uint64_t> plan_gen{0};
+    pl->gen = ++plan_gen;
     pl->alpha = pb.alpha;
     pl->opt_p = ctx.opt.p;
     pl->opt_leaf = ctx.opt.leaf_size;

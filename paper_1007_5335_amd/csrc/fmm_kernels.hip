@@ -1580,7 +1580,8 @@ void fmm_run(Context &ctx, FmmPlan &pl, const double *q, const double *dn, doubl
             check_launch(ctx, "k_to_float");
         }
         // downward pass
-        YK_HIP(hipMemsetAsync(pl.Lc.p, 0, (size_t)pl.nbox * Pp * sizeof(double), ctx.stream));
+        // a fill kernel rather than a memset node: this pass may be captured in a graph
+        launch_fill(ctx, (int64_t)pl.nbox * Pp, 0.0, pl.Lc.p);
         if (Pp <= 64) {
             {
                 // M2L of every level at once (levels are independent given the multipoles)

@@ -191,6 +191,17 @@ void launch_mul(Context &ctx, int64_t n, const double *a, const double *b, doubl
     check_launch(ctx, "k_mul");
 }
 
+__global__ void k_fill(int64_t n, double v, double *__restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = v;
+}
+
+void launch_fill(Context &ctx, int64_t n, double v, double *out) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_fill, dim3(nblk(n, 256)), dim3(256), 0, ctx.stream, n, v, out);
+    check_launch(ctx, "k_fill");
+}
+
 __global__ void k_differs(int64_t n, const double *__restrict__ a, const double *__restrict__ b,
                           int *__restrict__ flag) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;

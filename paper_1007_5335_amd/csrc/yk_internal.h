@@ -89,6 +89,22 @@ struct PlanDeleter {
 };
 using PlanPtr = std::unique_ptr<FmmPlan, PlanDeleter>;
 
+// A captured application of the density operator for one boundary tree
+// (plan generation), alpha and precision, with its own input, output and
+// work buffers (the graph holds their addresses).
+struct BieGraph {
+    uint64_t plan_gen = 0;
+    double alpha = 0;
+    int prec = 0;
+    int runs = 0;            // eager applications so far (capture after the first)
+    bool failed = false;     // capture or instantiation failed: stay eager
+    hipGraphExec_t exec = nullptr;
+    DevBuf<double> x, y, dn, dl;
+    ~BieGraph() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+    }
+};
+
 struct Context {
     yk_options opt{};
     hipStream_t stream = nullptr;
@@ -126,6 +142,11 @@ struct Context {
     // fork/join events that order it against the context's stream
     hipStream_t side = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+
+    // graph replays of the density operator (see BieGraph in capi.cpp)
+    bool capturing = false;                 // a stream capture is in progress
+    hipStream_t cap_stream = nullptr;
+    std::vector<std::unique_ptr<BieGraph>> bie_graphs;
 
     // optional per-stage event timing
     bool timing = false;
@@ -202,6 +223,8 @@ struct GmresResult {
 // residual b - A x of the returned x, unless b was zero.
 GmresResult gmres(Context &ctx, const Apply &A, int64_t n, const double *b, double *x,
                   bool zero_guess, double tol, int max_iter, int m, const double *r0 = nullptr);
+// out[i] = v for i < n
+void launch_fill(Context &ctx, int64_t n, double v, double *out);
 // flag = 1 if a and b differ anywhere (bitwise), on the context's stream
 void launch_differs(Context &ctx, int64_t n, const double *a, const double *b, int *flag);
 

@@ -323,3 +323,36 @@ def test_heat_steps_reuse_previous_residual(yk, precision):
     assert rel_l2(s1, s0) < 1e-10
     # steps after the first skip one application of the FP64 operator
     assert sum(mv1[1:]) <= sum(mv0[1:]) - 2, (mv1, mv0)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_density_operator_graph_replay(yk, oracle_lib, precision):
+    """The density operator captured in a HIP graph and replayed (many times per
+    solve, with the solver's own kernels and host synchronisations between
+    replays, and again in a second solve) gives the eager operator's solution."""
+    import torch
+    c = W.small_fmm_case(n_vol=16, n_nodes=256, alpha=0.05, seed=2)
+    b = c["bnd"]
+    g1 = np.sin(4 * b.xy[:, 0]) * np.cos(3 * b.xy[:, 1])
+    g2 = np.cos(2 * b.xy[:, 0]) + b.xy[:, 1] ** 2
+    prec = yk.YK_PREC_MIXED if precision == "mixed" else yk.YK_PREC_FP64
+    sols = {}
+    for flags in (4, 0):          # 4: graph replay, 0: eager operator
+        ctx = _ctx(yk, leaf_size=32, precision=prec, debug_flags=flags)
+        try:
+            bd = yk.Boundary.from_workload(b)
+            out = []
+            for g in (g1, g2, g1):
+                sig = torch.empty(b.n, dtype=torch.float64, device="cuda")
+                print(f"graph replay flags={flags} {precision}", flush=True)
+                st = yk.yk_gmres_density(ctx, bd, 0.05, dev(g), None, 1e-12, 200, sig)
+                torch.cuda.synchronize()
+                out.append((host(sig).copy(), st.iters))
+        finally:
+            yk.yk_destroy(ctx)
+        sols[flags] = out
+    ref1 = oracle_lib.DenseBIE(b.xy, b.normal, b.weights(), b.curvature, 0.05).solve(g1)
+    for (s_g, it_g), (s_e, it_e) in zip(sols[4], sols[0]):
+        assert rel_l2(s_g, s_e) < 1e-11
+    assert rel_l2(sols[4][0][0], ref1) < 1e-10
+    assert rel_l2(sols[4][2][0], ref1) < 1e-10
