@@ -663,13 +663,17 @@ __global__ __launch_bounds__(256) void k_tile_gemm(const int4 *__restrict__ tile
     constexpr int NB = SPLIT ? PP / 16 - 1 : PP / 16;   // 16-row blocks on the matrix cores
     constexpr int SP = 16 * NB;                         // split-off index (SPLIT only)
     constexpr int NKP = 2 * NB;                         // contraction pairs
-    // operator pairs per thread (PP = 16: 128 pairs, half the threads load one)
-    constexpr int NL2 = PP * PP >= 512 ? PP * PP / 512 : 1;
-    constexpr int kPairs = PP * PP / 2;
+    // LDS copy of the operator: the NCOL columns used, each LDA rows (with the
+    // split, 49 x 52 instead of 64 x 64 for p = 24: less LDS, so three
+    // workgroups fit a compute unit, and a column stride off the bank period)
+    constexpr int NCOL = SPLIT ? SP + 1 : PP;
+    constexpr int LDA = SPLIT ? ((SP + 1 + 3) & ~3) : PP;
+    constexpr int kPairs = NCOL * LDA / 2;              // operator pairs per slot
+    constexpr int NL2 = (kPairs + 255) / 256;           // pairs per thread
     constexpr int kMaxSlot = 27;
     using V2 = typename Pair2<TS>::type;
     using T2 = typename Pair2<T>::type;
-    __shared__ T As[2][PP * PP];
+    __shared__ T As[2][NCOL * LDA];
     __shared__ int32_t s_src[kMaxSlot * 64];
     using MF = Mfma<T>;
     // nparts > 1 (few tiles): the slots of a tile are shared among nparts
@@ -700,6 +704,8 @@ __global__ __launch_bounds__(256) void k_tile_gemm(const int4 *__restrict__ tile
     auto op_of = [&](int sl) -> const T2 * {
         return reinterpret_cast<const T2 *>(Olev + (size_t)slot_op[cls * nslot + sl] * PP * PP);
     };
+    // global pair of LDS pair e (column-major, PP rows per column in memory)
+    auto gpair = [&](int e) { return (e / (LDA / 2)) * (PP / 2) + e % (LDA / 2); };
     // B fragment of a slot: unconditional loads (row 0 stands in for an empty
     // slot) and the empty slot's zeros selected when the fragment is consumed,
     // so the loads of the next slot stay in flight during the current one (a
@@ -733,7 +739,7 @@ __global__ __launch_bounds__(256) void k_tile_gemm(const int4 *__restrict__ tile
         T2 *Ad = reinterpret_cast<T2 *>(As[0]);
 #pragma unroll
         for (int e = 0; e < NL2; ++e)
-            if (kPairs >= 256 * NL2 || tid + 256 * e < kPairs) Ad[tid + 256 * e] = Tg[tid + 256 * e];
+            if (kPairs >= 256 * NL2 || tid + 256 * e < kPairs) Ad[tid + 256 * e] = Tg[gpair(tid + 256 * e)];
     }
     take_b();
     __syncthreads();
@@ -745,18 +751,18 @@ __global__ __launch_bounds__(256) void k_tile_gemm(const int4 *__restrict__ tile
             const T2 *Tg = op_of(slot + 1);
 #pragma unroll
             for (int e = 0; e < NL2; ++e)
-                if (kPairs >= 256 * NL2 || tid + 256 * e < kPairs) pre[e] = Tg[tid + 256 * e];
+                if (kPairs >= 256 * NL2 || tid + 256 * e < kPairs) pre[e] = Tg[gpair(tid + 256 * e)];
         }
-        // operator column-major: A[i][k] = As[k * PP + i]; step (kp, e) takes
+        // operator column-major: A[i][k] = As[k * LDA + i]; step (kp, e) takes
         // contraction index 8 kp + 2 g + e in lane group g
-        const T *Ac = As[cur] + 2 * g * PP + (lane & 15);
+        const T *Ac = As[cur] + 2 * g * LDA + (lane & 15);
 #pragma unroll
         for (int kp = 0; kp < NKP; ++kp) {
 #pragma unroll
             for (int e = 0; e < 2; ++e) {
 #pragma unroll
                 for (int rt = 0; rt < NB; ++rt)
-                    acc[rt] = MF::step(Ac[(8 * kp + e) * PP + 16 * rt], bcur[2 * kp + e], acc[rt]);
+                    acc[rt] = MF::step(Ac[(8 * kp + e) * LDA + 16 * rt], bcur[2 * kp + e], acc[rt]);
             }
         }
         if constexpr (SPLIT) {
@@ -766,12 +772,12 @@ __global__ __launch_bounds__(256) void k_tile_gemm(const int4 *__restrict__ tile
 #pragma unroll
             for (int kp = 0; kp < NKP; ++kp)
 #pragma unroll
-                for (int e = 0; e < 2; ++e) rowacc += A[(8 * kp + 2 * g + e) * PP + SP] * bcur[2 * kp + e];
-            if (g == 0) rowacc += A[SP * PP + SP] * bs;
+                for (int e = 0; e < 2; ++e) rowacc += A[(8 * kp + 2 * g + e) * LDA + SP] * bcur[2 * kp + e];
+            if (g == 0) rowacc += A[SP * LDA + SP] * bs;
 #pragma unroll
             for (int rt = 0; rt < NB; ++rt)
 #pragma unroll
-                for (int q = 0; q < 4; ++q) colacc[rt][q] += A[SP * PP + 16 * rt + MF::row(lane, q)] * bs;
+                for (int q = 0; q < 4; ++q) colacc[rt][q] += A[SP * LDA + 16 * rt + MF::row(lane, q)] * bs;
         }
         if (more) {
             T2 *Ad = reinterpret_cast<T2 *>(As[cur ^ 1]);
@@ -907,8 +913,9 @@ void launch_small_gemv(Context &ctx, int Pp, int ns, int64_t nbox, const int32_t
     check_launch(ctx, "k_small_gemv");
 }
 
-// levels with at most this many boxes take k_small_gemv for M2M and L2L
-constexpr int64_t kSmallLevel = 4096;
+// levels with at most this many boxes take k_small_gemv for M2M (4 operators
+// per box: beyond ~1000 boxes the tile GEMM's shared operators win) and L2L
+constexpr int64_t kSmallLevelM2M = 1024, kSmallLevelL2L = 4096;
 
 __global__ void k_to_float(int64_t n, const double *__restrict__ a, float *__restrict__ b) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1555,7 +1562,7 @@ void fmm_run(Context &ctx, FmmPlan &pl, const double *q, const double *dn, doubl
             StageTimer tmm(ctx, YK_STAGE_M2M);
             for (int l = L - 1; l >= pl.lmin; --l) {
                 const int64_t nbl = pl.lev[l].end - pl.lev[l].begin;
-                if (Pp <= 64 && nbl <= kSmallLevel) {
+                if (Pp <= 64 && nbl <= kSmallLevelM2M) {
                     launch_small_gemv(ctx, Pp, 4, nbl, nullptr, pl.lev[l].begin, pl.child4.p, pl.bcode.p,
                                       pl.m2m.p + (size_t)l * 4 * Pp * Pp, pl.M.p, P, 1, pl.M.p);
                 } else if (Pp <= 64) {
@@ -1598,7 +1605,7 @@ void fmm_run(Context &ctx, FmmPlan &pl, const double *q, const double *dn, doubl
             StageTimer tl2(ctx, YK_STAGE_L2L);
             for (int l = pl.lmin + 1; l <= L; ++l) {
                 // L2L top-down: one parent slot, operator E[l-1][position]
-                if (as.l2l_count[l] <= kSmallLevel) {
+                if (as.l2l_count[l] <= kSmallLevelL2L) {
                     launch_small_gemv(ctx, Pp, 1, as.l2l_count[l], as.l2l_boxes.p + as.l2l_begin[l], 0,
                                       pl.bparent.p, pl.bcode.p, pl.l2l.p + (size_t)(l - 1) * 4 * Pp * Pp,
                                       pl.Lc.p, P, 0, pl.Lc.p);
