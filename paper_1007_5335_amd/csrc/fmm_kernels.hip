@@ -1296,17 +1296,39 @@ __global__ __launch_bounds__(64) void k_near_apply(
             }
             __syncthreads();
             if (!it.valid) continue;
+            // the values are read once per pass: eight loads in flight per lane
+            // (explicitly, the trip count is data dependent), non-temporal
+            const int gs = it.g;
+            const int64_t cs = (int64_t)it.c * gs;   // element stride of one pass
             if (set == 0) {
-                const VT *Mb = Mq + qoff[ib] + (int64_t)c0 * it.c + it.ti;
-#pragma unroll 4
-                for (int j = it.sub; j < cn; j += it.g) near_q = __builtin_fma((double)Mb[(int64_t)j * it.c], s_a[j], near_q);
-            } else {
-                const V2 *Mb = reinterpret_cast<const V2 *>(Md) + doff[ib] + (int64_t)c0 * it.c + it.ti;
-#pragma unroll 4
-                for (int j = it.sub; j < cn; j += it.g) {
-                    const V2 m = Mb[(int64_t)j * it.c];
-                    near_d = __builtin_fma((double)m.x, s_a[j], __builtin_fma((double)m.y, s_b[j], near_d));
+                const VT *Mb = Mq + qoff[ib] + (int64_t)c0 * it.c + it.ti + (int64_t)it.sub * it.c;
+                int j = it.sub;
+                for (; j + 7 * gs < cn; j += 8 * gs, Mb += 8 * cs) {
+                    VT m[8];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) m[u] = __builtin_nontemporal_load(Mb + u * cs);
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) near_q = __builtin_fma((double)m[u], s_a[j + u * gs], near_q);
                 }
+                for (; j < cn; j += gs, Mb += cs) near_q = __builtin_fma((double)__builtin_nontemporal_load(Mb), s_a[j], near_q);
+            } else {
+                const VT *Mb = Md + 2 * (doff[ib] + (int64_t)c0 * it.c + it.ti + (int64_t)it.sub * it.c);
+                int j = it.sub;
+                for (; j + 3 * gs < cn; j += 4 * gs, Mb += 8 * cs) {
+                    VT mx[4], my[4];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        mx[u] = __builtin_nontemporal_load(Mb + 2 * u * cs);
+                        my[u] = __builtin_nontemporal_load(Mb + 2 * u * cs + 1);
+                    }
+#pragma unroll
+                    for (int u = 0; u < 4; ++u)
+                        near_d = __builtin_fma((double)mx[u], s_a[j + u * gs],
+                                               __builtin_fma((double)my[u], s_b[j + u * gs], near_d));
+                }
+                for (; j < cn; j += gs, Mb += 2 * cs)
+                    near_d = __builtin_fma((double)__builtin_nontemporal_load(Mb), s_a[j],
+                                           __builtin_fma((double)__builtin_nontemporal_load(Mb + 1), s_b[j], near_d));
             }
         }
     }
