@@ -155,8 +155,7 @@ struct BieOperator {
         pb.alpha = alpha;
         double *const outs[3] = {nullptr, dl, nullptr};
         evaluate_sums(ctx, SLOT_BND, pb, nullptr, dn, outs, prec);
-        launch_dl_diagonal(ctx, n, bd.w.p, bd.curvature, x, dl);
-        launch_bie_combine(ctx, n, x, dl, y);
+        launch_bie_finish(ctx, n, bd.w.p, bd.curvature, x, dl, y);
     }
     // With debug_flags bit 2 the operator, applied many times per solve with
     // the same tree, is captured once (after one eager application) into a

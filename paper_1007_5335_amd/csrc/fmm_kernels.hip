@@ -1375,7 +1375,9 @@ __global__ __launch_bounds__(256) void k_l2p(
     int64_t leaf_base, const double *__restrict__ bcx, const double *__restrict__ bcy,
     const double *__restrict__ px, const double *__restrict__ py, const double *__restrict__ Lc,
     double inv_alpha, double invR, const double *__restrict__ invFY, const double *__restrict__ cnn,
-    const double *__restrict__ sc, int nser, int p, int Pp, double *__restrict__ outs) {
+    const double *__restrict__ sc, int nser, int p, int Pp, const double *__restrict__ outs,
+    const int32_t *__restrict__ perm, double *__restrict__ out0, double *__restrict__ out1,
+    double *__restrict__ out2) {
     extern __shared__ double dyn[];
     double *t_cnn = dyn;               // [p+1]
     double *t_ify = t_cnn + p + 1;     // [p+1]
@@ -1410,7 +1412,10 @@ __global__ __launch_bounds__(256) void k_l2p(
         F1 = F0;
     }
     const double F0 = F1 + yv * F2 * t_cnn[0];
-    outs[t] += (Lb[0] * F0 * t_ify[0] + 2.0 * (sr * zx - si * zy)) * kInv2Pi;
+    // near field + far field, written straight to the caller's array of the set
+    const double v = outs[t] + (Lb[0] * F0 * t_ify[0] + 2.0 * (sr * zx - si * zy)) * kInv2Pi;
+    double *o = set == 0 ? out0 : set == 1 ? out1 : out2;
+    o[perm[t]] = v;
 }
 
 LeafKernel pick_leaf_kernel(int nt, bool small_only, bool f32) {
@@ -1670,8 +1675,9 @@ void fmm_run(Context &ctx, FmmPlan &pl, const double *q, const double *dn, doubl
         hipLaunchKernelGGL(k_l2p, dim3(nblk(pl.N, 256)), dim3(256), lsh, ctx.stream, pl.N, pl.toff[1],
                            pl.toff[2], mask, pl.pleaf.p, leaf_base, pl.bcx.p, pl.bcy.p, pl.px.p, pl.py.p,
                            pl.Lc.p, inv_alpha, 1.0 / pl.lev[L].R, pl.invFY.p + L * lvl, pl.cnn.p,
-                           pl.serc.p, pl.nser, p, Pp, outs);
+                           pl.serc.p, pl.nser, p, Pp, outs, pl.perm.p, out[0], out[1], out[2]);
         check_launch(ctx, "k_l2p");
+        return;   // L2P wrote the outputs
     }
     StageTimer tsc(ctx, YK_STAGE_SCATTER);
     for (int s = 0; s < 3; ++s) {

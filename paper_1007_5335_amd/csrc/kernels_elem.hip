@@ -87,6 +87,16 @@ __global__ void k_bie_combine(int64_t n, const double *__restrict__ x,
     y[i] = x[i] - 2.0 * dl[i];
 }
 
+// y = x - 2 (dl + w (-kappa/2) x / (2 pi)): the diagonal limit and the
+// combination of the second-kind operator in one pass
+__global__ void k_bie_finish(int64_t n, const double *__restrict__ w, const double *__restrict__ kappa,
+                             const double *__restrict__ x, const double *__restrict__ dl,
+                             double *__restrict__ y) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    y[i] = x[i] - 2.0 * (dl[i] + w[i] * (-0.5 * kappa[i]) * x[i] * kInv2Pi);
+}
+
 __global__ void k_mul(int64_t n, const double *__restrict__ a, const double *__restrict__ b,
                       double *__restrict__ o) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -184,6 +194,12 @@ void launch_dl_diagonal(Context &ctx, int64_t n, const double *w, const double *
 void launch_bie_combine(Context &ctx, int64_t n, const double *x, const double *dl, double *y) {
     hipLaunchKernelGGL(k_bie_combine, dim3(nblk(n, 256)), dim3(256), 0, ctx.stream, n, x, dl, y);
     check_launch(ctx, "k_bie_combine");
+}
+
+void launch_bie_finish(Context &ctx, int64_t n, const double *w, const double *kappa, const double *x,
+                       const double *dl, double *y) {
+    hipLaunchKernelGGL(k_bie_finish, dim3(nblk(n, 256)), dim3(256), 0, ctx.stream, n, w, kappa, x, dl, y);
+    check_launch(ctx, "k_bie_finish");
 }
 
 void launch_mul(Context &ctx, int64_t n, const double *a, const double *b, double *out) {

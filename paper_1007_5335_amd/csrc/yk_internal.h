@@ -184,6 +184,9 @@ void launch_dl_diagonal(Context &ctx, int64_t n, const double *w, const double *
 // y = x - 2 * dl  (dl already includes 1/(2pi) and the diagonal)
 void launch_bie_combine(Context &ctx, int64_t n, const double *x, const double *dl, double *y);
 void launch_mul(Context &ctx, int64_t n, const double *a, const double *b, double *out);
+// y = x - 2 (dl + w (-kappa/2) x / (2 pi))  (diagonal limit + combination)
+void launch_bie_finish(Context &ctx, int64_t n, const double *w, const double *kappa, const double *x,
+                       const double *dl, double *y);
 // out = ca * a + cb * b  (b may be null -> out = ca * a)
 void launch_axpby(Context &ctx, int64_t n, double ca, const double *a, double cb, const double *b,
                   double *out);
