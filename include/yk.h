@@ -64,7 +64,9 @@ typedef struct {
     int gmres_m;            /* Krylov dimension before a restart */
     int debug_flags;        /* bit0: synchronise and check after every kernel;
                                bit1: run the near field on the context's stream
-                               (no overlap with the far field; for timing);
+                               (by default a tree of fewer than 8192 leaves
+                               runs it on a second stream, overlapped with the
+                               far field; larger trees always run it in turn);
                                bit2: capture the density operator in a HIP
                                graph and replay it (off by default: slower
                                than eager launches here) */

@@ -297,14 +297,22 @@ __global__ __launch_bounds__(64) void k_p2m_quad(
         if ((set == 0 && !has_q) || (set == 1 && !has_d)) continue;
         const int s0 = leaf_ok ? lrange[li * 6 + 2 * set] : 0;
         const int e0 = leaf_ok ? lrange[li * 6 + 2 * set + 1] : 0;
+        // a lane without a point reads a point of its own set (weight 0
+        // below): the leaf's first, else the set's first (index 0 or off1)
+        auto clamp_j = [&](int j) { return j < e0 ? j : (e0 > s0 ? s0 : (set == 0 ? 0 : (int)off1)); };
+        // the next point's coordinates are loaded one iteration ahead
+        int jn = clamp_j(s0 + q4);
+        double nx = px[jn], ny = py[jn];
         for (int j0 = s0;; j0 += 4) {
             const int j = j0 + q4;
             const bool valid = j < e0;
             if (!__any(valid)) break;
-            // a lane without a point reads a point of its own set (weight 0
-            // below): the leaf's first, else the set's first (index 0 or off1)
-            const int jc = valid ? j : (e0 > s0 ? s0 : (set == 0 ? 0 : (int)off1));
-            const double wx = (px[jc] - cx) * inv_alpha, wy = (py[jc] - cy) * inv_alpha;
+            const int jc = jn;
+            const double cxp = nx, cyp = ny;
+            jn = clamp_j(j + 4);
+            nx = px[jn];
+            ny = py[jn];
+            const double wx = (cxp - cx) * inv_alpha, wy = (cyp - cy) * inv_alpha;
             const double y = 0.25 * (wx * wx + wy * wy);
             const double zx = wx * invR, zy = -wy * invR;   // conj(w)/R
             double F1, F2;
@@ -1467,7 +1475,9 @@ void fmm_run(Context &ctx, FmmPlan &pl, const double *q, const double *dn, doubl
     // near field: independent of the far field until L2P, so it runs on the
     // side stream while M2M, M2L and L2L run on the main one (forked after P2M,
     // which would otherwise be starved of compute units)
-    const bool overlap = !(ctx.opt.debug_flags & 2);
+    // (only for small trees: with a large one both streams fill the GPU and
+    // sharing it was measured slower than running the stages in turn)
+    const bool overlap = !(ctx.opt.debug_flags & 2) && pl.nleaf < 8192;
     bool near_done = false;
     auto launch_near = [&]() {
         near_done = true;
