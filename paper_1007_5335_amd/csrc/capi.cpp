@@ -290,8 +290,12 @@ GmresResult solve_density(Context &ctx, BoundaryData &bd, double alpha, const do
             break;
         }
         if (tot.iters >= max_iter) break;
-        // inner FP32-operator solve to a modest relative tolerance
-        GmresResult in = gmres(ctx, A32, n, r, delta, true, 1e-5, max_iter - tot.iters, ctx.opt.gmres_m);
+        // inner FP32-operator solve: to the reduction that would finish the
+        // solve in this sweep (with a factor 2 to spare), but not below what
+        // an FP32 operator resolves (about 1e-6 relative, so a residual far
+        // above tol takes further sweeps) nor above 1e-4
+        const double inner_tol = std::min(1e-4, std::max(2e-6, 0.5 * tol * bnorm / rn));
+        GmresResult in = gmres(ctx, A32, n, r, delta, true, inner_tol, max_iter - tot.iters, ctx.opt.gmres_m);
         tot.iters += in.iters;
         tot.matvecs += in.matvecs;
         launch_axpby(ctx, n, 1.0, sigma, 1.0, delta, sigma);
@@ -631,8 +635,8 @@ yk_status yk_heat_step(yk_ctx ctx, const yk_boundary *bnd, int64_t n_vol, const 
             double *outs[3] = {u_next, nullptr, nullptr};
             evaluate_sums(c, SLOT_VOL, pb, q, dn, outs, vprec);
         }
-        if (flags & 1) launch_self_cell(c, n_vol, vol_w, B, alpha, u_next);
-        launch_axpby(c, n_vol, 1.0 / a2, u_next, 0.0, nullptr, u_next);
+        if (flags & 1) launch_self_cell(c, n_vol, vol_w, B, alpha, 1.0 / a2, u_next);
+        else launch_axpby(c, n_vol, 1.0 / a2, u_next, 0.0, nullptr, u_next);
         YK_HIP(hipStreamSynchronize(c.stream));
         if (stats) stats->ms[3] = ms_since(t2);
         fill_stats(stats, r, outer, guess);

@@ -470,32 +470,42 @@ __global__ __launch_bounds__(256) void k_p2m_rows(
     }
 }
 
-// one wavefront per leaf, four leaves per block; lanes over coefficients
+// one block of four wavefronts per leaf, lanes over coefficients: wavefront w
+// sums the leaf's points w, w + 4, ... (two chains per lane) and the four
+// partial rows are added through LDS
 __global__ __launch_bounds__(256) void k_p2m_apply(
     int64_t leaf_base, int64_t nleaf, const int32_t *__restrict__ lrange, int64_t off1, int has_q,
     int has_d, const double *__restrict__ qs, const double *__restrict__ dns,
     const double *__restrict__ rq, const double *__restrict__ rd, int P, int Pp, double *__restrict__ M) {
-    const int64_t li = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (li >= nleaf) return;
-    const int lane = threadIdx.x & 63;
+    __shared__ double part[4][64];
+    const int64_t li = blockIdx.x;
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int64_t b = leaf_base + li;
-    for (int o = lane; o < Pp; o += 64) {
-        double acc = 0.0;
-        if (has_q) {
-            const int s0 = lrange[li * 6], e0 = lrange[li * 6 + 1];
-#pragma unroll 4
-            for (int j = s0; j < e0; ++j) acc = __builtin_fma(rq[(int64_t)j * Pp + o], qs[j], acc);
-        }
-        if (has_d) {
-            const int s1 = lrange[li * 6 + 2], e1 = lrange[li * 6 + 3];
-#pragma unroll 2
-            for (int j = s1; j < e1; ++j) {
+    const int s0 = lrange[li * 6], e0 = has_q ? lrange[li * 6 + 1] : s0;
+    const int s1 = lrange[li * 6 + 2], e1 = has_d ? lrange[li * 6 + 3] : s1;
+    for (int ob = 0; ob < Pp; ob += 64) {
+        const int o = ob + lane;
+        double a0 = 0.0, a1 = 0.0;
+        if (o < Pp) {
+            for (int j = s0 + w; j < e0; j += 8) {
+                a0 = __builtin_fma(rq[(int64_t)j * Pp + o], qs[j], a0);
+                if (j + 4 < e0) a1 = __builtin_fma(rq[(int64_t)(j + 4) * Pp + o], qs[j + 4], a1);
+            }
+            for (int j = s1 + w; j < e1; j += 8) {
                 const int64_t jd = j - off1;
                 const double *r = rd + jd * 2 * (int64_t)Pp + o;
-                acc = __builtin_fma(r[0], dns[2 * jd], __builtin_fma(r[Pp], dns[2 * jd + 1], acc));
+                a0 = __builtin_fma(r[0], dns[2 * jd], __builtin_fma(r[Pp], dns[2 * jd + 1], a0));
+                if (j + 4 < e1) {
+                    const double *r4 = r + 8 * (int64_t)Pp;
+                    a1 = __builtin_fma(r4[0], dns[2 * jd + 8], __builtin_fma(r4[Pp], dns[2 * jd + 9], a1));
+                }
             }
         }
-        M[b * Pp + o] = o < P ? acc : 0.0;
+        part[w][lane] = a0 + a1;
+        __syncthreads();
+        if (w == 0 && o < Pp)
+            M[b * Pp + o] = o < P ? (part[0][lane] + part[1][lane]) + (part[2][lane] + part[3][lane]) : 0.0;
+        __syncthreads();
     }
 }
 
@@ -858,42 +868,54 @@ void launch_tile_gemm(Context &ctx, int P, int Pp, int ntiles, const int4 *tiles
     check_launch(ctx, "k_tile_gemm");
 }
 
-// Small levels of M2M (4 child slots) and L2L (1 parent slot): one wavefront
-// per box, all source rows staged in LDS at once and every operator load of a
-// thread issued from one unrolled loop.  (The tile GEMM chains one memory
-// round trip per slot, which dominates when a level has few boxes.)  Padding
-// rows and columns of the operators and of the coefficient vectors are zero.
+// Small levels of M2M (4 child slots) and L2L (1 parent slot): one block of
+// four wavefronts per box.  The (slot, column) pairs of the product are split
+// into four equal runs, one per wavefront (M2M: a child slot each; L2L: a
+// quarter of the columns each), so each lane's chain of operator loads is a
+// quarter as long; the four partial rows are summed through LDS.  (The tile
+// GEMM chains one memory round trip per slot, which dominates when a level
+// has few boxes.)  Padding rows and columns of the operators and of the
+// coefficient vectors are zero.
 template <int PP, int NS>
-__global__ __launch_bounds__(64) void k_small_gemv(
+__global__ __launch_bounds__(256) void k_small_gemv(
     const int32_t *__restrict__ boxes, int64_t box0, const int32_t *__restrict__ src,
     const uint32_t *__restrict__ bcode, const double *__restrict__ Op, const double *__restrict__ X,
     int P, int assign, double *__restrict__ out) {
-    __shared__ double xs[NS][PP];
+    constexpr int KW = NS * PP / 4;          // (slot, column) pairs per wavefront
+    constexpr int BT = KW < 16 ? KW : 16;    // operator loads issued together
+    __shared__ double xs[NS * PP];
+    __shared__ double red[4][PP];
     const int64_t box = boxes ? (int64_t)boxes[blockIdx.x] : box0 + blockIdx.x;
-    const int i = threadIdx.x;
-    int sj[NS];
-#pragma unroll
-    for (int s = 0; s < NS; ++s) sj[s] = src[box * NS + s];
-    const int cls = NS == 1 ? (int)(bcode[box] & 3u) : 0;
-#pragma unroll
-    for (int s = 0; s < NS; ++s)
-        for (int k = i; k < PP; k += 64) xs[s][k] = sj[s] >= 0 ? X[(int64_t)sj[s] * PP + k] : 0.0;
+    const int w = threadIdx.x >> 6, i = threadIdx.x & 63;
+    for (int f = threadIdx.x; f < NS * PP; f += 256) {
+        const int sj = src[box * NS + f / PP];
+        xs[f] = sj >= 0 ? X[(int64_t)sj * PP + f % PP] : 0.0;
+    }
+    const int s = NS == 1 ? 0 : w;           // this wavefront's slot
+    const int k0 = NS == 1 ? w * KW : 0;     // and its first column
+    const bool live = src[box * NS + s] >= 0;
     __syncthreads();
-    if (i >= PP) return;
-    double acc0 = 0.0, acc1 = 0.0;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    if (i < PP && live) {
+        const double *A = Op + (size_t)(NS == 1 ? (int)(bcode[box] & 3u) : s) * PP * PP +
+                          (size_t)k0 * PP + i;
+        const double *x = xs + s * PP + k0;
 #pragma unroll
-    for (int s = 0; s < NS; ++s) {
-        if (sj[s] < 0) continue;
-        const double *A = Op + (size_t)(NS == 1 ? cls : s) * PP * PP + i;
+        for (int kb = 0; kb < KW; kb += BT) {
+            double a[BT];
 #pragma unroll
-        for (int k = 0; k < PP; k += 2) {
-            acc0 = __builtin_fma(A[(size_t)k * PP], xs[s][k], acc0);
-            acc1 = __builtin_fma(A[(size_t)(k + 1) * PP], xs[s][k + 1], acc1);
+            for (int u = 0; u < BT; ++u) a[u] = A[(size_t)(kb + u) * PP];
+#pragma unroll
+            for (int u = 0; u < BT; ++u) acc[u & 3] = __builtin_fma(a[u], x[kb + u], acc[u & 3]);
         }
     }
-    const double acc = i < P ? acc0 + acc1 : 0.0;
-    double *o = out + box * PP + i;
-    *o = assign ? acc : *o + acc;
+    if (i < PP) red[w][i] = (acc[0] + acc[1]) + (acc[2] + acc[3]);
+    __syncthreads();
+    if (w == 0 && i < PP) {
+        const double v = i < P ? (red[0][i] + red[1][i]) + (red[2][i] + red[3][i]) : 0.0;
+        double *o = out + box * PP + i;
+        *o = assign ? v : *o + v;
+    }
 }
 
 void launch_small_gemv(Context &ctx, int Pp, int ns, int64_t nbox, const int32_t *boxes, int64_t box0,
@@ -903,10 +925,10 @@ void launch_small_gemv(Context &ctx, int Pp, int ns, int64_t nbox, const int32_t
 #define YK_SMALL_CASE(PPV)                                                                         \
     case PPV:                                                                                      \
         if (ns == 1)                                                                               \
-            hipLaunchKernelGGL((k_small_gemv<PPV, 1>), dim3((unsigned)nbox), dim3(64), 0, ctx.stream, \
+            hipLaunchKernelGGL((k_small_gemv<PPV, 1>), dim3((unsigned)nbox), dim3(256), 0, ctx.stream, \
                                boxes, box0, src, bcode, Op, X, P, assign, out);                    \
         else                                                                                       \
-            hipLaunchKernelGGL((k_small_gemv<PPV, 4>), dim3((unsigned)nbox), dim3(64), 0, ctx.stream, \
+            hipLaunchKernelGGL((k_small_gemv<PPV, 4>), dim3((unsigned)nbox), dim3(256), 0, ctx.stream, \
                                boxes, box0, src, bcode, Op, X, P, assign, out);                    \
         break;
     switch (Pp) {
@@ -1161,7 +1183,8 @@ struct ItemSetup {
 
 // Leaf ranges and U-list source ranges of an item (into the LDS arrays qa, qn,
 // da, dn_, one entry per neighbour), and this lane's target.  q_on / d_on
-// select which source sets are counted.
+// select which source sets are counted; NTB threads share the item.
+template <int NTB = 64>
 __device__ __forceinline__ ItemSetup item_setup(int2 item, const int32_t *__restrict__ lrange,
                                                 const int32_t *__restrict__ uoff,
                                                 const int32_t *__restrict__ ulist, int q_on, int d_on,
@@ -1195,7 +1218,7 @@ __device__ __forceinline__ ItemSetup item_setup(int2 item, const int32_t *__rest
         r.nd += dn_[u];
     }
     r.c = min(64, ntot - item.y);
-    r.g = 64 / r.c;
+    r.g = NTB / r.c;
     r.ti = lane % r.c;
     r.sub = lane / r.c;
     r.valid = r.sub < r.g;
@@ -1272,19 +1295,20 @@ __global__ __launch_bounds__(64) void k_near_build(
     }
 }
 
-template <typename VT>
-__global__ __launch_bounds__(64) void k_near_apply(
+// NTB = 64, or 256 for trees with too few items to fill the GPU (the layout
+// of the values does not depend on how many lanes share a target)
+template <typename VT, int NTB>
+__global__ __launch_bounds__(NTB) void k_near_apply(
     const int2 *__restrict__ items, const int32_t *__restrict__ lrange,
     const int32_t *__restrict__ uoff, const int32_t *__restrict__ ulist,
     const double *__restrict__ qs, const double *__restrict__ dns, int64_t off1, int q_on, int d_on,
     int has_q, int has_d, int mask, const int64_t *__restrict__ qoff, const int64_t *__restrict__ doff,
     const VT *__restrict__ Mq, const VT *__restrict__ Md, double dip_scale, double *__restrict__ outs) {
-    using V2 = typename Pair2<VT>::type;
-    __shared__ double s_a[kLeafStage], s_b[kLeafStage];
+    __shared__ double s_a[NTB > kLeafStage ? NTB : kLeafStage], s_b[kLeafStage];
     __shared__ int qa[9], qn[9], da[9], dn_[9];
     const int ib = xcd_remap(blockIdx.x, gridDim.x);
     const int lane = threadIdx.x;
-    const ItemSetup it = item_setup(items[ib], lrange, uoff, ulist, q_on, d_on, mask, qa, qn, da, dn_);
+    const ItemSetup it = item_setup<NTB>(items[ib], lrange, uoff, ulist, q_on, d_on, mask, qa, qn, da, dn_);
     double near_q = 0.0, near_d = 0.0;
     for (int set = 0; set < 2; ++set) {
         if ((set == 0 && !has_q) || (set == 1 && !has_d)) continue;
@@ -1292,7 +1316,7 @@ __global__ __launch_bounds__(64) void k_near_apply(
         for (int c0 = 0; c0 < ntot_s; c0 += kLeafStage) {
             const int cn = min(kLeafStage, ntot_s - c0);
             __syncthreads();
-            for (int f = lane; f < cn; f += 64) {
+            for (int f = lane; f < cn; f += NTB) {
                 const int j = flat_source(c0 + f, set == 0 ? qn : dn_, set == 0 ? qa : da);
                 if (set == 0) {
                     s_a[f] = qs[j];
@@ -1517,16 +1541,23 @@ void fmm_run(Context &ctx, FmmPlan &pl, const double *q, const double *dn, doubl
                     built = true;
                 }
                 StageTimer tl(ctx, YK_STAGE_LEAF, near_stream);
-                if (f32)
-                    hipLaunchKernelGGL(k_near_apply<float>, dim3(as.n_items), dim3(64), 0, near_stream,
+                // four wavefronts per item when the items alone would leave
+                // the GPU with under about eight wavefronts per CU
+                const bool wide = as.n_items < 2048;
+                const dim3 blk(wide ? 256 : 64);
+                if (f32) {
+                    auto kern = wide ? k_near_apply<float, 256> : k_near_apply<float, 64>;
+                    hipLaunchKernelGGL(kern, dim3(as.n_items), blk, 0, near_stream,
                                        as.leaf_items.p, pl.lrange.p, pl.ulist_off.p, pl.ulist.p, qs, dns,
                                        pl.toff[1], q_on, d_on, has_q, has_d, mask, as.item_qoff.p,
                                        as.item_doff.p, as.nq32.p, as.nd32.p, 0.5 * inv_alpha, outs);
-                else
-                    hipLaunchKernelGGL(k_near_apply<double>, dim3(as.n_items), dim3(64), 0, near_stream,
+                } else {
+                    auto kern = wide ? k_near_apply<double, 256> : k_near_apply<double, 64>;
+                    hipLaunchKernelGGL(kern, dim3(as.n_items), blk, 0, near_stream,
                                        as.leaf_items.p, pl.lrange.p, pl.ulist_off.p, pl.ulist.p, qs, dns,
                                        pl.toff[1], q_on, d_on, has_q, has_d, mask, as.item_qoff.p,
                                        as.item_doff.p, as.nq64.p, as.nd64.p, 0.5 * inv_alpha, outs);
+                }
                 check_launch(ctx, "k_near_apply");
             } else {
                 LeafKernel kern = pick_leaf_kernel(pl.near_terms, small_only, f32);
@@ -1565,7 +1596,7 @@ void fmm_run(Context &ctx, FmmPlan &pl, const double *q, const double *dn, doubl
         }
         StageTimer tm(ctx, YK_STAGE_P2M);
         if (p2m_cache) {
-            hipLaunchKernelGGL(k_p2m_apply, dim3((unsigned)((pl.nleaf + 3) / 4)), dim3(256), 0, ctx.stream,
+            hipLaunchKernelGGL(k_p2m_apply, dim3((unsigned)pl.nleaf), dim3(256), 0, ctx.stream,
                                leaf_base, pl.nleaf, pl.lrange.p, pl.toff[1], has_q, has_d, qs, dns,
                                pl.p2m_rq.p, pl.p2m_rd.p, P, Pp, pl.M.p);
             check_launch(ctx, "k_p2m_apply");

@@ -115,24 +115,37 @@ __global__ void k_axpby(int64_t n, double ca, const double *__restrict__ a, doub
 __constant__ double c_gl_x[32];
 __constant__ double c_gl_w[32];
 
-// out[i] += B[i] * (1/2pi) * 8 * int_0^{pi/4} (alpha^2 - alpha R K1(R/alpha)) dtheta,
+// out[i] = scale * (out[i] + B[i] * c(h_i)), where
+// c(h) = (1/2pi) * 8 * int_0^{pi/4} (alpha^2 - alpha R K1(R/alpha)) dtheta,
 // R = (h/2)/cos(theta), h = sqrt(vol_w[i]): the kernel integrated over the
-// target's own square cell (8 right triangles with apex at the centre).
-__global__ void k_self_cell(int64_t n, const double *__restrict__ vol_w,
-                            const double *__restrict__ B, double alpha,
-                            double *__restrict__ out) {
+// target's own square cell (8 right triangles with apex at the centre).  When
+// all points of a wavefront share one cell size (a uniform grid) the 32 nodes
+// of the rule are spread over the lanes and c(h) is formed once per wavefront.
+__device__ __forceinline__ double self_cell_node(int k, double h, double alpha) {
+    const double th = (c_gl_x[k] + 1.0) * (kPi / 8.0);
+    const double R = 0.5 * h / cos(th);
+    return c_gl_w[k] * (alpha * alpha - alpha * R * k1(R / alpha));
+}
+
+__global__ __launch_bounds__(256) void k_self_cell(int64_t n, const double *__restrict__ vol_w,
+                                                   const double *__restrict__ B, double alpha,
+                                                   double scale, double *__restrict__ out) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const double h = sqrt(vol_w[i]);
-    const double q8 = kPi / 8.0;
-    double s = 0.0;
-    for (int k = 0; k < 32; ++k) {
-        const double th = (c_gl_x[k] + 1.0) * q8;
-        const double R = 0.5 * h / cos(th);
-        const double z = R / alpha;
-        s += c_gl_w[k] * (alpha * alpha - alpha * R * k1(z));
+    const bool in = i < n;
+    const int lane = threadIdx.x & 63;
+    const double h = in ? sqrt(vol_w[i]) : 0.0;
+    // lane 0 of a wavefront with any point in range is in range itself
+    const double h0 = __shfl(h, 0);
+    double s;
+    if (__all(!in || h == h0)) {
+        s = lane < 32 ? self_cell_node(lane, h0, alpha) : 0.0;
+#pragma unroll
+        for (int m = 32; m >= 1; m >>= 1) s += __shfl_xor(s, m);
+    } else {
+        s = 0.0;
+        for (int k = 0; k < 32; ++k) s += self_cell_node(k, h, alpha);
     }
-    out[i] += B[i] * 8.0 * q8 * s * kInv2Pi;
+    if (in) out[i] = scale * (out[i] + B[i] * (8.0 * (kPi / 8.0) * kInv2Pi) * s);
 }
 
 __global__ void k_rhs_be(int64_t n, const double *__restrict__ u, const double *__restrict__ F,
@@ -259,7 +272,7 @@ static void gauss_legendre32(double *x, double *w) {
 }
 
 void launch_self_cell(Context &ctx, int64_t n, const double *vol_w, const double *B, double alpha,
-                      double *out_accum) {
+                      double scale, double *out_accum) {
     static bool ready = false;
     static double gx[32], gw[32];
     if (!ready) {
@@ -269,7 +282,7 @@ void launch_self_cell(Context &ctx, int64_t n, const double *vol_w, const double
     YK_HIP(hipMemcpyToSymbolAsync(HIP_SYMBOL(c_gl_x), gx, sizeof(gx), 0, hipMemcpyHostToDevice, ctx.stream));
     YK_HIP(hipMemcpyToSymbolAsync(HIP_SYMBOL(c_gl_w), gw, sizeof(gw), 0, hipMemcpyHostToDevice, ctx.stream));
     hipLaunchKernelGGL(k_self_cell, dim3(nblk(n, 256)), dim3(256), 0, ctx.stream, n, vol_w, B,
-                       alpha, out_accum);
+                       alpha, scale, out_accum);
     check_launch(ctx, "k_self_cell");
 }
 

@@ -190,8 +190,9 @@ void launch_bie_finish(Context &ctx, int64_t n, const double *w, const double *k
 // out = ca * a + cb * b  (b may be null -> out = ca * a)
 void launch_axpby(Context &ctx, int64_t n, double ca, const double *a, double cb, const double *b,
                   double *out);
+// out = scale * (out + B * (kernel integral over the point's own cell))
 void launch_self_cell(Context &ctx, int64_t n, const double *vol_w, const double *B, double alpha,
-                      double *out_accum);
+                      double scale, double *out_accum);
 void launch_rhs_be(Context &ctx, int64_t n, const double *u, const double *F, const int32_t *region,
                    int n_const, const double *c_dev, double dt, double *B);
 void launch_boundary_prep(Context &ctx, int64_t n, int n_curves, const int64_t *off_dev,
