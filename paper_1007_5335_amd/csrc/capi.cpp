@@ -32,6 +32,7 @@ Context::~Context() {
     if (ev_fork) (void)hipEventDestroy(ev_fork);
     if (ev_join) (void)hipEventDestroy(ev_join);
     if (side) (void)hipStreamDestroy(side);
+    if (gm_host) (void)hipHostFree(gm_host);
 }
 
 void ensure_side_stream(Context &ctx) {

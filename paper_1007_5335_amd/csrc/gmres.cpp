@@ -2,6 +2,7 @@
 // twice (CGS2) in FP64.  The Krylov basis, the operator and all vector work
 // stay on the device; only the k+2 projection scalars per iteration come back
 // to the host, where the Givens rotations and the small triangular solve run.
+#include <algorithm>
 #include <cmath>
 
 #include "yk_internal.h"
@@ -30,6 +31,9 @@ GmresResult gmres(Context &ctx, const Apply &A, int64_t n, const double *b, doub
     double *w = ctx.gm_w.ensure(n);   // reserved for GMRES; operators never touch them
     double *r = ctx.gm_r.ensure(n);
     double *dscal = ctx.scal.ensure(512);   // [0,128) h1, [128,256) h2, 256 norm^2, [300,...) y
+    if (!ctx.gm_host) YK_HIP(hipHostMalloc((void **)&ctx.gm_host, 512 * sizeof(double), hipHostMallocDefault));
+    double *host = ctx.gm_host;
+    double *P0 = arnoldi_partials(ctx, 0), *P1 = arnoldi_partials(ctx, 1), *P2 = arnoldi_partials(ctx, 2);
 
     const double bnorm2 = dot_host(ctx, n, b, b, dscal);
     if (!std::isfinite(bnorm2)) throw Error{YK_ERR_NONFINITE, "right-hand side is not finite"};
@@ -69,14 +73,17 @@ GmresResult gmres(Context &ctx, const Apply &A, int64_t n, const double *b, doub
             double *vk = V + (int64_t)k * n;
             A(vk, w);
             res.matvecs++;
-            launch_multi_dot(ctx, n, k + 1, V, n, w, dscal);
-            launch_multi_axpy(ctx, n, k + 1, V, n, dscal, w);
-            launch_multi_dot(ctx, n, k + 1, V, n, w, dscal + 128);
-            launch_multi_axpy(ctx, n, k + 1, V, n, dscal + 128, w);
-            launch_multi_dot(ctx, n, 1, w, n, w, dscal + 256);
-            YK_HIP(hipMemcpyAsync(hs.data(), dscal, (2 * 128 + 1) * sizeof(double),
-                                  hipMemcpyDeviceToHost, ctx.stream));
+            // CGS2 in four passes over w: partials of V^T w; h1 = V^T w,
+            // w -= V h1, partials of V^T w; h2, w -= V h2, partials of |w|^2;
+            // |w|, the next basis vector w/|w| and the column to the host.
+            // The basis vector is formed before the host sees the column and
+            // is used only if the iteration goes on.
+            launch_arnoldi_pass(ctx, n, V, n, w, 0, nullptr, nullptr, k + 1, false, P0);
+            launch_arnoldi_pass(ctx, n, V, n, w, k + 1, P0, dscal, k + 1, false, P1);
+            launch_arnoldi_pass(ctx, n, V, n, w, k + 1, P1, dscal + 128, 0, true, P2);
+            launch_arnoldi_finish(ctx, n, w, P2, dscal + 256, V + (int64_t)(k + 1) * n, dscal, host);
             YK_HIP(hipStreamSynchronize(ctx.stream));
+            std::copy(host, host + 2 * 128 + 1, hs.begin());
             double *col = &H[(size_t)k * (m + 1)];
             for (int i = 0; i <= k; ++i) col[i] = hs[i] + hs[128 + i];
             const double hk1 = std::sqrt(hs[256]);
@@ -102,7 +109,6 @@ GmresResult gmres(Context &ctx, const Apply &A, int64_t n, const double *b, doub
                 ++k;
                 break;
             }
-            launch_axpby(ctx, n, 1.0 / hk1, w, 0.0, nullptr, V + (int64_t)(k + 1) * n);
             if (std::fabs(g[k + 1]) <= tol * bnorm) {
                 ++k;
                 break;

@@ -7,6 +7,7 @@ namespace {
 
 constexpr int kRedBlock = 256;
 constexpr int kMaxChunks = 64;
+constexpr int kArnMaxRows = 128;
 
 __device__ __forceinline__ double block_sum(double v, double *sh) {
     // wavefront reduction (64 lanes) then across the block's waves, fixed order
@@ -71,9 +72,166 @@ __global__ __launch_bounds__(kRedBlock) void k_nonfinite(int64_t n, const double
     if (threadIdx.x == 0) flag[0] = s > 0.0 ? 1.0 : 0.0;
 }
 
+// Arnoldi step in passes over w, each a kernel of nchunk blocks.  Block c
+// takes the 512-element segments c, c + nchunk, ... and leaves one partial
+// per dot product; the next kernel sums the partials of the one before in
+// every block, in one fixed order (lane-strided, then a wavefront tree), so
+// all blocks hold identical sums and the result is deterministic without
+// any cross-block synchronisation inside a kernel.
+constexpr int kArnE = 2;                    // elements per thread per segment
+constexpr int kArnSeg = kRedBlock * kArnE;  // elements per segment
+constexpr int kArnMaxChunks = 256;
+constexpr int kArnRU = 8;                   // basis vectors whose loads are issued together
+
+inline int arn_chunks(int64_t n) {
+    return (int)std::max<int64_t>(1, std::min<int64_t>(kArnMaxChunks, (n + kArnSeg - 1) / kArnSeg));
+}
+
+// out[r] = sum_c p[r * nchunk + c] for r < nrows (one wavefront per row)
+__device__ __forceinline__ void sum_partials(const double *__restrict__ p, int nrows, int nchunk,
+                                             double *out) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    for (int r = wave; r < nrows; r += nw) {
+        double t = 0.0;
+        for (int c = lane; c < nchunk; c += 64) t += p[(int64_t)r * nchunk + c];
+        for (int off = 32; off > 0; off >>= 1) t += __shfl_down(t, off, 64);
+        if (lane == 0) out[r] = t;
+    }
+}
+
+// w -= sum_{v < nsub} h_v V_v, h summed from the partials psub (block 0 also
+// stores h to hsub_out); then the partials of V_r . w for r < nd and, with
+// self, of w . w, into pout
+__global__ __launch_bounds__(kRedBlock) void k_arnoldi_pass(
+    int64_t n, const double *__restrict__ V, int64_t ld, double *__restrict__ w, int nsub,
+    const double *__restrict__ psub, double *__restrict__ hsub_out, int nd, int self,
+    double *__restrict__ pout) {
+    __shared__ double hs[kArnMaxRows];
+    __shared__ double sh[(kArnMaxRows + 1) * 4];
+    const int c = blockIdx.x, nchunk = gridDim.x, tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int nrows = nd + (self ? 1 : 0);
+    if (nsub > 0) sum_partials(psub, nsub, nchunk, hs);
+    for (int r = tid; r < nrows * 4; r += kRedBlock) sh[r] = 0.0;
+    __syncthreads();
+    if (c == 0)
+        for (int r = tid; r < nsub; r += kRedBlock) hsub_out[r] = hs[r];
+    for (int64_t seg = c; seg * kArnSeg < n; seg += nchunk) {
+        // element e of this thread: index ix[e] (clamped into range; ok[e]
+        // false past the end), so every load below is unconditional
+        int64_t ix[kArnE];
+        bool ok[kArnE];
+        double x[kArnE];
+#pragma unroll
+        for (int e = 0; e < kArnE; ++e) {
+            const int64_t i = seg * kArnSeg + tid + e * kRedBlock;
+            ok[e] = i < n;
+            ix[e] = ok[e] ? i : n - 1;
+            x[e] = ok[e] ? w[ix[e]] : 0.0;
+        }
+        if (nsub > 0) {
+            // in increasing v
+            for (int v0 = 0; v0 < nsub; v0 += kArnRU) {
+                double a[kArnRU][kArnE];
+#pragma unroll
+                for (int u = 0; u < kArnRU; ++u) {
+                    const double *row = V + (int64_t)min(v0 + u, nsub - 1) * ld;
+#pragma unroll
+                    for (int e = 0; e < kArnE; ++e) a[u][e] = row[ix[e]];
+                }
+#pragma unroll
+                for (int u = 0; u < kArnRU; ++u) {
+                    if (v0 + u < nsub) {
+                        const double hv = hs[v0 + u];
+#pragma unroll
+                        for (int e = 0; e < kArnE; ++e) x[e] -= hv * a[u][e];
+                    }
+                }
+            }
+#pragma unroll
+            for (int e = 0; e < kArnE; ++e)
+                if (ok[e]) w[ix[e]] = x[e];
+        }
+        double xm[kArnE];   // x masked to the range
+#pragma unroll
+        for (int e = 0; e < kArnE; ++e) xm[e] = ok[e] ? x[e] : 0.0;
+        for (int r0 = 0; r0 < nd; r0 += kArnRU) {
+            double acc[kArnRU];
+#pragma unroll
+            for (int u = 0; u < kArnRU; ++u) {
+                const double *row = V + (int64_t)min(r0 + u, nd - 1) * ld;
+                acc[u] = 0.0;
+#pragma unroll
+                for (int e = 0; e < kArnE; ++e) acc[u] += row[ix[e]] * xm[e];
+            }
+#pragma unroll
+            for (int u = 0; u < kArnRU; ++u)
+                for (int off = 32; off > 0; off >>= 1) acc[u] += __shfl_down(acc[u], off, 64);
+            if (lane == 0) {
+#pragma unroll
+                for (int u = 0; u < kArnRU; ++u)
+                    if (r0 + u < nd) sh[(r0 + u) * 4 + wave] += acc[u];
+            }
+        }
+        if (self) {
+            double acc = 0.0;
+#pragma unroll
+            for (int e = 0; e < kArnE; ++e) acc += xm[e] * xm[e];
+            for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
+            if (lane == 0) sh[nd * 4 + wave] += acc;
+        }
+    }
+    __syncthreads();
+    for (int r = tid; r < nrows; r += kRedBlock)
+        pout[(int64_t)r * nchunk + c] = (sh[r * 4] + sh[r * 4 + 1]) + (sh[r * 4 + 2] + sh[r * 4 + 3]);
+}
+
+// |w|^2 from the partials p (nchunk of them); y = w / |w| (zero when |w| = 0).
+// Block 0 stores |w|^2 to nrm2_out and hands the column to the host:
+// host_dst[0..256) = col_src[0..256), host_dst[256] = |w|^2.
+__global__ __launch_bounds__(256) void k_arnoldi_finish(
+    int64_t n, const double *__restrict__ w, const double *__restrict__ p, int nchunk,
+    double *__restrict__ nrm2_out, double *__restrict__ y, const double *__restrict__ col_src,
+    double *__restrict__ host_dst) {
+    __shared__ double nrm;
+    if (threadIdx.x < 64) sum_partials(p, 1, nchunk, &nrm);
+    __syncthreads();
+    const double nrm2 = nrm;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) y[i] = nrm2 > 0.0 ? (1.0 / sqrt(nrm2)) * w[i] : 0.0;
+    if (blockIdx.x == 0) {
+        if (threadIdx.x == 0) nrm2_out[0] = nrm2;
+        if (host_dst) {
+            host_dst[threadIdx.x] = col_src[threadIdx.x];
+            if (threadIdx.x == 0) host_dst[256] = nrm2;
+        }
+    }
+}
+
 inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
 }  // namespace
+
+void launch_arnoldi_pass(Context &ctx, int64_t n, const double *V, int64_t ld, double *w, int nsub,
+                         const double *psub, double *hsub_out, int nd, bool self, double *pout) {
+    if (nd + (self ? 1 : 0) > kArnMaxRows + 1 || nsub > kArnMaxRows)
+        throw Error{YK_ERR_INTERNAL, "Arnoldi pass: too many basis vectors"};
+    hipLaunchKernelGGL(k_arnoldi_pass, dim3(arn_chunks(n)), dim3(kRedBlock), 0, ctx.stream, n, V, ld, w,
+                       nsub, psub, hsub_out, nd, self ? 1 : 0, pout);
+    check_launch(ctx, "k_arnoldi_pass");
+}
+
+void launch_arnoldi_finish(Context &ctx, int64_t n, const double *w, const double *p, double *nrm2_out,
+                           double *y, const double *col_src, double *host_dst) {
+    hipLaunchKernelGGL(k_arnoldi_finish, dim3(std::max(1u, nblk(n, 256))), dim3(256), 0, ctx.stream, n, w,
+                       p, arn_chunks(n), nrm2_out, y, col_src, host_dst);
+    check_launch(ctx, "k_arnoldi_finish");
+}
+
+double *arnoldi_partials(Context &ctx, int which) {
+    const size_t one = (size_t)kArnMaxChunks * (kArnMaxRows + 1);
+    return ctx.arn_partial.ensure(3 * one) + (size_t)which * one;
+}
 
 void launch_multi_dot(Context &ctx, int64_t n, int nv, const double *V, int64_t ld,
                       const double *x, double *h) {

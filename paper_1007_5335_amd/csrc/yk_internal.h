@@ -122,6 +122,8 @@ struct Context {
     DevBuf<double> gm_w, gm_r;             // GMRES-private vectors
     DevBuf<double> partial;                // reduction partials
     DevBuf<double> scal;                   // small device scalars
+    DevBuf<double> arn_partial;            // Arnoldi passes: block partials
+    double *gm_host = nullptr;             // pinned host copy of an Arnoldi column (hipHostMalloc)
     DevBuf<double> dn;                     // dipole vectors [N][2]
     std::vector<double> host_scal;
 
@@ -203,6 +205,17 @@ void launch_boundary_prep(Context &ctx, int64_t n, int n_curves, const int64_t *
 void launch_multi_dot(Context &ctx, int64_t n, int nv, const double *V, int64_t ld,
                       const double *x, double *h);
 // x -= sum_k h[k] V[k*ld + i]
+// Arnoldi step in passes (see kernels_blas.hip): w -= sum_{v<nsub} h_v V_v with
+// h summed from the partials psub of the previous pass (stored to hsub_out),
+// then partials of V_r . w (r < nd) and, with self, of w . w into pout
+void launch_arnoldi_pass(Context &ctx, int64_t n, const double *V, int64_t ld, double *w, int nsub,
+                         const double *psub, double *hsub_out, int nd, bool self, double *pout);
+// |w|^2 from the partials p (to nrm2_out), y = w / |w|; host_dst (pinned,
+// may be null) receives col_src[0..256) and then |w|^2
+void launch_arnoldi_finish(Context &ctx, int64_t n, const double *w, const double *p, double *nrm2_out,
+                           double *y, const double *col_src, double *host_dst);
+// partial buffer 0, 1 or 2 of the Arnoldi passes
+double *arnoldi_partials(Context &ctx, int which);
 void launch_multi_axpy(Context &ctx, int64_t n, int nv, const double *V, int64_t ld,
                        const double *h, double *x);
 // y = x / *s  (s on device)
