@@ -237,17 +237,19 @@ struct BieOperator {
 // Solves A sigma = b in FP64, or (mixed) by refinement: FP64 residuals with an
 // FP32-operator GMRES for each correction.
 // r0: b - A sigma for the incoming sigma (optional); Asig_out (optional): set
-// to A sigma of the returned density when the solve converged (FP64 operator)
+// to A sigma of the returned density when the solve converged (FP64 operator);
+// r0_norm2, b_norm2: |r0|^2 and |b|^2 when already known (else negative)
 GmresResult solve_density(Context &ctx, BoundaryData &bd, double alpha, const double *b,
                           double *sigma, bool zero_guess, double tol, int max_iter, int *outer,
                           const double *r0 = nullptr, double *Asig_out = nullptr,
-                          bool *asig_ok = nullptr) {
+                          bool *asig_ok = nullptr, double r0_norm2 = -1.0, double b_norm2 = -1.0) {
     if (asig_ok) *asig_ok = false;
     const int64_t n = bd.n;
     BieOperator A64{ctx, bd, alpha, SUM_FP64};
     *outer = 0;
     if (ctx.opt.precision == YK_PREC_FP64 || ctx.opt.direct) {
-        GmresResult g = gmres(ctx, A64, n, b, sigma, zero_guess, tol, max_iter, ctx.opt.gmres_m, r0);
+        GmresResult g = gmres(ctx, A64, n, b, sigma, zero_guess, tol, max_iter, ctx.opt.gmres_m, r0, r0_norm2,
+                              b_norm2);
         if (Asig_out && g.converged && g.res_final > 0) {   // A sigma = b - r
             launch_axpby(ctx, n, 1.0, b, -1.0, ctx.gm_r.p, Asig_out);
             if (asig_ok) *asig_ok = true;
@@ -267,7 +269,7 @@ GmresResult solve_density(Context &ctx, BoundaryData &bd, double alpha, const do
         return std::sqrt(h);
     };
     GmresResult tot;
-    const double bnorm = norm(b);
+    const double bnorm = b_norm2 >= 0.0 ? std::sqrt(b_norm2) : norm(b);
     if (zero_guess) YK_HIP(hipMemsetAsync(sigma, 0, n * sizeof(double), ctx.stream));
     for (int sweep = 0; sweep < 30; ++sweep) {
         if (sweep == 0 && r0 && !zero_guess) {
@@ -278,7 +280,7 @@ GmresResult solve_density(Context &ctx, BoundaryData &bd, double alpha, const do
             tot.matvecs++;
             launch_axpby(ctx, n, 1.0, b, -1.0, tmp, r);
         }
-        const double rn = norm(r);
+        const double rn = (sweep == 0 && r0 && !zero_guess && r0_norm2 >= 0.0) ? std::sqrt(r0_norm2) : norm(r);
         if (!std::isfinite(rn)) throw Error{YK_ERR_NONFINITE, "refinement residual is not finite"};
         if (sweep == 0) tot.res0 = bnorm > 0 ? rn / bnorm : 0.0;
         tot.res_final = bnorm > 0 ? rn / bnorm : 0.0;
@@ -294,8 +296,8 @@ GmresResult solve_density(Context &ctx, BoundaryData &bd, double alpha, const do
         // inner FP32-operator solve: to the reduction that would finish the
         // solve in this sweep (with a factor 2 to spare), but not below what
         // an FP32 operator resolves (about 1e-6 relative, so a residual far
-        // above tol takes further sweeps) nor above 1e-4
-        const double inner_tol = std::min(1e-4, std::max(2e-6, 0.5 * tol * bnorm / rn));
+        // above tol takes further sweeps)
+        const double inner_tol = std::min(0.5, std::max(1e-6, 0.5 * tol * bnorm / rn));
         GmresResult in = gmres(ctx, A32, n, r, delta, true, inner_tol, max_iter - tot.iters, ctx.opt.gmres_m);
         tot.iters += in.iters;
         tot.matvecs += in.matvecs;
@@ -305,21 +307,22 @@ GmresResult solve_density(Context &ctx, BoundaryData &bd, double alpha, const do
     return tot;
 }
 
-// The memo of the last FP64 density solve applies to this operator and sigma?
-bool memo_matches(Context &ctx, BoundaryData &bd, double alpha, const double *sigma) {
+// The memo of the last FP64 density solve was made for this operator?
+bool memo_key_matches(Context &ctx, BoundaryData &bd, double alpha) {
     const yk_options &o = ctx.opt;
-    if (!ctx.memo_valid || ctx.memo_xy != bd.xy || ctx.memo_n != bd.n || ctx.memo_alpha != alpha ||
-        ctx.memo_tol != o.fmm_tol || ctx.memo_p != o.p || ctx.memo_leaf != o.leaf_size ||
-        ctx.memo_direct != o.direct)
-        return false;
+    return ctx.memo_valid && ctx.memo_xy == bd.xy && ctx.memo_n == bd.n && ctx.memo_alpha == alpha &&
+           ctx.memo_tol == o.fmm_tol && ctx.memo_p == o.p && ctx.memo_leaf == o.leaf_size &&
+           ctx.memo_direct == o.direct;
+}
+
+// Enqueues the check that sigma is bitwise the memo's density; the returned
+// device flag is 0 when it is (read it after a synchronisation)
+int *memo_check(Context &ctx, BoundaryData &bd, const double *sigma) {
     int *flag = ctx.memo_flag.ensure(1);
     const int zero = 0;
     YK_HIP(hipMemcpyAsync(flag, &zero, sizeof(int), hipMemcpyHostToDevice, ctx.stream));
     launch_differs(ctx, bd.n, sigma, ctx.memo_sig.p, flag);
-    int h = 1;
-    YK_HIP(hipMemcpyAsync(&h, flag, sizeof(int), hipMemcpyDeviceToHost, ctx.stream));
-    YK_HIP(hipStreamSynchronize(ctx.stream));
-    return h == 0;
+    return flag;
 }
 
 void memo_store(Context &ctx, BoundaryData &bd, double alpha, const double *sigma) {
@@ -567,8 +570,8 @@ yk_status yk_heat_step(yk_ctx ctx, const yk_boundary *bnd, int64_t n_vol, const 
         }
         double *b = c.ws_f.ensure(nb);
         launch_axpby(c, nb, -2.0 * a2, f_next, 2.0, vb, b);
-        YK_HIP(hipStreamSynchronize(c.stream));
-        if (stats) {
+        if (stats) {   // (phase times need a synchronisation)
+            YK_HIP(hipStreamSynchronize(c.stream));
             stats->ms[0] = fmm_last_build_ms(c);
             stats->ms[1] = ms_since(t0);
         }
@@ -581,40 +584,65 @@ yk_status yk_heat_step(yk_ctx ctx, const yk_boundary *bnd, int64_t n_vol, const 
         // still held and its residual costs no operator application.
         int guess = (flags & 2) ? 0 : 1;
         const double *r0 = nullptr;
+        double r0_norm2 = -1.0;
         double *rprev = c.memo_r1.ensure(nb), *rml = c.memo_r2.ensure(nb);
-        const bool memo = guess == 1 && memo_matches(c, bd, alpha, sigma_io);
         BieOperator A64{c, bd, alpha, SUM_FP64};
-        // rv = b - A x (from the memo when from_memo); returns ||rv||^2
-        auto resid = [&](const double *x, double *rv, bool from_memo) {
+        // Everything the choice needs is enqueued first and read back with one
+        // synchronisation: ds = {|r_ml|^2, |r_prev|^2, |b|^2} and the memo flag.
+        const bool memo_key = guess == 1 && memo_key_matches(c, bd, alpha);
+        const bool learned = guess == 1 && c.warm && c.warm->trained && c.warm->obs.size() >= 2;
+        double *ds = c.scal.ensure(512) + 450;
+        double *sml = learned ? c.ws_ml.ensure(nb) : nullptr;
+        auto tg = std::chrono::steady_clock::now();
+        int *dflag = memo_key ? memo_check(c, bd, sigma_io) : nullptr;
+        auto resid_enqueue = [&](const double *x, double *rv, bool from_memo, double *d) {
             if (from_memo) {
                 launch_axpby(c, nb, 1.0, b, -1.0, c.memo_Asig.p, rv);
             } else {
                 A64(x, rv);
                 launch_axpby(c, nb, 1.0, b, -1.0, rv, rv);
             }
-            double *ds = c.scal.ensure(512) + 450;
-            launch_multi_dot(c, nb, 1, rv, nb, rv, ds);
-            double h = 0;
-            YK_HIP(hipMemcpyAsync(&h, ds, sizeof(double), hipMemcpyDeviceToHost, c.stream));
-            YK_HIP(hipStreamSynchronize(c.stream));
-            return h;
+            launch_multi_dot(c, nb, 1, rv, nb, rv, d);
         };
-        if (c.warm && c.warm->trained && c.warm->obs.size() >= 2 && guess == 1) {
-            auto tg = std::chrono::steady_clock::now();
-            double *sml = c.ws_ml.ensure(nb);
+        if (learned) {
             c.warm->predict(gN, sml);
-            const double r_ml = resid(sml, rml, false), r_prev = resid(sigma_io, rprev, memo);
+            resid_enqueue(sml, rml, false, ds);
+        }
+        // the previous density's residual: from the memo when it applies (a
+        // changed density is caught below), else by an operator application
+        // when the learned guess needs it for comparison
+        if (memo_key) resid_enqueue(sigma_io, rprev, true, ds + 1);
+        else if (learned) resid_enqueue(sigma_io, rprev, false, ds + 1);
+        launch_multi_dot(c, nb, 1, b, nb, b, ds + 2);
+        double *hsc = pinned_scalars(c) + 400;
+        YK_HIP(hipMemcpyAsync(hsc, ds, 3 * sizeof(double), hipMemcpyDeviceToHost, c.stream));
+        if (dflag) YK_HIP(hipMemcpyAsync(hsc + 3, dflag, sizeof(int), hipMemcpyDeviceToHost, c.stream));
+        YK_HIP(hipStreamSynchronize(c.stream));
+        double r_ml = hsc[0], r_prev = hsc[1];
+        const double b_norm2 = hsc[2];
+        int hflag = 0;
+        if (dflag) std::memcpy(&hflag, hsc + 3, sizeof(int));
+        const bool memo = memo_key && hflag == 0;
+        if (memo_key && !memo && learned) {   // the caller changed sigma since the memo
+            resid_enqueue(sigma_io, rprev, false, ds + 1);
+            YK_HIP(hipMemcpyAsync(hsc + 1, ds + 1, sizeof(double), hipMemcpyDeviceToHost, c.stream));
+            YK_HIP(hipStreamSynchronize(c.stream));
+            r_prev = hsc[1];
+        }
+        if (learned) {
             if (std::isfinite(r_ml) && r_ml < r_prev) {
                 YK_HIP(hipMemcpyAsync(sigma_io, sml, nb * sizeof(double), hipMemcpyDeviceToDevice, c.stream));
                 guess = 2;
                 r0 = rml;
+                r0_norm2 = r_ml;
             } else {
                 r0 = rprev;
+                r0_norm2 = r_prev;
             }
             if (stats) stats->ms[4] = ms_since(tg);
         } else if (memo) {
-            launch_axpby(c, nb, 1.0, b, -1.0, c.memo_Asig.p, rprev);
             r0 = rprev;
+            r0_norm2 = r_prev;
         }
         // sigma
         auto t1 = std::chrono::steady_clock::now();
@@ -622,7 +650,7 @@ yk_status yk_heat_step(yk_ctx ctx, const yk_boundary *bnd, int64_t n_vol, const 
         int outer = 0;
         bool asig_ok = false;
         GmresResult r = solve_density(c, bd, alpha, b, sigma_io, guess == 0, tol, 1000, &outer, r0,
-                                      c.memo_Asig.ensure(nb), &asig_ok);
+                                      c.memo_Asig.ensure(nb), &asig_ok, r0_norm2, b_norm2);
         if (asig_ok) memo_store(c, bd, alpha, sigma_io);
         else c.memo_valid = false;
         if (c.warm) c.warm->observe(gN, sigma_io);

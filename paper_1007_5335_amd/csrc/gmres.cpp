@@ -21,8 +21,14 @@ double dot_host(Context &ctx, int64_t n, const double *a, const double *b, doubl
 
 }  // namespace
 
+double *pinned_scalars(Context &ctx) {
+    if (!ctx.gm_host) YK_HIP(hipHostMalloc((void **)&ctx.gm_host, 512 * sizeof(double), hipHostMallocDefault));
+    return ctx.gm_host;
+}
+
 GmresResult gmres(Context &ctx, const Apply &A, int64_t n, const double *b, double *x,
-                  bool zero_guess, double tol, int max_iter, int m, const double *r0) {
+                  bool zero_guess, double tol, int max_iter, int m, const double *r0, double r0_norm2,
+                  double b_norm2) {
     GmresResult res;
     if (m < 1) m = 1;
     if (m > 120) m = 120;
@@ -31,11 +37,10 @@ GmresResult gmres(Context &ctx, const Apply &A, int64_t n, const double *b, doub
     double *w = ctx.gm_w.ensure(n);   // reserved for GMRES; operators never touch them
     double *r = ctx.gm_r.ensure(n);
     double *dscal = ctx.scal.ensure(512);   // [0,128) h1, [128,256) h2, 256 norm^2, [300,...) y
-    if (!ctx.gm_host) YK_HIP(hipHostMalloc((void **)&ctx.gm_host, 512 * sizeof(double), hipHostMallocDefault));
-    double *host = ctx.gm_host;
+    double *host = pinned_scalars(ctx);
     double *P0 = arnoldi_partials(ctx, 0), *P1 = arnoldi_partials(ctx, 1), *P2 = arnoldi_partials(ctx, 2);
 
-    const double bnorm2 = dot_host(ctx, n, b, b, dscal);
+    const double bnorm2 = b_norm2 >= 0.0 ? b_norm2 : dot_host(ctx, n, b, b, dscal);
     if (!std::isfinite(bnorm2)) throw Error{YK_ERR_NONFINITE, "right-hand side is not finite"};
     const double bnorm = std::sqrt(bnorm2);
     if (bnorm == 0.0) {
@@ -53,7 +58,9 @@ GmresResult gmres(Context &ctx, const Apply &A, int64_t n, const double *b, doub
         res.matvecs++;
         launch_axpby(ctx, n, 1.0, b, -1.0, w, r);
     }
-    double beta = std::sqrt(dot_host(ctx, n, r, r, dscal));
+    double beta = std::sqrt(zero_guess ? bnorm2
+                            : (r0 && r0_norm2 >= 0.0) ? r0_norm2
+                            : dot_host(ctx, n, r, r, dscal));
     if (!std::isfinite(beta)) throw Error{YK_ERR_NONFINITE, "initial residual is not finite"};
     res.res0 = beta / bnorm;
 

@@ -8,8 +8,10 @@
 
 namespace yk {
 
+// C = A B (FP32 matrix cores); with tanh_bias, C = tanh(A B + tanh_bias[col])
 void sgemm(Context &ctx, int M, int N, int K, const float *A, int64_t sam, int64_t sak, const float *B,
-           int64_t sbk, int64_t sbn, float *C, int64_t ldc, DevBuf<float> &part);
+           int64_t sbk, int64_t sbn, float *C, int64_t ldc, DevBuf<float> &part,
+           const float *tanh_bias = nullptr);
 
 struct WarmStart {
     struct Obs {
@@ -29,9 +31,8 @@ struct WarmStart {
     int64_t adam_t = 0;
     DevBuf<float> Xall, Tall, Xbat, Tbat, h1, h2, d1, d2, yb, dyb, part, cpart, lpart;
     DevBuf<int32_t> brows;
-    DevBuf<double> scal, dtmp;
+    DevBuf<double> scal, dtmp, fscale;
     std::vector<std::unique_ptr<Obs>> obs;
-    double kappa_rms = 0.0;
     bool trained = false;
 
     WarmStart(Context &c, BoundaryData &b, const yk_ws_options &o);
@@ -42,11 +43,10 @@ struct WarmStart {
     double loss_grad(int64_t rows, const float *X, const float *T, float *G);
 
   private:
-    static double sq(double v) { return v * v; }
-    double rms_dev(const double *a, const double *b, int64_t cnt);
-    // writes the features of one step into X; returns the step's density scale r_s
-    double features(const double *sm1, const double *s0, const double *gm1, const double *g0,
-                    const double *gp1, float *X);
+    // writes the features of one step into X and the step's scales into fs
+    // (device memory; fs[6] is the density scale r_s)
+    void features(const double *sm1, const double *s0, const double *gm1, const double *g0,
+                  const double *gp1, float *X, double *fs);
     void colsum(int64_t rows, int cols, const float *D, float *out);
 };
 

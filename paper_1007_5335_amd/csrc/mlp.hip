@@ -41,13 +41,14 @@ typedef float f4v __attribute__((ext_vector_type(4)));
 // B(k,n) = B[k*sbk + n*sbn].  64 x 64 tiles, 4 wavefronts each owning a
 // 32 x 32 quarter (2 x 2 tiles of v_mfma_f32_16x16x4f32), K staged in LDS in
 // steps of 16.  gridDim.z > 1 splits K; the partial sums are added afterwards
-// in a fixed order.
+// in a fixed order.  With tb (one split only) the result is tanh(C + tb[n]).
 constexpr int kLdsPad = 80;   // row stride of the LDS tiles (keeps the four lane groups on distinct banks)
 
 __global__ __launch_bounds__(256) void k_sgemm(int M, int N, int K, const float *__restrict__ A,
                                                int64_t sam, int64_t sak, const float *__restrict__ B,
                                                int64_t sbk, int64_t sbn, float *__restrict__ C,
-                                               int64_t ldc, int64_t ldz, int kchunk) {
+                                               int64_t ldc, int64_t ldz, int kchunk,
+                                               const float *__restrict__ tb) {
     __shared__ float As[16][kLdsPad];
     __shared__ float Bs[16][kLdsPad];
     const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
@@ -93,7 +94,8 @@ __global__ __launch_bounds__(256) void k_sgemm(int M, int N, int K, const float 
             for (int r = 0; r < 4; ++r) {
                 const int gm = m0 + wm + 16 * i + 4 * (lane >> 4) + r;
                 const int gn = n0 + wn + 16 * j + (lane & 15);
-                if (gm < M && gn < N) Cz[(int64_t)gm * ldc + gn] = acc[i][j][r];
+                if (gm < M && gn < N)
+                    Cz[(int64_t)gm * ldc + gn] = tb ? tanhf(acc[i][j][r] + tb[gn]) : acc[i][j][r];
             }
 }
 
@@ -186,16 +188,69 @@ __global__ void k_adam(int64_t n, float *__restrict__ p, const float *__restrict
     p[i] -= lr * (mi * c1) / (sqrtf(vi * c2) + eps);
 }
 
-// Features of every node for one (N-1, N, N+1) triple; scale[0..4] are the
-// per-channel factors, extra0/extra1 the two per-step scalar features.
+// Sums of squares of s0, s0 - sm1, gp1 - g0, g0 - gm1 and kappa: partials
+// part[q * 256 + block] (256 blocks)
+__global__ __launch_bounds__(256) void k_sumsq5(int64_t n, const double *__restrict__ sm1,
+                                                const double *__restrict__ s0, const double *__restrict__ gm1,
+                                                const double *__restrict__ g0, const double *__restrict__ gp1,
+                                                const double *__restrict__ kappa, double *__restrict__ part) {
+    __shared__ double sh[5][256];
+    double a[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+        const double v0 = s0[i], v1 = s0[i] - sm1[i], v2 = gp1[i] - g0[i], v3 = g0[i] - gm1[i], v4 = kappa[i];
+        a[0] += v0 * v0;
+        a[1] += v1 * v1;
+        a[2] += v2 * v2;
+        a[3] += v3 * v3;
+        a[4] += v4 * v4;
+    }
+    for (int q = 0; q < 5; ++q) sh[q][threadIdx.x] = a[q];
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if (threadIdx.x < off)
+            for (int q = 0; q < 5; ++q) sh[q][threadIdx.x] += sh[q][threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x < 5) part[threadIdx.x * 256 + blockIdx.x] = sh[threadIdx.x][0];
+}
+
+// The step's scales from the partials (one block, fixed order): RMS values
+// r0 = rms(s0), r_s = rms(s0 - sm1), r_g = rms(gp1 - g0), r_g0 = rms(g0 - gm1),
+// r_k = rms(kappa) (the first three and r_k floored at a tiny positive value);
+// fs = {1/r0, 1/r_s, 1/r_g, 1/r_k, ln(r_g/r_s), r_g0/r_g, r_s}
+__global__ void k_feature_scales(int64_t n, const double *__restrict__ part, double *__restrict__ fs) {
+    __shared__ double r[5];
+    if (threadIdx.x < 5) {
+        double t = 0.0;
+        for (int b = 0; b < 256; ++b) t += part[threadIdx.x * 256 + b];
+        r[threadIdx.x] = sqrt(t / (double)(n > 0 ? n : 1));
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const double tiny = 1e-300;
+        const double r0 = fmax(tiny, r[0]), rs = fmax(tiny, r[1]), rg = fmax(tiny, r[2]), rk = fmax(tiny, r[4]);
+        fs[0] = 1.0 / r0;
+        fs[1] = 1.0 / rs;
+        fs[2] = 1.0 / rg;
+        fs[3] = 1.0 / rk;
+        fs[4] = log(rg / rs);
+        fs[5] = r[3] / rg;
+        fs[6] = rs;
+    }
+}
+
+// Features of every node for one (N-1, N, N+1) triple; fs holds the per-step
+// scales written by k_feature_scales.
 __global__ void k_features(int64_t n, const double *__restrict__ sm1, const double *__restrict__ s0,
                            const double *__restrict__ gm1, const double *__restrict__ g0,
                            const double *__restrict__ gp1, const double *__restrict__ kappa,
                            const int32_t *__restrict__ curve, const int32_t *__restrict__ idx,
-                           const int64_t *__restrict__ off, float sc0, float sc1, float sc2, float sc4,
-                           float extra0, float extra1, int Fp, float *__restrict__ X) {
+                           const int64_t *__restrict__ off, const double *__restrict__ fs, int Fp,
+                           float *__restrict__ X) {
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= n) return;
+    const float sc0 = (float)fs[0], sc1 = (float)fs[1], sc2 = (float)fs[2], sc4 = (float)fs[3];
+    const float extra0 = (float)fs[4], extra1 = (float)fs[5];
     const int k = curve[j];
     const int64_t base = off[k], nk = off[k + 1] - off[k];
     const int64_t jl = idx[j];
@@ -215,38 +270,22 @@ __global__ void k_features(int64_t n, const double *__restrict__ sm1, const doub
     for (int f = kFeat; f < Fp; ++f) row[f] = 0.f;
 }
 
-// target (sigma^{N+1} - 2 sigma^N + sigma^{N-1}) * inv_sy, inv_sy = 1 / r_s
+// target (sigma^{N+1} - 2 sigma^N + sigma^{N-1}) / r_s, r_s = fs[6]
 __global__ void k_target(int64_t n, const double *__restrict__ sm1, const double *__restrict__ s0,
-                         const double *__restrict__ sp1, float inv_sy, float *__restrict__ t) {
+                         const double *__restrict__ sp1, const double *__restrict__ fs, float *__restrict__ t) {
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= n) return;
+    const float inv_sy = (float)(1.0 / fs[6]);
     t[j] = (float)((sp1[j] - 2.0 * s0[j] + sm1[j]) * inv_sy);
 }
 
-// sigma = 2 sigma^N - sigma^{N-1} + sy * y
+// sigma = 2 sigma^N - sigma^{N-1} + r_s * y, r_s = fs[6]
 __global__ void k_apply_pred(int64_t n, const double *__restrict__ sm1, const double *__restrict__ s0,
-                             const float *__restrict__ y, double sy, double *__restrict__ out) {
+                             const float *__restrict__ y, const double *__restrict__ fs,
+                             double *__restrict__ out) {
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= n) return;
-    out[j] = 2.0 * s0[j] - sm1[j] + sy * (double)y[j];
-}
-
-// sum of squares partials (double)
-__global__ __launch_bounds__(256) void k_sumsq(int64_t n, const double *__restrict__ a,
-                                               const double *__restrict__ b, double *__restrict__ part) {
-    __shared__ double sh[256];
-    double s = 0.0;
-    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
-        const double v = b ? a[i] - b[i] : a[i];
-        s += v * v;
-    }
-    sh[threadIdx.x] = s;
-    __syncthreads();
-    for (int off = 128; off > 0; off >>= 1) {
-        if (threadIdx.x < off) sh[threadIdx.x] += sh[threadIdx.x + off];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+    out[j] = 2.0 * s0[j] - sm1[j] + fs[6] * (double)y[j];
 }
 
 __global__ void k_gather_rows(int64_t nb, int Fp, const int32_t *__restrict__ rows,
@@ -264,7 +303,7 @@ __global__ void k_gather_rows(int64_t nb, int Fp, const int32_t *__restrict__ ro
 
 // --------------------------------------------------------------- host side --
 void sgemm(Context &ctx, int M, int N, int K, const float *A, int64_t sam, int64_t sak, const float *B,
-           int64_t sbk, int64_t sbn, float *C, int64_t ldc, DevBuf<float> &part) {
+           int64_t sbk, int64_t sbn, float *C, int64_t ldc, DevBuf<float> &part, const float *tanh_bias) {
     if (M <= 0 || N <= 0) return;
     const int gm = (M + 63) / 64, gn = (N + 63) / 64;
     // split K when the output has few tiles and K is long
@@ -275,17 +314,23 @@ void sgemm(Context &ctx, int M, int N, int K, const float *A, int64_t sam, int64
     nz = (K + kchunk - 1) / kchunk;
     if (nz <= 1) {
         hipLaunchKernelGGL(k_sgemm, dim3(gn, gm, 1), dim3(256), 0, ctx.stream, M, N, K, A, sam, sak, B, sbk, sbn,
-                           C, ldc, (int64_t)0, K);
+                           C, ldc, (int64_t)0, K, tanh_bias);
         check_launch(ctx, "k_sgemm");
         return;
     }
     const int64_t ldz = (int64_t)M * ldc;
     float *p = part.ensure((size_t)nz * ldz);
     hipLaunchKernelGGL(k_sgemm, dim3(gn, gm, nz), dim3(256), 0, ctx.stream, M, N, K, A, sam, sak, B, sbk, sbn,
-                       p, ldc, ldz, kchunk);
+                       p, ldc, ldz, kchunk, (const float *)nullptr);
     check_launch(ctx, "k_sgemm");
     hipLaunchKernelGGL(k_sum_partials, dim3(nblk(ldz, 256)), dim3(256), 0, ctx.stream, ldz, nz, p, ldz, C);
     check_launch(ctx, "k_sum_partials");
+    if (tanh_bias) {
+        if (ldc != N) throw Error{YK_ERR_INTERNAL, "sgemm: bias epilogue needs ldc == N"};
+        hipLaunchKernelGGL(k_bias_tanh, dim3(nblk((int64_t)M * N, 256)), dim3(256), 0, ctx.stream, (int64_t)M, N,
+                           C, tanh_bias);
+        check_launch(ctx, "k_bias_tanh");
+    }
 }
 
 WarmStart::WarmStart(Context &c, BoundaryData &b, const yk_ws_options &o) : ctx(c), opt(o) {
@@ -336,42 +381,24 @@ void WarmStart::observe(const double *g, const double *sigma) {
     if ((int)obs.size() > opt.max_obs) obs.erase(obs.begin());
 }
 
-double WarmStart::rms_dev(const double *a, const double *b, int64_t cnt) {
-    double *part = scal.ensure(256);
-    hipLaunchKernelGGL(k_sumsq, dim3(256), dim3(256), 0, ctx.stream, cnt, a, b, part);
-    check_launch(ctx, "k_sumsq");
-    std::vector<double> h(256);
-    YK_HIP(hipMemcpyAsync(h.data(), part, 256 * sizeof(double), hipMemcpyDeviceToHost, ctx.stream));
-    YK_HIP(hipStreamSynchronize(ctx.stream));
-    double s = 0;
-    for (double v : h) s += v;
-    return std::sqrt(s / (double)std::max<int64_t>(1, cnt));
-}
-
-double WarmStart::features(const double *sm1, const double *s0, const double *gm1, const double *g0,
-                           const double *gp1, float *X) {
-    const double tiny = 1e-300;
-    const double r0 = std::max(tiny, rms_dev(s0, nullptr, n));
-    const double rs = std::max(tiny, rms_dev(s0, sm1, n));
-    const double rg = std::max(tiny, rms_dev(gp1, g0, n));
-    const double rg0 = rms_dev(g0, gm1, n);
-    if (kappa_rms <= 0) kappa_rms = std::max(tiny, rms_dev(kappa, nullptr, n));
+void WarmStart::features(const double *sm1, const double *s0, const double *gm1, const double *g0,
+                         const double *gp1, float *X, double *fs) {
+    double *part = scal.ensure(5 * 256);
+    hipLaunchKernelGGL(k_sumsq5, dim3(256), dim3(256), 0, ctx.stream, n, sm1, s0, gm1, g0, gp1, kappa, part);
+    check_launch(ctx, "k_sumsq5");
+    hipLaunchKernelGGL(k_feature_scales, dim3(1), dim3(64), 0, ctx.stream, n, part, fs);
+    check_launch(ctx, "k_feature_scales");
     hipLaunchKernelGGL(k_features, dim3(nblk(n, 256)), dim3(256), 0, ctx.stream, n, sm1, s0, gm1, g0, gp1,
-                       kappa, curve, idx, off.p, (float)(1.0 / r0), (float)(1.0 / rs), (float)(1.0 / rg),
-                       (float)(1.0 / kappa_rms), (float)std::log(rg / rs), (float)(rg0 / rg), Fp, X);
+                       kappa, curve, idx, off.p, fs, Fp, X);
     check_launch(ctx, "k_features");
-    return rs;
 }
 
 void WarmStart::forward(int64_t rows, const float *X, float *y) {
     float *P = params.p;
     float *H1 = h1.ensure((size_t)rows * H), *H2 = h2.ensure((size_t)rows * H);
-    sgemm(ctx, (int)rows, H, Fp, X, Fp, 1, P + o_W1, 1, Fp, H1, H, part);
-    hipLaunchKernelGGL(k_bias_tanh, dim3(nblk(rows * H, 256)), dim3(256), 0, ctx.stream, rows, H, H1, P + o_b1);
-    check_launch(ctx, "k_bias_tanh");
-    sgemm(ctx, (int)rows, H, H, H1, H, 1, P + o_W2, 1, H, H2, H, part);
-    hipLaunchKernelGGL(k_bias_tanh, dim3(nblk(rows * H, 256)), dim3(256), 0, ctx.stream, rows, H, H2, P + o_b2);
-    check_launch(ctx, "k_bias_tanh");
+    // hidden layers with the bias and tanh applied as the products are stored
+    sgemm(ctx, (int)rows, H, Fp, X, Fp, 1, P + o_W1, 1, Fp, H1, H, part, P + o_b1);
+    sgemm(ctx, (int)rows, H, H, H1, H, 1, P + o_W2, 1, H, H2, H, part, P + o_b2);
     hipLaunchKernelGGL(k_rowdot, dim3(nblk(rows, 4)), dim3(256), 0, ctx.stream, rows, H, H2, P + o_w3, P + o_b3, y);
     check_launch(ctx, "k_rowdot");
 }
@@ -427,11 +454,12 @@ double WarmStart::train() {
     // features and targets of every triple (per-step scaling)
     const int64_t rows = (int64_t)ns * n;
     float *X = Xall.ensure((size_t)rows * Fp), *T = Tall.ensure(rows);
+    double *fs = fscale.ensure(8);
     for (int s = 0; s < ns; ++s) {
-        const double rs = features(obs[s]->s.p, obs[s + 1]->s.p, obs[s]->g.p, obs[s + 1]->g.p,
-                                   obs[s + 2]->g.p, X + (int64_t)s * n * Fp);
+        features(obs[s]->s.p, obs[s + 1]->s.p, obs[s]->g.p, obs[s + 1]->g.p, obs[s + 2]->g.p,
+                 X + (int64_t)s * n * Fp, fs);
         hipLaunchKernelGGL(k_target, dim3(nblk(n, 256)), dim3(256), 0, ctx.stream, n, obs[s]->s.p,
-                           obs[s + 1]->s.p, obs[s + 2]->s.p, (float)(1.0 / rs), T + (int64_t)s * n);
+                           obs[s + 1]->s.p, obs[s + 2]->s.p, fs, T + (int64_t)s * n);
         check_launch(ctx, "k_target");
     }
     // Adam on shuffled mini-batches
@@ -469,10 +497,11 @@ void WarmStart::predict(const double *g_next, double *out) {
     if (obs.size() < 2) throw Error{YK_ERR_ARG, "warm start needs two observed steps to predict"};
     const Obs &a = *obs[obs.size() - 2], &b = *obs[obs.size() - 1];
     float *X = Xbat.ensure((size_t)std::max<int64_t>(n, (int64_t)opt.batch) * Fp);
-    const double rs = features(a.s.p, b.s.p, a.g.p, b.g.p, g_next, X);
+    double *fs = fscale.ensure(8);
+    features(a.s.p, b.s.p, a.g.p, b.g.p, g_next, X, fs);
     float *y = yb.ensure(std::max<int64_t>(n, (int64_t)opt.batch));
     forward(n, X, y);
-    hipLaunchKernelGGL(k_apply_pred, dim3(nblk(n, 256)), dim3(256), 0, ctx.stream, n, a.s.p, b.s.p, y, rs, out);
+    hipLaunchKernelGGL(k_apply_pred, dim3(nblk(n, 256)), dim3(256), 0, ctx.stream, n, a.s.p, b.s.p, y, fs, out);
     check_launch(ctx, "k_apply_pred");
 }
 

@@ -236,10 +236,16 @@ struct GmresResult {
 };
 // Solves A x = b; x holds the initial guess on entry (zero if zero_guess).
 // r0, when given (and zero_guess is false), is b - A x for that guess, which
-// saves the first operator application.  On return ctx.gm_r holds the true
-// residual b - A x of the returned x, unless b was zero.
+// saves the first operator application.  r0_norm2 / b_norm2, when >= 0, are
+// |r0|^2 and |b|^2 already known to the caller (each saves a synchronising
+// reduction).  On return ctx.gm_r holds the true residual b - A x of the
+// returned x, unless b was zero.
 GmresResult gmres(Context &ctx, const Apply &A, int64_t n, const double *b, double *x,
-                  bool zero_guess, double tol, int max_iter, int m, const double *r0 = nullptr);
+                  bool zero_guess, double tol, int max_iter, int m, const double *r0 = nullptr,
+                  double r0_norm2 = -1.0, double b_norm2 = -1.0);
+// pinned host memory of the context (512 doubles: [0, 257) the Arnoldi
+// column, [400, 416) the heat step's scalars)
+double *pinned_scalars(Context &ctx);
 // out[i] = v for i < n
 void launch_fill(Context &ctx, int64_t n, double v, double *out);
 // flag = 1 if a and b differ anywhere (bitwise), on the context's stream
