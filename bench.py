@@ -76,7 +76,7 @@ def rooflines(info, st, steps, fp32):
         ach = nbytes / (t * 1e-3) / 1e9
         out["near"] = {"kernel": "k_near_apply (cached near field, P2P)", "bound": "hbm", "achieved": ach,
                        "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": ach / PEAK_HBM_GBS,
-                       "traffic": measured_traffic("k_near_apply"), "avg_launch_ms": t,
+                       "traffic": None if fp32 else measured_traffic("k_near_apply"), "avg_launch_ms": t,
                        "launches_per_pass": leaf_calls / steps, "algorithmic_bytes": nbytes}
     m2l_ms, m2l_calls = st["m2l"]
     if m2l_calls:
@@ -85,7 +85,7 @@ def rooflines(info, st, steps, fp32):
         ach = m2l_flops(info) / (t * 1e-3) / 1e12
         out["m2l"] = {"kernel": "k_tile_gemm (M2L, all levels)", "bound": "mfma", "achieved": ach,
                       "peak": peak, "unit": "TFLOP/s", "frac": ach / peak,
-                      "traffic": measured_traffic("k_tile_gemm_m2l"), "avg_launch_ms": t,
+                      "traffic": None if fp32 else measured_traffic("k_tile_gemm_m2l"), "avg_launch_ms": t,
                       "launches_per_pass": m2l_calls / steps, "algorithmic_flops": m2l_flops(info)}
     return out
 
@@ -114,7 +114,10 @@ def m2l_flops(info):
     return 2.0 * info.P * info.P * info.m2l_translations
 
 
-def run_fmm_bench(args, yk, torch, W):
+def run_fmm_bench(args, yk, torch, W, fp32=None, lite=False):
+    """Times the FMM pass; lite skips the overlapped and on-the-fly variants."""
+    if fp32 is None:
+        fp32 = args.fp32
     cfg = W.config_c1(n_vol=args.n_vol, n_nodes=args.n_nodes, alpha=args.alpha, seed=1)
     b = cfg["bnd"]
     n_pts = cfg["vol"].shape[0] + b.n
@@ -123,7 +126,7 @@ def run_fmm_bench(args, yk, torch, W):
     bd = yk.Boundary.from_workload(b)
     out_v = torch.empty(vol.shape[0], dtype=torch.float64, device="cuda")
     out_b = torch.empty(b.n, dtype=torch.float64, device="cuda")
-    prec = yk.YK_PREC_FP32 if args.fp32 else yk.YK_PREC_FP64
+    prec = yk.YK_PREC_FP32 if fp32 else yk.YK_PREC_FP64
     opt = yk.yk_default_options()
     opt.fmm_tol, opt.p, opt.leaf_size, opt.precision = args.tol, args.p, args.leaf, prec
     ctx = yk.yk_create(opt)
@@ -151,7 +154,7 @@ def run_fmm_bench(args, yk, torch, W):
         # per-stage kernel times: once as run (near field overlapping the far
         # field on a second stream), once serialised for per-kernel rooflines
         stages_overlap, stages = {}, {}
-        for serial, dst in ((False, stages_overlap), (True, stages)):
+        for serial, dst in ((False, stages_overlap), (True, stages)) if not lite else ((True, stages),):
             opt.debug_flags = 2 if serial else 0
             yk.yk_set_options(ctx, opt)
             yk.yk_timing_enable(ctx, True)
@@ -161,14 +164,16 @@ def run_fmm_bench(args, yk, torch, W):
             dst.update(yk.yk_timing_read(ctx, reset=True))
             yk.yk_timing_enable(ctx, False)
         # the near field evaluated on the fly (no cached values), serialised
-        opt.debug_flags, opt.near_cache_mb = 2, 0
-        yk.yk_set_options(ctx, opt)
-        yk.yk_timing_enable(ctx, True)
-        yk.yk_timing_read(ctx, reset=True)
-        for _ in range(args.steps):
-            yk.yk_fmm_potential(ctx, vol, q, bd, dip, args.alpha, out_v, out_b)
-        stages_otf = yk.yk_timing_read(ctx, reset=True)
-        yk.yk_timing_enable(ctx, False)
+        stages_otf = {"leaf": (0.0, 0)}
+        if not lite:
+            opt.debug_flags, opt.near_cache_mb = 2, 0
+            yk.yk_set_options(ctx, opt)
+            yk.yk_timing_enable(ctx, True)
+            yk.yk_timing_read(ctx, reset=True)
+            for _ in range(args.steps):
+                yk.yk_fmm_potential(ctx, vol, q, bd, dip, args.alpha, out_v, out_b)
+            stages_otf = yk.yk_timing_read(ctx, reset=True)
+            yk.yk_timing_enable(ctx, False)
         opt.debug_flags, opt.near_cache_mb = 0, yk.yk_default_options().near_cache_mb
         yk.yk_set_options(ctx, opt)
         info = yk.yk_plan_info_get(ctx, 0)
@@ -317,6 +322,7 @@ def main():
     ap.add_argument("--heat-steps", type=int, default=100)
     ap.add_argument("--heat-m", type=int, default=1024)
     ap.add_argument("--no-heat", action="store_true")
+    ap.add_argument("--no-fp32-pass", action="store_true", help="skip the FP32 pass of the same workload")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a plain 256 MiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -359,7 +365,19 @@ def main():
     roof = max((r for k, r in roofs.items() if k != "near_on_the_fly"),
                key=lambda r: r["avg_launch_ms"] * r["launches_per_pass"])
     m2l_rate = roofs["m2l"]["achieved"] if "m2l" in roofs else None
-    err, errmax, idx, _ = direct_check(args, res, yk, torch)
+    err, errmax, idx, ref = direct_check(args, res, yk, torch)
+    fp32_pass = None
+    if not args.fp32 and not args.no_fp32_pass:
+        # the same pass with FP32 sums (P2P and M2L in FP32, M2L on FP32 matrix
+        # cores) at the same expansion order; its error is set by FP32 rounding
+        r32 = run_fmm_bench(args, yk, torch, W, fp32=True, lite=True)
+        got = r32["out"][idx]
+        fp32_pass = {
+            "value": r32["n_pts"] / (r32["ms"] * 1e-3) / 1e6, "unit": "Mpts/s", "ms_per_step": r32["ms"],
+            "dtype": "f32", "p": r32["info"].p,
+            "rel_err_l2_sampled": float(np.linalg.norm(got - ref) / np.linalg.norm(ref)),
+            "stage_ms_per_step": {k: v[0] / args.steps for k, v in r32["stages"].items()},
+            "rooflines": rooflines(r32["info"], r32["stages"], args.steps, True)}
     err_oracle = cpu = None
     if not args.no_cpu:
         err_oracle, cpu = oracle_baseline(args, res, idx)
@@ -388,6 +406,7 @@ def main():
         },
         "roofline": roof,
         "cpu_baseline": cpu,
+        "fp32_pass": fp32_pass,
         "time_step": heat,
     }
     print(json.dumps(line), flush=True)

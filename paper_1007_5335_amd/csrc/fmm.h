@@ -41,6 +41,8 @@ struct ActiveSet {
     DevBuf<int32_t> m2l_boxes;         // active boxes of levels lmin..L, sorted by (level, class)
     DevBuf<int4> m2l_tiles;            // {level, class, start, count} into m2l_boxes
     int n_tiles = 0;
+    DevBuf<int4> m2l_tiles_w;          // the same boxes in tiles of up to 128 (FP32 M2L)
+    int n_tiles_w = 0;
     std::vector<int64_t> l2l_begin, l2l_count;   // per level: active boxes (children) list slices
     DevBuf<int32_t> l2l_boxes;         // active boxes of levels lmin+1..L (level-major)
     std::vector<int> tile_begin, tile_count;     // per level: slice of m2l_tiles

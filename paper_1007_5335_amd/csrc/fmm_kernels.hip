@@ -669,7 +669,7 @@ template <typename TS> struct Pair2;
 template <> struct Pair2<double> { using type = yk_dpair; };
 template <> struct Pair2<float> { using type = yk_fpair; };
 
-template <typename T, typename TS, int PP, bool SPLIT_REQ>
+template <typename T, typename TS, int PP, bool SPLIT_REQ, int CB>
 __global__ __launch_bounds__(256) void k_tile_gemm(const int4 *__restrict__ tiles, int tile0,
                                                    const int32_t *__restrict__ boxes, int nslot,
                                                    const int32_t *__restrict__ src,
@@ -689,10 +689,11 @@ __global__ __launch_bounds__(256) void k_tile_gemm(const int4 *__restrict__ tile
     constexpr int kPairs = NCOL * LDA / 2;              // operator pairs per slot
     constexpr int NL2 = (kPairs + 255) / 256;           // pairs per thread
     constexpr int kMaxSlot = 27;
+    constexpr int NC = 64 * CB;                         // boxes (columns) per workgroup
     using V2 = typename Pair2<TS>::type;
     using T2 = typename Pair2<T>::type;
     __shared__ T As[2][NCOL * LDA];
-    __shared__ int32_t s_src[kMaxSlot * 64];
+    __shared__ int32_t s_src[kMaxSlot * NC];
     using MF = Mfma<T>;
     // nparts > 1 (few tiles): the slots of a tile are shared among nparts
     // workgroups, which add their partial sums atomically (assign must be 0)
@@ -702,22 +703,35 @@ __global__ __launch_bounds__(256) void k_tile_gemm(const int4 *__restrict__ tile
     const int level = tl.x, cls = tl.y, start = tl.z, count = tl.w;
     const int sl0 = part * nslot / nparts, sl1 = (part + 1) * nslot / nparts;
     const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, g = lane >> 4;
-    const int jb = 16 * w + (lane & 15);
-    const bool colvalid = jb < count;
-    const int64_t boxj = colvalid ? boxes[start + jb] : -1;
+    // column block c of this wavefront: columns 16 (CB w + c) + lane % 16
+    int jb[CB];
+    bool colvalid[CB];
+    int64_t boxj[CB];
+#pragma unroll
+    for (int c = 0; c < CB; ++c) {
+        jb[c] = 16 * (CB * w + c) + (lane & 15);
+        colvalid[c] = jb[c] < count;
+        boxj[c] = colvalid[c] ? boxes[start + jb[c]] : -1;
+    }
     // source box of every (slot, column) of the tile, -1 where empty
-    for (int e = sl0 * 64 + tid; e < sl1 * 64; e += 256) {
-        const int sl = e >> 6, j = e & 63;
+    for (int e = sl0 * NC + tid; e < sl1 * NC; e += 256) {
+        const int sl = e / NC, j = e % NC;
         s_src[e] = j < count ? src[(int64_t)boxes[start + j] * nslot + sl] : -1;
     }
-    typename MF::acc acc[NB];
+    typename MF::acc acc[CB][NB];
 #pragma unroll
-    for (int r = 0; r < NB; ++r) acc[r] = typename MF::acc{0, 0, 0, 0};
-    T rowacc = T(0), colacc[NB][4];
+    for (int c = 0; c < CB; ++c)
 #pragma unroll
-    for (int r = 0; r < NB; ++r)
+        for (int r = 0; r < NB; ++r) acc[c][r] = typename MF::acc{0, 0, 0, 0};
+    T rowacc[CB], colacc[CB][NB][4];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) colacc[r][q] = T(0);
+    for (int c = 0; c < CB; ++c) {
+        rowacc[c] = T(0);
+#pragma unroll
+        for (int r = 0; r < NB; ++r)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) colacc[c][r][q] = T(0);
+    }
     const T *Olev = Op + (int64_t)(level + level_shift) * op_stride;
     auto op_of = [&](int sl) -> const T2 * {
         return reinterpret_cast<const T2 *>(Olev + (size_t)slot_op[cls * nslot + sl] * PP * PP);
@@ -728,27 +742,39 @@ __global__ __launch_bounds__(256) void k_tile_gemm(const int4 *__restrict__ tile
     // slot) and the empty slot's zeros selected when the fragment is consumed,
     // so the loads of the next slot stay in flight during the current one (a
     // select, not a product, so whatever row 0 holds never reaches the sums)
-    V2 braw[NKP];
-    TS bsraw = TS(0);
-    bool bvalid = false;
-    T bcur[2 * NKP], bs = T(0);
+    V2 braw[CB][NKP];
+    TS bsraw[CB];
+    bool bvalid[CB];
+    T bcur[CB][2 * NKP], bs[CB];
+#pragma unroll
+    for (int c = 0; c < CB; ++c) {
+        bsraw[c] = TS(0);
+        bvalid[c] = false;
+        bs[c] = T(0);
+    }
     T2 pre[NL2];
     auto load_b = [&](int sl) {
-        const int32_t sj = s_src[sl * 64 + jb];
-        const TS *row = X + (int64_t)(sj >= 0 ? sj : 0) * PP;
-        const V2 *row2 = reinterpret_cast<const V2 *>(row) + g;
 #pragma unroll
-        for (int kp = 0; kp < NKP; ++kp) braw[kp] = row2[4 * kp];
-        if constexpr (SPLIT) bsraw = row[SP];
-        bvalid = sj >= 0;
+        for (int c = 0; c < CB; ++c) {
+            const int32_t sj = s_src[sl * NC + jb[c]];
+            const TS *row = X + (int64_t)(sj >= 0 ? sj : 0) * PP;
+            const V2 *row2 = reinterpret_cast<const V2 *>(row) + g;
+#pragma unroll
+            for (int kp = 0; kp < NKP; ++kp) braw[c][kp] = row2[4 * kp];
+            if constexpr (SPLIT) bsraw[c] = row[SP];
+            bvalid[c] = sj >= 0;
+        }
     };
     auto take_b = [&]() {
 #pragma unroll
-        for (int kp = 0; kp < NKP; ++kp) {
-            bcur[2 * kp] = bvalid ? (T)braw[kp].x : T(0);
-            bcur[2 * kp + 1] = bvalid ? (T)braw[kp].y : T(0);
+        for (int c = 0; c < CB; ++c) {
+#pragma unroll
+            for (int kp = 0; kp < NKP; ++kp) {
+                bcur[c][2 * kp] = bvalid[c] ? (T)braw[c][kp].x : T(0);
+                bcur[c][2 * kp + 1] = bvalid[c] ? (T)braw[c][kp].y : T(0);
+            }
+            if constexpr (SPLIT) bs[c] = bvalid[c] ? (T)bsraw[c] : T(0);
         }
-        if constexpr (SPLIT) bs = bvalid ? (T)bsraw : T(0);
     };
     __syncthreads();
     load_b(sl0);
@@ -772,15 +798,19 @@ __global__ __launch_bounds__(256) void k_tile_gemm(const int4 *__restrict__ tile
                 if (kPairs >= 256 * NL2 || tid + 256 * e < kPairs) pre[e] = Tg[gpair(tid + 256 * e)];
         }
         // operator column-major: A[i][k] = As[k * LDA + i]; step (kp, e) takes
-        // contraction index 8 kp + 2 g + e in lane group g
+        // contraction index 8 kp + 2 g + e in lane group g; each operator
+        // fragment read from LDS serves the CB column blocks
         const T *Ac = As[cur] + 2 * g * LDA + (lane & 15);
 #pragma unroll
         for (int kp = 0; kp < NKP; ++kp) {
 #pragma unroll
             for (int e = 0; e < 2; ++e) {
 #pragma unroll
-                for (int rt = 0; rt < NB; ++rt)
-                    acc[rt] = MF::step(Ac[(8 * kp + e) * LDA + 16 * rt], bcur[2 * kp + e], acc[rt]);
+                for (int rt = 0; rt < NB; ++rt) {
+                    const T a = Ac[(8 * kp + e) * LDA + 16 * rt];
+#pragma unroll
+                    for (int c = 0; c < CB; ++c) acc[c][rt] = MF::step(a, bcur[c][2 * kp + e], acc[c][rt]);
+                }
             }
         }
         if constexpr (SPLIT) {
@@ -790,12 +820,24 @@ __global__ __launch_bounds__(256) void k_tile_gemm(const int4 *__restrict__ tile
 #pragma unroll
             for (int kp = 0; kp < NKP; ++kp)
 #pragma unroll
-                for (int e = 0; e < 2; ++e) rowacc += A[(8 * kp + 2 * g + e) * LDA + SP] * bcur[2 * kp + e];
-            if (g == 0) rowacc += A[SP * LDA + SP] * bs;
+                for (int e = 0; e < 2; ++e) {
+                    const T a = A[(8 * kp + 2 * g + e) * LDA + SP];
+#pragma unroll
+                    for (int c = 0; c < CB; ++c) rowacc[c] += a * bcur[c][2 * kp + e];
+                }
+            if (g == 0) {
+                const T a = A[SP * LDA + SP];
+#pragma unroll
+                for (int c = 0; c < CB; ++c) rowacc[c] += a * bs[c];
+            }
 #pragma unroll
             for (int rt = 0; rt < NB; ++rt)
 #pragma unroll
-                for (int q = 0; q < 4; ++q) colacc[rt][q] += A[SP * LDA + 16 * rt + MF::row(lane, q)] * bs;
+                for (int q = 0; q < 4; ++q) {
+                    const T a = A[SP * LDA + 16 * rt + MF::row(lane, q)];
+#pragma unroll
+                    for (int c = 0; c < CB; ++c) colacc[c][rt][q] += a * bs[c];
+                }
         }
         if (more) {
             T2 *Ad = reinterpret_cast<T2 *>(As[cur ^ 1]);
@@ -806,34 +848,37 @@ __global__ __launch_bounds__(256) void k_tile_gemm(const int4 *__restrict__ tile
         }
         __syncthreads();
     }
-    if constexpr (SPLIT) {
-        rowacc += __shfl_xor(rowacc, 16, 64);
-        rowacc += __shfl_xor(rowacc, 32, 64);
-    }
-    if (colvalid) {
-        double *o = out + boxj * PP;
 #pragma unroll
-        for (int rt = 0; rt < NB; ++rt)
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int i = 16 * rt + MF::row(lane, q);
-                const double v = SPLIT ? (double)acc[rt][q] + (double)colacc[rt][q] : (double)acc[rt][q];
-                if (nparts > 1) atomicAdd(o + i, v);
-                else o[i] = assign ? v : o[i] + v;
-            }
+    for (int c = 0; c < CB; ++c) {
         if constexpr (SPLIT) {
-            if (g == 0) {
-                if (nparts > 1) atomicAdd(o + SP, (double)rowacc);
-                else o[SP] = assign ? (double)rowacc : o[SP] + (double)rowacc;
+            rowacc[c] += __shfl_xor(rowacc[c], 16, 64);
+            rowacc[c] += __shfl_xor(rowacc[c], 32, 64);
+        }
+        if (colvalid[c]) {
+            double *o = out + boxj[c] * PP;
+#pragma unroll
+            for (int rt = 0; rt < NB; ++rt)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int i = 16 * rt + MF::row(lane, q);
+                    const double v = SPLIT ? (double)acc[c][rt][q] + (double)colacc[c][rt][q] : (double)acc[c][rt][q];
+                    if (nparts > 1) atomicAdd(o + i, v);
+                    else o[i] = assign ? v : o[i] + v;
+                }
+            if constexpr (SPLIT) {
+                if (g == 0) {
+                    if (nparts > 1) atomicAdd(o + SP, (double)rowacc[c]);
+                    else o[SP] = assign ? (double)rowacc[c] : o[SP] + (double)rowacc[c];
+                }
+                // padding entries SP + 1 .. PP - 1 stay zero for later readers
+                if (assign)
+                    for (int i = SP + 1 + g; i < PP; i += 4) o[i] = 0.0;
             }
-            // padding entries SP + 1 .. PP - 1 stay zero for later readers
-            if (assign)
-                for (int i = SP + 1 + g; i < PP; i += 4) o[i] = 0.0;
         }
     }
 }
 
-template <typename T, typename TS>
+template <typename T, typename TS, int CB = 1>
 void launch_tile_gemm(Context &ctx, int P, int Pp, int ntiles, const int4 *tiles, int tile0,
                       const int32_t *boxes, int nslot, const int32_t *src, const int32_t *slot_op,
                       const T *Op, int64_t op_stride, int level_shift, const TS *X, int assign,
@@ -848,11 +893,11 @@ void launch_tile_gemm(Context &ctx, int P, int Pp, int ntiles, const int4 *tiles
 #define YK_TILE_CASE(PPV)                                                                          \
     case PPV:                                                                                      \
         if (split)                                                                                 \
-            hipLaunchKernelGGL((k_tile_gemm<T, TS, PPV, true>), dim3(grid), dim3(256), 0,         \
+            hipLaunchKernelGGL((k_tile_gemm<T, TS, PPV, true, CB>), dim3(grid), dim3(256), 0,     \
                                ctx.stream, tiles, tile0, boxes, nslot, src, slot_op, Op, op_stride, \
                                level_shift, X, assign, nparts, out);                              \
         else                                                                                       \
-            hipLaunchKernelGGL((k_tile_gemm<T, TS, PPV, false>), dim3(grid), dim3(256), 0,        \
+            hipLaunchKernelGGL((k_tile_gemm<T, TS, PPV, false, CB>), dim3(grid), dim3(256), 0,    \
                                ctx.stream, tiles, tile0, boxes, nslot, src, slot_op, Op, op_stride, \
                                level_shift, X, assign, nparts, out);                              \
         break;
@@ -1661,10 +1706,13 @@ void fmm_run(Context &ctx, FmmPlan &pl, const double *q, const double *dn, doubl
             {
                 // M2L of every level at once (levels are independent given the multipoles)
                 StageTimer tl(ctx, YK_STAGE_M2L);
+                // (FP32: 128-box tiles, two column blocks per wavefront, so each
+                // operator fragment feeds two matrix-core steps)
                 if (f32)
-                    launch_tile_gemm<float, float>(ctx, P, Pp, as.n_tiles, as.m2l_tiles.p, 0, as.m2l_boxes.p,
-                                                   kNumV, pl.vlist.p, pl.slot_oid.p, pl.m2lf.p,
-                                                   (int64_t)kNumOff * Pp * Pp, 0, pl.Mf.p, 0, pl.Lc.p);
+                    launch_tile_gemm<float, float, 2>(ctx, P, Pp, as.n_tiles_w, as.m2l_tiles_w.p, 0,
+                                                      as.m2l_boxes.p, kNumV, pl.vlist.p, pl.slot_oid.p,
+                                                      pl.m2lf.p, (int64_t)kNumOff * Pp * Pp, 0, pl.Mf.p, 0,
+                                                      pl.Lc.p);
                 else
                     launch_tile_gemm<double, double>(ctx, P, Pp, as.n_tiles, as.m2l_tiles.p, 0, as.m2l_boxes.p,
                                                      kNumV, pl.vlist.p, pl.slot_oid.p, pl.m2l.p,

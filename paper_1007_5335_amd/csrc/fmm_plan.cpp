@@ -575,7 +575,7 @@ ActiveSet &get_active(Context &ctx, FmmPlan &pl, int mask) {
         YK_HIP(hipStreamSynchronize(ctx.stream));
     }
     std::vector<int32_t> mb;
-    std::vector<int4> tiles;
+    std::vector<int4> tiles, wtiles;
     for (int l = pl.lmin; l <= L; ++l) {
         for (int cls = 0; cls < 4; ++cls) {
             const int64_t start = (int64_t)mb.size();
@@ -590,6 +590,8 @@ ActiveSet &get_active(Context &ctx, FmmPlan &pl, int mask) {
             }
             for (int64_t s = start; s < (int64_t)mb.size(); s += kTile)
                 tiles.push_back(make_int4(l, cls, (int)s, (int)std::min<int64_t>(kTile, (int64_t)mb.size() - s)));
+            for (int64_t s = start; s < (int64_t)mb.size(); s += 2 * kTile)
+                wtiles.push_back(make_int4(l, cls, (int)s, (int)std::min<int64_t>(2 * kTile, (int64_t)mb.size() - s)));
         }
     }
     as->tile_begin.assign(L + 1, 0);
@@ -616,11 +618,13 @@ ActiveSet &get_active(Context &ctx, FmmPlan &pl, int mask) {
     };
     up(as->m2l_boxes, mb);
     up(as->m2l_tiles, tiles);
+    up(as->m2l_tiles_w, wtiles);
     up(as->l2l_boxes, l2lb);
     up(as->leaves, leaves);
     up(as->leaf_items, items);
     as->n_items = (int64_t)items.size();
     as->n_tiles = (int)tiles.size();
+    as->n_tiles_w = (int)wtiles.size();
     as->n_leaves = (int64_t)leaves.size();
     as->n_m2l_boxes = (int64_t)mb.size();
     YK_HIP(hipStreamSynchronize(ctx.stream));
