@@ -323,6 +323,8 @@ def main():
     ap.add_argument("--heat-m", type=int, default=1024)
     ap.add_argument("--no-heat", action="store_true")
     ap.add_argument("--no-fp32-pass", action="store_true", help="skip the FP32 pass of the same workload")
+    ap.add_argument("--heat-only", action="store_true",
+                    help="only the time-stepping comparison (profiling runs); prints its JSON object")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a plain 256 MiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -338,6 +340,9 @@ def main():
     yk.load_library()
     torch.cuda.set_device(0)
 
+    if args.heat_only:
+        print(json.dumps(heat_step_bench(args, yk, torch, W)), flush=True)
+        return
     if args.calib_copy:
         # a fill (writes 256 MiB) and an elementwise multiply (reads 256 MiB,
         # writes 256 MiB): reference dispatches for the HBM byte counters

@@ -40,17 +40,21 @@ typedef float f4v __attribute__((ext_vector_type(4)));
 // C[z][m][n] = sum_{k in chunk z} A(m,k) B(k,n), A(m,k) = A[m*sam + k*sak],
 // B(k,n) = B[k*sbk + n*sbn].  64 x 64 tiles, 4 wavefronts each owning a
 // 32 x 32 quarter (2 x 2 tiles of v_mfma_f32_16x16x4f32), K staged in LDS in
-// steps of 16.  gridDim.z > 1 splits K; the partial sums are added afterwards
-// in a fixed order.  With tb (one split only) the result is tanh(C + tb[n]).
+// steps of 32; the next step's global loads are issued before the current
+// step's matrix-core work, so they are in flight during it.  gridDim.z > 1
+// splits K; the partial sums are added afterwards in a fixed order.  With tb
+// (one split only) the result is tanh(C + tb[n]).
 constexpr int kLdsPad = 80;   // row stride of the LDS tiles (keeps the four lane groups on distinct banks)
+constexpr int kGemmKS = 32;   // K per LDS step
 
 __global__ __launch_bounds__(256) void k_sgemm(int M, int N, int K, const float *__restrict__ A,
                                                int64_t sam, int64_t sak, const float *__restrict__ B,
                                                int64_t sbk, int64_t sbn, float *__restrict__ C,
                                                int64_t ldc, int64_t ldz, int kchunk,
                                                const float *__restrict__ tb) {
-    __shared__ float As[16][kLdsPad];
-    __shared__ float Bs[16][kLdsPad];
+    constexpr int KS = kGemmKS, NE = 64 * KS / 256;   // elements per thread per operand and step
+    __shared__ float As[KS][kLdsPad];
+    __shared__ float Bs[KS][kLdsPad];
     const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
     const int m0 = blockIdx.y * 64, n0 = blockIdx.x * 64;
     const int kbeg = blockIdx.z * kchunk, kend = min(K, kbeg + kchunk);
@@ -59,22 +63,41 @@ __global__ __launch_bounds__(256) void k_sgemm(int M, int N, int K, const float 
     for (int i = 0; i < 2; ++i)
         for (int j = 0; j < 2; ++j) acc[i][j] = f4v{0.f, 0.f, 0.f, 0.f};
     const bool a_kfast = sak == 1, b_nfast = sbn == 1;
-    for (int k0 = kbeg; k0 < kend; k0 += 16) {
+    // element e of this thread in a step: A tile (mm, kk), B tile (kb, nn)
+    auto a_idx = [&](int e, int &mm, int &kk) {
+        const int idx = tid + 256 * e;
+        if (a_kfast) { mm = idx / KS; kk = idx % KS; } else { kk = idx >> 6; mm = idx & 63; }
+    };
+    auto b_idx = [&](int e, int &kb, int &nn) {
+        const int idx = tid + 256 * e;
+        if (b_nfast) { kb = idx >> 6; nn = idx & 63; } else { nn = idx / KS; kb = idx % KS; }
+    };
+    float ra[NE], rb[NE];
+    auto gload = [&](int k0) {
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            const int idx = tid + 256 * e;
-            int mm, kk;
-            if (a_kfast) { mm = idx >> 4; kk = idx & 15; } else { kk = idx >> 6; mm = idx & 63; }
-            const int gm = m0 + mm, gk = k0 + kk;
-            As[kk][mm] = (gm < M && gk < kend) ? A[(int64_t)gm * sam + (int64_t)gk * sak] : 0.f;
-            int nn, kb;
-            if (b_nfast) { kb = idx >> 6; nn = idx & 63; } else { nn = idx >> 4; kb = idx & 15; }
-            const int gn = n0 + nn, gkb = k0 + kb;
-            Bs[kb][nn] = (gn < N && gkb < kend) ? B[(int64_t)gkb * sbk + (int64_t)gn * sbn] : 0.f;
+        for (int e = 0; e < NE; ++e) {
+            int mm, kk, kb, nn;
+            a_idx(e, mm, kk);
+            b_idx(e, kb, nn);
+            const int gm = m0 + mm, gk = k0 + kk, gn = n0 + nn, gkb = k0 + kb;
+            ra[e] = (gm < M && gk < kend) ? A[(int64_t)gm * sam + (int64_t)gk * sak] : 0.f;
+            rb[e] = (gn < N && gkb < kend) ? B[(int64_t)gkb * sbk + (int64_t)gn * sbn] : 0.f;
+        }
+    };
+    if (kbeg < kend) gload(kbeg);
+    for (int k0 = kbeg; k0 < kend; k0 += KS) {
+#pragma unroll
+        for (int e = 0; e < NE; ++e) {
+            int mm, kk, kb, nn;
+            a_idx(e, mm, kk);
+            b_idx(e, kb, nn);
+            As[kk][mm] = ra[e];
+            Bs[kb][nn] = rb[e];
         }
         __syncthreads();
+        if (k0 + KS < kend) gload(k0 + KS);
 #pragma unroll
-        for (int kq = 0; kq < 4; ++kq) {
+        for (int kq = 0; kq < KS / 4; ++kq) {
             const int kk = 4 * kq + (lane >> 4);
             const float a0 = As[kk][wm + (lane & 15)], a1 = As[kk][wm + 16 + (lane & 15)];
             const float b0 = Bs[kk][wn + (lane & 15)], b1 = Bs[kk][wn + 16 + (lane & 15)];
@@ -104,6 +127,7 @@ __global__ void k_sum_partials(int64_t n, int nz, const float *__restrict__ part
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     float s = 0.f;
+#pragma unroll 8
     for (int z = 0; z < nz; ++z) s += part[z * ldz + i];
     out[i] = s;
 }
@@ -164,7 +188,8 @@ __global__ void k_back_tanh(int64_t n, const float *__restrict__ H, float *__res
     D[i] *= 1.f - h * h;
 }
 
-// column sums over row blocks: part[blk][c]
+// column sums over row blocks: part[blk][c] (one thread per column, eight
+// rows' loads in flight, rows taken in increasing order)
 __global__ void k_colsum_part(int64_t rows, int cols, const float *__restrict__ D, int rows_per_blk,
                               float *__restrict__ part) {
     const int c = threadIdx.x + blockIdx.y * blockDim.x;
@@ -172,8 +197,41 @@ __global__ void k_colsum_part(int64_t rows, int cols, const float *__restrict__ 
     const int64_t r0 = (int64_t)blockIdx.x * rows_per_blk;
     const int64_t r1 = min<int64_t>(rows, r0 + rows_per_blk);
     float s = 0.f;
-    for (int64_t r = r0; r < r1; ++r) s += D[r * cols + c];
+    int64_t r = r0;
+    for (; r + 8 <= r1; r += 8) {
+        float v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = D[(r + u) * cols + c];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) s += v[u];
+    }
+    for (; r < r1; ++r) s += D[r * cols + c];
     part[(int64_t)blockIdx.x * cols + c] = s;
+}
+
+// out[c] = sum_b part[b][c] over nb row blocks: 64 columns per block, four
+// wavefronts taking the row blocks b = w (mod 4), then the four sums in order
+__global__ __launch_bounds__(256) void k_colsum_final(int nb, int cols, const float *__restrict__ part,
+                                                      float *__restrict__ out) {
+    __shared__ float sh[4][64];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int c = blockIdx.x * 64 + lane;
+    float s = 0.f;
+    if (c < cols) {
+        int b = w;
+        for (; b + 12 < nb; b += 16) {
+            const float v0 = part[(int64_t)b * cols + c], v1 = part[(int64_t)(b + 4) * cols + c];
+            const float v2 = part[(int64_t)(b + 8) * cols + c], v3 = part[(int64_t)(b + 12) * cols + c];
+            s += v0;
+            s += v1;
+            s += v2;
+            s += v3;
+        }
+        for (; b < nb; b += 4) s += part[(int64_t)b * cols + c];
+    }
+    sh[w][lane] = s;
+    __syncthreads();
+    if (w == 0 && c < cols) out[c] = (sh[0][lane] + sh[1][lane]) + (sh[2][lane] + sh[3][lane]);
 }
 
 __global__ void k_adam(int64_t n, float *__restrict__ p, const float *__restrict__ g, float *__restrict__ m,
@@ -310,7 +368,7 @@ void sgemm(Context &ctx, int M, int N, int K, const float *A, int64_t sam, int64
     int nz = 1;
     if ((int64_t)gm * gn < 256 && K > 1024) nz = (int)std::min<int64_t>(64, std::max<int64_t>(1, 512 / ((int64_t)gm * gn)));
     int kchunk = (K + nz - 1) / nz;
-    kchunk = (kchunk + 15) / 16 * 16;
+    kchunk = (kchunk + kGemmKS - 1) / kGemmKS * kGemmKS;
     nz = (K + kchunk - 1) / kchunk;
     if (nz <= 1) {
         hipLaunchKernelGGL(k_sgemm, dim3(gn, gm, 1), dim3(256), 0, ctx.stream, M, N, K, A, sam, sak, B, sbk, sbn,
@@ -437,15 +495,14 @@ double WarmStart::loss_grad(int64_t rows, const float *X, const float *T, float 
 }
 
 void WarmStart::colsum(int64_t rows, int cols, const float *D, float *out) {
-    const int rpb = 512;
+    const int rpb = 128;
     const int nbr = (int)nblk(rows, rpb);
     float *p = cpart.ensure((size_t)nbr * cols);
     hipLaunchKernelGGL(k_colsum_part, dim3(nbr, nblk(cols, 256)), dim3(256), 0, ctx.stream, rows, cols, D, rpb, p);
     check_launch(ctx, "k_colsum_part");
     // fixed-order reduction of the row-block partials
-    hipLaunchKernelGGL(k_sum_partials, dim3(nblk(cols, 256)), dim3(256), 0, ctx.stream, (int64_t)cols, nbr, p,
-                       (int64_t)cols, out);
-    check_launch(ctx, "k_sum_partials");
+    hipLaunchKernelGGL(k_colsum_final, dim3(nblk(cols, 64)), dim3(256), 0, ctx.stream, nbr, cols, p, out);
+    check_launch(ctx, "k_colsum_final");
 }
 
 double WarmStart::train() {
