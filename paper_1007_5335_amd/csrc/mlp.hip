@@ -40,19 +40,21 @@ typedef float f4v __attribute__((ext_vector_type(4)));
 // C[z][m][n] = sum_{k in chunk z} A(m,k) B(k,n), A(m,k) = A[m*sam + k*sak],
 // B(k,n) = B[k*sbk + n*sbn].  64 x 64 tiles, 4 wavefronts each owning a
 // 32 x 32 quarter (2 x 2 tiles of v_mfma_f32_16x16x4f32), K staged in LDS in
-// steps of 32; the next step's global loads are issued before the current
-// step's matrix-core work, so they are in flight during it.  gridDim.z > 1
+// steps of KS (16 for a tall output with many tiles, 32 for a split K); the
+// next step's global loads are issued before the current step's matrix-core
+// work, so they are in flight during it.  gridDim.z > 1
 // splits K; the partial sums are added afterwards in a fixed order.  With tb
 // (one split only) the result is tanh(C + tb[n]).
 constexpr int kLdsPad = 80;   // row stride of the LDS tiles (keeps the four lane groups on distinct banks)
-constexpr int kGemmKS = 32;   // K per LDS step
+constexpr int kGemmKSplit = 32;   // K per LDS step when K is split
 
+template <int KS>
 __global__ __launch_bounds__(256) void k_sgemm(int M, int N, int K, const float *__restrict__ A,
                                                int64_t sam, int64_t sak, const float *__restrict__ B,
                                                int64_t sbk, int64_t sbn, float *__restrict__ C,
                                                int64_t ldc, int64_t ldz, int kchunk,
                                                const float *__restrict__ tb) {
-    constexpr int KS = kGemmKS, NE = 64 * KS / 256;   // elements per thread per operand and step
+    constexpr int NE = 64 * KS / 256;   // elements per thread per operand and step
     __shared__ float As[KS][kLdsPad];
     __shared__ float Bs[KS][kLdsPad];
     const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
@@ -298,34 +300,44 @@ __global__ void k_feature_scales(int64_t n, const double *__restrict__ part, dou
 }
 
 // Features of every node for one (N-1, N, N+1) triple; fs holds the per-step
-// scales written by k_feature_scales.
-__global__ void k_features(int64_t n, const double *__restrict__ sm1, const double *__restrict__ s0,
-                           const double *__restrict__ gm1, const double *__restrict__ g0,
-                           const double *__restrict__ gp1, const double *__restrict__ kappa,
-                           const int32_t *__restrict__ curve, const int32_t *__restrict__ idx,
-                           const int64_t *__restrict__ off, const double *__restrict__ fs, int Fp,
-                           float *__restrict__ X) {
-    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= n) return;
-    const float sc0 = (float)fs[0], sc1 = (float)fs[1], sc2 = (float)fs[2], sc4 = (float)fs[3];
-    const float extra0 = (float)fs[4], extra1 = (float)fs[5];
-    const int k = curve[j];
-    const int64_t base = off[k], nk = off[k + 1] - off[k];
-    const int64_t jl = idx[j];
-    float *row = X + j * Fp;
-    for (int o = 0; o < 13; ++o) {
-        int64_t q = (jl + kOffsets[o]) % nk;
-        if (q < 0) q += nk;
-        const int64_t jj = base + q;
-        row[0 * 13 + o] = (float)(s0[jj] * sc0);
-        row[1 * 13 + o] = (float)((s0[jj] - sm1[jj]) * sc1);
-        row[2 * 13 + o] = (float)((gp1[jj] - g0[jj]) * sc2);
-        row[3 * 13 + o] = (float)((g0[jj] - gm1[jj]) * sc2);
-        row[4 * 13 + o] = (float)(kappa[jj] * sc4);
+// scales written by k_feature_scales.  A block builds the rows of 64 nodes in
+// LDS (four thread groups over the 13 offsets) and stores them as one
+// contiguous run of 64 Fp floats.
+constexpr int kFp = (kFeat + 15) / 16 * 16;   // padded feature count
+__global__ __launch_bounds__(256) void k_features(
+    int64_t n, const double *__restrict__ sm1, const double *__restrict__ s0,
+    const double *__restrict__ gm1, const double *__restrict__ g0, const double *__restrict__ gp1,
+    const double *__restrict__ kappa, const int32_t *__restrict__ curve, const int32_t *__restrict__ idx,
+    const int64_t *__restrict__ off, const double *__restrict__ fs, float *__restrict__ X) {
+    __shared__ float rows[64 * kFp];
+    const int r = threadIdx.x & 63, grp = threadIdx.x >> 6;
+    const int64_t j0 = (int64_t)blockIdx.x * 64, j = j0 + r;
+    const int nrow = (int)min<int64_t>(64, n - j0);
+    if (j < n) {
+        const float sc0 = (float)fs[0], sc1 = (float)fs[1], sc2 = (float)fs[2], sc4 = (float)fs[3];
+        const int k = curve[j];
+        const int64_t base = off[k], nk = off[k + 1] - off[k];
+        const int64_t jl = idx[j];
+        float *row = rows + r * kFp;
+        for (int o = grp; o < 13; o += 4) {
+            int64_t q = (jl + kOffsets[o]) % nk;
+            if (q < 0) q += nk;
+            const int64_t jj = base + q;
+            row[0 * 13 + o] = (float)(s0[jj] * sc0);
+            row[1 * 13 + o] = (float)((s0[jj] - sm1[jj]) * sc1);
+            row[2 * 13 + o] = (float)((gp1[jj] - g0[jj]) * sc2);
+            row[3 * 13 + o] = (float)((g0[jj] - gm1[jj]) * sc2);
+            row[4 * 13 + o] = (float)(kappa[jj] * sc4);
+        }
+        if (grp == 3) {
+            row[65] = (float)fs[4];
+            row[66] = (float)fs[5];
+            for (int f = kFeat; f < kFp; ++f) row[f] = 0.f;
+        }
     }
-    row[65] = extra0;
-    row[66] = extra1;
-    for (int f = kFeat; f < Fp; ++f) row[f] = 0.f;
+    __syncthreads();
+    float *dst = X + j0 * kFp;
+    for (int e = threadIdx.x; e < nrow * kFp; e += 256) dst[e] = rows[e];
 }
 
 // target (sigma^{N+1} - 2 sigma^N + sigma^{N-1}) / r_s, r_s = fs[6]
@@ -368,18 +380,18 @@ void sgemm(Context &ctx, int M, int N, int K, const float *A, int64_t sam, int64
     int nz = 1;
     if ((int64_t)gm * gn < 256 && K > 1024) nz = (int)std::min<int64_t>(64, std::max<int64_t>(1, 512 / ((int64_t)gm * gn)));
     int kchunk = (K + nz - 1) / nz;
-    kchunk = (kchunk + kGemmKS - 1) / kGemmKS * kGemmKS;
+    kchunk = (kchunk + kGemmKSplit - 1) / kGemmKSplit * kGemmKSplit;
     nz = (K + kchunk - 1) / kchunk;
     if (nz <= 1) {
-        hipLaunchKernelGGL(k_sgemm, dim3(gn, gm, 1), dim3(256), 0, ctx.stream, M, N, K, A, sam, sak, B, sbk, sbn,
-                           C, ldc, (int64_t)0, K, tanh_bias);
+        hipLaunchKernelGGL(k_sgemm<16>, dim3(gn, gm, 1), dim3(256), 0, ctx.stream, M, N, K, A, sam, sak, B, sbk,
+                           sbn, C, ldc, (int64_t)0, K, tanh_bias);
         check_launch(ctx, "k_sgemm");
         return;
     }
     const int64_t ldz = (int64_t)M * ldc;
     float *p = part.ensure((size_t)nz * ldz);
-    hipLaunchKernelGGL(k_sgemm, dim3(gn, gm, nz), dim3(256), 0, ctx.stream, M, N, K, A, sam, sak, B, sbk, sbn,
-                       p, ldc, ldz, kchunk, (const float *)nullptr);
+    hipLaunchKernelGGL(k_sgemm<kGemmKSplit>, dim3(gn, gm, nz), dim3(256), 0, ctx.stream, M, N, K, A, sam, sak, B,
+                       sbk, sbn, p, ldc, ldz, kchunk, (const float *)nullptr);
     check_launch(ctx, "k_sgemm");
     hipLaunchKernelGGL(k_sum_partials, dim3(nblk(ldz, 256)), dim3(256), 0, ctx.stream, ldz, nz, p, ldz, C);
     check_launch(ctx, "k_sum_partials");
@@ -446,8 +458,9 @@ void WarmStart::features(const double *sm1, const double *s0, const double *gm1,
     check_launch(ctx, "k_sumsq5");
     hipLaunchKernelGGL(k_feature_scales, dim3(1), dim3(64), 0, ctx.stream, n, part, fs);
     check_launch(ctx, "k_feature_scales");
-    hipLaunchKernelGGL(k_features, dim3(nblk(n, 256)), dim3(256), 0, ctx.stream, n, sm1, s0, gm1, g0, gp1,
-                       kappa, curve, idx, off.p, fs, Fp, X);
+    if (Fp != kFp) throw Error{YK_ERR_INTERNAL, "feature width mismatch"};
+    hipLaunchKernelGGL(k_features, dim3(nblk(n, 64)), dim3(256), 0, ctx.stream, n, sm1, s0, gm1, g0, gp1,
+                       kappa, curve, idx, off.p, fs, X);
     check_launch(ctx, "k_features");
 }
 
