@@ -43,6 +43,13 @@ struct ActiveSet {
     int n_tiles = 0;
     DevBuf<int4> m2l_tiles_w;          // the same boxes in tiles of up to 128 (FP32 M2L)
     int n_tiles_w = 0;
+    // sparse M2L (trees whose V lists are mostly empty, such as a boundary
+    // tree): the non-empty translations bucketed by (level, offset), tiles
+    // {level, offset id, start, count} of up to 64 (target, source) pairs
+    bool m2l_sparse = false;
+    DevBuf<int4> m2l_ptiles;
+    int n_ptiles = 0;
+    DevBuf<int32_t> m2l_ptgt, m2l_psrc, m2l_piota;
     std::vector<int64_t> l2l_begin, l2l_count;   // per level: active boxes (children) list slices
     DevBuf<int32_t> l2l_boxes;         // active boxes of levels lmin+1..L (level-major)
     std::vector<int> tile_begin, tile_count;     // per level: slice of m2l_tiles
@@ -100,6 +107,8 @@ struct FmmPlan {
     DevBuf<int32_t> slot_oid;          // [4 classes][27 slots] -> offset id in 0..39
     DevBuf<int32_t> child4;            // [nbox][4] child at each position, -1 if none
     DevBuf<int32_t> iota4;             // {0,1,2,3}: slot -> operator for M2M and L2L
+    DevBuf<int32_t> iota40;            // 0..39: offset id -> M2L operator (sparse M2L)
+    std::vector<int32_t> h_soid;       // host copy of slot_oid
     DevBuf<int4> up_tiles;             // M2M tiles: parents of levels lmin..L-1, 64 per tile
     DevBuf<int32_t> up_boxes;
     std::vector<int> up_tile_begin, up_tile_count;

@@ -676,7 +676,8 @@ __global__ __launch_bounds__(256) void k_tile_gemm(const int4 *__restrict__ tile
                                                    const int32_t *__restrict__ slot_op,
                                                    const T *__restrict__ Op, int64_t op_stride,
                                                    int level_shift, const TS *__restrict__ X,
-                                                   int assign, int nparts, double *__restrict__ out) {
+                                                   int assign, int nparts, double *__restrict__ out,
+                                                   const int32_t *__restrict__ tgt, int atom) {
     constexpr bool SPLIT = SPLIT_REQ && PP > 16;   // (the host never asks for PP = 16)
     constexpr int NB = SPLIT ? PP / 16 - 1 : PP / 16;   // 16-row blocks on the matrix cores
     constexpr int SP = 16 * NB;                         // split-off index (SPLIT only)
@@ -696,7 +697,9 @@ __global__ __launch_bounds__(256) void k_tile_gemm(const int4 *__restrict__ tile
     __shared__ int32_t s_src[kMaxSlot * NC];
     using MF = Mfma<T>;
     // nparts > 1 (few tiles): the slots of a tile are shared among nparts
-    // workgroups, which add their partial sums atomically (assign must be 0)
+    // workgroups, which add their partial sums atomically (assign must be 0).
+    // With tgt (sparse M2L) the tile's entries are translation indices: the
+    // source is src[entry], the result is added atomically to row tgt[entry].
     const int bid = xcd_remap(blockIdx.x, gridDim.x);
     const int part = bid % nparts;
     const int4 tl = tiles[tile0 + bid / nparts];
@@ -711,7 +714,7 @@ __global__ __launch_bounds__(256) void k_tile_gemm(const int4 *__restrict__ tile
     for (int c = 0; c < CB; ++c) {
         jb[c] = 16 * (CB * w + c) + (lane & 15);
         colvalid[c] = jb[c] < count;
-        boxj[c] = colvalid[c] ? boxes[start + jb[c]] : -1;
+        boxj[c] = colvalid[c] ? (tgt ? tgt[boxes[start + jb[c]]] : boxes[start + jb[c]]) : -1;
     }
     // source box of every (slot, column) of the tile, -1 where empty
     for (int e = sl0 * NC + tid; e < sl1 * NC; e += 256) {
@@ -862,12 +865,12 @@ __global__ __launch_bounds__(256) void k_tile_gemm(const int4 *__restrict__ tile
                 for (int q = 0; q < 4; ++q) {
                     const int i = 16 * rt + MF::row(lane, q);
                     const double v = SPLIT ? (double)acc[c][rt][q] + (double)colacc[c][rt][q] : (double)acc[c][rt][q];
-                    if (nparts > 1) atomicAdd(o + i, v);
+                    if (nparts > 1 || atom) atomicAdd(o + i, v);
                     else o[i] = assign ? v : o[i] + v;
                 }
             if constexpr (SPLIT) {
                 if (g == 0) {
-                    if (nparts > 1) atomicAdd(o + SP, (double)rowacc[c]);
+                    if (nparts > 1 || atom) atomicAdd(o + SP, (double)rowacc[c]);
                     else o[SP] = assign ? (double)rowacc[c] : o[SP] + (double)rowacc[c];
                 }
                 // padding entries SP + 1 .. PP - 1 stay zero for later readers
@@ -882,8 +885,9 @@ template <typename T, typename TS, int CB = 1>
 void launch_tile_gemm(Context &ctx, int P, int Pp, int ntiles, const int4 *tiles, int tile0,
                       const int32_t *boxes, int nslot, const int32_t *src, const int32_t *slot_op,
                       const T *Op, int64_t op_stride, int level_shift, const TS *X, int assign,
-                      double *out) {
+                      double *out, const int32_t *tgt = nullptr) {
     if (ntiles <= 0) return;
+    const int atom = tgt ? 1 : 0;
     if (nslot < 1 || nslot > 27) throw Error{YK_ERR_INTERNAL, "tile GEMM supports 1..27 slots"};
     const bool split = Pp >= 32 && P == Pp - 15;
     // fewer tiles than compute units: share each tile's slots among up to 7
@@ -895,11 +899,11 @@ void launch_tile_gemm(Context &ctx, int P, int Pp, int ntiles, const int4 *tiles
         if (split)                                                                                 \
             hipLaunchKernelGGL((k_tile_gemm<T, TS, PPV, true, CB>), dim3(grid), dim3(256), 0,     \
                                ctx.stream, tiles, tile0, boxes, nslot, src, slot_op, Op, op_stride, \
-                               level_shift, X, assign, nparts, out);                              \
+                               level_shift, X, assign, nparts, out, tgt, atom);                   \
         else                                                                                       \
             hipLaunchKernelGGL((k_tile_gemm<T, TS, PPV, false, CB>), dim3(grid), dim3(256), 0,    \
                                ctx.stream, tiles, tile0, boxes, nslot, src, slot_op, Op, op_stride, \
-                               level_shift, X, assign, nparts, out);                              \
+                               level_shift, X, assign, nparts, out, tgt, atom);                   \
         break;
     switch (Pp) {
         YK_TILE_CASE(16)
@@ -1708,7 +1712,17 @@ void fmm_run(Context &ctx, FmmPlan &pl, const double *q, const double *dn, doubl
                 StageTimer tl(ctx, YK_STAGE_M2L);
                 // (FP32: 128-box tiles, two column blocks per wavefront, so each
                 // operator fragment feeds two matrix-core steps)
-                if (f32)
+                if (as.m2l_sparse && f32)
+                    launch_tile_gemm<float, float>(ctx, P, Pp, as.n_ptiles, as.m2l_ptiles.p, 0, as.m2l_piota.p,
+                                                   1, as.m2l_psrc.p, pl.iota40.p, pl.m2lf.p,
+                                                   (int64_t)kNumOff * Pp * Pp, 0, pl.Mf.p, 0, pl.Lc.p,
+                                                   as.m2l_ptgt.p);
+                else if (as.m2l_sparse)
+                    launch_tile_gemm<double, double>(ctx, P, Pp, as.n_ptiles, as.m2l_ptiles.p, 0,
+                                                     as.m2l_piota.p, 1, as.m2l_psrc.p, pl.iota40.p, pl.m2l.p,
+                                                     (int64_t)kNumOff * Pp * Pp, 0, pl.M.p, 0, pl.Lc.p,
+                                                     as.m2l_ptgt.p);
+                else if (f32)
                     launch_tile_gemm<float, float, 2>(ctx, P, Pp, as.n_tiles_w, as.m2l_tiles_w.p, 0,
                                                       as.m2l_boxes.p, kNumV, pl.vlist.p, pl.slot_oid.p,
                                                       pl.m2lf.p, (int64_t)kNumOff * Pp * Pp, 0, pl.Mf.p, 0,

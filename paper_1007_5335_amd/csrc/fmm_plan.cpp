@@ -345,6 +345,12 @@ void build_lists_and_tables(Context &ctx, FmmPlan &pl, const std::vector<uint32_
     up(pl.slot_oid, soid);
     up(pl.child4, ch4);
     up(pl.iota4, iota4);
+    {
+        std::vector<int32_t> iota40(kNumOff);
+        for (int k = 0; k < kNumOff; ++k) iota40[k] = k;
+        up(pl.iota40, iota40);
+    }
+    pl.h_soid = soid;
     if (!utiles.empty()) {
         up(pl.up_tiles, utiles);
         up(pl.up_boxes, uboxes);
@@ -594,6 +600,38 @@ ActiveSet &get_active(Context &ctx, FmmPlan &pl, int mask) {
                 wtiles.push_back(make_int4(l, cls, (int)s, (int)std::min<int64_t>(2 * kTile, (int64_t)mb.size() - s)));
         }
     }
+    // sparse M2L when fewer than half of the V-list slots of the active boxes
+    // hold a source (on a small tree, where the dense tiles' empty slots cost
+    // whole operator loads)
+    std::vector<int4> ptiles;
+    std::vector<int32_t> ptgt, psrc;
+    if (pl.nleaf < 8192 && !mb.empty() && 2 * as->m2l_trans < (int64_t)mb.size() * kNumV) {
+        as->m2l_sparse = true;
+        for (int l = pl.lmin; l <= L; ++l) {
+            std::vector<std::vector<std::pair<int32_t, int32_t>>> bucket(kNumOff);
+            for (int32_t b : mb) {
+                if (b < pl.lev[l].begin || b >= pl.lev[l].end) continue;
+                uint32_t ix, iy;
+                decode(pl.hcode[b], ix, iy);
+                const int cls = (int)((ix & 1) | ((iy & 1) << 1));
+                for (int k = 0; k < kNumV; ++k) {
+                    const int32_t src = vl_host[(size_t)b * kNumV + k];
+                    if (src >= 0) bucket[pl.h_soid[cls * kNumV + k]].push_back({b, src});
+                }
+            }
+            for (int oid = 0; oid < kNumOff; ++oid) {
+                const auto &v = bucket[oid];
+                for (size_t s0 = 0; s0 < v.size(); s0 += kTile) {
+                    const int cnt = (int)std::min<size_t>(kTile, v.size() - s0);
+                    ptiles.push_back(make_int4(l, oid, (int)ptgt.size(), cnt));
+                    for (int k = 0; k < cnt; ++k) {
+                        ptgt.push_back(v[s0 + k].first);
+                        psrc.push_back(v[s0 + k].second);
+                    }
+                }
+            }
+        }
+    }
     as->tile_begin.assign(L + 1, 0);
     as->tile_count.assign(L + 1, 0);
     for (size_t t = 0; t < tiles.size(); ++t) {
@@ -619,6 +657,15 @@ ActiveSet &get_active(Context &ctx, FmmPlan &pl, int mask) {
     up(as->m2l_boxes, mb);
     up(as->m2l_tiles, tiles);
     up(as->m2l_tiles_w, wtiles);
+    if (as->m2l_sparse) {
+        std::vector<int32_t> piota(ptgt.size());
+        for (size_t k = 0; k < piota.size(); ++k) piota[k] = (int32_t)k;
+        up(as->m2l_ptiles, ptiles);
+        up(as->m2l_ptgt, ptgt);
+        up(as->m2l_psrc, psrc);
+        up(as->m2l_piota, piota);
+        as->n_ptiles = (int)ptiles.size();
+    }
     up(as->l2l_boxes, l2lb);
     up(as->leaves, leaves);
     up(as->leaf_items, items);
