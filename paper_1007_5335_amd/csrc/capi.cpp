@@ -125,6 +125,15 @@ void evaluate_sums(Context &ctx, PlanSlot slot, const SumProblem &pb, const doub
         fmm_evaluate(ctx, slot, pb, q, dn, out, prec);
         return;
     }
+    if (pb.bie) {   // direct backend: the fused steps as separate kernels
+        double *dnb = ctx.dn.ensure(2 * pb.n[1]);
+        launch_dipole_vectors(ctx, pb.n[1], pb.bie->w, pb.bie->sigma, pb.bie->normal, 1.0, dnb);
+        SumProblem plain = pb;
+        plain.bie = nullptr;
+        evaluate_sums(ctx, slot, plain, q, dnb, out, prec);
+        if (out[1]) launch_bie_finish(ctx, pb.n[1], pb.bie->w, pb.bie->kappa, pb.bie->sigma, out[1], out[1]);
+        return;
+    }
     StageTimer st(ctx, YK_STAGE_DIRECT);
     for (int s = 0; s < 3; ++s) {
         if (!out[s] || pb.n[s] == 0) continue;
@@ -147,16 +156,23 @@ struct BieOperator {
     BoundaryData &bd;
     double alpha;
     SumPrec prec;
+    // (dn, dl: workspaces of the unfused form, unused now that the dipole
+    // vectors and the final combination are formed inside the sum)
     void apply_eager(const double *x, double *y, double *dn, double *dl) const {
-        const int64_t n = bd.n;
-        launch_dipole_vectors(ctx, n, bd.w.p, x, bd.normal, 1.0, dn);
+        (void)dn;
+        (void)dl;
         SumProblem pb;
-        pb.n[1] = n;
+        pb.n[1] = bd.n;
         pb.xy[1] = bd.xy;
         pb.alpha = alpha;
-        double *const outs[3] = {nullptr, dl, nullptr};
-        evaluate_sums(ctx, SLOT_BND, pb, nullptr, dn, outs, prec);
-        launch_bie_finish(ctx, n, bd.w.p, bd.curvature, x, dl, y);
+        BieFuse f;
+        f.w = bd.w.p;
+        f.sigma = x;
+        f.normal = bd.normal;
+        f.kappa = bd.curvature;
+        pb.bie = &f;
+        double *const outs[3] = {nullptr, y, nullptr};
+        evaluate_sums(ctx, SLOT_BND, pb, nullptr, nullptr, outs, prec);
     }
     // With debug_flags bit 2 the operator, applied many times per solve with
     // the same tree, is captured once (after one eager application) into a

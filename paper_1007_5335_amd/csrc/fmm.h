@@ -150,8 +150,9 @@ ActiveSet &get_active(Context &ctx, FmmPlan &pl, int mask);
 int choose_order(double tol);
 
 // fmm_kernels.hip
+// bie (optional): the double-layer operator fused in (dn is then unused)
 void fmm_run(Context &ctx, FmmPlan &pl, const double *q, const double *dn, double *const out[3],
-             SumPrec prec);
+             SumPrec prec, const BieFuse *bie = nullptr);
 
 // The tree of a slot for this problem (built, or rebuilt when stale).
 FmmPlan &get_plan(Context &ctx, PlanSlot slot, const SumProblem &pb);

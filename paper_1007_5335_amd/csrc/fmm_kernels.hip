@@ -44,6 +44,18 @@ __global__ void k_gather_dn(int64_t off, int64_t n, const int32_t *__restrict__ 
     dns[2 * k + 1] = dn[2 * i + 1];
 }
 
+// the same with the dipole vectors formed on the way: dn_i = w_i sigma_i n_i
+__global__ void k_gather_dn_form(int64_t off, int64_t n, const int32_t *__restrict__ perm,
+                                 const double *__restrict__ w, const double *__restrict__ sigma,
+                                 const double *__restrict__ normal, double *__restrict__ dns) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    const int32_t i = perm[off + k];
+    const double s = 1.0 * w[i] * sigma[i];
+    dns[2 * k] = s * normal[2 * i];
+    dns[2 * k + 1] = s * normal[2 * i + 1];
+}
+
 __global__ void k_scatter_out(int64_t off, int64_t n, const int32_t *__restrict__ perm,
                               const double *__restrict__ outs, double *__restrict__ out) {
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -472,12 +484,17 @@ __global__ __launch_bounds__(256) void k_p2m_rows(
 
 // one block of four wavefronts per leaf, lanes over coefficients: wavefront w
 // sums the leaf's points w, w + 4, ... (two chains per lane) and the four
-// partial rows are added through LDS
+// partial rows are added through LDS; the blocks also clear zero[0..nzero)
 __global__ __launch_bounds__(256) void k_p2m_apply(
     int64_t leaf_base, int64_t nleaf, const int32_t *__restrict__ lrange, int64_t off1, int has_q,
     int has_d, const double *__restrict__ qs, const double *__restrict__ dns,
-    const double *__restrict__ rq, const double *__restrict__ rd, int P, int Pp, double *__restrict__ M) {
+    const double *__restrict__ rq, const double *__restrict__ rd, int P, int Pp, double *__restrict__ M,
+    double *__restrict__ zero, int64_t nzero) {
     __shared__ double part[4][64];
+    // zero[0..nzero) = 0 on the side (the local expansions, cleared here
+    // rather than by a launch of their own)
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < nzero; e += (int64_t)gridDim.x * 256)
+        zero[e] = 0.0;
     const int64_t li = blockIdx.x;
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int64_t b = leaf_base + li;
@@ -1458,7 +1475,8 @@ __global__ __launch_bounds__(256) void k_l2p(
     double inv_alpha, double invR, const double *__restrict__ invFY, const double *__restrict__ cnn,
     const double *__restrict__ sc, int nser, int p, int Pp, const double *__restrict__ outs,
     const int32_t *__restrict__ perm, double *__restrict__ out0, double *__restrict__ out1,
-    double *__restrict__ out2) {
+    double *__restrict__ out2, const double *__restrict__ bw, const double *__restrict__ bk,
+    const double *__restrict__ bx) {
     extern __shared__ double dyn[];
     double *t_cnn = dyn;               // [p+1]
     double *t_ify = t_cnn + p + 1;     // [p+1]
@@ -1496,7 +1514,11 @@ __global__ __launch_bounds__(256) void k_l2p(
     // near field + far field, written straight to the caller's array of the set
     const double v = outs[t] + (Lb[0] * F0 * t_ify[0] + 2.0 * (sr * zx - si * zy)) * kInv2Pi;
     double *o = set == 0 ? out0 : set == 1 ? out1 : out2;
-    o[perm[t]] = v;
+    const int32_t i = perm[t];
+    if (set == 1 && bx)   // double-layer operator: x - 2 (DL + diagonal limit)
+        o[i] = bx[i] - 2.0 * (v + bw[i] * (-0.5 * bk[i]) * bx[i] * kInv2Pi);
+    else
+        o[i] = v;
 }
 
 LeafKernel pick_leaf_kernel(int nt, bool small_only, bool f32) {
@@ -1514,13 +1536,14 @@ LeafKernel pick_leaf_kernel(int nt, bool small_only, bool f32) {
 }  // namespace
 
 void fmm_run(Context &ctx, FmmPlan &pl, const double *q, const double *dn, double *const out[3],
-             SumPrec prec) {
+             SumPrec prec, const BieFuse *bie) {
     int mask = 0;
     for (int s = 0; s < 3; ++s)
         if (out[s] && pl.toff[s + 1] > pl.toff[s]) mask |= 1 << s;
     if (!mask) return;
     const int64_t n0 = pl.toff[1] - pl.toff[0], n1 = pl.toff[2] - pl.toff[1];
-    const int has_q = (q && n0 > 0) ? 1 : 0, has_d = (dn && n1 > 0) ? 1 : 0;
+    if (bie && !bie->sigma) bie = nullptr;
+    const int has_q = (q && n0 > 0) ? 1 : 0, has_d = ((dn || bie) && n1 > 0) ? 1 : 0;
     const int L = pl.L, p = pl.p, P = pl.P, Pp = pl.Pp;
     const double inv_alpha = 1.0 / pl.alpha;
     double *qs = pl.qs.ensure(n0 > 0 ? n0 : 1);
@@ -1535,7 +1558,11 @@ void fmm_run(Context &ctx, FmmPlan &pl, const double *q, const double *dn, doubl
         hipLaunchKernelGGL(k_gather_q, dim3(nblk(n0, 256)), dim3(256), 0, ctx.stream, n0, pl.perm.p, q, qs);
         check_launch(ctx, "k_gather_q");
     }
-    if (has_d) {
+    if (has_d && bie) {
+        hipLaunchKernelGGL(k_gather_dn_form, dim3(nblk(n1, 256)), dim3(256), 0, ctx.stream, pl.toff[1], n1,
+                           pl.perm.p, bie->w, bie->sigma, bie->normal, dns);
+        check_launch(ctx, "k_gather_dn_form");
+    } else if (has_d) {
         hipLaunchKernelGGL(k_gather_dn, dim3(nblk(n1, 256)), dim3(256), 0, ctx.stream, pl.toff[1], n1,
                            pl.perm.p, dn, dns);
         check_launch(ctx, "k_gather_dn");
@@ -1620,6 +1647,7 @@ void fmm_run(Context &ctx, FmmPlan &pl, const double *q, const double *dn, doubl
         if (overlap) YK_HIP(hipEventRecord(ctx.ev_join, ctx.side));
     };
     const size_t lvl = (size_t)(p + 2);
+    bool lc_clear = false;   // Lc already cleared (by the cached P2M kernel)
     if (far) {
         // upward pass
         {
@@ -1647,8 +1675,9 @@ void fmm_run(Context &ctx, FmmPlan &pl, const double *q, const double *dn, doubl
         if (p2m_cache) {
             hipLaunchKernelGGL(k_p2m_apply, dim3((unsigned)pl.nleaf), dim3(256), 0, ctx.stream,
                                leaf_base, pl.nleaf, pl.lrange.p, pl.toff[1], has_q, has_d, qs, dns,
-                               pl.p2m_rq.p, pl.p2m_rd.p, P, Pp, pl.M.p);
+                               pl.p2m_rq.p, pl.p2m_rd.p, P, Pp, pl.M.p, pl.Lc.p, (int64_t)pl.nbox * Pp);
             check_launch(ctx, "k_p2m_apply");
+            lc_clear = true;
         } else {
         const size_t tabs = (2 * (size_t)pl.nser + 4 * (size_t)(p + 2)) * sizeof(double);
         // four lanes per leaf for many leaves; sixteen (more parallelism per
@@ -1705,7 +1734,7 @@ void fmm_run(Context &ctx, FmmPlan &pl, const double *q, const double *dn, doubl
         }
         // downward pass
         // a fill kernel rather than a memset node: this pass may be captured in a graph
-        launch_fill(ctx, (int64_t)pl.nbox * Pp, 0.0, pl.Lc.p);
+        if (!lc_clear) launch_fill(ctx, (int64_t)pl.nbox * Pp, 0.0, pl.Lc.p);
         if (Pp <= 64) {
             {
                 // M2L of every level at once (levels are independent given the multipoles)
@@ -1778,7 +1807,8 @@ void fmm_run(Context &ctx, FmmPlan &pl, const double *q, const double *dn, doubl
         hipLaunchKernelGGL(k_l2p, dim3(nblk(pl.N, 256)), dim3(256), lsh, ctx.stream, pl.N, pl.toff[1],
                            pl.toff[2], mask, pl.pleaf.p, leaf_base, pl.bcx.p, pl.bcy.p, pl.px.p, pl.py.p,
                            pl.Lc.p, inv_alpha, 1.0 / pl.lev[L].R, pl.invFY.p + L * lvl, pl.cnn.p,
-                           pl.serc.p, pl.nser, p, Pp, outs, pl.perm.p, out[0], out[1], out[2]);
+                           pl.serc.p, pl.nser, p, Pp, outs, pl.perm.p, out[0], out[1], out[2],
+                           bie ? bie->w : nullptr, bie ? bie->kappa : nullptr, bie ? bie->sigma : nullptr);
         check_launch(ctx, "k_l2p");
         return;   // L2P wrote the outputs
     }
@@ -1789,6 +1819,7 @@ void fmm_run(Context &ctx, FmmPlan &pl, const double *q, const double *dn, doubl
         hipLaunchKernelGGL(k_scatter_out, dim3(nblk(n, 256)), dim3(256), 0, ctx.stream, pl.toff[s], n,
                            pl.perm.p, outs, out[s]);
         check_launch(ctx, "k_scatter_out");
+        if (s == 1 && bie) launch_bie_finish(ctx, n, bie->w, bie->kappa, bie->sigma, out[1], out[1]);
     }
 }
 
