@@ -272,11 +272,15 @@ typedef struct {
     int64_t pairs_charge;     /* near-field (target, charge) pairs of the last evaluation */
     int64_t pairs_dipole;     /* near-field (target, dipole) pairs of the last evaluation */
     int64_t m2l_translations; /* non-empty V-list entries of the last evaluation */
-    int64_t m2l_slots;        /* V-list slots processed (27 per active box, incl. empty) */
+    int64_t m2l_slots;        /* V-list slots processed (27 per active box, incl. empty;
+                                 the translations themselves when m2l_sparse) */
     int64_t p2m_points, l2p_points;
     int32_t near_terms;       /* series length of the near-field K0/K1 evaluation */
     int32_t nser;             /* series length of the F_n starting values */
     double build_ms;          /* host wall time of the last tree build */
+    int32_t m2l_sparse;       /* 1: M2L of the last evaluation ran over the non-empty
+                                 translations bucketed by (level, offset), as chosen
+                                 for small trees with mostly empty V lists */
 } yk_plan_info;
 
 enum {

@@ -96,6 +96,28 @@ def test_fmm_double_layer_on_surface(yk, oracle_lib):
     assert rel_l2(host(out), ref) < 1e-10
 
 
+def test_sparse_m2l_boundary_tree(yk, oracle_lib):
+    """A nodes-only tree (mostly empty V lists) takes the sparse M2L path; its
+    sums on the surface still match the oracle's direct sums."""
+    import torch
+    c = W.small_fmm_case(n_vol=16, n_nodes=1024, alpha=0.02, seed=4)
+    b = c["bnd"]
+    sig = np.sin(3 * b.xy[:, 1]) + b.xy[:, 0] ** 2
+    ctx = _ctx(yk, leaf_size=16)
+    try:
+        bd = yk.Boundary.from_workload(b)
+        out = torch.empty(b.n, dtype=torch.float64, device="cuda")
+        yk.yk_double_layer_apply(ctx, bd, dev(sig), None, 0.02, out)
+        torch.cuda.synchronize()
+        info = yk.yk_plan_info_get(ctx, 1)   # (on-surface sums use the nodes-only tree)
+    finally:
+        yk.yk_destroy(ctx)
+    assert info.m2l_sparse == 1 and info.m2l_translations > 0, info.as_dict()
+    assert info.m2l_slots == info.m2l_translations
+    ref = oracle_lib.dl_on_surface(b.xy, b.normal, b.weights(), b.curvature, sig, 0.02)
+    assert rel_l2(host(out), ref) < 1e-10
+
+
 def test_fmm_gmres_vs_dense_lu(yk, oracle_lib):
     import torch
     c = W.small_fmm_case(n_vol=16, n_nodes=256, alpha=0.05, seed=2)
