@@ -69,7 +69,10 @@ typedef struct {
                                far field; larger trees always run it in turn);
                                bit2: capture the density operator in a HIP
                                graph and replay it (off by default: slower
-                               than eager launches here) */
+                               than eager launches here);
+                               bit3: recompute the charges' multipoles in the
+                               heat step's second volume pass instead of
+                               reusing those of the first (same charges) */
     int near_cache_mb;      /* device memory (MiB) a tree may spend on its cached
                                near-field interaction values; 0 = evaluate the
                                near-field kernels on every call */

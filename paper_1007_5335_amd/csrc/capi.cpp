@@ -582,7 +582,9 @@ yk_status yk_heat_step(yk_ctx ctx, const yk_boundary *bnd, int64_t n_vol, const 
         double *vb = c.ws_e.ensure(nb);
         {
             double *outs[3] = {nullptr, vb, nullptr};
-            evaluate_sums(c, SLOT_VOL, pb, q, nullptr, outs, vprec);
+            SumProblem pk = pb;
+            pk.keep_charge_m = (c.opt.debug_flags & 8) ? 0 : 1;   // the assembly below has the same charges
+            evaluate_sums(c, SLOT_VOL, pk, q, nullptr, outs, vprec);
         }
         double *b = c.ws_f.ensure(nb);
         launch_axpby(c, nb, -2.0 * a2, f_next, 2.0, vb, b);
@@ -678,7 +680,9 @@ yk_status yk_heat_step(yk_ctx ctx, const yk_boundary *bnd, int64_t n_vol, const 
         launch_dipole_vectors(c, nb, bd.w.p, sigma_io, bd.normal, 1.0, dn);
         {
             double *outs[3] = {u_next, nullptr, nullptr};
-            evaluate_sums(c, SLOT_VOL, pb, q, dn, outs, vprec);
+            SumProblem pr = pb;
+            pr.keep_charge_m = (c.opt.debug_flags & 8) ? 0 : 2;   // q = W B again, equal to the first pass's
+            evaluate_sums(c, SLOT_VOL, pr, q, dn, outs, vprec);
         }
         if (flags & 1) launch_self_cell(c, n_vol, vol_w, B, alpha, 1.0 / a2, u_next);
         else launch_axpby(c, n_vol, 1.0 / a2, u_next, 0.0, nullptr, u_next);

@@ -118,6 +118,10 @@ struct FmmPlan {
     DevBuf<int32_t> ulist_off, ulist;  // CSR over leaves (leaf-local indices)
     std::vector<int32_t> h_lrange;     // host copy
     DevBuf<int32_t> pleaf;             // [N] leaf (level-local index) of every sorted point
+    DevBuf<int32_t> dleaves;           // leaves (level-local) that hold dipole sources
+    int64_t n_dleaves = 0;
+    DevBuf<double> Mq_keep;            // leaf multipoles of a charges-only pass (keep_charge_m)
+    bool mq_kept = false;
     // cached P2M rows: per charge [Pp], per dipole [2][Pp] (built on first use)
     DevBuf<double> p2m_rq, p2m_rd, p2m_gs;
     bool p2m_rows_built = false;
@@ -152,7 +156,7 @@ int choose_order(double tol);
 // fmm_kernels.hip
 // bie (optional): the double-layer operator fused in (dn is then unused)
 void fmm_run(Context &ctx, FmmPlan &pl, const double *q, const double *dn, double *const out[3],
-             SumPrec prec, const BieFuse *bie = nullptr);
+             SumPrec prec, const BieFuse *bie = nullptr, int keep_charge_m = 0);
 
 // The tree of a slot for this problem (built, or rebuilt when stale).
 FmmPlan &get_plan(Context &ctx, PlanSlot slot, const SumProblem &pb);

@@ -55,7 +55,7 @@ FmmPlan &get_plan(Context &ctx, PlanSlot slot, const SumProblem &pb) {
 void fmm_evaluate(Context &ctx, PlanSlot slot, const SumProblem &pb, const double *q,
                   const double *dn, double *const out[3], SumPrec prec) {
     FmmPlan &pl = get_plan(ctx, slot, pb);
-    fmm_run(ctx, pl, q, dn, out, prec, pb.bie);
+    fmm_run(ctx, pl, q, dn, out, prec, pb.bie, pb.keep_charge_m);
 }
 
 double fmm_last_build_ms(Context &ctx) {

@@ -264,12 +264,13 @@ __global__ __launch_bounds__(64) void k_p2m(
             if (k < nk) M[b * Pp + gl + 16 * k] = gl + 16 * k < P ? macc[k] : 0.0;
 }
 
-// P2M with four lanes per leaf (a DPP quad) for a compile-time order PO: each lane
-// takes every fourth point of its leaf and accumulates all 2p+1 outputs in
-// registers; the quad's partial sums are combined with two DPP steps at the
-// end.  Per point: F_n downwards (G_n = F_n(y)/F_n(Y) in registers), then the
-// terms with the powers of conj(z) upwards.
-template <int PO>
+// P2M with LPL lanes per leaf (4: a DPP quad; 16: a row) for a compile-time
+// order PO: each lane takes every LPL-th point of its leaf and accumulates all
+// 2p+1 outputs in registers; the lanes' partial sums are combined at the end
+// (DPP steps for a quad, shuffles for a row).  Per point: F_n downwards
+// (G_n = F_n(y)/F_n(Y) in registers), then the terms with the powers of
+// conj(z) upwards.
+template <int PO, int LPL>
 __global__ __launch_bounds__(64) void k_p2m_quad(
     int64_t leaf_base, int64_t nleaf, const int32_t *__restrict__ lrange,
     const double *__restrict__ bcx, const double *__restrict__ bcy, const double *__restrict__ px,
@@ -277,7 +278,7 @@ __global__ __launch_bounds__(64) void k_p2m_quad(
     int64_t off1, int has_q, int has_d, double inv_alpha, double invR,
     const double *__restrict__ invFY, const double *__restrict__ da, const double *__restrict__ db,
     const double *__restrict__ cnn, const double *__restrict__ sc, int nser, int /*p*/, int Pp,
-    double *__restrict__ M) {
+    double *__restrict__ M, const int32_t *__restrict__ leaf_list, int accumulate) {
     constexpr int p = PO, P = 2 * PO + 1;
     extern __shared__ double smem[];
     double *t_sc = smem;                   // [2 nser] F_{p+1}, F_{p+2} series
@@ -285,10 +286,13 @@ __global__ __launch_bounds__(64) void k_p2m_quad(
     double *t_ify = t_cnn + (p + 2);       // [p+2]
     double *t_da = t_ify + (p + 2);        // [p+1]
     double *t_db = t_da + (p + 1);         // [p+1]
-    const int lane = threadIdx.x, q4 = lane & 3;
-    const int64_t li = (int64_t)blockIdx.x * 16 + (lane >> 2);
-    const bool leaf_ok = li < nleaf;
-    const int64_t b = leaf_base + (leaf_ok ? li : 0);
+    constexpr int LPB = 64 / LPL;           // leaves per block
+    const int lane = threadIdx.x, q4 = lane % LPL;
+    // leaf_list (optional): the leaves to serve, nleaf of them
+    const int64_t lidx = (int64_t)blockIdx.x * LPB + lane / LPL;
+    const bool leaf_ok = lidx < nleaf;
+    const int64_t li = leaf_ok ? (leaf_list ? (int64_t)leaf_list[lidx] : lidx) : 0;
+    const int64_t b = leaf_base + li;
     for (int k = lane; k < 2 * nser; k += 64) t_sc[k] = sc[k];
     for (int k = lane; k < p + 2; k += 64) {
         t_cnn[k] = cnn[k];
@@ -315,13 +319,13 @@ __global__ __launch_bounds__(64) void k_p2m_quad(
         // the next point's coordinates are loaded one iteration ahead
         int jn = clamp_j(s0 + q4);
         double nx = px[jn], ny = py[jn];
-        for (int j0 = s0;; j0 += 4) {
+        for (int j0 = s0;; j0 += LPL) {
             const int j = j0 + q4;
             const bool valid = j < e0;
             if (!__any(valid)) break;
             const int jc = jn;
             const double cxp = nx, cyp = ny;
-            jn = clamp_j(j + 4);
+            jn = clamp_j(j + LPL);
             nx = px[jn];
             ny = py[jn];
             const double wx = (cxp - cx) * inv_alpha, wy = (cyp - cy) * inv_alpha;
@@ -388,16 +392,159 @@ __global__ __launch_bounds__(64) void k_p2m_quad(
             }
         }
     }
-    // quad sums; lane q4 of the quad writes outputs q4, q4 + 4, ...
+    // sums over the leaf's lanes; lane q4 writes outputs q4, q4 + LPL, ...
 #pragma unroll
     for (int o = 0; o < P; ++o) {
         double v = acc[o];
+        if constexpr (LPL == 4) {
+            v += dpp_d<0xB1>(v);    // quad_perm [1,0,3,2]
+            v += dpp_d<0x4E>(v);    // quad_perm [2,3,0,1]
+        } else {
+#pragma unroll
+            for (int m = LPL / 2; m >= 1; m >>= 1) v += __shfl_xor(v, m, LPL);
+        }
+        if (leaf_ok && o % LPL == q4) M[b * Pp + o] = accumulate ? M[b * Pp + o] + v : v;
+    }
+    if (leaf_ok && !accumulate)
+        for (int o = P + q4; o < Pp; o += LPL) M[b * Pp + o] = 0.0;
+}
+
+// Charges-only P2M in two halves of the orders: blockIdx.y = 0 takes orders
+// 0..NS-1, blockIdx.y = 1 orders NS..p (NS = (p+1)/2), so each wavefront holds
+// half the accumulators and half the G_n and more wavefronts fit a SIMD.  As
+// in k_p2m_quad, four lanes per leaf over its points and DPP quad sums.  The
+// upper half starts its powers at conj(z)^NS by repeated squaring and stops
+// its downward F recurrence at NS.  Writes every entry of the leaves'
+// multipoles (padding included); dipoles are added afterwards.
+constexpr int kP2MStage = 384;   // charges staged in LDS per block and round
+
+template <int PO, int H>
+__device__ __forceinline__ void p2m_half_body(
+    int64_t leaf_base, int64_t nleaf, const int32_t *__restrict__ lrange,
+    const double *__restrict__ bcx, const double *__restrict__ bcy, const double *__restrict__ px,
+    const double *__restrict__ py, const double *__restrict__ qs, int has_q, double inv_alpha,
+    double invR, const double *t_ify, const double *t_cnn, const double *t_sc, int nser, int Pp,
+    double *__restrict__ M, double *sx, double *sy, double *sq, int skip_d) {
+    constexpr int p = PO, NS = (PO + 1) / 2;
+    constexpr int N0 = H == 0 ? 0 : NS, N1 = H == 0 ? NS - 1 : p;   // orders of this half
+    constexpr int O0 = H == 0 ? 0 : 2 * NS - 1;                      // its first output
+    constexpr int NA = H == 0 ? 2 * NS - 1 : 2 * (p - NS + 1);       // its outputs
+    constexpr int NG = N1 - N0 + 1;
+    const int lane = threadIdx.x, q4 = lane & 3;
+    const int64_t l0 = (int64_t)blockIdx.x * 16;
+    const int64_t li = l0 + (lane >> 2);
+    // (with skip_d, leaves that hold dipoles are left to the dipole pass)
+    const bool leaf_ok = li < nleaf && !(skip_d && lrange[li * 6 + 3] > lrange[li * 6 + 2]);
+    const int64_t b = leaf_base + (leaf_ok ? li : 0);
+    double acc[NA];
+#pragma unroll
+    for (int o = 0; o < NA; ++o) acc[o] = 0.0;
+    double G[NG];
+    const double cx = bcx[b], cy = bcy[b];
+    const int s0 = leaf_ok ? lrange[li * 6] : 0;
+    const int e0 = (leaf_ok && has_q) ? lrange[li * 6 + 1] : s0;
+    // the block's 16 leaves hold one contiguous run of charges, staged in LDS
+    // in rounds of kP2MStage (one memory round trip per round, not per point)
+    const int64_t llast = (l0 + 16 < nleaf ? l0 + 16 : nleaf) - 1;
+    const int pbeg = lrange[l0 * 6], pend = has_q ? lrange[llast * 6 + 1] : pbeg;
+    for (int cs = pbeg; cs < pend; cs += kP2MStage) {
+        const int cn = min(kP2MStage, pend - cs);
+        __syncthreads();
+        for (int k = lane; k < cn; k += 64) {
+            sx[k] = px[cs + k];
+            sy[k] = py[cs + k];
+            sq[k] = qs[cs + k];
+        }
+        __syncthreads();
+        // this lane's points j = s0 + q4 + 4k that fall in [cs, cs + cn)
+        int j = s0 + q4;
+        if (j < cs) j += (cs - j + 3) / 4 * 4;
+        for (;; j += 4) {
+            const bool valid = j < e0 && j < cs + cn;
+            if (!__any(valid)) break;
+            const int jl = valid ? j - cs : 0;
+            const double qv = valid ? sq[jl] : 0.0;
+            const double wx = (sx[jl] - cx) * inv_alpha, wy = (sy[jl] - cy) * inv_alpha;
+            const double y = 0.25 * (wx * wx + wy * wy);
+            const double zx = wx * invR, zy = -wy * invR;   // conj(w)/R
+            double F1, F2;
+            f_start(y, t_sc, nser, F1, F2);
+#pragma unroll
+            for (int n = p; n >= N0; --n) {
+                const double F0 = F1 + y * F2 * t_cnn[n];
+                if (n <= N1) G[n - N0] = F0 * t_ify[n];
+                F2 = F1;
+                F1 = F0;
+            }
+            // conj(z)^N0
+            double pr = 1.0, pi = 0.0;
+            {
+                double br = zx, bi = zy;
+#pragma unroll
+                for (int bit = 0; bit < 6; ++bit) {
+                    if ((N0 >> bit) & 1) {
+                        const double nr = pr * br - pi * bi;
+                        pi = pr * bi + pi * br;
+                        pr = nr;
+                    }
+                    if ((N0 >> (bit + 1)) != 0) {
+                        const double nr = br * br - bi * bi;
+                        bi = 2.0 * br * bi;
+                        br = nr;
+                    }
+                }
+            }
+#pragma unroll
+            for (int n = N0; n <= N1; ++n) {
+                const double g = qv * G[n - N0];
+                if (n == 0) {
+                    acc[0] += g;
+                } else {
+                    acc[2 * n - 1 - O0] = __builtin_fma(g, pr, acc[2 * n - 1 - O0]);
+                    acc[2 * n - O0] = __builtin_fma(g, pi, acc[2 * n - O0]);
+                }
+                const double nr = pr * zx - pi * zy;
+                pi = pr * zy + pi * zx;
+                pr = nr;
+            }
+        }
+    }
+#pragma unroll
+    for (int o = 0; o < NA; ++o) {
+        double v = acc[o];
         v += dpp_d<0xB1>(v);    // quad_perm [1,0,3,2]
         v += dpp_d<0x4E>(v);    // quad_perm [2,3,0,1]
-        if (leaf_ok && (o & 3) == q4) M[b * Pp + o] = v;
+        if (leaf_ok && (o & 3) == q4) M[b * Pp + O0 + o] = v;
     }
-    if (leaf_ok)
-        for (int o = P + q4; o < Pp; o += 4) M[b * Pp + o] = 0.0;
+    if (H == 1 && leaf_ok)
+        for (int o = 2 * p + 1 + q4; o < Pp; o += 4) M[b * Pp + o] = 0.0;
+}
+
+template <int PO>
+__global__ __launch_bounds__(64) void k_p2m_half(
+    int64_t leaf_base, int64_t nleaf, const int32_t *__restrict__ lrange,
+    const double *__restrict__ bcx, const double *__restrict__ bcy, const double *__restrict__ px,
+    const double *__restrict__ py, const double *__restrict__ qs, int has_q, double inv_alpha,
+    double invR, const double *__restrict__ invFY, const double *__restrict__ cnn,
+    const double *__restrict__ sc, int nser, int Pp, double *__restrict__ M, int skip_d) {
+    constexpr int p = PO;
+    extern __shared__ double smem[];
+    double *t_sc = smem;                   // [2 nser] F_{p+1}, F_{p+2} series
+    double *t_cnn = t_sc + 2 * nser;       // [p+2]
+    double *t_ify = t_cnn + (p + 2);       // [p+2]
+    for (int k = threadIdx.x; k < 2 * nser; k += 64) t_sc[k] = sc[k];
+    for (int k = threadIdx.x; k < p + 2; k += 64) {
+        t_cnn[k] = cnn[k];
+        t_ify[k] = invFY[k];
+    }
+    __syncthreads();
+    __shared__ double sx[kP2MStage], sy[kP2MStage], sq[kP2MStage];
+    if (blockIdx.y == 0)
+        p2m_half_body<PO, 0>(leaf_base, nleaf, lrange, bcx, bcy, px, py, qs, has_q, inv_alpha, invR, t_ify,
+                             t_cnn, t_sc, nser, Pp, M, sx, sy, sq, skip_d);
+    else
+        p2m_half_body<PO, 1>(leaf_base, nleaf, lrange, bcx, bcy, px, py, qs, has_q, inv_alpha, invR, t_ify,
+                             t_cnn, t_sc, nser, Pp, M, sx, sy, sq, skip_d);
 }
 
 // Cached P2M: the map from a point's strength to its leaf's multipole depends
@@ -1536,13 +1683,14 @@ LeafKernel pick_leaf_kernel(int nt, bool small_only, bool f32) {
 }  // namespace
 
 void fmm_run(Context &ctx, FmmPlan &pl, const double *q, const double *dn, double *const out[3],
-             SumPrec prec, const BieFuse *bie) {
+             SumPrec prec, const BieFuse *bie, int keep_charge_m) {
     int mask = 0;
     for (int s = 0; s < 3; ++s)
         if (out[s] && pl.toff[s + 1] > pl.toff[s]) mask |= 1 << s;
     if (!mask) return;
     const int64_t n0 = pl.toff[1] - pl.toff[0], n1 = pl.toff[2] - pl.toff[1];
     if (bie && !bie->sigma) bie = nullptr;
+    if (keep_charge_m == 1) pl.mq_kept = false;   // (set again once this pass has kept them)
     const int has_q = (q && n0 > 0) ? 1 : 0, has_d = ((dn || bie) && n1 > 0) ? 1 : 0;
     const int L = pl.L, p = pl.p, P = pl.P, Pp = pl.Pp;
     const double inv_alpha = 1.0 / pl.alpha;
@@ -1683,15 +1831,52 @@ void fmm_run(Context &ctx, FmmPlan &pl, const double *q, const double *dn, doubl
         // four lanes per leaf for many leaves; sixteen (more parallelism per
         // leaf, shorter chains) when the leaves are too few to fill the GPU
         auto quad = pl.nleaf < 8192 ? nullptr
-                  : p == 8 ? k_p2m_quad<8> : p == 12 ? k_p2m_quad<12> : p == 16 ? k_p2m_quad<16>
-                  : p == 20 ? k_p2m_quad<20> : p == 24 ? k_p2m_quad<24> : p == 28 ? k_p2m_quad<28>
-                  : p == 31 ? k_p2m_quad<31> : nullptr;
-        if (quad) {
+                  : p == 8 ? k_p2m_quad<8, 4> : p == 12 ? k_p2m_quad<12, 4> : p == 16 ? k_p2m_quad<16, 4>
+                  : p == 20 ? k_p2m_quad<20, 4> : p == 24 ? k_p2m_quad<24, 4> : p == 28 ? k_p2m_quad<28, 4>
+                  : p == 31 ? k_p2m_quad<31, 4> : nullptr;
+        auto row = p == 8 ? k_p2m_quad<8, 16> : p == 12 ? k_p2m_quad<12, 16> : p == 16 ? k_p2m_quad<16, 16>
+                 : p == 20 ? k_p2m_quad<20, 16> : p == 24 ? k_p2m_quad<24, 16> : p == 28 ? k_p2m_quad<28, 16>
+                 : p == 31 ? k_p2m_quad<31, 16> : nullptr;
+        auto half = p == 8 ? k_p2m_half<8> : p == 12 ? k_p2m_half<12> : p == 16 ? k_p2m_half<16>
+                  : p == 20 ? k_p2m_half<20> : p == 24 ? k_p2m_half<24> : p == 28 ? k_p2m_half<28>
+                  : p == 31 ? k_p2m_half<31> : nullptr;
+        const size_t leaf_m_bytes = (size_t)pl.nleaf * Pp * sizeof(double);
+        // the leaves that hold dipoles (few, but their points are dense along
+        // the curves): sixteen lanes per leaf; charges too unless add_only
+        auto dipole_leaves = [&](int with_q, int add_only) {
+            hipLaunchKernelGGL(row, dim3((unsigned)((pl.n_dleaves + 3) / 4)), dim3(64), tabs, ctx.stream,
+                               leaf_base, pl.n_dleaves, pl.lrange.p, pl.bcx.p, pl.bcy.p, pl.px.p, pl.py.p, qs,
+                               dns, pl.toff[1], with_q, 1, inv_alpha, 1.0 / pl.lev[L].R, pl.invFY.p + L * lvl,
+                               pl.dipa.p + L * lvl, pl.dipb.p + L * lvl, pl.cnn.p, pl.serc.p, pl.nser, p, Pp,
+                               pl.M.p, pl.dleaves.p, add_only);
+        };
+        if (quad && half && keep_charge_m == 2 && pl.mq_kept && has_q) {
+            // the charges' leaf multipoles of the keeping pass, then the dipoles added
+            YK_HIP(hipMemcpyAsync(pl.M.p + leaf_base * Pp, pl.Mq_keep.p, leaf_m_bytes, hipMemcpyDeviceToDevice,
+                                  ctx.stream));
+            if (has_d && pl.n_dleaves > 0) dipole_leaves(0, 1);
+        } else if (quad && half) {
+            // charges in two halves of the orders on the leaves without
+            // dipoles (all leaves when there are none), then the leaves with
+            // dipoles, charges and dipoles together
+            const int split_d = has_d && pl.n_dleaves > 0;
+            const size_t tabh = (2 * (size_t)pl.nser + 2 * (size_t)(p + 2)) * sizeof(double);
+            hipLaunchKernelGGL(half, dim3((unsigned)((pl.nleaf + 15) / 16), 2), dim3(64), tabh, ctx.stream,
+                               leaf_base, pl.nleaf, pl.lrange.p, pl.bcx.p, pl.bcy.p, pl.px.p, pl.py.p, qs,
+                               has_q, inv_alpha, 1.0 / pl.lev[L].R, pl.invFY.p + L * lvl, pl.cnn.p, pl.serc.p,
+                               pl.nser, Pp, pl.M.p, split_d);
+            if (keep_charge_m == 1 && has_q && !has_d) {
+                YK_HIP(hipMemcpyAsync(pl.Mq_keep.ensure((size_t)pl.nleaf * Pp), pl.M.p + leaf_base * Pp,
+                                      leaf_m_bytes, hipMemcpyDeviceToDevice, ctx.stream));
+                pl.mq_kept = true;
+            }
+            if (split_d) dipole_leaves(has_q, 0);
+        } else if (quad) {
             hipLaunchKernelGGL(quad, dim3((unsigned)((pl.nleaf + 15) / 16)), dim3(64), tabs, ctx.stream,
                                leaf_base, pl.nleaf, pl.lrange.p, pl.bcx.p, pl.bcy.p, pl.px.p, pl.py.p, qs,
                                dns, pl.toff[1], has_q, has_d, inv_alpha, 1.0 / pl.lev[L].R,
                                pl.invFY.p + L * lvl, pl.dipa.p + L * lvl, pl.dipb.p + L * lvl, pl.cnn.p,
-                               pl.serc.p, pl.nser, p, Pp, pl.M.p);
+                               pl.serc.p, pl.nser, p, Pp, pl.M.p, (const int32_t *)nullptr, 0);
         } else {
             const size_t shp = ((size_t)(p + 2) * 64 + 4 * Pp) * sizeof(double) + tabs;
             hipLaunchKernelGGL(k_p2m<0>, dim3((unsigned)((pl.nleaf + 3) / 4)), dim3(64), shp, ctx.stream,

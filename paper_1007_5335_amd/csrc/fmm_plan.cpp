@@ -358,6 +358,13 @@ void build_lists_and_tables(Context &ctx, FmmPlan &pl, const std::vector<uint32_
     up(pl.vlist, vl);
     up(pl.lrange, pl.h_lrange);
     {
+        std::vector<int32_t> dl;
+        for (int64_t li = 0; li < pl.nleaf; ++li)
+            if (pl.h_lrange[(size_t)li * 6 + 3] > pl.h_lrange[(size_t)li * 6 + 2]) dl.push_back((int32_t)li);
+        pl.n_dleaves = (int64_t)dl.size();
+        if (!dl.empty()) up(pl.dleaves, dl);
+    }
+    {
         std::vector<int32_t> hp((size_t)pl.N, 0);
         for (int64_t li = 0; li < pl.nleaf; ++li)
             for (int s = 0; s < 3; ++s)

@@ -24,6 +24,11 @@ struct SumProblem {
     const double *xy[3] = {nullptr, nullptr, nullptr};
     double alpha = 0.0;
     const BieFuse *bie = nullptr;   // (FMM backend only; see evaluate_sums)
+    // FMM backend: 1 = keep the leaf multipoles of this (charges-only) pass;
+    // 2 = the charges equal those of the keeping pass on the same tree: start
+    // from the kept multipoles and add only the dipoles' (both are hints: a
+    // pass that cannot use them computes everything)
+    int keep_charge_m = 0;
 };
 
 enum PlanSlot { SLOT_VOL = 0, SLOT_BND = 1, SLOT_MISC = 2 };

@@ -269,6 +269,38 @@ def test_fmm_full_size_sampled_vs_oracle(yk, oracle_lib, precision):
     assert err < (1e-9 if precision == "fp64" else 2e-5)
 
 
+@pytest.mark.parametrize("p,bound", [(8, 1e-3), (16, 1e-6), (31, 1e-10)])
+def test_fmm_full_size_orders_vs_oracle(yk, oracle_lib, p, bound):
+    """Other expansion orders on the full-size tree (65,536 leaves, where P2M
+    runs in two halves of the orders and adds the dipoles afterwards): sampled
+    outputs against the oracle, within a bound set by the order's truncation
+    (about 0.025 * 0.44^p relative)."""
+    import torch
+    c = W.config_c1()
+    b = c["bnd"]
+    ctx = _ctx(yk, p=p, leaf_size=64)
+    try:
+        bd = yk.Boundary.from_workload(b)
+        ov = torch.empty(c["vol"].shape[0], dtype=torch.float64, device="cuda")
+        ob = torch.empty(b.n, dtype=torch.float64, device="cuda")
+        print(f"full-size C1 p={p}", flush=True)
+        yk.yk_fmm_potential(ctx, dev(c["vol"]), dev(c["q"]), bd, dev(c["dip"]), c["alpha"], ov, ob)
+        torch.cuda.synchronize()
+        info = yk.yk_plan_info_get(ctx, 0)
+    finally:
+        yk.yk_destroy(ctx)
+    assert info.p == p and info.n_leaves >= 8192
+    iv = W.sample_targets(c["vol"].shape[0], 16, seed=21)
+    ib = W.sample_targets(b.n, 8, seed=22)
+    tgt = np.concatenate([c["vol"][iv], b.xy[ib]])
+    ref = (oracle_lib.volume_sum(c["vol"], c["q"], c["alpha"], tgt_xy=tgt)
+           + oracle_lib.dl_sum(b.xy, b.normal, c["dip"], c["alpha"], tgt))
+    got = np.concatenate([host(ov)[iv], host(ob)[ib]])
+    err = float(np.max(np.abs(got - ref)) / np.sqrt(np.mean(ref ** 2)))
+    print(f"  max err / rms {err:.2e}", flush=True)
+    assert err < bound
+
+
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 def test_near_cache_matches_on_the_fly(yk, oracle_lib, precision):
     """The cached near-field values give the same sums as evaluating the
@@ -302,6 +334,41 @@ def test_near_cache_matches_on_the_fly(yk, oracle_lib, precision):
     rv, rb = _oracle_fmm_potential(oracle_lib, c)
     ref = np.concatenate([rv, rb])
     assert rel_l2(outs[16384][0], ref) < (1e-10 if precision == "fp64" else 2e-5)
+
+
+def test_heat_step_reuses_charge_multipoles(yk):
+    """Two C3-size heat steps (1024^2 grid, 65,536 leaves): the second volume
+    pass of each step starts from the charges' multipoles kept by the first
+    and adds only the dipoles'; the result equals recomputing them (debug_flags
+    bit 3) to rounding."""
+    import torch
+    cfg = W.config_c3(m=1024, n_holes=10, n_nodes=2048, dt=1e-3, seed=3)
+    b = cfg["bnd"]
+    runs = {}
+    for flags in (0, 8):
+        opt = yk.yk_default_options()
+        opt.debug_flags = flags
+        ctx = yk.yk_create(opt)
+        try:
+            bd = yk.Boundary.from_workload(b)
+            vol, w, f = dev(cfg["vol"]), dev(cfg["vol_w"]), dev(cfg["f_bnd"])
+            region = torch.as_tensor(cfg["region"], dtype=torch.int32, device="cuda")
+            u = dev(cfg["u0"])
+            B, un = torch.empty_like(u), torch.empty_like(u)
+            sig = torch.zeros(b.n, dtype=torch.float64, device="cuda")
+            for step in range(2):
+                print(f"C3 step {step} flags={flags}", flush=True)
+                yk.yk_rhs_backward_euler(ctx, u, None, region, cfg["consts"], cfg["dt"], B)
+                yk.yk_heat_step(ctx, bd, vol, w, B, yk.HEAT_GRID_SELF_CELL, f, cfg["dt"], 1e-10, sig, un)
+                u, un = un, u
+            torch.cuda.synchronize()
+            info = yk.yk_plan_info_get(ctx, 0)
+        finally:
+            yk.yk_destroy(ctx)
+        assert info.n_leaves >= 8192
+        runs[flags] = (host(u).copy(), host(sig).copy())
+    assert rel_l2(runs[0][0], runs[8][0]) < 1e-12
+    assert rel_l2(runs[0][1], runs[8][1]) < 1e-10
 
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
