@@ -131,7 +131,8 @@ void evaluate_sums(Context &ctx, PlanSlot slot, const SumProblem &pb, const doub
         SumProblem plain = pb;
         plain.bie = nullptr;
         evaluate_sums(ctx, slot, plain, q, dnb, out, prec);
-        if (out[1]) launch_bie_finish(ctx, pb.n[1], pb.bie->w, pb.bie->kappa, pb.bie->sigma, out[1], out[1]);
+        if (out[1] && pb.bie->kappa)
+            launch_bie_finish(ctx, pb.n[1], pb.bie->w, pb.bie->kappa, pb.bie->sigma, out[1], out[1]);
         return;
     }
     StageTimer st(ctx, YK_STAGE_DIRECT);
@@ -676,13 +677,16 @@ yk_status yk_heat_step(yk_ctx ctx, const yk_boundary *bnd, int64_t n_vol, const 
         // u = (V[q] + DL[w sigma] + B C_self) / alpha^2 at the volume points
         auto t2 = std::chrono::steady_clock::now();
         launch_mul(c, n_vol, vol_w, B, q);   // q again (ws_d was used by the solver)
-        double *dn = c.dn.ensure(2 * nb);
-        launch_dipole_vectors(c, nb, bd.w.p, sigma_io, bd.normal, 1.0, dn);
         {
             double *outs[3] = {u_next, nullptr, nullptr};
             SumProblem pr = pb;
             pr.keep_charge_m = (c.opt.debug_flags & 8) ? 0 : 2;   // q = W B again, equal to the first pass's
-            evaluate_sums(c, SLOT_VOL, pr, q, dn, outs, vprec);
+            BieFuse f;   // dipole vectors w sigma n, formed in the gather
+            f.w = bd.w.p;
+            f.sigma = sigma_io;
+            f.normal = bd.normal;
+            pr.bie = &f;
+            evaluate_sums(c, SLOT_VOL, pr, q, nullptr, outs, vprec);
         }
         if (flags & 1) launch_self_cell(c, n_vol, vol_w, B, alpha, 1.0 / a2, u_next);
         else launch_axpby(c, n_vol, 1.0 / a2, u_next, 0.0, nullptr, u_next);
@@ -720,17 +724,20 @@ yk_status yk_fmm_potential(yk_ctx ctx, int64_t n_vol, const double *vol_xy, cons
         YK_REQUIRE(n_vol > 0 && vol_xy && q && d && out_vol && out_bnd, "invalid arguments");
         check_alpha(alpha);
         BoundaryData &bd = prepare_boundary(c, bnd);
-        double *dn = c.dn.ensure(2 * bd.n);
-        // dn_j = d_j n_j  (no quadrature weight: d is the full dipole strength)
-        launch_dipole_vectors(c, bd.n, nullptr, d, bd.normal, 1.0, dn);
         SumProblem pb;
         pb.n[0] = n_vol;
         pb.xy[0] = vol_xy;
         pb.n[1] = bd.n;
         pb.xy[1] = bd.xy;
         pb.alpha = alpha;
+        // dn_j = d_j n_j, formed as the sum gathers its sources (no quadrature
+        // weight: d is the full dipole strength)
+        BieFuse f;
+        f.sigma = d;
+        f.normal = bd.normal;
+        pb.bie = &f;
         double *outs[3] = {out_vol, out_bnd, nullptr};
-        evaluate_sums(c, SLOT_VOL, pb, q, dn, outs,
+        evaluate_sums(c, SLOT_VOL, pb, q, nullptr, outs,
                       c.opt.precision == YK_PREC_FP32 ? SUM_FP32 : SUM_FP64);
         return YK_OK;
     });

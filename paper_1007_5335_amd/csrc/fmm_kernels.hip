@@ -51,7 +51,7 @@ __global__ void k_gather_dn_form(int64_t off, int64_t n, const int32_t *__restri
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= n) return;
     const int32_t i = perm[off + k];
-    const double s = 1.0 * w[i] * sigma[i];
+    const double s = 1.0 * (w ? w[i] : 1.0) * sigma[i];
     dns[2 * k] = s * normal[2 * i];
     dns[2 * k + 1] = s * normal[2 * i + 1];
 }
@@ -415,7 +415,9 @@ __global__ __launch_bounds__(64) void k_p2m_quad(
 // in k_p2m_quad, four lanes per leaf over its points and DPP quad sums.  The
 // upper half starts its powers at conj(z)^NS by repeated squaring and stops
 // its downward F recurrence at NS.  Writes every entry of the leaves'
-// multipoles (padding included); dipoles are added afterwards.
+// multipoles (padding included); dipoles are added afterwards.  The blocks
+// also clear zero[0..nzero) on the side (the local expansions, so that no
+// launch of its own is needed).
 constexpr int kP2MStage = 384;   // charges staged in LDS per block and round
 
 template <int PO, int H>
@@ -526,9 +528,15 @@ __global__ __launch_bounds__(64) void k_p2m_half(
     const double *__restrict__ bcx, const double *__restrict__ bcy, const double *__restrict__ px,
     const double *__restrict__ py, const double *__restrict__ qs, int has_q, double inv_alpha,
     double invR, const double *__restrict__ invFY, const double *__restrict__ cnn,
-    const double *__restrict__ sc, int nser, int Pp, double *__restrict__ M, int skip_d) {
+    const double *__restrict__ sc, int nser, int Pp, double *__restrict__ M, int skip_d,
+    double *__restrict__ zero, int64_t nzero) {
     constexpr int p = PO;
     extern __shared__ double smem[];
+    {
+        const int64_t nthr = (int64_t)gridDim.x * gridDim.y * 64;
+        for (int64_t e = ((int64_t)blockIdx.y * gridDim.x + blockIdx.x) * 64 + threadIdx.x; e < nzero; e += nthr)
+            zero[e] = 0.0;
+    }
     double *t_sc = smem;                   // [2 nser] F_{p+1}, F_{p+2} series
     double *t_cnn = t_sc + 2 * nser;       // [p+2]
     double *t_ify = t_cnn + (p + 2);       // [p+2]
@@ -1843,8 +1851,8 @@ void fmm_run(Context &ctx, FmmPlan &pl, const double *q, const double *dn, doubl
         const size_t leaf_m_bytes = (size_t)pl.nleaf * Pp * sizeof(double);
         // the leaves that hold dipoles (few, but their points are dense along
         // the curves): sixteen lanes per leaf; charges too unless add_only
-        auto dipole_leaves = [&](int with_q, int add_only) {
-            hipLaunchKernelGGL(row, dim3((unsigned)((pl.n_dleaves + 3) / 4)), dim3(64), tabs, ctx.stream,
+        auto dipole_leaves = [&](int with_q, int add_only, hipStream_t st) {
+            hipLaunchKernelGGL(row, dim3((unsigned)((pl.n_dleaves + 3) / 4)), dim3(64), tabs, st,
                                leaf_base, pl.n_dleaves, pl.lrange.p, pl.bcx.p, pl.bcy.p, pl.px.p, pl.py.p, qs,
                                dns, pl.toff[1], with_q, 1, inv_alpha, 1.0 / pl.lev[L].R, pl.invFY.p + L * lvl,
                                pl.dipa.p + L * lvl, pl.dipb.p + L * lvl, pl.cnn.p, pl.serc.p, pl.nser, p, Pp,
@@ -1854,23 +1862,27 @@ void fmm_run(Context &ctx, FmmPlan &pl, const double *q, const double *dn, doubl
             // the charges' leaf multipoles of the keeping pass, then the dipoles added
             YK_HIP(hipMemcpyAsync(pl.M.p + leaf_base * Pp, pl.Mq_keep.p, leaf_m_bytes, hipMemcpyDeviceToDevice,
                                   ctx.stream));
-            if (has_d && pl.n_dleaves > 0) dipole_leaves(0, 1);
+            if (has_d && pl.n_dleaves > 0) dipole_leaves(0, 1, ctx.stream);
         } else if (quad && half) {
             // charges in two halves of the orders on the leaves without
             // dipoles (all leaves when there are none), then the leaves with
             // dipoles, charges and dipoles together
             const int split_d = has_d && pl.n_dleaves > 0;
+            // (the two kernels write disjoint leaves, but running the dipole
+            // leaves' one on a second stream was measured no faster: the
+            // other fills the GPU)
             const size_t tabh = (2 * (size_t)pl.nser + 2 * (size_t)(p + 2)) * sizeof(double);
             hipLaunchKernelGGL(half, dim3((unsigned)((pl.nleaf + 15) / 16), 2), dim3(64), tabh, ctx.stream,
                                leaf_base, pl.nleaf, pl.lrange.p, pl.bcx.p, pl.bcy.p, pl.px.p, pl.py.p, qs,
                                has_q, inv_alpha, 1.0 / pl.lev[L].R, pl.invFY.p + L * lvl, pl.cnn.p, pl.serc.p,
-                               pl.nser, Pp, pl.M.p, split_d);
+                               pl.nser, Pp, pl.M.p, split_d, pl.Lc.p, (int64_t)pl.nbox * Pp);
+            lc_clear = true;
             if (keep_charge_m == 1 && has_q && !has_d) {
                 YK_HIP(hipMemcpyAsync(pl.Mq_keep.ensure((size_t)pl.nleaf * Pp), pl.M.p + leaf_base * Pp,
                                       leaf_m_bytes, hipMemcpyDeviceToDevice, ctx.stream));
                 pl.mq_kept = true;
             }
-            if (split_d) dipole_leaves(has_q, 0);
+            if (split_d) dipole_leaves(has_q, 0, ctx.stream);
         } else if (quad) {
             hipLaunchKernelGGL(quad, dim3((unsigned)((pl.nleaf + 15) / 16)), dim3(64), tabs, ctx.stream,
                                leaf_base, pl.nleaf, pl.lrange.p, pl.bcx.p, pl.bcy.p, pl.px.p, pl.py.p, qs,
@@ -1993,7 +2005,8 @@ void fmm_run(Context &ctx, FmmPlan &pl, const double *q, const double *dn, doubl
                            pl.toff[2], mask, pl.pleaf.p, leaf_base, pl.bcx.p, pl.bcy.p, pl.px.p, pl.py.p,
                            pl.Lc.p, inv_alpha, 1.0 / pl.lev[L].R, pl.invFY.p + L * lvl, pl.cnn.p,
                            pl.serc.p, pl.nser, p, Pp, outs, pl.perm.p, out[0], out[1], out[2],
-                           bie ? bie->w : nullptr, bie ? bie->kappa : nullptr, bie ? bie->sigma : nullptr);
+                           bie ? bie->w : nullptr, bie ? bie->kappa : nullptr,
+                           (bie && bie->kappa) ? bie->sigma : nullptr);
         check_launch(ctx, "k_l2p");
         return;   // L2P wrote the outputs
     }
@@ -2004,7 +2017,7 @@ void fmm_run(Context &ctx, FmmPlan &pl, const double *q, const double *dn, doubl
         hipLaunchKernelGGL(k_scatter_out, dim3(nblk(n, 256)), dim3(256), 0, ctx.stream, pl.toff[s], n,
                            pl.perm.p, outs, out[s]);
         check_launch(ctx, "k_scatter_out");
-        if (s == 1 && bie) launch_bie_finish(ctx, n, bie->w, bie->kappa, bie->sigma, out[1], out[1]);
+        if (s == 1 && bie && bie->kappa) launch_bie_finish(ctx, n, bie->w, bie->kappa, bie->sigma, out[1], out[1]);
     }
 }
 

@@ -12,9 +12,10 @@ namespace yk {
 // out[s] (if non-null) receives, at every point of set s,
 //   sum_q q_j K0(r/alpha)/(2pi) + sum_d (x - y_j).dn_j K1(r/alpha)/(alpha r)/(2pi)
 // with pairs at distance zero skipped.
-// Double-layer operator fused into a sum over boundary nodes (set 1): the
-// dipole vectors dn_j = w_j sigma_j n_j are formed from these instead of being
-// passed, and set 1's output v becomes y = sigma - 2 (v + w (-kappa/2) sigma / (2 pi)).
+// Dipole vectors formed inside a sum over boundary nodes (set 1):
+// dn_j = w_j sigma_j n_j (w null: w_j = 1) instead of being passed; with kappa
+// also the double-layer operator: set 1's output v becomes
+// y = sigma - 2 (v + w (-kappa/2) sigma / (2 pi)).
 struct BieFuse {
     const double *w = nullptr, *sigma = nullptr, *normal = nullptr, *kappa = nullptr;
 };
