@@ -1,5 +1,6 @@
 // gmres.cpp -- restarted GMRES (Saad) with classical Gram-Schmidt applied
-// twice (CGS2) in FP64.  The Krylov basis, the operator and all vector work
+// twice (CGS2) in FP64 (the norm after the second projection taken as
+// |w|^2 - |h2|^2, which V's orthonormality makes exact up to rounding).  The Krylov basis, the operator and all vector work
 // stay on the device; only the k+2 projection scalars per iteration come back
 // to the host, where the Givens rotations and the small triangular solve run.
 #include <algorithm>
@@ -38,7 +39,7 @@ GmresResult gmres(Context &ctx, const Apply &A, int64_t n, const double *b, doub
     double *r = ctx.gm_r.ensure(n);
     double *dscal = ctx.scal.ensure(512);   // [0,128) h1, [128,256) h2, 256 norm^2, [300,...) y
     double *host = pinned_scalars(ctx);
-    double *P0 = arnoldi_partials(ctx, 0), *P1 = arnoldi_partials(ctx, 1), *P2 = arnoldi_partials(ctx, 2);
+    double *P0 = arnoldi_partials(ctx, 0), *P1 = arnoldi_partials(ctx, 1);
 
     const double bnorm2 = b_norm2 >= 0.0 ? b_norm2 : dot_host(ctx, n, b, b, dscal);
     if (!std::isfinite(bnorm2)) throw Error{YK_ERR_NONFINITE, "right-hand side is not finite"};
@@ -80,15 +81,16 @@ GmresResult gmres(Context &ctx, const Apply &A, int64_t n, const double *b, doub
             double *vk = V + (int64_t)k * n;
             A(vk, w);
             res.matvecs++;
-            // CGS2 in four passes over w: partials of V^T w; h1 = V^T w,
-            // w -= V h1, partials of V^T w; h2, w -= V h2, partials of |w|^2;
-            // |w|, the next basis vector w/|w| and the column to the host.
-            // The basis vector is formed before the host sees the column and
-            // is used only if the iteration goes on.
+            // CGS2 in three passes over w: partials of V^T w; h1 = V^T w,
+            // w -= V h1, partials of V^T w and |w|^2; h2, w - V h2 and its
+            // norm (|w|^2 - |h2|^2, V being orthonormal), the next basis
+            // vector and the column to the host.  The basis vector is formed
+            // before the host sees the column; it is used only if the
+            // iteration goes on.
             launch_arnoldi_pass(ctx, n, V, n, w, 0, nullptr, nullptr, k + 1, false, P0);
-            launch_arnoldi_pass(ctx, n, V, n, w, k + 1, P0, dscal, k + 1, false, P1);
-            launch_arnoldi_pass(ctx, n, V, n, w, k + 1, P1, dscal + 128, 0, true, P2);
-            launch_arnoldi_finish(ctx, n, w, P2, dscal + 256, V + (int64_t)(k + 1) * n, dscal, host);
+            launch_arnoldi_pass(ctx, n, V, n, w, k + 1, P0, dscal, k + 1, true, P1);
+            launch_arnoldi_finish(ctx, n, V, n, w, k + 1, P1, dscal + 128, dscal + 256, V + (int64_t)(k + 1) * n,
+                                  dscal, host);
             YK_HIP(hipStreamSynchronize(ctx.stream));
             std::copy(host, host + 2 * 128 + 1, hs.begin());
             double *col = &H[(size_t)k * (m + 1)];

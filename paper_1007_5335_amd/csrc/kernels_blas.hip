@@ -186,24 +186,43 @@ __global__ __launch_bounds__(kRedBlock) void k_arnoldi_pass(
         pout[(int64_t)r * nchunk + c] = (sh[r * 4] + sh[r * 4 + 1]) + (sh[r * 4 + 2] + sh[r * 4 + 3]);
 }
 
-// |w|^2 from the partials p (nchunk of them); y = w / |w| (zero when |w| = 0).
-// Block 0 stores |w|^2 to nrm2_out and hands the column to the host:
-// host_dst[0..256) = col_src[0..256), host_dst[256] = |w|^2.
+// Second subtraction and normalisation of a CGS2 step, from the partials p of
+// the previous pass (rows 0..nsub-1: h2 = V^T w; row nsub: |w|^2):
+//   y = (w - sum_v h2_v V_v) / |.|,  |.|^2 = |w|^2 - |h2|^2
+// (V orthonormal, so the norm of the result follows from the partials and no
+// further pass over the vector is needed; a negative value from rounding is
+// taken as zero, and y is then zero).  Block 0 stores h2 to h2_out and the
+// squared norm to nrm2_out, and hands the column to the host:
+// host_dst[0..128) = h1[0..128), host_dst[128 + v] = h2_v, host_dst[256] = |.|^2.
 __global__ __launch_bounds__(256) void k_arnoldi_finish(
-    int64_t n, const double *__restrict__ w, const double *__restrict__ p, int nchunk,
-    double *__restrict__ nrm2_out, double *__restrict__ y, const double *__restrict__ col_src,
-    double *__restrict__ host_dst) {
+    int64_t n, const double *__restrict__ V, int64_t ld, const double *__restrict__ w, int nsub,
+    const double *__restrict__ p, int nchunk, double *__restrict__ h2_out, double *__restrict__ nrm2_out,
+    double *__restrict__ y, const double *__restrict__ h1, double *__restrict__ host_dst) {
+    __shared__ double hs[kArnMaxRows + 1];
     __shared__ double nrm;
-    if (threadIdx.x < 64) sum_partials(p, 1, nchunk, &nrm);
+    sum_partials(p, nsub + 1, nchunk, hs);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double s2 = 0.0;
+        for (int v = 0; v < nsub; ++v) s2 += hs[v] * hs[v];
+        nrm = fmax(hs[nsub] - s2, 0.0);
+    }
     __syncthreads();
     const double nrm2 = nrm;
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) y[i] = nrm2 > 0.0 ? (1.0 / sqrt(nrm2)) * w[i] : 0.0;
+    if (i < n) {
+        double x = w[i];
+        for (int v = 0; v < nsub; ++v) x -= hs[v] * V[(int64_t)v * ld + i];
+        y[i] = nrm2 > 0.0 ? (1.0 / sqrt(nrm2)) * x : 0.0;
+    }
     if (blockIdx.x == 0) {
+        for (int t = threadIdx.x; t < nsub; t += blockDim.x) h2_out[t] = hs[t];
         if (threadIdx.x == 0) nrm2_out[0] = nrm2;
         if (host_dst) {
-            host_dst[threadIdx.x] = col_src[threadIdx.x];
-            if (threadIdx.x == 0) host_dst[256] = nrm2;
+            const int t = threadIdx.x;
+            if (t < 128) host_dst[t] = h1[t];
+            else if (t - 128 < nsub) host_dst[t] = hs[t - 128];
+            if (t == 0) host_dst[256] = nrm2;
         }
     }
 }
@@ -221,10 +240,12 @@ void launch_arnoldi_pass(Context &ctx, int64_t n, const double *V, int64_t ld, d
     check_launch(ctx, "k_arnoldi_pass");
 }
 
-void launch_arnoldi_finish(Context &ctx, int64_t n, const double *w, const double *p, double *nrm2_out,
-                           double *y, const double *col_src, double *host_dst) {
-    hipLaunchKernelGGL(k_arnoldi_finish, dim3(std::max(1u, nblk(n, 256))), dim3(256), 0, ctx.stream, n, w,
-                       p, arn_chunks(n), nrm2_out, y, col_src, host_dst);
+void launch_arnoldi_finish(Context &ctx, int64_t n, const double *V, int64_t ld, const double *w, int nsub,
+                           const double *p, double *h2_out, double *nrm2_out, double *y, const double *h1,
+                           double *host_dst) {
+    if (nsub > kArnMaxRows) throw Error{YK_ERR_INTERNAL, "Arnoldi finish: too many basis vectors"};
+    hipLaunchKernelGGL(k_arnoldi_finish, dim3(std::max(1u, nblk(n, 256))), dim3(256), 0, ctx.stream, n, V, ld,
+                       w, nsub, p, arn_chunks(n), h2_out, nrm2_out, y, h1, host_dst);
     check_launch(ctx, "k_arnoldi_finish");
 }
 

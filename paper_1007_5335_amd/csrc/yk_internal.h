@@ -210,10 +210,13 @@ void launch_multi_dot(Context &ctx, int64_t n, int nv, const double *V, int64_t 
 // then partials of V_r . w (r < nd) and, with self, of w . w into pout
 void launch_arnoldi_pass(Context &ctx, int64_t n, const double *V, int64_t ld, double *w, int nsub,
                          const double *psub, double *hsub_out, int nd, bool self, double *pout);
-// |w|^2 from the partials p (to nrm2_out), y = w / |w|; host_dst (pinned,
-// may be null) receives col_src[0..256) and then |w|^2
-void launch_arnoldi_finish(Context &ctx, int64_t n, const double *w, const double *p, double *nrm2_out,
-                           double *y, const double *col_src, double *host_dst);
+// CGS2's second subtraction and normalisation from the previous pass's
+// partials p (h2 = V^T w in rows 0..nsub-1, |w|^2 in row nsub): y = (w - V h2)
+// / sqrt(|w|^2 - |h2|^2); stores h2 and the squared norm; host_dst (pinned, may
+// be null) receives h1[0..128), h2 at 128.. and the squared norm at 256
+void launch_arnoldi_finish(Context &ctx, int64_t n, const double *V, int64_t ld, const double *w, int nsub,
+                           const double *p, double *h2_out, double *nrm2_out, double *y, const double *h1,
+                           double *host_dst);
 // partial buffer 0, 1 or 2 of the Arnoldi passes
 double *arnoldi_partials(Context &ctx, int which);
 void launch_multi_axpy(Context &ctx, int64_t n, int nv, const double *V, int64_t ld,
