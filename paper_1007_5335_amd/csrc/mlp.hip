@@ -36,6 +36,16 @@ inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
 typedef float f4v __attribute__((ext_vector_type(4)));
 
+// Workgroups are dispatched to the 8 XCDs in turn; map the b-th of n to a
+// tile so that each XCD serves one contiguous run of tiles (neighbouring
+// tiles share operand rows, which then stay in one XCD's L2).
+__device__ __forceinline__ int xcd_tile(int b, int n) {
+    constexpr int kXcd = 8;
+    const int x = b % kXcd, i = b / kXcd;
+    const int q = n / kXcd, r = n % kXcd;
+    return x * q + min(x, r) + i;
+}
+
 // ------------------------------------------------------------------ GEMM ---
 // C[z][m][n] = sum_{k in chunk z} A(m,k) B(k,n), A(m,k) = A[m*sam + k*sak],
 // B(k,n) = B[k*sbk + n*sbn].  64 x 64 tiles, 4 wavefronts each owning a
@@ -58,8 +68,13 @@ __global__ __launch_bounds__(256) void k_sgemm(int M, int N, int K, const float 
     __shared__ float As[KS][kLdsPad];
     __shared__ float Bs[KS][kLdsPad];
     const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
-    const int m0 = blockIdx.y * 64, n0 = blockIdx.x * 64;
-    const int kbeg = blockIdx.z * kchunk, kend = min(K, kbeg + kchunk);
+    // tile (tx, ty, tz) of this workgroup, XCD-aware: the column tiles of one
+    // row of tiles (which read the same rows of A) run on one XCD
+    const int gx = gridDim.x, gy = gridDim.y;
+    const int t = xcd_tile(blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z), gx * gy * gridDim.z);
+    const int tx = t % gx, ty = (t / gx) % gy, tz = t / (gx * gy);
+    const int m0 = ty * 64, n0 = tx * 64;
+    const int kbeg = tz * kchunk, kend = min(K, kbeg + kchunk);
     const int wm = (w >> 1) * 32, wn = (w & 1) * 32;
     f4v acc[2][2];
     for (int i = 0; i < 2; ++i)
@@ -110,7 +125,7 @@ __global__ __launch_bounds__(256) void k_sgemm(int M, int N, int K, const float 
         }
         __syncthreads();
     }
-    float *Cz = C + (int64_t)blockIdx.z * ldz;
+    float *Cz = C + (int64_t)tz * ldz;
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
