@@ -1,5 +1,6 @@
 // fmm_kernels.hip -- upward pass, M2L, downward pass and near field of the
 // modified-Helmholtz FMM (expansion conventions in fmm.h), FP64.
+#include <climits>
 #include <type_traits>
 
 #include "fmm.h"
@@ -445,10 +446,17 @@ __device__ __forceinline__ void p2m_half_body(
     const double cx = bcx[b], cy = bcy[b];
     const int s0 = leaf_ok ? lrange[li * 6] : 0;
     const int e0 = (leaf_ok && has_q) ? lrange[li * 6 + 1] : s0;
-    // the block's 16 leaves hold one contiguous run of charges, staged in LDS
-    // in rounds of kP2MStage (one memory round trip per round, not per point)
-    const int64_t llast = (l0 + 16 < nleaf ? l0 + 16 : nleaf) - 1;
-    const int pbeg = lrange[l0 * 6], pend = has_q ? lrange[llast * 6 + 1] : pbeg;
+    // the charges of the block's leaves (consecutive in Morton order, so one
+    // run, up to the charges of leaves left to the dipole pass) are staged in
+    // LDS in rounds of kP2MStage: one memory round trip per round, not per
+    // point.  The run's ends come from the leaves that hold charges (an empty
+    // range carries no position).
+    int pbeg = e0 > s0 ? s0 : INT_MAX, pend = e0 > s0 ? e0 : 0;
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) {
+        pbeg = min(pbeg, __shfl_xor(pbeg, m, 64));
+        pend = max(pend, __shfl_xor(pend, m, 64));
+    }
     for (int cs = pbeg; cs < pend; cs += kP2MStage) {
         const int cn = min(kP2MStage, pend - cs);
         __syncthreads();
@@ -1174,8 +1182,8 @@ __global__ void k_to_float(int64_t n, const double *__restrict__ a, float *__res
 }
 
 // ----------------------------------------------------------- leaf kernel ---
-// Near field in scaled coordinates: points are multiplied by 1/(2 alpha), so
-// the squared distance of two scaled points is t = r^2/(4 alpha^2) itself and
+// Near field in scaled coordinates: separations are multiplied by 1/(2 alpha),
+// so the squared scaled separation is t = r^2/(4 alpha^2) itself and
 //     K0(r/alpha)            = h(t) A(t) + B(t),           h = -(1/2) ln t,
 //     4 K1(r/alpha)/(r/alpha) = 1/t - 2 h(t) C(t) - D(t)
 // for t <= 1 (series in bessel_tables.h); larger t use the Chebyshev forms.
@@ -1330,8 +1338,11 @@ __global__ __launch_bounds__(64) void k_leaf(
         if (t < 0 && k < n) t = rs[s] + k;
         k -= n;
     }
-    const double x = px[t], y = py[t];
-    const double xs = x * inv2a, ys = y * inv2a;
+    // separations are formed from the unscaled coordinates and then scaled:
+    // the difference of two nearby coordinates is exact, whereas scaling
+    // first would round each coordinate, which costs digits in (x - y).n for
+    // the nearly tangential pairs of densely sampled, tightly curved curves
+    const double xs = px[t], ys = py[t];
     using NearT = Near<NT, kSmallOnly, kF32>;
     typename NearT::acc_t near_q = 0, near_d = 0;
     for (int set = 0; set < 2; ++set) {
@@ -1345,8 +1356,8 @@ __global__ __launch_bounds__(64) void k_leaf(
                 const int *cnt = set == 0 ? qn : dn_;
                 while (u < 8 && r >= cnt[u]) { r -= cnt[u]; ++u; }
                 const int j = (set == 0 ? qa[u] : da[u]) + r;
-                s_x[f] = px[j] * inv2a;
-                s_y[f] = py[j] * inv2a;
+                s_x[f] = px[j];
+                s_y[f] = py[j];
                 if (set == 0) {
                     s_a[f] = qs[j];
                 } else {
@@ -1361,7 +1372,7 @@ __global__ __launch_bounds__(64) void k_leaf(
                 const int nfull = cn - cn % g;
                 if (set == 0) {
                     auto pair = [&](int j) {
-                        const double dx = xs - s_x[j], dy = ys - s_y[j];
+                        const double dx = (xs - s_x[j]) * inv2a, dy = (ys - s_y[j]) * inv2a;
                         const double tt = __builtin_fma(dx, dx, dy * dy);
                         if (tt > 0.0) near_q += NearT::charge(s_a[j], tt, s_log);
                     };
@@ -1370,7 +1381,7 @@ __global__ __launch_bounds__(64) void k_leaf(
                     if (nfull + sub < cn) pair(nfull + sub);
                 } else {
                     auto pair = [&](int j) {
-                        const double dx = xs - s_x[j], dy = ys - s_y[j];
+                        const double dx = (xs - s_x[j]) * inv2a, dy = (ys - s_y[j]) * inv2a;
                         const double tt = __builtin_fma(dx, dx, dy * dy);
                         if (tt > 0.0) near_d += NearT::dipole(__builtin_fma(dx, s_a[j], dy * s_b[j]), tt, s_log);
                     };
@@ -1477,7 +1488,7 @@ __global__ __launch_bounds__(64) void k_near_build(
     if constexpr (!kF32)
         for (int i = lane; i < YK_LOG_TAB; i += 64) s_log[i] = make_double2(yk_log_tab[2 * i], yk_log_tab[2 * i + 1]);
     const ItemSetup it = item_setup(items[ib], lrange, uoff, ulist, q_on, d_on, mask, qa, qn, da, dn_);
-    const double xs = px[it.t] * inv2a, ys = py[it.t] * inv2a;
+    const double xs = px[it.t], ys = py[it.t];   // unscaled: see k_leaf
     for (int set = 0; set < 2; ++set) {
         const int ntot_s = set == 0 ? it.nq : it.nd;
         VT *Mb = set == 0 ? Mq + qoff[ib] : Md + 2 * doff[ib];
@@ -1486,13 +1497,13 @@ __global__ __launch_bounds__(64) void k_near_build(
             __syncthreads();
             for (int f = lane; f < cn; f += 64) {
                 const int j = flat_source(c0 + f, set == 0 ? qn : dn_, set == 0 ? qa : da);
-                s_x[f] = px[j] * inv2a;
-                s_y[f] = py[j] * inv2a;
+                s_x[f] = px[j];
+                s_y[f] = py[j];
             }
             __syncthreads();
             if (!it.valid) continue;
             for (int j = it.sub; j < cn; j += it.g) {
-                const double dx = xs - s_x[j], dy = ys - s_y[j];
+                const double dx = (xs - s_x[j]) * inv2a, dy = (ys - s_y[j]) * inv2a;
                 const double tt = __builtin_fma(dx, dx, dy * dy);
                 const int64_t e = (int64_t)(c0 + j) * it.c + it.ti;
                 if (set == 0) {

@@ -217,6 +217,36 @@ def test_mixed_precision_gmres_refines_to_fp64(yk, oracle_lib):
     assert rel_l2(host(sig), ref) < 1e-10
 
 
+@pytest.mark.parametrize("alpha", [0.01, 0.05, 0.2])
+def test_mixed_density_solve_full_boundary(yk, alpha):
+    """The mixed-precision density solve on the full-size boundary (outer
+    circle + 5 holes x 4096 nodes) for each alpha: FP32-operator corrections,
+    FP64 residuals, refined to 1e-10; the density equals the plain FP64
+    solve's within the tolerance's reach, and the mixed solve's final FP64
+    residual meets the tolerance."""
+    import torch
+    c = W.config_c1()
+    b = c["bnd"]
+    g = np.sin(40 * b.xy[:, 0]) * np.cos(30 * b.xy[:, 1]) + 1.0
+    out = {}
+    for prec in (yk.YK_PREC_FP64, yk.YK_PREC_MIXED):
+        ctx = _ctx(yk, fmm_tol=1e-10, precision=prec)
+        try:
+            bd = yk.Boundary.from_workload(b)
+            sig = torch.empty(b.n, dtype=torch.float64, device="cuda")
+            print(f"full boundary alpha={alpha} precision={prec}", flush=True)
+            st = yk.yk_gmres_density(ctx, bd, alpha, dev(g), None, 1e-10, 400, sig)
+            torch.cuda.synchronize()
+        finally:
+            yk.yk_destroy(ctx)
+        out[prec] = (host(sig).copy(), st)
+    (s64, st64), (smx, stmx) = out[yk.YK_PREC_FP64], out[yk.YK_PREC_MIXED]
+    print("  fp64", st64.as_dict(), "\n  mixed", stmx.as_dict(), flush=True)
+    assert st64.res_final <= 1e-10 and stmx.res_final <= 1e-10
+    assert stmx.outer_iters >= 1
+    assert rel_l2(smx, s64) < 1e-8
+
+
 def test_fmm_near_field_accuracy_tight(yk, oracle_lib):
     """Points packed so every near pair has t = r^2/(4 alpha^2) <= 1, and p = 31:
     the near field (own logarithm and series) and the far field agree with the
@@ -299,6 +329,69 @@ def test_fmm_full_size_orders_vs_oracle(yk, oracle_lib, p, bound):
     err = float(np.max(np.abs(got - ref)) / np.sqrt(np.mean(ref ** 2)))
     print(f"  max err / rms {err:.2e}", flush=True)
     assert err < bound
+
+
+def _c4_like_pass_vs_oracle(yk, oracle_lib, c, nv, nb, seed, orders=(0,)):
+    """One FMM pass per expansion order (0: chosen from fmm_tol = 1e-10);
+    per-target and l2 relative errors against the oracle on sampled targets."""
+    import torch
+    b, vol = c["bnd"], c["vol"]
+    n = vol.shape[0]
+    rng = np.random.default_rng(seed)
+    q = rng.standard_normal(n) * c["vol_w"] * np.sqrt(n)
+    dip = rng.standard_normal(b.n) * 1e-3
+    iv = W.sample_targets(n, nv, seed=seed + 1)
+    ib = W.sample_targets(b.n, nb, seed=seed + 2)
+    tgt = np.concatenate([vol[iv], b.xy[ib]])
+    ref = (oracle_lib.volume_sum(vol, q, c["alpha"], tgt_xy=tgt)
+           + oracle_lib.dl_sum(b.xy, b.normal, dip, c["alpha"], tgt))
+    res = []
+    for p in orders:
+        ctx = _ctx(yk, fmm_tol=1e-10, leaf_size=64, p=p)
+        try:
+            bd = yk.Boundary.from_workload(b)
+            ov = torch.empty(n, dtype=torch.float64, device="cuda")
+            ob = torch.empty(b.n, dtype=torch.float64, device="cuda")
+            yk.yk_fmm_potential(ctx, dev(vol), dev(q), bd, dev(dip), c["alpha"], ov, ob)
+            torch.cuda.synchronize()
+            info = yk.yk_plan_info_get(ctx, 0)
+        finally:
+            yk.yk_destroy(ctx)
+        got = np.concatenate([host(ov)[iv], host(ob)[ib]])
+        err = np.abs(got - ref) / np.abs(ref)
+        l2 = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+        print(f"  p={info.p} leaf level {info.leaf_level}, {info.n_leaves} leaves, lmin {info.lmin}; "
+              f"per-target relative errors {err}, l2 {l2:.2e}", flush=True)
+        res.append((info, err, l2))
+    return res
+
+
+def test_clustered_small_alpha_pass_vs_oracle(yk, oracle_lib):
+    """A reduced C4-shaped set (2^20 points from 8 Gaussians, 8 small holes of
+    4096 nodes in the gaps, alpha = 1e-3): many leaves hold no charges, which
+    the large-tree P2M must not mistake for the ends of a block's run of
+    charges; sampled outputs against the oracle's direct sums.  The order
+    chosen for 1e-10 (p = 24) leaves volume targets near 1e-12 and boundary
+    nodes on the small holes near 2e-9 (the far field of their dense dipoles
+    converges more slowly in p); p = 31 brings every target below 1e-10."""
+    c = W.config_c4(n_vol=1 << 20, n_holes=8, n_nodes=4096, seed=9)
+    print("clustered 2^20, alpha 1e-3", flush=True)
+    (i24, e24, l24), (i31, e31, l31) = _c4_like_pass_vs_oracle(yk, oracle_lib, c, 6, 6, 31, orders=(0, 31))
+    assert i24.p == 24 and i24.n_leaves >= 8192
+    assert l24 < 5e-9 and np.max(e24) < 1e-8, e24
+    assert np.max(e31) < 1e-10, e31
+
+
+def test_c4_full_size_pass_vs_oracle(yk, oracle_lib):
+    """The large adaptive set at full size (2^24 points from 8 Gaussians, 20
+    holes x 8192 nodes, alpha = 1e-3): one FMM pass at the order chosen for
+    1e-10, a few sampled outputs against the oracle's direct sums (bounds as
+    for the reduced set above)."""
+    c = W.config_c4()
+    print("C4 full size", flush=True)
+    ((info, err, l2),) = _c4_like_pass_vs_oracle(yk, oracle_lib, c, 2, 2, 41)
+    assert info.n_leaves > 1_000_000
+    assert l2 < 5e-9 and np.max(err) < 1e-8, err
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
