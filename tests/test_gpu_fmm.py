@@ -394,6 +394,55 @@ def test_c4_full_size_pass_vs_oracle(yk, oracle_lib):
     assert l2 < 5e-9 and np.max(err) < 1e-8, err
 
 
+def test_c4_heat_steps_mixed_learned(yk):
+    """Backward-Euler steps on the large adaptive set (2^24 scattered volume
+    points with weights 1/(N p), 20 holes x 8192 nodes, dt = alpha^2 = 1e-6,
+    u = c_k on hole k): plain FP64 with the previous-step guess against mixed
+    precision with the learned warm start (trained after five steps).  Every
+    step of both reaches the GMRES tolerance, the learned guess is taken, and
+    the solutions agree to the solves' reach."""
+    import time
+    import torch
+    c = W.config_c4()
+    b, vol = c["bnd"], c["vol"]
+    region = torch.as_tensor(b.region(vol), dtype=torch.int32, device="cuda")
+    f = dev(np.repeat(c["consts"], np.diff(b.offset)))
+    n_steps = 7
+    finals = {}
+    for name, prec, learned in (("fp64", yk.YK_PREC_FP64, False), ("mixed_learned", yk.YK_PREC_MIXED, True)):
+        ctx = yk.yk_create(fmm_tol=1e-10, precision=prec)
+        ws = None
+        try:
+            bd = yk.Boundary.from_workload(b)
+            if learned:
+                ws = yk.yk_ws_create(ctx, bd)
+                yk.yk_set_warm_start(ctx, ws)
+            vx, vw = dev(vol), dev(c["vol_w"])
+            u = torch.zeros(vol.shape[0], dtype=torch.float64, device="cuda")
+            B, un = torch.empty_like(u), torch.empty_like(u)
+            sig = torch.zeros(b.n, dtype=torch.float64, device="cuda")
+            for step in range(1, n_steps + 1):
+                if ws is not None and step == 6:
+                    yk.yk_ws_train(ws)
+                yk.yk_rhs_backward_euler(ctx, u, None, region, c["consts"], c["dt"], B)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                st = yk.yk_heat_step(ctx, bd, vx, vw, B, 0, f, c["dt"], 1e-10, sig, un)
+                torch.cuda.synchronize()
+                print(f"C4 {name} step {step}: {(time.perf_counter() - t0) * 1e3:.1f} ms, "
+                      f"{st.iters} iterations, res0 {st.res0:.2e}, guess {st.guess_used}", flush=True)
+                assert st.res_final <= 1e-10
+                if learned and step >= 6:
+                    assert st.guess_used == 2
+                u, un = un, u
+            finals[name] = host(u).copy()
+        finally:
+            if ws is not None:
+                yk.yk_ws_destroy(ws)
+            yk.yk_destroy(ctx)
+    assert rel_l2(finals["mixed_learned"], finals["fp64"]) < 1e-8
+
+
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 def test_near_cache_matches_on_the_fly(yk, oracle_lib, precision):
     """The cached near-field values give the same sums as evaluating the
