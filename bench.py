@@ -63,8 +63,11 @@ def rooflines(info, st, steps, fp32):
     """Per-kernel rooflines from the serialised per-stage event times.
 
     Near field (cached): algorithmic bytes = the interaction values read once
-    per pass, 8 bytes per charge pair and 16 per dipole pair in FP64 (half in
-    FP32); source strengths and outputs add under 3% and are not counted.
+    per pass, 8 bytes per stored charge value and 16 per dipole pair in FP64
+    (half in FP32), plus the 8-byte entries of the incoming slots the kernel
+    writes; with the symmetric layout a charge value stands for two pairs
+    (stored once per pair of neighbouring leaves).  Source strengths and
+    outputs add under 3% and are not counted.
     M2L: 2 P^2 flops per non-empty V-list translation (padding not credited),
     against the dense matrix-core peak of the arithmetic type."""
     out = {}
@@ -72,7 +75,7 @@ def rooflines(info, st, steps, fp32):
     if leaf_calls:
         t = leaf_ms / leaf_calls
         vb = 4 if fp32 else 8
-        nbytes = info.pairs_charge * vb + info.pairs_dipole * 2 * vb
+        nbytes = info.near_charge_values * vb + info.pairs_dipole * 2 * vb + info.near_incoming * 8
         ach = nbytes / (t * 1e-3) / 1e9
         out["near"] = {"kernel": "k_near_apply (cached near field, P2P)", "bound": "hbm", "achieved": ach,
                        "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": ach / PEAK_HBM_GBS,

@@ -72,7 +72,13 @@ typedef struct {
                                than eager launches here);
                                bit3: recompute the charges' multipoles in the
                                heat step's second volume pass instead of
-                               reusing those of the first (same charges) */
+                               reusing those of the first (same charges);
+                               bit4: store the cached charge-to-charge
+                               near-field values for both orders of every
+                               pair of leaves (by default each pair block of
+                               neighbouring leaves is stored once and applied
+                               both ways, when every leaf holds at most 64
+                               charges) */
     int near_cache_mb;      /* device memory (MiB) a tree may spend on its cached
                                near-field interaction values; 0 = evaluate the
                                near-field kernels on every call */
@@ -284,6 +290,13 @@ typedef struct {
     int32_t m2l_sparse;       /* 1: M2L of the last evaluation ran over the non-empty
                                  translations bucketed by (level, offset), as chosen
                                  for small trees with mostly empty V lists */
+    int32_t near_sym;         /* 1: the cached charge-to-charge values are stored once
+                                 per pair of neighbouring leaves (K0 is symmetric) */
+    int64_t near_charge_values; /* charge values the cached near field reads per
+                                   evaluation (pairs_charge unless near_sym; not
+                                   counting the zeros that pad rows to vectors) */
+    int64_t near_incoming;    /* entries written to (and read back from) the incoming
+                                 slots of the symmetric near field per evaluation */
 } yk_plan_info;
 
 enum {

@@ -884,6 +884,9 @@ yk_status yk_plan_info_get(yk_ctx ctx, int slot, yk_plan_info *info) {
             info->m2l_translations = far ? as.m2l_trans : 0;
             info->m2l_slots = far ? (as.m2l_sparse ? as.m2l_trans : as.n_m2l_boxes * kNumV) : 0;
             info->m2l_sparse = far && as.m2l_sparse ? 1 : 0;
+            info->near_sym = as.near_sym ? 1 : 0;
+            info->near_charge_values = pl->last_has_q ? (as.near_sym ? as.near_q_vals : as.pairs_q) : 0;
+            info->near_incoming = pl->last_has_q && as.near_sym ? as.inc_len : 0;
             info->l2p_points = far ? as.l2p_points : 0;
             info->p2m_points = far ? (pl->last_has_q ? pl->toff[1] - pl->toff[0] : 0) +
                                          (pl->last_has_d ? pl->toff[2] - pl->toff[1] : 0)

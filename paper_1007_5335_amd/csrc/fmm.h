@@ -65,9 +65,23 @@ struct ActiveSet {
     // entries K0, dipole entries the pair (dx, dy) 4 K1(z)/z (scaled units)
     DevBuf<int64_t> item_qoff, item_doff;   // entry offsets per item
     int64_t near_q_len = 0, near_d_len = 0; // entries (dipole entries are pairs)
+    int64_t near_q_vals = 0;                // charge entries other than alignment padding
     DevBuf<double> nq64, nd64;
     DevBuf<float> nq32, nd32;
     bool near64 = false, near32 = false;     // built
+    // symmetric charge values (the charges among the targets, at most 64 per
+    // leaf): each pair block of neighbouring leaves stored once, by the
+    // leaf of smaller index, which also adds it, transposed, into the other
+    // leaf's incoming slot.  Per item a descriptor and the slot each U-list
+    // entry writes (-1: none); per leaf the first slot entry and the number
+    // of slots.
+    bool near_sym = false;
+    DevBuf<int32_t> sym_desc;          // per item: U-list ranges and target ranges (52 entries)
+    DevBuf<int64_t> sym_desc_dst;      // per item: the incoming slot of each U-list entry
+    DevBuf<int64_t> inc_base;
+    DevBuf<int32_t> inc_cnt;
+    DevBuf<double> inc;
+    int64_t inc_len = 0;
 };
 
 struct FmmPlan {

@@ -1606,6 +1606,360 @@ __global__ __launch_bounds__(NTB) void k_near_apply(
     }
 }
 
+// ---------------------------------------------------- symmetric near field --
+// The charge-to-charge values K0(|x - y|/alpha) are symmetric in the two
+// points.  When every leaf fits one item, the block of each unordered pair of
+// neighbouring leaves {A, B} is stored once, with the leaf of smaller index
+// (its owner), and the owner's item applies it both ways: to its own charges
+// (a sum over B's charges) and, transposed, to B's charges (a sum over its
+// own), the latter written to B's incoming slot, which k_l2p adds.  A leaf's
+// own block is stored whole.  Every leaf holds at most 64 charges; they lead
+// its targets, so they all fall in its first item.  Per item (starting at a
+// multiple of four entries) the charge values are, source major and target
+// minor: (1) the item's charges as targets against the charges of the owned
+// neighbours (the leaf itself and those of larger index, in U-list order),
+// each source's row padded with zeros to a multiple of four targets, (2) its
+// other targets against the charges of all neighbours.  The dipole values keep
+// the layout of k_near_build.
+//
+// owned charge count of each U-list entry (lanes < 9; published by the
+// barrier in item_setup)
+__device__ __forceinline__ void owned_counts(int li, const int32_t *__restrict__ lrange,
+                                             const int32_t *__restrict__ uoff, const int32_t *__restrict__ ulist,
+                                             int *qo) {
+    const int lane = threadIdx.x;
+    if (lane < 9) {
+        const int u0 = uoff[li], nu = uoff[li + 1] - u0;
+        int o = 0;
+        if (lane < nu) {
+            const int ul = ulist[u0 + lane];
+            if (ul >= li) o = lrange[ul * 6 + 1] - lrange[ul * 6];
+        }
+        qo[lane] = o;
+    }
+}
+
+// sorted index of the k-th target of a leaf (sets in order, those of the mask)
+__device__ __forceinline__ int item_target(int li, int k, const int32_t *__restrict__ lrange, int mask) {
+    for (int s = 0; s < 3; ++s) {
+        const int rs = lrange[li * 6 + 2 * s], n = (mask >> s) & 1 ? lrange[li * 6 + 2 * s + 1] - rs : 0;
+        if (k < n) return rs + k;
+        k -= n;
+    }
+    return -1;
+}
+
+template <int NT, bool kSmallOnly, bool kF32>
+__global__ __launch_bounds__(64) void k_near_build_sym(
+    const int2 *__restrict__ items, const int32_t *__restrict__ lrange, const int32_t *__restrict__ uoff,
+    const int32_t *__restrict__ ulist, const double *__restrict__ px, const double *__restrict__ py, int mask,
+    double inv2a, const int64_t *__restrict__ qoff,
+    typename std::conditional<kF32, float, double>::type *__restrict__ Mq) {
+    using VT = typename std::conditional<kF32, float, double>::type;
+    __shared__ double2 s_log[YK_LOG_TAB];
+    __shared__ int qa[9], qn[9], da[9], dn_[9], qo[9];
+    const int ib = xcd_remap(blockIdx.x, gridDim.x);
+    const int lane = threadIdx.x;
+    if constexpr (!kF32)
+        for (int i = lane; i < YK_LOG_TAB; i += 64) s_log[i] = make_double2(yk_log_tab[2 * i], yk_log_tab[2 * i + 1]);
+    const int2 item = items[ib];
+    const int li = item.x;
+    owned_counts(li, lrange, uoff, ulist, qo);
+    const ItemSetup it = item_setup(item, lrange, uoff, ulist, 1, 0, mask, qa, qn, da, dn_);
+    int nown = 0;
+    for (int u = 0; u < 9; ++u) nown += qo[u];
+    // (the mask has the charges; they lead a leaf's targets, all in its first item)
+    const int rs0 = lrange[li * 6], nA0 = item.y == 0 ? lrange[li * 6 + 1] - rs0 : 0;
+    const int cB = it.c - nA0;
+    auto value = [&](int t, int j) -> VT {
+        const double dx = (px[t] - px[j]) * inv2a, dy = (py[t] - py[j]) * inv2a;
+        const double tt = __builtin_fma(dx, dx, dy * dy);
+        double v = 0.0;
+        if (tt > 0.0) {
+            if constexpr (kF32) v = (double)near_k0_f<kSmallOnly>((float)tt);
+            else v = near_k0<NT, kSmallOnly>(tt, s_log);
+        }
+        return (VT)v;
+    };
+    VT *M1 = Mq + qoff[ib];
+    const int cA4 = (nA0 + 3) & ~3;
+    const int64_t n1 = (int64_t)cA4 * nown;
+    for (int64_t e = lane; e < n1; e += 64) {
+        const int f = (int)(e / cA4), t = (int)(e % cA4);
+        M1[e] = t < nA0 ? value(rs0 + t, flat_source(f, qo, qa)) : (VT)0;
+    }
+    VT *M2 = M1 + n1;
+    const int64_t n2 = (int64_t)cB * it.nq;
+    for (int64_t e = lane; e < n2; e += 64) {
+        const int f = (int)(e / cB), k = (int)(e % cB);
+        M2[e] = value(item_target(li, item.y + nA0 + k, lrange, mask), flat_source(f, qn, qa));
+    }
+}
+
+// Per-item descriptor of the symmetric near field (built with the plan): for
+// the nine U-list entries the first charge, the charge count, the owned charge
+// count, the first dipole and the dipole count (entries 0-44), the item's
+// target ranges per set, empty for sets outside the mask (45-47 first, 48-50
+// end), its first target (51); and per entry the incoming slot it writes.
+constexpr int kItemDesc = 52;
+
+template <int NTB>
+__device__ __forceinline__ ItemSetup setup_from_desc(const int *d) {
+    const int lane = threadIdx.x;
+    ItemSetup r;
+    r.nq = 0;
+    r.nd = 0;
+    for (int u = 0; u < 9; ++u) {
+        r.nq += d[9 + u];
+        r.nd += d[36 + u];
+    }
+    int ntot = 0;
+    for (int s = 0; s < 3; ++s) ntot += d[48 + s] - d[45 + s];
+    const int y = d[51];
+    r.c = min(64, ntot - y);
+    r.g = NTB / r.c;
+    r.ti = lane % r.c;
+    r.sub = lane / r.c;
+    r.valid = r.sub < r.g;
+    int k = y + r.ti;
+    r.t = -1;
+    for (int s = 0; s < 3; ++s) {
+        const int n = d[48 + s] - d[45 + s];
+        if (r.t < 0 && k < n) r.t = d[45 + s] + k;
+        k -= n;
+    }
+    return r;
+}
+
+// Sources per lane and batch in the owned charge block (each lane has this
+// many quarter rows of four values in flight).
+constexpr int kSymRounds = 4;
+
+// four consecutive values (16-byte aligned for float, 32 for double), read once
+__device__ __forceinline__ void load4(const double *p, double (&o)[4]) {
+    const yk_dpair a = __builtin_nontemporal_load(reinterpret_cast<const yk_dpair *>(p));
+    const yk_dpair b = __builtin_nontemporal_load(reinterpret_cast<const yk_dpair *>(p) + 1);
+    o[0] = a.x;
+    o[1] = a.y;
+    o[2] = b.x;
+    o[3] = b.y;
+}
+__device__ __forceinline__ void load4(const float *p, double (&o)[4]) {
+    const yk_f4 a = __builtin_nontemporal_load(reinterpret_cast<const yk_f4 *>(p));
+    o[0] = a.x;
+    o[1] = a.y;
+    o[2] = a.z;
+    o[3] = a.w;
+}
+
+template <typename VT, int NTB>
+__global__ __launch_bounds__(NTB) __attribute__((amdgpu_waves_per_eu(5))) void k_near_apply_sym(
+    const int32_t *__restrict__ desc, const int64_t *__restrict__ desc_dst, const double *__restrict__ qs,
+    const double *__restrict__ dns, int64_t off1, int has_q, int has_d, const int64_t *__restrict__ qoff, const int64_t *__restrict__ doff, const VT *__restrict__ Mq,
+    const VT *__restrict__ Md, double dip_scale, double *__restrict__ outs, double *__restrict__ inc) {
+    __shared__ double s_a[NTB > kLeafStage ? NTB : kLeafStage], s_b[kLeafStage];
+    __shared__ double s_res[64];
+    __shared__ double s_p[4 * NTB];   // direct sums of part (1), four targets per lane
+    __shared__ int s_d[kItemDesc], s_pre[9];
+    __shared__ int64_t s_dst[9];
+    const int ib = xcd_remap(blockIdx.x, gridDim.x);
+    const int lane = threadIdx.x;
+    // the item's descriptor: one round trip instead of the chain leaf -> U list -> ranges
+    if (lane < kItemDesc) s_d[lane] = desc[(int64_t)ib * kItemDesc + lane];
+    if (lane < 9) s_dst[lane] = desc_dst[(int64_t)ib * 9 + lane];
+    if (lane < 64) s_res[lane] = 0.0;
+    __syncthreads();
+    const int *qa = s_d, *qn = s_d + 9, *qo = s_d + 18, *da = s_d + 27, *dn_ = s_d + 36;
+    const ItemSetup it = setup_from_desc<NTB>(s_d);
+    // first owned source of each U-list entry (published by part (1)'s barriers)
+    if (lane < 9) {
+        int a = 0;
+        for (int u = 0; u < lane; ++u) a += qo[u];
+        s_pre[lane] = a;
+    }
+    const int c = it.c;
+    // the leaf's charges (at most 64) lead its targets, all in its first item
+    const int rs0 = s_d[45], nA0 = s_d[51] == 0 ? s_d[48] - rs0 : 0;
+    int nown = 0;
+    for (int u = 0; u < 9; ++u) nown += qo[u];
+    // (1) the item's charges against the owned charges, both ways.  A lane
+    // takes four consecutive targets (one quarter row) of four sources per
+    // batch, read as vectors; it sums the direct products over its sources in
+    // registers for the whole block and the transposed ones over its targets,
+    // then over the tb lanes that share the sources (shuffles within a
+    // wavefront: the lanes of a source never straddle one).
+    if (has_q && nA0 > 0) {
+        const int cA = nA0, cA4 = (cA + 3) & ~3, tb = cA4 >> 2;
+        const int nf = 64 / tb, nfb = (NTB / 64) * nf;
+        const int wl = lane & 63, lt = wl % tb;
+        const int fs = (lane >> 6) * nf + wl / tb;
+        const bool vA = wl / tb < nf;
+        double qa4[4], y4[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int t = 4 * lt + i;
+            qa4[i] = (vA && t < cA) ? qs[rs0 + t] : 0.0;
+            y4[i] = 0.0;
+        }
+        const VT *Mb = Mq + qoff[ib] + 4 * lt;
+        for (int c0 = 0; c0 < nown; c0 += kLeafStage) {
+            const int cn = min(kLeafStage, nown - c0);
+            double w[kSymRounds][4];
+            // rounds of a batch that hold sources (the same for all lanes)
+            int nr = 0;
+            auto load_batch = [&](int r0) {
+                nr = min(kSymRounds, (cn - r0 + nfb - 1) / nfb);
+#pragma unroll
+                for (int j = 0; j < kSymRounds; ++j) {
+                    const int f = r0 + j * nfb + fs;
+                    if (j < nr && vA && f < cn) {
+                        load4(Mb + (int64_t)(c0 + f) * cA4, w[j]);
+                    } else {
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) w[j][i] = 0.0;
+                    }
+                }
+            };
+            // the first batch is in flight while the sources' charges are staged
+            load_batch(0);
+            __syncthreads();
+            for (int f = lane; f < cn; f += NTB) s_a[f] = qs[flat_source(c0 + f, qo, qa)];
+            __syncthreads();
+            for (int r0 = 0; r0 < cn; r0 += kSymRounds * nfb) {
+                if (r0 > 0) load_batch(r0);
+                double z[kSymRounds];
+#pragma unroll
+                for (int j = 0; j < kSymRounds; ++j) {
+                    z[j] = 0.0;
+                    if (j >= nr) continue;
+                    const int f = r0 + j * nfb + fs;
+                    const double qb = (vA && f < cn) ? s_a[f] : 0.0;
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        y4[i] = __builtin_fma(w[j][i], qb, y4[i]);
+                        z[j] = __builtin_fma(w[j][i], qa4[i], z[j]);
+                    }
+                }
+                for (int k = 1; k < tb; k <<= 1) {
+                    const bool in = lt + k < tb;
+#pragma unroll
+                    for (int j = 0; j < kSymRounds; ++j) {
+                        if (j >= nr) continue;
+                        const double o = __shfl_down(z[j], k, 64);
+                        z[j] += in ? o : 0.0;
+                    }
+                }
+                if (vA && lt == 0) {
+#pragma unroll
+                    for (int j = 0; j < kSymRounds; ++j) {
+                        const int f = r0 + j * nfb + fs;
+                        if (f >= cn) break;
+                        // the U-list entry of owned source c0 + f: the last one
+                        // starting at or before it (empty entries share the
+                        // next one's start)
+                        const int ff = c0 + f;
+                        int u = 0;
+#pragma unroll
+                        for (int k = 1; k < 9; ++k) u += ff >= s_pre[k] ? 1 : 0;
+                        const int64_t d = s_dst[u];
+                        if (d >= 0) inc[d + ff - s_pre[u]] = z[j] * kInv2Pi;
+                    }
+                }
+            }
+        }
+        // the direct sums over the source slots: lane (slot, lt) holds targets 4 lt .. 4 lt + 3
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < 4; ++i) s_p[4 * lane + i] = vA ? y4[i] : 0.0;
+        __syncthreads();
+        if (lane < cA) {
+            double tot = 0.0;
+            for (int q = 0; q < nfb; ++q) {
+                const int ln = (q / nf) * 64 + (q % nf) * tb + (lane >> 2);
+                tot += s_p[4 * ln + (lane & 3)];
+            }
+            s_res[lane] += tot;
+        }
+    }
+    // (2) the item's other targets against all neighbouring charges
+    const int cB = c - nA0;
+    if (has_q && cB > 0 && it.nq > 0) {
+        const int gB = NTB / cB, tiB = lane % cB, subB = lane / cB;
+        const bool vB = subB < gB;
+        const VT *Mb = Mq + qoff[ib] + (int64_t)((nA0 + 3) & ~3) * nown;
+        double acc = 0.0;
+        for (int c0 = 0; c0 < it.nq; c0 += kLeafStage) {
+            const int cn = min(kLeafStage, it.nq - c0);
+            __syncthreads();
+            for (int f = lane; f < cn; f += NTB) s_a[f] = qs[flat_source(c0 + f, qn, qa)];
+            __syncthreads();
+            if (!vB) continue;
+            const VT *Mr = Mb + (int64_t)c0 * cB + tiB + (int64_t)subB * cB;
+            const int64_t cs = (int64_t)cB * gB;
+            int j = subB;
+            for (; j + 7 * gB < cn; j += 8 * gB, Mr += 8 * cs) {
+                VT m[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) m[u] = __builtin_nontemporal_load(Mr + u * cs);
+#pragma unroll
+                for (int u = 0; u < 8; ++u) acc = __builtin_fma((double)m[u], s_a[j + u * gB], acc);
+            }
+            for (; j < cn; j += gB, Mr += cs) acc = __builtin_fma((double)__builtin_nontemporal_load(Mr), s_a[j], acc);
+        }
+        __syncthreads();
+        s_a[lane] = vB ? acc : 0.0;
+        __syncthreads();
+        if (lane < cB) {
+            double tot = 0.0;
+            for (int s = 0; s < gB; ++s) tot += s_a[s * cB + lane];
+            s_res[nA0 + lane] += tot;
+        }
+    }
+    // (3) every target against the dipoles (layout of k_near_build)
+    if (has_d && it.nd > 0) {
+        double acc = 0.0;
+        for (int c0 = 0; c0 < it.nd; c0 += kLeafStage) {
+            const int cn = min(kLeafStage, it.nd - c0);
+            __syncthreads();
+            for (int f = lane; f < cn; f += NTB) {
+                const int64_t jd = flat_source(c0 + f, dn_, da) - off1;
+                s_a[f] = dns[2 * jd];
+                s_b[f] = dns[2 * jd + 1];
+            }
+            __syncthreads();
+            if (!it.valid) continue;
+            const int gs = it.g;
+            const int64_t cs = (int64_t)c * gs;
+            const VT *Mr = Md + 2 * (doff[ib] + (int64_t)c0 * c + it.ti + (int64_t)it.sub * c);
+            int j = it.sub;
+            for (; j + 3 * gs < cn; j += 4 * gs, Mr += 8 * cs) {
+                VT mx[4], my[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    mx[u] = __builtin_nontemporal_load(Mr + 2 * u * cs);
+                    my[u] = __builtin_nontemporal_load(Mr + 2 * u * cs + 1);
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+                    acc = __builtin_fma((double)mx[u], s_a[j + u * gs], __builtin_fma((double)my[u], s_b[j + u * gs], acc));
+            }
+            for (; j < cn; j += gs, Mr += 2 * cs)
+                acc = __builtin_fma((double)__builtin_nontemporal_load(Mr), s_a[j],
+                                    __builtin_fma((double)__builtin_nontemporal_load(Mr + 1), s_b[j], acc));
+        }
+        __syncthreads();
+        s_a[lane] = it.valid ? acc : 0.0;
+        __syncthreads();
+        if (lane < c) {
+            double tot = 0.0;
+            for (int s = 0; s < it.g; ++s) tot += s_a[s * c + lane];
+            s_res[lane] += dip_scale * tot;
+        }
+    }
+    __syncthreads();
+    if (lane < c) outs[it.t] = s_res[lane] * kInv2Pi;
+}
+
 using NearBuild64 = void (*)(const int2 *, const int32_t *, const int32_t *, const int32_t *,
                              const double *, const double *, int, int, int, double, const int64_t *,
                              const int64_t *, double *, double *);
@@ -1626,6 +1980,23 @@ NearBuild64 pick_near_build64(int nt, bool small_only) {
 NearBuild32 pick_near_build32(bool small_only) {
     return small_only ? k_near_build<8, true, true> : k_near_build<8, false, true>;
 }
+using NearBuildSym64 = void (*)(const int2 *, const int32_t *, const int32_t *, const int32_t *,
+                                const double *, const double *, int, double, const int64_t *, double *);
+using NearBuildSym32 = void (*)(const int2 *, const int32_t *, const int32_t *, const int32_t *,
+                                const double *, const double *, int, double, const int64_t *, float *);
+NearBuildSym64 pick_near_build_sym64(int nt, bool small_only) {
+    if (small_only) {
+        if (nt <= 5) return k_near_build_sym<5, true, false>;
+        if (nt <= 6) return k_near_build_sym<6, true, false>;
+        if (nt <= 8) return k_near_build_sym<8, true, false>;
+        if (nt <= 10) return k_near_build_sym<10, true, false>;
+        return k_near_build_sym<14, true, false>;
+    }
+    return k_near_build_sym<14, false, false>;
+}
+NearBuildSym32 pick_near_build_sym32(bool small_only) {
+    return small_only ? k_near_build_sym<8, true, true> : k_near_build_sym<8, false, true>;
+}
 
 using LeafKernel = void (*)(const int2 *, int64_t, const int32_t *, const int32_t *,
                             const int32_t *, const double *, const double *, const double *,
@@ -1642,7 +2013,8 @@ __global__ __launch_bounds__(256) void k_l2p(
     const double *__restrict__ sc, int nser, int p, int Pp, const double *__restrict__ outs,
     const int32_t *__restrict__ perm, double *__restrict__ out0, double *__restrict__ out1,
     double *__restrict__ out2, const double *__restrict__ bw, const double *__restrict__ bk,
-    const double *__restrict__ bx) {
+    const double *__restrict__ bx, const double *__restrict__ inc, const int64_t *__restrict__ inc_base,
+    const int32_t *__restrict__ inc_cnt, const int32_t *__restrict__ lrange) {
     extern __shared__ double dyn[];
     double *t_cnn = dyn;               // [p+1]
     double *t_ify = t_cnn + p + 1;     // [p+1]
@@ -1678,7 +2050,14 @@ __global__ __launch_bounds__(256) void k_l2p(
     }
     const double F0 = F1 + yv * F2 * t_cnn[0];
     // near field + far field, written straight to the caller's array of the set
-    const double v = outs[t] + (Lb[0] * F0 * t_ify[0] + 2.0 * (sr * zx - si * zy)) * kInv2Pi;
+    double v = outs[t] + (Lb[0] * F0 * t_ify[0] + 2.0 * (sr * zx - si * zy)) * kInv2Pi;
+    if (set == 0 && inc) {
+        // symmetric near field: the charges of the neighbours that own the
+        // pair blocks with this leaf, one incoming slot per owner
+        const int32_t lb = pleaf[t], s0 = lrange[lb * 6], n0 = lrange[lb * 6 + 1] - s0;
+        const double *ip = inc + inc_base[lb] + (t - s0);
+        for (int k = 0; k < inc_cnt[lb]; ++k) v += ip[(int64_t)k * n0];
+    }
     double *o = set == 0 ? out0 : set == 1 ? out1 : out2;
     const int32_t i = perm[t];
     if (set == 1 && bx)   // double-layer operator: x - 2 (DL + diagonal limit)
@@ -1746,6 +2125,7 @@ void fmm_run(Context &ctx, FmmPlan &pl, const double *q, const double *dn, doubl
     // sharing it was measured slower than running the stages in turn)
     const bool overlap = !(ctx.opt.debug_flags & 2) && pl.nleaf < 8192;
     bool near_done = false;
+    const double *sym_inc = nullptr;   // incoming slots of the symmetric near field (for k_l2p)
     auto launch_near = [&]() {
         near_done = true;
         if (overlap) {
@@ -1763,6 +2143,37 @@ void fmm_run(Context &ctx, FmmPlan &pl, const double *q, const double *dn, doubl
             const bool cache = ctx.opt.near_cache_mb > 0 && bytes <= ((int64_t)ctx.opt.near_cache_mb << 20);
             if (cache) {
                 bool &built = f32 ? as.near32 : as.near64;
+                if (!built && as.near_sym) {
+                    // charge values in the symmetric layout, dipole values as below
+                    StageTimer tb(ctx, YK_STAGE_NEAR_BUILD, near_stream);
+                    if (f32) {
+                        float *mq = as.nq32.ensure(std::max<int64_t>(as.near_q_len, 1));
+                        float *md = as.nd32.ensure(std::max<int64_t>(2 * as.near_d_len, 1));
+                        hipLaunchKernelGGL(pick_near_build_sym32(small_only), dim3(as.n_items), dim3(64), 0,
+                                           near_stream, as.leaf_items.p, pl.lrange.p, pl.ulist_off.p,
+                                           pl.ulist.p, pl.px.p, pl.py.p, mask, 0.5 * inv_alpha, as.item_qoff.p,
+                                           mq);
+                        if (d_on)
+                            hipLaunchKernelGGL(pick_near_build32(small_only), dim3(as.n_items), dim3(64), 0,
+                                               near_stream, as.leaf_items.p, pl.lrange.p, pl.ulist_off.p,
+                                               pl.ulist.p, pl.px.p, pl.py.p, 0, d_on, mask, 0.5 * inv_alpha,
+                                               as.item_qoff.p, as.item_doff.p, mq, md);
+                    } else {
+                        double *mq = as.nq64.ensure(std::max<int64_t>(as.near_q_len, 1));
+                        double *md = as.nd64.ensure(std::max<int64_t>(2 * as.near_d_len, 1));
+                        hipLaunchKernelGGL(pick_near_build_sym64(pl.near_terms, small_only), dim3(as.n_items),
+                                           dim3(64), 0, near_stream, as.leaf_items.p, pl.lrange.p,
+                                           pl.ulist_off.p, pl.ulist.p, pl.px.p, pl.py.p, mask, 0.5 * inv_alpha,
+                                           as.item_qoff.p, mq);
+                        if (d_on)
+                            hipLaunchKernelGGL(pick_near_build64(pl.near_terms, small_only), dim3(as.n_items),
+                                               dim3(64), 0, near_stream, as.leaf_items.p, pl.lrange.p,
+                                               pl.ulist_off.p, pl.ulist.p, pl.px.p, pl.py.p, 0, d_on, mask,
+                                               0.5 * inv_alpha, as.item_qoff.p, as.item_doff.p, mq, md);
+                    }
+                    check_launch(ctx, "k_near_build_sym");
+                    built = true;
+                }
                 if (!built) {
                     StageTimer tb(ctx, YK_STAGE_NEAR_BUILD, near_stream);
                     if (f32) {
@@ -1788,7 +2199,23 @@ void fmm_run(Context &ctx, FmmPlan &pl, const double *q, const double *dn, doubl
                 // the GPU with under about eight wavefronts per CU
                 const bool wide = as.n_items < 2048;
                 const dim3 blk(wide ? 256 : 64);
-                if (f32) {
+                if (as.near_sym) {
+                    double *inc = has_q ? as.inc.ensure(std::max<int64_t>(as.inc_len, 1)) : nullptr;
+                    if (f32) {
+                        auto kern = wide ? k_near_apply_sym<float, 256> : k_near_apply_sym<float, 64>;
+                        hipLaunchKernelGGL(kern, dim3(as.n_items), blk, 0, near_stream, as.sym_desc.p,
+                                           as.sym_desc_dst.p, qs, dns, pl.toff[1], has_q, has_d,
+                                           as.item_qoff.p, as.item_doff.p, as.nq32.p, as.nd32.p, 0.5 * inv_alpha, outs,
+                                           inc);
+                    } else {
+                        auto kern = wide ? k_near_apply_sym<double, 256> : k_near_apply_sym<double, 64>;
+                        hipLaunchKernelGGL(kern, dim3(as.n_items), blk, 0, near_stream, as.sym_desc.p,
+                                           as.sym_desc_dst.p, qs, dns, pl.toff[1], has_q, has_d,
+                                           as.item_qoff.p, as.item_doff.p, as.nq64.p, as.nd64.p, 0.5 * inv_alpha, outs,
+                                           inc);
+                    }
+                    sym_inc = inc;
+                } else if (f32) {
                     auto kern = wide ? k_near_apply<float, 256> : k_near_apply<float, 64>;
                     hipLaunchKernelGGL(kern, dim3(as.n_items), blk, 0, near_stream,
                                        as.leaf_items.p, pl.lrange.p, pl.ulist_off.p, pl.ulist.p, qs, dns,
@@ -2017,7 +2444,8 @@ void fmm_run(Context &ctx, FmmPlan &pl, const double *q, const double *dn, doubl
                            pl.Lc.p, inv_alpha, 1.0 / pl.lev[L].R, pl.invFY.p + L * lvl, pl.cnn.p,
                            pl.serc.p, pl.nser, p, Pp, outs, pl.perm.p, out[0], out[1], out[2],
                            bie ? bie->w : nullptr, bie ? bie->kappa : nullptr,
-                           (bie && bie->kappa) ? bie->sigma : nullptr);
+                           (bie && bie->kappa) ? bie->sigma : nullptr, sym_inc, as.inc_base.p, as.inc_cnt.p,
+                           pl.lrange.p);
         check_launch(ctx, "k_l2p");
         return;   // L2P wrote the outputs
     }

@@ -557,18 +557,102 @@ ActiveSet &get_active(Context &ctx, FmmPlan &pl, int mask) {
             as->pairs_d += nt * sd;
             as->l2p_points += nt;
         }
+        // symmetric charge values
+        const int64_t n0 = pl.toff[1] - pl.toff[0];
+        // charges among the targets, at most 64 per leaf (so that they all
+        // fall in the leaf's first item, which they lead), and a far field
+        // (k_l2p adds the incoming slots)
+        auto n0_of = [&](int64_t li) -> int64_t { return pl.h_lrange[(size_t)li * 6 + 1] - pl.h_lrange[(size_t)li * 6]; };
+        bool sym = (mask & 1) && n0 > 0 && pl.lmin <= L && !(ctx.opt.debug_flags & 16);
+        for (int64_t li = 0; li < pl.nleaf && sym; ++li)
+            if (n0_of(li) > 64) sym = false;
+        if (sym) {
+            // incoming slots of leaf B: one per U-list neighbour A < B with
+            // charges, in B's U-list order, each n0(B) entries; the writer is
+            // A's U-list entry that names B
+            std::vector<int64_t> dst(ul.size(), -1), ibase(pl.nleaf, 0);
+            std::vector<int32_t> icnt(pl.nleaf, 0);
+            int64_t off = 0;
+            for (int64_t b = 0; b < pl.nleaf; ++b) {
+                ibase[b] = off;
+                int k = 0;
+                for (int32_t u = uoff[b]; u < uoff[b + 1]; ++u) {
+                    const int32_t a = ul[u];
+                    if (a >= b || n0_of(a) == 0) continue;
+                    int32_t ua = uoff[a];
+                    while (ua < uoff[a + 1] && ul[ua] != b) ++ua;
+                    if (ua == uoff[a + 1]) throw Error{YK_ERR_INTERNAL, "U-lists are not symmetric"};
+                    dst[ua] = off + (int64_t)k * n0_of(b);
+                    ++k;
+                }
+                icnt[b] = k;
+                off += (int64_t)k * n0_of(b);
+            }
+            as->inc_len = off;
+            int64_t *db = as->inc_base.ensure(ibase.size());
+            int32_t *dc = as->inc_cnt.ensure(icnt.size());
+            YK_HIP(hipMemcpyAsync(db, ibase.data(), ibase.size() * sizeof(int64_t), hipMemcpyHostToDevice, ctx.stream));
+            YK_HIP(hipMemcpyAsync(dc, icnt.data(), icnt.size() * sizeof(int32_t), hipMemcpyHostToDevice, ctx.stream));
+            as->inc.ensure(std::max<int64_t>(off, 1));
+            // per-item descriptors (layout: kItemDesc in the near-field kernels)
+            constexpr int kDesc = 52;
+            const int q_on = 1, d_on = (pl.toff[2] > pl.toff[1]) ? 1 : 0;
+            std::vector<int32_t> desc(items.size() * kDesc, 0);
+            std::vector<int64_t> ddst(items.size() * 9, -1);
+            for (size_t i = 0; i < items.size(); ++i) {
+                const int32_t li = items[i].x;
+                int32_t *d = desc.data() + i * kDesc;
+                const int32_t u0 = uoff[li], nu = uoff[li + 1] - u0;
+                for (int u = 0; u < 9 && u < nu; ++u) {
+                    const int32_t b = ul[u0 + u];
+                    const int32_t *r = pl.h_lrange.data() + (size_t)b * 6;
+                    d[u] = r[0];
+                    d[9 + u] = q_on ? r[1] - r[0] : 0;
+                    d[18 + u] = (q_on && b >= li) ? r[1] - r[0] : 0;
+                    d[27 + u] = r[2];
+                    d[36 + u] = d_on ? r[3] - r[2] : 0;
+                    ddst[i * 9 + u] = dst[u0 + u];
+                }
+                const int32_t *r = pl.h_lrange.data() + (size_t)li * 6;
+                for (int st = 0; st < 3; ++st) {
+                    d[45 + st] = r[2 * st];
+                    d[48 + st] = (mask >> st) & 1 ? r[2 * st + 1] : r[2 * st];
+                }
+                d[51] = items[i].y;
+            }
+            int32_t *dde = as->sym_desc.ensure(desc.size());
+            int64_t *ddd = as->sym_desc_dst.ensure(ddst.size());
+            YK_HIP(hipMemcpyAsync(dde, desc.data(), desc.size() * sizeof(int32_t), hipMemcpyHostToDevice, ctx.stream));
+            YK_HIP(hipMemcpyAsync(ddd, ddst.data(), ddst.size() * sizeof(int64_t), hipMemcpyHostToDevice, ctx.stream));
+            YK_HIP(hipStreamSynchronize(ctx.stream));
+            as->near_sym = true;
+        }
         // entry offsets of the cached near field, item by item
         std::vector<int64_t> qoff(items.size()), doff(items.size());
-        int64_t oq = 0, od = 0;
+        int64_t oq = 0, od = 0, vq = 0;   // (vq: charge values without the padding)
         for (size_t i = 0; i < items.size(); ++i) {
             const int li = items[i].x;
             const int64_t c = std::min<int64_t>(64, cnt[pl.lev[L].begin + li] - items[i].y);
+            if (sym) oq = (oq + 3) & ~(int64_t)3;   // (vector reads of four values)
             qoff[i] = oq;
             doff[i] = od;
-            oq += c * sq_leaf[li];
+            if (sym) {
+                // the leaf's charges against the owned neighbours' charges,
+                // its other targets against all neighbouring charges
+                int64_t own = 0;
+                for (int32_t u = uoff[li]; u < uoff[li + 1]; ++u)
+                    if (ul[u] >= li) own += n0_of(ul[u]);
+                const int64_t na = items[i].y == 0 ? n0_of(li) : 0;
+                oq += ((na + 3) & ~(int64_t)3) * own + (c - na) * sq_leaf[li];
+                vq += na * own + (c - na) * sq_leaf[li];
+            } else {
+                oq += c * sq_leaf[li];
+                vq += c * sq_leaf[li];
+            }
             od += c * sd_leaf[li];
         }
         as->near_q_len = oq;
+        as->near_q_vals = vq;
         as->near_d_len = od;
         if (!items.empty()) {
             int64_t *dq = as->item_qoff.ensure(items.size());

@@ -75,7 +75,9 @@ class yk_plan_info(ctypes.Structure):
                 ("m2l_translations", ctypes.c_int64), ("m2l_slots", ctypes.c_int64),
                 ("p2m_points", ctypes.c_int64), ("l2p_points", ctypes.c_int64),
                 ("near_terms", ctypes.c_int32), ("nser", ctypes.c_int32),
-                ("build_ms", ctypes.c_double), ("m2l_sparse", ctypes.c_int32)]
+                ("build_ms", ctypes.c_double), ("m2l_sparse", ctypes.c_int32),
+                ("near_sym", ctypes.c_int32), ("near_charge_values", ctypes.c_int64),
+                ("near_incoming", ctypes.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -478,6 +478,55 @@ def test_near_cache_matches_on_the_fly(yk, oracle_lib, precision):
     assert rel_l2(outs[16384][0], ref) < (1e-10 if precision == "fp64" else 2e-5)
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("case", ["few_items", "many_items", "clustered"])
+def test_symmetric_near_field_matches_full_storage(yk, oracle_lib, precision, case):
+    """Charge-to-charge near-field values stored once per pair of neighbouring
+    leaves and applied both ways (the default when every leaf holds at most 64
+    charges) give the sums of storing both orders (debug_flags bit 4), also on
+    a second call with new strengths; they are read at about half the bytes.
+    Few items run four wavefronts per item, many items one; the clustered set
+    has leaves of more than 64 targets (nodes of the holes), split into
+    several items."""
+    import torch
+    n_vol, leaf = {"few_items": (6000, 32), "many_items": (1 << 17, 16), "clustered": (20000, 32)}[case]
+    c = W.small_fmm_case(n_vol=n_vol, n_nodes=256, alpha=0.05, seed=23, clustered=case == "clustered")
+    b = c["bnd"]
+    rng = np.random.default_rng(24)
+    strengths = ((c["q"], c["dip"]), (rng.standard_normal(c["q"].size), rng.standard_normal(b.n)))
+    prec = yk.YK_PREC_FP32 if precision == "fp32" else yk.YK_PREC_FP64
+    outs, infos = {}, {}
+    for flags in (0, 16):
+        ctx = _ctx(yk, leaf_size=leaf, fmm_tol=1e-10, precision=prec, debug_flags=flags)
+        try:
+            bd = yk.Boundary.from_workload(b)
+            res = []
+            for q, dip in strengths:
+                ov = torch.empty(c["vol"].shape[0], dtype=torch.float64, device="cuda")
+                ob = torch.empty(b.n, dtype=torch.float64, device="cuda")
+                print(f"symmetric near field {case} {precision} flags {flags}", flush=True)
+                yk.yk_fmm_potential(ctx, dev(c["vol"]), dev(q), bd, dev(dip), c["alpha"], ov, ob)
+                torch.cuda.synchronize()
+                res.append(np.concatenate([host(ov), host(ob)]))
+            infos[flags] = yk.yk_plan_info_get(ctx, 0)
+        finally:
+            yk.yk_destroy(ctx)
+        outs[flags] = res
+    full, sym = infos[16], infos[0]
+    assert full.near_sym == 0 and full.near_charge_values == full.pairs_charge
+    if case != "clustered":
+        assert sym.near_sym == 1
+    if sym.near_sym:
+        assert sym.near_charge_values < 0.7 * sym.pairs_charge
+        assert sym.near_incoming > 0
+    tol = 1e-13 if precision == "fp64" else 2e-6
+    for a, bb in zip(outs[0], outs[16]):
+        assert rel_l2(a, bb) < tol
+    if case == "few_items":
+        rv, rb = _oracle_fmm_potential(oracle_lib, c)
+        assert rel_l2(outs[0][0], np.concatenate([rv, rb])) < (1e-10 if precision == "fp64" else 2e-5)
+
+
 def test_heat_step_reuses_charge_multipoles(yk):
     """Two C3-size heat steps (1024^2 grid, 65,536 leaves): the second volume
     pass of each step starts from the charges' multipoles kept by the first
