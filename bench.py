@@ -77,7 +77,9 @@ def rooflines(info, st, steps, fp32):
         vb = 4 if fp32 else 8
         nbytes = info.near_charge_values * vb + info.pairs_dipole * 2 * vb + info.near_incoming * 8
         ach = nbytes / (t * 1e-3) / 1e9
-        out["near"] = {"kernel": "k_near_apply (cached near field, P2P)", "bound": "hbm", "achieved": ach,
+        kname = ("k_near_apply_sym (cached near field, P2P; charge blocks stored once per leaf pair)"
+                 if info.near_sym else "k_near_apply (cached near field, P2P)")
+        out["near"] = {"kernel": kname, "bound": "hbm", "achieved": ach,
                        "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": ach / PEAK_HBM_GBS,
                        "traffic": None if fp32 else measured_traffic("k_near_apply"), "avg_launch_ms": t,
                        "launches_per_pass": leaf_calls / steps, "algorithmic_bytes": nbytes}
@@ -409,6 +411,8 @@ def main():
             "stage_ms_per_step_near_on_the_fly": {k: v[0] / args.steps for k, v in res["stages_otf"].items()},
             "m2l_tflops": m2l_rate, "pairs_per_step": info.pairs_charge + info.pairs_dipole,
             "near_cache_build_ms": res["near_build_ms"],
+            "near_symmetric": bool(info.near_sym), "near_charge_values": info.near_charge_values,
+            "near_incoming_entries": info.near_incoming,
             "rooflines": roofs,
             "m2l_translations": info.m2l_translations,
         },
