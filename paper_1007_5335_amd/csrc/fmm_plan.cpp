@@ -671,9 +671,15 @@ ActiveSet &get_active(Context &ctx, FmmPlan &pl, int mask) {
                               hipMemcpyDeviceToHost, ctx.stream));
         YK_HIP(hipStreamSynchronize(ctx.stream));
     }
+    // Within a level the tiles of the four classes are interleaved: the k-th
+    // tiles of the classes hold the children at the four positions of (about)
+    // the same parents, so their V lists draw on the same source boxes, and
+    // consecutive tiles run on one XCD at about the same time (the launch
+    // maps consecutive tiles to one XCD), where the sources stay in its L2.
     std::vector<int32_t> mb;
     std::vector<int4> tiles, wtiles;
     for (int l = pl.lmin; l <= L; ++l) {
+        std::vector<int4> ct[4], cw[4];
         for (int cls = 0; cls < 4; ++cls) {
             const int64_t start = (int64_t)mb.size();
             for (int64_t b = pl.lev[l].begin; b < pl.lev[l].end; ++b) {
@@ -686,9 +692,27 @@ ActiveSet &get_active(Context &ctx, FmmPlan &pl, int mask) {
                 }
             }
             for (int64_t s = start; s < (int64_t)mb.size(); s += kTile)
-                tiles.push_back(make_int4(l, cls, (int)s, (int)std::min<int64_t>(kTile, (int64_t)mb.size() - s)));
+                ct[cls].push_back(make_int4(l, cls, (int)s, (int)std::min<int64_t>(kTile, (int64_t)mb.size() - s)));
             for (int64_t s = start; s < (int64_t)mb.size(); s += 2 * kTile)
-                wtiles.push_back(make_int4(l, cls, (int)s, (int)std::min<int64_t>(2 * kTile, (int64_t)mb.size() - s)));
+                cw[cls].push_back(make_int4(l, cls, (int)s, (int)std::min<int64_t>(2 * kTile, (int64_t)mb.size() - s)));
+        }
+        for (size_t k = 0;; ++k) {
+            bool any = false;
+            for (int cls = 0; cls < 4; ++cls)
+                if (k < ct[cls].size()) {
+                    tiles.push_back(ct[cls][k]);
+                    any = true;
+                }
+            if (!any) break;
+        }
+        for (size_t k = 0;; ++k) {
+            bool any = false;
+            for (int cls = 0; cls < 4; ++cls)
+                if (k < cw[cls].size()) {
+                    wtiles.push_back(cw[cls][k]);
+                    any = true;
+                }
+            if (!any) break;
         }
     }
     // sparse M2L when fewer than half of the V-list slots of the active boxes
