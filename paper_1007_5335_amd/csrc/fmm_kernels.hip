@@ -1608,13 +1608,14 @@ __global__ __launch_bounds__(NTB) void k_near_apply(
 
 // ---------------------------------------------------- symmetric near field --
 // The charge-to-charge values K0(|x - y|/alpha) are symmetric in the two
-// points.  When every leaf fits one item, the block of each unordered pair of
-// neighbouring leaves {A, B} is stored once, with the leaf of smaller index
+// points.  When no leaf holds more than 64 charges (and the charges are among
+// the targets), the block of each unordered pair of neighbouring leaves {A, B}
+// is stored once, with the leaf of smaller index
 // (its owner), and the owner's item applies it both ways: to its own charges
 // (a sum over B's charges) and, transposed, to B's charges (a sum over its
 // own), the latter written to B's incoming slot, which k_l2p adds.  A leaf's
-// own block is stored whole.  Every leaf holds at most 64 charges; they lead
-// its targets, so they all fall in its first item.  Per item (starting at a
+// own block is stored whole.  A leaf's charges lead its targets, so they all
+// fall in its first item.  Per item (starting at a
 // multiple of four entries) the charge values are, source major and target
 // minor: (1) the item's charges as targets against the charges of the owned
 // neighbours (the leaf itself and those of larger index, in U-list order),
