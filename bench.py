@@ -309,6 +309,85 @@ def heat_step_bench(args, yk, torch, W):
     return out
 
 
+def large_step_bench(args, yk, torch, W):
+    """s/time-step on the large adaptive set (about 2^24 cells of an adaptive
+    quadtree refined where a mixture of eight Gaussians is dense, weights the
+    cell areas plus each cell's own integral, 20 holes x 8192 nodes,
+    alpha = 1e-3, dt = alpha^2, u = c_k on hole k, u = 0 at t = 0): plain FP64 with the
+    previous-step guess, FP64 and mixed precision with the learned warm start
+    (trained on the first half of the steps); averages over the second half.
+    Opt-in (--large-steps): the tree takes seconds to build per context."""
+    c = W.config_c4()
+    b, volh = c["bnd"], c["vol"]
+    d = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+    region = torch.as_tensor(b.region(volh), dtype=torch.int32, device="cuda")
+    f = d(np.repeat(c["consts"], np.diff(b.offset)))
+    vol, w = d(volh), d(c["vol_w"])
+    bd = yk.Boundary.from_workload(b)
+    n_steps, half = args.large_steps, args.large_steps // 2
+    runs = (("fp64", yk.YK_PREC_FP64, False), ("fp64_learned", yk.YK_PREC_FP64, True),
+            ("mixed_learned", yk.YK_PREC_MIXED, True))
+    out, finals = {}, {}
+    for name, prec, learned in runs:
+        ctx = yk.yk_create(fmm_tol=1e-10, precision=prec)
+        ws = None
+        try:
+            if learned:
+                ws = yk.yk_ws_create(ctx, bd)
+                yk.yk_set_warm_start(ctx, ws)
+            u = torch.zeros(volh.shape[0], dtype=torch.float64, device="cuda")
+            B, un = torch.empty_like(u), torch.empty_like(u)
+            sig = torch.zeros(b.n, dtype=torch.float64, device="cuda")
+            times, iters, res0, used, train_s, first, phases, umax = [], [], [], [], None, None, [], []
+            for step in range(1, n_steps + 1):
+                if ws is not None and step == half + 1:
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    yk.yk_ws_train(ws)
+                    train_s = time.perf_counter() - t0
+                yk.yk_rhs_backward_euler(ctx, u, None, region, c["consts"], c["dt"], B)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                st = yk.yk_heat_step(ctx, bd, vol, w, B, yk.HEAT_GRID_SELF_CELL, f, c["dt"], 1e-10, sig, un)
+                torch.cuda.synchronize()
+                dt_s = time.perf_counter() - t0
+                if step == 1:
+                    first = dt_s
+                print(f"large set {name} step {step}: {dt_s * 1e3:.1f} ms, {st.iters} iterations", file=sys.stderr,
+                      flush=True)
+                if step > half:
+                    times.append(dt_s)
+                    iters.append(st.iters)
+                    res0.append(st.res0)
+                    used.append(st.guess_used == 2)
+                    phases.append([st.ms[1], st.ms[4], st.ms[2], st.ms[3]])
+                umax.append(float(un.abs().max()))
+                u, un = un, u
+            finals[name] = u.cpu().numpy()
+        finally:
+            if ws is not None:
+                yk.yk_ws_destroy(ws)
+            yk.yk_destroy(ctx)
+        out[name] = {"s_per_step": float(np.mean(times)), "gmres_iters": float(np.mean(iters)),
+                     "initial_rel_residual": float(np.mean(res0)),
+                     "learned_guess_used": float(np.mean(used)) if learned else None, "train_s": train_s,
+                     "first_step_s": first,
+                     "phase_ms": dict(zip(("volume_to_nodes", "guess_selection", "density_solve",
+                                           "volume_assembly"), np.mean(phases, axis=0).tolist())),
+                     "u_max_abs_per_step": umax}
+    ref = finals["fp64"]
+    for name in finals:
+        out[name]["u_rel_diff_vs_fp64"] = float(np.max(np.abs(finals[name] - ref)) / np.max(np.abs(ref)))
+        out[name]["u_rel_l2_vs_fp64"] = float(np.linalg.norm(finals[name] - ref) / np.linalg.norm(ref))
+    out["speedup_mixed_learned_vs_fp64"] = out["fp64"]["s_per_step"] / out["mixed_learned"]["s_per_step"]
+    out["workload"] = (f"{n_steps} backward-Euler steps on the large adaptive set: {volh.shape[0]} adaptive cells "
+                       f"(refined by a mixture of 8 Gaussians), outer circle + 20 circular holes x 8192 nodes, "
+                       f"alpha=1e-3, dt=alpha^2, "
+                       f"GMRES tol 1e-10; network trained on steps 1-{half}, timing and iterations averaged over "
+                       f"steps {half + 1}-{n_steps}; the first step includes the tree builds")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -330,6 +409,9 @@ def main():
     ap.add_argument("--no-fp32-pass", action="store_true", help="skip the FP32 pass of the same workload")
     ap.add_argument("--heat-only", action="store_true",
                     help="only the time-stepping comparison (profiling runs); prints its JSON object")
+    ap.add_argument("--large-steps", type=int, default=0,
+                    help="only the time-stepping comparison on the large adaptive set, this many steps; "
+                         "prints its JSON object")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a plain 256 MiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -347,6 +429,9 @@ def main():
 
     if args.heat_only:
         print(json.dumps(heat_step_bench(args, yk, torch, W)), flush=True)
+        return
+    if args.large_steps > 0:
+        print(json.dumps(large_step_bench(args, yk, torch, W)), flush=True)
         return
     if args.calib_copy:
         # a fill (writes 256 MiB) and an elementwise multiply (reads 256 MiB,

@@ -27,7 +27,7 @@ import numpy as np
 __all__ = [
     "Curve", "Boundary", "circle", "ellipse", "make_boundary",
     "config_c0", "config_c1", "config_c2", "config_c3", "config_c4",
-    "small_fmm_case", "sample_targets",
+    "small_fmm_case", "sample_targets", "adaptive_cells",
 ]
 
 
@@ -263,25 +263,55 @@ def config_c3(m=1024, n_holes=10, n_nodes=2048, dt=1e-3, seed=3, n_outer=None):
                 u0=np.zeros(vol.shape[0]), grid=True)
 
 
+def _mixture_density(x, y, mu, sg):
+    """Density of an equal-weight mixture of isotropic Gaussians at (x, y)."""
+    p = np.zeros_like(x)
+    for g in range(len(sg)):
+        d2 = (x - mu[g, 0]) ** 2 + (y - mu[g, 1]) ** 2
+        p += np.exp(-d2 / (2 * sg[g] ** 2)) / (2 * np.pi * sg[g] ** 2)
+    return p / len(sg)
+
+
+def adaptive_cells(target, density, max_level=16):
+    """Square cells of an adaptive quadtree over the unit square: a cell of side
+    h is split while h > 1/sqrt(target * density(centre)) (and its level is
+    below max_level).  Returns the cell centres and sides."""
+    cx, cy = np.array([0.5]), np.array([0.5])
+    ox, oy, oh = [], [], []
+    for level in range(max_level + 1):
+        h = 2.0 ** -level
+        split = h * h * target * density(cx, cy) > 1.0
+        if level == max_level:
+            split[:] = False
+        ox.append(cx[~split])
+        oy.append(cy[~split])
+        oh.append(np.full(int((~split).sum()), h))
+        sx, sy, q = cx[split], cy[split], h / 4
+        if sx.size == 0:
+            break
+        cx = np.concatenate([sx - q, sx + q, sx - q, sx + q])
+        cy = np.concatenate([sy - q, sy - q, sy + q, sy + q])
+    return np.concatenate(ox), np.concatenate(oy), np.concatenate(oh)
+
+
 def config_c4(n_vol=1 << 24, n_holes=20, n_nodes=8192, alpha=1e-3, seed=4, n_gauss=8):
-    """Large adaptive set: mixture of n_gauss isotropic Gaussians (means
-    U[0.2,0.8]^2, widths log-uniform on [0.01, 0.1]), resampled inside the
-    unit square; weights 1/(N p(x)); n_holes circular holes r ~ U[0.01,0.05]."""
+    """Large adaptive set: the centres of about n_vol square cells of an
+    adaptive quadtree over the unit square, refined where a mixture of n_gauss
+    isotropic Gaussians (means U[0.2,0.8]^2, widths log-uniform on
+    [0.01, 0.1]) is dense (side about 1/sqrt(T p(x)), T set by a coarse trial
+    so that the count comes out near n_vol); weights the cell areas (the heat
+    step adds each cell's own integral); n_holes circular holes
+    r ~ U[0.01, 0.05]."""
     rng = np.random.default_rng(seed)
     mu = rng.uniform(0.2, 0.8, size=(n_gauss, 2))
     sg = np.exp(rng.uniform(math.log(0.01), math.log(0.1), size=n_gauss))
-    pts = np.empty((0, 2))
-    while pts.shape[0] < n_vol:
-        k = rng.integers(0, n_gauss, size=n_vol)
-        cand = mu[k] + sg[k, None] * rng.standard_normal((n_vol, 2))
-        ok = (cand >= 0).all(1) & (cand < 1).all(1)
-        pts = np.concatenate([pts, cand[ok]])
-    pts = np.ascontiguousarray(pts[:n_vol])
-    dens = np.zeros(n_vol)
-    for g in range(n_gauss):
-        d2 = ((pts - mu[g]) ** 2).sum(1)
-        dens += np.exp(-d2 / (2 * sg[g] ** 2)) / (2 * np.pi * sg[g] ** 2) / n_gauss
-    w = 1.0 / (n_vol * dens)
+    dens = lambda x, y: _mixture_density(x, y, mu, sg)
+    # the count grows about linearly with T once the cells are fine: a trial
+    # at 1/64 of the density sets the scale
+    n_trial = adaptive_cells(n_vol / 64.0, dens)[0].size
+    x, y, h = adaptive_cells(n_vol / 64.0 * n_vol / n_trial, dens)
+    pts = np.ascontiguousarray(np.stack([x, y], axis=1))
+    w = h * h
     curves = [circle((0.5, 0.5), 0.5, n_nodes, ccw=True)]
     placed = []
     while len(placed) < n_holes:
@@ -297,7 +327,7 @@ def config_c4(n_vol=1 << 24, n_holes=20, n_nodes=8192, alpha=1e-3, seed=4, n_gau
     bnd = make_boundary(curves)
     consts = np.concatenate([[0.0], rng.choice([-1.0, -0.5, 0.5, 1.0], size=n_holes)])
     return dict(name="c4", bnd=bnd, vol=pts, vol_w=w, consts=consts, alpha=alpha,
-                dt=alpha * alpha, grid=False)
+                dt=alpha * alpha, grid=True)
 
 
 def small_fmm_case(n_vol=4096, n_nodes=256, alpha=0.05, seed=11, n_holes=5, clustered=False):
