@@ -31,6 +31,7 @@ Context::~Context() {
     if (cap_stream) (void)hipStreamDestroy(cap_stream);
     if (ev_fork) (void)hipEventDestroy(ev_fork);
     if (ev_join) (void)hipEventDestroy(ev_join);
+    if (ev_col) (void)hipEventDestroy(ev_col);
     if (side) (void)hipStreamDestroy(side);
     if (gm_host) (void)hipHostFree(gm_host);
 }

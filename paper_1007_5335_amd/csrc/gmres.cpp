@@ -66,6 +66,7 @@ GmresResult gmres(Context &ctx, const Apply &A, int64_t n, const double *b, doub
     res.res0 = beta / bnorm;
 
     std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), y(m), hs(2 * 128 + 1);
+    if (!ctx.ev_col) YK_HIP(hipEventCreateWithFlags(&ctx.ev_col, hipEventDisableTiming));
     while (true) {
         if (beta <= tol * bnorm) {
             res.converged = true;
@@ -77,10 +78,15 @@ GmresResult gmres(Context &ctx, const Apply &A, int64_t n, const double *b, doub
         g[0] = beta;
         int k = 0;
         bool breakdown = false;
+        bool issued = false;   // the apply of V[k] is already on the stream
+        double rho = 0.25;     // residual reduction per iteration, as last seen
         for (; k < m && res.iters < max_iter; ++k) {
             double *vk = V + (int64_t)k * n;
-            A(vk, w);
-            res.matvecs++;
+            if (!issued) {
+                A(vk, w);
+                res.matvecs++;
+            }
+            issued = false;
             // CGS2 in three passes over w: partials of V^T w; h1 = V^T w,
             // w -= V h1, partials of V^T w and |w|^2; h2, w - V h2 and its
             // norm (|w|^2 - |h2|^2, V being orthonormal), the next basis
@@ -91,7 +97,19 @@ GmresResult gmres(Context &ctx, const Apply &A, int64_t n, const double *b, doub
             launch_arnoldi_pass(ctx, n, V, n, w, k + 1, P0, dscal, k + 1, true, P1);
             launch_arnoldi_finish(ctx, n, V, n, w, k + 1, P1, dscal + 128, dscal + 256, V + (int64_t)(k + 1) * n,
                                   dscal, host);
-            YK_HIP(hipStreamSynchronize(ctx.stream));
+            YK_HIP(hipEventRecord(ctx.ev_col, ctx.stream));
+            // The next basis vector is already formed on the device, so its
+            // apply goes on the stream before the host waits for the column:
+            // the host's rotations then overlap the GPU's work instead of
+            // leaving it idle.  Skipped when, at the last seen rate, this
+            // column should meet the tolerance (a wasted apply costs more
+            // than the wait it hides).
+            if (k + 1 < m && res.iters + 1 < max_iter && rho * std::fabs(g[k]) > 2.0 * tol * bnorm) {
+                A(V + (int64_t)(k + 1) * n, w);
+                res.matvecs++;
+                issued = true;
+            }
+            YK_HIP(hipEventSynchronize(ctx.ev_col));
             std::copy(host, host + 2 * 128 + 1, hs.begin());
             double *col = &H[(size_t)k * (m + 1)];
             for (int i = 0; i <= k; ++i) col[i] = hs[i] + hs[128 + i];
@@ -111,8 +129,10 @@ GmresResult gmres(Context &ctx, const Apply &A, int64_t n, const double *b, doub
             sn[k] = den > 0 ? col[k + 1] / den : 0.0;
             col[k] = den;
             col[k + 1] = 0.0;
+            const double gprev = std::fabs(g[k]);
             g[k + 1] = -sn[k] * g[k];
             g[k] = cs[k] * g[k];
+            if (gprev > 0.0) rho = std::min(1.0, std::fabs(g[k + 1]) / gprev);
             if (hk1 <= 1e-300 * bnorm) {   // lucky breakdown: exact in this space
                 breakdown = true;
                 ++k;

@@ -144,6 +144,7 @@ struct Context {
     // fork/join events that order it against the context's stream
     hipStream_t side = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    hipEvent_t ev_col = nullptr;            // GMRES: an Arnoldi column is on the host
 
     // graph replays of the density operator (see BieGraph in capi.cpp)
     bool capturing = false;                 // a stream capture is in progress
