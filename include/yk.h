@@ -78,7 +78,11 @@ typedef struct {
                                pair of leaves (by default each pair block of
                                neighbouring leaves is stored once and applied
                                both ways, when every leaf holds at most 64
-                               charges) */
+                               charges);
+                               bit5: run the warm-start network's inference
+                               layer by layer (general matrix products and
+                               stored activations) instead of the fused
+                               kernel */
     int near_cache_mb;      /* device memory (MiB) a tree may spend on its cached
                                near-field interaction values; 0 = evaluate the
                                near-field kernels on every call */

@@ -316,7 +316,9 @@ GmresResult solve_density(Context &ctx, BoundaryData &bd, double alpha, const do
         // an FP32 operator resolves (about 1e-6 relative, so a residual far
         // above tol takes further sweeps)
         const double inner_tol = std::min(0.5, std::max(1e-6, 0.5 * tol * bnorm / rn));
-        GmresResult in = gmres(ctx, A32, n, r, delta, true, inner_tol, max_iter - tot.iters, ctx.opt.gmres_m);
+        // (|r|^2 is known on the host: no second reduction and wait)
+        GmresResult in = gmres(ctx, A32, n, r, delta, true, inner_tol, max_iter - tot.iters, ctx.opt.gmres_m,
+                               nullptr, -1.0, rn * rn);
         tot.iters += in.iters;
         tot.matvecs += in.matvecs;
         launch_axpby(ctx, n, 1.0, sigma, 1.0, delta, sigma);

@@ -30,6 +30,7 @@ struct WarmStart {
     DevBuf<float> params, adam_m, adam_v, grad;
     int64_t adam_t = 0;
     DevBuf<float> Xall, Tall, Xbat, Tbat, h1, h2, d1, d2, yb, dyb, part, cpart, lpart;
+    DevBuf<float> wt;                     // transposed hidden-layer weights for the fused inference
     DevBuf<int32_t> brows;
     DevBuf<double> scal, dtmp, fscale;
     std::vector<std::unique_ptr<Obs>> obs;
@@ -40,6 +41,9 @@ struct WarmStart {
     double train();
     void predict(const double *g_next, double *out);
     void forward(int64_t rows, const float *X, float *y);
+    // the same outputs without activation arrays: both hidden layers of a
+    // block of rows in one kernel (when the sizes are the default ones)
+    void forward_fused(int64_t rows, const float *X, float *y);
     double loss_grad(int64_t rows, const float *X, const float *T, float *G);
 
   private:

@@ -384,6 +384,108 @@ __global__ void k_gather_rows(int64_t nb, int Fp, const int32_t *__restrict__ ro
     if (f == 0) Tb[r] = T[src];
 }
 
+// ------------------------------------------------------- fused inference --
+// Inference over many rows: a workgroup of four wavefronts takes kPredRows rows
+// through both hidden layers on the matrix cores and writes one output per
+// row; the first layer's activations stay in LDS.  Wavefront w owns columns
+// 64 w .. 64 w + 63 of both layers.  Weights are read transposed (WT[k][col],
+// so a fragment's sixteen columns are contiguous).
+//   v_mfma_f32_16x16x4f32: lane l holds A[l%16][l/16], B[l/16][l%16];
+//   C rows 4(l/16) + r, column l%16.
+// LDS row strides are 4 more than a multiple of 64 words, so the sixteen rows
+// and four k of a fragment read fall on distinct banks.
+constexpr int kPredRows = 32;
+
+template <int FP, int H>
+__global__ __launch_bounds__(256) void k_mlp_predict(int64_t rows, const float *__restrict__ X,
+                                                     const float *__restrict__ W1T, const float *__restrict__ b1,
+                                                     const float *__restrict__ W2T, const float *__restrict__ b2,
+                                                     const float *__restrict__ w3, const float *__restrict__ b3,
+                                                     float *__restrict__ y) {
+    static_assert(H == 256 && FP % 4 == 0, "four wavefronts of 64 columns");
+    constexpr int SX = (FP + 59) / 64 * 64 + 4, SH = H + 4;
+    constexpr int RT = kPredRows / 16;
+    __shared__ float xs[kPredRows * SX];
+    __shared__ float hs[kPredRows * SH];
+    __shared__ float ys[4][kPredRows];
+    const int tid = threadIdx.x, w = tid >> 6, l = tid & 63, lr = l & 15, lk = l >> 4;
+    const int64_t r0 = (int64_t)blockIdx.x * kPredRows;
+    for (int e = tid; e < kPredRows * FP; e += 256) {
+        const int r = e / FP, k = e % FP;
+        xs[r * SX + k] = r0 + r < rows ? X[(r0 + r) * FP + k] : 0.f;
+    }
+    __syncthreads();
+    const int c0 = 64 * w;
+    f4v acc[RT][4];
+    auto clear = [&]() {
+#pragma unroll
+        for (int i = 0; i < RT; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) acc[i][j] = f4v{0.f, 0.f, 0.f, 0.f};
+    };
+    // acc += A[rows][k] WT[k][cols] over k < K, A in LDS with row stride S
+    auto layer = [&](const float *As, int S, const float *WT, int K) {
+        for (int k0 = 0; k0 < K; k0 += 4) {
+            const int k = k0 + lk;
+            float a[RT], b[4];
+#pragma unroll
+            for (int i = 0; i < RT; ++i) a[i] = As[(16 * i + lr) * S + k];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) b[j] = WT[(int64_t)k * H + c0 + 16 * j + lr];
+#pragma unroll
+            for (int i = 0; i < RT; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], b[j], acc[i][j], 0, 0, 0);
+        }
+    };
+    clear();
+    layer(xs, SX, W1T, FP);
+#pragma unroll
+    for (int i = 0; i < RT; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int col = c0 + 16 * j + lr;
+            const float bb = b1[col];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) hs[(16 * i + 4 * lk + r) * SH + col] = tanhf(acc[i][j][r] + bb);
+        }
+    __syncthreads();
+    clear();
+    layer(hs, SH, W2T, H);
+    // this wavefront's share of sum_col tanh(z + b2[col]) w3[col], then the
+    // sixteen lanes of each row group and the four wavefronts
+    float part[RT][4];
+#pragma unroll
+    for (int i = 0; i < RT; ++i)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            float sacc = 0.f;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int col = c0 + 16 * j + lr;
+                sacc += tanhf(acc[i][j][r] + b2[col]) * w3[col];
+            }
+#pragma unroll
+            for (int m = 8; m >= 1; m >>= 1) sacc += __shfl_xor(sacc, m, 16);
+            part[i][r] = sacc;
+        }
+    if (lr == 0)
+#pragma unroll
+        for (int i = 0; i < RT; ++i)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) ys[w][16 * i + 4 * lk + r] = part[i][r];
+    __syncthreads();
+    if (tid < kPredRows && r0 + tid < rows) y[r0 + tid] = ((ys[0][tid] + ys[1][tid]) + (ys[2][tid] + ys[3][tid])) + b3[0];
+}
+
+// WT[k][col] = W[col][k] for a [cols][K] block (column-major weights)
+__global__ void k_transpose_w(int cols, int K, const float *__restrict__ W, float *__restrict__ WT) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (int64_t)cols * K) return;
+    const int k = (int)(e / cols), col = (int)(e % cols);
+    WT[e] = W[(int64_t)col * K + k];
+}
+
 }  // namespace
 
 // --------------------------------------------------------------- host side --
@@ -489,6 +591,23 @@ void WarmStart::forward(int64_t rows, const float *X, float *y) {
     check_launch(ctx, "k_rowdot");
 }
 
+void WarmStart::forward_fused(int64_t rows, const float *X, float *y) {
+    if (H != 256 || Fp != kFp) {   // (other widths: the layer-by-layer products)
+        forward(rows, X, y);
+        return;
+    }
+    const float *P = params.p;
+    float *W1T = wt.ensure((size_t)H * Fp + (size_t)H * H), *W2T = W1T + (size_t)H * Fp;
+    hipLaunchKernelGGL(k_transpose_w, dim3(nblk((int64_t)H * Fp, 256)), dim3(256), 0, ctx.stream, H, Fp, P + o_W1,
+                       W1T);
+    hipLaunchKernelGGL(k_transpose_w, dim3(nblk((int64_t)H * H, 256)), dim3(256), 0, ctx.stream, H, H, P + o_W2,
+                       W2T);
+    check_launch(ctx, "k_transpose_w");
+    hipLaunchKernelGGL((k_mlp_predict<kFp, 256>), dim3(nblk(rows, kPredRows)), dim3(256), 0, ctx.stream, rows, X,
+                       W1T, P + o_b1, W2T, P + o_b2, P + o_w3, P + o_b3, y);
+    check_launch(ctx, "k_mlp_predict");
+}
+
 double WarmStart::loss_grad(int64_t rows, const float *X, const float *T, float *G) {
     float *P = params.p;
     float *y = yb.ensure(rows), *dy = dyb.ensure(rows);
@@ -585,7 +704,8 @@ void WarmStart::predict(const double *g_next, double *out) {
     double *fs = fscale.ensure(8);
     features(a.s.p, b.s.p, a.g.p, b.g.p, g_next, X, fs);
     float *y = yb.ensure(std::max<int64_t>(n, (int64_t)opt.batch));
-    forward(n, X, y);
+    if (ctx.opt.debug_flags & 32) forward(n, X, y);
+    else forward_fused(n, X, y);
     hipLaunchKernelGGL(k_apply_pred, dim3(nblk(n, 256)), dim3(256), 0, ctx.stream, n, a.s.p, b.s.p, y, fs, out);
     check_launch(ctx, "k_apply_pred");
 }

@@ -49,6 +49,41 @@ def test_mlp_loss_and_gradients_vs_fp64(yk):
         assert err < 2e-4, (a, b, err)
 
 
+def test_fused_inference_matches_layered(yk):
+    """The fused inference kernel (both hidden layers of a block of 32 rows in
+    one kernel, no activation arrays) gives the predictions of the
+    layer-by-layer products (debug_flags bit 5), whose forward pass the test
+    above ties to FP64; 1200 nodes make 37 full blocks and a partial one."""
+    import torch
+    cfg = W.config_c0(n_nodes=600, m=8)
+    b = cfg["bnd"]
+    ctx = yk.yk_create()
+    bd = yk.Boundary.from_workload(b)
+    ws = yk.yk_ws_create(ctx, bd, hidden=256)
+    try:
+        n, H, Fp = yk.yk_ws_num_params(ws)
+        rng = np.random.default_rng(11)
+        yk.yk_ws_set_params(ws, dev((rng.standard_normal(n) * 0.08).astype(np.float32), torch.float32))
+        for _ in range(2):
+            yk.yk_ws_observe(ws, dev(rng.standard_normal(b.n)), dev(rng.standard_normal(b.n)))
+        g_next = dev(rng.standard_normal(b.n))
+        outs = {}
+        for flags in (0, 32):
+            opt = yk.yk_default_options()
+            opt.debug_flags = flags
+            yk.yk_set_options(ctx, opt)
+            o = torch.empty(b.n, dtype=torch.float64, device="cuda")
+            print(f"warm-start prediction, debug_flags {flags}", flush=True)
+            yk.yk_ws_predict(ws, g_next, o)
+            torch.cuda.synchronize()
+            outs[flags] = host(o)
+    finally:
+        yk.yk_ws_destroy(ws)
+        yk.yk_destroy(ctx)
+    assert np.all(np.isfinite(outs[0]))
+    assert np.linalg.norm(outs[0] - outs[32]) <= 1e-5 * np.linalg.norm(outs[32])
+
+
 def _run_loop(yk, cfg, n_steps, train_at=None, ws_opts=None, garbage=False, precision=0):
     import torch
     b = cfg["bnd"]
