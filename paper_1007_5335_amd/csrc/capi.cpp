@@ -624,18 +624,19 @@ yk_status yk_heat_step(yk_ctx ctx, const yk_boundary *bnd, int64_t n_vol, const 
                 A64(x, rv);
                 launch_axpby(c, nb, 1.0, b, -1.0, rv, rv);
             }
-            launch_multi_dot(c, nb, 1, rv, nb, rv, d);
+            if (d) launch_multi_dot(c, nb, 1, rv, nb, rv, d);
         };
         if (learned) {
             c.warm->predict(gN, sml);
-            resid_enqueue(sml, rml, false, ds);
+            resid_enqueue(sml, rml, false, nullptr);
         }
         // the previous density's residual: from the memo when it applies (a
         // changed density is caught below), else by an operator application
         // when the learned guess needs it for comparison
-        if (memo_key) resid_enqueue(sigma_io, rprev, true, ds + 1);
-        else if (learned) resid_enqueue(sigma_io, rprev, false, ds + 1);
-        launch_multi_dot(c, nb, 1, b, nb, b, ds + 2);
+        if (memo_key) resid_enqueue(sigma_io, rprev, true, nullptr);
+        else if (learned) resid_enqueue(sigma_io, rprev, false, nullptr);
+        // the three squared norms in one reduction
+        launch_sumsq3(c, nb, learned ? rml : nullptr, (memo_key || learned) ? rprev : nullptr, b, ds);
         double *hsc = pinned_scalars(c) + 400;
         YK_HIP(hipMemcpyAsync(hsc, ds, 3 * sizeof(double), hipMemcpyDeviceToHost, c.stream));
         if (dflag) YK_HIP(hipMemcpyAsync(hsc + 3, dflag, sizeof(int), hipMemcpyDeviceToHost, c.stream));

@@ -37,6 +37,23 @@ __global__ __launch_bounds__(kRedBlock) void k_multi_dot(int64_t n, const double
     if (threadIdx.x == 0) partial[(int64_t)v * nchunk + c] = s;
 }
 
+// partial[v * nchunk + c] = sum over chunk c of x_v[i]^2 for v = 0, 1, 2 (a
+// null vector gives zeros); the chunks are those of k_multi_dot
+__global__ __launch_bounds__(kRedBlock) void k_sumsq3(int64_t n, const double *__restrict__ x0,
+                                                      const double *__restrict__ x1,
+                                                      const double *__restrict__ x2,
+                                                      double *__restrict__ partial) {
+    __shared__ double sh[kRedBlock / 64];
+    const int v = blockIdx.y, c = blockIdx.x, nchunk = gridDim.x;
+    const double *x = v == 0 ? x0 : v == 1 ? x1 : x2;
+    double acc = 0.0;
+    if (x)
+        for (int64_t i = (int64_t)c * kRedBlock + threadIdx.x; i < n; i += (int64_t)nchunk * kRedBlock)
+            acc += x[i] * x[i];
+    const double s = block_sum(acc, sh);
+    if (threadIdx.x == 0) partial[(int64_t)v * nchunk + c] = s;
+}
+
 __global__ void k_reduce_rows2(int nv, int nchunk, const double *__restrict__ partial,
                                double *__restrict__ h) {
     const int v = blockIdx.x * blockDim.x + threadIdx.x;
@@ -264,6 +281,16 @@ void launch_multi_dot(Context &ctx, int64_t n, int nv, const double *V, int64_t 
     check_launch(ctx, "k_multi_dot");
     hipLaunchKernelGGL(k_reduce_rows2, dim3(nblk(nv, 64)), dim3(64), 0, ctx.stream, nv, nchunk, part,
                        h);
+    check_launch(ctx, "k_reduce_rows");
+}
+
+void launch_sumsq3(Context &ctx, int64_t n, const double *x0, const double *x1, const double *x2, double *h) {
+    int nchunk = (int)std::min<int64_t>(kMaxChunks, (n + 4 * kRedBlock - 1) / (4 * kRedBlock));
+    if (nchunk < 1) nchunk = 1;
+    double *part = ctx.partial.ensure((size_t)kMaxChunks * 128);
+    hipLaunchKernelGGL(k_sumsq3, dim3(nchunk, 3), dim3(kRedBlock), 0, ctx.stream, n, x0, x1, x2, part);
+    check_launch(ctx, "k_sumsq3");
+    hipLaunchKernelGGL(k_reduce_rows2, dim3(1), dim3(64), 0, ctx.stream, 3, nchunk, part, h);
     check_launch(ctx, "k_reduce_rows");
 }
 

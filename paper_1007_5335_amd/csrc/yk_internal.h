@@ -205,6 +205,8 @@ void launch_boundary_prep(Context &ctx, int64_t n, int n_curves, const int64_t *
 // h[k] = sum_i V[k*ld + i] * x[i], k < nv  (result on device at h)
 void launch_multi_dot(Context &ctx, int64_t n, int nv, const double *V, int64_t ld,
                       const double *x, double *h);
+// h[v] = |x_v|^2 for v = 0, 1, 2 (a null vector gives 0), in one reduction
+void launch_sumsq3(Context &ctx, int64_t n, const double *x0, const double *x1, const double *x2, double *h);
 // x -= sum_k h[k] V[k*ld + i]
 // Arnoldi step in passes (see kernels_blas.hip): w -= sum_{v<nsub} h_v V_v with
 // h summed from the partials psub of the previous pass (stored to hsub_out),
