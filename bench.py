@@ -14,10 +14,17 @@ The JSON line carries:
   config       workload, p, leaf size, relative error over 1000 sampled targets
                against FP64 direct sums on the GPU, and over 100 of them against
                the CPU oracle
-  roofline     the dominant kernel (near field + local evaluation) against the
-               FP64 vector peak, from HIP events recorded around its launches
+  roofline     the dominant kernel (M2L on the FP64 matrix cores) against its
+               peak, from HIP events recorded around its launches; the config's
+               `rooflines` add the cached near field (HBM) and the near field
+               evaluated on the fly (FP64 vector units)
   cpu_baseline the CPU oracle's direct sums at the sampled targets
-  time_step    s/time-step of the backward-Euler heat step, plain FP64 vs mixed
+  time_step    s/time-step of the backward-Euler heat step on the 1024^2 grid,
+               plain FP64 vs FP64 and mixed precision with the learned guess
+
+Opt-in modes that print their own JSON object instead: --heat-only (the
+time-step comparison alone) and --large-steps K (the same comparison over K
+steps of the large adaptive set, about 2^24 cells; the tree takes seconds).
 """
 from __future__ import annotations
 
