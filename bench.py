@@ -469,8 +469,8 @@ def main():
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU only: this build runs the FMM on a single MI355X "
-              "(the multi-GPU decomposition is a design, not an implementation); use --gpus 1",
+        print("bench.py measures one GPU only: the FMM runs on a single MI355X "
+              "(its multi-GPU decomposition is described, not implemented); use --gpus 1",
               file=sys.stderr)
         sys.exit(2)
     import torch
