@@ -265,10 +265,10 @@ __global__ __launch_bounds__(64) void k_p2m(
             if (k < nk) M[b * Pp + gl + 16 * k] = gl + 16 * k < P ? macc[k] : 0.0;
 }
 
-// P2M with LPL lanes per leaf (4: a DPP quad; 16: a row) for a compile-time
+// P2M with LPL lanes per leaf (4: a DPP quad; 32: half a wavefront) for a compile-time
 // order PO: each lane takes every LPL-th point of its leaf and accumulates all
 // 2p+1 outputs in registers; the lanes' partial sums are combined at the end
-// (DPP steps for a quad, shuffles for a row).  Per point: F_n downwards
+// (DPP steps for a quad, shuffles otherwise).  Per point: F_n downwards
 // (G_n = F_n(y)/F_n(Y) in registers), then the terms with the powers of
 // conj(z) upwards.
 template <int PO, int LPL>
@@ -2030,8 +2030,19 @@ __global__ __launch_bounds__(256) void k_l2p(
     if (t >= n) return;
     const int set = (t >= toff1) + (t >= toff2);
     if (!((mask >> set) & 1)) return;
-    const int64_t b = leaf_base + pleaf[t];
+    const int32_t lb = pleaf[t];
+    const int64_t b = leaf_base + lb;
     const double *Lb = Lc + b * Pp;
+    // the incoming slots of the symmetric near field (charge targets): their
+    // indices are read before the series, which hides the loads behind it
+    int32_t n_in = 0, n0 = 0;
+    int64_t in_base = 0;
+    if (set == 0 && inc) {
+        const int32_t s0 = lrange[lb * 6];
+        n0 = lrange[lb * 6 + 1] - s0;
+        in_base = inc_base[lb] + (t - s0);
+        n_in = inc_cnt[lb];
+    }
     const double wx = (px[t] - bcx[b]) * inv_alpha, wy = (py[t] - bcy[b]) * inv_alpha;
     const double yv = 0.25 * (wx * wx + wy * wy);
     const double zx = wx * invR, zy = wy * invR;
@@ -2052,13 +2063,9 @@ __global__ __launch_bounds__(256) void k_l2p(
     const double F0 = F1 + yv * F2 * t_cnn[0];
     // near field + far field, written straight to the caller's array of the set
     double v = outs[t] + (Lb[0] * F0 * t_ify[0] + 2.0 * (sr * zx - si * zy)) * kInv2Pi;
-    if (set == 0 && inc) {
-        // symmetric near field: the charges of the neighbours that own the
-        // pair blocks with this leaf, one incoming slot per owner
-        const int32_t lb = pleaf[t], s0 = lrange[lb * 6], n0 = lrange[lb * 6 + 1] - s0;
-        const double *ip = inc + inc_base[lb] + (t - s0);
-        for (int k = 0; k < inc_cnt[lb]; ++k) v += ip[(int64_t)k * n0];
-    }
+    // symmetric near field: the charges of the neighbours that own the pair
+    // blocks with this leaf, one incoming slot per owner
+    for (int k = 0; k < n_in; ++k) v += inc[in_base + (int64_t)k * n0];
     double *o = set == 0 ? out0 : set == 1 ? out1 : out2;
     const int32_t i = perm[t];
     if (set == 1 && bx)   // double-layer operator: x - 2 (DL + diagonal limit)
@@ -2281,17 +2288,17 @@ void fmm_run(Context &ctx, FmmPlan &pl, const double *q, const double *dn, doubl
                   : p == 8 ? k_p2m_quad<8, 4> : p == 12 ? k_p2m_quad<12, 4> : p == 16 ? k_p2m_quad<16, 4>
                   : p == 20 ? k_p2m_quad<20, 4> : p == 24 ? k_p2m_quad<24, 4> : p == 28 ? k_p2m_quad<28, 4>
                   : p == 31 ? k_p2m_quad<31, 4> : nullptr;
-        auto row = p == 8 ? k_p2m_quad<8, 16> : p == 12 ? k_p2m_quad<12, 16> : p == 16 ? k_p2m_quad<16, 16>
-                 : p == 20 ? k_p2m_quad<20, 16> : p == 24 ? k_p2m_quad<24, 16> : p == 28 ? k_p2m_quad<28, 16>
-                 : p == 31 ? k_p2m_quad<31, 16> : nullptr;
+        auto row = p == 8 ? k_p2m_quad<8, 32> : p == 12 ? k_p2m_quad<12, 32> : p == 16 ? k_p2m_quad<16, 32>
+                 : p == 20 ? k_p2m_quad<20, 32> : p == 24 ? k_p2m_quad<24, 32> : p == 28 ? k_p2m_quad<28, 32>
+                 : p == 31 ? k_p2m_quad<31, 32> : nullptr;
         auto half = p == 8 ? k_p2m_half<8> : p == 12 ? k_p2m_half<12> : p == 16 ? k_p2m_half<16>
                   : p == 20 ? k_p2m_half<20> : p == 24 ? k_p2m_half<24> : p == 28 ? k_p2m_half<28>
                   : p == 31 ? k_p2m_half<31> : nullptr;
         const size_t leaf_m_bytes = (size_t)pl.nleaf * Pp * sizeof(double);
         // the leaves that hold dipoles (few, but their points are dense along
-        // the curves): sixteen lanes per leaf; charges too unless add_only
+        // the curves): 32 lanes per leaf; charges too unless add_only
         auto dipole_leaves = [&](int with_q, int add_only, hipStream_t st) {
-            hipLaunchKernelGGL(row, dim3((unsigned)((pl.n_dleaves + 3) / 4)), dim3(64), tabs, st,
+            hipLaunchKernelGGL(row, dim3((unsigned)((pl.n_dleaves + 1) / 2)), dim3(64), tabs, st,
                                leaf_base, pl.n_dleaves, pl.lrange.p, pl.bcx.p, pl.bcy.p, pl.px.p, pl.py.p, qs,
                                dns, pl.toff[1], with_q, 1, inv_alpha, 1.0 / pl.lev[L].R, pl.invFY.p + L * lvl,
                                pl.dipa.p + L * lvl, pl.dipb.p + L * lvl, pl.cnn.p, pl.serc.p, pl.nser, p, Pp,
