@@ -134,8 +134,7 @@ struct FmmPlan {
     DevBuf<int32_t> pleaf;             // [N] leaf (level-local index) of every sorted point
     DevBuf<int32_t> dleaves;           // leaves (level-local) that hold dipole sources
     int64_t n_dleaves = 0;
-    DevBuf<double> Mq_keep;            // leaf multipoles of a charges-only pass (keep_charge_m)
-    bool mq_kept = false;
+    bool mq_kept = false;              // M's leaf level holds a charges-only pass's multipoles (keep_charge_m)
     // cached P2M rows: per charge [Pp], per dipole [2][Pp] (built on first use)
     DevBuf<double> p2m_rq, p2m_rd, p2m_gs;
     bool p2m_rows_built = false;

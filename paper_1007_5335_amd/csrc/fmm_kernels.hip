@@ -2096,7 +2096,10 @@ void fmm_run(Context &ctx, FmmPlan &pl, const double *q, const double *dn, doubl
     if (!mask) return;
     const int64_t n0 = pl.toff[1] - pl.toff[0], n1 = pl.toff[2] - pl.toff[1];
     if (bie && !bie->sigma) bie = nullptr;
-    if (keep_charge_m == 1) pl.mq_kept = false;   // (set again once this pass has kept them)
+    // The charges' leaf multipoles of a charges-only pass stay in M for a
+    // later pass with the same charges (keep_charge_m 1, then 2); any other
+    // pass may overwrite them, and the reusing pass adds the dipoles to them.
+    if (keep_charge_m != 2) pl.mq_kept = false;
     const int has_q = (q && n0 > 0) ? 1 : 0, has_d = ((dn || bie) && n1 > 0) ? 1 : 0;
     const int L = pl.L, p = pl.p, P = pl.P, Pp = pl.Pp;
     const double inv_alpha = 1.0 / pl.alpha;
@@ -2294,7 +2297,6 @@ void fmm_run(Context &ctx, FmmPlan &pl, const double *q, const double *dn, doubl
         auto half = p == 8 ? k_p2m_half<8> : p == 12 ? k_p2m_half<12> : p == 16 ? k_p2m_half<16>
                   : p == 20 ? k_p2m_half<20> : p == 24 ? k_p2m_half<24> : p == 28 ? k_p2m_half<28>
                   : p == 31 ? k_p2m_half<31> : nullptr;
-        const size_t leaf_m_bytes = (size_t)pl.nleaf * Pp * sizeof(double);
         // the leaves that hold dipoles (few, but their points are dense along
         // the curves): 32 lanes per leaf; charges too unless add_only
         auto dipole_leaves = [&](int with_q, int add_only, hipStream_t st) {
@@ -2305,10 +2307,10 @@ void fmm_run(Context &ctx, FmmPlan &pl, const double *q, const double *dn, doubl
                                pl.M.p, pl.dleaves.p, add_only);
         };
         if (quad && half && keep_charge_m == 2 && pl.mq_kept && has_q) {
-            // the charges' leaf multipoles of the keeping pass, then the dipoles added
-            YK_HIP(hipMemcpyAsync(pl.M.p + leaf_base * Pp, pl.Mq_keep.p, leaf_m_bytes, hipMemcpyDeviceToDevice,
-                                  ctx.stream));
+            // the charges' leaf multipoles of the keeping pass are still in M:
+            // the dipoles are added to them
             if (has_d && pl.n_dleaves > 0) dipole_leaves(0, 1, ctx.stream);
+            pl.mq_kept = false;
         } else if (quad && half) {
             // charges in two halves of the orders on the leaves without
             // dipoles (all leaves when there are none), then the leaves with
@@ -2323,11 +2325,7 @@ void fmm_run(Context &ctx, FmmPlan &pl, const double *q, const double *dn, doubl
                                has_q, inv_alpha, 1.0 / pl.lev[L].R, pl.invFY.p + L * lvl, pl.cnn.p, pl.serc.p,
                                pl.nser, Pp, pl.M.p, split_d, pl.Lc.p, (int64_t)pl.nbox * Pp);
             lc_clear = true;
-            if (keep_charge_m == 1 && has_q && !has_d) {
-                YK_HIP(hipMemcpyAsync(pl.Mq_keep.ensure((size_t)pl.nleaf * Pp), pl.M.p + leaf_base * Pp,
-                                      leaf_m_bytes, hipMemcpyDeviceToDevice, ctx.stream));
-                pl.mq_kept = true;
-            }
+            if (keep_charge_m == 1 && has_q && !has_d) pl.mq_kept = true;
             if (split_d) dipole_leaves(has_q, 0, ctx.stream);
         } else if (quad) {
             hipLaunchKernelGGL(quad, dim3((unsigned)((pl.nleaf + 15) / 16)), dim3(64), tabs, ctx.stream,

@@ -25,10 +25,11 @@ struct SumProblem {
     const double *xy[3] = {nullptr, nullptr, nullptr};
     double alpha = 0.0;
     const BieFuse *bie = nullptr;   // (FMM backend only; see evaluate_sums)
-    // FMM backend: 1 = keep the leaf multipoles of this (charges-only) pass;
-    // 2 = the charges equal those of the keeping pass on the same tree: start
-    // from the kept multipoles and add only the dipoles' (both are hints: a
-    // pass that cannot use them computes everything)
+    // FMM backend: 1 = leave the leaf multipoles of this (charges-only) pass
+    // in place for a later pass; 2 = the charges equal those of that pass on
+    // the same tree, with no other pass on it in between: start from its
+    // multipoles and add only the dipoles' (both are hints: a pass that
+    // cannot use them computes everything)
     int keep_charge_m = 0;
 };
 
