@@ -61,6 +61,40 @@ def test_fmm_potential_vs_direct(yk, oracle_lib, alpha, leaf, clustered):
     assert ev < 1e-10 and eb < 1e-10
 
 
+@pytest.mark.parametrize("n_src,n_tgt", [(1, 0), (5, 0), (5, 7), (100, 0), (300, 33)])
+def test_fmm_tiny_trees(yk, oracle_lib, n_src, n_tgt):
+    """Degenerate trees: a single point (zero extent, no pair at all: the self
+    pair is left out, so the output is exactly zero), depth 0 and depth 1
+    (every pair in the near field, no expansion used), and the smallest sizes
+    with a far field, against the oracle's direct sums."""
+    import torch
+    rng = np.random.default_rng(100 + n_src)
+    src = rng.random((n_src, 2)); q = rng.standard_normal(n_src)
+    tgt = rng.random((n_tgt, 2)) * 1.2 - 0.1 if n_tgt else None
+    n_out = n_tgt if n_tgt else n_src
+    ctx = _ctx(yk, leaf_size=64, fmm_tol=1e-10, debug_flags=1)
+    try:
+        print(f"case n_src={n_src} n_tgt={n_tgt}", flush=True)
+        out = torch.full((n_out,), float("nan"), dtype=torch.float64, device="cuda")
+        yk.yk_volume_potential(ctx, dev(src), dev(q), dev(tgt) if n_tgt else None, 0.07, out)
+        torch.cuda.synchronize()
+        info = yk.yk_plan_info_get(ctx, 2)   # (the stand-alone sums' tree)
+    finally:
+        yk.yk_destroy(ctx)
+    got = host(out)
+    print(f"  leaf level {info.leaf_level}, far field from level {info.lmin}", flush=True)
+    if n_src + n_tgt <= 64:
+        assert info.leaf_level == 0
+    assert np.all(np.isfinite(got))
+    if n_src == 1 and not n_tgt:
+        assert np.all(got == 0.0)
+        return
+    ref = oracle_lib.volume_sum(src, q, 0.07, tgt_xy=tgt) if n_tgt else oracle_lib.volume_sum(src, q, 0.07)
+    err = rel_l2(got, ref)
+    print(f"  rel l2 err {err:.2e}", flush=True)
+    assert err < 1e-10
+
+
 def test_fmm_volume_potential_separate_targets(yk, oracle_lib):
     import torch
     rng = np.random.default_rng(8)
