@@ -58,7 +58,10 @@ enum {
 typedef struct {
     int precision;          /* YK_PREC_* */
     double fmm_tol;         /* target relative accuracy of the sums; picks p when p == 0 */
-    int p;                  /* expansion order (terms -p..p); 0 = derived from fmm_tol */
+    int p;                  /* expansion order (terms -p..p), 0..31; 0 = derived from
+                               fmm_tol.  The order used is the smallest of 8, 12,
+                               16, 20, 24, 28, 31 not below p (yk_plan_info.p);
+                               p > 31 is rejected (YK_ERR_ARG) */
     int leaf_size;          /* target mean number of points per leaf box */
     int direct;             /* 1 = all sums by O(N^2) direct summation */
     int gmres_m;            /* Krylov dimension before a restart */
@@ -253,7 +256,9 @@ yk_status yk_ws_train(yk_ws ws, double *loss);
 /* sigma_out [N] = the network's prediction of sigma^{N+1} from the last two
  * recorded steps and g_next [N]. */
 yk_status yk_ws_predict(yk_ws ws, const double *g_next, double *sigma_out);
-/* Attaches (ws != NULL) or detaches the warm start used by yk_heat_step. */
+/* Attaches (ws != NULL) or detaches the warm start used by yk_heat_step.
+ * yk_heat_step returns YK_ERR_ARG when the attached warm start was created
+ * for another boundary (other node array, curvature array or offsets). */
 yk_status yk_set_warm_start(yk_ctx ctx, yk_ws ws);
 /* Parameter access and one loss/gradient evaluation, for checking the
  * training kernels: params/grad are DEVICE FP32 arrays of yk_ws_num_params
@@ -264,6 +269,14 @@ yk_status yk_ws_get_params(yk_ws ws, float *params);
 yk_status yk_ws_set_params(yk_ws ws, const float *params);
 yk_status yk_ws_loss_grad(yk_ws ws, int64_t rows, const float *X, const float *t, float *grad,
                           double *loss);
+/* y [rows] device FP32 = the network's outputs for the feature rows X
+ * [rows][Fp] by the inference path yk_heat_step uses (the fused kernel, or
+ * layer by layer with debug_flags bit 5). */
+yk_status yk_ws_forward(yk_ws ws, int64_t rows, const float *X, float *y);
+/* One Adam step (Kingma & Ba: decays 0.9 and 0.999, eps 1e-8, the options'
+ * learning rate, bias corrections from the network's own step count, which
+ * yk_ws_train advances too) of the parameters on grad [n_params] (device FP32). */
+yk_status yk_ws_adam_step(yk_ws ws, const float *grad);
 
 /*
  * Introspection for measurement (not part of the method).
@@ -301,6 +314,14 @@ typedef struct {
                                    counting the zeros that pad rows to vectors) */
     int64_t near_incoming;    /* entries written to (and read back from) the incoming
                                  slots of the symmetric near field per evaluation */
+    int32_t p_initial;        /* order first derived from fmm_tol (= p when given) */
+    double order_check_err;   /* build-time order check: the largest error of the
+                                 sampled probe outputs at the order kept, relative to
+                                 each output (floored at a tenth of the samples' RMS);
+                                 -1 when no check ran (order given, or no far field).
+                                 When fmm_tol derives the order, the tree raises it
+                                 along 8, 12, 16, 20, 24, 31 until this error is at
+                                 most fmm_tol / 2, or the order reaches 31 */
 } yk_plan_info;
 
 enum {

@@ -3,7 +3,9 @@
 Plain numpy forward pass and backpropagation of
     y = w3 . tanh(W2 tanh(W1 x + b1) + b2) + b3,   loss = mean (y - t)^2,
 written from the chain rule, on the same flat parameter layout as the
-library (W1 [H][Fp], b1 [H], W2 [H][H], b2 [H], w3 [H], b3).
+library (W1 [H][Fp], b1 [H], W2 [H][H], b2 [H], w3 [H], b3), and one step of
+the Adam optimiser (Kingma & Ba, 2015: first and second moment estimates with
+decays b1, b2, each divided by (1 - b^t) to undo its zero start).
 """
 from __future__ import annotations
 
@@ -50,3 +52,13 @@ def loss_grad(p, H, Fp, X, t):
     g_b1 = d1.sum(0)
     g = np.concatenate([g_W1.ravel(), g_b1, g_W2.ravel(), g_b2, g_w3, [g_b3]])
     return float(np.mean((y - t) ** 2)), g
+
+
+def adam_step(p, g, m, v, t, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
+    """Step t (1-based) of Adam from moments m, v; returns (p, m, v)."""
+    p = np.asarray(p, dtype=np.float64); g = np.asarray(g, dtype=np.float64)
+    m = b1 * np.asarray(m, dtype=np.float64) + (1.0 - b1) * g
+    v = b2 * np.asarray(v, dtype=np.float64) + (1.0 - b2) * g * g
+    m_hat = m / (1.0 - b1 ** t)
+    v_hat = v / (1.0 - b2 ** t)
+    return p - lr * m_hat / (np.sqrt(v_hat) + eps), m, v

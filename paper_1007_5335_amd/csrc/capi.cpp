@@ -166,6 +166,7 @@ struct BieOperator {
         SumProblem pb;
         pb.n[1] = bd.n;
         pb.xy[1] = bd.xy;
+        pb.normal = bd.normal;
         pb.alpha = alpha;
         BieFuse f;
         f.w = bd.w.p;
@@ -189,6 +190,7 @@ struct BieOperator {
         SumProblem pb;
         pb.n[1] = bd.n;
         pb.xy[1] = bd.xy;
+        pb.normal = bd.normal;
         pb.alpha = alpha;
         FmmPlan &pl = get_plan(ctx, SLOT_BND, pb);
         for (auto &g : ctx.bie_graphs)
@@ -402,7 +404,7 @@ void yk_default_options(yk_options *opt) {
 }
 
 static bool valid_options(const yk_options *o) {
-    return o->precision >= 0 && o->precision <= 2 && o->p >= 0 && o->p <= 80 &&
+    return o->precision >= 0 && o->precision <= 2 && o->p >= 0 && o->p <= 31 &&
            o->leaf_size >= 1 && o->leaf_size <= 4096 && o->gmres_m >= 1 && o->gmres_m <= 120 &&
            o->near_cache_mb >= 0 &&
            (o->p > 0 || (o->fmm_tol > 0 && o->fmm_tol < 1));
@@ -504,6 +506,7 @@ yk_status yk_double_layer_apply(yk_ctx ctx, const yk_boundary *bnd, const double
         SumProblem pb;
         pb.n[1] = bd.n;
         pb.xy[1] = bd.xy;
+        pb.normal = bd.normal;
         pb.alpha = alpha;
         double *outs[3] = {nullptr, nullptr, nullptr};
         if (tgt_xy) {
@@ -572,8 +575,16 @@ yk_status yk_heat_step(yk_ctx ctx, const yk_boundary *bnd, int64_t n_vol, const 
         const int64_t nb = bd.n;
         const double alpha = std::sqrt(dt), a2 = dt;
         const SumPrec vprec = c.opt.precision == YK_PREC_FP32 ? SUM_FP32 : SUM_FP64;
-        // q = W B
-        double *q = c.ws_d.ensure(n_vol);   // ws_d is free until the solve
+        // the attached warm start must have been made for this boundary: its
+        // feature kernels read and write N-node arrays with its own offsets
+        if (c.warm) {
+            const WarmStart &ws = *c.warm;
+            YK_REQUIRE(ws.n == nb && ws.offsets == bd.offset && ws.kappa == bd.curvature && ws.xy == bd.xy,
+                       "the attached warm start was created for another boundary");
+        }
+        // q = W B, in a buffer of its own (the density solve below takes the
+        // shared workspaces and may reallocate them)
+        double *q = c.ws_q.ensure(n_vol);
         auto t0 = std::chrono::steady_clock::now();
         launch_mul(c, n_vol, vol_w, B, q);
         SumProblem pb;
@@ -581,6 +592,7 @@ yk_status yk_heat_step(yk_ctx ctx, const yk_boundary *bnd, int64_t n_vol, const 
         pb.xy[0] = vol_xy;
         pb.n[1] = nb;
         pb.xy[1] = bd.xy;
+        pb.normal = bd.normal;
         pb.alpha = alpha;
         // U^p on the nodes: b = -2 alpha^2 (f - V[q]/alpha^2) = -2 alpha^2 f + 2 V[q]
         double *vb = c.ws_e.ensure(nb);
@@ -669,7 +681,6 @@ yk_status yk_heat_step(yk_ctx ctx, const yk_boundary *bnd, int64_t n_vol, const 
         }
         // sigma
         auto t1 = std::chrono::steady_clock::now();
-        // the solver's operators use ws_a..ws_d, so q is formed again afterwards
         int outer = 0;
         bool asig_ok = false;
         GmresResult r = solve_density(c, bd, alpha, b, sigma_io, guess == 0, tol, 1000, &outer, r0,
@@ -680,11 +691,10 @@ yk_status yk_heat_step(yk_ctx ctx, const yk_boundary *bnd, int64_t n_vol, const 
         if (stats) stats->ms[2] = ms_since(t1);
         // u = (V[q] + DL[w sigma] + B C_self) / alpha^2 at the volume points
         auto t2 = std::chrono::steady_clock::now();
-        launch_mul(c, n_vol, vol_w, B, q);   // q again (ws_d was used by the solver)
         {
             double *outs[3] = {u_next, nullptr, nullptr};
             SumProblem pr = pb;
-            pr.keep_charge_m = (c.opt.debug_flags & 8) ? 0 : 2;   // q = W B again, equal to the first pass's
+            pr.keep_charge_m = (c.opt.debug_flags & 8) ? 0 : 2;   // the same charges q as the first pass
             BieFuse f;   // dipole vectors w sigma n, formed in the gather
             f.w = bd.w.p;
             f.sigma = sigma_io;
@@ -733,6 +743,7 @@ yk_status yk_fmm_potential(yk_ctx ctx, int64_t n_vol, const double *vol_xy, cons
         pb.xy[0] = vol_xy;
         pb.n[1] = bd.n;
         pb.xy[1] = bd.xy;
+        pb.normal = bd.normal;
         pb.alpha = alpha;
         // dn_j = d_j n_j, formed as the sum gathers its sources (no quadrature
         // weight: d is the full dipole strength)
@@ -860,6 +871,27 @@ yk_status yk_ws_loss_grad(yk_ws ws, int64_t rows, const float *X, const float *t
     });
 }
 
+yk_status yk_ws_forward(yk_ws ws, int64_t rows, const float *X, float *y) {
+    if (!ws) return YK_ERR_ARG;
+    return guarded(ws->owner, [&](Context &c) {
+        YK_REQUIRE(rows > 0 && rows < ((int64_t)1 << 31) && X && y, "invalid arguments");
+        if (c.opt.debug_flags & 32) ws->w->forward(rows, X, y);
+        else ws->w->forward_fused(rows, X, y);
+        YK_HIP(hipStreamSynchronize(c.stream));
+        return YK_OK;
+    });
+}
+
+yk_status yk_ws_adam_step(yk_ws ws, const float *grad) {
+    if (!ws) return YK_ERR_ARG;
+    return guarded(ws->owner, [&](Context &c) {
+        YK_REQUIRE(grad != nullptr, "grad is NULL");
+        ws->w->adam_step(grad);
+        YK_HIP(hipStreamSynchronize(c.stream));
+        return YK_OK;
+    });
+}
+
 yk_status yk_plan_info_get(yk_ctx ctx, int slot, yk_plan_info *info) {
     return guarded(ctx, [&](Context &c) {
         YK_REQUIRE(info != nullptr, "info is NULL");
@@ -877,6 +909,8 @@ yk_status yk_plan_info_get(yk_ctx ctx, int slot, yk_plan_info *info) {
         info->n_boxes = pl->nbox;
         info->n_leaves = pl->nleaf;
         info->build_ms = pl->build_ms;
+        info->p_initial = pl->calib_p0;
+        info->order_check_err = pl->calib_err;
         info->near_terms = pl->near_terms;
         info->nser = pl->nser;
         auto it = pl->active.find(pl->last_mask);

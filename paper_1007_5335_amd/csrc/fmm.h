@@ -50,6 +50,13 @@ struct ActiveSet {
     DevBuf<int4> m2l_ptiles;
     int n_ptiles = 0;
     DevBuf<int32_t> m2l_ptgt, m2l_psrc, m2l_piota;
+    // partial rows of M2L launches whose workgroups share output rows (sparse
+    // M2L; split slots on trees of few tiles), summed in a fixed order: for
+    // the sparse form, per target box (csr_tgt) its translations
+    // csr_rows[csr_off[t] .. csr_off[t+1]) in increasing index
+    DevBuf<double> m2l_slab;
+    DevBuf<int32_t> csr_tgt, csr_off, csr_rows;
+    int64_t n_csr_tgt = 0, n_ptrans = 0;
     std::vector<int64_t> l2l_begin, l2l_count;   // per level: active boxes (children) list slices
     DevBuf<int32_t> l2l_boxes;         // active boxes of levels lmin+1..L (level-major)
     std::vector<int> tile_begin, tile_count;     // per level: slice of m2l_tiles
@@ -152,6 +159,16 @@ struct FmmPlan {
     std::map<int, std::unique_ptr<ActiveSet>> active;   // by target mask
 
     double build_ms = 0;
+    // order check at build time (fmm_order.hip): the order first derived from
+    // the tolerance and the largest sampled error of the order kept (-1: not run)
+    int calib_p0 = 0;
+    double calib_err = -1.0;
+    int mask_all() const {
+        int m = 0;
+        for (int s = 0; s < 3; ++s)
+            if (toff[s + 1] > toff[s]) m |= 1 << s;
+        return m;
+    }
     bool fresh = false;
     uint64_t gen = 0;                  // unique per plan built in this process
     int last_mask = 0;
@@ -161,10 +178,21 @@ FmmPlan *plan_in_slot(Context &ctx, int slot);
 
 // tree.hip
 void build_tree(Context &ctx, FmmPlan &pl, const SumProblem &pb);
-// fmm_plan.cpp
-void build_lists_and_tables(Context &ctx, FmmPlan &pl, const std::vector<uint32_t> &keys);
+// fmm_plan.cpp: boxes and lists from the sorted keys, then the translation
+// operators and expansion tables of order p (rebuilt when p changes)
+void build_lists(Context &ctx, FmmPlan &pl, const std::vector<uint32_t> &keys);
+void build_tables(Context &ctx, FmmPlan &pl, int p);
 ActiveSet &get_active(Context &ctx, FmmPlan &pl, int mask);
+// expansion orders with kernels: the smallest one >= p (at most kMaxOrder)
+constexpr int kNumOrders = 7;
+constexpr int kOrders[kNumOrders] = {8, 12, 16, 20, 24, 28, 31};
+constexpr int kMaxOrder = 31;
+int supported_order(int p);
 int choose_order(double tol);
+
+// fmm_order.hip: raises the order derived from fmm_tol until sampled outputs
+// of probe strengths meet the tolerance (no-op when the order is given)
+void calibrate_order(Context &ctx, FmmPlan &pl, const SumProblem &pb);
 
 // fmm_kernels.hip
 // bie (optional): the double-layer operator fused in (dn is then unused)

@@ -46,7 +46,11 @@ FmmPlan &get_plan(Context &ctx, PlanSlot slot, const SumProblem &pb) {
     pl->opt_p = ctx.opt.p;
     pl->opt_leaf = ctx.opt.leaf_size;
     pl->opt_tol = ctx.opt.fmm_tol;
+    const auto t0 = std::chrono::steady_clock::now();
     build_tree(ctx, *pl, pb);
+    calibrate_order(ctx, *pl, pb);
+    pl->last_mask = 0;
+    pl->build_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     pl->fresh = true;
     ref = std::move(pl);
     return *ref;

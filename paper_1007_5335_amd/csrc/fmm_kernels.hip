@@ -689,113 +689,6 @@ __global__ __launch_bounds__(256) void k_p2m_apply(
     }
 }
 
-// ------------------------------------------------------------ M2M / L2L ---
-// Parent multipole from its children: M_b = sum_c S[pos(c)] M_c.
-__global__ __launch_bounds__(128) void k_m2m(int64_t pbegin, const int32_t *__restrict__ fchild,
-                                             const int32_t *__restrict__ nchild,
-                                             const uint32_t *__restrict__ code,
-                                             const double *__restrict__ S, int P, int Pp,
-                                             double *__restrict__ M) {
-    extern __shared__ double mc[];
-    const int64_t b = pbegin + blockIdx.x;
-    const int i = threadIdx.x;
-    double acc = 0.0;
-    const int c0 = fchild[b], nc = nchild[b];
-    for (int c = c0; c < c0 + nc; ++c) {
-        for (int k = i; k < Pp; k += blockDim.x) mc[k] = M[(int64_t)c * Pp + k];
-        __syncthreads();
-        const double *Sc = S + (size_t)(code[c] & 3u) * Pp * Pp;
-        if (i < P)
-            for (int j = 0; j < P; ++j) acc += Sc[(size_t)j * Pp + i] * mc[j];
-        __syncthreads();
-    }
-    if (i < Pp) M[b * Pp + i] = i < P ? acc : 0.0;
-}
-
-// Child local expansion from its parent: L_b += E[pos(b)] L_parent.
-__global__ __launch_bounds__(128) void k_l2l(const int32_t *__restrict__ boxes,
-                                             const int32_t *__restrict__ parent,
-                                             const uint32_t *__restrict__ code,
-                                             const double *__restrict__ E, int P, int Pp,
-                                             double *__restrict__ Lc) {
-    extern __shared__ double lp[];
-    const int64_t b = boxes[blockIdx.x];
-    const int64_t pa = parent[b];
-    const int i = threadIdx.x;
-    for (int k = i; k < Pp; k += blockDim.x) lp[k] = Lc[pa * Pp + k];
-    __syncthreads();
-    if (i < P) {
-        const double *Ec = E + (size_t)(code[b] & 3u) * Pp * Pp;
-        double acc = 0.0;
-        for (int j = 0; j < P; ++j) acc += Ec[(size_t)j * Pp + i] * lp[j];
-        Lc[b * Pp + i] += acc;
-    }
-}
-
-// -------------------------------------------------------------------- M2L ---
-// One block per tile of up to 16 target boxes of one level and one parity
-// class (so all share the same 27 offsets).  For each offset the Pp x Pp
-// operator is streamed through LDS in column chunks and applied to the 16
-// gathered multipoles.
-constexpr int kM2LTile = 16;
-constexpr int kM2LChunk = 32;
-__global__ __launch_bounds__(256) void k_m2l(const int4 *__restrict__ tiles, int tile0,
-                                             const int32_t *__restrict__ boxes,
-                                             const int32_t *__restrict__ vlist,
-                                             const int32_t *__restrict__ slot_oid,
-                                             const double *__restrict__ T, int P, int Pp,
-                                             const double *__restrict__ M, double *__restrict__ Lc) {
-    extern __shared__ double sm[];
-    double *Ts = sm;                               // kM2LChunk * Pp
-    double *Ms = sm + (size_t)kM2LChunk * Pp;      // 16 * Pp
-    const int4 tl = tiles[tile0 + blockIdx.x];
-    const int level = tl.x, cls = tl.y;
-    const int t = threadIdx.x;
-    for (int sub0 = 0; sub0 < tl.w; sub0 += kM2LTile) {
-    const int start = tl.z + sub0, count = min(kM2LTile, tl.w - sub0);
-    const int bb = t >> 4, r0 = t & 15;
-    const int nr = Pp / 16;
-    double acc[8];
-#pragma unroll
-    for (int r = 0; r < 8; ++r) acc[r] = 0.0;
-    const int64_t mybox = bb < count ? boxes[start + bb] : -1;
-    for (int slot = 0; slot < kNumV; ++slot) {
-        const int oid = slot_oid[cls * kNumV + slot];
-        const double *Tg = T + ((size_t)level * kNumOff + oid) * Pp * Pp;
-        for (int k = t; k < kM2LTile * Pp; k += 256) {
-            const int b2 = k / Pp, j = k - b2 * Pp;
-            double v = 0.0;
-            if (b2 < count) {
-                const int32_t src = vlist[(int64_t)boxes[start + b2] * kNumV + slot];
-                if (src >= 0) v = M[(int64_t)src * Pp + j];
-            }
-            Ms[k] = v;
-        }
-        for (int j0 = 0; j0 < P; j0 += kM2LChunk) {
-            const int jn = min(kM2LChunk, P - j0);
-            for (int k = t; k < jn * Pp; k += 256) Ts[k] = Tg[(size_t)j0 * Pp + k];
-            __syncthreads();
-            if (bb < count) {
-                const double *mrow = Ms + bb * Pp + j0;
-                for (int j = 0; j < jn; ++j) {
-                    const double mj = mrow[j];
-#pragma unroll
-                    for (int r = 0; r < 8; ++r)
-                        if (r < nr) acc[r] += Ts[(size_t)j * Pp + r0 + 16 * r] * mj;
-                }
-            }
-            __syncthreads();
-        }
-    }
-    if (mybox >= 0) {
-#pragma unroll
-        for (int r = 0; r < 8; ++r)
-            if (r < nr) Lc[mybox * Pp + r0 + 16 * r] += acc[r];
-    }
-    __syncthreads();
-    }
-}
-
 // ------------------------------------------------------------- M2L (MFMA) --
 // Matrix-core version: one workgroup (4 wavefronts) per tile of up to 64
 // target boxes of one level and parity class.  C (Pp x 64 local
@@ -857,7 +750,7 @@ __global__ __launch_bounds__(256) void k_tile_gemm(const int4 *__restrict__ tile
                                                    const T *__restrict__ Op, int64_t op_stride,
                                                    int level_shift, const TS *__restrict__ X,
                                                    int assign, int nparts, double *__restrict__ out,
-                                                   const int32_t *__restrict__ tgt, int atom) {
+                                                   const int32_t *__restrict__ tgt, double *__restrict__ slab) {
     constexpr bool SPLIT = SPLIT_REQ && PP > 16;   // (the host never asks for PP = 16)
     constexpr int NB = SPLIT ? PP / 16 - 1 : PP / 16;   // 16-row blocks on the matrix cores
     constexpr int SP = 16 * NB;                         // split-off index (SPLIT only)
@@ -877,9 +770,13 @@ __global__ __launch_bounds__(256) void k_tile_gemm(const int4 *__restrict__ tile
     __shared__ int32_t s_src[kMaxSlot * NC];
     using MF = Mfma<T>;
     // nparts > 1 (few tiles): the slots of a tile are shared among nparts
-    // workgroups, which add their partial sums atomically (assign must be 0).
-    // With tgt (sparse M2L) the tile's entries are translation indices: the
-    // source is src[entry], the result is added atomically to row tgt[entry].
+    // workgroups (assign must be 0).  With tgt (sparse M2L) the tile's
+    // entries are translation indices: the source is src[entry], the target
+    // is row tgt[entry].  In both cases several workgroups contribute to one
+    // output row, so each stores its result in a row of its own of slab
+    // (translation `entry`, or column j of workgroup bid: row bid * NC + j),
+    // which k_slab_reduce_* then add to the outputs in a fixed order: the
+    // sums do not depend on the order the workgroups run in.
     const int bid = xcd_remap(blockIdx.x, gridDim.x);
     const int part = bid % nparts;
     const int4 tl = tiles[tile0 + bid / nparts];
@@ -1038,52 +935,98 @@ __global__ __launch_bounds__(256) void k_tile_gemm(const int4 *__restrict__ tile
             rowacc[c] += __shfl_xor(rowacc[c], 32, 64);
         }
         if (colvalid[c]) {
-            double *o = out + boxj[c] * PP;
+            const bool to_slab = slab != nullptr;
+            const int store = to_slab || assign;
+            double *o = to_slab ? slab + (tgt ? (int64_t)boxes[start + jb[c]] : (int64_t)bid * NC + jb[c]) * PP
+                                : out + boxj[c] * PP;
 #pragma unroll
             for (int rt = 0; rt < NB; ++rt)
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
                     const int i = 16 * rt + MF::row(lane, q);
                     const double v = SPLIT ? (double)acc[c][rt][q] + (double)colacc[c][rt][q] : (double)acc[c][rt][q];
-                    if (nparts > 1 || atom) atomicAdd(o + i, v);
-                    else o[i] = assign ? v : o[i] + v;
+                    o[i] = store ? v : o[i] + v;
                 }
             if constexpr (SPLIT) {
-                if (g == 0) {
-                    if (nparts > 1 || atom) atomicAdd(o + SP, (double)rowacc[c]);
-                    else o[SP] = assign ? (double)rowacc[c] : o[SP] + (double)rowacc[c];
-                }
+                if (g == 0) o[SP] = store ? (double)rowacc[c] : o[SP] + (double)rowacc[c];
                 // padding entries SP + 1 .. PP - 1 stay zero for later readers
-                if (assign)
+                if (store)
                     for (int i = SP + 1 + g; i < PP; i += 4) o[i] = 0.0;
             }
         }
     }
 }
 
+// Fixed-order sums of the slab rows of k_tile_gemm into the outputs.
+// Sparse M2L: target box t of the list gets rows[off[t] .. off[t+1]) (its
+// translations in increasing index), one wavefront per target.
+__global__ __launch_bounds__(256) void k_slab_reduce_csr(int64_t ntgt, const int32_t *__restrict__ tgt,
+                                                         const int32_t *__restrict__ off,
+                                                         const int32_t *__restrict__ rows,
+                                                         const double *__restrict__ slab, int PP,
+                                                         double *__restrict__ out) {
+    const int64_t t = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int i = threadIdx.x & 63;
+    if (t >= ntgt || i >= PP) return;
+    double acc = 0.0;
+    for (int k = off[t]; k < off[t + 1]; ++k) acc += slab[(int64_t)rows[k] * PP + i];
+    double *o = out + (int64_t)tgt[t] * PP + i;
+    *o += acc;
+}
+
+// Split slots: column j of tile t gets the rows of its nparts workgroups in
+// part order; one workgroup per tile.
+__global__ __launch_bounds__(256) void k_slab_reduce_parts(const int4 *__restrict__ tiles, int tile0,
+                                                           const int32_t *__restrict__ boxes, int nparts, int NC,
+                                                           const double *__restrict__ slab, int PP,
+                                                           double *__restrict__ out) {
+    const int t = blockIdx.x;
+    const int4 tl = tiles[tile0 + t];
+    for (int e = threadIdx.x; e < tl.w * PP; e += 256) {
+        const int j = e / PP, i = e % PP;
+        double acc = 0.0;
+        for (int part = 0; part < nparts; ++part)
+            acc += slab[((int64_t)(t * nparts + part) * NC + j) * PP + i];
+        out[(int64_t)boxes[tl.z + j] * PP + i] += acc;
+    }
+}
+
+// Where the partial rows of a launch whose workgroups share output rows go,
+// and (sparse M2L) the fixed order in which they are summed.
+struct SlabPlan {
+    DevBuf<double> *buf = nullptr;
+    int64_t ntgt = 0;                           // sparse: targets with translations
+    const int32_t *tgt = nullptr, *off = nullptr, *rows = nullptr;
+};
+
 template <typename T, typename TS, int CB = 1>
 void launch_tile_gemm(Context &ctx, int P, int Pp, int ntiles, const int4 *tiles, int tile0,
                       const int32_t *boxes, int nslot, const int32_t *src, const int32_t *slot_op,
                       const T *Op, int64_t op_stride, int level_shift, const TS *X, int assign,
-                      double *out, const int32_t *tgt = nullptr) {
+                      double *out, const int32_t *tgt = nullptr, const SlabPlan *slab = nullptr,
+                      int64_t ntrans = 0) {
     if (ntiles <= 0) return;
-    const int atom = tgt ? 1 : 0;
     if (nslot < 1 || nslot > 27) throw Error{YK_ERR_INTERNAL, "tile GEMM supports 1..27 slots"};
     const bool split = Pp >= 32 && P == Pp - 15;
     // fewer tiles than compute units: share each tile's slots among up to 7
-    // workgroups (about 4 slots each) that accumulate atomically
-    const int nparts = (!assign && nslot >= 8 && ntiles < 256) ? std::min(7, (512 + ntiles - 1) / ntiles) : 1;
+    // workgroups (about 4 slots each), whose partial rows are summed after
+    const int nparts = (!assign && slab && nslot >= 8 && ntiles < 256) ? std::min(7, (512 + ntiles - 1) / ntiles) : 1;
     const unsigned grid = (unsigned)ntiles * (unsigned)nparts;
+    if (tgt && !slab) throw Error{YK_ERR_INTERNAL, "sparse tile GEMM needs a slab"};
+    constexpr int NC = 64 * CB;
+    double *sl = nullptr;
+    if (tgt) sl = slab->buf->ensure((size_t)std::max<int64_t>(ntrans, 1) * Pp);
+    else if (nparts > 1) sl = slab->buf->ensure((size_t)grid * NC * Pp);
 #define YK_TILE_CASE(PPV)                                                                          \
     case PPV:                                                                                      \
         if (split)                                                                                 \
             hipLaunchKernelGGL((k_tile_gemm<T, TS, PPV, true, CB>), dim3(grid), dim3(256), 0,     \
                                ctx.stream, tiles, tile0, boxes, nslot, src, slot_op, Op, op_stride, \
-                               level_shift, X, assign, nparts, out, tgt, atom);                   \
+                               level_shift, X, assign, nparts, out, tgt, sl);                     \
         else                                                                                       \
             hipLaunchKernelGGL((k_tile_gemm<T, TS, PPV, false, CB>), dim3(grid), dim3(256), 0,    \
                                ctx.stream, tiles, tile0, boxes, nslot, src, slot_op, Op, op_stride, \
-                               level_shift, X, assign, nparts, out, tgt, atom);                   \
+                               level_shift, X, assign, nparts, out, tgt, sl);                     \
         break;
     switch (Pp) {
         YK_TILE_CASE(16)
@@ -1095,6 +1038,16 @@ void launch_tile_gemm(Context &ctx, int P, int Pp, int ntiles, const int4 *tiles
     }
 #undef YK_TILE_CASE
     check_launch(ctx, "k_tile_gemm");
+    if (tgt) {
+        if (slab->ntgt > 0)
+            hipLaunchKernelGGL(k_slab_reduce_csr, dim3((unsigned)((slab->ntgt + 3) / 4)), dim3(256), 0, ctx.stream,
+                               slab->ntgt, slab->tgt, slab->off, slab->rows, sl, Pp, out);
+        check_launch(ctx, "k_slab_reduce_csr");
+    } else if (nparts > 1) {
+        hipLaunchKernelGGL(k_slab_reduce_parts, dim3((unsigned)ntiles), dim3(256), 0, ctx.stream, tiles, tile0, boxes,
+                           nparts, NC, sl, Pp, out);
+        check_launch(ctx, "k_slab_reduce_parts");
+    }
 }
 
 // Small levels of M2M (4 child slots) and L2L (1 parent slot): one block of
@@ -2349,24 +2302,19 @@ void fmm_run(Context &ctx, FmmPlan &pl, const double *q, const double *dn, doubl
             StageTimer tmm(ctx, YK_STAGE_M2M);
             for (int l = L - 1; l >= pl.lmin; --l) {
                 const int64_t nbl = pl.lev[l].end - pl.lev[l].begin;
-                if (Pp <= 64 && nbl <= kSmallLevelM2M) {
+                if (nbl <= kSmallLevelM2M) {
                     launch_small_gemv(ctx, Pp, 4, nbl, nullptr, pl.lev[l].begin, pl.child4.p, pl.bcode.p,
                                       pl.m2m.p + (size_t)l * 4 * Pp * Pp, pl.M.p, P, 1, pl.M.p);
-                } else if (Pp <= 64) {
+                } else {
                     // M2M on matrix cores: 4 child slots, operators S[l][position]
                     launch_tile_gemm<double, double>(ctx, P, Pp, pl.up_tile_count[l], pl.up_tiles.p,
                                                      pl.up_tile_begin[l], pl.up_boxes.p, 4, pl.child4.p,
                                                      pl.iota4.p, pl.m2m.p, (int64_t)4 * Pp * Pp, 0, pl.M.p,
                                                      1, pl.M.p);
-                } else {
-                    hipLaunchKernelGGL(k_m2m, dim3(nbl), dim3(128), Pp * sizeof(double), ctx.stream,
-                                       pl.lev[l].begin, pl.fchild.p, pl.nchild.p, pl.bcode.p,
-                                       pl.m2m.p + (size_t)l * 4 * Pp * Pp, P, Pp, pl.M.p);
-                    check_launch(ctx, "k_m2m");
                 }
             }
         }
-        const bool f32 = prec == SUM_FP32 && Pp <= 64;
+        const bool f32 = prec == SUM_FP32;
         if (f32) {
             const int64_t nm = pl.nbox * (int64_t)Pp;
             float *mf = pl.Mf.ensure(nm);
@@ -2376,31 +2324,38 @@ void fmm_run(Context &ctx, FmmPlan &pl, const double *q, const double *dn, doubl
         // downward pass
         // a fill kernel rather than a memset node: this pass may be captured in a graph
         if (!lc_clear) launch_fill(ctx, (int64_t)pl.nbox * Pp, 0.0, pl.Lc.p);
-        if (Pp <= 64) {
+        {
             {
                 // M2L of every level at once (levels are independent given the multipoles)
                 StageTimer tl(ctx, YK_STAGE_M2L);
                 // (FP32: 128-box tiles, two column blocks per wavefront, so each
                 // operator fragment feeds two matrix-core steps)
+                SlabPlan slab;
+                slab.buf = &as.m2l_slab;
+                slab.ntgt = as.n_csr_tgt;
+                slab.tgt = as.csr_tgt.p;
+                slab.off = as.csr_off.p;
+                slab.rows = as.csr_rows.p;
                 if (as.m2l_sparse && f32)
                     launch_tile_gemm<float, float>(ctx, P, Pp, as.n_ptiles, as.m2l_ptiles.p, 0, as.m2l_piota.p,
                                                    1, as.m2l_psrc.p, pl.iota40.p, pl.m2lf.p,
                                                    (int64_t)kNumOff * Pp * Pp, 0, pl.Mf.p, 0, pl.Lc.p,
-                                                   as.m2l_ptgt.p);
+                                                   as.m2l_ptgt.p, &slab, as.n_ptrans);
                 else if (as.m2l_sparse)
                     launch_tile_gemm<double, double>(ctx, P, Pp, as.n_ptiles, as.m2l_ptiles.p, 0,
                                                      as.m2l_piota.p, 1, as.m2l_psrc.p, pl.iota40.p, pl.m2l.p,
                                                      (int64_t)kNumOff * Pp * Pp, 0, pl.M.p, 0, pl.Lc.p,
-                                                     as.m2l_ptgt.p);
+                                                     as.m2l_ptgt.p, &slab, as.n_ptrans);
                 else if (f32)
                     launch_tile_gemm<float, float, 2>(ctx, P, Pp, as.n_tiles_w, as.m2l_tiles_w.p, 0,
                                                       as.m2l_boxes.p, kNumV, pl.vlist.p, pl.slot_oid.p,
                                                       pl.m2lf.p, (int64_t)kNumOff * Pp * Pp, 0, pl.Mf.p, 0,
-                                                      pl.Lc.p);
+                                                      pl.Lc.p, nullptr, &slab);
                 else
                     launch_tile_gemm<double, double>(ctx, P, Pp, as.n_tiles, as.m2l_tiles.p, 0, as.m2l_boxes.p,
                                                      kNumV, pl.vlist.p, pl.slot_oid.p, pl.m2l.p,
-                                                     (int64_t)kNumOff * Pp * Pp, 0, pl.M.p, 0, pl.Lc.p);
+                                                     (int64_t)kNumOff * Pp * Pp, 0, pl.M.p, 0, pl.Lc.p, nullptr,
+                                                     &slab);
             }
             StageTimer tl2(ctx, YK_STAGE_L2L);
             for (int l = pl.lmin + 1; l <= L; ++l) {
@@ -2419,24 +2374,6 @@ void fmm_run(Context &ctx, FmmPlan &pl, const double *q, const double *dn, doubl
                                                      as.tile_begin[l], as.m2l_boxes.p, 1, pl.bparent.p,
                                                      pl.iota4.p, pl.l2l.p, (int64_t)4 * Pp * Pp, -1, pl.Lc.p,
                                                      0, pl.Lc.p);
-            }
-        } else {
-            for (int l = pl.lmin; l <= L; ++l) {
-                if (l > pl.lmin && as.l2l_count[l] > 0) {
-                    StageTimer tl(ctx, YK_STAGE_L2L);
-                    hipLaunchKernelGGL(k_l2l, dim3(as.l2l_count[l]), dim3(128), Pp * sizeof(double), ctx.stream,
-                                       as.l2l_boxes.p + as.l2l_begin[l], pl.bparent.p, pl.bcode.p,
-                                       pl.l2l.p + (size_t)(l - 1) * 4 * Pp * Pp, P, Pp, pl.Lc.p);
-                    check_launch(ctx, "k_l2l");
-                }
-                if (as.tile_count[l] > 0) {
-                    StageTimer tl(ctx, YK_STAGE_M2L);
-                    const size_t shm = ((size_t)kM2LChunk * Pp + (size_t)kM2LTile * Pp) * sizeof(double);
-                    hipLaunchKernelGGL(k_m2l, dim3(as.tile_count[l]), dim3(256), shm, ctx.stream,
-                                       as.m2l_tiles.p, as.tile_begin[l], as.m2l_boxes.p, pl.vlist.p,
-                                       pl.slot_oid.p, pl.m2l.p, P, Pp, pl.M.p, pl.Lc.p);
-                    check_launch(ctx, "k_m2l");
-                }
             }
         }
     }

@@ -112,15 +112,23 @@ inline cld cis(ld phi, int m) { return std::polar((ld)1, phi * (ld)m); }
 
 }  // namespace
 
+int supported_order(int p) {
+    // the orders the expansion kernels are instantiated for (P = 2p + 1 real
+    // coefficients padded to 16, 32, 48 or 64)
+    for (int q : kOrders)
+        if (p <= q) return q;
+    return kOrders[kNumOrders - 1];
+}
+
 int choose_order(double tol) {
     // Measured on uniform and clustered point sets: the relative error of the
     // sums behaves like 0.0123 * 0.44^p; take the smallest p with half the
     // tolerance to spare.
     int p = (int)std::ceil(std::log(0.5 * tol / 0.0123) / std::log(0.44));
-    return std::max(4, std::min(60, p));
+    return supported_order(std::max(1, p));
 }
 
-void build_lists_and_tables(Context &ctx, FmmPlan &pl, const std::vector<uint32_t> &keys) {
+void build_lists(Context &ctx, FmmPlan &pl, const std::vector<uint32_t> &keys) {
     const int64_t N = pl.N;
     const uint32_t kMask = 0x3fffffffu;
     // ---- merged Morton codes (each set's block is sorted) ----
@@ -374,9 +382,22 @@ void build_lists_and_tables(Context &ctx, FmmPlan &pl, const std::vector<uint32_
     }
     up(pl.ulist_off, uoff);
     up(pl.ulist, ul);
+    YK_HIP(hipStreamSynchronize(ctx.stream));
+}
 
-    // ---- expansion order and operators ----
-    const int p = pl.opt_p > 0 ? pl.opt_p : choose_order(pl.opt_tol);
+void build_tables(Context &ctx, FmmPlan &pl, int p) {
+    const int L = pl.L, lmin = pl.lmin;
+    const int64_t nb = pl.nbox;
+    auto up = [&](auto &buf, const auto &vec) {
+        using T = typename std::decay_t<decltype(vec)>::value_type;
+        T *d = buf.ensure(vec.size());
+        YK_HIP(hipMemcpyAsync(d, vec.data(), vec.size() * sizeof(T), hipMemcpyHostToDevice, ctx.stream));
+    };
+    // (state that depends on the order: cached P2M rows, kept multipoles)
+    pl.p2m_rows_built = false;
+    pl.p2m_rq.release();
+    pl.p2m_rd.release();
+    pl.mq_kept = false;
     pl.p = p;
     pl.P = 2 * p + 1;
     pl.Pp = (pl.P + 15) / 16 * 16;
@@ -780,6 +801,24 @@ ActiveSet &get_active(Context &ctx, FmmPlan &pl, int mask) {
         up(as->m2l_psrc, psrc);
         up(as->m2l_piota, piota);
         as->n_ptiles = (int)ptiles.size();
+        // the translations of each target box, in increasing index (the
+        // fixed order of their sum)
+        std::vector<int32_t> order(ptgt.size());
+        for (size_t k = 0; k < order.size(); ++k) order[k] = (int32_t)k;
+        std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return ptgt[a] < ptgt[b]; });
+        std::vector<int32_t> ctgt, coff;
+        for (size_t k = 0; k < order.size(); ++k) {
+            if (k == 0 || ptgt[order[k]] != ptgt[order[k - 1]]) {
+                ctgt.push_back(ptgt[order[k]]);
+                coff.push_back((int32_t)k);
+            }
+        }
+        coff.push_back((int32_t)order.size());
+        up(as->csr_tgt, ctgt);
+        up(as->csr_off, coff);
+        up(as->csr_rows, order);
+        as->n_csr_tgt = (int64_t)ctgt.size();
+        as->n_ptrans = (int64_t)ptgt.size();
     }
     up(as->l2l_boxes, l2lb);
     up(as->leaves, leaves);

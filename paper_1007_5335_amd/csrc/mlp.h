@@ -26,6 +26,7 @@ struct WarmStart {
     DevBuf<int32_t> curve_buf, idx_buf;   // private copies of the boundary's curve ids and indices
     const int32_t *curve = nullptr, *idx = nullptr;
     const double *kappa = nullptr;
+    const double *xy = nullptr;           // the boundary's node array (identifies it)
     int64_t o_W1 = 0, o_b1 = 0, o_W2 = 0, o_b2 = 0, o_w3 = 0, o_b3 = 0, n_params = 0;
     DevBuf<float> params, adam_m, adam_v, grad;
     int64_t adam_t = 0;
@@ -45,6 +46,8 @@ struct WarmStart {
     // block of rows in one kernel (when the sizes are the default ones)
     void forward_fused(int64_t rows, const float *X, float *y);
     double loss_grad(int64_t rows, const float *X, const float *T, float *G);
+    // one Adam step of the parameters on the gradient G [n_params]
+    void adam_step(const float *G);
 
   private:
     // writes the features of one step into X and the step's scales into fs

@@ -532,6 +532,7 @@ WarmStart::WarmStart(Context &c, BoundaryData &b, const yk_ws_options &o) : ctx(
     YK_HIP(hipMemcpyAsync(curve_buf.p, b.curve.p, n * sizeof(int32_t), hipMemcpyDeviceToDevice, ctx.stream));
     YK_HIP(hipMemcpyAsync(idx_buf.p, b.idx.p, n * sizeof(int32_t), hipMemcpyDeviceToDevice, ctx.stream));
     kappa = b.curvature;
+    xy = b.xy;
     // parameters: W1 [H x Fp], b1 [H], W2 [H x H], b2 [H], w3 [H], b3 [1]
     o_W1 = 0;
     o_b1 = o_W1 + (int64_t)H * Fp;
@@ -675,7 +676,6 @@ double WarmStart::train() {
     for (int64_t i = 0; i < rows; ++i) perm[i] = (int32_t)i;
     int64_t pos = rows;
     double loss = 0;
-    const float b1 = 0.9f, b2 = 0.999f;
     for (int it = 0; it < opt.steps; ++it) {
         if (pos + B > rows) {
             std::shuffle(perm.begin(), perm.end(), rng);
@@ -687,14 +687,21 @@ double WarmStart::train() {
                            Xb, Tb);
         check_launch(ctx, "k_gather_rows");
         loss = loss_grad(B, Xb, Tb, G);
-        ++adam_t;
-        const float c1 = 1.f / (1.f - std::pow(b1, (float)adam_t)), c2 = 1.f / (1.f - std::pow(b2, (float)adam_t));
-        hipLaunchKernelGGL(k_adam, dim3(nblk(n_params, 256)), dim3(256), 0, ctx.stream, n_params, params.p, G,
-                           adam_m.p, adam_v.p, (float)opt.lr, b1, b2, 1e-8f, c1, c2);
-        check_launch(ctx, "k_adam");
+        adam_step(G);
     }
     trained = true;
     return loss;
+}
+
+void WarmStart::adam_step(const float *G) {
+    // Adam (Kingma & Ba): moments with decay b1, b2 and bias corrections
+    // 1 / (1 - b^t) for the step count t
+    const float b1 = 0.9f, b2 = 0.999f;
+    ++adam_t;
+    const float c1 = 1.f / (1.f - std::pow(b1, (float)adam_t)), c2 = 1.f / (1.f - std::pow(b2, (float)adam_t));
+    hipLaunchKernelGGL(k_adam, dim3(nblk(n_params, 256)), dim3(256), 0, ctx.stream, n_params, params.p, G,
+                       adam_m.p, adam_v.p, (float)opt.lr, b1, b2, 1e-8f, c1, c2);
+    check_launch(ctx, "k_adam");
 }
 
 void WarmStart::predict(const double *g_next, double *out) {

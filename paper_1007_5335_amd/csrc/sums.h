@@ -25,6 +25,9 @@ struct SumProblem {
     const double *xy[3] = {nullptr, nullptr, nullptr};
     double alpha = 0.0;
     const BieFuse *bie = nullptr;   // (FMM backend only; see evaluate_sums)
+    const double *normal = nullptr; // unit normals of set 1 [n1][2] when known (FMM
+                                    // backend: the build-time order check probes
+                                    // dipoles along them)
     // FMM backend: 1 = leave the leaf multipoles of this (charges-only) pass
     // in place for a later pass; 2 = the charges equal those of that pass on
     // the same tree, with no other pass on it in between: start from its

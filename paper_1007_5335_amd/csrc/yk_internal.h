@@ -139,6 +139,7 @@ struct Context {
     double memo_alpha = 0, memo_tol = 0;
     int memo_p = 0, memo_leaf = 0, memo_direct = 0;
     DevBuf<double> ws_g, ws_ml, ws_t;       // heat-step buffers of the guess selection
+    DevBuf<double> ws_q;                    // heat step: volume charges W B (no solver touches it)
 
     // second stream for the near field (overlaps the far-field chain) and the
     // fork/join events that order it against the context's stream

@@ -37,7 +37,7 @@ EXPORTS = (
     "yk_plan_info_get", "yk_timing_enable", "yk_timing_read",
     "yk_ws_default_options", "yk_ws_create", "yk_ws_destroy", "yk_ws_observe", "yk_ws_train",
     "yk_ws_predict", "yk_set_warm_start", "yk_ws_num_params", "yk_ws_get_params",
-    "yk_ws_set_params", "yk_ws_loss_grad",
+    "yk_ws_set_params", "yk_ws_loss_grad", "yk_ws_forward", "yk_ws_adam_step",
 )
 
 STAGES = ("gather", "p2m", "m2m", "m2l", "l2l", "leaf", "scatter", "direct", "l2p", "near_build")
@@ -77,7 +77,8 @@ class yk_plan_info(ctypes.Structure):
                 ("near_terms", ctypes.c_int32), ("nser", ctypes.c_int32),
                 ("build_ms", ctypes.c_double), ("m2l_sparse", ctypes.c_int32),
                 ("near_sym", ctypes.c_int32), ("near_charge_values", ctypes.c_int64),
-                ("near_incoming", ctypes.c_int64)]
+                ("near_incoming", ctypes.c_int64), ("p_initial", ctypes.c_int32),
+                ("order_check_err", ctypes.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -138,6 +139,8 @@ def load_library(path: str = LIB_PATH):
         "yk_ws_get_params": (ip, [vp, vp]),
         "yk_ws_set_params": (ip, [vp, vp]),
         "yk_ws_loss_grad": (ip, [vp, i64, vp, vp, vp, P(dbl)]),
+        "yk_ws_forward": (ip, [vp, i64, vp, vp]),
+        "yk_ws_adam_step": (ip, [vp, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -393,3 +396,13 @@ def yk_ws_loss_grad(ws: WarmStartHandle, X, t, grad) -> float:
                                                   _dev(t, "t", dtype="float32"),
                                                   _dev(grad, "grad", dtype="float32"), ctypes.byref(loss)))
     return loss.value
+
+
+def yk_ws_forward(ws: WarmStartHandle, X, y):
+    _check(ws.ctx, load_library().yk_ws_forward(ws.h, X.shape[0], _dev(X, "X", dtype="float32"),
+                                                _dev(y, "y", dtype="float32")))
+    return y
+
+
+def yk_ws_adam_step(ws: WarmStartHandle, grad):
+    _check(ws.ctx, load_library().yk_ws_adam_step(ws.h, _dev(grad, "grad", dtype="float32")))

@@ -16,3 +16,12 @@ def host(t):
 
 def rel_max(a, b):
     return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
+
+
+def elem_err(got, ref):
+    """Largest element-wise difference relative to the largest reference entry
+    (max_i |got_i - ref_i| / max_i |ref_i|)."""
+    got = np.asarray(got)
+    ref = np.asarray(ref)
+    assert got.shape == ref.shape
+    return float(np.max(np.abs(got - ref)) / max(np.max(np.abs(ref)), 1e-300))

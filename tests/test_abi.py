@@ -42,3 +42,19 @@ def test_default_options_and_null_handles():
     assert lib.yk_destroy(None) == yk.YK_ERR_ARG
     assert lib.yk_create(ctypes.byref(o), None) == yk.YK_ERR_ARG
     assert lib.yk_volume_potential(None, 1, None, None, 0, None, 1.0, None) == yk.YK_ERR_ARG
+
+
+def test_order_above_31_is_rejected():
+    """The expansion kernels exist for orders up to 31; a larger p is refused
+    before any device work (no silently truncated expansion)."""
+    import ctypes
+    import paper_1007_5335_amd.yk as yk
+    if not os.path.exists(yk.LIB_PATH):
+        pytest.skip("libyk.so not built")
+    lib = yk.load_library()
+    o = yk.yk_default_options()
+    h = ctypes.c_void_p()
+    for p in (32, 40, 80):
+        o.p = p
+        assert lib.yk_create(ctypes.byref(o), ctypes.byref(h)) == yk.YK_ERR_ARG
+        assert not h.value

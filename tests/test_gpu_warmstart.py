@@ -4,7 +4,7 @@ import numpy as np
 import pytest
 
 import workloads as W
-from gpu_util import dev, host
+from gpu_util import dev, elem_err, host
 
 pytestmark = pytest.mark.gpu
 
@@ -47,6 +47,80 @@ def test_mlp_loss_and_gradients_vs_fp64(yk):
     for a, b in blocks:
         err = np.max(np.abs(gg[a:b] - ref_g[a:b])) / np.max(np.abs(ref_g[a:b]))
         assert err < 2e-4, (a, b, err)
+
+
+@pytest.mark.parametrize("rows", [5, 1200])
+def test_inference_kernels_vs_fp64_forward(yk, rows):
+    """The network's output for given feature rows by the fused inference
+    kernel (the production path: both hidden layers of 32 rows per
+    workgroup) and by the layer-by-layer products (debug_flags bit 5), each
+    element by element against the FP64 forward pass of the reference on the
+    same FP32 parameters; 1200 rows make 37 full blocks and a partial one, 5
+    rows a single partial block."""
+    import torch
+    from oracle import mlp
+    cfg = W.config_c0(n_nodes=64, m=8)
+    ctx = yk.yk_create()
+    bd = yk.Boundary.from_workload(cfg["bnd"])
+    ws = yk.yk_ws_create(ctx, bd, hidden=256)
+    try:
+        n, H, Fp = yk.yk_ws_num_params(ws)
+        rng = np.random.default_rng(17)
+        p = (rng.standard_normal(n) * 0.08).astype(np.float32)
+        X = rng.standard_normal((rows, Fp)).astype(np.float32)
+        yk.yk_ws_set_params(ws, dev(p, torch.float32))
+        got = {}
+        for flags in (0, 32):
+            opt = yk.yk_default_options()
+            opt.debug_flags = flags
+            yk.yk_set_options(ctx, opt)
+            y = torch.full((rows,), float("nan"), dtype=torch.float32, device="cuda")
+            print(f"network forward rows={rows} debug_flags={flags}", flush=True)
+            yk.yk_ws_forward(ws, dev(X, torch.float32), y)
+            got[flags] = host(y).astype(np.float64)
+    finally:
+        yk.yk_ws_destroy(ws)
+        yk.yk_destroy(ctx)
+    ref, _ = mlp.forward(p.astype(np.float64), H, Fp, X.astype(np.float64))
+    for flags, y in got.items():
+        err = elem_err(y, ref)
+        print(f"  flags {flags}: max err / max |ref| {err:.2e}", flush=True)
+        assert err <= 2e-5
+
+
+def test_adam_kernel_vs_fp64(yk):
+    """Three Adam steps of the library's optimiser kernel (FP32) on given
+    gradients, from zero moments, against the reference's FP64 Adam on the
+    same parameters and gradients: every parameter's total move within 1e-4
+    of the learning rate."""
+    import torch
+    from oracle import mlp
+    cfg = W.config_c0(n_nodes=64, m=8)
+    ctx = yk.yk_create()
+    bd = yk.Boundary.from_workload(cfg["bnd"])
+    lr = 1e-3
+    ws = yk.yk_ws_create(ctx, bd, hidden=64, lr=lr)
+    try:
+        n, H, Fp = yk.yk_ws_num_params(ws)
+        rng = np.random.default_rng(19)
+        p0 = (rng.standard_normal(n) * 0.1).astype(np.float32)
+        grads = [(rng.standard_normal(n) * np.exp(rng.uniform(-4, 2, n))).astype(np.float32) for _ in range(3)]
+        yk.yk_ws_set_params(ws, dev(p0, torch.float32))
+        for g in grads:
+            yk.yk_ws_adam_step(ws, dev(g, torch.float32))
+        out = torch.empty(n, dtype=torch.float32, device="cuda")
+        yk.yk_ws_get_params(ws, out)
+        got = host(out).astype(np.float64)
+    finally:
+        yk.yk_ws_destroy(ws)
+        yk.yk_destroy(ctx)
+    p, m, v = p0.astype(np.float64), np.zeros(n), np.zeros(n)
+    for t, g in enumerate(grads, start=1):
+        p, m, v = mlp.adam_step(p, g.astype(np.float64), m, v, t, lr=lr)
+    move_got, move_ref = got - p0.astype(np.float64), p - p0.astype(np.float64)
+    err = float(np.max(np.abs(move_got - move_ref)))
+    print(f"  Adam: max |move error| {err:.2e} (lr {lr})", flush=True)
+    assert err <= 1e-4 * lr
 
 
 def test_fused_inference_matches_layered(yk):
@@ -138,6 +212,8 @@ def test_time_loop_with_learned_guess(yk):
           f"learned guess used {used}/10", flush=True)
     assert r0_l <= r0_b * 1.0001
     assert used >= 1
+    # what the network gains: at least half an iteration per step on average
+    assert it_l <= it_b - 0.5, (it_b, it_l)
 
 
 def test_warm_start_falls_back_on_garbage_network(yk):
