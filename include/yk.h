@@ -197,6 +197,27 @@ yk_status yk_heat_step(yk_ctx ctx, const yk_boundary *bnd, int64_t n_vol, const 
                        double dt, double tol, double *sigma_io, double *u_next, yk_stats *stats);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the solve
+ * of yk_gmres_density with direct O(N^2) sums (as with options.direct = 1),
+ * with the same arguments, results and status codes, that allocates
+ * nothing.  Its device workspace is a fixed array of 4,194,304 doubles
+ * (32 MiB) that the library holds on each GPU it runs on until the process
+ * ends; it takes (gmres_m + 9) N doubles plus about 108,000 for N nodes
+ * (gmres_m 60: up to about 60,000 nodes), and larger sizes are rejected with
+ * YK_ERR_ARG before any work.  The caller passes the context (its stream and
+ * gmres_m are used), the boundary, g, sigma0 and sigma as for
+ * yk_gmres_density.  No pinned memory or event is created: the Arnoldi
+ * scalars come back by ordinary copies, so the host waits for each
+ * iteration.  Every call on one GPU shares that GPU's array (whatever the
+ * context), so calls that overlap on one GPU race; the array keeps the last
+ * call's contents, and the solve initialises everything it reads.
+ */
+yk_status yk_gmres_density_noalloc(yk_ctx ctx, const yk_boundary *bnd, double alpha, const double *g,
+                                   const double *sigma0, double tol, int max_iter, double *sigma,
+                                   yk_stats *stats);
+
+/*
  * Right-hand side of the backward-Euler step with the constant extension of
  * Sec. 3.1 (boundary data constant on each curve):
  *   B_i = u_i + dt F_i       if region[i] < 0 (inside the domain)

@@ -363,6 +363,12 @@ void memo_store(Context &ctx, BoundaryData &bd, double alpha, const double *sigm
 
 }  // namespace
 
+GmresResult solve_density_direct(Context &ctx, BoundaryData &bd, double alpha, const double *b, double *sigma,
+                                 bool zero_guess, double tol, int max_iter) {
+    int outer = 0;
+    return solve_density(ctx, bd, alpha, b, sigma, zero_guess, tol, max_iter, &outer);
+}
+
 }  // namespace yk
 
 using namespace yk;
@@ -421,6 +427,12 @@ yk_status yk_create(const yk_options *opt, yk_ctx *out) {
     if (!c) return YK_ERR_NOMEM;
     c->c.opt = o;
     if (hipGetDevice(&c->c.device) != hipSuccess) {
+        delete c;
+        return YK_ERR_HIP;
+    }
+    try {   // the allocation-free entry point's array on this device
+        noalloc_init_device(c->c.device);
+    } catch (...) {
         delete c;
         return YK_ERR_HIP;
     }

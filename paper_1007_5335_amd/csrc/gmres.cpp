@@ -23,6 +23,10 @@ double dot_host(Context &ctx, int64_t n, const double *a, const double *b, doubl
 }  // namespace
 
 double *pinned_scalars(Context &ctx) {
+    if (ctx.noalloc) {   // (ordinary host memory, filled by stream-ordered copies)
+        if (ctx.host_scal.size() < 512) ctx.host_scal.resize(512);
+        return ctx.host_scal.data();
+    }
     if (!ctx.gm_host) YK_HIP(hipHostMalloc((void **)&ctx.gm_host, 512 * sizeof(double), hipHostMallocDefault));
     return ctx.gm_host;
 }
@@ -66,7 +70,7 @@ GmresResult gmres(Context &ctx, const Apply &A, int64_t n, const double *b, doub
     res.res0 = beta / bnorm;
 
     std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), y(m), hs(2 * 128 + 1);
-    if (!ctx.ev_col) YK_HIP(hipEventCreateWithFlags(&ctx.ev_col, hipEventDisableTiming));
+    if (!ctx.ev_col && !ctx.noalloc) YK_HIP(hipEventCreateWithFlags(&ctx.ev_col, hipEventDisableTiming));
     while (true) {
         if (beta <= tol * bnorm) {
             res.converged = true;
@@ -96,20 +100,28 @@ GmresResult gmres(Context &ctx, const Apply &A, int64_t n, const double *b, doub
             launch_arnoldi_pass(ctx, n, V, n, w, 0, nullptr, nullptr, k + 1, false, P0);
             launch_arnoldi_pass(ctx, n, V, n, w, k + 1, P0, dscal, k + 1, true, P1);
             launch_arnoldi_finish(ctx, n, V, n, w, k + 1, P1, dscal + 128, dscal + 256, V + (int64_t)(k + 1) * n,
-                                  dscal, host);
-            YK_HIP(hipEventRecord(ctx.ev_col, ctx.stream));
+                                  dscal, ctx.noalloc ? nullptr : host);
+            if (ctx.noalloc) {
+                // no pinned memory or event: copy the column (h1 at 0, h2 at
+                // 128, the squared norm at 256) and wait for the stream
+                YK_HIP(hipMemcpyAsync(host, dscal, (2 * 128 + 1) * sizeof(double), hipMemcpyDeviceToHost,
+                                      ctx.stream));
+                YK_HIP(hipStreamSynchronize(ctx.stream));
+            } else {
+                YK_HIP(hipEventRecord(ctx.ev_col, ctx.stream));
+            }
             // The next basis vector is already formed on the device, so its
             // apply goes on the stream before the host waits for the column:
             // the host's rotations then overlap the GPU's work instead of
             // leaving it idle.  Skipped when, at the last seen rate, this
             // column should meet the tolerance (a wasted apply costs more
             // than the wait it hides).
-            if (k + 1 < m && res.iters + 1 < max_iter && rho * std::fabs(g[k]) > 2.0 * tol * bnorm) {
+            if (!ctx.noalloc && k + 1 < m && res.iters + 1 < max_iter && rho * std::fabs(g[k]) > 2.0 * tol * bnorm) {
                 A(V + (int64_t)(k + 1) * n, w);
                 res.matvecs++;
                 issued = true;
             }
-            YK_HIP(hipEventSynchronize(ctx.ev_col));
+            if (!ctx.noalloc) YK_HIP(hipEventSynchronize(ctx.ev_col));
             std::copy(host, host + 2 * 128 + 1, hs.begin());
             double *col = &H[(size_t)k * (m + 1)];
             for (int i = 0; i <= k; ++i) col[i] = hs[i] + hs[128 + i];

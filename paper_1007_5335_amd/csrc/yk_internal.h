@@ -35,22 +35,36 @@ struct Error {
         if (!(cond)) throw ::yk::Error{YK_ERR_ARG, std::string(msg)}; \
     } while (0)
 
-// Device buffer owned by the library (grow-only).
+// Device buffer owned by the library (grow-only), or a borrowed window of
+// fixed size into memory the library does not allocate here (the
+// allocation-free entry point's array): a borrowed buffer never allocates or
+// frees, and asking it for more than its window is an internal error.
 template <typename T>
 struct DevBuf {
     T *p = nullptr;
     size_t n = 0;
+    bool borrowed = false;
     DevBuf() = default;
     DevBuf(const DevBuf &) = delete;
     DevBuf &operator=(const DevBuf &) = delete;
     ~DevBuf() { release(); }
+    void borrow(T *ptr, size_t count) {
+        release();
+        p = ptr;
+        n = count;
+        borrowed = true;
+    }
     void release() {
-        if (p) (void)hipFree(p);
+        if (p && !borrowed) (void)hipFree(p);
         p = nullptr;
         n = 0;
+        borrowed = false;
     }
     T *ensure(size_t count) {
         if (count <= n && p) return p;
+        if (borrowed)
+            throw Error{YK_ERR_INTERNAL, "a fixed workspace window of " + std::to_string(n) +
+                                             " entries was asked for " + std::to_string(count)};
         release();
         size_t c = count ? count : 1;
         if (hipMalloc(&p, c * sizeof(T)) != hipSuccess) {
@@ -124,6 +138,9 @@ struct Context {
     DevBuf<double> scal;                   // small device scalars
     DevBuf<double> arn_partial;            // Arnoldi passes: block partials
     double *gm_host = nullptr;             // pinned host copy of an Arnoldi column (hipHostMalloc)
+    // allocation-free mode: every device buffer is borrowed, no event or
+    // pinned memory is created, and host copies go through host_scal
+    bool noalloc = false;
     DevBuf<double> dn;                     // dipole vectors [N][2]
     std::vector<double> host_scal;
 
@@ -257,6 +274,10 @@ double *pinned_scalars(Context &ctx);
 void launch_fill(Context &ctx, int64_t n, double v, double *out);
 // flag = 1 if a and b differ anywhere (bitwise), on the context's stream
 void launch_differs(Context &ctx, int64_t n, const double *a, const double *b, int *flag);
+
+// takes the device address of the allocation-free entry point's array on this
+// device (once per device; noalloc.hip)
+void noalloc_init_device(int device);
 
 // -------------------------------------------------------------------- FMM ---
 // Evaluate V[q] + DL[dn] at targets with the cached plan.

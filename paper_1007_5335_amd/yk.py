@@ -38,6 +38,7 @@ EXPORTS = (
     "yk_ws_default_options", "yk_ws_create", "yk_ws_destroy", "yk_ws_observe", "yk_ws_train",
     "yk_ws_predict", "yk_set_warm_start", "yk_ws_num_params", "yk_ws_get_params",
     "yk_ws_set_params", "yk_ws_loss_grad", "yk_ws_forward", "yk_ws_adam_step",
+    "yk_gmres_density_noalloc",
 )
 
 STAGES = ("gather", "p2m", "m2m", "m2l", "l2l", "leaf", "scatter", "direct", "l2p", "near_build")
@@ -141,6 +142,7 @@ def load_library(path: str = LIB_PATH):
         "yk_ws_loss_grad": (ip, [vp, i64, vp, vp, vp, P(dbl)]),
         "yk_ws_forward": (ip, [vp, i64, vp, vp]),
         "yk_ws_adam_step": (ip, [vp, vp]),
+        "yk_gmres_density_noalloc": (ip, [vp, P(yk_boundary), dbl, vp, vp, dbl, ip, vp, P(yk_stats)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -272,6 +274,18 @@ def yk_gmres_density(ctx, bnd: Boundary, alpha, g, sigma0, tol, max_iter, sigma,
     s = load_library().yk_gmres_density(ctx, ctypes.byref(bnd.struct), float(alpha), _dev(g, "g"),
                                         _dev(sigma0, "sigma0"), float(tol), int(max_iter),
                                         _dev(sigma, "sigma"), ctypes.byref(st))
+    if s == YK_ERR_NOCONV and not raise_on_noconv:
+        return st
+    _check(ctx, s, st)
+    return st
+
+
+def yk_gmres_density_noalloc(ctx, bnd: Boundary, alpha, g, sigma0, tol, max_iter, sigma,
+                             raise_on_noconv=True):
+    st = yk_stats()
+    s = load_library().yk_gmres_density_noalloc(ctx, ctypes.byref(bnd.struct), float(alpha), _dev(g, "g"),
+                                                _dev(sigma0, "sigma0"), float(tol), int(max_iter),
+                                                _dev(sigma, "sigma"), ctypes.byref(st))
     if s == YK_ERR_NOCONV and not raise_on_noconv:
         return st
     _check(ctx, s, st)
