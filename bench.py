@@ -99,6 +99,27 @@ def rooflines(info, st, steps, fp32):
                       "peak": peak, "unit": "TFLOP/s", "frac": ach / peak,
                       "traffic": None if fp32 else measured_traffic("k_tile_gemm_m2l"), "avg_launch_ms": t,
                       "launches_per_pass": m2l_calls / steps, "algorithmic_flops": m2l_flops(info)}
+    # the upward and downward chain: 10 P flops per point for P2M and L2P
+    # (the expansion's P terms, about ten operations each), 2 P^2 per
+    # child-parent translation for M2M and L2L (one dense P x P product);
+    # FP64 in both precision modes (P2M, M2M, L2P) or in FP64 mode (L2L),
+    # against the FP64 peak; per pass (all launches of the stage)
+    P = info.P
+    chain = {"p2m": ("P2M (k_p2m_half + k_p2m_quad, or cached rows on small trees)", 10.0 * P * info.p2m_points),
+             "m2m": ("M2M (k_tile_gemm on large levels, k_small_gemv on small ones)",
+                     2.0 * P * P * info.m2m_children),
+             "l2l": ("L2L (k_tile_gemm on large levels, k_small_gemv on small ones)",
+                     2.0 * P * P * info.l2l_children),
+             "l2p": ("k_l2p (L2P, writes the outputs)", 10.0 * P * info.l2p_points)}
+    for key, (kname, flops) in chain.items():
+        ms, calls = st[key]
+        if not calls or flops <= 0:
+            continue
+        t_pass = ms / steps
+        ach = flops / (t_pass * 1e-3) / 1e12
+        out[key] = {"kernel": kname, "bound": "alu", "achieved": ach, "peak": PEAK_FP64_MFMA_TF,
+                    "unit": "TFLOP/s", "frac": ach / PEAK_FP64_MFMA_TF, "traffic": None,
+                    "ms_per_pass": t_pass, "launches_per_pass": calls / steps, "algorithmic_flops": flops}
     return out
 
 
@@ -253,17 +274,73 @@ def oracle_baseline(args, res, idx):
     n_vol = cfg["vol"].shape[0]
     sub = idx[: args.cpu_samples]
     tgt = np.concatenate([cfg["vol"], b.xy])[sub]
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    threads = oracle.max_threads()
     t0 = time.perf_counter()
     ref = oracle.volume_sum(cfg["vol"], cfg["q"], cfg["alpha"], tgt_xy=tgt) + \
         oracle.dl_sum(b.xy, b.normal, cfg["dip"], cfg["alpha"], tgt)
     t_cpu = time.perf_counter() - t0
     got = res["out"][sub]
     err = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+    n_src = n_vol + b.n
     cpu = {"value": len(sub) / t_cpu / 1e6, "unit": "Mpts/s", "cores": threads, "kind": "oracle",
            "sample": f"{len(sub)} sampled targets x all {n_vol} charges + {b.n} dipoles, direct FP64 "
-                     f"sums in {t_cpu:.2f} s; each sampled point is one full O(N) sum"}
+                     f"sums in {t_cpu:.2f} s; each sampled point is one full O(N) sum",
+           "pairs_per_s": len(sub) * n_src / t_cpu,
+           "full_pass_s_extrapolated": t_cpu * n_src / len(sub)}
+    # the same sums on one core (a tenth of the sample)
+    sub1 = sub[: max(1, len(sub) // 10)]
+    tgt1 = np.concatenate([cfg["vol"], b.xy])[sub1]
+    oracle.set_threads(1)
+    try:
+        t0 = time.perf_counter()
+        oracle.volume_sum(cfg["vol"], cfg["q"], cfg["alpha"], tgt_xy=tgt1)
+        oracle.dl_sum(b.xy, b.normal, cfg["dip"], cfg["alpha"], tgt1)
+        t1 = time.perf_counter() - t0
+    finally:
+        oracle.set_threads(threads)
+    cpu["one_core"] = {"value": len(sub1) / t1 / 1e6, "unit": "Mpts/s", "cores": 1,
+                       "pairs_per_s": len(sub1) * n_src / t1, "sample": f"{len(sub1)} of the sampled targets"}
+    if not args.no_cpu_steps:
+        cpu["oracle_steps"] = oracle_step_timings(oracle)
     return err, cpu
+
+
+def oracle_step_timings(oracle):
+    """Whole backward-Euler steps of the oracle (direct sums, dense matrix of
+    the boundary system and its LU, all host cores) at the C0 size and at a
+    reduced time-stepping set, and the dense LU timed at the reduced set's
+    boundary size and extrapolated (n^3) to the full set's."""
+    import scipy.linalg as sla
+    import workloads as W
+    out = {}
+    c0 = W.config_c0()
+    b = c0["bnd"]
+    t0 = time.perf_counter()
+    oracle.heat_step(b.xy, b.normal, b.weights(), b.curvature, c0["vol"], c0["vol_w"], c0["B"],
+                     c0["f_next"], c0["dt"], grid_h=c0["h"])
+    out["c0_step_s"] = time.perf_counter() - t0
+    out["c0_size"] = f"{c0['vol'].shape[0]} volume points, {b.n} nodes"
+    c3 = W.config_c3(m=128, n_holes=10, n_nodes=256, dt=1e-3, seed=3)
+    b = c3["bnd"]
+    B = np.where(c3["region"] < 0, c3["u0"], c3["consts"][np.maximum(c3["region"], 0)])
+    t0 = time.perf_counter()
+    A = oracle.dl_matrix(b.xy, b.normal, b.weights(), b.curvature, c3["alpha"])
+    t_mat = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    lu = sla.lu_factor(A)
+    t_lu = time.perf_counter() - t0
+    del A, lu
+    t0 = time.perf_counter()
+    oracle.heat_step(b.xy, b.normal, b.weights(), b.curvature, c3["vol"], c3["vol_w"], B, c3["f_bnd"],
+                     c3["dt"], grid_h=c3["h"])
+    out["reduced_c3_step_s"] = time.perf_counter() - t0
+    out["reduced_c3_size"] = f"{c3['vol'].shape[0]} volume points, {b.n} nodes"
+    n_full = 8192 + 10 * 2048
+    out["dense_lu"] = {"n": int(b.n), "matrix_s": t_mat, "lu_s": t_lu, "n_full": n_full,
+                       "matrix_s_extrapolated": t_mat * (n_full / b.n) ** 2,
+                       "lu_s_extrapolated": t_lu * (n_full / b.n) ** 3,
+                       "note": "measured at n, extrapolated to the full boundary (n^2 matrix, n^3 LU)"}
+    return out
 
 
 def heat_step_bench(args, yk, torch, W):
@@ -455,6 +532,7 @@ def main():
     ap.add_argument("--cpu-samples", type=int, default=100)
     ap.add_argument("--fp32", action="store_true")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle check (profiling runs)")
+    ap.add_argument("--no-cpu-steps", action="store_true", help="skip the oracle's whole-step timings")
     ap.add_argument("--heat-steps", type=int, default=100)
     ap.add_argument("--heat-m", type=int, default=1024)
     ap.add_argument("--no-heat", action="store_true")
@@ -522,7 +600,8 @@ def main():
             "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": ach / PEAK_HBM_GBS,
             "traffic": None, "avg_launch_ms": t, "launches_per_pass": 0.0, "algorithmic_bytes": nbytes}
     # the dominant kernel: largest time per pass
-    roof = max((r for k, r in roofs.items() if k not in ("near_on_the_fly", "near_full_layout")),
+    roof = max((r for k, r in roofs.items()
+                if k not in ("near_on_the_fly", "near_full_layout", "p2m", "m2m", "l2l", "l2p")),
                key=lambda r: r["avg_launch_ms"] * r["launches_per_pass"])
     m2l_rate = roofs["m2l"]["achieved"] if "m2l" in roofs else None
     err, errmax, idx, ref = direct_check(args, res, yk, torch)

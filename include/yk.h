@@ -130,6 +130,8 @@ yk_status yk_destroy(yk_ctx ctx);
 yk_status yk_set_stream(yk_ctx ctx, void *hip_stream);
 /* Replaces the options; cached trees are dropped when p/leaf_size change. */
 yk_status yk_set_options(yk_ctx ctx, const yk_options *opt);
+/* The message of the context's last failed call; with ctx == NULL, why the
+ * last yk_create on the calling thread failed. */
 const char *yk_last_error(yk_ctx ctx);
 /* Drops every cached tree and operator table. */
 yk_status yk_invalidate_geometry(yk_ctx ctx);
@@ -343,6 +345,10 @@ typedef struct {
                                  When fmm_tol derives the order, the tree raises it
                                  along 8, 12, 16, 20, 24, 31 until this error is at
                                  most fmm_tol / 2, or the order reaches 31 */
+    int64_t m2m_children;     /* child-to-parent translations of the upward pass
+                                 (non-empty children of the boxes at levels lmin..L-1) */
+    int64_t l2l_children;     /* parent-to-child translations of the downward pass of
+                                 the last evaluation (its active boxes at levels > lmin) */
 } yk_plan_info;
 
 enum {

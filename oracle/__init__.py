@@ -63,10 +63,23 @@ def _load():
     lib.yko_volume_sum.argtypes = [i64, dp, i64, dp, dp, ctypes.c_double, ctypes.c_int, dp]
     lib.yko_dl_sum.restype = None
     lib.yko_dl_sum.argtypes = [i64, dp, i64, dp, dp, dp, ctypes.c_double, dp]
+    lib.yko_set_threads.restype = None
+    lib.yko_set_threads.argtypes = [ctypes.c_int]
+    lib.yko_max_threads.restype = ctypes.c_int
+    lib.yko_max_threads.argtypes = []
     lib.yko_dl_matrix.restype = None
     lib.yko_dl_matrix.argtypes = [i64, dp, dp, dp, dp, ctypes.c_double, dp]
     _lib = lib
     return lib
+
+
+def set_threads(n: int) -> None:
+    """Number of OpenMP threads of the direct sums (timing only)."""
+    _load().yko_set_threads(int(n))
+
+
+def max_threads() -> int:
+    return int(_load().yko_max_threads())
 
 
 def _p(a: np.ndarray):

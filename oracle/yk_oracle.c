@@ -28,6 +28,9 @@
 #include <math.h>
 #include <stdint.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define YKO_PI 3.14159265358979323846
 #define YKO_EULER_GAMMA 0.57721566490153286061
@@ -203,4 +206,20 @@ void yko_i0_vec(int64_t n, const double *z, double *out) {
 }
 void yko_i1_vec(int64_t n, const double *z, double *out) {
     for (int64_t i = 0; i < n; ++i) out[i] = yko_i1(z[i]);
+}
+
+/* Thread count of the OpenMP loops (the CPU baseline is also timed on one core). */
+void yko_set_threads(int n) {
+#ifdef _OPENMP
+    omp_set_num_threads(n > 0 ? n : 1);
+#else
+    (void)n;
+#endif
+}
+int yko_max_threads(void) {
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
 }

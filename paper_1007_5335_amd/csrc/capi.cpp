@@ -416,25 +416,45 @@ static bool valid_options(const yk_options *o) {
            (o->p > 0 || (o->fmm_tol > 0 && o->fmm_tol < 1));
 }
 
+// why the last yk_create on this thread failed (no context holds it)
+static thread_local std::string g_create_error;
+
 yk_status yk_create(const yk_options *opt, yk_ctx *out) {
-    if (!out) return YK_ERR_ARG;
+    g_create_error.clear();
+    if (!out) {
+        g_create_error = "out is NULL";
+        return YK_ERR_ARG;
+    }
     *out = nullptr;
     yk_options o;
     yk_default_options(&o);
     if (opt) o = *opt;
-    if (!valid_options(&o)) return YK_ERR_ARG;
+    if (!valid_options(&o)) {
+        g_create_error = "invalid options";
+        return YK_ERR_ARG;
+    }
     yk_ctx c = new (std::nothrow) yk_ctx_s();
-    if (!c) return YK_ERR_NOMEM;
+    if (!c) {
+        g_create_error = "host allocation failed";
+        return YK_ERR_NOMEM;
+    }
     c->c.opt = o;
-    if (hipGetDevice(&c->c.device) != hipSuccess) {
+    const hipError_t e = hipGetDevice(&c->c.device);
+    if (e != hipSuccess) {
+        g_create_error = std::string("hipGetDevice: ") + hipGetErrorString(e);
         delete c;
         return YK_ERR_HIP;
     }
     try {   // the allocation-free entry point's array on this device
         noalloc_init_device(c->c.device);
-    } catch (...) {
+    } catch (const Error &err) {
+        g_create_error = err.msg;
         delete c;
-        return YK_ERR_HIP;
+        return err.code;
+    } catch (...) {
+        g_create_error = "unknown error taking the workspace array's address";
+        delete c;
+        return YK_ERR_INTERNAL;
     }
     *out = c;
     return YK_OK;
@@ -467,7 +487,7 @@ yk_status yk_set_options(yk_ctx ctx, const yk_options *opt) {
 }
 
 const char *yk_last_error(yk_ctx ctx) {
-    if (!ctx) return "null context";
+    if (!ctx) return g_create_error.empty() ? "null context" : g_create_error.c_str();
     return ctx->c.last_error.c_str();
 }
 
@@ -923,6 +943,9 @@ yk_status yk_plan_info_get(yk_ctx ctx, int slot, yk_plan_info *info) {
         info->build_ms = pl->build_ms;
         info->p_initial = pl->calib_p0;
         info->order_check_err = pl->calib_err;
+        if (pl->lmin <= pl->L) {
+            for (int l = pl->lmin + 1; l <= pl->L; ++l) info->m2m_children += pl->lev[l].end - pl->lev[l].begin;
+        }
         info->near_terms = pl->near_terms;
         info->nser = pl->nser;
         auto it = pl->active.find(pl->last_mask);
@@ -938,6 +961,8 @@ yk_status yk_plan_info_get(yk_ctx ctx, int slot, yk_plan_info *info) {
             info->near_charge_values = pl->last_has_q ? (as.near_sym ? as.near_q_vals : as.pairs_q) : 0;
             info->near_incoming = pl->last_has_q && as.near_sym ? as.inc_len : 0;
             info->l2p_points = far ? as.l2p_points : 0;
+            if (far)
+                for (int l = pl->lmin + 1; l <= pl->L; ++l) info->l2l_children += as.l2l_count[l];
             info->p2m_points = far ? (pl->last_has_q ? pl->toff[1] - pl->toff[0] : 0) +
                                          (pl->last_has_d ? pl->toff[2] - pl->toff[1] : 0)
                                    : 0;

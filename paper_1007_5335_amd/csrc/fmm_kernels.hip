@@ -880,18 +880,24 @@ __global__ __launch_bounds__(256) void k_tile_gemm(const int4 *__restrict__ tile
         // operator column-major: A[i][k] = As[k * LDA + i]; step (kp, e) takes
         // contraction index 8 kp + 2 g + e in lane group g; each operator
         // fragment read from LDS serves the CB column blocks
+        // (the fragments of step s are read two steps ahead, into a ring of
+        // three, so the matrix cores do not wait on LDS between steps)
         const T *Ac = As[cur] + 2 * g * LDA + (lane & 15);
+        constexpr int NS = 2 * NKP;   // steps; step s = 2 kp + e
+        T afr[3][NB];
+        auto read_a = [&](int st, T *dst) {
 #pragma unroll
-        for (int kp = 0; kp < NKP; ++kp) {
+            for (int rt = 0; rt < NB; ++rt) dst[rt] = Ac[(8 * (st >> 1) + (st & 1)) * LDA + 16 * rt];
+        };
+        read_a(0, afr[0]);
+        if (NS > 1) read_a(1, afr[1]);
 #pragma unroll
-            for (int e = 0; e < 2; ++e) {
+        for (int st = 0; st < NS; ++st) {
+            if (st + 2 < NS) read_a(st + 2, afr[(st + 2) % 3]);
 #pragma unroll
-                for (int rt = 0; rt < NB; ++rt) {
-                    const T a = Ac[(8 * kp + e) * LDA + 16 * rt];
+            for (int rt = 0; rt < NB; ++rt)
 #pragma unroll
-                    for (int c = 0; c < CB; ++c) acc[c][rt] = MF::step(a, bcur[c][2 * kp + e], acc[c][rt]);
-                }
-            }
+                for (int c = 0; c < CB; ++c) acc[c][rt] = MF::step(afr[st % 3][rt], bcur[c][st], acc[c][rt]);
         }
         if constexpr (SPLIT) {
             const T *A = As[cur];
@@ -2352,10 +2358,10 @@ void fmm_run(Context &ctx, FmmPlan &pl, const double *q, const double *dn, doubl
                                                       pl.m2lf.p, (int64_t)kNumOff * Pp * Pp, 0, pl.Mf.p, 0,
                                                       pl.Lc.p, nullptr, &slab);
                 else
-                    launch_tile_gemm<double, double>(ctx, P, Pp, as.n_tiles, as.m2l_tiles.p, 0, as.m2l_boxes.p,
-                                                     kNumV, pl.vlist.p, pl.slot_oid.p, pl.m2l.p,
-                                                     (int64_t)kNumOff * Pp * Pp, 0, pl.M.p, 0, pl.Lc.p, nullptr,
-                                                     &slab);
+                    launch_tile_gemm<double, double, 1>(ctx, P, Pp, as.n_tiles, as.m2l_tiles.p, 0,
+                                                        as.m2l_boxes.p, kNumV, pl.vlist.p, pl.slot_oid.p, pl.m2l.p,
+                                                        (int64_t)kNumOff * Pp * Pp, 0, pl.M.p, 0, pl.Lc.p, nullptr,
+                                                        &slab);
             }
             StageTimer tl2(ctx, YK_STAGE_L2L);
             for (int l = pl.lmin + 1; l <= L; ++l) {

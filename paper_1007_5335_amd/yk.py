@@ -79,7 +79,8 @@ class yk_plan_info(ctypes.Structure):
                 ("build_ms", ctypes.c_double), ("m2l_sparse", ctypes.c_int32),
                 ("near_sym", ctypes.c_int32), ("near_charge_values", ctypes.c_int64),
                 ("near_incoming", ctypes.c_int64), ("p_initial", ctypes.c_int32),
-                ("order_check_err", ctypes.c_double)]
+                ("order_check_err", ctypes.c_double), ("m2m_children", ctypes.c_int64),
+                ("l2l_children", ctypes.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -108,6 +109,9 @@ def load_library(path: str = LIB_PATH):
     if not os.path.exists(path):
         raise ImportError(f"libyk.so not found at {path}; build it with "
                           f"`python -m paper_1007_5335_amd.build` (no fallback exists)")
+    # torch brings its own HIP runtime; loaded first, it is the one libyk
+    # binds to (loaded the other way round, the library's calls find no device)
+    import torch  # noqa: F401
     lib = ctypes.CDLL(path)
     vp, i64, dbl, ip = ctypes.c_void_p, ctypes.c_int64, ctypes.c_double, ctypes.c_int
     P = ctypes.POINTER
@@ -222,9 +226,10 @@ def yk_create(opt: yk_options | None = None, **kw):
     for k, v in kw.items():
         setattr(opt, k, v)
     h = ctypes.c_void_p()
-    st = load_library().yk_create(ctypes.byref(opt), ctypes.byref(h))
+    lib = load_library()
+    st = lib.yk_create(ctypes.byref(opt), ctypes.byref(h))
     if st != YK_OK:
-        raise YkError(st, "yk_create failed")
+        raise YkError(st, "yk_create failed: " + lib.yk_last_error(None).decode(errors="replace"))
     import torch
     yk_set_stream(h, torch.cuda.current_stream())
     return h
