@@ -349,6 +349,10 @@ typedef struct {
                                  (non-empty children of the boxes at levels lmin..L-1) */
     int64_t l2l_children;     /* parent-to-child translations of the downward pass of
                                  the last evaluation (its active boxes at levels > lmin) */
+    int64_t n_ulist;          /* U-list entries of the leaves (yk_plan_tree_export) */
+    double tables_ms;         /* host time spent on the translation operator tables
+                                 (each order tried by the order check) */
+    double order_check_ms;    /* time of the build-time order check (within build_ms) */
 } yk_plan_info;
 
 enum {
@@ -358,6 +362,31 @@ enum {
 };
 
 yk_status yk_plan_info_get(yk_ctx ctx, int slot, yk_plan_info *info);
+/*
+ * The tree cached in `slot`, for checking its construction (Sec. 3.1's
+ * quad-tree, built from Morton keys).  Every pointer may be NULL (skipped);
+ * sizes come from yk_plan_info_get.
+ *   square       HOST [3]: x0, y0, side of the bounding square; a point's
+ *                level-15 cell is floor((x - x0) 2^15 / side), clamped to
+ *                [0, 2^15), and its key is (set << 30) | Morton(cell)
+ *   level_begin  HOST [leaf_level + 2]: first box index of each level, then n_boxes
+ *   keys         DEVICE [n_points] sorted keys (sets 0 charges, 1 nodes, 2 targets)
+ *   perm         DEVICE [n_points] index of each sorted point within its set
+ *   box_code     DEVICE [n_boxes] Morton code of each box at its level
+ *   parent       DEVICE [n_boxes] parent box (-1 at level 0)
+ *   leaf_range   DEVICE [n_leaves][6] first and one-past-last sorted position
+ *                of each set in each leaf (0, 0 when empty)
+ *   ulist_off    DEVICE [n_leaves + 1], ulist DEVICE [n_ulist]: leaf-local
+ *                indices of the non-empty leaves of each leaf's 3 x 3 block,
+ *                row by row
+ *   vlist        DEVICE [n_boxes][27]: the V list in the slot order of the
+ *                box's parity class (dy outer, dx inner over the 6 x 6 block
+ *                of the parent's neighbours' children minus the 3 x 3 block),
+ *                -1 where absent and at levels below max(lmin, 2)
+ */
+yk_status yk_plan_tree_export(yk_ctx ctx, int slot, double *square, int64_t *level_begin, uint32_t *keys,
+                              int32_t *perm, uint32_t *box_code, int32_t *parent, int32_t *leaf_range,
+                              int32_t *ulist_off, int32_t *ulist, int32_t *vlist);
 yk_status yk_timing_enable(yk_ctx ctx, int enable);
 yk_status yk_timing_read(yk_ctx ctx, double ms[YK_NUM_STAGES], int64_t calls[YK_NUM_STAGES],
                          int reset);

@@ -941,6 +941,9 @@ yk_status yk_plan_info_get(yk_ctx ctx, int slot, yk_plan_info *info) {
         info->n_boxes = pl->nbox;
         info->n_leaves = pl->nleaf;
         info->build_ms = pl->build_ms;
+        info->n_ulist = pl->n_ulist;
+        info->tables_ms = pl->tables_ms;
+        info->order_check_ms = pl->check_ms;
         info->p_initial = pl->calib_p0;
         info->order_check_err = pl->calib_err;
         if (pl->lmin <= pl->L) {
@@ -967,6 +970,36 @@ yk_status yk_plan_info_get(yk_ctx ctx, int slot, yk_plan_info *info) {
                                          (pl->last_has_d ? pl->toff[2] - pl->toff[1] : 0)
                                    : 0;
         }
+        return YK_OK;
+    });
+}
+
+yk_status yk_plan_tree_export(yk_ctx ctx, int slot, double *square, int64_t *level_begin, uint32_t *keys,
+                              int32_t *perm, uint32_t *box_code, int32_t *parent, int32_t *leaf_range,
+                              int32_t *ulist_off, int32_t *ulist, int32_t *vlist) {
+    return guarded(ctx, [&](Context &c) {
+        YK_REQUIRE(slot >= 0 && slot <= 2, "slot must be 0, 1 or 2");
+        const FmmPlan *pl = plan_in_slot(c, slot);
+        YK_REQUIRE(pl != nullptr, "no tree is cached in this slot");
+        auto copy = [&](void *dst, const void *src, size_t bytes) {
+            if (dst && bytes) YK_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, c.stream));
+        };
+        if (square) {
+            square[0] = pl->x0;
+            square[1] = pl->y0;
+            square[2] = pl->size;
+        }
+        if (level_begin)
+            for (int l = 0; l <= pl->L + 1; ++l) level_begin[l] = l <= pl->L ? pl->lev[l].begin : pl->nbox;
+        copy(keys, pl->skeys.p, (size_t)pl->N * sizeof(uint32_t));
+        copy(perm, pl->perm.p, (size_t)pl->N * sizeof(int32_t));
+        copy(box_code, pl->bcode.p, (size_t)pl->nbox * sizeof(uint32_t));
+        copy(parent, pl->bparent.p, (size_t)pl->nbox * sizeof(int32_t));
+        copy(leaf_range, pl->lrange.p, (size_t)pl->nleaf * 6 * sizeof(int32_t));
+        copy(ulist_off, pl->ulist_off.p, (size_t)(pl->nleaf + 1) * sizeof(int32_t));
+        copy(ulist, pl->ulist.p, (size_t)pl->n_ulist * sizeof(int32_t));
+        copy(vlist, pl->vlist.p, (size_t)pl->nbox * kNumV * sizeof(int32_t));
+        YK_HIP(hipStreamSynchronize(c.stream));
         return YK_OK;
     });
 }

@@ -89,6 +89,14 @@ struct ActiveSet {
     DevBuf<int32_t> inc_cnt;
     DevBuf<double> inc;
     int64_t inc_len = 0;
+    // the cache's layout (offsets, symmetric slots, descriptors) is built on
+    // the first evaluation that reads the cache (ensure_near_layout), from
+    // these host copies
+    bool layout = false;
+    int mask = 0;
+    std::vector<int2> h_items;
+    std::vector<int64_t> h_sq, h_sd, h_tcnt;   // per leaf: neighbouring charges, dipoles; targets
+    std::vector<int32_t> h_uoff, h_ul;         // U lists (CSR)
 };
 
 struct FmmPlan {
@@ -139,6 +147,8 @@ struct FmmPlan {
     DevBuf<int32_t> ulist_off, ulist;  // CSR over leaves (leaf-local indices)
     std::vector<int32_t> h_lrange;     // host copy
     DevBuf<int32_t> pleaf;             // [N] leaf (level-local index) of every sorted point
+    DevBuf<uint32_t> skeys;            // [N] sorted keys (set << 30 | Morton code at level 15)
+    int64_t n_ulist = 0;               // U-list entries
     DevBuf<int32_t> dleaves;           // leaves (level-local) that hold dipole sources
     int64_t n_dleaves = 0;
     bool mq_kept = false;              // M's leaf level holds a charges-only pass's multipoles (keep_charge_m)
@@ -163,6 +173,7 @@ struct FmmPlan {
     // the tolerance and the largest sampled error of the order kept (-1: not run)
     int calib_p0 = 0;
     double calib_err = -1.0;
+    double tables_ms = 0, check_ms = 0;   // host time of the operator tables, of the order check
     int mask_all() const {
         int m = 0;
         for (int s = 0; s < 3; ++s)
@@ -180,9 +191,15 @@ FmmPlan *plan_in_slot(Context &ctx, int slot);
 void build_tree(Context &ctx, FmmPlan &pl, const SumProblem &pb);
 // fmm_plan.cpp: boxes and lists from the sorted keys, then the translation
 // operators and expansion tables of order p (rebuilt when p changes)
-void build_lists(Context &ctx, FmmPlan &pl, const std::vector<uint32_t> &keys);
+void build_lists(Context &ctx, FmmPlan &pl, const std::vector<uint32_t> &keys, const uint32_t *dkeys);
+// lists.hip: the GPU parts of build_lists and get_active
+void gpu_point_leaves(Context &ctx, FmmPlan &pl, const uint32_t *dkeys, const uint32_t *dleaf_codes);
+void gpu_ulists(Context &ctx, FmmPlan &pl, const uint32_t *dleaf_codes);
+void gpu_vlists(Context &ctx, FmmPlan &pl);
+int64_t gpu_count_slots(Context &ctx, FmmPlan &pl, const int32_t *dboxes, int64_t n);
 void build_tables(Context &ctx, FmmPlan &pl, int p);
 ActiveSet &get_active(Context &ctx, FmmPlan &pl, int mask);
+void ensure_near_layout(Context &ctx, FmmPlan &pl, ActiveSet &as);
 // expansion orders with kernels: the smallest one >= p (at most kMaxOrder)
 constexpr int kNumOrders = 7;
 constexpr int kOrders[kNumOrders] = {8, 12, 16, 20, 24, 28, 31};
@@ -196,8 +213,9 @@ void calibrate_order(Context &ctx, FmmPlan &pl, const SumProblem &pb);
 
 // fmm_kernels.hip
 // bie (optional): the double-layer operator fused in (dn is then unused)
+// parts: 1 the near field only, 2 the far field only, 3 both (the sums)
 void fmm_run(Context &ctx, FmmPlan &pl, const double *q, const double *dn, double *const out[3],
-             SumPrec prec, const BieFuse *bie = nullptr, int keep_charge_m = 0);
+             SumPrec prec, const BieFuse *bie = nullptr, int keep_charge_m = 0, int parts = 3);
 
 // The tree of a slot for this problem (built, or rebuilt when stale).
 FmmPlan &get_plan(Context &ctx, PlanSlot slot, const SumProblem &pb);

@@ -2048,7 +2048,7 @@ LeafKernel pick_leaf_kernel(int nt, bool small_only, bool f32) {
 }  // namespace
 
 void fmm_run(Context &ctx, FmmPlan &pl, const double *q, const double *dn, double *const out[3],
-             SumPrec prec, const BieFuse *bie, int keep_charge_m) {
+             SumPrec prec, const BieFuse *bie, int keep_charge_m, int parts) {
     int mask = 0;
     for (int s = 0; s < 3; ++s)
         if (out[s] && pl.toff[s + 1] > pl.toff[s]) mask |= 1 << s;
@@ -2085,7 +2085,10 @@ void fmm_run(Context &ctx, FmmPlan &pl, const double *q, const double *dn, doubl
     }
     }
     ActiveSet &as = get_active(ctx, pl, mask);
-    const bool far = pl.lmin <= L && (has_q || has_d);
+    // parts: bit 0 the near field, bit 1 the far field (the order check
+    // evaluates them apart; the near field alone is then evaluated on the fly)
+    const bool far = pl.lmin <= L && (has_q || has_d) && (parts & 2);
+    const bool near_on = (parts & 1) != 0;
     const int64_t leaf_base = pl.lev[L].begin;
 
     // near field: independent of the far field until L2P, so it runs on the
@@ -2093,11 +2096,15 @@ void fmm_run(Context &ctx, FmmPlan &pl, const double *q, const double *dn, doubl
     // which would otherwise be starved of compute units)
     // (only for small trees: with a large one both streams fill the GPU and
     // sharing it was measured slower than running the stages in turn)
-    const bool overlap = !(ctx.opt.debug_flags & 2) && pl.nleaf < 8192;
+    const bool overlap = !(ctx.opt.debug_flags & 2) && pl.nleaf < 8192 && near_on;
     bool near_done = false;
     const double *sym_inc = nullptr;   // incoming slots of the symmetric near field (for k_l2p)
     auto launch_near = [&]() {
         near_done = true;
+        if (!near_on) {   // far field alone: L2P adds it to zeros
+            launch_fill(ctx, pl.N, 0.0, outs);
+            return;
+        }
         if (overlap) {
             ensure_side_stream(ctx);
             YK_HIP(hipEventRecord(ctx.ev_fork, ctx.stream));
@@ -2108,9 +2115,13 @@ void fmm_run(Context &ctx, FmmPlan &pl, const double *q, const double *dn, doubl
             const double tmax = 2.0 * pl.lev[L].side * pl.lev[L].side * inv_alpha * inv_alpha;
             const bool f32 = prec == SUM_FP32, small_only = tmax <= 1.0;
             const int q_on = n0 > 0 ? 1 : 0, d_on = n1 > 0 ? 1 : 0;
+            // (the near field alone, without the far field's L2P, cannot use the
+            // symmetric cache's incoming slots: it is evaluated on the fly)
+            const bool want_cache = ctx.opt.near_cache_mb > 0 && (parts & 2);
+            if (want_cache) ensure_near_layout(ctx, pl, as);
             const int64_t entries = as.near_q_len + 2 * as.near_d_len;
             const int64_t bytes = entries * (f32 ? 4 : 8);
-            const bool cache = ctx.opt.near_cache_mb > 0 && bytes <= ((int64_t)ctx.opt.near_cache_mb << 20);
+            const bool cache = want_cache && bytes <= ((int64_t)ctx.opt.near_cache_mb << 20);
             if (cache) {
                 bool &built = f32 ? as.near32 : as.near64;
                 if (!built && as.near_sym) {

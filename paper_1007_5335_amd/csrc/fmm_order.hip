@@ -70,6 +70,12 @@ __global__ void k_take(int64_t k, const int64_t *__restrict__ idx, const double 
 }  // namespace
 
 void calibrate_order(Context &ctx, FmmPlan &pl, const SumProblem &pb) {
+    const auto t_start = std::chrono::steady_clock::now();
+    struct Done {   // records the check's time however it ends
+        FmmPlan &pl;
+        std::chrono::steady_clock::time_point t0;
+        ~Done() { pl.check_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count(); }
+    } done{pl, t_start};
     pl.calib_err = -1.0;
     pl.calib_p0 = pl.p;
     if (pl.opt_p > 0 || pl.lmin > pl.L) return;   // order given, or no far field
@@ -105,36 +111,52 @@ void calibrate_order(Context &ctx, FmmPlan &pl, const SumProblem &pb) {
     double *outs[3] = {nullptr, nullptr, nullptr};
     for (int s = 0; s < 3; ++s)
         if (pb.n[s] > 0) outs[s] = outbuf[s].ensure(pb.n[s]);
-    double *dref = ref.ensure(K), *dgot = got.ensure(K);
-    std::vector<double> href(K), hgot(K);
+    double *dref = ref.ensure(2 * K), *dgot = got.ensure(K);
+    std::vector<double> href(2 * K), hnear(2 * K), hfar(K);
     // the probes run without the near-field cache (evaluated on the fly, so
-    // no cache is built for a target set later calls may never use) and
-    // leave no work lists behind
+    // no cache is built for a target set later calls may never use); their
+    // work lists (every set a target) stay for later calls with that mask
     const int cache_mb = ctx.opt.near_cache_mb;
-    const bool had_set = pl.active.count(pl.mask_all()) > 0;
     ctx.opt.near_cache_mb = 0;
-    // probe 0: charges alone; probe 1: dipoles alone
-    auto measure = [&](int probe) -> double {
-        const double *pq = probe == 0 ? q : nullptr;
-        const double *pd = probe == 1 ? dn : nullptr;
-        if (!pq && !pd) return 0.0;
-        fmm_run(ctx, pl, pq, pd, outs, SUM_FP64);
-        launch_direct(ctx, K, dtxy, pq ? n0 : 0, pb.xy[0], pq, pd ? n1 : 0, pb.xy[1], pd, pl.alpha, dref, false);
+    // probe 0: charges alone; probe 1: dipoles alone.  The direct sums and
+    // the near field do not depend on the order: they are evaluated once;
+    // each order tried evaluates the far field alone.
+    auto sample = [&](double *dst_host) {
         for (int s = 0; s < 3; ++s)
             if (kcount[s] > 0)
                 hipLaunchKernelGGL(k_take, dim3(nblk(kcount[s], 256)), dim3(256), 0, ctx.stream, kcount[s],
                                    didx.p + kbase[s], outs[s], 1, dgot + kbase[s]);
         check_launch(ctx, "k_take");
-        YK_HIP(hipMemcpyAsync(href.data(), dref, K * sizeof(double), hipMemcpyDeviceToHost, ctx.stream));
-        YK_HIP(hipMemcpyAsync(hgot.data(), dgot, K * sizeof(double), hipMemcpyDeviceToHost, ctx.stream));
+        YK_HIP(hipMemcpyAsync(dst_host, dgot, K * sizeof(double), hipMemcpyDeviceToHost, ctx.stream));
         YK_HIP(hipStreamSynchronize(ctx.stream));
+    };
+    bool present[2] = {q != nullptr, dn != nullptr};
+    for (int probe = 0; probe < 2; ++probe) {
+        if (!present[probe]) continue;
+        const double *pq = probe == 0 ? q : nullptr;
+        const double *pd = probe == 1 ? dn : nullptr;
+        launch_direct(ctx, K, dtxy, pq ? n0 : 0, pb.xy[0], pq, pd ? n1 : 0, pb.xy[1], pd, pl.alpha,
+                      dref + probe * K, false);
+        YK_HIP(hipMemcpyAsync(href.data() + probe * K, dref + probe * K, K * sizeof(double),
+                              hipMemcpyDeviceToHost, ctx.stream));
+        fmm_run(ctx, pl, pq, pd, outs, SUM_FP64, nullptr, 0, 1);
+        sample(hnear.data() + probe * K);
+    }
+    auto measure = [&](int probe) -> double {
+        if (!present[probe]) return 0.0;
+        const double *pq = probe == 0 ? q : nullptr;
+        const double *pd = probe == 1 ? dn : nullptr;
+        fmm_run(ctx, pl, pq, pd, outs, SUM_FP64, nullptr, 0, 2);
+        sample(hfar.data());
+        const double *rf = href.data() + probe * K, *nr = hnear.data() + probe * K;
         double ss = 0.0;
-        for (int64_t k = 0; k < K; ++k) ss += href[k] * href[k];
+        for (int64_t k = 0; k < K; ++k) ss += rf[k] * rf[k];
         const double floor = 0.1 * std::sqrt(ss / (double)K);
         double worst = 0.0;
         for (int64_t k = 0; k < K; ++k) {
-            const double den = std::max(std::fabs(href[k]), floor);
-            const double e = den > 0.0 ? std::fabs(hgot[k] - href[k]) / den : std::fabs(hgot[k] - href[k]);
+            const double den = std::max(std::fabs(rf[k]), floor);
+            const double d = std::fabs(nr[k] + hfar[k] - rf[k]);
+            const double e = den > 0.0 ? d / den : d;
             if (!std::isfinite(e)) return INFINITY;
             worst = std::max(worst, e);
         }
@@ -159,7 +181,6 @@ void calibrate_order(Context &ctx, FmmPlan &pl, const SumProblem &pb) {
         throw;
     }
     ctx.opt.near_cache_mb = cache_mb;
-    if (!had_set) pl.active.erase(pl.mask_all());
     pl.mq_kept = false;
 }
 

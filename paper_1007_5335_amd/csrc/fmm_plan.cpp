@@ -9,8 +9,12 @@
 // Levels whose boxes are wider than 40 alpha get no M2L: across such a gap
 // the kernel is below K0(40) ~ 1e-18.
 #include <algorithm>
+#include <array>
+#include <atomic>
+#include <chrono>
 #include <cmath>
 #include <complex>
+#include <thread>
 
 #include "fmm.h"
 #include "yk_bessel.h"
@@ -44,12 +48,6 @@ inline uint32_t encode(uint32_t ix, uint32_t iy) { return spread(ix) | (spread(i
 inline void decode(uint32_t c, uint32_t &ix, uint32_t &iy) {
     ix = compact15(c);
     iy = compact15(c >> 1);
-}
-
-int64_t find_code(const std::vector<uint32_t> &codes, int64_t lo, int64_t hi, uint32_t c) {
-    auto it = std::lower_bound(codes.begin() + lo, codes.begin() + hi, c);
-    if (it != codes.begin() + hi && *it == c) return it - codes.begin();
-    return -1;
 }
 
 // F_n(y) = sum_k y^k / (k! (n+1)_k), so that I_n(x) = (x/2)^n / n! F_n(x^2/4).
@@ -110,6 +108,21 @@ void to_real(const std::vector<cld> &C, int p, int Pp, double *out) {
 
 inline cld cis(ld phi, int m) { return std::polar((ld)1, phi * (ld)m); }
 
+// f(i0, i1) on contiguous chunks of [0, n) on up to 16 host threads
+template <typename F>
+void parallel_for(int64_t n, F f) {
+    const int64_t nt = std::max<int64_t>(1, std::min<int64_t>({16, (int64_t)std::thread::hardware_concurrency(),
+                                                                (n + 65535) / 65536}));
+    if (nt <= 1) {
+        f((int64_t)0, n);
+        return;
+    }
+    const int64_t per = (n + nt - 1) / nt;
+    std::vector<std::thread> pool;
+    for (int64_t t = 0; t < nt && t * per < n; ++t) pool.emplace_back(f, t * per, std::min(n, (t + 1) * per));
+    for (auto &th : pool) th.join();
+}
+
 }  // namespace
 
 int supported_order(int p) {
@@ -128,7 +141,7 @@ int choose_order(double tol) {
     return supported_order(std::max(1, p));
 }
 
-void build_lists(Context &ctx, FmmPlan &pl, const std::vector<uint32_t> &keys) {
+void build_lists(Context &ctx, FmmPlan &pl, const std::vector<uint32_t> &keys, const uint32_t *dkeys) {
     const int64_t N = pl.N;
     const uint32_t kMask = 0x3fffffffu;
     // ---- merged Morton codes (each set's block is sorted) ----
@@ -162,26 +175,27 @@ void build_lists(Context &ctx, FmmPlan &pl, const std::vector<uint32_t> &keys) {
     std::vector<std::vector<uint32_t>> codes(kMaxLevel + 1);
     std::vector<double> occ(kMaxLevel + 1, 0.0);
     {
-        std::vector<uint32_t> c = uniq15;
-        std::vector<int64_t> n = cnt15;
+        // coarsen the (code, count) runs in place, level by level
+        std::vector<uint32_t> &c = uniq15;
+        std::vector<int64_t> &n = cnt15;
         for (int l = kMaxLevel; l >= 0; --l) {
             double s2 = 0;
             for (int64_t v : n) s2 += (double)v * (double)v;
             occ[l] = s2 / (double)N;
-            codes[l] = c;
             if (l == 0) break;
-            std::vector<uint32_t> c2;
-            std::vector<int64_t> n2;
+            size_t m = 0;
             for (size_t k = 0; k < c.size(); ++k) {
                 const uint32_t v = c[k] >> 2;
-                if (c2.empty() || c2.back() != v) {
-                    c2.push_back(v);
-                    n2.push_back(0);
+                if (m > 0 && c[m - 1] == v) {
+                    n[m - 1] += n[k];
+                } else {
+                    c[m] = v;
+                    n[m] = n[k];
+                    ++m;
                 }
-                n2.back() += n[k];
             }
-            c.swap(c2);
-            n.swap(n2);
+            c.resize(m);
+            n.resize(m);
         }
     }
     int L = kMaxLevel;
@@ -220,6 +234,9 @@ void build_lists(Context &ctx, FmmPlan &pl, const std::vector<uint32_t> &keys) {
     pl.hparent.assign(nb, -1);
     std::vector<double> cx(nb), cy(nb);
     for (int l = 0; l <= L; ++l) {
+        // parents by a merge of the two sorted code lists (each parent code
+        // is the child's code without its last two bits)
+        int64_t pi = 0;
         for (size_t k = 0; k < codes[l].size(); ++k) {
             const int64_t gidx = pl.lev[l].begin + (int64_t)k;
             pl.hcode[gidx] = codes[l][k];
@@ -228,7 +245,7 @@ void build_lists(Context &ctx, FmmPlan &pl, const std::vector<uint32_t> &keys) {
             cx[gidx] = pl.x0 + (ix + 0.5) * pl.lev[l].side;
             cy[gidx] = pl.y0 + (iy + 0.5) * pl.lev[l].side;
             if (l > 0) {
-                const int64_t pi = find_code(codes[l - 1], 0, (int64_t)codes[l - 1].size(), codes[l][k] >> 2);
+                while (codes[l - 1][pi] != (codes[l][k] >> 2)) ++pi;
                 pl.hparent[gidx] = (int32_t)(pl.lev[l - 1].begin + pi);
             }
         }
@@ -237,62 +254,18 @@ void build_lists(Context &ctx, FmmPlan &pl, const std::vector<uint32_t> &keys) {
     int lmin = 2;
     while (lmin <= L && pl.lev[lmin].side >= kFarCut * pl.alpha) ++lmin;
     pl.lmin = lmin;
-    // ---- leaf ranges per set ----
-    pl.h_lrange.assign((size_t)pl.nleaf * 6, 0);
-    for (int s = 0; s < 3; ++s) {
-        int64_t k = pl.toff[s];
-        const int64_t e = pl.toff[s + 1];
-        while (k < e) {
-            const uint32_t lc = (keys[k] & kMask) >> (2 * (kMaxLevel - L));
-            int64_t k2 = k;
-            while (k2 < e && ((keys[k2] & kMask) >> (2 * (kMaxLevel - L))) == lc) ++k2;
-            const int64_t li = find_code(codes[L], 0, pl.nleaf, lc);
-            if (li < 0) throw Error{YK_ERR_INTERNAL, "leaf code not found"};
-            pl.h_lrange[(size_t)li * 6 + 2 * s] = (int32_t)k;
-            pl.h_lrange[(size_t)li * 6 + 2 * s + 1] = (int32_t)k2;
-            k = k2;
-        }
-    }
-    // ---- U-lists ----
-    std::vector<int32_t> uoff(pl.nleaf + 1, 0), ul;
-    ul.reserve((size_t)pl.nleaf * 9);
-    const int64_t nside = (int64_t)1 << L;
-    for (int64_t li = 0; li < pl.nleaf; ++li) {
-        uint32_t ix, iy;
-        decode(codes[L][li], ix, iy);
-        for (int dy = -1; dy <= 1; ++dy)
-            for (int dx = -1; dx <= 1; ++dx) {
-                const int64_t jx = (int64_t)ix + dx, jy = (int64_t)iy + dy;
-                if (jx < 0 || jy < 0 || jx >= nside || jy >= nside) continue;
-                const int64_t j = find_code(codes[L], 0, pl.nleaf, encode((uint32_t)jx, (uint32_t)jy));
-                if (j >= 0) ul.push_back((int32_t)j);
-            }
-        uoff[li + 1] = (int32_t)ul.size();
-    }
-    // ---- V-lists (27 slots per box, in class order) ----
-    std::vector<int32_t> vl((size_t)nb * kNumV, -1);
-    for (int l = std::max(lmin, 2); l <= L; ++l) {
-        const int64_t ns = (int64_t)1 << l;
-        for (size_t k = 0; k < codes[l].size(); ++k) {
-            uint32_t ix, iy;
-            decode(codes[l][k], ix, iy);
-            const int cxs = ix & 1, cys = iy & 1;
-            int slot = 0;
-            for (int dy = -2 - cys; dy <= 3 - cys; ++dy)
-                for (int dx = -2 - cxs; dx <= 3 - cxs; ++dx) {
-                    if (std::abs(dx) <= 1 && std::abs(dy) <= 1) continue;
-                    const int64_t jx = (int64_t)ix + dx, jy = (int64_t)iy + dy;
-                    int32_t src = -1;
-                    if (jx >= 0 && jy >= 0 && jx < ns && jy < ns) {
-                        const int64_t j = find_code(codes[l], 0, (int64_t)codes[l].size(),
-                                                    encode((uint32_t)jx, (uint32_t)jy));
-                        if (j >= 0) src = (int32_t)(pl.lev[l].begin + j);
-                    }
-                    vl[(pl.lev[l].begin + (int64_t)k) * kNumV + slot] = src;
-                    ++slot;
-                }
-        }
-    }
+    auto up = [&](auto &buf, const auto &vec) {
+        using T = typename std::decay_t<decltype(vec)>::value_type;
+        T *d = buf.ensure(vec.size());
+        YK_HIP(hipMemcpyAsync(d, vec.data(), vec.size() * sizeof(T), hipMemcpyHostToDevice, ctx.stream));
+    };
+    up(pl.bcode, pl.hcode);
+    const uint32_t *dleaf_codes = pl.bcode.p + pl.lev[L].begin;
+    // ---- on the GPU: each point's leaf and the leaves' ranges per set, the
+    //      U lists of the leaves and the V lists of every box (lists.hip) ----
+    gpu_point_leaves(ctx, pl, dkeys, dleaf_codes);
+    gpu_ulists(ctx, pl, dleaf_codes);
+    gpu_vlists(ctx, pl);
     // ---- children (contiguous at the next level because codes are sorted) ----
     std::vector<int32_t> fch(nb, -1), nch(nb, 0);
     for (int64_t b = 0; b < nb; ++b) {
@@ -339,15 +312,9 @@ void build_lists(Context &ctx, FmmPlan &pl, const std::vector<uint32_t> &keys) {
             }
     }
     // ---- upload tree ----
-    auto up = [&](auto &buf, const auto &vec) {
-        using T = typename std::decay_t<decltype(vec)>::value_type;
-        T *d = buf.ensure(vec.size());
-        YK_HIP(hipMemcpyAsync(d, vec.data(), vec.size() * sizeof(T), hipMemcpyHostToDevice, ctx.stream));
-    };
     up(pl.bcx, cx);
     up(pl.bcy, cy);
     up(pl.bparent, pl.hparent);
-    up(pl.bcode, pl.hcode);
     up(pl.fchild, fch);
     up(pl.nchild, nch);
     up(pl.slot_oid, soid);
@@ -363,8 +330,6 @@ void build_lists(Context &ctx, FmmPlan &pl, const std::vector<uint32_t> &keys) {
         up(pl.up_tiles, utiles);
         up(pl.up_boxes, uboxes);
     }
-    up(pl.vlist, vl);
-    up(pl.lrange, pl.h_lrange);
     {
         std::vector<int32_t> dl;
         for (int64_t li = 0; li < pl.nleaf; ++li)
@@ -372,20 +337,13 @@ void build_lists(Context &ctx, FmmPlan &pl, const std::vector<uint32_t> &keys) {
         pl.n_dleaves = (int64_t)dl.size();
         if (!dl.empty()) up(pl.dleaves, dl);
     }
-    {
-        std::vector<int32_t> hp((size_t)pl.N, 0);
-        for (int64_t li = 0; li < pl.nleaf; ++li)
-            for (int s = 0; s < 3; ++s)
-                for (int32_t t = pl.h_lrange[(size_t)li * 6 + 2 * s]; t < pl.h_lrange[(size_t)li * 6 + 2 * s + 1]; ++t)
-                    hp[(size_t)t] = (int32_t)li;
-        up(pl.pleaf, hp);
-    }
-    up(pl.ulist_off, uoff);
-    up(pl.ulist, ul);
+    // the sorted keys (kept for introspection)
+    YK_HIP(hipMemcpyAsync(pl.skeys.ensure(N), dkeys, N * sizeof(uint32_t), hipMemcpyDeviceToDevice, ctx.stream));
     YK_HIP(hipStreamSynchronize(ctx.stream));
 }
 
 void build_tables(Context &ctx, FmmPlan &pl, int p) {
+    const auto t_start = std::chrono::steady_clock::now();
     const int L = pl.L, lmin = pl.lmin;
     const int64_t nb = pl.nbox;
     auto up = [&](auto &buf, const auto &vec) {
@@ -487,14 +445,25 @@ void build_tables(Context &ctx, FmmPlan &pl, int p) {
             to_real(C, p, Pp, &l2l[((size_t)l * 4 + c) * Pp * Pp]);
         }
     }
-    // M2L for levels lmin..L, 40 offsets (dy outer, dx inner over [-3,3]^2 minus [-1,1]^2)
+    // M2L for levels lmin..L, 40 offsets (dy outer, dx inner over [-3,3]^2
+    // minus [-1,1]^2); the (level, offset) operators are independent and are
+    // computed on several host threads
     std::vector<double> m2l((size_t)nL * kNumOff * Pp * Pp, 0.0);
-    for (int l = lmin; l <= L; ++l) {
-        const auto &I = IR[l];
-        int oid = 0;
-        for (int dy = -3; dy <= 3; ++dy)
-            for (int dx = -3; dx <= 3; ++dx) {
-                if (std::abs(dx) <= 1 && std::abs(dy) <= 1) continue;
+    {
+        std::vector<std::array<int, 4>> tasks;   // level, dx, dy, offset id
+        for (int l = lmin; l <= L; ++l) {
+            int oid = 0;
+            for (int dy = -3; dy <= 3; ++dy)
+                for (int dx = -3; dx <= 3; ++dx) {
+                    if (std::abs(dx) <= 1 && std::abs(dy) <= 1) continue;
+                    tasks.push_back({l, dx, dy, oid++});
+                }
+        }
+        auto work = [&](size_t t0, size_t t1) {
+            std::vector<cld> Ct((size_t)(p + 1) * nC);
+            for (size_t t = t0; t < t1; ++t) {
+                const int l = tasks[t][0], dx = tasks[t][1], dy = tasks[t][2], oid = tasks[t][3];
+                const auto &I = IR[l];
                 // d = (c_t - c_s)/alpha with the source at offset (dx, dy)
                 const double ddx = -dx * pl.lev[l].side / alpha, ddy = -dy * pl.lev[l].side / alpha;
                 const double dd = std::sqrt(ddx * ddx + ddy * ddy);
@@ -503,11 +472,17 @@ void build_tables(Context &ctx, FmmPlan &pl, int p) {
                 for (int m = 0; m <= p; ++m)
                     for (int n = -p; n <= p; ++n) {
                         const ld sgn = (m & 1) ? -1.0L : 1.0L;
-                        C[(size_t)m * nC + n + p] = sgn * I[m] * I[std::abs(n)] * K[std::abs(n - m)] * cis(phi, n - m);
+                        Ct[(size_t)m * nC + n + p] = sgn * I[m] * I[std::abs(n)] * K[std::abs(n - m)] * cis(phi, n - m);
                     }
-                to_real(C, p, Pp, &m2l[((size_t)l * kNumOff + oid) * Pp * Pp]);
-                ++oid;
+                to_real(Ct, p, Pp, &m2l[((size_t)l * kNumOff + oid) * Pp * Pp]);
             }
+        };
+        const size_t nt = std::max<size_t>(1, std::min<size_t>(16, std::thread::hardware_concurrency()));
+        const size_t per = (tasks.size() + nt - 1) / nt;
+        std::vector<std::thread> pool;
+        for (size_t i = 0; i < nt && i * per < tasks.size(); ++i)
+            pool.emplace_back(work, i * per, std::min(tasks.size(), (i + 1) * per));
+        for (auto &th : pool) th.join();
     }
     up(pl.m2m, m2m);
     up(pl.l2l, l2l);
@@ -521,6 +496,7 @@ void build_tables(Context &ctx, FmmPlan &pl, int p) {
     pl.M.ensure((size_t)nb * Pp);
     pl.Lc.ensure((size_t)nb * Pp);
     YK_HIP(hipStreamSynchronize(ctx.stream));
+    pl.tables_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
 }
 
 FmmPlan *plan_in_slot(Context &ctx, int slot) {
@@ -530,6 +506,152 @@ FmmPlan *plan_in_slot(Context &ctx, int slot) {
         case 2: return ctx.plan_misc.get();
         default: return nullptr;
     }
+}
+
+void ensure_near_layout(Context &ctx, FmmPlan &pl, ActiveSet &as_ref) {
+    if (as_ref.layout) return;
+    ActiveSet *as = &as_ref;
+    const int L = pl.L, mask = as->mask;
+    const std::vector<int32_t> &uoff = as->h_uoff, &ul = as->h_ul;
+    const std::vector<int64_t> &sq_leaf = as->h_sq, &sd_leaf = as->h_sd;
+    const std::vector<int2> &items = as->h_items;
+    auto tcnt = [&](int64_t li) { return as->h_tcnt[li]; };
+    {
+        // symmetric charge values
+        const int64_t n0 = pl.toff[1] - pl.toff[0];
+        // charges among the targets, at most 64 per leaf (so that they all
+        // fall in the leaf's first item, which they lead), and a far field
+        // (k_l2p adds the incoming slots)
+        auto n0_of = [&](int64_t li) -> int64_t { return pl.h_lrange[(size_t)li * 6 + 1] - pl.h_lrange[(size_t)li * 6]; };
+        bool sym = (mask & 1) && n0 > 0 && pl.lmin <= L && !(ctx.opt.debug_flags & 16);
+        for (int64_t li = 0; li < pl.nleaf && sym; ++li)
+            if (n0_of(li) > 64) sym = false;
+        if (sym) {
+            // incoming slots of leaf B: one per U-list neighbour A < B with
+            // charges, in B's U-list order, each n0(B) entries; the writer is
+            // A's U-list entry that names B
+            std::vector<int64_t> dst(ul.size(), -1), ibase(pl.nleaf, 0);
+            std::vector<int32_t> icnt(pl.nleaf, 0);
+            // (three passes: slots per leaf, their offsets, then each writer's
+            // destination; every entry of dst has exactly one writer)
+            parallel_for(pl.nleaf, [&](int64_t b0, int64_t b1) {
+                for (int64_t b = b0; b < b1; ++b) {
+                    int k = 0;
+                    for (int32_t u = uoff[b]; u < uoff[b + 1]; ++u)
+                        if (ul[u] < b && n0_of(ul[u]) > 0) ++k;
+                    icnt[b] = k;
+                }
+            });
+            int64_t off = 0;
+            for (int64_t b = 0; b < pl.nleaf; ++b) {
+                ibase[b] = off;
+                off += (int64_t)icnt[b] * n0_of(b);
+            }
+            std::atomic<bool> asym{false};
+            parallel_for(pl.nleaf, [&](int64_t b0, int64_t b1) {
+                for (int64_t b = b0; b < b1; ++b) {
+                    int k = 0;
+                    for (int32_t u = uoff[b]; u < uoff[b + 1]; ++u) {
+                        const int32_t a = ul[u];
+                        if (a >= b || n0_of(a) == 0) continue;
+                        int32_t ua = uoff[a];
+                        while (ua < uoff[a + 1] && ul[ua] != b) ++ua;
+                        if (ua == uoff[a + 1]) {
+                            asym = true;
+                            return;
+                        }
+                        dst[ua] = ibase[b] + (int64_t)k * n0_of(b);
+                        ++k;
+                    }
+                }
+            });
+            if (asym) throw Error{YK_ERR_INTERNAL, "U-lists are not symmetric"};
+            as->inc_len = off;
+            int64_t *db = as->inc_base.ensure(ibase.size());
+            int32_t *dc = as->inc_cnt.ensure(icnt.size());
+            YK_HIP(hipMemcpyAsync(db, ibase.data(), ibase.size() * sizeof(int64_t), hipMemcpyHostToDevice, ctx.stream));
+            YK_HIP(hipMemcpyAsync(dc, icnt.data(), icnt.size() * sizeof(int32_t), hipMemcpyHostToDevice, ctx.stream));
+            as->inc.ensure(std::max<int64_t>(off, 1));
+            // per-item descriptors (layout: kItemDesc in the near-field kernels)
+            constexpr int kDesc = 52;
+            const int q_on = 1, d_on = (pl.toff[2] > pl.toff[1]) ? 1 : 0;
+            std::vector<int32_t> desc(items.size() * kDesc, 0);
+            std::vector<int64_t> ddst(items.size() * 9, -1);
+            parallel_for((int64_t)items.size(), [&](int64_t i0, int64_t i1) {
+            for (int64_t i = i0; i < i1; ++i) {
+                const int32_t li = items[i].x;
+                int32_t *d = desc.data() + i * kDesc;
+                const int32_t u0 = uoff[li], nu = uoff[li + 1] - u0;
+                for (int u = 0; u < 9 && u < nu; ++u) {
+                    const int32_t b = ul[u0 + u];
+                    const int32_t *r = pl.h_lrange.data() + (size_t)b * 6;
+                    d[u] = r[0];
+                    d[9 + u] = q_on ? r[1] - r[0] : 0;
+                    d[18 + u] = (q_on && b >= li) ? r[1] - r[0] : 0;
+                    d[27 + u] = r[2];
+                    d[36 + u] = d_on ? r[3] - r[2] : 0;
+                    ddst[i * 9 + u] = dst[u0 + u];
+                }
+                const int32_t *r = pl.h_lrange.data() + (size_t)li * 6;
+                for (int st = 0; st < 3; ++st) {
+                    d[45 + st] = r[2 * st];
+                    d[48 + st] = (mask >> st) & 1 ? r[2 * st + 1] : r[2 * st];
+                }
+                d[51] = items[i].y;
+            }
+            });
+            int32_t *dde = as->sym_desc.ensure(desc.size());
+            int64_t *ddd = as->sym_desc_dst.ensure(ddst.size());
+            YK_HIP(hipMemcpyAsync(dde, desc.data(), desc.size() * sizeof(int32_t), hipMemcpyHostToDevice, ctx.stream));
+            YK_HIP(hipMemcpyAsync(ddd, ddst.data(), ddst.size() * sizeof(int64_t), hipMemcpyHostToDevice, ctx.stream));
+            YK_HIP(hipStreamSynchronize(ctx.stream));
+            as->near_sym = true;
+        }
+        // entry offsets of the cached near field, item by item
+        std::vector<int64_t> qoff(items.size()), doff(items.size());
+        // per item: its charge entries (stored, and without padding) and
+        // dipole pairs; then their offsets in order
+        std::vector<int64_t> qlen(items.size()), qval(items.size()), dlen(items.size());
+        parallel_for((int64_t)items.size(), [&](int64_t i0, int64_t i1) {
+            for (int64_t i = i0; i < i1; ++i) {
+                const int li = items[i].x;
+                const int64_t c = std::min<int64_t>(64, tcnt(li) - items[i].y);
+                if (sym) {
+                    // the leaf's charges against the owned neighbours' charges,
+                    // its other targets against all neighbouring charges
+                    int64_t own = 0;
+                    for (int32_t u = uoff[li]; u < uoff[li + 1]; ++u)
+                        if (ul[u] >= li) own += n0_of(ul[u]);
+                    const int64_t na = items[i].y == 0 ? n0_of(li) : 0;
+                    qlen[i] = ((na + 3) & ~(int64_t)3) * own + (c - na) * sq_leaf[li];
+                    qval[i] = na * own + (c - na) * sq_leaf[li];
+                } else {
+                    qlen[i] = qval[i] = c * sq_leaf[li];
+                }
+                dlen[i] = c * sd_leaf[li];
+            }
+        });
+        int64_t oq = 0, od = 0, vq = 0;   // (vq: charge values without the padding)
+        for (size_t i = 0; i < items.size(); ++i) {
+            if (sym) oq = (oq + 3) & ~(int64_t)3;   // (vector reads of four values)
+            qoff[i] = oq;
+            doff[i] = od;
+            oq += qlen[i];
+            vq += qval[i];
+            od += dlen[i];
+        }
+        as->near_q_len = oq;
+        as->near_q_vals = vq;
+        as->near_d_len = od;
+        if (!items.empty()) {
+            int64_t *dq = as->item_qoff.ensure(items.size());
+            int64_t *dd = as->item_doff.ensure(items.size());
+            YK_HIP(hipMemcpyAsync(dq, qoff.data(), qoff.size() * sizeof(int64_t), hipMemcpyHostToDevice, ctx.stream));
+            YK_HIP(hipMemcpyAsync(dd, doff.data(), doff.size() * sizeof(int64_t), hipMemcpyHostToDevice, ctx.stream));
+            YK_HIP(hipStreamSynchronize(ctx.stream));
+        }
+    }
+    as->layout = true;
 }
 
 ActiveSet &get_active(Context &ctx, FmmPlan &pl, int mask) {
@@ -565,128 +687,39 @@ ActiveSet &get_active(Context &ctx, FmmPlan &pl, int mask) {
                               hipMemcpyDeviceToHost, ctx.stream));
         YK_HIP(hipStreamSynchronize(ctx.stream));
         std::vector<int64_t> sq_leaf(pl.nleaf, 0), sd_leaf(pl.nleaf, 0);
+        parallel_for(pl.nleaf, [&](int64_t i0, int64_t i1) {
+            for (int64_t li = i0; li < i1; ++li) {
+                int64_t sq = 0, sd = 0;
+                for (int32_t u = uoff[li]; u < uoff[li + 1]; ++u) {
+                    sq += pl.h_lrange[(size_t)ul[u] * 6 + 1] - pl.h_lrange[(size_t)ul[u] * 6];
+                    sd += pl.h_lrange[(size_t)ul[u] * 6 + 3] - pl.h_lrange[(size_t)ul[u] * 6 + 2];
+                }
+                sq_leaf[li] = sq;
+                sd_leaf[li] = sd;
+            }
+        });
         for (int32_t li : leaves) {
             const int64_t nt = cnt[pl.lev[L].begin + li];
-            int64_t sq = 0, sd = 0;
-            for (int32_t u = uoff[li]; u < uoff[li + 1]; ++u) {
-                sq += pl.h_lrange[(size_t)ul[u] * 6 + 1] - pl.h_lrange[(size_t)ul[u] * 6];
-                sd += pl.h_lrange[(size_t)ul[u] * 6 + 3] - pl.h_lrange[(size_t)ul[u] * 6 + 2];
-            }
-            sq_leaf[li] = sq;
-            sd_leaf[li] = sd;
-            as->pairs_q += nt * sq;
-            as->pairs_d += nt * sd;
+            as->pairs_q += nt * sq_leaf[li];
+            as->pairs_d += nt * sd_leaf[li];
             as->l2p_points += nt;
         }
-        // symmetric charge values
-        const int64_t n0 = pl.toff[1] - pl.toff[0];
-        // charges among the targets, at most 64 per leaf (so that they all
-        // fall in the leaf's first item, which they lead), and a far field
-        // (k_l2p adds the incoming slots)
-        auto n0_of = [&](int64_t li) -> int64_t { return pl.h_lrange[(size_t)li * 6 + 1] - pl.h_lrange[(size_t)li * 6]; };
-        bool sym = (mask & 1) && n0 > 0 && pl.lmin <= L && !(ctx.opt.debug_flags & 16);
-        for (int64_t li = 0; li < pl.nleaf && sym; ++li)
-            if (n0_of(li) > 64) sym = false;
-        if (sym) {
-            // incoming slots of leaf B: one per U-list neighbour A < B with
-            // charges, in B's U-list order, each n0(B) entries; the writer is
-            // A's U-list entry that names B
-            std::vector<int64_t> dst(ul.size(), -1), ibase(pl.nleaf, 0);
-            std::vector<int32_t> icnt(pl.nleaf, 0);
-            int64_t off = 0;
-            for (int64_t b = 0; b < pl.nleaf; ++b) {
-                ibase[b] = off;
-                int k = 0;
-                for (int32_t u = uoff[b]; u < uoff[b + 1]; ++u) {
-                    const int32_t a = ul[u];
-                    if (a >= b || n0_of(a) == 0) continue;
-                    int32_t ua = uoff[a];
-                    while (ua < uoff[a + 1] && ul[ua] != b) ++ua;
-                    if (ua == uoff[a + 1]) throw Error{YK_ERR_INTERNAL, "U-lists are not symmetric"};
-                    dst[ua] = off + (int64_t)k * n0_of(b);
-                    ++k;
-                }
-                icnt[b] = k;
-                off += (int64_t)k * n0_of(b);
-            }
-            as->inc_len = off;
-            int64_t *db = as->inc_base.ensure(ibase.size());
-            int32_t *dc = as->inc_cnt.ensure(icnt.size());
-            YK_HIP(hipMemcpyAsync(db, ibase.data(), ibase.size() * sizeof(int64_t), hipMemcpyHostToDevice, ctx.stream));
-            YK_HIP(hipMemcpyAsync(dc, icnt.data(), icnt.size() * sizeof(int32_t), hipMemcpyHostToDevice, ctx.stream));
-            as->inc.ensure(std::max<int64_t>(off, 1));
-            // per-item descriptors (layout: kItemDesc in the near-field kernels)
-            constexpr int kDesc = 52;
-            const int q_on = 1, d_on = (pl.toff[2] > pl.toff[1]) ? 1 : 0;
-            std::vector<int32_t> desc(items.size() * kDesc, 0);
-            std::vector<int64_t> ddst(items.size() * 9, -1);
-            for (size_t i = 0; i < items.size(); ++i) {
-                const int32_t li = items[i].x;
-                int32_t *d = desc.data() + i * kDesc;
-                const int32_t u0 = uoff[li], nu = uoff[li + 1] - u0;
-                for (int u = 0; u < 9 && u < nu; ++u) {
-                    const int32_t b = ul[u0 + u];
-                    const int32_t *r = pl.h_lrange.data() + (size_t)b * 6;
-                    d[u] = r[0];
-                    d[9 + u] = q_on ? r[1] - r[0] : 0;
-                    d[18 + u] = (q_on && b >= li) ? r[1] - r[0] : 0;
-                    d[27 + u] = r[2];
-                    d[36 + u] = d_on ? r[3] - r[2] : 0;
-                    ddst[i * 9 + u] = dst[u0 + u];
-                }
-                const int32_t *r = pl.h_lrange.data() + (size_t)li * 6;
-                for (int st = 0; st < 3; ++st) {
-                    d[45 + st] = r[2 * st];
-                    d[48 + st] = (mask >> st) & 1 ? r[2 * st + 1] : r[2 * st];
-                }
-                d[51] = items[i].y;
-            }
-            int32_t *dde = as->sym_desc.ensure(desc.size());
-            int64_t *ddd = as->sym_desc_dst.ensure(ddst.size());
-            YK_HIP(hipMemcpyAsync(dde, desc.data(), desc.size() * sizeof(int32_t), hipMemcpyHostToDevice, ctx.stream));
-            YK_HIP(hipMemcpyAsync(ddd, ddst.data(), ddst.size() * sizeof(int64_t), hipMemcpyHostToDevice, ctx.stream));
-            YK_HIP(hipStreamSynchronize(ctx.stream));
-            as->near_sym = true;
-        }
-        // entry offsets of the cached near field, item by item
-        std::vector<int64_t> qoff(items.size()), doff(items.size());
-        int64_t oq = 0, od = 0, vq = 0;   // (vq: charge values without the padding)
-        for (size_t i = 0; i < items.size(); ++i) {
-            const int li = items[i].x;
-            const int64_t c = std::min<int64_t>(64, cnt[pl.lev[L].begin + li] - items[i].y);
-            if (sym) oq = (oq + 3) & ~(int64_t)3;   // (vector reads of four values)
-            qoff[i] = oq;
-            doff[i] = od;
-            if (sym) {
-                // the leaf's charges against the owned neighbours' charges,
-                // its other targets against all neighbouring charges
-                int64_t own = 0;
-                for (int32_t u = uoff[li]; u < uoff[li + 1]; ++u)
-                    if (ul[u] >= li) own += n0_of(ul[u]);
-                const int64_t na = items[i].y == 0 ? n0_of(li) : 0;
-                oq += ((na + 3) & ~(int64_t)3) * own + (c - na) * sq_leaf[li];
-                vq += na * own + (c - na) * sq_leaf[li];
-            } else {
-                oq += c * sq_leaf[li];
-                vq += c * sq_leaf[li];
-            }
-            od += c * sd_leaf[li];
-        }
-        as->near_q_len = oq;
-        as->near_q_vals = vq;
-        as->near_d_len = od;
-        if (!items.empty()) {
-            int64_t *dq = as->item_qoff.ensure(items.size());
-            int64_t *dd = as->item_doff.ensure(items.size());
-            YK_HIP(hipMemcpyAsync(dq, qoff.data(), qoff.size() * sizeof(int64_t), hipMemcpyHostToDevice, ctx.stream));
-            YK_HIP(hipMemcpyAsync(dd, doff.data(), doff.size() * sizeof(int64_t), hipMemcpyHostToDevice, ctx.stream));
-            YK_HIP(hipStreamSynchronize(ctx.stream));
-        }
+        as->h_sq = std::move(sq_leaf);
+        as->h_sd = std::move(sd_leaf);
+        as->h_uoff = std::move(uoff);
+        as->h_ul = std::move(ul);
     }
-    // M2L tiles: active boxes of levels lmin..L grouped by (level, class)
+    as->h_items = items;
+    as->h_tcnt.assign(pl.nleaf, 0);
+    for (int64_t li = 0; li < pl.nleaf; ++li) as->h_tcnt[li] = cnt[pl.lev[L].begin + li];
+    as->mask = mask;
+    // M2L tiles: active boxes of levels lmin..L grouped by (level, class).
+    // The V lists come to the host only for small trees (the sparse form's
+    // buckets); a large tree's translations are counted on the GPU.
     constexpr int kTile = 64;
+    const bool small_tree = pl.nleaf < 8192;
     std::vector<int32_t> vl_host;
-    if (pl.lmin <= L) {
+    if (pl.lmin <= L && small_tree) {
         vl_host.resize((size_t)pl.nbox * kNumV);
         YK_HIP(hipMemcpyAsync(vl_host.data(), pl.vlist.p, vl_host.size() * sizeof(int32_t),
                               hipMemcpyDeviceToHost, ctx.stream));
@@ -709,7 +742,8 @@ ActiveSet &get_active(Context &ctx, FmmPlan &pl, int mask) {
                 decode(pl.hcode[b], ix, iy);
                 if ((int)((ix & 1) | ((iy & 1) << 1)) == cls) {
                     mb.push_back((int32_t)b);
-                    for (int k = 0; k < kNumV; ++k) as->m2l_trans += vl_host[(size_t)b * kNumV + k] >= 0;
+                    if (small_tree)
+                        for (int k = 0; k < kNumV; ++k) as->m2l_trans += vl_host[(size_t)b * kNumV + k] >= 0;
                 }
             }
             for (int64_t s = start; s < (int64_t)mb.size(); s += kTile)
@@ -741,7 +775,7 @@ ActiveSet &get_active(Context &ctx, FmmPlan &pl, int mask) {
     // whole operator loads)
     std::vector<int4> ptiles;
     std::vector<int32_t> ptgt, psrc;
-    if (pl.nleaf < 8192 && !mb.empty() && 2 * as->m2l_trans < (int64_t)mb.size() * kNumV) {
+    if (small_tree && !mb.empty() && 2 * as->m2l_trans < (int64_t)mb.size() * kNumV) {
         as->m2l_sparse = true;
         for (int l = pl.lmin; l <= L; ++l) {
             std::vector<std::vector<std::pair<int32_t, int32_t>>> bucket(kNumOff);
@@ -791,6 +825,7 @@ ActiveSet &get_active(Context &ctx, FmmPlan &pl, int mask) {
             YK_HIP(hipMemcpyAsync(d, vec.data(), vec.size() * sizeof(T), hipMemcpyHostToDevice, ctx.stream));
     };
     up(as->m2l_boxes, mb);
+    if (!small_tree && !mb.empty()) as->m2l_trans = gpu_count_slots(ctx, pl, as->m2l_boxes.p, (int64_t)mb.size());
     up(as->m2l_tiles, tiles);
     up(as->m2l_tiles_w, wtiles);
     if (as->m2l_sparse) {

@@ -1,4 +1,6 @@
 // kernels_elem.hip -- direct sums and elementwise kernels (FP64).
+#include <algorithm>
+
 #include "yk_bessel.h"
 #include "yk_internal.h"
 
@@ -11,26 +13,32 @@ constexpr int kDirectBlock = 256;
 // All-pairs sum: one target per thread, sources staged through LDS in tiles.
 // Charges contribute q K0(z)/(2pi); dipoles contribute (x - y).dn K1(z)/(alpha^2 z)/(2pi),
 // z = r/alpha.  Pairs at distance zero are skipped (self pairs included).
+// With gridDim.y > 1 the sources are split into gridDim.y contiguous chunks
+// (one per blockIdx.y) and each chunk's raw sum goes to part[chunk][target],
+// for k_direct_reduce to add in chunk order (few targets, many sources).
 __global__ __launch_bounds__(kDirectBlock) void k_direct(
     int64_t nt, const double *__restrict__ txy, int64_t ns, const double *__restrict__ sxy,
     const double *__restrict__ q, int64_t nb, const double *__restrict__ bxy,
     const double *__restrict__ dn, double inv4a2, double inva2, double *__restrict__ out,
-    int accumulate) {
+    int accumulate, double *__restrict__ part) {
     __shared__ double sx[kDirectBlock], sy[kDirectBlock], sq[kDirectBlock], sn[kDirectBlock];
     const int64_t i = (int64_t)blockIdx.x * kDirectBlock + threadIdx.x;
     const bool live = i < nt;
     const double x = live ? txy[2 * i] : 0.0;
     const double y = live ? txy[2 * i + 1] : 0.0;
+    const int64_t c = blockIdx.y, nc = gridDim.y;
+    const int64_t qs0 = c * ns / nc, qs1 = (c + 1) * ns / nc;
+    const int64_t bs0 = c * nb / nc, bs1 = (c + 1) * nb / nc;
     double acc = 0.0;
-    for (int64_t s0 = 0; s0 < ns; s0 += kDirectBlock) {
+    for (int64_t s0 = qs0; s0 < qs1; s0 += kDirectBlock) {
         const int64_t j = s0 + threadIdx.x;
-        if (j < ns) {
+        if (j < qs1) {
             sx[threadIdx.x] = sxy[2 * j];
             sy[threadIdx.x] = sxy[2 * j + 1];
             sq[threadIdx.x] = q[j];
         }
         __syncthreads();
-        const int cnt = (int)min<int64_t>(kDirectBlock, ns - s0);
+        const int cnt = (int)min<int64_t>(kDirectBlock, qs1 - s0);
         for (int k = 0; k < cnt; ++k) {
             const double dx = x - sx[k], dy = y - sy[k];
             const double r2 = dx * dx + dy * dy;
@@ -38,16 +46,16 @@ __global__ __launch_bounds__(kDirectBlock) void k_direct(
         }
         __syncthreads();
     }
-    for (int64_t s0 = 0; s0 < nb; s0 += kDirectBlock) {
+    for (int64_t s0 = bs0; s0 < bs1; s0 += kDirectBlock) {
         const int64_t j = s0 + threadIdx.x;
-        if (j < nb) {
+        if (j < bs1) {
             sx[threadIdx.x] = bxy[2 * j];
             sy[threadIdx.x] = bxy[2 * j + 1];
             sq[threadIdx.x] = dn[2 * j];
             sn[threadIdx.x] = dn[2 * j + 1];
         }
         __syncthreads();
-        const int cnt = (int)min<int64_t>(kDirectBlock, nb - s0);
+        const int cnt = (int)min<int64_t>(kDirectBlock, bs1 - s0);
         for (int k = 0; k < cnt; ++k) {
             const double dx = x - sx[k], dy = y - sy[k];
             const double r2 = dx * dx + dy * dy;
@@ -56,9 +64,23 @@ __global__ __launch_bounds__(kDirectBlock) void k_direct(
         __syncthreads();
     }
     if (live) {
-        const double v = acc * kInv2Pi;
-        out[i] = accumulate ? out[i] + v : v;
+        if (part) {
+            part[c * nt + i] = acc;
+        } else {
+            const double v = acc * kInv2Pi;
+            out[i] = accumulate ? out[i] + v : v;
+        }
     }
+}
+
+__global__ void k_direct_reduce(int64_t nt, int nchunk, const double *__restrict__ part, double *__restrict__ out,
+                                int accumulate) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nt) return;
+    double acc = 0.0;
+    for (int c = 0; c < nchunk; ++c) acc += part[(int64_t)c * nt + i];
+    const double v = acc * kInv2Pi;
+    out[i] = accumulate ? out[i] + v : v;
 }
 
 __global__ void k_dipole_vectors(int64_t n, const double *__restrict__ w,
@@ -185,8 +207,25 @@ void launch_direct(Context &ctx, int64_t nt, const double *txy, int64_t ns, cons
                    double *out, bool accumulate) {
     if (nt <= 0) return;
     const double inv4a2 = 1.0 / (4.0 * alpha * alpha), inva2 = 1.0 / (alpha * alpha);
+    // few targets against many sources (sampled checks): the sources are
+    // split into chunks of at least 8192 so the launch fills the GPU, and the
+    // chunks' sums are added in a fixed order.  (Square problems, such as the
+    // density operator with the nodes as targets and sources, keep one chunk.)
+    const int64_t nsrc = ns + nb;
+    int nchunk = 1;
+    if (nt <= 4096 && nsrc >= 65536) nchunk = (int)std::min<int64_t>(512, nsrc / 8192);
+    if (nchunk > 1) {
+        double *part = ctx.direct_part.ensure((size_t)nchunk * nt);
+        hipLaunchKernelGGL(k_direct, dim3(nblk(nt, kDirectBlock), nchunk), dim3(kDirectBlock), 0, ctx.stream, nt,
+                           txy, ns, sxy, q, nb, bxy, dn, inv4a2, inva2, out, 0, part);
+        check_launch(ctx, "k_direct");
+        hipLaunchKernelGGL(k_direct_reduce, dim3(nblk(nt, 256)), dim3(256), 0, ctx.stream, nt, nchunk, part, out,
+                           accumulate ? 1 : 0);
+        check_launch(ctx, "k_direct_reduce");
+        return;
+    }
     hipLaunchKernelGGL(k_direct, dim3(nblk(nt, kDirectBlock)), dim3(kDirectBlock), 0, ctx.stream,
-                       nt, txy, ns, sxy, q, nb, bxy, dn, inv4a2, inva2, out, accumulate ? 1 : 0);
+                       nt, txy, ns, sxy, q, nb, bxy, dn, inv4a2, inva2, out, accumulate ? 1 : 0, (double *)nullptr);
     check_launch(ctx, "k_direct");
 }
 

@@ -142,6 +142,7 @@ struct Context {
     // pinned memory is created, and host copies go through host_scal
     bool noalloc = false;
     DevBuf<double> dn;                     // dipole vectors [N][2]
+    DevBuf<double> direct_part;            // direct sums split over source chunks: [chunk][target]
     std::vector<double> host_scal;
 
     struct WarmStart *warm = nullptr;       // attached learned warm start (not owned)

@@ -38,7 +38,7 @@ EXPORTS = (
     "yk_ws_default_options", "yk_ws_create", "yk_ws_destroy", "yk_ws_observe", "yk_ws_train",
     "yk_ws_predict", "yk_set_warm_start", "yk_ws_num_params", "yk_ws_get_params",
     "yk_ws_set_params", "yk_ws_loss_grad", "yk_ws_forward", "yk_ws_adam_step",
-    "yk_gmres_density_noalloc",
+    "yk_gmres_density_noalloc", "yk_plan_tree_export",
 )
 
 STAGES = ("gather", "p2m", "m2m", "m2l", "l2l", "leaf", "scatter", "direct", "l2p", "near_build")
@@ -80,7 +80,8 @@ class yk_plan_info(ctypes.Structure):
                 ("near_sym", ctypes.c_int32), ("near_charge_values", ctypes.c_int64),
                 ("near_incoming", ctypes.c_int64), ("p_initial", ctypes.c_int32),
                 ("order_check_err", ctypes.c_double), ("m2m_children", ctypes.c_int64),
-                ("l2l_children", ctypes.c_int64)]
+                ("l2l_children", ctypes.c_int64), ("n_ulist", ctypes.c_int64),
+                ("tables_ms", ctypes.c_double), ("order_check_ms", ctypes.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -147,6 +148,7 @@ def load_library(path: str = LIB_PATH):
         "yk_ws_forward": (ip, [vp, i64, vp, vp]),
         "yk_ws_adam_step": (ip, [vp, vp]),
         "yk_gmres_density_noalloc": (ip, [vp, P(yk_boundary), dbl, vp, vp, dbl, ip, vp, P(yk_stats)]),
+        "yk_plan_tree_export": (ip, [vp, ip, P(dbl), P(i64), vp, vp, vp, vp, vp, vp, vp, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -425,3 +427,29 @@ def yk_ws_forward(ws: WarmStartHandle, X, y):
 
 def yk_ws_adam_step(ws: WarmStartHandle, grad):
     _check(ws.ctx, load_library().yk_ws_adam_step(ws.h, _dev(grad, "grad", dtype="float32")))
+
+
+def yk_plan_tree_export(ctx, slot=0):
+    """The cached tree of `slot` as numpy arrays (keys, perm, box codes,
+    parents, leaf ranges, U lists, V lists) plus the bounding square."""
+    import numpy as np
+    import torch
+    info = yk_plan_info_get(ctx, slot)
+    if not info.valid:
+        raise YkError(YK_ERR_ARG, "no tree cached in this slot")
+    N, nb, nl, L = info.n_points, info.n_boxes, info.n_leaves, info.leaf_level
+    dev = lambda n, dt: torch.empty(max(int(n), 1), dtype=dt, device="cuda")
+    keys, perm = dev(N, torch.int32), dev(N, torch.int32)
+    code, parent = dev(nb, torch.int32), dev(nb, torch.int32)
+    lr, uoff, ul = dev(nl * 6, torch.int32), dev(nl + 1, torch.int32), dev(info.n_ulist, torch.int32)
+    vl = dev(nb * 27, torch.int32)
+    sq = (ctypes.c_double * 3)()
+    lb = (ctypes.c_int64 * (L + 2))()
+    ptr = lambda t: ctypes.c_void_p(t.data_ptr())
+    _check(ctx, load_library().yk_plan_tree_export(ctx, int(slot), sq, lb, ptr(keys), ptr(perm), ptr(code),
+                                                   ptr(parent), ptr(lr), ptr(uoff), ptr(ul), ptr(vl)))
+    h = lambda t, n: t.cpu().numpy()[:int(n)]
+    return dict(square=(sq[0], sq[1], sq[2]), level_begin=np.array(lb[:], dtype=np.int64), leaf_level=L,
+                lmin=info.lmin, keys=h(keys, N).view(np.uint32), perm=h(perm, N), box_code=h(code, nb).view(np.uint32),
+                parent=h(parent, nb), leaf_range=h(lr, nl * 6).reshape(nl, 6), ulist_off=h(uoff, nl + 1),
+                ulist=h(ul, info.n_ulist), vlist=h(vl, nb * 27).reshape(nb, 27))

@@ -398,7 +398,9 @@ def _c4_like_pass_vs_oracle(yk, oracle_lib, c, nv, nb, seed, orders=(0,)):
         got = np.concatenate([host(ov)[iv], host(ob)[ib]])
         err = np.abs(got - ref) / np.abs(ref)
         l2 = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
-        print(f"  p={info.p} leaf level {info.leaf_level}, {info.n_leaves} leaves, lmin {info.lmin}; "
+        print(f"  p={info.p} leaf level {info.leaf_level}, {info.n_leaves} leaves, lmin {info.lmin}, "
+              f"tree build {info.build_ms:.0f} ms (tables {info.tables_ms:.0f}, order check "
+              f"{info.order_check_ms:.0f}); "
               f"per-target relative errors {err}, l2 {l2:.2e}", flush=True)
         res.append((info, err, l2))
     return res
