@@ -317,7 +317,7 @@ def oracle_step_timings(oracle):
     b = c0["bnd"]
     t0 = time.perf_counter()
     oracle.heat_step(b.xy, b.normal, b.weights(), b.curvature, c0["vol"], c0["vol_w"], c0["B"],
-                     c0["f_next"], c0["dt"], grid_h=c0["h"])
+                     c0["f_next"], c0["dt"], grid_h=c0["h"], offsets=b.offset)
     out["c0_step_s"] = time.perf_counter() - t0
     out["c0_size"] = f"{c0['vol'].shape[0]} volume points, {b.n} nodes"
     c3 = W.config_c3(m=128, n_holes=10, n_nodes=256, dt=1e-3, seed=3)
@@ -332,7 +332,7 @@ def oracle_step_timings(oracle):
     del A, lu
     t0 = time.perf_counter()
     oracle.heat_step(b.xy, b.normal, b.weights(), b.curvature, c3["vol"], c3["vol_w"], B, c3["f_bnd"],
-                     c3["dt"], grid_h=c3["h"])
+                     c3["dt"], grid_h=c3["h"], offsets=b.offset)
     out["reduced_c3_step_s"] = time.perf_counter() - t0
     out["reduced_c3_size"] = f"{c3['vol'].shape[0]} volume points, {b.n} nodes"
     n_full = 8192 + 10 * 2048

@@ -153,9 +153,13 @@ yk_status yk_volume_potential(yk_ctx ctx, int64_t n_src, const double *src_xy, c
  *   D(x, y) = d/dnu_y K0(|x - y|/alpha) = (1/alpha) K1(r/alpha) (x - y).n_y / r,
  *   w_j = (2 pi / N_k) speed_j.
  * tgt_xy == NULL evaluates on the curve at the nodes (n_tgt ignored, out has
- * N entries), with the diagonal term w_j (-kappa_j / 2) sigma_j / (2 pi) (the
- * continuity of the kernel along the curve, Sec. 2); off the curve, pairs at
- * distance zero are skipped.
+ * N entries) with the corrected trapezoid rule: the diagonal term is
+ * w_j D_jj sigma_j / (2 pi) with D_jj = kappa_j (-1/2 + zeta(3) w_j^2 /
+ * (8 pi^2 alpha^2)) -- the kernel's limit -kappa/2 along the curve (Sec. 2)
+ * plus the generalised Euler-Maclaurin error of its t^2 log|t| term, which
+ * makes the rule fifth order in the node spacing (it stands where the paper
+ * uses Alpert's hybrid rule, Sec. 3.2); off the curve, pairs at distance zero
+ * are skipped.  The density solves and heat steps use the same rule.
  */
 yk_status yk_double_layer_apply(yk_ctx ctx, const yk_boundary *bnd, const double *sigma,
                                 int64_t n_tgt, const double *tgt_xy, double alpha, double *out);
@@ -184,11 +188,30 @@ yk_status yk_gmres_density(yk_ctx ctx, const yk_boundary *bnd, double alpha, con
  * B [n_vol] must already be extended to every volume point (values outside
  * the domain are the caller's extension, Sec. 3.1).  vol_w [n_vol] quadrature
  * weights.  flags bit0: volume points are centres of square cells of area
- * vol_w, and each gets the integral of the kernel over its own cell,
- * C_self = (1/2pi) int_cell K0(|y|/alpha) dA, instead of the skipped self pair.
+ * vol_w = h^2, and each gets the weight of its own cell,
+ * C_self = (1/2pi) int_cell K0(|y|/alpha) dA + kappa h^2, instead of the
+ * skipped self pair; kappa = 0.0396864785674955 is the lattice correction of
+ * the kernel's logarithmic singularity, (c - Z'(0)/2) / (2 pi) with
+ * c = (pi/2 - 3 - log 2)/2 (the mean of log|u| over the unit cell) and Z the
+ * Epstein zeta function of the square lattice, 4 zeta(s) beta(s): with it
+ * the rule on a uniform grid is about fourth order in h / alpha, without it
+ * second order.
  * f_next [N] boundary data at t^{N+1}.  sigma_io [N]: in = initial guess,
  * out = sigma^{N+1}.  flags bit1: ignore sigma_io on input (zero guess).
  * u_next [n_vol] (meaningful at points inside the domain).
+ * Near-boundary evaluation (on unless flags bit2): at volume points on the
+ * domain side of a curve and closer to it than 4 local node spacings, where
+ * the trapezoid rule loses accuracy, U^h comes from the curves'
+ * trigonometric interpolants (Sec. 3.2 interpolates sigma in Fourier space):
+ * the point is projected onto its curve (theta*, distance d, local spacing
+ * s), U^h is evaluated at 6 check points at 1..6 spacings along the inward
+ * normal with the trapezoid rule on 8 times as many nodes, its limit on the
+ * curve is g(theta*), and the point takes the degree-6 polynomial in d / s
+ * through these values.  The set of such points, their projections and the
+ * finer nodes are built on the first step for a (boundary, vol_xy) pair and
+ * reused; each curve's nodes must be equispaced in a periodic parameter (as
+ * the trapezoid weights assume).  Candidates are points within 5 spacings of
+ * their nearest node; a point near two curves takes the nearest one.
  * The context keeps a copy of the density it returned and of A sigma; when the
  * next call passes that same density (bitwise) for the same boundary, alpha
  * and FMM options, its residual is formed from the kept A sigma instead of a
@@ -197,6 +220,44 @@ yk_status yk_gmres_density(yk_ctx ctx, const yk_boundary *bnd, double alpha, con
 yk_status yk_heat_step(yk_ctx ctx, const yk_boundary *bnd, int64_t n_vol, const double *vol_xy,
                        const double *vol_w, const double *B, int flags, const double *f_next,
                        double dt, double tol, double *sigma_io, double *u_next, yk_stats *stats);
+
+/*
+ * One step of (1 - alpha^2 Lap) u = B, u = f_next on the curves (eq.
+ * mod_helm_forced), on a uniform cell-centred grid: the grid form of
+ * yk_heat_step, with alpha^2 passed as it is (backward Euler: dt; extrapolated
+ * Gear: 2 dt / 3; times the diffusivity, see yk_rhs_imex).
+ *   grid     the cells: point j nx + i at (x0 + (i + 1/2) h, y0 + (j + 1/2) h);
+ *            the library generates the coordinates; every boundary node must
+ *            have two cells of the grid beyond it on each side
+ *   B        [nx ny] device, at every cell (the caller's extension outside
+ *            the domain, e.g. yk_rhs_imex)
+ *   U^p      = (V[h^2 B] + B C_self) / alpha^2 at the cell centres (C_self as
+ *            for yk_heat_step flags bit0), and on the nodes by tensor cubic
+ *            Lagrange interpolation of these values (the point-grid form of
+ *            evaluating the leaf polynomials of Sec. 3.1)
+ *   g        = f_next - U^p on the nodes;  sigma solves A sigma = -2 alpha^2 g
+ *   u_next   = U^p + DL[w sigma] / alpha^2 at the cell centres, with the
+ *            near-boundary evaluation of yk_heat_step (off with flags bit2)
+ * flags bit1: zero initial guess.  sigma_io, u_next, stats as for
+ * yk_heat_step (stats->ms[1] is the U^p stage).  Outside the domain u_next is
+ * not meaningful.  YK_ERR_ARG when a node's interpolation stencil leaves the
+ * grid.
+ */
+typedef struct {
+    double x0, y0;      /* lower-left corner of the gridded square */
+    double h;           /* cell side */
+    int64_t nx, ny;     /* cells per row, rows (4 .. 2^20 each, nx ny < 2^31) */
+} yk_grid;
+
+yk_status yk_heat_step_grid(yk_ctx ctx, const yk_boundary *bnd, const yk_grid *grid, const double *B, int flags,
+                            const double *f_next, double alpha2, double tol, double *sigma_io, double *u_next,
+                            yk_stats *stats);
+
+/*
+ * Introspection: number of volume points the last step evaluated with the
+ * near-boundary rule, and the time (ms) that set took to build.
+ */
+yk_status yk_near_info(yk_ctx ctx, int64_t *n_near, double *setup_ms);
 
 /*
  * For callers that cannot allocate device memory (code under HIP graph
@@ -230,6 +291,29 @@ yk_status yk_gmres_density_noalloc(yk_ctx ctx, const yk_boundary *bnd, double al
 yk_status yk_rhs_backward_euler(yk_ctx ctx, int64_t n, const double *u, const double *F,
                                 const int32_t *region, int n_const, const double *c,
                                 double dt, double *B);
+
+/*
+ * Right-hand side B of the linearly implicit (IMEX) schemes of Sec. 2 (eq.
+ * mod_helm_forced) for u_t - nu Lap u = F + R(u):
+ *   YK_SCHEME_EULER (backward Euler):  alpha^2 = nu dt,
+ *       B = ub + dt f
+ *   YK_SCHEME_GEAR (extrapolated Gear, eq. exg):  alpha^2 = 2 nu dt / 3,
+ *       B = 4/3 ub - 1/3 ub' + dt (4/3 f - 2/3 f')
+ * with f = F + R(ub), ub = u where region[i] < 0 (inside the domain) and
+ * ub = c[region[i]] elsewhere (the constant extension of Sec. 3.1; 0 when
+ * region[i] >= n_const), primes marking step N - 1.  F applies at every point
+ * (pass zeros outside the domain for the zero extension of F); the reaction
+ * R is 0 (YK_REACTION_NONE) or u (1 - u^2) (YK_REACTION_ALLEN_CAHN, Sec. 4,
+ * Example 3), evaluated on ub.  The step itself is yk_heat_step or
+ * yk_heat_step_grid with the scheme's alpha^2.
+ * u, u_prev, F, F_prev, B [n] device FP64 (F, F_prev may be NULL = 0; u_prev
+ * is needed for Gear only); region [n] device int32; c [n_const] HOST FP64.
+ */
+enum { YK_SCHEME_EULER = 0, YK_SCHEME_GEAR = 1 };
+enum { YK_REACTION_NONE = 0, YK_REACTION_ALLEN_CAHN = 1 };
+yk_status yk_rhs_imex(yk_ctx ctx, int scheme, int reaction, int64_t n, const double *u, const double *u_prev,
+                      const double *F, const double *F_prev, const int32_t *region, int n_const,
+                      const double *c, double dt, double *B);
 
 /*
  * One full FMM evaluation with charges on the volume points and dipoles on the
@@ -305,8 +389,10 @@ yk_status yk_ws_adam_step(yk_ws ws, const float *grad);
  * Introspection for measurement (not part of the method).
  * yk_plan_info: shape of the tree cached in `slot` (0 = volume points and
  * nodes, as used by the heat step and yk_fmm_potential; 1 = nodes only, as
- * used by the density solve; 2 = the stand-alone sum calls) and the work of
- * its last evaluation: near-field pairs and M2L translations.
+ * used by the density solve; 2 = the stand-alone sum calls; 3 = the finer
+ * boundary rule and the check points of the near-boundary evaluation; 4 = the
+ * nodes and the near-boundary targets) and the work of its last evaluation:
+ * near-field pairs and M2L translations.
  * yk_timing_enable: when on, every FMM stage is bracketed by HIP events on
  * the stream it runs on (the near field, YK_STAGE_LEAF, runs on a second
  * stream of the context concurrently with the far-field stages, unless

@@ -8,7 +8,10 @@ It computes, plainly and slowly (Kropinski & Quaife, arXiv 1007.5335):
   * direct O(N_t N_s) sums of K0(|x-y|/alpha)/(2 pi) and of the double-layer
     kernel (Sec. 2; library-sum normalisation without the 1/alpha^2 of G);
   * the dense matrix of the trapezoid discretisation of the second-kind
-    equation (Sec. 3.2, eq. discrete_sys) and its LU solve;
+    equation (Sec. 3.2, eq. discrete_sys) and its LU solve; the diagonal
+    carries the generalised Euler-Maclaurin correction of the kernel's
+    t^2 log|t| term, which makes the rule fifth order (in place of the
+    paper's Alpert rule, whose node tables are not reproduced here);
   * one backward-Euler step (Sec. 2: alpha^2 = dt, B = u^N + dt F^N), split
     into volume potential plus double layer (eqs. particular, mod_helm_hom,
     vol_potential), evaluated as weighted point sums with a self-cell
@@ -55,6 +58,8 @@ def _load():
         f.argtypes = [ctypes.c_double]
     lib.yko_dl_kernel.restype = ctypes.c_double
     lib.yko_dl_kernel.argtypes = [ctypes.c_double] * 7
+    lib.yko_dl_diag.restype = ctypes.c_double
+    lib.yko_dl_diag.argtypes = [ctypes.c_double] * 3
     for name in ("yko_k0_vec", "yko_k1_vec", "yko_i0_vec", "yko_i1_vec"):
         f = getattr(lib, name)
         f.restype = None
@@ -142,9 +147,18 @@ def dl_sum(bxy, bnormal, d, alpha, tgt_xy) -> np.ndarray:
     return out
 
 
+def dl_diag(w, kappa, alpha):
+    """Diagonal kernel value of the corrected trapezoid rule: the limit -kappa/2
+    (Sec. 2) plus zeta(3) kappa w^2 / (8 pi^2 alpha^2), the generalised
+    Euler-Maclaurin error of the kernel's t^2 log|t| term along the curve
+    (derivation at yko_dl_diag in yk_oracle.c)."""
+    return np.array([_load().yko_dl_diag(float(a), float(b), float(alpha))
+                     for a, b in zip(np.atleast_1d(w), np.atleast_1d(kappa))])
+
+
 def dl_matrix(bxy, bnormal, w, kappa, alpha) -> np.ndarray:
-    """A = I - 2 [w_n D(y_j, y_n)/(2 pi)], diagonal D = -kappa/2 (eq. discrete_sys,
-    trapezoid rule)."""
+    """A = I - 2 [w_n D(y_j, y_n)/(2 pi)], diagonal D = dl_diag (eq. discrete_sys,
+    corrected trapezoid rule)."""
     b = _f64(bxy); n = _f64(bnormal); w = _f64(w); k = _f64(kappa)
     nb = b.shape[0]
     A = np.empty((nb, nb))
@@ -153,11 +167,10 @@ def dl_matrix(bxy, bnormal, w, kappa, alpha) -> np.ndarray:
 
 
 def dl_on_surface(bxy, bnormal, w, kappa, sigma, alpha) -> np.ndarray:
-    """On-surface DL[w sigma](y_j) with the diagonal limit (the matrix action of
-    (I - A)/2 written as a sum)."""
-    nb = len(sigma)
+    """On-surface DL[w sigma](y_j) with the corrected diagonal (the matrix action
+    of (I - A)/2 written as a sum)."""
     off = dl_sum(bxy, bnormal, _f64(w) * _f64(sigma), alpha, bxy)
-    return off + _f64(w) * (-0.5 * _f64(kappa)) * _f64(sigma) / (2.0 * math.pi)
+    return off + _f64(w) * dl_diag(w, kappa, alpha) * _f64(sigma) / (2.0 * math.pi)
 
 
 def apply_bie(bxy, bnormal, w, kappa, sigma, alpha) -> np.ndarray:
@@ -200,16 +213,21 @@ class DenseBIE:
 
 
 def heat_step(bnd_xy, bnd_normal, bnd_w, bnd_kappa, vol_xy, vol_w, B, f_next, dt,
-              grid_h=None, bie=None, tgt_mask=None):
-    """One backward-Euler step, alpha^2 = dt, B already extended to all volume
-    points.  Returns (u_next at volume points, sigma, U^p on the nodes).
+              grid_h=None, bie=None, tgt_mask=None, offsets=None, near=True):
+    """One step with alpha^2 = dt (backward Euler; pass 2 dt / 3 for the
+    extrapolated Gear scheme), B already extended to all volume points.
+    Returns (u_next at the targets, sigma, U^p on the nodes).
 
       q      = W * B
-      U^p    = (V[q] + B * C_self) / alpha^2   (C_self only for grid points)
+      U^p    = (V[q] + B * C_self) / alpha^2   (C_self only for grid points:
+               the cell integral plus the lattice correction, grid.self_weight)
       g      = f^{N+1} - U^p on the nodes
       sigma  = A^{-1} (-2 alpha^2 g)
-      u^{N+1} = U^p + DL[w sigma] / alpha^2
+      u^{N+1} = U^p + DL[w sigma] / alpha^2, and at targets within a few node
+               spacings of a curve U^h from grid.near_values (when the curve
+               offsets are given and near is true)
     """
+    from . import grid as _grid
     alpha = math.sqrt(dt)
     vol_xy = _f64(vol_xy); B = _f64(B)
     q = _f64(vol_w) * B
@@ -222,7 +240,7 @@ def heat_step(bnd_xy, bnd_normal, bnd_w, bnd_kappa, vol_xy, vol_w, B, f_next, dt
         Vv = volume_sum(vol_xy, q, alpha, tgt_xy=tx)
         Bt = B[tgt_mask]
     if grid_h is not None:
-        Vv = Vv + Bt * self_cell(grid_h, alpha)
+        Vv = Vv + Bt * _grid.self_weight(grid_h, alpha)
     Vb = volume_sum(vol_xy, q, alpha, tgt_xy=bnd_xy)
     up_b = Vb / alpha ** 2
     g = _f64(f_next) - up_b
@@ -230,4 +248,10 @@ def heat_step(bnd_xy, bnd_normal, bnd_w, bnd_kappa, vol_xy, vol_w, B, f_next, dt
         bie = DenseBIE(bnd_xy, bnd_normal, bnd_w, bnd_kappa, alpha)
     sigma = bie.solve(g)
     uh = dl_sum(bnd_xy, bnd_normal, _f64(bnd_w) * sigma, alpha, tx) / alpha ** 2
+    if near and offsets is not None:
+        off = np.asarray(offsets, dtype=np.int64)
+        ncj = np.repeat(np.diff(off), np.diff(off))
+        speed = _f64(bnd_w) * ncj / (2.0 * math.pi)
+        nt = _grid.near_targets(bnd_xy, bnd_normal, speed, off, tx)
+        uh[nt[0]] = _grid.near_values(bnd_xy, bnd_normal, off, sigma, g, alpha, tx, nt)
     return Vv / alpha ** 2 + uh, sigma, up_b

@@ -178,15 +178,30 @@ void yko_dl_sum(int64_t nt, const double *txy, int64_t nb, const double *bxy,
     }
 }
 
-/* Dense matrix of eq. discrete_sys with the trapezoid rule (row-major, nb x nb):
- *   A[j][n] = delta_jn - 2 w_n D(y_j, y_n) / (2 pi),  D(y_j, y_j) = -kappa_j / 2. */
+/* Diagonal value of the corrected trapezoid rule for the on-curve kernel.
+ * Along the curve the kernel is smooth except for a term
+ * -(kappa_j |y'_j|^2 / (4 alpha^2)) t^2 log|t| (t the parameter offset), which
+ * comes from the (z^2/2) log z term of z K1(z) (Sec. 2: K0 behaves like -log).
+ * The punctured trapezoid rule with spacing h integrates t^2 log|t| g(t) with
+ * the error -2 zeta'(-2) h^3 g(0) (generalised Euler-Maclaurin expansion,
+ * Navot), and zeta'(-2) = -zeta(3) / (4 pi^2); adding the error back at the
+ * node makes the rule fifth order.  With w_j = |y'_j| h the kernel's diagonal
+ * value becomes -kappa_j / 2 + zeta(3) kappa_j w_j^2 / (8 pi^2 alpha^2). */
+double yko_dl_diag(double w, double kappa, double alpha) {
+    const double zeta3 = 1.2020569031595942854;
+    return kappa * (-0.5 + zeta3 * w * w / (8.0 * YKO_PI * YKO_PI * alpha * alpha));
+}
+
+/* Dense matrix of eq. discrete_sys with the corrected trapezoid rule
+ * (row-major, nb x nb):
+ *   A[j][n] = delta_jn - 2 w_n D(y_j, y_n) / (2 pi),  D(y_j, y_j) = yko_dl_diag. */
 void yko_dl_matrix(int64_t nb, const double *bxy, const double *bn, const double *w,
                    const double *kappa, double alpha, double *A) {
     const double c = 2.0 / (2.0 * YKO_PI);
 #pragma omp parallel for schedule(dynamic, 8)
     for (int64_t j = 0; j < nb; ++j) {
         for (int64_t n = 0; n < nb; ++n) {
-            double dv = (j == n) ? -0.5 * kappa[j]
+            double dv = (j == n) ? yko_dl_diag(w[j], kappa[j], alpha)
                                  : dl_kernel(bxy[2 * j], bxy[2 * j + 1], bxy[2 * n], bxy[2 * n + 1],
                                              bn[2 * n], bn[2 * n + 1], alpha);
             A[j * nb + n] = (j == n ? 1.0 : 0.0) - c * w[n] * dv;

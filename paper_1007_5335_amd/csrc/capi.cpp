@@ -1,6 +1,7 @@
 // capi.cpp -- the C ABI of libyk: argument checks, status codes, and the
 // drivers of the solve and of the heat step (Kropinski & Quaife, Sec. 2-3).
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <new>
@@ -98,7 +99,9 @@ BoundaryData &prepare_boundary(Context &ctx, const yk_boundary *b) {
     if (same)
         for (int k = 0; k <= b->n_curves; ++k) same = same && cur->offset[k] == b->offset[k];
     if (same) return *cur;
+    static std::atomic<uint64_t> bnd_gen{0};
     auto nb = std::make_unique<BoundaryData>();
+    nb->gen = ++bnd_gen;
     nb->xy = b->xy;
     nb->n = n;
     nb->n_curves = b->n_curves;
@@ -114,9 +117,12 @@ BoundaryData &prepare_boundary(Context &ctx, const yk_boundary *b) {
                          nb->idx.ensure(n));
     YK_HIP(hipStreamSynchronize(ctx.stream));
     ctx.bnd = std::move(nb);
-    // trees that contain the nodes are stale
+    // trees that contain the nodes are stale, and so is the near-boundary set
     ctx.plan_vol.reset();
     ctx.plan_bnd.reset();
+    ctx.plan_near.reset();
+    ctx.plan_nearc.reset();
+    ctx.near.reset();
     return *ctx.bnd;
 }
 
@@ -133,7 +139,7 @@ void evaluate_sums(Context &ctx, PlanSlot slot, const SumProblem &pb, const doub
         plain.bie = nullptr;
         evaluate_sums(ctx, slot, plain, q, dnb, out, prec);
         if (out[1] && pb.bie->kappa)
-            launch_bie_finish(ctx, pb.n[1], pb.bie->w, pb.bie->kappa, pb.bie->sigma, out[1], out[1]);
+            launch_bie_finish(ctx, pb.n[1], pb.bie->w, pb.bie->kappa, pb.alpha, pb.bie->sigma, out[1], out[1]);
         return;
     }
     StageTimer st(ctx, YK_STAGE_DIRECT);
@@ -482,6 +488,8 @@ yk_status yk_set_options(yk_ctx ctx, const yk_options *opt) {
         ctx->c.plan_vol.reset();
         ctx->c.plan_bnd.reset();
         ctx->c.plan_misc.reset();
+        ctx->c.plan_near.reset();
+        ctx->c.plan_nearc.reset();
     }
     return YK_OK;
 }
@@ -497,6 +505,11 @@ yk_status yk_invalidate_geometry(yk_ctx ctx) {
         c.plan_vol.reset();
         c.plan_bnd.reset();
         c.plan_misc.reset();
+        c.plan_near.reset();
+        c.plan_nearc.reset();
+        c.near.reset();
+        c.grid_nx = c.grid_ny = 0;
+        c.grid_bnd_gen = 0;
         c.bnd.reset();
         c.memo_valid = false;
         return YK_OK;
@@ -549,7 +562,7 @@ yk_status yk_double_layer_apply(yk_ctx ctx, const yk_boundary *bnd, const double
         } else {
             outs[1] = out;
             evaluate_sums(c, SLOT_BND, pb, nullptr, dn, outs, SUM_FP64);
-            launch_dl_diagonal(c, bd.n, bd.w.p, bd.curvature, sigma, out);
+            launch_dl_diagonal(c, bd.n, bd.w.p, bd.curvature, alpha, sigma, out);
         }
         return YK_OK;
     });
@@ -594,6 +607,102 @@ yk_status yk_gmres_density(yk_ctx ctx, const yk_boundary *bnd, double alpha, con
     });
 }
 
+// The attached warm start must have been made for this boundary: its
+// feature kernels read and write N-node arrays with its own offsets.
+static void check_warm(Context &c, const BoundaryData &bd) {
+    if (!c.warm) return;
+    const WarmStart &ws = *c.warm;
+    YK_REQUIRE(ws.n == bd.n && ws.offsets == bd.offset && ws.kappa == bd.curvature && ws.xy == bd.xy,
+               "the attached warm start was created for another boundary");
+}
+
+// The density of one step: the initial guess (the caller's density, whose
+// residual may come from the kept image A sigma, or the learned prediction
+// when its residual is smaller), GMRES to tol, and the bookkeeping of the kept
+// image and the warm start.  b = -2 alpha^2 g and gN = g on the nodes.
+static GmresResult step_density(Context &c, BoundaryData &bd, double alpha, const double *b, const double *gN,
+                                int flags, double tol, double *sigma_io, yk_stats *stats, int &outer, int &guess) {
+    const int64_t nb = bd.n;
+    // initial guess: the caller's (previous-step) density, or the learned
+    // prediction when its residual is smaller.  When the caller's density
+    // is the last solution of this same operator, its image A sigma is
+    // still held and its residual costs no operator application.
+    guess = (flags & 2) ? 0 : 1;
+    const double *r0 = nullptr;
+    double r0_norm2 = -1.0;
+    double *rprev = c.memo_r1.ensure(nb), *rml = c.memo_r2.ensure(nb);
+    BieOperator A64{c, bd, alpha, SUM_FP64};
+    // Everything the choice needs is enqueued first and read back with one
+    // synchronisation: ds = {|r_ml|^2, |r_prev|^2, |b|^2} and the memo flag.
+    const bool memo_key = guess == 1 && memo_key_matches(c, bd, alpha);
+    const bool learned = guess == 1 && c.warm && c.warm->trained && c.warm->obs.size() >= 2;
+    double *ds = c.scal.ensure(512) + 450;
+    double *sml = learned ? c.ws_ml.ensure(nb) : nullptr;
+    auto tg = std::chrono::steady_clock::now();
+    int *dflag = memo_key ? memo_check(c, bd, sigma_io) : nullptr;
+    auto resid_enqueue = [&](const double *x, double *rv, bool from_memo, double *d) {
+        if (from_memo) {
+            launch_axpby(c, nb, 1.0, b, -1.0, c.memo_Asig.p, rv);
+        } else {
+            A64(x, rv);
+            launch_axpby(c, nb, 1.0, b, -1.0, rv, rv);
+        }
+        if (d) launch_multi_dot(c, nb, 1, rv, nb, rv, d);
+    };
+    if (learned) {
+        c.warm->predict(gN, sml);
+        resid_enqueue(sml, rml, false, nullptr);
+    }
+    // the previous density's residual: from the memo when it applies (a
+    // changed density is caught below), else by an operator application
+    // when the learned guess needs it for comparison
+    if (memo_key) resid_enqueue(sigma_io, rprev, true, nullptr);
+    else if (learned) resid_enqueue(sigma_io, rprev, false, nullptr);
+    // the three squared norms in one reduction
+    launch_sumsq3(c, nb, learned ? rml : nullptr, (memo_key || learned) ? rprev : nullptr, b, ds);
+    double *hsc = pinned_scalars(c) + 400;
+    YK_HIP(hipMemcpyAsync(hsc, ds, 3 * sizeof(double), hipMemcpyDeviceToHost, c.stream));
+    if (dflag) YK_HIP(hipMemcpyAsync(hsc + 3, dflag, sizeof(int), hipMemcpyDeviceToHost, c.stream));
+    YK_HIP(hipStreamSynchronize(c.stream));
+    double r_ml = hsc[0], r_prev = hsc[1];
+    const double b_norm2 = hsc[2];
+    int hflag = 0;
+    if (dflag) std::memcpy(&hflag, hsc + 3, sizeof(int));
+    const bool memo = memo_key && hflag == 0;
+    if (memo_key && !memo && learned) {   // the caller changed sigma since the memo
+        resid_enqueue(sigma_io, rprev, false, ds + 1);
+        YK_HIP(hipMemcpyAsync(hsc + 1, ds + 1, sizeof(double), hipMemcpyDeviceToHost, c.stream));
+        YK_HIP(hipStreamSynchronize(c.stream));
+        r_prev = hsc[1];
+    }
+    if (learned) {
+        if (std::isfinite(r_ml) && r_ml < r_prev) {
+            YK_HIP(hipMemcpyAsync(sigma_io, sml, nb * sizeof(double), hipMemcpyDeviceToDevice, c.stream));
+            guess = 2;
+            r0 = rml;
+            r0_norm2 = r_ml;
+        } else {
+            r0 = rprev;
+            r0_norm2 = r_prev;
+        }
+        if (stats) stats->ms[4] = ms_since(tg);
+    } else if (memo) {
+        r0 = rprev;
+        r0_norm2 = r_prev;
+    }
+    // sigma
+    auto t1 = std::chrono::steady_clock::now();
+    outer = 0;
+    bool asig_ok = false;
+    GmresResult r = solve_density(c, bd, alpha, b, sigma_io, guess == 0, tol, 1000, &outer, r0,
+                                  c.memo_Asig.ensure(nb), &asig_ok, r0_norm2, b_norm2);
+    if (asig_ok) memo_store(c, bd, alpha, sigma_io);
+    else c.memo_valid = false;
+    if (c.warm) c.warm->observe(gN, sigma_io);
+    if (stats) stats->ms[2] = ms_since(t1);
+    return r;
+}
+
 yk_status yk_heat_step(yk_ctx ctx, const yk_boundary *bnd, int64_t n_vol, const double *vol_xy,
                        const double *vol_w, const double *B, int flags, const double *f_next,
                        double dt, double tol, double *sigma_io, double *u_next, yk_stats *stats) {
@@ -607,13 +716,7 @@ yk_status yk_heat_step(yk_ctx ctx, const yk_boundary *bnd, int64_t n_vol, const 
         const int64_t nb = bd.n;
         const double alpha = std::sqrt(dt), a2 = dt;
         const SumPrec vprec = c.opt.precision == YK_PREC_FP32 ? SUM_FP32 : SUM_FP64;
-        // the attached warm start must have been made for this boundary: its
-        // feature kernels read and write N-node arrays with its own offsets
-        if (c.warm) {
-            const WarmStart &ws = *c.warm;
-            YK_REQUIRE(ws.n == nb && ws.offsets == bd.offset && ws.kappa == bd.curvature && ws.xy == bd.xy,
-                       "the attached warm start was created for another boundary");
-        }
+        check_warm(c, bd);
         // q = W B, in a buffer of its own (the density solve below takes the
         // shared workspaces and may reallocate them)
         double *q = c.ws_q.ensure(n_vol);
@@ -644,83 +747,8 @@ yk_status yk_heat_step(yk_ctx ctx, const yk_boundary *bnd, int64_t n_vol, const 
         // g = f - U^p on the nodes (recorded for the learned warm start)
         double *gN = c.ws_g.ensure(nb);
         launch_axpby(c, nb, 1.0, f_next, -1.0 / a2, vb, gN);
-        // initial guess: the caller's (previous-step) density, or the learned
-        // prediction when its residual is smaller.  When the caller's density
-        // is the last solution of this same operator, its image A sigma is
-        // still held and its residual costs no operator application.
-        int guess = (flags & 2) ? 0 : 1;
-        const double *r0 = nullptr;
-        double r0_norm2 = -1.0;
-        double *rprev = c.memo_r1.ensure(nb), *rml = c.memo_r2.ensure(nb);
-        BieOperator A64{c, bd, alpha, SUM_FP64};
-        // Everything the choice needs is enqueued first and read back with one
-        // synchronisation: ds = {|r_ml|^2, |r_prev|^2, |b|^2} and the memo flag.
-        const bool memo_key = guess == 1 && memo_key_matches(c, bd, alpha);
-        const bool learned = guess == 1 && c.warm && c.warm->trained && c.warm->obs.size() >= 2;
-        double *ds = c.scal.ensure(512) + 450;
-        double *sml = learned ? c.ws_ml.ensure(nb) : nullptr;
-        auto tg = std::chrono::steady_clock::now();
-        int *dflag = memo_key ? memo_check(c, bd, sigma_io) : nullptr;
-        auto resid_enqueue = [&](const double *x, double *rv, bool from_memo, double *d) {
-            if (from_memo) {
-                launch_axpby(c, nb, 1.0, b, -1.0, c.memo_Asig.p, rv);
-            } else {
-                A64(x, rv);
-                launch_axpby(c, nb, 1.0, b, -1.0, rv, rv);
-            }
-            if (d) launch_multi_dot(c, nb, 1, rv, nb, rv, d);
-        };
-        if (learned) {
-            c.warm->predict(gN, sml);
-            resid_enqueue(sml, rml, false, nullptr);
-        }
-        // the previous density's residual: from the memo when it applies (a
-        // changed density is caught below), else by an operator application
-        // when the learned guess needs it for comparison
-        if (memo_key) resid_enqueue(sigma_io, rprev, true, nullptr);
-        else if (learned) resid_enqueue(sigma_io, rprev, false, nullptr);
-        // the three squared norms in one reduction
-        launch_sumsq3(c, nb, learned ? rml : nullptr, (memo_key || learned) ? rprev : nullptr, b, ds);
-        double *hsc = pinned_scalars(c) + 400;
-        YK_HIP(hipMemcpyAsync(hsc, ds, 3 * sizeof(double), hipMemcpyDeviceToHost, c.stream));
-        if (dflag) YK_HIP(hipMemcpyAsync(hsc + 3, dflag, sizeof(int), hipMemcpyDeviceToHost, c.stream));
-        YK_HIP(hipStreamSynchronize(c.stream));
-        double r_ml = hsc[0], r_prev = hsc[1];
-        const double b_norm2 = hsc[2];
-        int hflag = 0;
-        if (dflag) std::memcpy(&hflag, hsc + 3, sizeof(int));
-        const bool memo = memo_key && hflag == 0;
-        if (memo_key && !memo && learned) {   // the caller changed sigma since the memo
-            resid_enqueue(sigma_io, rprev, false, ds + 1);
-            YK_HIP(hipMemcpyAsync(hsc + 1, ds + 1, sizeof(double), hipMemcpyDeviceToHost, c.stream));
-            YK_HIP(hipStreamSynchronize(c.stream));
-            r_prev = hsc[1];
-        }
-        if (learned) {
-            if (std::isfinite(r_ml) && r_ml < r_prev) {
-                YK_HIP(hipMemcpyAsync(sigma_io, sml, nb * sizeof(double), hipMemcpyDeviceToDevice, c.stream));
-                guess = 2;
-                r0 = rml;
-                r0_norm2 = r_ml;
-            } else {
-                r0 = rprev;
-                r0_norm2 = r_prev;
-            }
-            if (stats) stats->ms[4] = ms_since(tg);
-        } else if (memo) {
-            r0 = rprev;
-            r0_norm2 = r_prev;
-        }
-        // sigma
-        auto t1 = std::chrono::steady_clock::now();
-        int outer = 0;
-        bool asig_ok = false;
-        GmresResult r = solve_density(c, bd, alpha, b, sigma_io, guess == 0, tol, 1000, &outer, r0,
-                                      c.memo_Asig.ensure(nb), &asig_ok, r0_norm2, b_norm2);
-        if (asig_ok) memo_store(c, bd, alpha, sigma_io);
-        else c.memo_valid = false;
-        if (c.warm) c.warm->observe(gN, sigma_io);
-        if (stats) stats->ms[2] = ms_since(t1);
+        int outer = 0, guess = 0;
+        GmresResult r = step_density(c, bd, alpha, b, gN, flags, tol, sigma_io, stats, outer, guess);
         // u = (V[q] + DL[w sigma] + B C_self) / alpha^2 at the volume points
         auto t2 = std::chrono::steady_clock::now();
         {
@@ -734,8 +762,14 @@ yk_status yk_heat_step(yk_ctx ctx, const yk_boundary *bnd, int64_t n_vol, const 
             pr.bie = &f;
             evaluate_sums(c, SLOT_VOL, pr, q, nullptr, outs, vprec);
         }
-        if (flags & 1) launch_self_cell(c, n_vol, vol_w, B, alpha, 1.0 / a2, u_next);
+        if (flags & 1) launch_self_cell(c, n_vol, vol_w, 0.0, B, alpha, 1.0 / a2, u_next);
         else launch_axpby(c, n_vol, 1.0 / a2, u_next, 0.0, nullptr, u_next);
+        // targets closer to a curve than a few node spacings: U^h from the
+        // curves' interpolants instead of the node sums
+        if (!(flags & 4)) {
+            NearPlan &np = near_prepare(c, bd, n_vol, vol_xy);
+            near_apply(c, np, bd, alpha, sigma_io, gN, nullptr, u_next);
+        }
         YK_HIP(hipStreamSynchronize(c.stream));
         if (stats) stats->ms[3] = ms_since(t2);
         fill_stats(stats, r, outer, guess);
@@ -745,6 +779,136 @@ yk_status yk_heat_step(yk_ctx ctx, const yk_boundary *bnd, int64_t n_vol, const 
         }
         return YK_OK;
     });
+}
+
+namespace {
+
+// Cell centres of the grid in the context's buffer (regenerated, with the
+// trees and near-boundary sets that contain them, when the grid changes)
+const double *grid_points(Context &c, const yk_grid &g) {
+    const int64_t n = g.nx * g.ny;
+    if (c.grid_nx == g.nx && c.grid_ny == g.ny && c.grid_key[0] == g.x0 && c.grid_key[1] == g.y0 &&
+        c.grid_key[2] == g.h && c.grid_xy.p)
+        return c.grid_xy.p;
+    c.plan_vol.reset();
+    c.plan_near.reset();
+    c.plan_nearc.reset();
+    c.near.reset();
+    c.grid_bnd_gen = 0;
+    double *xy = c.grid_xy.ensure(2 * n);
+    launch_grid_points(c, n, g.x0, g.y0, g.h, g.nx, xy);
+    c.grid_key[0] = g.x0;
+    c.grid_key[1] = g.y0;
+    c.grid_key[2] = g.h;
+    c.grid_nx = g.nx;
+    c.grid_ny = g.ny;
+    return xy;
+}
+
+// every node's 4 x 4 interpolation stencil lies inside the grid
+void grid_check_nodes(Context &c, const BoundaryData &bd, const yk_grid &g) {
+    if (c.grid_bnd_gen == bd.gen) return;
+    std::vector<double> hxy(2 * bd.n);
+    YK_HIP(hipMemcpyAsync(hxy.data(), bd.xy, 2 * bd.n * sizeof(double), hipMemcpyDeviceToHost, c.stream));
+    YK_HIP(hipStreamSynchronize(c.stream));
+    for (int64_t j = 0; j < bd.n; ++j) {
+        const double sx = (hxy[2 * j] - g.x0) / g.h - 0.5, sy = (hxy[2 * j + 1] - g.y0) / g.h - 0.5;
+        YK_REQUIRE(std::isfinite(sx) && std::isfinite(sy) && std::floor(sx) >= 1.0 &&
+                       std::floor(sx) + 2.0 <= (double)(g.nx - 1) && std::floor(sy) >= 1.0 &&
+                       std::floor(sy) + 2.0 <= (double)(g.ny - 1),
+                   "a boundary node's interpolation stencil leaves the grid (keep two cells between the "
+                   "curves and the grid's edge)");
+    }
+    c.grid_bnd_gen = bd.gen;
+}
+
+}  // namespace
+
+yk_status yk_heat_step_grid(yk_ctx ctx, const yk_boundary *bnd, const yk_grid *grid, const double *B, int flags,
+                            const double *f_next, double alpha2, double tol, double *sigma_io, double *u_next,
+                            yk_stats *stats) {
+    return guarded(ctx, [&](Context &c) {
+        YK_REQUIRE(grid && B && f_next && sigma_io && u_next, "invalid grid-step arguments");
+        YK_REQUIRE(std::isfinite(grid->x0) && std::isfinite(grid->y0) && std::isfinite(grid->h) && grid->h > 0.0,
+                   "invalid grid origin or cell size");
+        YK_REQUIRE(grid->nx >= 4 && grid->ny >= 4 && grid->nx <= ((int64_t)1 << 20) &&
+                       grid->ny <= ((int64_t)1 << 20) && grid->nx * grid->ny < ((int64_t)1 << 31),
+                   "grid sides must be 4 .. 2^20 cells and the grid below 2^31 cells");
+        YK_REQUIRE(std::isfinite(alpha2) && alpha2 > 0.0, "alpha2 must be finite and > 0");
+        YK_REQUIRE(std::isfinite(tol) && tol >= 0.0, "tol must be finite and >= 0");
+        if (stats) std::memset(stats, 0, sizeof(*stats));
+        BoundaryData &bd = prepare_boundary(c, bnd);
+        check_warm(c, bd);
+        const int64_t n = grid->nx * grid->ny, nb = bd.n;
+        const double h = grid->h, a2 = alpha2, alpha = std::sqrt(alpha2);
+        const SumPrec vprec = c.opt.precision == YK_PREC_FP32 ? SUM_FP32 : SUM_FP64;
+        const double *gxy = grid_points(c, *grid);
+        grid_check_nodes(c, bd, *grid);
+        auto t0 = std::chrono::steady_clock::now();
+        // U^p = (V[h^2 B] + B (C_cell + kappa h^2)) / alpha^2 at the cell centres
+        double *q = c.ws_q.ensure(n);
+        launch_axpby(c, n, h * h, B, 0.0, nullptr, q);
+        SumProblem pb;
+        pb.n[0] = n;
+        pb.xy[0] = gxy;
+        pb.n[1] = nb;
+        pb.xy[1] = bd.xy;
+        pb.normal = bd.normal;
+        pb.alpha = alpha;
+        double *up = c.grid_up.ensure(n);
+        {
+            double *outs[3] = {up, nullptr, nullptr};
+            evaluate_sums(c, SLOT_VOL, pb, q, nullptr, outs, vprec);
+        }
+        launch_self_cell(c, n, nullptr, h * h, B, alpha, 1.0 / a2, up);
+        // U^p on the nodes by bicubic interpolation; b = -2 alpha^2 (f - U^p), g = f - U^p
+        double *vb = c.ws_e.ensure(nb);
+        launch_bicubic(c, nb, bd.xy, grid->x0, grid->y0, h, grid->nx, grid->ny, up, vb);
+        double *b = c.ws_f.ensure(nb);
+        launch_axpby(c, nb, -2.0 * a2, f_next, 2.0 * a2, vb, b);
+        double *gN = c.ws_g.ensure(nb);
+        launch_axpby(c, nb, 1.0, f_next, -1.0, vb, gN);
+        if (stats) {
+            YK_HIP(hipStreamSynchronize(c.stream));
+            stats->ms[0] = fmm_last_build_ms(c);
+            stats->ms[1] = ms_since(t0);
+        }
+        int outer = 0, guess = 0;
+        GmresResult r = step_density(c, bd, alpha, b, gN, flags, tol, sigma_io, stats, outer, guess);
+        // u = U^p + DL[w sigma] / alpha^2 at the cell centres
+        auto t2 = std::chrono::steady_clock::now();
+        {
+            double *outs[3] = {u_next, nullptr, nullptr};
+            SumProblem pr = pb;
+            BieFuse f;
+            f.w = bd.w.p;
+            f.sigma = sigma_io;
+            f.normal = bd.normal;
+            pr.bie = &f;
+            evaluate_sums(c, SLOT_VOL, pr, nullptr, nullptr, outs, vprec);
+        }
+        launch_axpby(c, n, 1.0, up, 1.0 / a2, u_next, u_next);
+        if (!(flags & 4)) {
+            NearPlan &np = near_prepare(c, bd, n, gxy);
+            near_apply(c, np, bd, alpha, sigma_io, gN, up, u_next);
+        }
+        YK_HIP(hipStreamSynchronize(c.stream));
+        if (stats) stats->ms[3] = ms_since(t2);
+        fill_stats(stats, r, outer, guess);
+        if (!r.converged) {
+            c.last_error = "GMRES did not reach the tolerance";
+            return YK_ERR_NOCONV;
+        }
+        return YK_OK;
+    });
+}
+
+yk_status yk_near_info(yk_ctx ctx, int64_t *n_near, double *setup_ms) {
+    if (!ctx) return YK_ERR_ARG;
+    Context &c = ctx->c;
+    if (n_near) *n_near = c.near ? near_count(*c.near) : 0;
+    if (setup_ms) *setup_ms = c.near ? near_setup_ms(*c.near) : 0.0;
+    return YK_OK;
 }
 
 yk_status yk_rhs_backward_euler(yk_ctx ctx, int64_t n, const double *u, const double *F,
@@ -758,6 +922,26 @@ yk_status yk_rhs_backward_euler(yk_ctx ctx, int64_t n, const double *u, const do
         if (n_const > 0)
             YK_HIP(hipMemcpyAsync(cdev, cvals, n_const * sizeof(double), hipMemcpyHostToDevice, c.stream));
         launch_rhs_be(c, n, u, F, region, n_const, cdev, dt, B);
+        YK_HIP(hipStreamSynchronize(c.stream));
+        return YK_OK;
+    });
+}
+
+yk_status yk_rhs_imex(yk_ctx ctx, int scheme, int reaction, int64_t n, const double *u, const double *u_prev,
+                      const double *F, const double *F_prev, const int32_t *region, int n_const,
+                      const double *cvals, double dt, double *B) {
+    return guarded(ctx, [&](Context &c) {
+        YK_REQUIRE(scheme == YK_SCHEME_EULER || scheme == YK_SCHEME_GEAR, "unknown scheme");
+        YK_REQUIRE(reaction == YK_REACTION_NONE || reaction == YK_REACTION_ALLEN_CAHN, "unknown reaction");
+        YK_REQUIRE(n > 0 && u && region && B, "invalid arguments");
+        YK_REQUIRE(scheme == YK_SCHEME_EULER || u_prev, "the Gear scheme needs u_prev");
+        YK_REQUIRE(n_const >= 0 && n_const <= 4096 && (n_const == 0 || cvals), "invalid constants");
+        YK_REQUIRE(std::isfinite(dt) && dt > 0.0, "dt must be finite and > 0");
+        double *cdev = c.ws_c.ensure(n_const > 0 ? n_const : 1);
+        if (n_const > 0)
+            YK_HIP(hipMemcpyAsync(cdev, cvals, n_const * sizeof(double), hipMemcpyHostToDevice, c.stream));
+        launch_rhs_imex(c, n, scheme == YK_SCHEME_GEAR, reaction == YK_REACTION_ALLEN_CAHN, u, u_prev, F,
+                        F_prev, region, n_const, cdev, dt, B);
         YK_HIP(hipStreamSynchronize(c.stream));
         return YK_OK;
     });
@@ -927,7 +1111,7 @@ yk_status yk_ws_adam_step(yk_ws ws, const float *grad) {
 yk_status yk_plan_info_get(yk_ctx ctx, int slot, yk_plan_info *info) {
     return guarded(ctx, [&](Context &c) {
         YK_REQUIRE(info != nullptr, "info is NULL");
-        YK_REQUIRE(slot >= 0 && slot <= 2, "slot must be 0, 1 or 2");
+        YK_REQUIRE(slot >= 0 && slot <= 4, "slot must be 0 .. 4");
         std::memset(info, 0, sizeof(*info));
         const FmmPlan *pl = plan_in_slot(c, slot);
         if (!pl) return YK_OK;
@@ -978,7 +1162,7 @@ yk_status yk_plan_tree_export(yk_ctx ctx, int slot, double *square, int64_t *lev
                               int32_t *perm, uint32_t *box_code, int32_t *parent, int32_t *leaf_range,
                               int32_t *ulist_off, int32_t *ulist, int32_t *vlist) {
     return guarded(ctx, [&](Context &c) {
-        YK_REQUIRE(slot >= 0 && slot <= 2, "slot must be 0, 1 or 2");
+        YK_REQUIRE(slot >= 0 && slot <= 4, "slot must be 0 .. 4");
         const FmmPlan *pl = plan_in_slot(c, slot);
         YK_REQUIRE(pl != nullptr, "no tree is cached in this slot");
         auto copy = [&](void *dst, const void *src, size_t bytes) {

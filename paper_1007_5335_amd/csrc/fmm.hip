@@ -15,6 +15,8 @@ PlanPtr &slot_ref(Context &ctx, PlanSlot slot) {
     switch (slot) {
         case SLOT_VOL: return ctx.plan_vol;
         case SLOT_BND: return ctx.plan_bnd;
+        case SLOT_NEAR: return ctx.plan_near;
+        case SLOT_NEARC: return ctx.plan_nearc;
         default: return ctx.plan_misc;
     }
 }
@@ -64,7 +66,7 @@ void fmm_evaluate(Context &ctx, PlanSlot slot, const SumProblem &pb, const doubl
 
 double fmm_last_build_ms(Context &ctx) {
     double ms = 0;
-    for (PlanPtr *p : {&ctx.plan_vol, &ctx.plan_bnd, &ctx.plan_misc})
+    for (PlanPtr *p : {&ctx.plan_vol, &ctx.plan_bnd, &ctx.plan_misc, &ctx.plan_near, &ctx.plan_nearc})
         if (*p && (*p)->fresh) ms += (*p)->build_ms;
     return ms;
 }

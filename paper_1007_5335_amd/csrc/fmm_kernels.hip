@@ -2027,8 +2027,8 @@ __global__ __launch_bounds__(256) void k_l2p(
     for (int k = 0; k < n_in; ++k) v += inc[in_base + (int64_t)k * n0];
     double *o = set == 0 ? out0 : set == 1 ? out1 : out2;
     const int32_t i = perm[t];
-    if (set == 1 && bx)   // double-layer operator: x - 2 (DL + diagonal limit)
-        o[i] = bx[i] - 2.0 * (v + bw[i] * (-0.5 * bk[i]) * bx[i] * kInv2Pi);
+    if (set == 1 && bx)   // double-layer operator: x - 2 (DL + corrected diagonal)
+        o[i] = bx[i] - 2.0 * (v + dl_diag_weight(bw[i], bk[i], inv_alpha * inv_alpha) * bx[i]);
     else
         o[i] = v;
 }
@@ -2416,7 +2416,8 @@ void fmm_run(Context &ctx, FmmPlan &pl, const double *q, const double *dn, doubl
         hipLaunchKernelGGL(k_scatter_out, dim3(nblk(n, 256)), dim3(256), 0, ctx.stream, pl.toff[s], n,
                            pl.perm.p, outs, out[s]);
         check_launch(ctx, "k_scatter_out");
-        if (s == 1 && bie && bie->kappa) launch_bie_finish(ctx, n, bie->w, bie->kappa, bie->sigma, out[1], out[1]);
+        if (s == 1 && bie && bie->kappa)
+            launch_bie_finish(ctx, n, bie->w, bie->kappa, pl.alpha, bie->sigma, out[1], out[1]);
     }
 }
 

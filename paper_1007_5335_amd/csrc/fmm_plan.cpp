@@ -504,6 +504,8 @@ FmmPlan *plan_in_slot(Context &ctx, int slot) {
         case 0: return ctx.plan_vol.get();
         case 1: return ctx.plan_bnd.get();
         case 2: return ctx.plan_misc.get();
+        case 3: return ctx.plan_near.get();
+        case 4: return ctx.plan_nearc.get();
         default: return nullptr;
     }
 }

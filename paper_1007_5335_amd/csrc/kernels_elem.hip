@@ -95,11 +95,11 @@ __global__ void k_dipole_vectors(int64_t n, const double *__restrict__ w,
 }
 
 __global__ void k_dl_diagonal(int64_t n, const double *__restrict__ w,
-                              const double *__restrict__ kappa, const double *__restrict__ sigma,
+                              const double *__restrict__ kappa, double inv_a2, const double *__restrict__ sigma,
                               double *__restrict__ out) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    out[i] += w[i] * (-0.5 * kappa[i]) * sigma[i] * kInv2Pi;
+    out[i] += dl_diag_weight(w[i], kappa[i], inv_a2) * sigma[i];
 }
 
 __global__ void k_bie_combine(int64_t n, const double *__restrict__ x,
@@ -109,14 +109,14 @@ __global__ void k_bie_combine(int64_t n, const double *__restrict__ x,
     y[i] = x[i] - 2.0 * dl[i];
 }
 
-// y = x - 2 (dl + w (-kappa/2) x / (2 pi)): the diagonal limit and the
-// combination of the second-kind operator in one pass
+// y = x - 2 (dl + diagonal x): the corrected diagonal and the combination of
+// the second-kind operator in one pass
 __global__ void k_bie_finish(int64_t n, const double *__restrict__ w, const double *__restrict__ kappa,
-                             const double *__restrict__ x, const double *__restrict__ dl,
+                             double inv_a2, const double *__restrict__ x, const double *__restrict__ dl,
                              double *__restrict__ y) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    y[i] = x[i] - 2.0 * (dl[i] + w[i] * (-0.5 * kappa[i]) * x[i] * kInv2Pi);
+    y[i] = x[i] - 2.0 * (dl[i] + dl_diag_weight(w[i], kappa[i], inv_a2) * x[i]);
 }
 
 __global__ void k_mul(int64_t n, const double *__restrict__ a, const double *__restrict__ b,
@@ -143,19 +143,31 @@ __constant__ double c_gl_w[32];
 // target's own square cell (8 right triangles with apex at the centre).  When
 // all points of a wavefront share one cell size (a uniform grid) the 32 nodes
 // of the rule are spread over the lanes and c(h) is formed once per wavefront.
+// Lattice correction of a grid point's own weight.  Near the target the kernel
+// is -(1/2pi) log|x| times a smooth factor psi; the punctured lattice sum of
+// log|x| psi misses h^2 psi(0) (log h + Z'(0)/2) (generalised Euler-Maclaurin
+// expansion of lattice sums; Z(s) = 4 zeta(s) beta(s) is the Epstein zeta
+// function of the square lattice, Z'(0)/2 = log(4 pi)/2 - 2 log Gamma(1/4)),
+// while the cell integral supplies h^2 psi(0) (log h + c_cell) with
+// c_cell = (pi/2 - 3 - log 2) / 2; the difference, with the kernel's -1/(2pi),
+// is kappa h^2 psi(0), kappa = (c_cell - Z'(0)/2) / (2 pi).  With it the rule
+// is about fourth order in h / alpha instead of second.
+constexpr double kLatticeSelf = 0.039686478567495465;
+
 __device__ __forceinline__ double self_cell_node(int k, double h, double alpha) {
     const double th = (c_gl_x[k] + 1.0) * (kPi / 8.0);
     const double R = 0.5 * h / cos(th);
     return c_gl_w[k] * (alpha * alpha - alpha * R * k1(R / alpha));
 }
 
-__global__ __launch_bounds__(256) void k_self_cell(int64_t n, const double *__restrict__ vol_w,
+__global__ __launch_bounds__(256) void k_self_cell(int64_t n, const double *__restrict__ vol_w, double w_const,
                                                    const double *__restrict__ B, double alpha,
                                                    double scale, double *__restrict__ out) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const bool in = i < n;
     const int lane = threadIdx.x & 63;
-    const double h = in ? sqrt(vol_w[i]) : 0.0;
+    const double h2 = in ? (vol_w ? vol_w[i] : w_const) : 0.0;
+    const double h = sqrt(h2);
     // lane 0 of a wavefront with any point in range is in range itself
     const double h0 = __shfl(h, 0);
     double s;
@@ -167,7 +179,51 @@ __global__ __launch_bounds__(256) void k_self_cell(int64_t n, const double *__re
         s = 0.0;
         for (int k = 0; k < 32; ++k) s += self_cell_node(k, h, alpha);
     }
-    if (in) out[i] = scale * (out[i] + B[i] * (8.0 * (kPi / 8.0) * kInv2Pi) * s);
+    // the cell integral plus the lattice correction kappa h^2 (kLatticeSelf)
+    if (in) out[i] = scale * (out[i] + B[i] * ((8.0 * (kPi / 8.0) * kInv2Pi) * s + kLatticeSelf * h2));
+}
+
+__global__ void k_grid_points(int64_t n, double x0, double y0, double h, int64_t nx, double *__restrict__ xy) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    const int64_t j = k / nx, i = k - j * nx;
+    xy[2 * k] = x0 + ((double)i + 0.5) * h;
+    xy[2 * k + 1] = y0 + ((double)j + 0.5) * h;
+}
+
+// cubic Lagrange weights on the nodes -1, 0, 1, 2 at t in [0, 1)
+__device__ __forceinline__ void cubic_weights(double t, double w[4]) {
+    w[0] = -t * (t - 1.0) * (t - 2.0) / 6.0;
+    w[1] = (t + 1.0) * (t - 1.0) * (t - 2.0) / 2.0;
+    w[2] = -(t + 1.0) * t * (t - 2.0) / 2.0;
+    w[3] = (t + 1.0) * t * (t - 1.0) / 6.0;
+}
+
+// tensor cubic interpolation of cell-centre values: for a coordinate x the
+// stencil is the centres i0 - 1 .. i0 + 2, i0 = floor((x - x0)/h - 1/2)
+// (the host checks that every stencil lies inside the grid; indices are
+// clamped all the same)
+__global__ void k_bicubic(int64_t n, const double *__restrict__ xy, double x0, double y0, double h, int64_t nx,
+                          int64_t ny, const double *__restrict__ V, double *__restrict__ out) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    const double sx = (xy[2 * k] - x0) / h - 0.5, sy = (xy[2 * k + 1] - y0) / h - 0.5;
+    const double fx = floor(sx), fy = floor(sy);
+    double wx[4], wy[4];
+    cubic_weights(sx - fx, wx);
+    cubic_weights(sy - fy, wy);
+    const int64_t ix = (int64_t)fx, iy = (int64_t)fy;
+    double acc = 0.0;
+    for (int b = 0; b < 4; ++b) {
+        const int64_t r = min(max(iy + b - 1, (int64_t)0), ny - 1);
+        double row = 0.0;
+        for (int a = 0; a < 4; ++a) {
+            const int64_t cidx = min(max(ix + a - 1, (int64_t)0), nx - 1);
+            row += wx[a] * V[r * nx + cidx];
+        }
+        acc += wy[b] * row;
+    }
+    out[k] = acc;
 }
 
 __global__ void k_rhs_be(int64_t n, const double *__restrict__ u, const double *__restrict__ F,
@@ -180,6 +236,30 @@ __global__ void k_rhs_be(int64_t n, const double *__restrict__ u, const double *
         B[i] = u[i] + (F ? dt * F[i] : 0.0);
     else
         B[i] = (r < n_const) ? c[r] : 0.0;
+}
+
+// B of the linearly implicit schemes (Sec. 2): with ub the extended u (u inside
+// the domain, the enclosing curve's constant elsewhere) and f = F + R(ub),
+//   Euler: B = ub + dt f
+//   Gear:  B = 4/3 ub - 1/3 ub' + dt (4/3 f - 2/3 f')   (primes: step N - 1)
+// R = u (1 - u^2) for the Allen-Cahn reaction, else 0.
+__global__ void k_rhs_imex(int64_t n, int gear, int allen_cahn, const double *__restrict__ u,
+                           const double *__restrict__ up, const double *__restrict__ F,
+                           const double *__restrict__ Fp, const int32_t *__restrict__ region, int n_const,
+                           const double *__restrict__ c, double dt, double *__restrict__ B) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int r = region[i];
+    const double cr = (r >= 0 && r < n_const) ? c[r] : 0.0;
+    const double u0 = r < 0 ? u[i] : cr;
+    const double f0 = (F ? F[i] : 0.0) + (allen_cahn ? u0 * (1.0 - u0 * u0) : 0.0);
+    if (!gear) {
+        B[i] = u0 + dt * f0;
+        return;
+    }
+    const double u1 = r < 0 ? up[i] : cr;
+    const double f1 = (Fp ? Fp[i] : 0.0) + (allen_cahn ? u1 * (1.0 - u1 * u1) : 0.0);
+    B[i] = (4.0 / 3.0) * u0 - (1.0 / 3.0) * u1 + dt * ((4.0 / 3.0) * f0 - (2.0 / 3.0) * f1);
 }
 
 __global__ void k_boundary_prep(int64_t n, int n_curves, const int64_t *__restrict__ off,
@@ -236,10 +316,10 @@ void launch_dipole_vectors(Context &ctx, int64_t n, const double *w, const doubl
     check_launch(ctx, "k_dipole_vectors");
 }
 
-void launch_dl_diagonal(Context &ctx, int64_t n, const double *w, const double *kappa,
+void launch_dl_diagonal(Context &ctx, int64_t n, const double *w, const double *kappa, double alpha,
                         const double *sigma, double *out) {
     hipLaunchKernelGGL(k_dl_diagonal, dim3(nblk(n, 256)), dim3(256), 0, ctx.stream, n, w, kappa,
-                       sigma, out);
+                       1.0 / (alpha * alpha), sigma, out);
     check_launch(ctx, "k_dl_diagonal");
 }
 
@@ -248,9 +328,10 @@ void launch_bie_combine(Context &ctx, int64_t n, const double *x, const double *
     check_launch(ctx, "k_bie_combine");
 }
 
-void launch_bie_finish(Context &ctx, int64_t n, const double *w, const double *kappa, const double *x,
-                       const double *dl, double *y) {
-    hipLaunchKernelGGL(k_bie_finish, dim3(nblk(n, 256)), dim3(256), 0, ctx.stream, n, w, kappa, x, dl, y);
+void launch_bie_finish(Context &ctx, int64_t n, const double *w, const double *kappa, double alpha,
+                       const double *x, const double *dl, double *y) {
+    hipLaunchKernelGGL(k_bie_finish, dim3(nblk(n, 256)), dim3(256), 0, ctx.stream, n, w, kappa,
+                       1.0 / (alpha * alpha), x, dl, y);
     check_launch(ctx, "k_bie_finish");
 }
 
@@ -310,7 +391,18 @@ static void gauss_legendre32(double *x, double *w) {
     }
 }
 
-void launch_self_cell(Context &ctx, int64_t n, const double *vol_w, const double *B, double alpha,
+void launch_grid_points(Context &ctx, int64_t n, double x0, double y0, double h, int64_t nx, double *xy) {
+    hipLaunchKernelGGL(k_grid_points, dim3(nblk(n, 256)), dim3(256), 0, ctx.stream, n, x0, y0, h, nx, xy);
+    check_launch(ctx, "k_grid_points");
+}
+
+void launch_bicubic(Context &ctx, int64_t n, const double *xy, double x0, double y0, double h, int64_t nx,
+                    int64_t ny, const double *V, double *out) {
+    hipLaunchKernelGGL(k_bicubic, dim3(nblk(n, 256)), dim3(256), 0, ctx.stream, n, xy, x0, y0, h, nx, ny, V, out);
+    check_launch(ctx, "k_bicubic");
+}
+
+void launch_self_cell(Context &ctx, int64_t n, const double *vol_w, double w_const, const double *B, double alpha,
                       double scale, double *out_accum) {
     static bool ready = false;
     static double gx[32], gw[32];
@@ -320,7 +412,7 @@ void launch_self_cell(Context &ctx, int64_t n, const double *vol_w, const double
     }
     YK_HIP(hipMemcpyToSymbolAsync(HIP_SYMBOL(c_gl_x), gx, sizeof(gx), 0, hipMemcpyHostToDevice, ctx.stream));
     YK_HIP(hipMemcpyToSymbolAsync(HIP_SYMBOL(c_gl_w), gw, sizeof(gw), 0, hipMemcpyHostToDevice, ctx.stream));
-    hipLaunchKernelGGL(k_self_cell, dim3(nblk(n, 256)), dim3(256), 0, ctx.stream, n, vol_w, B,
+    hipLaunchKernelGGL(k_self_cell, dim3(nblk(n, 256)), dim3(256), 0, ctx.stream, n, vol_w, w_const, B,
                        alpha, scale, out_accum);
     check_launch(ctx, "k_self_cell");
 }
@@ -330,6 +422,14 @@ void launch_rhs_be(Context &ctx, int64_t n, const double *u, const double *F, co
     hipLaunchKernelGGL(k_rhs_be, dim3(nblk(n, 256)), dim3(256), 0, ctx.stream, n, u, F, region,
                        n_const, c_dev, dt, B);
     check_launch(ctx, "k_rhs_be");
+}
+
+void launch_rhs_imex(Context &ctx, int64_t n, bool gear, bool allen_cahn, const double *u, const double *up,
+                     const double *F, const double *Fp, const int32_t *region, int n_const, const double *c_dev,
+                     double dt, double *B) {
+    hipLaunchKernelGGL(k_rhs_imex, dim3(nblk(n, 256)), dim3(256), 0, ctx.stream, n, gear ? 1 : 0,
+                       allen_cahn ? 1 : 0, u, up, F, Fp, region, n_const, c_dev, dt, B);
+    check_launch(ctx, "k_rhs_imex");
 }
 
 void launch_boundary_prep(Context &ctx, int64_t n, int n_curves, const int64_t *off_dev,

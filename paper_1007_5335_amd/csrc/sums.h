@@ -15,7 +15,7 @@ namespace yk {
 // Dipole vectors formed inside a sum over boundary nodes (set 1):
 // dn_j = w_j sigma_j n_j (w null: w_j = 1) instead of being passed; with kappa
 // also the double-layer operator: set 1's output v becomes
-// y = sigma - 2 (v + w (-kappa/2) sigma / (2 pi)).
+// y = sigma - 2 (v + dl_diag_weight(w, kappa, 1 / alpha^2) sigma).
 struct BieFuse {
     const double *w = nullptr, *sigma = nullptr, *normal = nullptr, *kappa = nullptr;
 };
@@ -36,7 +36,7 @@ struct SumProblem {
     int keep_charge_m = 0;
 };
 
-enum PlanSlot { SLOT_VOL = 0, SLOT_BND = 1, SLOT_MISC = 2 };
+enum PlanSlot { SLOT_VOL = 0, SLOT_BND = 1, SLOT_MISC = 2, SLOT_NEAR = 3, SLOT_NEARC = 4 };
 
 enum SumPrec { SUM_FP64 = 0, SUM_FP32 = 1 };
 

@@ -16,6 +16,18 @@ namespace yk {
 
 constexpr double kPi = 3.14159265358979323846;
 constexpr double kInv2Pi = 1.0 / (2.0 * kPi);
+constexpr double kZeta3 = 1.2020569031595942854;   // Apery's constant
+
+// The diagonal entry w_j D(y_j, y_j) / (2 pi) of the on-curve double layer.
+// The kernel's limit along the curve is -kappa / 2 (Sec. 2); its only
+// non-smooth part is -(kappa |y'|^2 / (4 alpha^2)) t^2 log|t| (t the parameter
+// offset, from the (z^2/2) log z term of z K1(z)), whose trapezoid-rule error
+// -2 zeta'(-2) h^3 g(0) (generalised Euler-Maclaurin expansion, with
+// zeta'(-2) = -zeta(3) / (4 pi^2)) is added back at the node: the rule becomes
+// fifth order.  w = |y'| h is the node's weight, inv_a2 = 1 / alpha^2.
+__host__ __device__ inline double dl_diag_weight(double w, double kappa, double inv_a2) {
+    return w * kappa * (-0.5 + (kZeta3 / (8.0 * kPi * kPi)) * w * w * inv_a2) * kInv2Pi;
+}
 
 // Internal error: thrown inside the library, converted to a status at the ABI.
 struct Error {
@@ -84,6 +96,7 @@ void check_launch(Context &ctx, const char *what);
 
 // Boundary geometry prepared once per boundary (weights, curve ids).
 struct BoundaryData {
+    uint64_t gen = 0;                 // distinct for every preparation
     const double *xy = nullptr;
     int64_t n = 0;
     int n_curves = 0;
@@ -95,6 +108,15 @@ struct BoundaryData {
     const double *curvature = nullptr;
     const double *speed = nullptr;
 };
+
+// Near-boundary evaluation of the double layer (near.hip): the targets
+// closer to a curve than a few node spacings, their projections, check
+// points and the finer trapezoid rule used there.
+struct NearPlan;
+struct NearPlanDeleter {
+    void operator()(NearPlan *p) const;
+};
+using NearPtr = std::unique_ptr<NearPlan, NearPlanDeleter>;
 
 struct FmmPlan;   // tree + lists + operator tables (fmm.hip)
 void destroy_plan(FmmPlan *p);
@@ -129,6 +151,15 @@ struct Context {
     PlanPtr plan_vol;                      // tree over volume points and nodes
     PlanPtr plan_bnd;                      // tree over the nodes only (solver)
     PlanPtr plan_misc;                     // tree for the stand-alone sum calls
+    PlanPtr plan_near;                     // fine nodes -> near-boundary check points
+    PlanPtr plan_nearc;                    // nodes -> near targets (coarse rule, subtracted)
+    NearPtr near;                          // near-boundary targets of the last volume set
+
+    // cell-centred grid of yk_heat_step_grid (coordinates generated here)
+    DevBuf<double> grid_xy, grid_up;
+    double grid_key[3] = {0, 0, 0};
+    int64_t grid_nx = 0, grid_ny = 0;
+    uint64_t grid_bnd_gen = 0;             // boundary whose nodes were checked against the grid
 
     // workspaces
     DevBuf<double> ws_a, ws_b, ws_c, ws_d, ws_e, ws_f;
@@ -200,23 +231,30 @@ void launch_direct(Context &ctx, int64_t nt, const double *txy, int64_t ns, cons
 // dn_j = scale * w_j * sigma_j * n_j  (w == nullptr: unit weights)
 void launch_dipole_vectors(Context &ctx, int64_t n, const double *w, const double *sigma,
                            const double *normal, double scale, double *dn);
-// out_j += w_j (-kappa_j/2) sigma_j / (2 pi)
-void launch_dl_diagonal(Context &ctx, int64_t n, const double *w, const double *kappa,
+// out_j += dl_diag_weight(w_j, kappa_j, 1 / alpha^2) sigma_j
+void launch_dl_diagonal(Context &ctx, int64_t n, const double *w, const double *kappa, double alpha,
                         const double *sigma, double *out);
 // y = x - 2 * dl  (dl already includes 1/(2pi) and the diagonal)
 void launch_bie_combine(Context &ctx, int64_t n, const double *x, const double *dl, double *y);
 void launch_mul(Context &ctx, int64_t n, const double *a, const double *b, double *out);
-// y = x - 2 (dl + w (-kappa/2) x / (2 pi))  (diagonal limit + combination)
-void launch_bie_finish(Context &ctx, int64_t n, const double *w, const double *kappa, const double *x,
-                       const double *dl, double *y);
+// y = x - 2 (dl + dl_diag_weight(w, kappa, 1 / alpha^2) x)  (diagonal + combination)
+void launch_bie_finish(Context &ctx, int64_t n, const double *w, const double *kappa, double alpha,
+                       const double *x, const double *dl, double *y);
 // out = ca * a + cb * b  (b may be null -> out = ca * a)
 void launch_axpby(Context &ctx, int64_t n, double ca, const double *a, double cb, const double *b,
                   double *out);
 // out = scale * (out + B * (kernel integral over the point's own cell))
-void launch_self_cell(Context &ctx, int64_t n, const double *vol_w, const double *B, double alpha,
+// (h^2 = vol_w[i], or w_const when vol_w is NULL; the weight is the integral
+// plus the lattice correction of the logarithmic singularity, kappa h^2)
+void launch_self_cell(Context &ctx, int64_t n, const double *vol_w, double w_const, const double *B, double alpha,
                       double scale, double *out_accum);
 void launch_rhs_be(Context &ctx, int64_t n, const double *u, const double *F, const int32_t *region,
                    int n_const, const double *c_dev, double dt, double *B);
+// B of the Euler (gear false) or extrapolated Gear scheme, optional Allen-Cahn
+// reaction; up/Fp are step N - 1 (Gear only); c_dev [n_const] on the device
+void launch_rhs_imex(Context &ctx, int64_t n, bool gear, bool allen_cahn, const double *u, const double *up,
+                     const double *F, const double *Fp, const int32_t *region, int n_const, const double *c_dev,
+                     double dt, double *B);
 void launch_boundary_prep(Context &ctx, int64_t n, int n_curves, const int64_t *off_dev,
                           const double *speed, double *w, int32_t *curve, int32_t *idx);
 
@@ -284,6 +322,21 @@ void noalloc_init_device(int device);
 // Evaluate V[q] + DL[dn] at targets with the cached plan.
 struct FmmRequest;
 BoundaryData &prepare_boundary(Context &ctx, const yk_boundary *b);
+
+// cell centres of a grid, point j nx + i at (x0 + (i + 1/2) h, y0 + (j + 1/2) h)
+void launch_grid_points(Context &ctx, int64_t n, double x0, double y0, double h, int64_t nx, double *xy);
+// out_j = tensor cubic Lagrange interpolation of the cell-centre values V at xy_j
+void launch_bicubic(Context &ctx, int64_t n, const double *xy, double x0, double y0, double h, int64_t nx,
+                    int64_t ny, const double *V, double *out);
+
+// near-boundary evaluation (near.hip): the near targets of tgt_xy for the
+// boundary (built once per boundary and target array), and one step's
+// correction: out[i] = (base ? base[i] : out[i] - coarse DL_i / alpha^2) + U^h_i
+NearPlan &near_prepare(Context &ctx, BoundaryData &bd, int64_t n_tgt, const double *tgt_xy);
+void near_apply(Context &ctx, NearPlan &np, BoundaryData &bd, double alpha, const double *sigma, const double *g,
+                const double *base, double *out);
+int64_t near_count(const NearPlan &np);
+double near_setup_ms(const NearPlan &np);
 
 }  // namespace yk
 

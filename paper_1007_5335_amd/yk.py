@@ -29,6 +29,12 @@ YK_PREC_FP32 = 2
 
 HEAT_GRID_SELF_CELL = 1
 HEAT_ZERO_GUESS = 2
+HEAT_NO_NEAR = 4
+
+SCHEME_EULER = 0
+SCHEME_GEAR = 1
+REACTION_NONE = 0
+REACTION_ALLEN_CAHN = 1
 
 EXPORTS = (
     "yk_default_options", "yk_create", "yk_destroy", "yk_set_stream", "yk_set_options",
@@ -38,7 +44,8 @@ EXPORTS = (
     "yk_ws_default_options", "yk_ws_create", "yk_ws_destroy", "yk_ws_observe", "yk_ws_train",
     "yk_ws_predict", "yk_set_warm_start", "yk_ws_num_params", "yk_ws_get_params",
     "yk_ws_set_params", "yk_ws_loss_grad", "yk_ws_forward", "yk_ws_adam_step",
-    "yk_gmres_density_noalloc", "yk_plan_tree_export",
+    "yk_gmres_density_noalloc", "yk_plan_tree_export", "yk_rhs_imex", "yk_heat_step_grid",
+    "yk_near_info",
 )
 
 STAGES = ("gather", "p2m", "m2m", "m2l", "l2l", "leaf", "scatter", "direct", "l2p", "near_build")
@@ -54,6 +61,11 @@ class yk_boundary(ctypes.Structure):
     _fields_ = [("n_curves", ctypes.c_int32), ("offset", ctypes.POINTER(ctypes.c_int64)),
                 ("xy", ctypes.c_void_p), ("normal", ctypes.c_void_p),
                 ("speed", ctypes.c_void_p), ("curvature", ctypes.c_void_p)]
+
+
+class yk_grid(ctypes.Structure):
+    _fields_ = [("x0", ctypes.c_double), ("y0", ctypes.c_double), ("h", ctypes.c_double),
+                ("nx", ctypes.c_int64), ("ny", ctypes.c_int64)]
 
 
 class yk_stats(ctypes.Structure):
@@ -149,6 +161,9 @@ def load_library(path: str = LIB_PATH):
         "yk_ws_adam_step": (ip, [vp, vp]),
         "yk_gmres_density_noalloc": (ip, [vp, P(yk_boundary), dbl, vp, vp, dbl, ip, vp, P(yk_stats)]),
         "yk_plan_tree_export": (ip, [vp, ip, P(dbl), P(i64), vp, vp, vp, vp, vp, vp, vp, vp]),
+        "yk_rhs_imex": (ip, [vp, ip, ip, i64, vp, vp, vp, vp, vp, ip, P(dbl), dbl, vp]),
+        "yk_heat_step_grid": (ip, [vp, P(yk_boundary), P(yk_grid), vp, ip, vp, dbl, dbl, vp, vp, P(yk_stats)]),
+        "yk_near_info": (ip, [vp, P(i64), P(dbl)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -319,6 +334,45 @@ def yk_rhs_backward_euler(ctx, u, F, region, consts, dt, B):
         ctx, u.shape[0], _dev(u, "u"), _dev(F, "F"), _dev(region, "region", dtype="int32"),
         int(c.size), c.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), float(dt), _dev(B, "B")))
     return B
+
+
+def alpha2_of(scheme, dt, nu=1.0):
+    """alpha^2 of the scheme for u_t - nu Lap u = F: nu dt (Euler), 2 nu dt / 3 (Gear)."""
+    return nu * dt if scheme == SCHEME_EULER else 2.0 * nu * dt / 3.0
+
+
+def yk_rhs_imex(ctx, scheme, reaction, u, u_prev, F, F_prev, region, consts, dt, B):
+    c = np.ascontiguousarray(consts, dtype=np.float64)
+    _check(ctx, load_library().yk_rhs_imex(
+        ctx, int(scheme), int(reaction), u.shape[0], _dev(u, "u"), _dev(u_prev, "u_prev"), _dev(F, "F"),
+        _dev(F_prev, "F_prev"), _dev(region, "region", dtype="int32"), int(c.size),
+        c.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), float(dt), _dev(B, "B")))
+    return B
+
+
+def make_grid(x0, y0, h, nx, ny) -> yk_grid:
+    return yk_grid(float(x0), float(y0), float(h), int(nx), int(ny))
+
+
+def yk_heat_step_grid(ctx, bnd: Boundary, grid: yk_grid, B, flags, f_next, alpha2, tol, sigma_io, u_next,
+                      raise_on_noconv=True):
+    st = yk_stats()
+    if B.shape[0] != grid.nx * grid.ny or u_next.shape[0] != grid.nx * grid.ny:
+        raise ValueError("B and u_next need one value per grid cell")
+    s = load_library().yk_heat_step_grid(ctx, ctypes.byref(bnd.struct), ctypes.byref(grid), _dev(B, "B"),
+                                         int(flags), _dev(f_next, "f_next"), float(alpha2), float(tol),
+                                         _dev(sigma_io, "sigma_io"), _dev(u_next, "u_next"), ctypes.byref(st))
+    if s == YK_ERR_NOCONV and not raise_on_noconv:
+        return st
+    _check(ctx, s, st)
+    return st
+
+
+def yk_near_info(ctx):
+    n = ctypes.c_int64(0)
+    ms = ctypes.c_double(0.0)
+    _check(ctx, load_library().yk_near_info(ctx, ctypes.byref(n), ctypes.byref(ms)))
+    return int(n.value), float(ms.value)
 
 
 def yk_fmm_potential(ctx, vol_xy, q, bnd: Boundary, d, alpha, out_vol, out_bnd):

@@ -115,7 +115,7 @@ def test_heat_step_c0_direct(yk, ctx, oracle_lib):
                          cfg["dt"], 1e-13, sig, u)
     u_ref, s_ref, _ = oracle_lib.heat_step(b.xy, b.normal, b.weights(), b.curvature, cfg["vol"],
                                            cfg["vol_w"], cfg["B"], cfg["f_next"], cfg["dt"],
-                                           grid_h=cfg["h"])
+                                           grid_h=cfg["h"], offsets=b.offset)
     assert rel_max(host(u), u_ref) < 1e-10
     assert rel_max(host(sig), s_ref) < 1e-10
     # and the physics: close to the manufactured solution inside the domain, away from the boundary

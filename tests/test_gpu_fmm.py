@@ -181,7 +181,7 @@ def test_fmm_heat_step_c0(yk, oracle_lib):
         yk.yk_destroy(ctx)
     u_ref, s_ref, _ = oracle_lib.heat_step(b.xy, b.normal, b.weights(), b.curvature, cfg["vol"],
                                            cfg["vol_w"], cfg["B"], cfg["f_next"], cfg["dt"],
-                                           grid_h=cfg["h"])
+                                           grid_h=cfg["h"], offsets=b.offset)
     assert elem_err(host(u), u_ref) <= 1e-10, st.as_dict()
     assert elem_err(host(sig), s_ref) <= 1e-10
 

@@ -39,7 +39,7 @@ def reduced_c3(oracle_lib):
     for _ in range(4):
         B = _rhs(u, cfg["region"], cfg["consts"])
         u, sig, _ = oracle_lib.heat_step(b.xy, b.normal, b.weights(), b.curvature, cfg["vol"], cfg["vol_w"],
-                                         B, cfg["f_bnd"], cfg["dt"], grid_h=cfg["h"], bie=bie)
+                                         B, cfg["f_bnd"], cfg["dt"], grid_h=cfg["h"], bie=bie, offsets=b.offset)
         steps.append((u.copy(), sig.copy()))
     return cfg, steps
 
@@ -112,7 +112,7 @@ def test_mixed_heat_step_few_volume_points_many_nodes(yk, oracle_lib):
     finally:
         yk.yk_destroy(ctx)
     u_ref, s_ref, _ = oracle_lib.heat_step(b.xy, b.normal, b.weights(), b.curvature, cfg["vol"],
-                                           cfg["vol_w"], cfg["B"], cfg["f_next"], cfg["dt"], grid_h=cfg["h"])
+                                           cfg["vol_w"], cfg["B"], cfg["f_next"], cfg["dt"], grid_h=cfg["h"], offsets=b.offset)
     assert st.outer_iters >= 1
     assert elem_err(host(u), u_ref) <= 1e-10
     assert elem_err(host(sig), s_ref) <= 1e-10

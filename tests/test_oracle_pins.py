@@ -231,7 +231,7 @@ def test_rothe_step_closed_form(oracle_lib):
         mask = cfg["region"] < 0
         u, sig, _ = oracle_lib.heat_step(b.xy, b.normal, b.weights(), b.curvature, vol,
                                          cfg["vol_w"], cfg["B"], f1, dt, grid_h=cfg["h"],
-                                         tgt_mask=mask)
+                                         tgt_mask=mask, offsets=b.offset)
         ex = np.sin(vol[mask, 0]) * np.sin(vol[mask, 1]) / (1 + 2 * dt)
         far = b.distance_to_boundary(vol[mask]) > 0.12
         errs.append(np.max(np.abs(u - ex)[far]) / np.max(np.abs(ex)))
@@ -252,6 +252,6 @@ def test_rothe_step_without_self_cell_is_worse(oracle_lib):
     res = []
     for gh in (cfg["h"], None):
         u, _, _ = oracle_lib.heat_step(b.xy, b.normal, b.weights(), b.curvature, vol,
-                                       cfg["vol_w"], cfg["B"], f1, dt, grid_h=gh, tgt_mask=mask)
+                                       cfg["vol_w"], cfg["B"], f1, dt, grid_h=gh, tgt_mask=mask, offsets=b.offset)
         res.append(np.max(np.abs(u - ex)[far]) / np.max(np.abs(ex)))
     assert res[1] > 3 * res[0], res

@@ -3,7 +3,9 @@
 This module is shared by the tests, the benchmark and the smoke check.  It
 holds geometry and problem data only (node positions, analytic normals and
 curvatures, point clouds, manufactured solutions, boundary constants) and none
-of the method's arithmetic: no Bessel functions, no kernel sums, no solves.
+of the method's arithmetic: no kernel sums, no solves, no K0/K1.  The one
+closed form built from Bessel functions is Example 1's exact solution (J0/Y0
+from scipy.special), the reference the temporal study is measured against.
 Both the CPU oracle and the GPU library receive what it produces as plain
 arrays.
 
@@ -27,7 +29,7 @@ import numpy as np
 __all__ = [
     "Curve", "Boundary", "circle", "ellipse", "make_boundary",
     "config_c0", "config_c1", "config_c2", "config_c3", "config_c4",
-    "small_fmm_case", "sample_targets", "adaptive_cells",
+    "small_fmm_case", "sample_targets", "adaptive_cells", "example1", "example3", "grid_box",
 ]
 
 
@@ -356,3 +358,57 @@ def sample_targets(n_total: int, k: int, seed: int = 0) -> np.ndarray:
     rng = np.random.default_rng(seed)
     k = min(k, n_total)
     return np.sort(rng.choice(n_total, size=k, replace=False)).astype(np.int64)
+
+
+# ----------------------------------------------------------------------------
+# The paper's examples (Sec. 4)
+# ----------------------------------------------------------------------------
+def grid_box(lo, hi, m):
+    """(x0, y0, h, nx, ny) of an m x m cell-centred grid over [lo, hi]^2 and its points."""
+    h = (hi - lo) / m
+    pts, _ = _cell_grid(lo, hi, m)
+    return (lo, lo, h, m, m), pts
+
+
+def example1(m=256, n_outer=1024, n_inner=512, lo=-0.5, hi=0.5):
+    """Example 1: the annulus 0.1 < |x| < 0.4 (outer circle counter-clockwise,
+    hole clockwise), forcing F = 400 cos(20 r) + 20 sin(20 r) / r, Dirichlet
+    data cos 8 on r = 0.4 and cos 2 on r = 0.1, exact solution
+      u = exp(-lam^2 t) [Y0(0.1 lam) J0(lam r) - J0(0.1 lam) Y0(lam r)] + cos(20 r)
+    with lam the first root of Y0(0.1 lam) J0(0.4 lam) = J0(0.1 lam) Y0(0.4 lam)
+    (lam ~ 10.244, so the transient vanishes on both circles).  Volume points:
+    an m x m cell-centred grid over [lo, hi]^2; F is given everywhere, u is
+    extended by the boundary constants (region 0 outside, 1 in the hole)."""
+    from scipy import optimize, special
+    bnd = make_boundary([circle((0.0, 0.0), 0.4, n_outer, ccw=True),
+                         circle((0.0, 0.0), 0.1, n_inner, ccw=False)])
+    grid, pts = grid_box(lo, hi, m)
+    f = lambda l: special.y0(0.1 * l) * special.j0(0.4 * l) - special.j0(0.1 * l) * special.y0(0.4 * l)
+    lam = optimize.brentq(f, 9.0, 11.5, xtol=1e-15)
+    r = np.hypot(pts[:, 0], pts[:, 1])
+    F = 400.0 * np.cos(20.0 * r) + 20.0 * np.sin(20.0 * r) / r
+
+    def exact(xy, t):
+        rr = np.hypot(xy[:, 0], xy[:, 1])
+        z = (special.y0(0.1 * lam) * special.j0(lam * rr) - special.j0(0.1 * lam) * special.y0(lam * rr))
+        return math.exp(-lam * lam * t) * z + np.cos(20.0 * rr)
+
+    consts = np.array([math.cos(8.0), math.cos(2.0)])
+    f_bnd = np.concatenate([np.full(n_outer, consts[0]), np.full(n_inner, consts[1])])
+    return dict(name="example1", bnd=bnd, grid=grid, pts=pts, F=F, lam=lam, exact=exact,
+                consts=consts, f_bnd=f_bnd, region=bnd.region(pts))
+
+
+def example3(m=256, n_outer=1024, n_inner=512, seed=3, lo=-0.5, hi=0.5):
+    """Example 3's setting (and Example 2's domain): an elliptical region with
+    an off-centre elliptical hole, u = 0 on both curves, random initial data
+    uniform on [-1/2, 1/2] inside; the Allen-Cahn reaction u (1 - u^2) with
+    eps = 1e-5 and dt = 1 (alpha^2 = eps dt for the Euler scheme)."""
+    rng = np.random.default_rng(seed)
+    bnd = make_boundary([ellipse((0.0, 0.0), 0.45, 0.32, n_outer, rotation=0.2, ccw=True),
+                         ellipse((0.12, 0.04), 0.12, 0.07, n_inner, rotation=0.6, ccw=False)])
+    grid, pts = grid_box(lo, hi, m)
+    region = bnd.region(pts)
+    u0 = np.where(region < 0, rng.uniform(-0.5, 0.5, pts.shape[0]), 0.0)
+    return dict(name="example3", bnd=bnd, grid=grid, pts=pts, region=region, u0=u0,
+                consts=np.zeros(2), f_bnd=np.zeros(bnd.n), eps=1e-5, dt=1.0)
