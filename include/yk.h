@@ -188,14 +188,18 @@ yk_status yk_gmres_density(yk_ctx ctx, const yk_boundary *bnd, double alpha, con
  * B [n_vol] must already be extended to every volume point (values outside
  * the domain are the caller's extension, Sec. 3.1).  vol_w [n_vol] quadrature
  * weights.  flags bit0: volume points are centres of square cells of area
- * vol_w = h^2, and each gets the weight of its own cell,
- * C_self = (1/2pi) int_cell K0(|y|/alpha) dA + kappa h^2, instead of the
- * skipped self pair; kappa = 0.0396864785674955 is the lattice correction of
- * the kernel's logarithmic singularity, (c - Z'(0)/2) / (2 pi) with
- * c = (pi/2 - 3 - log 2)/2 (the mean of log|u| over the unit cell) and Z the
- * Epstein zeta function of the square lattice, 4 zeta(s) beta(s): with it
- * the rule on a uniform grid is about fourth order in h / alpha, without it
- * second order.
+ * vol_w = h^2, and each gets the weight of its own cell instead of the
+ * skipped self pair: the weight that makes the lattice rule exact for
+ * constant B (the kernel integrates to 1 over the plane),
+ *   C_self = alpha^2 - (h^2 / 2pi) sum_{j in Z^2, j != 0} K0(|j| h / alpha),
+ * and for h / alpha < 0.005 its expansion (1/2pi) int_cell K0(|y|/alpha) dA
+ * + kappa h^2, kappa = 0.0396864785674955 the lattice correction of the
+ * kernel's logarithmic singularity ((c - Z'(0)/2) / (2 pi), c the mean of
+ * log|u| over the unit cell, Z the Epstein zeta function of the square
+ * lattice).  With it the rule on a uniform grid is about fourth order in
+ * h / alpha where the cell integral alone is second order, and it tends to
+ * alpha^2 (U^p = B) for cells much larger than alpha.  The distinct cell
+ * areas of vol_w are found on the first call for an array (at most 65535).
  * f_next [N] boundary data at t^{N+1}.  sigma_io [N]: in = initial guess,
  * out = sigma^{N+1}.  flags bit1: ignore sigma_io on input (zero guess).
  * u_next [n_vol] (meaningful at points inside the domain).

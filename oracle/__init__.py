@@ -60,6 +60,8 @@ def _load():
     lib.yko_dl_kernel.argtypes = [ctypes.c_double] * 7
     lib.yko_dl_diag.restype = ctypes.c_double
     lib.yko_dl_diag.argtypes = [ctypes.c_double] * 3
+    lib.yko_lattice_k0_sum.restype = ctypes.c_double
+    lib.yko_lattice_k0_sum.argtypes = [ctypes.c_double]
     for name in ("yko_k0_vec", "yko_k1_vec", "yko_i0_vec", "yko_i1_vec"):
         f = getattr(lib, name)
         f.restype = None
@@ -181,6 +183,11 @@ def apply_bie(bxy, bnormal, w, kappa, sigma, alpha) -> np.ndarray:
 # ---------------------------------------------------------------------------
 # Self-cell correction for grid points
 # ---------------------------------------------------------------------------
+def lattice_k0_sum(eps: float) -> float:
+    """sum over the nonzero points j of Z^2 with |j| eps <= 40 of K0(|j| eps)."""
+    return float(_load().yko_lattice_k0_sum(float(eps)))
+
+
 def self_cell(h: float, alpha: float, n_gauss: int = 48) -> float:
     """(1/2pi) int over the h x h cell centred at the target of K0(|y|/alpha) dA.
 
@@ -220,8 +227,10 @@ def heat_step(bnd_xy, bnd_normal, bnd_w, bnd_kappa, vol_xy, vol_w, B, f_next, dt
 
       q      = W * B
       U^p    = (V[q] + B * C_self) / alpha^2   (C_self only for grid points:
-               the cell integral plus the lattice correction, grid.self_weight)
-      g      = f^{N+1} - U^p on the nodes
+               the constant-exact lattice weight, grid.self_weight)
+      g      = f^{N+1} - U^p on the nodes (for grid points, the cells within
+               two sides of a node enter with their integral,
+               grid.node_cell_correction)
       sigma  = A^{-1} (-2 alpha^2 g)
       u^{N+1} = U^p + DL[w sigma] / alpha^2, and at targets within a few node
                spacings of a curve U^h from grid.near_values (when the curve
@@ -242,6 +251,9 @@ def heat_step(bnd_xy, bnd_normal, bnd_w, bnd_kappa, vol_xy, vol_w, B, f_next, dt
     if grid_h is not None:
         Vv = Vv + Bt * _grid.self_weight(grid_h, alpha)
     Vb = volume_sum(vol_xy, q, alpha, tgt_xy=bnd_xy)
+    if grid_h is not None:
+        # cells next to a node enter with their integral (grid.node_cell_correction)
+        Vb = Vb + _grid.node_cell_correction(bnd_xy, vol_xy, vol_w, B, alpha)
     up_b = Vb / alpha ** 2
     g = _f64(f_next) - up_b
     if bie is None:

@@ -13,10 +13,11 @@ passage of Kropinski & Quaife (arXiv 1007.5335) or a stated reading of it:
     u is extended by the boundary constants outside the domain (Sec. 3.1),
     F by the caller;
   * self_weight: the weight of a grid point's own cell in the lattice rule of
-    the volume potential (eq. vol_potential on a uniform grid): the integral
-    of the kernel over the cell plus kappa h^2, the lattice correction of the
-    kernel's logarithmic singularity (derivation at self_weight; the
-    corrected rule is about fourth order in h / alpha instead of second);
+    the volume potential (eq. vol_potential on a uniform grid): the weight
+    that makes the rule exact for constant B (the kernel integrates to 1 over
+    the plane), alpha^2 - (h^2 / 2 pi) sum' K0(|j| h / alpha); for
+    h / alpha < 0.005 its expansion, the cell integral plus kappa h^2 (the
+    lattice correction of the logarithmic singularity);
   * bicubic: U^p at off-grid points (the boundary nodes) by tensor cubic
     Lagrange interpolation of the grid values, the point-grid counterpart of
     evaluating each leaf's cubic polynomial (Sec. 3.1);
@@ -105,17 +106,30 @@ LATTICE_SELF = ((math.pi / 2 - 3 - math.log(2)) / 2
                 - (0.5 * math.log(4 * math.pi) - 2 * math.lgamma(0.25))) / (2 * math.pi)
 
 
-def self_weight(h: float, alpha: float) -> float:
-    """(1/2pi) int_cell K0(|y|/alpha) dA + kappa h^2 (library normalisation).
+SELF_WEIGHT_SERIES_BELOW = 0.005
 
-    Near the target the kernel is -(1/2pi) log|x| times a smooth factor.  By
-    the generalised Euler-Maclaurin expansion of lattice sums (differentiate
-    h^2 sum' |jh|^(-2s) psi(jh) - int |x|^(-2s) psi = h^(2-2s) Z(s) psi(0) + ...
-    at s = 0, with Z(0) = -1), the punctured lattice sum of log|x| psi misses
-    h^2 psi(0) (log h + Z'(0)/2), while the cell integral supplies
-    h^2 psi(0) (log h + c_cell); the difference, with the kernel's -1/(2pi),
-    is kappa h^2 psi(0).  The next terms are O(h^4) up to logarithms."""
-    return self_cell(h, alpha) + LATTICE_SELF * h * h
+
+def self_weight(h: float, alpha: float) -> float:
+    """The own-cell weight w0 (library normalisation, U^p = (V + B w0) / alpha^2).
+
+    The lattice rule sum_j h^2 G(x_i - x_j) B_j with the self pair weighted by
+    w0 / alpha^2 integrates a constant B exactly when
+      w0 = alpha^2 - (h^2 / 2 pi) sum_{j != 0} K0(|j| h / alpha)
+    (the kernel G = K0 / (2 pi alpha^2) integrates to 1 over the plane).  For
+    small eps = h / alpha its expansion is the cell integral plus kappa h^2:
+    near the target the kernel is -(1/2pi) log|x| times a smooth factor psi;
+    by the generalised Euler-Maclaurin expansion of lattice sums (the
+    derivative at s = 0 of h^2 sum' |jh|^(-2s) psi(jh) - int |x|^(-2s) psi =
+    h^(2-2s) Z(s) psi(0) + ..., Z(0) = -1) the punctured sum of log|x| psi
+    misses h^2 psi(0) (log h + Z'(0)/2), while the cell integral supplies
+    h^2 psi(0) (log h + c_cell).  The expansion's relative error is about
+    0.04 eps^2 (a U^p error of 0.04 eps^4 B); it is used below eps = 0.005,
+    where the lattice sum would need more than 10^7 terms."""
+    eps = h / alpha
+    if eps < SELF_WEIGHT_SERIES_BELOW:
+        return self_cell(h, alpha) + LATTICE_SELF * h * h
+    from . import lattice_k0_sum
+    return alpha * alpha - h * h / (2.0 * math.pi) * lattice_k0_sum(eps)
 
 
 def bicubic(values, x0, y0, h, nx, ny, pts) -> np.ndarray:
@@ -145,6 +159,85 @@ def bicubic(values, x0, y0, h, nx, ny, pts) -> np.ndarray:
     for b in range(4):
         for a in range(4):
             out += wy[:, b] * wx[:, a] * V[iy + b - 1, ix + a - 1]
+    return out
+
+
+def cell_k0_integral(px, py, cx, cy, h, alpha, n_gauss=64):
+    """(1/2pi) int over the square of side h centred at (cx, cy) of K0(|y - p|/alpha) dA.
+
+    The square is the signed sum of the four triangles with apex p and one
+    edge each (sign = orientation of (p, a, b)).  Over a triangle, in polar
+    coordinates about p, the radial integral is F(R) = alpha^2 - alpha R K1(R/alpha)
+    (d/dr of -alpha r K1(r/alpha) is r K0(r/alpha)); along the edge, at signed
+    coordinate t from the foot of the perpendicular (distance q), R = q cosh s
+    and dtheta = ds / cosh s with t = q sinh s.  The s-integral is taken by
+    Gauss-Legendre on unit panels.  Vectorised over the inputs."""
+    from . import k1
+    px, py, cx, cy, h = (np.atleast_1d(_f64(v)).astype(np.float64) for v in (px, py, cx, cy, h))
+    n = max(px.size, cx.size, h.size)
+    px, py, cx, cy, h = (np.broadcast_to(v, (n,)).copy() for v in (px, py, cx, cy, h))
+    xg, wg = np.polynomial.legendre.leggauss(n_gauss)
+    corners = [(-0.5, -0.5), (0.5, -0.5), (0.5, 0.5), (-0.5, 0.5)]
+    total = np.zeros(n)
+    for e in range(4):
+        ax, ay = cx + corners[e][0] * h, cy + corners[e][1] * h
+        bx, by = cx + corners[(e + 1) % 4][0] * h, cy + corners[(e + 1) % 4][1] * h
+        ex, ey = (bx - ax) / h, (by - ay) / h               # unit edge direction
+        q = (ax - px) * ey - (ay - py) * ex                 # signed distance (outward normal (ey, -ex))
+        ta = (ax - px) * ex + (ay - py) * ey
+        tb = ta + h
+        aq = np.abs(q)
+        ok = aq > 1e-300
+        sa = np.where(ok, np.arcsinh(ta / np.where(ok, aq, 1.0)), 0.0)
+        sb = np.where(ok, np.arcsinh(tb / np.where(ok, aq, 1.0)), 0.0)
+        npan = np.maximum(1, np.ceil(sb - sa)).astype(np.int64)
+        acc = np.zeros(n)
+        for npv in np.unique(npan[ok]):          # pairs with the same panel count together
+            sel = np.flatnonzero(ok & (npan == npv))
+            for c0 in range(0, sel.size, 4096):
+                ii = sel[c0:c0 + 4096]
+                frac = np.arange(npv + 1) / npv
+                edges = sa[ii, None] + (sb[ii] - sa[ii])[:, None] * frac[None, :]   # [m, npv+1]
+                mid = 0.5 * (edges[:, 1:] + edges[:, :-1])
+                half = 0.5 * (edges[:, 1:] - edges[:, :-1])
+                sv = mid[:, :, None] + half[:, :, None] * xg[None, None, :]
+                wv = half[:, :, None] * wg[None, None, :]
+                R = aq[ii, None, None] * np.cosh(sv)
+                F = alpha * alpha - alpha * R * k1((R / alpha).ravel()).reshape(R.shape)
+                acc[ii] = np.sum(wv * F / np.cosh(sv), axis=(1, 2))
+        total += np.sign(q) * acc
+    return total / (2.0 * math.pi)
+
+
+def node_cell_pairs(bxy, vol_xy, vol_w, reach=2.0):
+    """(node, cell) pairs with the node closer to the cell centre than reach
+    cell sides (cells: squares of area vol_w centred at vol_xy)."""
+    bxy = _f64(bxy); vol_xy = _f64(vol_xy); hs = np.sqrt(_f64(vol_w))
+    ni, ci = [], []
+    for s0 in range(0, bxy.shape[0], 256):
+        blk = bxy[s0:s0 + 256]
+        d2 = ((blk[:, None, :] - vol_xy[None, :, :]) ** 2).sum(-1)
+        a, c = np.nonzero(d2 < (reach * hs[None, :]) ** 2)
+        ni.append(a + s0); ci.append(c)
+    return np.concatenate(ni), np.concatenate(ci)
+
+
+def node_cell_correction(bxy, vol_xy, vol_w, B, alpha):
+    """Change of V[q](node) (q = vol_w B, library normalisation without 1/alpha^2)
+    when the cells near each node enter with their integral instead of the
+    point value: sum over the pairs of B_j (cell integral - point value)."""
+    from . import k0
+    ni, ci = node_cell_pairs(bxy, vol_xy, vol_w)
+    out = np.zeros(_f64(bxy).shape[0])
+    if ni.size == 0:
+        return out
+    vx, bb, w = _f64(vol_xy), _f64(B), _f64(vol_w)
+    hs = np.sqrt(w)
+    P = _f64(bxy)[ni]
+    integ = cell_k0_integral(P[:, 0], P[:, 1], vx[ci, 0], vx[ci, 1], hs[ci], alpha)
+    d = np.hypot(P[:, 0] - vx[ci, 0], P[:, 1] - vx[ci, 1])
+    point = np.where(d > 0, w[ci] * k0(np.where(d > 0, d, 1.0) / alpha) / (2.0 * math.pi), 0.0)
+    np.add.at(out, ni, bb[ci] * (integ - point))
     return out
 
 

@@ -209,6 +209,28 @@ void yko_dl_matrix(int64_t nb, const double *bxy, const double *bn, const double
     }
 }
 
+/* S(eps) = sum over the nonzero points j of the square lattice with
+ * |j| eps <= 40 of K0(|j| eps) (the terms beyond are below 1e-17 of the
+ * sum), by the eight-fold symmetry of the lattice: the axes (4 each), the
+ * diagonals (4 each) and the points a > b >= 1 (8 each). */
+double yko_lattice_k0_sum(double eps) {
+    const double rmax = 40.0;
+    const long A = (long)floor(rmax / eps);
+    double s = 0.0;
+    for (long a = 1; a <= A; ++a) {
+        const double ra = (double)a * eps;
+        s += 4.0 * yko_k0(ra);
+        const double rd = sqrt(2.0) * ra;
+        if (rd <= rmax) s += 4.0 * yko_k0(rd);
+        for (long b = 1; b < a; ++b) {
+            const double r = sqrt((double)(a * a + b * b)) * eps;
+            if (r > rmax) break;
+            s += 8.0 * yko_k0(r);
+        }
+    }
+    return s;
+}
+
 /* Vectorised helpers so tests can evaluate the oracle's special functions. */
 void yko_k0_vec(int64_t n, const double *z, double *out) {
     for (int64_t i = 0; i < n; ++i) out[i] = yko_k0(z[i]);

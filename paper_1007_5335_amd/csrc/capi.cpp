@@ -5,6 +5,7 @@
 #include <chrono>
 #include <cmath>
 #include <new>
+#include <unordered_map>
 
 #include "fmm.h"
 #include "mlp.h"
@@ -508,8 +509,11 @@ yk_status yk_invalidate_geometry(yk_ctx ctx) {
         c.plan_near.reset();
         c.plan_nearc.reset();
         c.near.reset();
+        c.cell_nodes.reset();
         c.grid_nx = c.grid_ny = 0;
         c.grid_bnd_gen = 0;
+        c.self_w = nullptr;
+        c.self_n = 0;
         c.bnd.reset();
         c.memo_valid = false;
         return YK_OK;
@@ -605,6 +609,58 @@ yk_status yk_gmres_density(yk_ctx ctx, const yk_boundary *bnd, double alpha, con
         }
         return YK_OK;
     });
+}
+
+// Own-cell weights of cell centres whose areas are vol_w (yk_heat_step flags
+// bit0): the distinct areas are found once per array (key: pointer and
+// size), an index per point is kept on the device, and the weights are
+// recomputed when alpha changes.
+static const double *self_weights(Context &c, int64_t n, const double *vol_w, double alpha,
+                                  const uint16_t **idx_out) {
+    if (c.self_w != vol_w || c.self_n != n) {
+        std::vector<double> hw((size_t)n);
+        YK_HIP(hipMemcpyAsync(hw.data(), vol_w, n * sizeof(double), hipMemcpyDeviceToHost, c.stream));
+        YK_HIP(hipStreamSynchronize(c.stream));
+        std::unordered_map<uint64_t, int> seen;
+        std::vector<double> distinct;
+        for (int64_t i = 0; i < n; ++i) {
+            uint64_t bits;
+            std::memcpy(&bits, &hw[i], sizeof(bits));
+            if (seen.emplace(bits, (int)distinct.size()).second) {
+                YK_REQUIRE(std::isfinite(hw[i]) && hw[i] > 0.0, "vol_w must be finite and > 0");
+                YK_REQUIRE(distinct.size() < 65535, "cell centres (flags bit0) need at most 65535 distinct cell areas");
+                distinct.push_back(hw[i]);
+            }
+        }
+        std::sort(distinct.begin(), distinct.end());
+        std::unordered_map<uint64_t, uint16_t> rank;
+        for (size_t k = 0; k < distinct.size(); ++k) {
+            uint64_t bits;
+            std::memcpy(&bits, &distinct[k], sizeof(bits));
+            rank[bits] = (uint16_t)k;
+        }
+        std::vector<uint16_t> hidx((size_t)n);
+        for (int64_t i = 0; i < n; ++i) {
+            uint64_t bits;
+            std::memcpy(&bits, &hw[i], sizeof(bits));
+            hidx[i] = rank[bits];
+        }
+        YK_HIP(hipMemcpyAsync(c.self_idx.ensure(n), hidx.data(), n * sizeof(uint16_t), hipMemcpyHostToDevice,
+                              c.stream));
+        YK_HIP(hipMemcpyAsync(c.self_dh2.ensure(distinct.size()), distinct.data(), distinct.size() * sizeof(double),
+                              hipMemcpyHostToDevice, c.stream));
+        YK_HIP(hipStreamSynchronize(c.stream));
+        c.self_h2 = distinct;
+        c.self_w = vol_w;
+        c.self_n = n;
+        c.self_alpha = 0.0;
+    }
+    if (c.self_alpha != alpha) {
+        launch_self_weights(c, (int)c.self_h2.size(), c.self_dh2.p, alpha, c.self_w0.ensure(c.self_h2.size()));
+        c.self_alpha = alpha;
+    }
+    *idx_out = c.self_idx.p;
+    return c.self_w0.p;
 }
 
 // The attached warm start must have been made for this boundary: its
@@ -737,6 +793,11 @@ yk_status yk_heat_step(yk_ctx ctx, const yk_boundary *bnd, int64_t n_vol, const 
             pk.keep_charge_m = (c.opt.debug_flags & 8) ? 0 : 1;   // the assembly below has the same charges
             evaluate_sums(c, SLOT_VOL, pk, q, nullptr, outs, vprec);
         }
+        // cell centres: the cells next to a node enter with their integral
+        if (flags & 1) {
+            CellNodePlan &cp = cells_prepare(c, bd, n_vol, vol_xy, vol_w);
+            cells_correct_nodes(c, cp, bd, vol_xy, vol_w, B, alpha, vb);
+        }
         double *b = c.ws_f.ensure(nb);
         launch_axpby(c, nb, -2.0 * a2, f_next, 2.0, vb, b);
         if (stats) {   // (phase times need a synchronisation)
@@ -762,7 +823,11 @@ yk_status yk_heat_step(yk_ctx ctx, const yk_boundary *bnd, int64_t n_vol, const 
             pr.bie = &f;
             evaluate_sums(c, SLOT_VOL, pr, q, nullptr, outs, vprec);
         }
-        if (flags & 1) launch_self_cell(c, n_vol, vol_w, 0.0, B, alpha, 1.0 / a2, u_next);
+        if (flags & 1) {
+            const uint16_t *sidx = nullptr;
+            const double *w0 = self_weights(c, n_vol, vol_w, alpha, &sidx);
+            launch_self_cell(c, n_vol, sidx, w0, B, 1.0 / a2, u_next);
+        }
         else launch_axpby(c, n_vol, 1.0 / a2, u_next, 0.0, nullptr, u_next);
         // targets closer to a curve than a few node spacings: U^h from the
         // curves' interpolants instead of the node sums
@@ -860,7 +925,16 @@ yk_status yk_heat_step_grid(yk_ctx ctx, const yk_boundary *bnd, const yk_grid *g
             double *outs[3] = {up, nullptr, nullptr};
             evaluate_sums(c, SLOT_VOL, pb, q, nullptr, outs, vprec);
         }
-        launch_self_cell(c, n, nullptr, h * h, B, alpha, 1.0 / a2, up);
+        if (c.grid_w0_key[0] != h * h || c.grid_w0_key[1] != alpha || !c.grid_w0.p) {
+            double *dh2 = c.grid_w0.ensure(2);
+            const double hh = h * h;
+            YK_HIP(hipMemcpyAsync(dh2 + 1, &hh, sizeof(double), hipMemcpyHostToDevice, c.stream));
+            launch_self_weights(c, 1, dh2 + 1, alpha, dh2);
+            YK_HIP(hipStreamSynchronize(c.stream));
+            c.grid_w0_key[0] = hh;
+            c.grid_w0_key[1] = alpha;
+        }
+        launch_self_cell(c, n, nullptr, c.grid_w0.p, B, 1.0 / a2, up);
         // U^p on the nodes by bicubic interpolation; b = -2 alpha^2 (f - U^p), g = f - U^p
         double *vb = c.ws_e.ensure(nb);
         launch_bicubic(c, nb, bd.xy, grid->x0, grid->y0, h, grid->nx, grid->ny, up, vb);

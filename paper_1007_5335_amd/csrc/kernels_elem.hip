@@ -143,16 +143,24 @@ __constant__ double c_gl_w[32];
 // target's own square cell (8 right triangles with apex at the centre).  When
 // all points of a wavefront share one cell size (a uniform grid) the 32 nodes
 // of the rule are spread over the lanes and c(h) is formed once per wavefront.
-// Lattice correction of a grid point's own weight.  Near the target the kernel
-// is -(1/2pi) log|x| times a smooth factor psi; the punctured lattice sum of
+// The own-cell weight w0 of a grid point (U^p = (V + B w0) / alpha^2): the
+// weight that makes the lattice rule exact for constant B, the kernel
+// K0 / (2 pi alpha^2) integrating to 1 over the plane:
+//   w0 = alpha^2 - (h^2 / 2 pi) sum_{j != 0} K0(|j| eps),  eps = h / alpha,
+// the sum over the nonzero points of the square lattice with |j| eps <= 40
+// (the rest is below 1e-17 of it), taken by the lattice's eight-fold
+// symmetry.  Below eps = 0.005 (more than 10^7 terms) its expansion is used:
+// the cell integral plus kappa h^2.  Near the target the kernel is
+// -(1/2pi) log|x| times a smooth factor psi; the punctured lattice sum of
 // log|x| psi misses h^2 psi(0) (log h + Z'(0)/2) (generalised Euler-Maclaurin
 // expansion of lattice sums; Z(s) = 4 zeta(s) beta(s) is the Epstein zeta
 // function of the square lattice, Z'(0)/2 = log(4 pi)/2 - 2 log Gamma(1/4)),
 // while the cell integral supplies h^2 psi(0) (log h + c_cell) with
-// c_cell = (pi/2 - 3 - log 2) / 2; the difference, with the kernel's -1/(2pi),
-// is kappa h^2 psi(0), kappa = (c_cell - Z'(0)/2) / (2 pi).  With it the rule
-// is about fourth order in h / alpha instead of second.
+// c_cell = (pi/2 - 3 - log 2) / 2, so kappa = (c_cell - Z'(0)/2) / (2 pi).
+// The expansion's relative error is about 0.04 eps^2.
 constexpr double kLatticeSelf = 0.039686478567495465;
+constexpr double kSelfSeriesBelow = 0.005;
+constexpr double kLatticeReach = 40.0;
 
 __device__ __forceinline__ double self_cell_node(int k, double h, double alpha) {
     const double th = (c_gl_x[k] + 1.0) * (kPi / 8.0);
@@ -160,27 +168,51 @@ __device__ __forceinline__ double self_cell_node(int k, double h, double alpha) 
     return c_gl_w[k] * (alpha * alpha - alpha * R * k1(R / alpha));
 }
 
-__global__ __launch_bounds__(256) void k_self_cell(int64_t n, const double *__restrict__ vol_w, double w_const,
-                                                   const double *__restrict__ B, double alpha,
-                                                   double scale, double *__restrict__ out) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const bool in = i < n;
-    const int lane = threadIdx.x & 63;
-    const double h2 = in ? (vol_w ? vol_w[i] : w_const) : 0.0;
-    const double h = sqrt(h2);
-    // lane 0 of a wavefront with any point in range is in range itself
-    const double h0 = __shfl(h, 0);
-    double s;
-    if (__all(!in || h == h0)) {
-        s = lane < 32 ? self_cell_node(lane, h0, alpha) : 0.0;
-#pragma unroll
-        for (int m = 32; m >= 1; m >>= 1) s += __shfl_xor(s, m);
+// one block of 256 per cell size: w0[d] for the squared side h2[d]
+__global__ __launch_bounds__(256) void k_self_weights(int nd, const double *__restrict__ h2, double alpha,
+                                                      double *__restrict__ w0) {
+    __shared__ double red[256];
+    const int d = blockIdx.x;
+    if (d >= nd) return;
+    const double h = sqrt(h2[d]), eps = h / alpha;
+    double s = 0.0;
+    if (eps < kSelfSeriesBelow) {
+        if (threadIdx.x < 32) s = self_cell_node(threadIdx.x, h, alpha);
     } else {
-        s = 0.0;
-        for (int k = 0; k < 32; ++k) s += self_cell_node(k, h, alpha);
+        const int64_t A = (int64_t)floor(kLatticeReach / eps);
+        for (int64_t a = 1 + threadIdx.x; a <= A; a += blockDim.x) {
+            const double ra = (double)a * eps;
+            double t = 4.0 * k0(ra);
+            const double rd = 1.4142135623730951 * ra;
+            if (rd <= kLatticeReach) t += 4.0 * k0(rd);
+            for (int64_t b = 1; b < a; ++b) {
+                const double r = sqrt((double)(a * a + b * b)) * eps;
+                if (r > kLatticeReach) break;
+                t += 8.0 * k0(r);
+            }
+            s += t;
+        }
     }
-    // the cell integral plus the lattice correction kappa h^2 (kLatticeSelf)
-    if (in) out[i] = scale * (out[i] + B[i] * ((8.0 * (kPi / 8.0) * kInv2Pi) * s + kLatticeSelf * h2));
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        if (eps < kSelfSeriesBelow)
+            w0[d] = (8.0 * (kPi / 8.0) * kInv2Pi) * red[0] + kLatticeSelf * h2[d];
+        else
+            w0[d] = alpha * alpha - h2[d] * kInv2Pi * red[0];
+    }
+}
+
+// out = scale (out + B w0[idx]) (idx NULL: one size, w0[0])
+__global__ void k_self_cell(int64_t n, const uint16_t *__restrict__ idx, const double *__restrict__ w0,
+                            const double *__restrict__ B, double scale, double *__restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    out[i] = scale * (out[i] + B[i] * w0[idx ? idx[i] : 0]);
 }
 
 __global__ void k_grid_points(int64_t n, double x0, double y0, double h, int64_t nx, double *__restrict__ xy) {
@@ -402,8 +434,7 @@ void launch_bicubic(Context &ctx, int64_t n, const double *xy, double x0, double
     check_launch(ctx, "k_bicubic");
 }
 
-void launch_self_cell(Context &ctx, int64_t n, const double *vol_w, double w_const, const double *B, double alpha,
-                      double scale, double *out_accum) {
+void launch_self_weights(Context &ctx, int nd, const double *h2, double alpha, double *w0) {
     static bool ready = false;
     static double gx[32], gw[32];
     if (!ready) {
@@ -412,8 +443,13 @@ void launch_self_cell(Context &ctx, int64_t n, const double *vol_w, double w_con
     }
     YK_HIP(hipMemcpyToSymbolAsync(HIP_SYMBOL(c_gl_x), gx, sizeof(gx), 0, hipMemcpyHostToDevice, ctx.stream));
     YK_HIP(hipMemcpyToSymbolAsync(HIP_SYMBOL(c_gl_w), gw, sizeof(gw), 0, hipMemcpyHostToDevice, ctx.stream));
-    hipLaunchKernelGGL(k_self_cell, dim3(nblk(n, 256)), dim3(256), 0, ctx.stream, n, vol_w, w_const, B,
-                       alpha, scale, out_accum);
+    hipLaunchKernelGGL(k_self_weights, dim3(nd), dim3(256), 0, ctx.stream, nd, h2, alpha, w0);
+    check_launch(ctx, "k_self_weights");
+}
+
+void launch_self_cell(Context &ctx, int64_t n, const uint16_t *idx, const double *w0, const double *B, double scale,
+                      double *out_accum) {
+    hipLaunchKernelGGL(k_self_cell, dim3(nblk(n, 256)), dim3(256), 0, ctx.stream, n, idx, w0, B, scale, out_accum);
     check_launch(ctx, "k_self_cell");
 }
 

