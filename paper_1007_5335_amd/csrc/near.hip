@@ -25,6 +25,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <memory>
 #include <vector>
 
 #include "sums.h"
@@ -61,6 +62,17 @@ struct NearPlan {
     DevBuf<double> fdn;              // [n_fine][2]
     DevBuf<double> chk_val;          // [n_near * K]
     DevBuf<double> coarse;           // [n_near]
+    DevBuf<double> gstar;            // [n_near] g(theta*)
+    // curves whose node count is a power of two up to 2^kFftMaxLog take the
+    // LDS FFTs, grouped by size; the others the direct sums (flag 1 = skip there)
+    struct FftGroup {
+        int logn = 0;
+        int count = 0;
+        DevBuf<int32_t> ids;
+    };
+    std::vector<std::unique_ptr<FftGroup>> fft;
+    DevBuf<int8_t> fft_curve;        // [n_curves]: 1 when the curve takes the FFTs
+    bool any_direct = false;
     double setup_ms = 0;
 };
 
@@ -84,10 +96,12 @@ __device__ __forceinline__ int find_curve(const int64_t *__restrict__ off, int n
 // index in the curve; v read with a stride, coefficients written at
 // coef[i * cs + 2 * cc + {0, 1}]
 __global__ void k_curve_dft(int64_t nb, int n_curves, const int64_t *__restrict__ off, const double *__restrict__ v,
-                            int vs, int vc, double *__restrict__ coef, int cs, int cc) {
+                            int vs, int vc, double *__restrict__ coef, int cs, int cc,
+                            const int8_t *__restrict__ skip) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= nb) return;
     const int c = find_curve(off, n_curves, i, 1);
+    if (skip && skip[c]) return;
     const int64_t base = off[c], N = off[c + 1] - base, k = i - base;
     double re = 0.0, im = 0.0;
     for (int64_t j = 0; j < N; ++j) {
@@ -245,10 +259,12 @@ __global__ void k_check_points(int64_t nn, const int64_t *__restrict__ idx, cons
 // dipole vectors of the finer rule: w sigma(theta) n, sigma interpolated
 __global__ void k_fine_dipoles(int64_t nf, int n_curves, const int64_t *__restrict__ off,
                                const double *__restrict__ scoef, const double *__restrict__ fnrm,
-                               const double *__restrict__ fw, double *__restrict__ fdn) {
+                               const double *__restrict__ fw, double *__restrict__ fdn,
+                               const int8_t *__restrict__ skip) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= nf) return;
     const int c = find_curve(off, n_curves, i, kNearM);
+    if (skip && skip[c]) return;
     const int64_t base = off[c], N = off[c + 1] - base, M = kNearM * N, k = i - kNearM * base;
     double v[1], d1[1], d2[1];
     series_eval<1>(scoef + base * 2, 2, N, kTwoPi * (double)k / (double)M, v, d1, d2);
@@ -257,22 +273,143 @@ __global__ void k_fine_dipoles(int64_t nf, int n_curves, const int64_t *__restri
     fdn[2 * i + 1] = s * fnrm[2 * i + 1];
 }
 
+// Fourier coefficients c_k = (1/N) sum_j v_j e^{-2 pi i j k / N} of a curve
+// whose N = 2^LOGN, by an in-place radix-2 FFT in LDS (input in bit-reversed
+// order, decimation in time); one workgroup per (curve, field)
+template <int LOGN>
+__global__ __launch_bounds__(256) void k_fft_coef(const int32_t *__restrict__ curves, const int64_t *__restrict__ off,
+                                                  const double *__restrict__ v0, const double *__restrict__ v1,
+                                                  double *__restrict__ c0, double *__restrict__ c1) {
+    constexpr int N = 1 << LOGN;
+    __shared__ double re[N], im[N];
+    const int64_t base = off[curves[blockIdx.x]];
+    const double *v = blockIdx.y ? v1 : v0;
+    double *cf = blockIdx.y ? c1 : c0;
+    for (int i = threadIdx.x; i < N; i += blockDim.x) {
+        const int j = (int)(__brev((unsigned)i) >> (32 - LOGN));
+        re[j] = v[base + i];
+        im[j] = 0.0;
+    }
+    __syncthreads();
+    for (int s = 1; s <= LOGN; ++s) {
+        const int half = 1 << (s - 1);
+        for (int t = threadIdx.x; t < N / 2; t += blockDim.x) {
+            const int k = t & (half - 1), i = ((t >> (s - 1)) << s) + k, j = i + half;
+            double sn, cs;
+            sincospi(-(double)k / (double)half, &sn, &cs);
+            const double tr = re[j] * cs - im[j] * sn, ti = re[j] * sn + im[j] * cs;
+            re[j] = re[i] - tr;
+            im[j] = im[i] - ti;
+            re[i] += tr;
+            im[i] += ti;
+        }
+        __syncthreads();
+    }
+    for (int i = threadIdx.x; i < N; i += blockDim.x) {
+        cf[2 * (base + i)] = re[i] * (1.0 / N);
+        cf[2 * (base + i) + 1] = im[i] * (1.0 / N);
+    }
+}
+
+// The interpolant at the finer nodes theta = 2 pi (m j + r) / (m N) as m
+// inverse FFTs of size N of the shifted coefficients c_k e^{i kk phi},
+// phi = 2 pi r / (m N), kk the signed mode (the Nyquist mode of an even N
+// contributes c_{N/2} cos(N theta / 2)); one workgroup per (curve, r); writes
+// the finer rule's dipole vectors w sigma n
+template <int LOGN>
+__global__ __launch_bounds__(256) void k_fft_fine(const int32_t *__restrict__ curves, const int64_t *__restrict__ off,
+                                                  const double *__restrict__ coef, const double *__restrict__ fnrm,
+                                                  const double *__restrict__ fw, double *__restrict__ fdn) {
+    constexpr int N = 1 << LOGN;
+    constexpr int M = kNearM * N;
+    __shared__ double re[N], im[N];
+    const int cidx = blockIdx.x / kNearM, r = blockIdx.x - cidx * kNearM;
+    const int64_t base = off[curves[cidx]];
+    for (int k = threadIdx.x; k < N; k += blockDim.x) {
+        const int j = (int)(__brev((unsigned)k) >> (32 - LOGN));
+        const double a = coef[2 * (base + k)], b = coef[2 * (base + k) + 1];
+        if (2 * k == N) {
+            re[j] = a * cospi((double)r / kNearM);
+            im[j] = 0.0;
+        } else {
+            const int kk = 2 * k < N ? k : k - N;
+            double sn, cs;
+            sincospi(2.0 * (double)kk * (double)r / (double)M, &sn, &cs);
+            re[j] = a * cs - b * sn;
+            im[j] = a * sn + b * cs;
+        }
+    }
+    __syncthreads();
+    for (int s = 1; s <= LOGN; ++s) {
+        const int half = 1 << (s - 1);
+        for (int t = threadIdx.x; t < N / 2; t += blockDim.x) {
+            const int k = t & (half - 1), i = ((t >> (s - 1)) << s) + k, j = i + half;
+            double sn, cs;
+            sincospi((double)k / (double)half, &sn, &cs);
+            const double tr = re[j] * cs - im[j] * sn, ti = re[j] * sn + im[j] * cs;
+            re[j] = re[i] - tr;
+            im[j] = im[i] - ti;
+            re[i] += tr;
+            im[i] += ti;
+        }
+        __syncthreads();
+    }
+    for (int j = threadIdx.x; j < N; j += blockDim.x) {
+        const int64_t f = kNearM * base + (int64_t)kNearM * j + r;
+        const double sgm = fw[f] * re[j];
+        fdn[2 * f] = sgm * fnrm[2 * f];
+        fdn[2 * f + 1] = sgm * fnrm[2 * f + 1];
+    }
+}
+
+// g(theta*) at the near targets, one wavefront per target: the lanes split the
+// modes in contiguous runs (e^{ik theta} by recurrence, re-seeded every 32),
+// and the partial sums meet in a fixed shuffle tree
+__global__ __launch_bounds__(256) void k_near_g(int64_t nn, const int32_t *__restrict__ cur,
+                                                const double *__restrict__ th, const int64_t *__restrict__ off,
+                                                const double *__restrict__ gcoef, double *__restrict__ gstar) {
+    const int64_t w = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int lane = threadIdx.x & 63;
+    if (w >= nn) return;   // whole wavefronts leave together
+    const int c = cur[w];
+    const int64_t base = off[c], N = off[c + 1] - base, kmax = (N - 1) / 2;
+    const double t = th[w];
+    const double *cf = gcoef + 2 * base;
+    const int64_t chunk = (kmax + 63) / 64, k0 = 1 + lane * chunk, k1 = min(kmax, k0 + chunk - 1);
+    double acc = 0.0;
+    if (k0 <= k1) {
+        double s1, c1, ei, er;
+        sincos(t, &s1, &c1);
+        sincos((double)k0 * t, &ei, &er);
+        for (int64_t k = k0; k <= k1; ++k) {
+            if (k > k0 && (k & 31) == 0) {
+                sincos((double)k * t, &ei, &er);
+            } else if (k > k0) {
+                const double nr = er * c1 - ei * s1;
+                ei = er * s1 + ei * c1;
+                er = nr;
+            }
+            acc += 2.0 * (cf[2 * k] * er - cf[2 * k + 1] * ei);
+        }
+    }
+    for (int m = 32; m >= 1; m >>= 1) acc += __shfl_xor(acc, m);
+    if (lane == 0) {
+        double v = cf[0] + acc;
+        if ((N & 1) == 0) v += cf[2 * (N / 2)] * cos(0.5 * (double)N * t);
+        gstar[w] = v;
+    }
+}
+
 // U^h at the near targets from the polynomial through (0, g(theta*)) and the
 // check points, then out[idx] = (base[idx] or out[idx] - coarse / alpha^2) + U^h
-__global__ void k_near_finish(int64_t nn, const int64_t *__restrict__ idx, const int32_t *__restrict__ cur,
-                              const double *__restrict__ th, const double *__restrict__ d,
-                              const double *__restrict__ sp, const int64_t *__restrict__ off,
-                              const double *__restrict__ gcoef, const double *__restrict__ chk_val,
-                              const double *__restrict__ coarse, const double *__restrict__ base_vals,
-                              double inv_a2, double *__restrict__ out) {
+__global__ void k_near_finish(int64_t nn, const int64_t *__restrict__ idx, const double *__restrict__ d,
+                              const double *__restrict__ sp, const double *__restrict__ gstar,
+                              const double *__restrict__ chk_val, const double *__restrict__ coarse,
+                              const double *__restrict__ base_vals, double inv_a2, double *__restrict__ out) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= nn) return;
-    const int c = cur[i];
-    const int64_t b0 = off[c], N = off[c + 1] - b0;
-    double v[1], d1[1], d2[1];
-    series_eval<1>(gcoef + b0 * 2, 2, N, th[i], v, d1, d2);
     double vals[kNearK + 1];
-    vals[0] = v[0];
+    vals[0] = gstar[i];
     for (int k = 1; k <= kNearK; ++k) vals[k] = chk_val[i * kNearK + k - 1] * inv_a2;
     const double t = d[i] / sp[i];
     double uh = 0.0;
@@ -285,6 +422,41 @@ __global__ void k_near_finish(int64_t nn, const int64_t *__restrict__ idx, const
     const int64_t p = idx[i];
     const double basev = base_vals ? base_vals[p] : out[p] - coarse[i] * inv_a2;
     out[p] = basev + uh;
+}
+
+using FftCoefKernel = void (*)(const int32_t *, const int64_t *, const double *, const double *, double *, double *);
+using FftFineKernel = void (*)(const int32_t *, const int64_t *, const double *, const double *, const double *,
+                               double *);
+constexpr int kFftMinLog = 4, kFftMaxLog = 13;
+
+FftCoefKernel fft_coef_kernel(int logn) {
+    switch (logn) {
+        case 4: return k_fft_coef<4>;
+        case 5: return k_fft_coef<5>;
+        case 6: return k_fft_coef<6>;
+        case 7: return k_fft_coef<7>;
+        case 8: return k_fft_coef<8>;
+        case 9: return k_fft_coef<9>;
+        case 10: return k_fft_coef<10>;
+        case 11: return k_fft_coef<11>;
+        case 12: return k_fft_coef<12>;
+        default: return k_fft_coef<13>;
+    }
+}
+
+FftFineKernel fft_fine_kernel(int logn) {
+    switch (logn) {
+        case 4: return k_fft_fine<4>;
+        case 5: return k_fft_fine<5>;
+        case 6: return k_fft_fine<6>;
+        case 7: return k_fft_fine<7>;
+        case 8: return k_fft_fine<8>;
+        case 9: return k_fft_fine<9>;
+        case 10: return k_fft_fine<10>;
+        case 11: return k_fft_fine<11>;
+        case 12: return k_fft_fine<12>;
+        default: return k_fft_fine<13>;
+    }
 }
 
 double ms_since(std::chrono::steady_clock::time_point t0) {
@@ -318,7 +490,7 @@ NearPlan &near_prepare(Context &ctx, BoundaryData &bd, int64_t n_tgt, const doub
     double *geo = np->geo.ensure((size_t)nb * 4);
     for (int comp = 0; comp < 2; ++comp) {
         hipLaunchKernelGGL(k_curve_dft, dim3(nblk(nb, 128)), dim3(128), 0, ctx.stream, nb, nc, doff, bd.xy, 2,
-                           comp, geo, 4, comp);
+                           comp, geo, 4, comp, (const int8_t *)nullptr);
         check_launch(ctx, "k_curve_dft");
     }
     DevBuf<double> ddot;
@@ -488,6 +660,32 @@ NearPlan &near_prepare(Context &ctx, BoundaryData &bd, int64_t n_tgt, const doub
                            np->fnrm.ensure((size_t)np->n_fine * 2), np->fw.ensure(np->n_fine));
         check_launch(ctx, "k_fine_geometry");
     }
+    // curves for the LDS FFTs, by size
+    {
+        std::vector<int8_t> flag(nc, 0);
+        std::vector<std::vector<int32_t>> by(kFftMaxLog + 1);
+        for (int c = 0; c < nc; ++c) {
+            const int64_t N = np->off[c + 1] - np->off[c];
+            int lg = 0;
+            while (((int64_t)1 << lg) < N) ++lg;
+            if (((int64_t)1 << lg) == N && lg >= kFftMinLog && lg <= kFftMaxLog) {
+                by[lg].push_back(c);
+                flag[c] = 1;
+            } else {
+                np->any_direct = true;
+            }
+        }
+        for (int lg = kFftMinLog; lg <= kFftMaxLog; ++lg) {
+            if (by[lg].empty()) continue;
+            auto gr = std::make_unique<NearPlan::FftGroup>();
+            gr->logn = lg;
+            gr->count = (int)by[lg].size();
+            YK_HIP(hipMemcpyAsync(gr->ids.ensure(gr->count), by[lg].data(), gr->count * sizeof(int32_t),
+                                  hipMemcpyHostToDevice, ctx.stream));
+            np->fft.push_back(std::move(gr));
+        }
+        YK_HIP(hipMemcpyAsync(np->fft_curve.ensure(nc), flag.data(), nc, hipMemcpyHostToDevice, ctx.stream));
+    }
     YK_HIP(hipStreamSynchronize(ctx.stream));
     np->setup_ms = ms_since(t0);
     ctx.near = std::move(np);
@@ -500,16 +698,34 @@ void near_apply(Context &ctx, NearPlan &np, BoundaryData &bd, double alpha, cons
     if (nn == 0) return;
     const int nc = np.n_curves;
     double *sc = np.scoef.ensure((size_t)nb * 2), *gc = np.gcoef.ensure((size_t)nb * 2);
-    hipLaunchKernelGGL(k_curve_dft, dim3(nblk(nb, 128)), dim3(128), 0, ctx.stream, nb, nc, np.doff.p, sigma, 1, 0,
-                       sc, 2, 0);
-    check_launch(ctx, "k_curve_dft");
-    hipLaunchKernelGGL(k_curve_dft, dim3(nblk(nb, 128)), dim3(128), 0, ctx.stream, nb, nc, np.doff.p, g, 1, 0, gc,
-                       2, 0);
-    check_launch(ctx, "k_curve_dft");
     double *fdn = np.fdn.ensure((size_t)np.n_fine * 2);
-    hipLaunchKernelGGL(k_fine_dipoles, dim3(nblk(np.n_fine, 128)), dim3(128), 0, ctx.stream, np.n_fine, nc,
-                       np.doff.p, sc, np.fnrm.p, np.fw.p, fdn);
-    check_launch(ctx, "k_fine_dipoles");
+    // Fourier coefficients of sigma and g, and sigma's finer-rule dipoles:
+    // LDS FFTs for power-of-two curves, direct sums for the others
+    for (const auto &gp : np.fft) {
+        const NearPlan::FftGroup &gr = *gp;
+        hipLaunchKernelGGL(fft_coef_kernel(gr.logn), dim3(gr.count, 2), dim3(256), 0, ctx.stream, gr.ids.p,
+                           np.doff.p, sigma, g, sc, gc);
+        check_launch(ctx, "k_fft_coef");
+        hipLaunchKernelGGL(fft_fine_kernel(gr.logn), dim3(gr.count * kNearM), dim3(256), 0, ctx.stream, gr.ids.p,
+                           np.doff.p, sc, np.fnrm.p, np.fw.p, fdn);
+        check_launch(ctx, "k_fft_fine");
+    }
+    if (np.any_direct) {
+        const int8_t *skip = np.fft_curve.p;
+        hipLaunchKernelGGL(k_curve_dft, dim3(nblk(nb, 128)), dim3(128), 0, ctx.stream, nb, nc, np.doff.p, sigma, 1,
+                           0, sc, 2, 0, skip);
+        check_launch(ctx, "k_curve_dft");
+        hipLaunchKernelGGL(k_curve_dft, dim3(nblk(nb, 128)), dim3(128), 0, ctx.stream, nb, nc, np.doff.p, g, 1, 0,
+                           gc, 2, 0, skip);
+        check_launch(ctx, "k_curve_dft");
+        hipLaunchKernelGGL(k_fine_dipoles, dim3(nblk(np.n_fine, 128)), dim3(128), 0, ctx.stream, np.n_fine, nc,
+                           np.doff.p, sc, np.fnrm.p, np.fw.p, fdn, skip);
+        check_launch(ctx, "k_fine_dipoles");
+    }
+    double *gs = np.gstar.ensure(nn);
+    hipLaunchKernelGGL(k_near_g, dim3(nblk(nn * 64, 256)), dim3(256), 0, ctx.stream, nn, np.cur.p, np.th.p,
+                       np.doff.p, gc, gs);
+    check_launch(ctx, "k_near_g");
     // U^h (without 1/alpha^2) at the check points from the finer rule
     double *cv = np.chk_val.ensure((size_t)nn * kNearK);
     {
@@ -539,8 +755,8 @@ void near_apply(Context &ctx, NearPlan &np, BoundaryData &bd, double alpha, cons
         double *outs[3] = {nullptr, nullptr, coarse};
         evaluate_sums(ctx, SLOT_NEARC, pb, nullptr, dn, outs, SUM_FP64);
     }
-    hipLaunchKernelGGL(k_near_finish, dim3(nblk(nn, 128)), dim3(128), 0, ctx.stream, nn, np.idx.p, np.cur.p,
-                       np.th.p, np.d.p, np.sp.p, np.doff.p, gc, cv, coarse, base, 1.0 / (alpha * alpha), out);
+    hipLaunchKernelGGL(k_near_finish, dim3(nblk(nn, 128)), dim3(128), 0, ctx.stream, nn, np.idx.p, np.d.p,
+                       np.sp.p, gs, cv, coarse, base, 1.0 / (alpha * alpha), out);
     check_launch(ctx, "k_near_finish");
 }
 

@@ -56,20 +56,21 @@ def test_rhs_imex_matches_oracle(yk, scheme, reaction):
     assert np.max(np.abs(host(B) - ref)) <= 4e-16 * np.max(np.abs(ref))
 
 
-def _grid_case():
-    b = W.make_boundary([W.circle((0.0, 0.0), 0.4, 256), W.circle((0.0, 0.0), 0.1, 128, ccw=False)])
+def _grid_case(n0=256, n1=128):
+    b = W.make_boundary([W.circle((0.0, 0.0), 0.4, n0), W.circle((0.0, 0.0), 0.1, n1, ccw=False)])
     grid, pts = W.grid_box(-0.5, 0.5, 48)
     uf = lambda p: np.sin(3 * p[:, 0]) * np.sin(2 * p[:, 1]) + 1.0
     return b, grid, pts, uf
 
 
-@pytest.mark.parametrize("direct", [1, 0])
-def test_grid_step_matches_oracle(yk, direct):
+@pytest.mark.parametrize("direct,nodes", [(1, (256, 128)), (0, (256, 128)), (0, (250, 130))])
+def test_grid_step_matches_oracle(yk, direct, nodes):
     """One grid step (U^p on the grid, bicubic U^p on the nodes, the density,
-    U^h with the near-boundary rule) element by element against the oracle."""
+    U^h with the near-boundary rule) element by element against the oracle;
+    power-of-two curves take the LDS FFTs, the others the direct sums."""
     import torch
     from oracle import grid as G
-    b, grid, pts, uf = _grid_case()
+    b, grid, pts, uf = _grid_case(*nodes)
     a2 = 2.5e-3
     B = (1 + 13 * a2) * uf(pts) - 13 * a2
     f = uf(b.xy)
