@@ -963,6 +963,147 @@ __global__ __launch_bounds__(256) void k_tile_gemm(const int4 *__restrict__ tile
     }
 }
 
+// Persistent M2L for 64 padded coefficients without the split (p = 31), FP64,
+// on trees with at least as many tiles as the launch has workgroups.  The
+// launch is one resident round (three workgroups per compute unit: the slot's
+// operator is staged in LDS in two halves of 32 contraction columns, double
+// buffered at half-slot steps, 32 KB); workgroup b takes the contiguous run
+// [U b / G, U (b + 1) / G) of the U = 54 ntiles (tile, slot, half) units in
+// the tiles' order and keeps the tile's results in its accumulators across
+// the slots, so no compute unit idles while another finishes a last round of
+// whole tiles.  A run is at least 54 units long, so a tile is shared by at
+// most two workgroups; those add into the local expansions, which are zero
+// before M2L, with atomic adds, and with two addends into zero the sum does
+// not depend on their order.  A tile that lies within one run is added
+// without atomics.  The matrix-core steps and fragment layout are those of
+// k_tile_gemm.
+__global__ __launch_bounds__(256) void k_m2l_persist(const int4 *__restrict__ tiles, int ntiles,
+                                                     const int32_t *__restrict__ boxes,
+                                                     const int32_t *__restrict__ src,
+                                                     const int32_t *__restrict__ slot_op,
+                                                     const double *__restrict__ Op, int64_t op_stride,
+                                                     const double *__restrict__ X, double *__restrict__ out) {
+    constexpr int PP = 64, NB = 4, LDA = 64, NCOLH = 32, NSH = 8, kSlots = 27, NH = 2;
+    constexpr int kPairs = NCOLH * LDA / 2;   // operator pairs per half
+    constexpr int NL2 = kPairs / 256;         // pairs per thread
+    __shared__ double As[2][NCOLH * LDA];
+    using MF = Mfma<double>;
+    const int G = gridDim.x;
+    const int bid = xcd_remap(blockIdx.x, G);
+    const int64_t U = (int64_t)ntiles * kSlots * NH;
+    const int64_t u0 = U * bid / G, u1 = U * (bid + 1) / G;
+    if (u0 >= u1) return;
+    const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, g = lane >> 4;
+    const int jb = 16 * w + (lane & 15);
+    // current tile
+    int4 tl = tiles[(int)(u0 / (kSlots * NH))];
+    bool colvalid = jb < tl.w;
+    int64_t boxj = colvalid ? boxes[tl.z + jb] : -1;
+    yk_d4 acc[NB];
+#pragma unroll
+    for (int r = 0; r < NB; ++r) acc[r] = yk_d4{0, 0, 0, 0};
+    yk_dpair braw[8];
+    bool bvalid = false;
+    double bcur[16];
+    yk_dpair pre[NL2];
+    auto load_b = [&](const int4 &t, int sl) {
+        int32_t sj = -1;
+        if (jb < t.w) sj = src[(int64_t)boxes[t.z + jb] * kSlots + sl];
+        const yk_dpair *row2 = reinterpret_cast<const yk_dpair *>(X + (int64_t)(sj >= 0 ? sj : 0) * PP) + g;
+#pragma unroll
+        for (int kp = 0; kp < 8; ++kp) braw[kp] = row2[4 * kp];
+        bvalid = sj >= 0;
+    };
+    auto take_b = [&]() {
+#pragma unroll
+        for (int kp = 0; kp < 8; ++kp) {
+            bcur[2 * kp] = bvalid ? braw[kp].x : 0.0;
+            bcur[2 * kp + 1] = bvalid ? braw[kp].y : 0.0;
+        }
+    };
+    auto op_half = [&](const int4 &t, int sl, int h) -> const yk_dpair * {
+        return reinterpret_cast<const yk_dpair *>(Op + (int64_t)t.x * op_stride +
+                                                  (size_t)slot_op[t.y * kSlots + sl] * PP * PP) +
+               (size_t)h * NCOLH * (PP / 2);
+    };
+    {
+        const int sl = (int)((u0 / NH) % kSlots), h = (int)(u0 % NH);
+        load_b(tl, sl);
+        const yk_dpair *Tg = op_half(tl, sl, h);
+        yk_dpair *Ad = reinterpret_cast<yk_dpair *>(As[0]);
+#pragma unroll
+        for (int e = 0; e < NL2; ++e) Ad[tid + 256 * e] = Tg[tid + 256 * e];
+        take_b();
+    }
+    __syncthreads();
+    int64_t tile_first = (u0 / (kSlots * NH)) * (kSlots * NH);
+    for (int64_t u = u0; u < u1; ++u) {
+        const int cur = (int)((u - u0) & 1);
+        const int h = (int)(u % NH), sl = (int)((u / NH) % kSlots);
+        const bool more = u + 1 < u1;
+        const int64_t un = u + 1;
+        const int hn = (int)(un % NH), sln = (int)((un / NH) % kSlots);
+        const bool new_tile = more && sln == 0 && hn == 0;
+        int4 tn = tl;
+        if (more) {
+            if (new_tile) tn = tiles[(int)(un / (kSlots * NH))];
+            if (hn == 0) load_b(tn, sln);
+            const yk_dpair *Tg = op_half(tn, sln, hn);
+#pragma unroll
+            for (int e = 0; e < NL2; ++e) pre[e] = Tg[tid + 256 * e];
+        }
+        // this half's B values (a select: bcur is never indexed at run time)
+        double bp[NSH];
+#pragma unroll
+        for (int st = 0; st < NSH; ++st) bp[st] = h ? bcur[NSH + st] : bcur[st];
+        const double *Ac = As[cur] + 2 * g * LDA + (lane & 15);
+        double afr[3][NB];
+        auto read_a = [&](int st, double *dst) {
+#pragma unroll
+            for (int rt = 0; rt < NB; ++rt) dst[rt] = Ac[(8 * (st >> 1) + (st & 1)) * LDA + 16 * rt];
+        };
+        read_a(0, afr[0]);
+        read_a(1, afr[1]);
+#pragma unroll
+        for (int st = 0; st < NSH; ++st) {
+            if (st + 2 < NSH) read_a(st + 2, afr[(st + 2) % 3]);
+#pragma unroll
+            for (int rt = 0; rt < NB; ++rt) acc[rt] = MF::step(afr[st % 3][rt], bp[st], acc[rt]);
+        }
+        // the tile's last unit, or the run's: add the results (a run may end,
+        // or start, between the two halves of a slot)
+        if ((h == NH - 1 && sl == kSlots - 1) || !more) {
+            const bool whole = tile_first >= u0 && tile_first + kSlots * NH <= u1;
+            if (colvalid) {
+                double *o = out + boxj * PP;
+#pragma unroll
+                for (int rt = 0; rt < NB; ++rt)
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const int i = 16 * rt + MF::row(lane, q);
+                        if (whole) o[i] += acc[rt][q];
+                        else atomicAdd(o + i, acc[rt][q]);
+                    }
+            }
+#pragma unroll
+            for (int r = 0; r < NB; ++r) acc[r] = yk_d4{0, 0, 0, 0};
+        }
+        if (more) {
+            yk_dpair *Ad = reinterpret_cast<yk_dpair *>(As[cur ^ 1]);
+#pragma unroll
+            for (int e = 0; e < NL2; ++e) Ad[tid + 256 * e] = pre[e];
+            if (hn == 0) take_b();
+            if (new_tile) {
+                tl = tn;
+                tile_first = un;
+                colvalid = jb < tl.w;
+                boxj = colvalid ? boxes[tl.z + jb] : -1;
+            }
+        }
+        __syncthreads();
+    }
+}
+
 // Fixed-order sums of the slab rows of k_tile_gemm into the outputs.
 // Sparse M2L: target box t of the list gets rows[off[t] .. off[t+1]) (its
 // translations in increasing index), one wavefront per target.
@@ -2047,6 +2188,17 @@ LeafKernel pick_leaf_kernel(int nt, bool small_only, bool f32) {
 
 }  // namespace
 
+// one resident round of the persistent M2L: three workgroups per compute unit
+int m2l_persist_grid(Context &ctx) {
+    static int cus = 0;
+    if (cus == 0) {
+        int n = 0;
+        YK_HIP(hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, ctx.device));
+        cus = n > 0 ? n : 256;
+    }
+    return 3 * cus;
+}
+
 void fmm_run(Context &ctx, FmmPlan &pl, const double *q, const double *dn, double *const out[3],
              SumPrec prec, const BieFuse *bie, int keep_charge_m, int parts) {
     int mask = 0;
@@ -2368,7 +2520,12 @@ void fmm_run(Context &ctx, FmmPlan &pl, const double *q, const double *dn, doubl
                                                       as.m2l_boxes.p, kNumV, pl.vlist.p, pl.slot_oid.p,
                                                       pl.m2lf.p, (int64_t)kNumOff * Pp * Pp, 0, pl.Mf.p, 0,
                                                       pl.Lc.p, nullptr, &slab);
-                else
+                else if (Pp == 64 && P == 63 && as.n_tiles >= m2l_persist_grid(ctx)) {
+                    hipLaunchKernelGGL(k_m2l_persist, dim3(m2l_persist_grid(ctx)), dim3(256), 0, ctx.stream,
+                                       as.m2l_tiles.p, as.n_tiles, as.m2l_boxes.p, pl.vlist.p, pl.slot_oid.p,
+                                       pl.m2l.p, (int64_t)kNumOff * Pp * Pp, pl.M.p, pl.Lc.p);
+                    check_launch(ctx, "k_m2l_persist");
+                } else
                     launch_tile_gemm<double, double, 1>(ctx, P, Pp, as.n_tiles, as.m2l_tiles.p, 0,
                                                         as.m2l_boxes.p, kNumV, pl.vlist.p, pl.slot_oid.p, pl.m2l.p,
                                                         (int64_t)kNumOff * Pp * Pp, 0, pl.M.p, 0, pl.Lc.p, nullptr,
