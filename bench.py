@@ -95,9 +95,11 @@ def rooflines(info, st, steps, fp32):
         t = m2l_ms / m2l_calls
         peak = PEAK_FP32_MFMA_TF if fp32 else PEAK_FP64_MFMA_TF
         ach = m2l_flops(info) / (t * 1e-3) / 1e12
-        out["m2l"] = {"kernel": "k_tile_gemm (M2L, all levels)", "bound": "mfma", "achieved": ach,
+        out["m2l"] = {"kernel": ("k_tile_gemm (M2L, all levels, FP32)" if fp32 else
+                                 "k_m2l_persist (M2L, all levels, one resident round)"),
+                      "bound": "mfma", "achieved": ach,
                       "peak": peak, "unit": "TFLOP/s", "frac": ach / peak,
-                      "traffic": None if fp32 else measured_traffic("k_tile_gemm_m2l"), "avg_launch_ms": t,
+                      "traffic": None if fp32 else measured_traffic("k_m2l_persist"), "avg_launch_ms": t,
                       "launches_per_pass": m2l_calls / steps, "algorithmic_flops": m2l_flops(info)}
     # the upward and downward chain: 10 P flops per point for P2M and L2P
     # (the expansion's P terms, about ten operations each), 2 P^2 per
