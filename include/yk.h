@@ -89,7 +89,20 @@ typedef struct {
     int near_cache_mb;      /* device memory (MiB) a tree may spend on its cached
                                near-field interaction values; 0 = evaluate the
                                near-field kernels on every call */
+    int tree;               /* YK_TREE_*: the quad-tree of Sec. 3.1.  UNIFORM: every
+                               leaf at one level (the smallest level whose
+                               point-weighted occupancy is <= leaf_size), U and
+                               V lists.  ADAPTIVE: boxes split while they hold
+                               more than leaf_size points, then 2:1 balanced
+                               (touching leaves differ by at most one level);
+                               U, V, W (multipoles of finer boxes evaluated at a
+                               leaf's points) and X (a coarser leaf's sources
+                               into a box's local expansion) lists; the near
+                               field is evaluated on the fly (near_cache_mb
+                               unused) */
 } yk_options;
+
+enum { YK_TREE_UNIFORM = 0, YK_TREE_ADAPTIVE = 1 };
 
 typedef struct {
     int32_t n_curves;             /* >= 1; curve 0 outer, 1.. holes */
@@ -443,6 +456,10 @@ typedef struct {
     double tables_ms;         /* host time spent on the translation operator tables
                                  (each order tried by the order check) */
     double order_check_ms;    /* time of the build-time order check (within build_ms) */
+    int32_t tree;             /* YK_TREE_* of the cached tree */
+    int32_t max_u;            /* adaptive tree: the longest U list (at most 13) */
+    int64_t n_wlist;          /* adaptive tree: W-list entries (= X-list entries) */
+    int64_t n_xboxes;         /* adaptive tree: boxes with a non-empty X list */
 } yk_plan_info;
 
 enum {
@@ -477,6 +494,25 @@ yk_status yk_plan_info_get(yk_ctx ctx, int slot, yk_plan_info *info);
 yk_status yk_plan_tree_export(yk_ctx ctx, int slot, double *square, int64_t *level_begin, uint32_t *keys,
                               int32_t *perm, uint32_t *box_code, int32_t *parent, int32_t *leaf_range,
                               int32_t *ulist_off, int32_t *ulist, int32_t *vlist);
+/*
+ * The adaptive parts of the tree cached in `slot` (options.tree ==
+ * YK_TREE_ADAPTIVE; YK_ERR_ARG otherwise).  Leaves lie at any level and are
+ * numbered in Morton order of their first level-15 cell; leaf_range, ulist_off
+ * and ulist of yk_plan_tree_export then use that numbering, and the U lists
+ * hold the touching leaves (the leaf itself included) in increasing index.
+ * Every pointer may be NULL (skipped):
+ *   leaf_box     DEVICE [n_leaves] box index of each leaf
+ *   box_level    DEVICE [n_boxes] level of each box
+ *   wlist_off    DEVICE [n_leaves + 1], wlist DEVICE [n_wlist]: per leaf, the
+ *                boxes of levels >= lmin, finer than the leaf, whose parent
+ *                touches it and which do not (increasing box index)
+ *   xbox         DEVICE [n_xboxes] the boxes with a non-empty X list
+ *   xlist_off    DEVICE [n_xboxes + 1], xlist DEVICE [n_wlist]: per such box,
+ *                the leaves whose W list holds it (increasing leaf index)
+ */
+yk_status yk_plan_adaptive_export(yk_ctx ctx, int slot, int32_t *leaf_box, int32_t *box_level,
+                                  int32_t *wlist_off, int32_t *wlist, int32_t *xbox, int32_t *xlist_off,
+                                  int32_t *xlist);
 yk_status yk_timing_enable(yk_ctx ctx, int enable);
 yk_status yk_timing_read(yk_ctx ctx, double ms[YK_NUM_STAGES], int64_t calls[YK_NUM_STAGES],
                          int reset);

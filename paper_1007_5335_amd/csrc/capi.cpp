@@ -414,12 +414,13 @@ void yk_default_options(yk_options *opt) {
     opt->gmres_m = 60;
     opt->debug_flags = 0;
     opt->near_cache_mb = 16384;
+    opt->tree = YK_TREE_UNIFORM;
 }
 
 static bool valid_options(const yk_options *o) {
     return o->precision >= 0 && o->precision <= 2 && o->p >= 0 && o->p <= 31 &&
            o->leaf_size >= 1 && o->leaf_size <= 4096 && o->gmres_m >= 1 && o->gmres_m <= 120 &&
-           o->near_cache_mb >= 0 &&
+           o->near_cache_mb >= 0 && (o->tree == YK_TREE_UNIFORM || o->tree == YK_TREE_ADAPTIVE) &&
            (o->p > 0 || (o->fmm_tol > 0 && o->fmm_tol < 1));
 }
 
@@ -485,7 +486,8 @@ yk_status yk_set_options(yk_ctx ctx, const yk_options *opt) {
     const yk_options old = ctx->c.opt;
     ctx->c.opt = *opt;
     ctx->c.memo_valid = false;
-    if (old.p != opt->p || old.leaf_size != opt->leaf_size || old.fmm_tol != opt->fmm_tol) {
+    if (old.p != opt->p || old.leaf_size != opt->leaf_size || old.fmm_tol != opt->fmm_tol ||
+        old.tree != opt->tree) {
         ctx->c.plan_vol.reset();
         ctx->c.plan_bnd.reset();
         ctx->c.plan_misc.reset();
@@ -1204,6 +1206,10 @@ yk_status yk_plan_info_get(yk_ctx ctx, int slot, yk_plan_info *info) {
         info->order_check_ms = pl->check_ms;
         info->p_initial = pl->calib_p0;
         info->order_check_err = pl->calib_err;
+        info->tree = pl->adaptive ? YK_TREE_ADAPTIVE : YK_TREE_UNIFORM;
+        info->max_u = pl->max_u;
+        info->n_wlist = pl->n_wl;
+        info->n_xboxes = pl->n_xbox;
         if (pl->lmin <= pl->L) {
             for (int l = pl->lmin + 1; l <= pl->L; ++l) info->m2m_children += pl->lev[l].end - pl->lev[l].begin;
         }
@@ -1257,6 +1263,29 @@ yk_status yk_plan_tree_export(yk_ctx ctx, int slot, double *square, int64_t *lev
         copy(ulist_off, pl->ulist_off.p, (size_t)(pl->nleaf + 1) * sizeof(int32_t));
         copy(ulist, pl->ulist.p, (size_t)pl->n_ulist * sizeof(int32_t));
         copy(vlist, pl->vlist.p, (size_t)pl->nbox * kNumV * sizeof(int32_t));
+        YK_HIP(hipStreamSynchronize(c.stream));
+        return YK_OK;
+    });
+}
+
+yk_status yk_plan_adaptive_export(yk_ctx ctx, int slot, int32_t *leaf_box, int32_t *box_level,
+                                  int32_t *wlist_off, int32_t *wlist, int32_t *xbox, int32_t *xlist_off,
+                                  int32_t *xlist) {
+    return guarded(ctx, [&](Context &c) {
+        YK_REQUIRE(slot >= 0 && slot <= 4, "slot must be 0 .. 4");
+        const FmmPlan *pl = plan_in_slot(c, slot);
+        YK_REQUIRE(pl != nullptr, "no tree is cached in this slot");
+        YK_REQUIRE(pl->adaptive, "the tree in this slot is not adaptive");
+        auto copy = [&](void *dst, const void *src, size_t bytes) {
+            if (dst && bytes) YK_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, c.stream));
+        };
+        copy(leaf_box, pl->leaf_box.p, (size_t)pl->nleaf * sizeof(int32_t));
+        copy(box_level, pl->blevel.p, (size_t)pl->nbox * sizeof(int32_t));
+        copy(wlist_off, pl->woff.p, (size_t)(pl->nleaf + 1) * sizeof(int32_t));
+        copy(wlist, pl->wl.p, (size_t)pl->n_wl * sizeof(int32_t));
+        copy(xbox, pl->xbox.p, (size_t)pl->n_xbox * sizeof(int32_t));
+        copy(xlist_off, pl->xoff.p, (size_t)(pl->n_xbox + 1) * sizeof(int32_t));
+        copy(xlist, pl->xl.p, (size_t)pl->n_xl * sizeof(int32_t));
         YK_HIP(hipStreamSynchronize(c.stream));
         return YK_OK;
     });

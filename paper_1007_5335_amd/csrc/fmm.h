@@ -180,6 +180,31 @@ struct FmmPlan {
             if (toff[s + 1] > toff[s]) m |= 1 << s;
         return m;
     }
+    // ---- adaptive tree (leaves at any level; U, V, W and X lists) ----
+    // Leaf li is box leaf_box[li] (uniform tree: box lev[L].begin + li); the
+    // leaf-indexed arrays above (lrange, pleaf, ulist) follow that numbering.
+    bool adaptive = false;
+    int opt_tree = 0;
+    std::vector<int32_t> h_leaf_box, h_box_leaf;   // leaf -> box, box -> leaf (-1: split box)
+    std::vector<int32_t> h_blevel;                 // level of every box
+    DevBuf<int32_t> leaf_box, box_leaf, blevel, leaf_lev;
+    DevBuf<uint32_t> leaf_start;                   // first level-15 cell of each leaf (sorted)
+    DevBuf<int32_t> alr;                           // [nbox][6] leaf ranges by box (split boxes: empty)
+    DevBuf<int32_t> p2m_list;                      // per level >= lmin: level-local indices of its leaves
+    std::vector<int64_t> p2m_off;                  // [L + 2] slices of p2m_list by level
+    std::vector<int64_t> up_off, up_n;             // per level: the split boxes' slice of up_boxes (M2M)
+    DevBuf<int32_t> woff, wl, wleaves;             // W lists (CSR over leaves), leaves with a W list
+    int64_t n_wl = 0, n_wleaves = 0;
+    DevBuf<int32_t> xbox, xoff, xl;                // X lists: boxes with one, CSR of source leaves
+    int64_t n_xbox = 0, n_xl = 0;
+    int max_u = 0;                                 // longest U list
+    // per-level tables for expansions at any level >= lmin
+    int nser_stride = 0;                           // serc_lv: [level][2][nser_stride]
+    std::vector<int> nser_lv;
+    DevBuf<double> serc_lv, rI, invR_lv;           // rI: [level][p+3] = {I_0(R_l), I_n/I_{n-1} (n = 1..p+2)}
+    DevBuf<int32_t> nser_dev;
+    double near_tmax = 0;                          // largest t = r^2/(4 alpha^2) of a U-list pair
+
     bool fresh = false;
     uint64_t gen = 0;                  // unique per plan built in this process
     int last_mask = 0;
@@ -192,11 +217,17 @@ void build_tree(Context &ctx, FmmPlan &pl, const SumProblem &pb);
 // fmm_plan.cpp: boxes and lists from the sorted keys, then the translation
 // operators and expansion tables of order p (rebuilt when p changes)
 void build_lists(Context &ctx, FmmPlan &pl, const std::vector<uint32_t> &keys, const uint32_t *dkeys);
+// the adaptive tree (opt_tree 1): boxes split while they hold more than
+// leaf_size points, then 2:1 balanced; U, V, W and X lists
+void build_lists_adaptive(Context &ctx, FmmPlan &pl, const std::vector<uint32_t> &keys, const uint32_t *dkeys);
 // lists.hip: the GPU parts of build_lists and get_active
 void gpu_point_leaves(Context &ctx, FmmPlan &pl, const uint32_t *dkeys, const uint32_t *dleaf_codes);
 void gpu_ulists(Context &ctx, FmmPlan &pl, const uint32_t *dleaf_codes);
 void gpu_vlists(Context &ctx, FmmPlan &pl);
 int64_t gpu_count_slots(Context &ctx, FmmPlan &pl, const int32_t *dboxes, int64_t n);
+void gpu_point_leaves_adaptive(Context &ctx, FmmPlan &pl, const uint32_t *dkeys);
+void gpu_ulists_adaptive(Context &ctx, FmmPlan &pl);
+void gpu_wlists(Context &ctx, FmmPlan &pl, std::vector<int32_t> &woff, std::vector<int32_t> &wl);
 void build_tables(Context &ctx, FmmPlan &pl, int p);
 ActiveSet &get_active(Context &ctx, FmmPlan &pl, int mask);
 void ensure_near_layout(Context &ctx, FmmPlan &pl, ActiveSet &as);

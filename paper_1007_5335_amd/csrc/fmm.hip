@@ -25,7 +25,7 @@ bool plan_matches(const FmmPlan &pl, const Context &ctx, const SumProblem &pb) {
     for (int s = 0; s < 3; ++s)
         if (pl.key_n[s] != pb.n[s] || pl.key_xy[s] != (pb.n[s] ? pb.xy[s] : nullptr)) return false;
     return pl.alpha == pb.alpha && pl.opt_p == ctx.opt.p && pl.opt_leaf == ctx.opt.leaf_size &&
-           pl.opt_tol == ctx.opt.fmm_tol;
+           pl.opt_tol == ctx.opt.fmm_tol && pl.opt_tree == ctx.opt.tree;
 }
 
 }  // namespace
@@ -48,6 +48,7 @@ FmmPlan &get_plan(Context &ctx, PlanSlot slot, const SumProblem &pb) {
     pl->opt_p = ctx.opt.p;
     pl->opt_leaf = ctx.opt.leaf_size;
     pl->opt_tol = ctx.opt.fmm_tol;
+    pl->opt_tree = ctx.opt.tree;
     const auto t0 = std::chrono::steady_clock::now();
     build_tree(ctx, *pl, pb);
     calibrate_order(ctx, *pl, pb);

@@ -1385,7 +1385,9 @@ struct Near {
 // the end.  The result is the near field alone (k_l2p adds the far field).
 constexpr int kLeafStage = 192;
 
-template <int NT, bool kSmallOnly, bool kF32 = false>
+// MU: the longest U list (9 in a uniform tree; 16 for the adaptive one, whose
+// 2:1 balance bounds it by 13)
+template <int NT, bool kSmallOnly, bool kF32 = false, int MU = 9>
 __global__ __launch_bounds__(64) void k_leaf(
     const int2 *__restrict__ items, int64_t leaf_base, const int32_t *__restrict__ lrange,
     const int32_t *__restrict__ uoff, const int32_t *__restrict__ ulist,
@@ -1394,7 +1396,7 @@ __global__ __launch_bounds__(64) void k_leaf(
     double dip_scale, double *__restrict__ outs) {
     __shared__ double s_x[kLeafStage], s_y[kLeafStage], s_a[kLeafStage], s_b[kLeafStage];
     __shared__ double2 s_log[YK_LOG_TAB];
-    __shared__ int qa[9], qn[9], da[9], dn_[9];
+    __shared__ int qa[MU], qn[MU], da[MU], dn_[MU];
     const int2 item = items[xcd_remap(blockIdx.x, gridDim.x)];
     const int li = item.x;
     const int lane = threadIdx.x;
@@ -1407,9 +1409,9 @@ __global__ __launch_bounds__(64) void k_leaf(
         ntot += re[s] - rs[s];
     }
     const int u0 = uoff[li], nu = uoff[li + 1] - u0;
-    // U-list source ranges (at most 9 neighbours) of the two source sets, in
+    // U-list source ranges (at most MU leaves) of the two source sets, in
     // LDS (indexed per lane below; a private array would live in scratch)
-    if (lane < 9) {
+    if (lane < MU) {
         const int u = lane;
         int a = 0, an = 0, b2 = 0, bn = 0;
         if (u < nu) {
@@ -1423,7 +1425,7 @@ __global__ __launch_bounds__(64) void k_leaf(
     }
     __syncthreads();
     int nq = 0, nd = 0;
-    for (int u = 0; u < 9; ++u) {
+    for (int u = 0; u < MU; ++u) {
         nq += qn[u];
         nd += dn_[u];
     }
@@ -1454,7 +1456,7 @@ __global__ __launch_bounds__(64) void k_leaf(
             for (int f = lane; f < cn; f += 64) {
                 int r = c0 + f, u = 0;
                 const int *cnt = set == 0 ? qn : dn_;
-                while (u < 8 && r >= cnt[u]) { r -= cnt[u]; ++u; }
+                while (u < MU - 1 && r >= cnt[u]) { r -= cnt[u]; ++u; }
                 const int j = (set == 0 ? qa[u] : da[u]) + r;
                 s_x[f] = px[j];
                 s_y[f] = py[j];
@@ -2174,7 +2176,230 @@ __global__ __launch_bounds__(256) void k_l2p(
         o[i] = v;
 }
 
-LeafKernel pick_leaf_kernel(int nt, bool small_only, bool f32) {
+// ------------------------------------------------------- adaptive tree ---
+// beyond this scaled distance K_0 < 1e-250: the pair is dropped (also keeps
+// K_0 and the ratio K_1/K_0 away from underflow)
+constexpr double kFarRho = 600.0;
+// The products I_n(R_l) K_n(rho) of the W and X translations, from I_0(R_l)
+// K_0(rho) by the ratios of I (a per-level table, rI[l] = {I_0(R_l),
+// I_n(R_l)/I_{n-1}(R_l)}) and of K (the upward recurrence K_{n+1} = K_{n-1} +
+// (2n/rho) K_n, stable for K, run on the ratios), so that no factor leaves
+// the range of doubles however small the box.
+
+// W list (M2P): the multipole of every box of the leaf's W list evaluated at
+// the leaf's targets, phi(x) = sum_n M_n F^K_n((x - c)/alpha) =
+// M_0 K_0 + 2 sum_{n>=1} Re(M_n e^{in theta}) K_n, added to the near-field
+// sums in outs.  One wavefront per leaf, a lane per target; each target sums
+// its boxes in list order (deterministic, no atomics).
+__global__ __launch_bounds__(64) void k_ad_m2p(
+    const int32_t *__restrict__ wleaves, const int32_t *__restrict__ woff, const int32_t *__restrict__ wl,
+    const int32_t *__restrict__ lrange, int mask, const int32_t *__restrict__ blevel,
+    const double *__restrict__ bcx, const double *__restrict__ bcy, const double *__restrict__ px,
+    const double *__restrict__ py, const double *__restrict__ M, const double *__restrict__ rI, int p, int Pp,
+    double inv_alpha, double *__restrict__ outs) {
+    const int li = wleaves[blockIdx.x];
+    const int w0 = woff[li], w1 = woff[li + 1];
+    int rs[3], rn[3], ntot = 0;
+    for (int st = 0; st < 3; ++st) {
+        rs[st] = lrange[li * 6 + 2 * st];
+        rn[st] = (mask >> st) & 1 ? lrange[li * 6 + 2 * st + 1] - rs[st] : 0;
+        ntot += rn[st];
+    }
+    for (int k = threadIdx.x; k < ntot; k += 64) {
+        int t = -1, r = k;
+        for (int st = 0; st < 3; ++st) {
+            if (t < 0 && r < rn[st]) t = rs[st] + r;
+            r -= rn[st];
+        }
+        const double x = px[t], y = py[t];
+        double acc = 0.0;
+        for (int w = w0; w < w1; ++w) {
+            const int32_t d = wl[w];
+            const double *Md = M + (int64_t)d * Pp;
+            const double *ri = rI + (int64_t)blevel[d] * (p + 3);
+            const double wx = (x - bcx[d]) * inv_alpha, wy = (y - bcy[d]) * inv_alpha;
+            const double rho = sqrt(wx * wx + wy * wy), ir = 1.0 / rho;
+            if (rho > kFarRho) continue;          // below 1e-250 of the box's sources
+            const double c = wx * ir, sn = wy * ir;
+            const double k0v = k0(rho);
+            double rk = k1(rho) / k0v;            // K_1 / K_0
+            double T = ri[0] * k0v;               // I_0(R) K_0(rho)
+            double sum = Md[0] * T;
+            double er = c, ei = sn;               // e^{i n theta}
+            for (int n = 1; n <= p; ++n) {
+                T *= ri[n] * rk;                  // I_n(R) K_n(rho)
+                sum += 2.0 * T * (Md[2 * n - 1] * er - Md[2 * n] * ei);
+                rk = 1.0 / rk + 2.0 * n * ir;     // K_{n+1} / K_n
+                const double nr = er * c - ei * sn;
+                ei = er * sn + ei * c;
+                er = nr;
+            }
+            acc += sum;
+        }
+        outs[t] += acc * kInv2Pi;
+    }
+}
+
+// X list (P2L): the sources of every leaf of the box's X list into the box's
+// local expansion (scaled, Lh_m = L_m I_m(R_l)).  By Graf's addition theorem a
+// charge q at w = (y - c)/alpha contributes L_m = q K_m(|w|) e^{-i m theta};
+// a dipole D = d (n_x + i n_y), the normal derivative at y of that,
+// L_m = -(1/(2 alpha)) [conj(D) K_{|m-1|} e^{-i(m-1) theta} + D K_{m+1}
+// e^{-i(m+1) theta}].  One wavefront per box: per batch of 64 sources each
+// lane writes its source's P terms to LDS, then lane o adds up output o over
+// the batch (a fixed order); the box's row is added once at the end.
+constexpr int kP2LStride = 65;   // LDS row stride (doubles): conflict-free transposed reads
+
+__global__ __launch_bounds__(64) void k_ad_p2l(
+    const int32_t *__restrict__ xbox, const int32_t *__restrict__ xoff, const int32_t *__restrict__ xl,
+    const int32_t *__restrict__ lrange, int has_q, int has_d, const int32_t *__restrict__ blevel,
+    const double *__restrict__ bcx, const double *__restrict__ bcy, const double *__restrict__ px,
+    const double *__restrict__ py, const double *__restrict__ qs, const double *__restrict__ dns, int64_t off1,
+    const double *__restrict__ rI, int p, int Pp, double inv_alpha, double *__restrict__ Lc) {
+    extern __shared__ double sh[];   // [Pp][kP2LStride]
+    const int lane = threadIdx.x;
+    const int32_t d = xbox[blockIdx.x];
+    const double *ri = rI + (int64_t)blevel[d] * (p + 3);
+    const double cx = bcx[d], cy = bcy[d], h = 0.5 * inv_alpha;
+    const int P = 2 * p + 1;
+    double acc = 0.0;
+    for (int xi = xoff[blockIdx.x]; xi < xoff[blockIdx.x + 1]; ++xi) {
+        const int32_t c = xl[xi];
+        for (int set = 0; set < 2; ++set) {
+            if ((set == 0 && !has_q) || (set == 1 && !has_d)) continue;
+            const int a = lrange[c * 6 + 2 * set], e = lrange[c * 6 + 2 * set + 1];
+            for (int base = a; base < e; base += 64) {
+                const int j = base + lane;
+                double *col = sh + lane;
+                const double wx = j < e ? (px[j] - cx) * inv_alpha : 0.0;
+                const double wy = j < e ? (py[j] - cy) * inv_alpha : 0.0;
+                const double rho = sqrt(wx * wx + wy * wy);
+                if (j < e && rho <= kFarRho) {
+                    const double ir = 1.0 / rho;
+                    const double co = wx * ir, sn = wy * ir;
+                    const double k0v = k0(rho);
+                    double rk = k1(rho) / k0v;
+                    double T = ri[0] * k0v;                    // T_0 = I_0 K_0
+                    if (set == 0) {
+                        const double q = qs[j];
+                        col[0] = q * T;
+                        double er = co, ei = sn;
+                        for (int m = 1; m <= p; ++m) {
+                            T *= ri[m] * rk;                   // T_m
+                            rk = 1.0 / rk + 2.0 * m * ir;
+                            col[(2 * m - 1) * kP2LStride] = q * T * er;
+                            col[(2 * m) * kP2LStride] = -q * T * ei;
+                            const double nr = er * co - ei * sn;
+                            ei = er * sn + ei * co;
+                            er = nr;
+                        }
+                    } else {
+                        const double Dx = dns[2 * (j - off1)], Dy = dns[2 * (j - off1) + 1];
+                        // T_m and T_{m+1} side by side: A_m = K_{|m-1|} I_m, B_m = K_{m+1} I_m
+                        double Tn = T * ri[1] * rk;            // T_1
+                        rk = 1.0 / rk + 2.0 * ir;              // K_2 / K_1
+                        double Tp = T;                         // T_{m-1} (unused at m = 0)
+                        // m = 0: A_0 = B_0 = K_1 I_0 = T_1 / (I_1/I_0)
+                        const double B0 = Tn / ri[1];
+                        col[0] = -2.0 * h * B0 * (Dx * co + Dy * sn);
+                        double ur = 1.0, ui = 0.0;             // e^{i(m-1) theta} at m = 1
+                        double vr = co * co - sn * sn, vi = 2.0 * co * sn;   // e^{i(m+1) theta} at m = 1
+                        double Tm = Tn;                        // T_m at m = 1
+                        for (int m = 1; m <= p; ++m) {
+                            Tn = Tm * ri[m + 1] * rk;          // T_{m+1}
+                            rk = 1.0 / rk + 2.0 * (m + 1) * ir;
+                            const double A = Tp * ri[m];       // K_{m-1} I_m
+                            const double B = Tn / ri[m + 1];   // K_{m+1} I_m
+                            const double re = -h * (A * (Dx * ur - Dy * ui) + B * (Dx * vr + Dy * vi));
+                            const double im = -h * (-A * (Dx * ui + Dy * ur) + B * (Dy * vr - Dx * vi));
+                            col[(2 * m - 1) * kP2LStride] = re;
+                            col[(2 * m) * kP2LStride] = im;
+                            Tp = Tm;
+                            Tm = Tn;
+                            double t2 = ur * co - ui * sn;
+                            ui = ur * sn + ui * co;
+                            ur = t2;
+                            t2 = vr * co - vi * sn;
+                            vi = vr * sn + vi * co;
+                            vr = t2;
+                        }
+                    }
+                } else {
+                    for (int o = 0; o < P; ++o) col[o * kP2LStride] = 0.0;
+                }
+                __syncthreads();
+                if (lane < P) {
+                    const double *row = sh + lane * kP2LStride;
+                    double s0 = 0.0, s1 = 0.0;
+                    for (int k = 0; k < 64; k += 2) {
+                        s0 += row[k];
+                        s1 += row[k + 1];
+                    }
+                    acc += s0 + s1;
+                }
+                __syncthreads();
+            }
+        }
+    }
+    if (lane < P) Lc[(int64_t)d * Pp + lane] += acc;
+}
+
+// L2P of the adaptive tree: as k_l2p, with the leaf's level (and its tables)
+// per point; leaves coarser than lmin have no local expansion.
+__global__ __launch_bounds__(256) void k_ad_l2p(
+    int64_t n, int64_t toff1, int64_t toff2, int mask, const int32_t *__restrict__ pleaf,
+    const int32_t *__restrict__ leaf_box, const int32_t *__restrict__ leaf_lev, int lmin,
+    const double *__restrict__ bcx, const double *__restrict__ bcy, const double *__restrict__ px,
+    const double *__restrict__ py, const double *__restrict__ Lc, double inv_alpha,
+    const double *__restrict__ invR_lv, const double *__restrict__ invFY, const double *__restrict__ cnn,
+    const double *__restrict__ serc_lv, const int32_t *__restrict__ nser_lv, int nser_stride, int p, int Pp,
+    const double *__restrict__ outs, const int32_t *__restrict__ perm, double *__restrict__ out0,
+    double *__restrict__ out1, double *__restrict__ out2, const double *__restrict__ bw,
+    const double *__restrict__ bk, const double *__restrict__ bx) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    const int set = (t >= toff1) + (t >= toff2);
+    if (!((mask >> set) & 1)) return;
+    const int32_t li = pleaf[t];
+    const int l = leaf_lev[li];
+    double v = outs[t];
+    if (l >= lmin) {
+        const int64_t b = leaf_box[li];
+        const double *Lb = Lc + b * Pp;
+        const double *ify = invFY + (int64_t)l * (p + 2);
+        const double invR = invR_lv[l];
+        const double wx = (px[t] - bcx[b]) * inv_alpha, wy = (py[t] - bcy[b]) * inv_alpha;
+        const double yv = 0.25 * (wx * wx + wy * wy);
+        const double zx = wx * invR, zy = wy * invR;
+        double F1, F2;
+        f_start(yv, serc_lv + (int64_t)l * 2 * nser_stride, nser_lv[l], F1, F2);
+        double sr = 0.0, si = 0.0;
+        for (int m = p; m >= 1; --m) {
+            const double F0 = F1 + yv * F2 * cnn[m];
+            const double gm = F0 * ify[m];
+            const double cr = Lb[2 * m - 1] * gm, ci = Lb[2 * m] * gm;
+            const double nr = sr * zx - si * zy + cr;
+            si = sr * zy + si * zx + ci;
+            sr = nr;
+            F2 = F1;
+            F1 = F0;
+        }
+        const double F0 = F1 + yv * F2 * cnn[0];
+        v += (Lb[0] * F0 * ify[0] + 2.0 * (sr * zx - si * zy)) * kInv2Pi;
+    }
+    double *o = set == 0 ? out0 : set == 1 ? out1 : out2;
+    const int32_t i = perm[t];
+    if (set == 1 && bx)   // double-layer operator: x - 2 (DL + corrected diagonal)
+        o[i] = bx[i] - 2.0 * (v + dl_diag_weight(bw[i], bk[i], inv_alpha * inv_alpha) * bx[i]);
+    else
+        o[i] = v;
+}
+
+LeafKernel pick_leaf_kernel(int nt, bool small_only, bool f32, bool adaptive) {
+    if (adaptive) {
+        if (f32) return small_only ? k_leaf<8, true, true, 16> : k_leaf<8, false, true, 16>;
+        return small_only ? k_leaf<14, true, false, 16> : k_leaf<14, false, false, 16>;
+    }
     if (f32) return small_only ? k_leaf<8, true, true> : k_leaf<8, false, true>;
     if (small_only) {
         if (nt <= 5) return k_leaf<5, true>;
@@ -2264,12 +2489,12 @@ void fmm_run(Context &ctx, FmmPlan &pl, const double *q, const double *dn, doubl
         }
         hipStream_t near_stream = overlap ? ctx.side : ctx.stream;
         if (as.n_leaves > 0) {
-            const double tmax = 2.0 * pl.lev[L].side * pl.lev[L].side * inv_alpha * inv_alpha;
-            const bool f32 = prec == SUM_FP32, small_only = tmax <= 1.0;
+            const bool f32 = prec == SUM_FP32, small_only = pl.near_tmax <= 1.0;
             const int q_on = n0 > 0 ? 1 : 0, d_on = n1 > 0 ? 1 : 0;
             // (the near field alone, without the far field's L2P, cannot use the
             // symmetric cache's incoming slots: it is evaluated on the fly)
-            const bool want_cache = ctx.opt.near_cache_mb > 0 && (parts & 2);
+            // (the adaptive tree's near field is evaluated on the fly)
+            const bool want_cache = ctx.opt.near_cache_mb > 0 && (parts & 2) && !pl.adaptive;
             if (want_cache) ensure_near_layout(ctx, pl, as);
             const int64_t entries = as.near_q_len + 2 * as.near_d_len;
             const int64_t bytes = entries * (f32 ? 4 : 8);
@@ -2363,7 +2588,7 @@ void fmm_run(Context &ctx, FmmPlan &pl, const double *q, const double *dn, doubl
                 }
                 check_launch(ctx, "k_near_apply");
             } else {
-                LeafKernel kern = pick_leaf_kernel(pl.near_terms, small_only, f32);
+                LeafKernel kern = pick_leaf_kernel(pl.near_terms, small_only, f32, pl.adaptive);
                 StageTimer tl(ctx, YK_STAGE_LEAF, near_stream);
                 hipLaunchKernelGGL(kern, dim3(as.n_items), dim3(64), 0, near_stream, as.leaf_items.p,
                                    leaf_base, pl.lrange.p, pl.ulist_off.p, pl.ulist.p, pl.px.p, pl.py.p, qs,
@@ -2375,14 +2600,37 @@ void fmm_run(Context &ctx, FmmPlan &pl, const double *q, const double *dn, doubl
     };
     const size_t lvl = (size_t)(p + 2);
     bool lc_clear = false;   // Lc already cleared (by the cached P2M kernel)
+    if (far && pl.adaptive) {
+        // P2M at the leaves of every level from lmin on (one launch per level,
+        // the level's tables; leaves coarser than lmin need no multipole)
+        StageTimer tm(ctx, YK_STAGE_P2M);
+        pl.mq_kept = false;
+        auto quad4 = p == 8 ? k_p2m_quad<8, 4> : p == 12 ? k_p2m_quad<12, 4> : p == 16 ? k_p2m_quad<16, 4>
+                   : p == 20 ? k_p2m_quad<20, 4> : p == 24 ? k_p2m_quad<24, 4> : p == 28 ? k_p2m_quad<28, 4>
+                   : p == 31 ? k_p2m_quad<31, 4> : nullptr;
+        YK_REQUIRE(quad4 != nullptr, "no P2M kernel for this order");
+        for (int l = pl.lmin; l <= L; ++l) {
+            const int64_t nl = pl.p2m_off[l + 1] - pl.p2m_off[l];
+            if (nl == 0) continue;
+            const int ns = pl.nser_lv[l];
+            const size_t tabs = (2 * (size_t)ns + 4 * (size_t)(p + 2)) * sizeof(double);
+            hipLaunchKernelGGL(quad4, dim3((unsigned)((nl + 15) / 16)), dim3(64), tabs, ctx.stream,
+                               pl.lev[l].begin, nl, pl.alr.p + pl.lev[l].begin * 6, pl.bcx.p, pl.bcy.p, pl.px.p,
+                               pl.py.p, qs, dns, pl.toff[1], has_q, has_d, inv_alpha, 1.0 / pl.lev[l].R,
+                               pl.invFY.p + l * lvl, pl.dipa.p + l * lvl, pl.dipb.p + l * lvl, pl.cnn.p,
+                               pl.serc_lv.p + (size_t)l * 2 * pl.nser_stride, ns, p, Pp, pl.M.p,
+                               pl.p2m_list.p + pl.p2m_off[l], 0);
+            check_launch(ctx, "k_p2m_quad");
+        }
+    }
     if (far) {
         // upward pass
-        {
+        if (!pl.adaptive) {
         // cached rows for small trees (there the compute kernel's chains are
         // latency-bound; for large ones it beats reading the rows) when they
         // fit the cache budget (built on first use)
         const int64_t rows_bytes = (n0 + 2 * n1) * (int64_t)Pp * (int64_t)sizeof(double);
-        const bool p2m_cache = ctx.opt.near_cache_mb > 0 && pl.nleaf < 8192 &&
+        const bool p2m_cache = ctx.opt.near_cache_mb > 0 && pl.nleaf < 8192 && !pl.adaptive &&
                                rows_bytes <= ((int64_t)ctx.opt.near_cache_mb << 20);
         if (p2m_cache && !pl.p2m_rows_built) {
             StageTimer tb(ctx, YK_STAGE_NEAR_BUILD);
@@ -2471,7 +2719,17 @@ void fmm_run(Context &ctx, FmmPlan &pl, const double *q, const double *dn, doubl
             StageTimer tmm(ctx, YK_STAGE_M2M);
             for (int l = L - 1; l >= pl.lmin; --l) {
                 const int64_t nbl = pl.lev[l].end - pl.lev[l].begin;
-                if (nbl <= kSmallLevelM2M) {
+                if (pl.adaptive) {
+                    // the split boxes only (a leaf keeps its P2M multipole)
+                    if (pl.up_n[l] <= kSmallLevelM2M)
+                        launch_small_gemv(ctx, Pp, 4, pl.up_n[l], pl.up_boxes.p + pl.up_off[l], 0, pl.child4.p,
+                                          pl.bcode.p, pl.m2m.p + (size_t)l * 4 * Pp * Pp, pl.M.p, P, 1, pl.M.p);
+                    else
+                        launch_tile_gemm<double, double>(ctx, P, Pp, pl.up_tile_count[l], pl.up_tiles.p,
+                                                         pl.up_tile_begin[l], pl.up_boxes.p, 4, pl.child4.p,
+                                                         pl.iota4.p, pl.m2m.p, (int64_t)4 * Pp * Pp, 0, pl.M.p,
+                                                         1, pl.M.p);
+                } else if (nbl <= kSmallLevelM2M) {
                     launch_small_gemv(ctx, Pp, 4, nbl, nullptr, pl.lev[l].begin, pl.child4.p, pl.bcode.p,
                                       pl.m2m.p + (size_t)l * 4 * Pp * Pp, pl.M.p, P, 1, pl.M.p);
                 } else {
@@ -2531,6 +2789,16 @@ void fmm_run(Context &ctx, FmmPlan &pl, const double *q, const double *dn, doubl
                                                         (int64_t)kNumOff * Pp * Pp, 0, pl.M.p, 0, pl.Lc.p, nullptr,
                                                         &slab);
             }
+            if (pl.adaptive && pl.n_xbox > 0) {
+                // X lists: coarser leaves' sources straight into the local
+                // expansions (before L2L passes them down)
+                StageTimer tx(ctx, YK_STAGE_M2L);
+                hipLaunchKernelGGL(k_ad_p2l, dim3((unsigned)pl.n_xbox), dim3(64),
+                                   (size_t)Pp * kP2LStride * sizeof(double), ctx.stream, pl.xbox.p, pl.xoff.p,
+                                   pl.xl.p, pl.lrange.p, has_q, has_d, pl.blevel.p, pl.bcx.p, pl.bcy.p, pl.px.p,
+                                   pl.py.p, qs, dns, pl.toff[1], pl.rI.p, p, Pp, inv_alpha, pl.Lc.p);
+                check_launch(ctx, "k_ad_p2l");
+            }
             StageTimer tl2(ctx, YK_STAGE_L2L);
             for (int l = pl.lmin + 1; l <= L; ++l) {
                 // L2L top-down: one parent slot, operator E[l-1][position]
@@ -2553,6 +2821,24 @@ void fmm_run(Context &ctx, FmmPlan &pl, const double *q, const double *dn, doubl
     }
     if (!near_done) launch_near();
     if (overlap) YK_HIP(hipStreamWaitEvent(ctx.stream, ctx.ev_join, 0));
+    if (far && pl.adaptive && as.n_leaves > 0) {
+        StageTimer tl(ctx, YK_STAGE_L2P);
+        if (pl.n_wleaves > 0) {
+            // W lists: finer boxes' multipoles at the leaves' targets
+            hipLaunchKernelGGL(k_ad_m2p, dim3((unsigned)pl.n_wleaves), dim3(64), 0, ctx.stream, pl.wleaves.p,
+                               pl.woff.p, pl.wl.p, pl.lrange.p, mask, pl.blevel.p, pl.bcx.p, pl.bcy.p, pl.px.p,
+                               pl.py.p, pl.M.p, pl.rI.p, p, Pp, inv_alpha, outs);
+            check_launch(ctx, "k_ad_m2p");
+        }
+        hipLaunchKernelGGL(k_ad_l2p, dim3(nblk(pl.N, 256)), dim3(256), 0, ctx.stream, pl.N, pl.toff[1], pl.toff[2],
+                           mask, pl.pleaf.p, pl.leaf_box.p, pl.leaf_lev.p, pl.lmin, pl.bcx.p, pl.bcy.p, pl.px.p,
+                           pl.py.p, pl.Lc.p, inv_alpha, pl.invR_lv.p, pl.invFY.p, pl.cnn.p, pl.serc_lv.p,
+                           pl.nser_dev.p, pl.nser_stride, p, Pp, outs, pl.perm.p, out[0], out[1], out[2],
+                           bie ? bie->w : nullptr, bie ? bie->kappa : nullptr,
+                           (bie && bie->kappa) ? bie->sigma : nullptr);
+        check_launch(ctx, "k_ad_l2p");
+        return;   // L2P wrote the outputs
+    }
     if (far && as.n_leaves > 0) {
         StageTimer tl(ctx, YK_STAGE_L2P);
         const size_t lsh = (size_t)(2 * (p + 1) + 2 * pl.nser) * sizeof(double);

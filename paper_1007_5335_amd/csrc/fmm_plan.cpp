@@ -141,23 +141,67 @@ int choose_order(double tol) {
     return supported_order(std::max(1, p));
 }
 
-void build_lists(Context &ctx, FmmPlan &pl, const std::vector<uint32_t> &keys, const uint32_t *dkeys) {
-    const int64_t N = pl.N;
+// the level-15 Morton codes of all points in one sorted sequence (each set's
+// block of the sorted keys is sorted)
+std::vector<uint32_t> merged_codes(const FmmPlan &pl, const std::vector<uint32_t> &keys) {
     const uint32_t kMask = 0x3fffffffu;
-    // ---- merged Morton codes (each set's block is sorted) ----
     std::vector<uint32_t> merged;
-    merged.reserve(N);
-    {
-        std::vector<uint32_t> a, b;
-        for (int s = 0; s < 3; ++s) {
-            if (pl.toff[s + 1] == pl.toff[s]) continue;
-            b.resize(pl.toff[s + 1] - pl.toff[s]);
-            for (int64_t k = pl.toff[s]; k < pl.toff[s + 1]; ++k) b[k - pl.toff[s]] = keys[k] & kMask;
-            a.swap(merged);
-            merged.resize(a.size() + b.size());
-            std::merge(a.begin(), a.end(), b.begin(), b.end(), merged.begin());
+    merged.reserve(pl.N);
+    std::vector<uint32_t> a, b;
+    for (int s = 0; s < 3; ++s) {
+        if (pl.toff[s + 1] == pl.toff[s]) continue;
+        b.resize(pl.toff[s + 1] - pl.toff[s]);
+        for (int64_t k = pl.toff[s]; k < pl.toff[s + 1]; ++k) b[k - pl.toff[s]] = keys[k] & kMask;
+        a.swap(merged);
+        merged.resize(a.size() + b.size());
+        std::merge(a.begin(), a.end(), b.begin(), b.end(), merged.begin());
+    }
+    return merged;
+}
+
+// boxes of levels 0..L from the sorted codes of each level: level ranges,
+// codes, parents (by a merge of consecutive levels) and centres
+void boxes_from_codes(FmmPlan &pl, const std::vector<std::vector<uint32_t>> &codes, std::vector<double> &cx,
+                      std::vector<double> &cy) {
+    const int L = pl.L;
+    pl.lev.assign(L + 1, LevelInfo{});
+    int64_t nb = 0;
+    for (int l = 0; l <= L; ++l) {
+        pl.lev[l].begin = nb;
+        nb += (int64_t)codes[l].size();
+        pl.lev[l].end = nb;
+        pl.lev[l].side = pl.size / (double)(1u << l);
+        pl.lev[l].R = pl.lev[l].side * 0.70710678118654752440 / pl.alpha;
+    }
+    pl.nbox = nb;
+    pl.hcode.resize(nb);
+    pl.hparent.assign(nb, -1);
+    cx.resize(nb);
+    cy.resize(nb);
+    for (int l = 0; l <= L; ++l) {
+        int64_t pi = 0;
+        for (size_t k = 0; k < codes[l].size(); ++k) {
+            const int64_t gidx = pl.lev[l].begin + (int64_t)k;
+            pl.hcode[gidx] = codes[l][k];
+            uint32_t ix, iy;
+            decode(codes[l][k], ix, iy);
+            cx[gidx] = pl.x0 + (ix + 0.5) * pl.lev[l].side;
+            cy[gidx] = pl.y0 + (iy + 0.5) * pl.lev[l].side;
+            if (l > 0) {
+                while (codes[l - 1][pi] != (codes[l][k] >> 2)) ++pi;
+                pl.hparent[gidx] = (int32_t)(pl.lev[l - 1].begin + pi);
+            }
         }
     }
+}
+
+void finish_tree(Context &ctx, FmmPlan &pl, const std::vector<double> &cx, const std::vector<double> &cy,
+                 const uint32_t *dkeys);
+
+void build_lists(Context &ctx, FmmPlan &pl, const std::vector<uint32_t> &keys, const uint32_t *dkeys) {
+    const int64_t N = pl.N;
+    // ---- merged Morton codes (each set's block is sorted) ----
+    std::vector<uint32_t> merged = merged_codes(pl, keys);
     // ---- leaf level: smallest level whose point-weighted occupancy
     //      sum_i n_i^2 / N (the leaf size seen by an average point, which sets
     //      the near-field work per target) is <= leaf_size ----
@@ -219,37 +263,10 @@ void build_lists(Context &ctx, FmmPlan &pl, const std::vector<uint32_t> &keys, c
             if (codes[l].empty() || codes[l].back() != (v >> 2)) codes[l].push_back(v >> 2);
     }
     // ---- boxes ----
-    pl.lev.assign(L + 1, LevelInfo{});
-    int64_t nb = 0;
-    for (int l = 0; l <= L; ++l) {
-        pl.lev[l].begin = nb;
-        nb += (int64_t)codes[l].size();
-        pl.lev[l].end = nb;
-        pl.lev[l].side = pl.size / (double)(1u << l);
-        pl.lev[l].R = pl.lev[l].side * 0.70710678118654752440 / pl.alpha;
-    }
-    pl.nbox = nb;
+    std::vector<double> cx, cy;
+    boxes_from_codes(pl, codes, cx, cy);
     pl.nleaf = (int64_t)codes[L].size();
-    pl.hcode.resize(nb);
-    pl.hparent.assign(nb, -1);
-    std::vector<double> cx(nb), cy(nb);
-    for (int l = 0; l <= L; ++l) {
-        // parents by a merge of the two sorted code lists (each parent code
-        // is the child's code without its last two bits)
-        int64_t pi = 0;
-        for (size_t k = 0; k < codes[l].size(); ++k) {
-            const int64_t gidx = pl.lev[l].begin + (int64_t)k;
-            pl.hcode[gidx] = codes[l][k];
-            uint32_t ix, iy;
-            decode(codes[l][k], ix, iy);
-            cx[gidx] = pl.x0 + (ix + 0.5) * pl.lev[l].side;
-            cy[gidx] = pl.y0 + (iy + 0.5) * pl.lev[l].side;
-            if (l > 0) {
-                while (codes[l - 1][pi] != (codes[l][k] >> 2)) ++pi;
-                pl.hparent[gidx] = (int32_t)(pl.lev[l - 1].begin + pi);
-            }
-        }
-    }
+    pl.near_tmax = 2.0 * pl.lev[L].side * pl.lev[L].side / (pl.alpha * pl.alpha);
     // ---- M2L levels ----
     int lmin = 2;
     while (lmin <= L && pl.lev[lmin].side >= kFarCut * pl.alpha) ++lmin;
@@ -266,6 +283,232 @@ void build_lists(Context &ctx, FmmPlan &pl, const std::vector<uint32_t> &keys, c
     gpu_point_leaves(ctx, pl, dkeys, dleaf_codes);
     gpu_ulists(ctx, pl, dleaf_codes);
     gpu_vlists(ctx, pl);
+    finish_tree(ctx, pl, cx, cy, dkeys);
+}
+
+// The adaptive tree (Sec. 3.1's quad-tree refined box by box): a box is split
+// while it holds more than leaf_size points (down to level 15); then, until
+// nothing changes, a leaf touched by an existing box two levels finer is split
+// (2:1 balance, so that touching leaves differ by at most one level and a U
+// list holds at most 13 leaves).  Leaves are numbered in Morton order of their
+// first level-15 cell; the U and W lists are built on the GPU (lists.hip), X
+// is the transpose of W.
+void build_lists_adaptive(Context &ctx, FmmPlan &pl, const std::vector<uint32_t> &keys, const uint32_t *dkeys) {
+    const int64_t N = pl.N, s = pl.opt_leaf;
+    std::vector<uint32_t> merged = merged_codes(pl, keys);
+    // non-empty boxes of every level and their point counts
+    std::vector<std::vector<uint32_t>> code(kMaxLevel + 1);
+    std::vector<std::vector<int32_t>> cnt(kMaxLevel + 1);
+    for (int64_t k = 0; k < N; ++k) {
+        if (k == 0 || merged[k] != merged[k - 1]) {
+            code[kMaxLevel].push_back(merged[k]);
+            cnt[kMaxLevel].push_back(0);
+        }
+        cnt[kMaxLevel].back()++;
+    }
+    merged.clear();
+    merged.shrink_to_fit();
+    for (int l = kMaxLevel - 1; l >= 0; --l) {
+        const auto &c1 = code[l + 1];
+        const auto &n1 = cnt[l + 1];
+        for (size_t k = 0; k < c1.size(); ++k) {
+            const uint32_t v = c1[k] >> 2;
+            if (code[l].empty() || code[l].back() != v) {
+                code[l].push_back(v);
+                cnt[l].push_back(0);
+            }
+            cnt[l].back() += n1[k];
+        }
+    }
+    // state of every non-empty box: absent (inside a leaf), leaf or split
+    enum : int8_t { kAbsent = 0, kLeafBox = 1, kSplitBox = 2 };
+    std::vector<std::vector<int8_t>> st(kMaxLevel + 1);
+    for (int l = 0; l <= kMaxLevel; ++l) {
+        st[l].assign(code[l].size(), kAbsent);
+        size_t pi = 0;
+        for (size_t k = 0; k < code[l].size(); ++k) {
+            bool exists = l == 0;
+            if (l > 0) {
+                while (code[l - 1][pi] != (code[l][k] >> 2)) ++pi;
+                exists = st[l - 1][pi] == kSplitBox;
+            }
+            if (exists) st[l][k] = (cnt[l][k] > s && l < kMaxLevel) ? kSplitBox : kLeafBox;
+        }
+    }
+    auto find = [&](int l, uint32_t c) -> int64_t {
+        auto it = std::lower_bound(code[l].begin(), code[l].end(), c);
+        return (it != code[l].end() && *it == c) ? (int64_t)(it - code[l].begin()) : -1;
+    };
+    // 2:1 balance: the 20 cells two levels finer that ring a leaf touch it
+    for (bool changed = true; changed;) {
+        changed = false;
+        for (int l = 0; l + 2 <= kMaxLevel; ++l) {
+            const int64_t nl = (int64_t)code[l].size();
+            std::vector<char> hit((size_t)nl, 0);
+            const int64_t ns = (int64_t)1 << (l + 2);
+            parallel_for(nl, [&](int64_t i0, int64_t i1) {
+                for (int64_t k = i0; k < i1; ++k) {
+                    if (st[l][k] != kLeafBox) continue;
+                    uint32_t bx, by;
+                    decode(code[l][k], bx, by);
+                    for (int j = -1; j <= 4 && !hit[k]; ++j)
+                        for (int i = -1; i <= 4; ++i) {
+                            if (i >= 0 && i <= 3 && j >= 0 && j <= 3) continue;
+                            const int64_t X = 4 * (int64_t)bx + i, Y = 4 * (int64_t)by + j;
+                            if (X < 0 || Y < 0 || X >= ns || Y >= ns) continue;
+                            const int64_t q = find(l + 2, encode((uint32_t)X, (uint32_t)Y));
+                            if (q >= 0 && st[l + 2][q] != kAbsent) {
+                                hit[k] = 1;
+                                break;
+                            }
+                        }
+                }
+            });
+            for (int64_t k = 0; k < nl; ++k) {
+                if (!hit[k]) continue;
+                changed = true;
+                st[l][k] = kSplitBox;
+                // its children become leaves (they hold at most the parent's s points)
+                const uint32_t c0 = code[l][k] << 2;
+                auto it = std::lower_bound(code[l + 1].begin(), code[l + 1].end(), c0);
+                for (; it != code[l + 1].end() && (*it >> 2) == code[l][k]; ++it)
+                    st[l + 1][it - code[l + 1].begin()] = kLeafBox;
+            }
+        }
+    }
+    int L = 0;
+    for (int l = 0; l <= kMaxLevel; ++l)
+        for (int8_t v : st[l])
+            if (v != kAbsent) {
+                L = l;
+                break;
+            }
+    pl.L = L;
+    std::vector<std::vector<uint32_t>> codes(L + 1);
+    std::vector<std::vector<int8_t>> lst(L + 1);
+    for (int l = 0; l <= L; ++l)
+        for (size_t k = 0; k < code[l].size(); ++k)
+            if (st[l][k] != kAbsent) {
+                codes[l].push_back(code[l][k]);
+                lst[l].push_back(st[l][k]);
+            }
+    code.clear();
+    cnt.clear();
+    st.clear();
+    std::vector<double> cx, cy;
+    boxes_from_codes(pl, codes, cx, cy);
+    const int64_t nb = pl.nbox;
+    // leaves in Morton order of their first level-15 cell
+    pl.h_blevel.assign(nb, 0);
+    pl.h_box_leaf.assign(nb, -1);
+    std::vector<std::pair<uint32_t, int32_t>> lv;
+    for (int l = 0; l <= L; ++l)
+        for (int64_t b = pl.lev[l].begin; b < pl.lev[l].end; ++b) {
+            pl.h_blevel[b] = l;
+            if (lst[l][b - pl.lev[l].begin] == kLeafBox)
+                lv.push_back({pl.hcode[b] << (2 * (kMaxLevel - l)), (int32_t)b});
+        }
+    std::sort(lv.begin(), lv.end());
+    pl.nleaf = (int64_t)lv.size();
+    pl.h_leaf_box.resize(lv.size());
+    std::vector<uint32_t> lstart(lv.size());
+    std::vector<int32_t> llev(lv.size());
+    for (size_t k = 0; k < lv.size(); ++k) {
+        pl.h_leaf_box[k] = lv[k].second;
+        pl.h_box_leaf[lv[k].second] = (int32_t)k;
+        lstart[k] = lv[k].first;
+        llev[k] = pl.h_blevel[lv[k].second];
+    }
+    int lmin = 2;
+    while (lmin <= L && pl.lev[lmin].side >= kFarCut * pl.alpha) ++lmin;
+    pl.lmin = lmin;
+    auto up = [&](auto &buf, const auto &vec) {
+        using T = typename std::decay_t<decltype(vec)>::value_type;
+        T *d = buf.ensure(std::max<size_t>(vec.size(), 1));
+        if (!vec.empty())
+            YK_HIP(hipMemcpyAsync(d, vec.data(), vec.size() * sizeof(T), hipMemcpyHostToDevice, ctx.stream));
+    };
+    up(pl.bcode, pl.hcode);
+    up(pl.blevel, pl.h_blevel);
+    up(pl.leaf_box, pl.h_leaf_box);
+    up(pl.box_leaf, pl.h_box_leaf);
+    up(pl.leaf_start, lstart);
+    up(pl.leaf_lev, llev);
+    finish_tree(ctx, pl, cx, cy, dkeys);   // children (the list walks need them)
+    // ---- on the GPU: each point's leaf and the ranges, U and W lists, V lists ----
+    gpu_point_leaves_adaptive(ctx, pl, dkeys);
+    gpu_ulists_adaptive(ctx, pl);
+    gpu_vlists(ctx, pl);
+    std::vector<int32_t> woff, wl;
+    gpu_wlists(ctx, pl, woff, wl);
+    // ---- X lists: the transpose of W (source leaves in increasing index) ----
+    {
+        std::vector<int32_t> xc(nb, 0);
+        for (int32_t d : wl) xc[d]++;
+        std::vector<int32_t> xbox, xoff, xpos(nb, -1);
+        xoff.push_back(0);
+        for (int64_t d = 0; d < nb; ++d)
+            if (xc[d] > 0) {
+                xpos[d] = (int32_t)xbox.size();
+                xbox.push_back((int32_t)d);
+                xoff.push_back(xoff.back() + xc[d]);
+            }
+        std::vector<int32_t> xl(wl.size()), fill(xbox.size(), 0);
+        std::vector<int32_t> wleaves;
+        for (int64_t li = 0; li < pl.nleaf; ++li) {
+            if (woff[li + 1] > woff[li]) wleaves.push_back((int32_t)li);
+            for (int32_t k = woff[li]; k < woff[li + 1]; ++k) {
+                const int32_t x = xpos[wl[k]];
+                xl[xoff[x] + fill[x]++] = (int32_t)li;
+            }
+        }
+        pl.n_xbox = (int64_t)xbox.size();
+        pl.n_xl = (int64_t)xl.size();
+        pl.n_wleaves = (int64_t)wleaves.size();
+        up(pl.xbox, xbox);
+        up(pl.xoff, xoff);
+        up(pl.xl, xl);
+        up(pl.wleaves, wleaves);
+    }
+    // ---- leaf ranges by box (P2M launches per level), leaves per level ----
+    {
+        std::vector<int32_t> alr((size_t)nb * 6, 0);
+        for (int64_t li = 0; li < pl.nleaf; ++li)
+            for (int j = 0; j < 6; ++j) alr[(size_t)pl.h_leaf_box[li] * 6 + j] = pl.h_lrange[(size_t)li * 6 + j];
+        up(pl.alr, alr);
+        std::vector<int32_t> pls;
+        pl.p2m_off.assign(L + 2, 0);
+        for (int l = 0; l <= L; ++l) {
+            pl.p2m_off[l] = (int64_t)pls.size();
+            if (l < lmin) continue;
+            for (int64_t b = pl.lev[l].begin; b < pl.lev[l].end; ++b)
+                if (pl.h_box_leaf[b] >= 0) pls.push_back((int32_t)(b - pl.lev[l].begin));
+        }
+        pl.p2m_off[L + 1] = (int64_t)pls.size();
+        up(pl.p2m_list, pls);
+    }
+    // near field: t = r^2 / (4 alpha^2) of a U-list pair is at most 2 s^2 / alpha^2
+    // for the side s of the coarser leaf
+    {
+        int lc = L;
+        for (int32_t v : llev) lc = std::min(lc, v);
+        pl.near_tmax = 2.0 * pl.lev[lc].side * pl.lev[lc].side / (pl.alpha * pl.alpha);
+    }
+    YK_HIP(hipStreamSynchronize(ctx.stream));
+}
+
+// children, M2M tiles (over the split boxes), the slot -> offset table, and
+// the uploads common to both tree forms
+void finish_tree(Context &ctx, FmmPlan &pl, const std::vector<double> &cx, const std::vector<double> &cy,
+                 const uint32_t *dkeys) {
+    const int64_t N = pl.N, nb = pl.nbox;
+    const int L = pl.L, lmin = pl.lmin;
+    auto up = [&](auto &buf, const auto &vec) {
+        using T = typename std::decay_t<decltype(vec)>::value_type;
+        T *d = buf.ensure(std::max<size_t>(vec.size(), 1));
+        if (!vec.empty())
+            YK_HIP(hipMemcpyAsync(d, vec.data(), vec.size() * sizeof(T), hipMemcpyHostToDevice, ctx.stream));
+    };
     // ---- children (contiguous at the next level because codes are sorted) ----
     std::vector<int32_t> fch(nb, -1), nch(nb, 0);
     for (int64_t b = 0; b < nb; ++b) {
@@ -282,12 +525,20 @@ void build_lists(Context &ctx, FmmPlan &pl, const std::vector<uint32_t> &keys, c
     std::vector<int32_t> uboxes;
     pl.up_tile_begin.assign(L + 1, 0);
     pl.up_tile_count.assign(L + 1, 0);
+    pl.up_off.assign(L + 1, 0);
+    pl.up_n.assign(L + 1, 0);
     for (int l = lmin; l < L; ++l) {
+        // the boxes with children (all of them in the uniform tree)
+        std::vector<int32_t> par;
+        for (int64_t b = pl.lev[l].begin; b < pl.lev[l].end; ++b)
+            if (nch[b] > 0) par.push_back((int32_t)b);
         pl.up_tile_begin[l] = (int)utiles.size();
-        for (int64_t b = pl.lev[l].begin; b < pl.lev[l].end; b += 64) {
-            const int cnt = (int)std::min<int64_t>(64, pl.lev[l].end - b);
+        pl.up_off[l] = (int64_t)uboxes.size();
+        pl.up_n[l] = (int64_t)par.size();
+        for (size_t k0 = 0; k0 < par.size(); k0 += 64) {
+            const int cnt = (int)std::min<size_t>(64, par.size() - k0);
             utiles.push_back(make_int4(l, 0, (int)uboxes.size(), cnt));
-            for (int k = 0; k < cnt; ++k) uboxes.push_back((int32_t)(b + k));
+            for (int k = 0; k < cnt; ++k) uboxes.push_back(par[k0 + k]);
         }
         pl.up_tile_count[l] = (int)utiles.size() - pl.up_tile_begin[l];
     }
@@ -330,7 +581,7 @@ void build_lists(Context &ctx, FmmPlan &pl, const std::vector<uint32_t> &keys, c
         up(pl.up_tiles, utiles);
         up(pl.up_boxes, uboxes);
     }
-    {
+    if (!pl.adaptive) {
         std::vector<int32_t> dl;
         for (int64_t li = 0; li < pl.nleaf; ++li)
             if (pl.h_lrange[(size_t)li * 6 + 3] > pl.h_lrange[(size_t)li * 6 + 2]) dl.push_back((int32_t)li);
@@ -379,26 +630,56 @@ void build_tables(Context &ctx, FmmPlan &pl, int p) {
     up(pl.dipa, da);
     up(pl.dipb, db);
     up(pl.cnn, cnn);
-    // series length for F_{p+1}, F_{p+2} at the leaf level
-    {
-        const ld Y = 0.25L * pl.lev[L].R * pl.lev[L].R * 1.0001L;
+    // series length for F_{p+1}, F_{p+2} at level l (leaf level of a uniform
+    // tree; every level from lmin on in an adaptive one)
+    auto series_len = [&](int l) {
+        const ld Y = 0.25L * pl.lev[l].R * pl.lev[l].R * 1.0001L;
         ld t = 1;
         int k = 1;
         for (; k < 200; ++k) {
             t *= Y / ((ld)k * (ld)(p + 1 + k));
             if (t < 1e-19L) break;
         }
-        pl.nser = k + 1;
-        std::vector<double> sc(2 * pl.nser);
+        return k + 1;
+    };
+    auto series_coef = [&](int ns, double *sc) {
         for (int w = 0; w < 2; ++w) {
             const int n = p + 1 + w;
             ld c = 1;
-            for (int kk = 0; kk < pl.nser; ++kk) {
+            for (int kk = 0; kk < ns; ++kk) {
                 if (kk > 0) c /= (ld)kk * (ld)(n + kk);
-                sc[w * pl.nser + kk] = (double)c;
+                sc[w * ns + kk] = (double)c;
             }
         }
+    };
+    {
+        pl.nser = series_len(L);
+        std::vector<double> sc(2 * pl.nser);
+        series_coef(pl.nser, sc.data());
         up(pl.serc, sc);
+    }
+    if (pl.adaptive && lmin <= L) {
+        pl.nser_lv.assign(nL, 0);
+        pl.nser_stride = 0;
+        for (int l = lmin; l <= L; ++l) {
+            pl.nser_lv[l] = series_len(l);
+            pl.nser_stride = std::max(pl.nser_stride, pl.nser_lv[l]);
+        }
+        std::vector<double> sc((size_t)nL * 2 * pl.nser_stride, 0.0), invR(nL, 0.0);
+        std::vector<double> ri((size_t)nL * (p + 3), 0.0);
+        for (int l = lmin; l <= L; ++l) {
+            series_coef(pl.nser_lv[l], &sc[(size_t)l * 2 * pl.nser_stride]);
+            invR[l] = 1.0 / pl.lev[l].R;
+            // I_0(R_l), then the ratios I_n(R_l) / I_{n-1}(R_l): the products
+            // I_n(R) K_n(rho) of M2P and P2L are built from them and from the
+            // ratios of K, which keeps every factor in range
+            ri[(size_t)l * (p + 3)] = (double)IR[l][0];
+            for (int n = 1; n <= p + 2; ++n) ri[(size_t)l * (p + 3) + n] = (double)(IR[l][n] / IR[l][n - 1]);
+        }
+        up(pl.serc_lv, sc);
+        up(pl.invR_lv, invR);
+        up(pl.rI, ri);
+        up(pl.nser_dev, pl.nser_lv);
     }
     // near-field series length: t = r^2/(4 alpha^2) over U-list pairs is at most
     // (2 sqrt(2) side_L)^2 / (4 alpha^2); when it exceeds 1 the large-argument
@@ -407,7 +688,7 @@ void build_tables(Context &ctx, FmmPlan &pl, int p) {
     // the digamma weights of B and D), is below half an ulp of the smallest
     // K0 on the range (K0(z) > -(1/2) ln t - 0.58, and K0(2) > 0.11).
     {
-        const double tmax = 2.0 * pl.lev[L].side * pl.lev[L].side / (alpha * alpha);
+        const double tmax = pl.near_tmax;
         const double tt = std::min(1.0, tmax);
         const double weight = 0.5 * std::fabs(std::log(tt)) + 3.0;
         const double k0min = std::max(0.11, -0.5 * std::log(tt) - 0.58);
@@ -661,19 +942,23 @@ ActiveSet &get_active(Context &ctx, FmmPlan &pl, int mask) {
     if (it != pl.active.end()) return *it->second;
     auto as = std::make_unique<ActiveSet>();
     const int L = pl.L;
+    // the box of leaf li (uniform tree: the li-th box of the leaf level)
+    auto leaf_gbox = [&](int64_t li) -> int64_t {
+        return pl.adaptive ? (int64_t)pl.h_leaf_box[li] : pl.lev[L].begin + li;
+    };
     std::vector<int64_t> cnt(pl.nbox, 0);
     for (int64_t li = 0; li < pl.nleaf; ++li) {
         int64_t c = 0;
         for (int s = 0; s < 3; ++s)
             if (mask & (1 << s)) c += pl.h_lrange[li * 6 + 2 * s + 1] - pl.h_lrange[li * 6 + 2 * s];
-        cnt[pl.lev[L].begin + li] = c;
+        cnt[leaf_gbox(li)] = c;
     }
     for (int64_t b = pl.nbox - 1; b >= 0; --b)
         if (pl.hparent[b] >= 0) cnt[pl.hparent[b]] += cnt[b];
     std::vector<int32_t> leaves;
     std::vector<int2> items;
     for (int64_t li = 0; li < pl.nleaf; ++li) {
-        const int64_t c = cnt[pl.lev[L].begin + li];
+        const int64_t c = cnt[leaf_gbox(li)];
         if (c > 0) leaves.push_back((int32_t)li);
         for (int64_t tb = 0; tb < c; tb += 64) items.push_back(make_int2((int)li, (int)tb));
     }
@@ -701,7 +986,7 @@ ActiveSet &get_active(Context &ctx, FmmPlan &pl, int mask) {
             }
         });
         for (int32_t li : leaves) {
-            const int64_t nt = cnt[pl.lev[L].begin + li];
+            const int64_t nt = cnt[leaf_gbox(li)];
             as->pairs_q += nt * sq_leaf[li];
             as->pairs_d += nt * sd_leaf[li];
             as->l2p_points += nt;
@@ -713,7 +998,7 @@ ActiveSet &get_active(Context &ctx, FmmPlan &pl, int mask) {
     }
     as->h_items = items;
     as->h_tcnt.assign(pl.nleaf, 0);
-    for (int64_t li = 0; li < pl.nleaf; ++li) as->h_tcnt[li] = cnt[pl.lev[L].begin + li];
+    for (int64_t li = 0; li < pl.nleaf; ++li) as->h_tcnt[li] = cnt[leaf_gbox(li)];
     as->mask = mask;
     // M2L tiles: active boxes of levels lmin..L grouped by (level, class).
     // The V lists come to the host only for small trees (the sparse form's

@@ -27,6 +27,9 @@ YK_PREC_FP64 = 0
 YK_PREC_MIXED = 1
 YK_PREC_FP32 = 2
 
+YK_TREE_UNIFORM = 0
+YK_TREE_ADAPTIVE = 1
+
 HEAT_GRID_SELF_CELL = 1
 HEAT_ZERO_GUESS = 2
 HEAT_NO_NEAR = 4
@@ -45,7 +48,7 @@ EXPORTS = (
     "yk_ws_predict", "yk_set_warm_start", "yk_ws_num_params", "yk_ws_get_params",
     "yk_ws_set_params", "yk_ws_loss_grad", "yk_ws_forward", "yk_ws_adam_step",
     "yk_gmres_density_noalloc", "yk_plan_tree_export", "yk_rhs_imex", "yk_heat_step_grid",
-    "yk_near_info",
+    "yk_near_info", "yk_plan_adaptive_export",
 )
 
 STAGES = ("gather", "p2m", "m2m", "m2l", "l2l", "leaf", "scatter", "direct", "l2p", "near_build")
@@ -54,7 +57,7 @@ STAGES = ("gather", "p2m", "m2m", "m2l", "l2l", "leaf", "scatter", "direct", "l2
 class yk_options(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int), ("fmm_tol", ctypes.c_double), ("p", ctypes.c_int),
                 ("leaf_size", ctypes.c_int), ("direct", ctypes.c_int), ("gmres_m", ctypes.c_int),
-                ("debug_flags", ctypes.c_int), ("near_cache_mb", ctypes.c_int)]
+                ("debug_flags", ctypes.c_int), ("near_cache_mb", ctypes.c_int), ("tree", ctypes.c_int)]
 
 
 class yk_boundary(ctypes.Structure):
@@ -93,7 +96,9 @@ class yk_plan_info(ctypes.Structure):
                 ("near_incoming", ctypes.c_int64), ("p_initial", ctypes.c_int32),
                 ("order_check_err", ctypes.c_double), ("m2m_children", ctypes.c_int64),
                 ("l2l_children", ctypes.c_int64), ("n_ulist", ctypes.c_int64),
-                ("tables_ms", ctypes.c_double), ("order_check_ms", ctypes.c_double)]
+                ("tables_ms", ctypes.c_double), ("order_check_ms", ctypes.c_double),
+                ("tree", ctypes.c_int32), ("max_u", ctypes.c_int32), ("n_wlist", ctypes.c_int64),
+                ("n_xboxes", ctypes.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -161,6 +166,7 @@ def load_library(path: str = LIB_PATH):
         "yk_ws_adam_step": (ip, [vp, vp]),
         "yk_gmres_density_noalloc": (ip, [vp, P(yk_boundary), dbl, vp, vp, dbl, ip, vp, P(yk_stats)]),
         "yk_plan_tree_export": (ip, [vp, ip, P(dbl), P(i64), vp, vp, vp, vp, vp, vp, vp, vp]),
+        "yk_plan_adaptive_export": (ip, [vp, ip, vp, vp, vp, vp, vp, vp, vp]),
         "yk_rhs_imex": (ip, [vp, ip, ip, i64, vp, vp, vp, vp, vp, ip, P(dbl), dbl, vp]),
         "yk_heat_step_grid": (ip, [vp, P(yk_boundary), P(yk_grid), vp, ip, vp, dbl, dbl, vp, vp, P(yk_stats)]),
         "yk_near_info": (ip, [vp, P(i64), P(dbl)]),
@@ -507,3 +513,22 @@ def yk_plan_tree_export(ctx, slot=0):
                 lmin=info.lmin, keys=h(keys, N).view(np.uint32), perm=h(perm, N), box_code=h(code, nb).view(np.uint32),
                 parent=h(parent, nb), leaf_range=h(lr, nl * 6).reshape(nl, 6), ulist_off=h(uoff, nl + 1),
                 ulist=h(ul, info.n_ulist), vlist=h(vl, nb * 27).reshape(nb, 27))
+
+
+def yk_plan_adaptive_export(ctx, slot=0):
+    """The adaptive parts of the cached tree of `slot` as numpy arrays: each
+    leaf's box, each box's level, the W lists (CSR over leaves) and the X
+    lists (CSR over the boxes that have one)."""
+    import torch
+    info = yk_plan_info_get(ctx, slot)
+    if not info.valid:
+        raise YkError(YK_ERR_ARG, "no tree cached in this slot")
+    nb, nl, nw, nx = info.n_boxes, info.n_leaves, info.n_wlist, info.n_xboxes
+    dev = lambda n: torch.empty(max(int(n), 1), dtype=torch.int32, device="cuda")
+    lb, bl, wo, wl, xb, xo, xl = dev(nl), dev(nb), dev(nl + 1), dev(nw), dev(nx), dev(nx + 1), dev(nw)
+    ptr = lambda t: ctypes.c_void_p(t.data_ptr())
+    _check(ctx, load_library().yk_plan_adaptive_export(ctx, int(slot), ptr(lb), ptr(bl), ptr(wo), ptr(wl),
+                                                       ptr(xb), ptr(xo), ptr(xl)))
+    h = lambda t, n: t.cpu().numpy()[:int(n)]
+    return dict(leaf_box=h(lb, nl), box_level=h(bl, nb), wlist_off=h(wo, nl + 1), wlist=h(wl, nw),
+                xbox=h(xb, nx), xlist_off=h(xo, nx + 1), xlist=h(xl, nw))
