@@ -403,10 +403,11 @@ def heat_step_bench(args, yk, torch, W):
                      "train_s": train_s,
                      "phase_ms": dict(zip(("volume_to_nodes", "guess_selection", "density_solve",
                                            "volume_assembly"), np.mean(phases, axis=0).tolist()))}
-    ref = finals["fp64"]
+    ref = finals.get("fp64", next(iter(finals.values())) if finals else None)
     for name in finals:
         out[name]["u_rel_diff_vs_fp64"] = float(np.max(np.abs(finals[name] - ref)) / np.max(np.abs(ref)))
-    out["speedup_mixed_learned_vs_fp64"] = out["fp64"]["s_per_step"] / out["mixed_learned"]["s_per_step"]
+    if "fp64" in out and "mixed_learned" in out:
+        out["speedup_mixed_learned_vs_fp64"] = out["fp64"]["s_per_step"] / out["mixed_learned"]["s_per_step"]
     out["workload"] = (f"{n_steps} backward-Euler steps, dt=1e-3, alpha=sqrt(dt), {args.heat_m}^2 cell grid "
                        f"in the unit square, outer circle ({b.curves[0].n} nodes) + 10 random ellipses x "
                        f"2048 nodes, GMRES tol 1e-10; network trained on steps 1-{half}, timing and "
@@ -433,7 +434,8 @@ def large_step_bench(args, yk, torch, W):
     out, finals = {}, {}
     # one FMM pass over every point (volume charges a positive density times
     # the cell areas, unit-scale dipoles), tree already built
-    ctx = yk.yk_create(fmm_tol=1e-10)
+    tree = yk.YK_TREE_ADAPTIVE if args.tree == "adaptive" else yk.YK_TREE_UNIFORM
+    ctx = yk.yk_create(fmm_tol=1e-10, tree=tree)
     try:
         rng = np.random.default_rng(5)
         q = d(rng.uniform(0.5, 1.5, volh.shape[0]) * c["vol_w"])
@@ -452,6 +454,8 @@ def large_step_bench(args, yk, torch, W):
         out["pass"] = {"first_call_ms": ms[0], "ms": float(np.mean(ms[1:])),
                        "mpts_per_s": npts / (float(np.mean(ms[1:])) * 1e-3) / 1e6, "n_points": npts,
                        "p": info.p, "leaf_level": info.leaf_level, "n_leaves": info.n_leaves,
+                       "tree": args.tree, "n_boxes": info.n_boxes, "w_entries": info.n_wlist,
+                       "x_boxes": info.n_xboxes,
                        "tree_build_ms": info.build_ms, "near_symmetric": bool(info.near_sym),
                        "near_charge_values": info.near_charge_values, "pairs": info.pairs_charge + info.pairs_dipole}
         print(f"large set pass: {out['pass']['ms']:.1f} ms", file=sys.stderr, flush=True)
@@ -459,8 +463,9 @@ def large_step_bench(args, yk, torch, W):
         yk.yk_destroy(ctx)
     runs = (("fp64", yk.YK_PREC_FP64, False), ("fp64_learned", yk.YK_PREC_FP64, True),
             ("mixed_learned", yk.YK_PREC_MIXED, True))
+    runs = tuple(r for r in runs if r[0] in args.large_runs.split(","))
     for name, prec, learned in runs:
-        ctx = yk.yk_create(fmm_tol=1e-10, precision=prec)
+        ctx = yk.yk_create(fmm_tol=1e-10, precision=prec, tree=tree)
         ws = None
         try:
             if learned:
@@ -506,12 +511,14 @@ def large_step_bench(args, yk, torch, W):
                      "phase_ms": dict(zip(("volume_to_nodes", "guess_selection", "density_solve",
                                            "volume_assembly"), np.mean(phases, axis=0).tolist())),
                      "u_max_abs_per_step": umax}
-    ref = finals["fp64"]
+    ref = finals.get("fp64", next(iter(finals.values())) if finals else None)
     for name in finals:
         out[name]["u_rel_diff_vs_fp64"] = float(np.max(np.abs(finals[name] - ref)) / np.max(np.abs(ref)))
         out[name]["u_rel_l2_vs_fp64"] = float(np.linalg.norm(finals[name] - ref) / np.linalg.norm(ref))
-    out["speedup_mixed_learned_vs_fp64"] = out["fp64"]["s_per_step"] / out["mixed_learned"]["s_per_step"]
-    out["workload"] = (f"{n_steps} backward-Euler steps on the large adaptive set: {volh.shape[0]} adaptive cells "
+    if "fp64" in out and "mixed_learned" in out:
+        out["speedup_mixed_learned_vs_fp64"] = out["fp64"]["s_per_step"] / out["mixed_learned"]["s_per_step"]
+    out["workload"] = (f"{n_steps} backward-Euler steps on the large adaptive set ({args.tree} quad-tree): "
+                       f"{volh.shape[0]} adaptive cells "
                        f"(refined by a mixture of 8 Gaussians), outer circle + 20 circular holes x 8192 nodes, "
                        f"alpha=1e-3, dt=alpha^2, "
                        f"GMRES tol 1e-10; network trained on steps 1-{half}, timing and iterations averaged over "
@@ -544,6 +551,10 @@ def main():
     ap.add_argument("--large-steps", type=int, default=0,
                     help="only the time-stepping comparison on the large adaptive set, this many steps; "
                          "prints its JSON object")
+    ap.add_argument("--tree", choices=("uniform", "adaptive"), default="uniform",
+                    help="quad-tree of the large-set runs (--large-steps)")
+    ap.add_argument("--large-runs", default="fp64,fp64_learned,mixed_learned",
+                    help="which of the large-set step runs to time (comma-separated)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a plain 256 MiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
