@@ -435,7 +435,7 @@ def large_step_bench(args, yk, torch, W):
     out, finals = {}, {}
     # one FMM pass over every point (volume charges a positive density times
     # the cell areas, unit-scale dipoles), tree already built
-    tree = yk.YK_TREE_ADAPTIVE if args.tree == "adaptive" else yk.YK_TREE_UNIFORM
+    tree = {"auto": yk.YK_TREE_AUTO, "uniform": yk.YK_TREE_UNIFORM, "adaptive": yk.YK_TREE_ADAPTIVE}[args.tree]
     ctx = yk.yk_create(fmm_tol=1e-10, tree=tree)
     try:
         rng = np.random.default_rng(5)
@@ -455,7 +455,8 @@ def large_step_bench(args, yk, torch, W):
         out["pass"] = {"first_call_ms": ms[0], "ms": float(np.mean(ms[1:])),
                        "mpts_per_s": npts / (float(np.mean(ms[1:])) * 1e-3) / 1e6, "n_points": npts,
                        "p": info.p, "leaf_level": info.leaf_level, "n_leaves": info.n_leaves,
-                       "tree": args.tree, "n_boxes": info.n_boxes, "w_entries": info.n_wlist,
+                       "tree": "adaptive" if info.tree == yk.YK_TREE_ADAPTIVE else "uniform",
+                       "n_boxes": info.n_boxes, "w_entries": info.n_wlist,
                        "x_boxes": info.n_xboxes,
                        "tree_build_ms": info.build_ms, "near_symmetric": bool(info.near_sym),
                        "near_charge_values": info.near_charge_values, "pairs": info.pairs_charge + info.pairs_dipole}
@@ -552,8 +553,9 @@ def main():
     ap.add_argument("--large-steps", type=int, default=0,
                     help="only the time-stepping comparison on the large adaptive set, this many steps; "
                          "prints its JSON object")
-    ap.add_argument("--tree", choices=("uniform", "adaptive"), default="uniform",
-                    help="quad-tree of the large-set runs (--large-steps)")
+    ap.add_argument("--tree", choices=("auto", "uniform", "adaptive"), default="auto",
+                    help="quad-tree of the large-set runs (--large-steps; auto: adaptive for the "
+                         "clustered volume set, uniform for the boundary)")
     ap.add_argument("--large-runs", default="fp64,fp64_learned,mixed_learned",
                     help="which of the large-set step runs to time (comma-separated)")
     ap.add_argument("--calib-copy", action="store_true",

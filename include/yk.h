@@ -89,7 +89,11 @@ typedef struct {
     int near_cache_mb;      /* device memory (MiB) a tree may spend on its cached
                                near-field interaction values; 0 = evaluate the
                                near-field kernels on every call */
-    int tree;               /* YK_TREE_*: the quad-tree of Sec. 3.1.  UNIFORM: every
+    int tree;               /* YK_TREE_*: the quad-tree of Sec. 3.1.  AUTO (default):
+                               the uniform tree unless it would hold more than
+                               six times N / leaf_size leaves (points clustered
+                               so strongly that most of its leaves are nearly
+                               empty), then the adaptive one.  UNIFORM: every
                                leaf at one level (the smallest level whose
                                point-weighted occupancy is <= leaf_size), U and
                                V lists.  ADAPTIVE: boxes split while they hold
@@ -102,7 +106,7 @@ typedef struct {
                                unused) */
 } yk_options;
 
-enum { YK_TREE_UNIFORM = 0, YK_TREE_ADAPTIVE = 1 };
+enum { YK_TREE_UNIFORM = 0, YK_TREE_ADAPTIVE = 1, YK_TREE_AUTO = 2 };
 
 typedef struct {
     int32_t n_curves;             /* >= 1; curve 0 outer, 1.. holes */
@@ -456,7 +460,7 @@ typedef struct {
     double tables_ms;         /* host time spent on the translation operator tables
                                  (each order tried by the order check) */
     double order_check_ms;    /* time of the build-time order check (within build_ms) */
-    int32_t tree;             /* YK_TREE_* of the cached tree */
+    int32_t tree;             /* YK_TREE_UNIFORM or YK_TREE_ADAPTIVE: the cached tree's form */
     int32_t max_u;            /* adaptive tree: the longest U list (at most 13) */
     int64_t n_wlist;          /* adaptive tree: W-list entries (= X-list entries) */
     int64_t n_xboxes;         /* adaptive tree: boxes with a non-empty X list */

@@ -414,13 +414,13 @@ void yk_default_options(yk_options *opt) {
     opt->gmres_m = 60;
     opt->debug_flags = 0;
     opt->near_cache_mb = 16384;
-    opt->tree = YK_TREE_UNIFORM;
+    opt->tree = YK_TREE_AUTO;
 }
 
 static bool valid_options(const yk_options *o) {
     return o->precision >= 0 && o->precision <= 2 && o->p >= 0 && o->p <= 31 &&
            o->leaf_size >= 1 && o->leaf_size <= 4096 && o->gmres_m >= 1 && o->gmres_m <= 120 &&
-           o->near_cache_mb >= 0 && (o->tree == YK_TREE_UNIFORM || o->tree == YK_TREE_ADAPTIVE) &&
+           o->near_cache_mb >= 0 && o->tree >= YK_TREE_UNIFORM && o->tree <= YK_TREE_AUTO &&
            (o->p > 0 || (o->fmm_tol > 0 && o->fmm_tol < 1));
 }
 

@@ -184,7 +184,7 @@ struct FmmPlan {
     // Leaf li is box leaf_box[li] (uniform tree: box lev[L].begin + li); the
     // leaf-indexed arrays above (lrange, pleaf, ulist) follow that numbering.
     bool adaptive = false;
-    int opt_tree = 0;
+    int opt_tree = 0;                              // 0 uniform, 1 adaptive, 2 automatic
     std::vector<int32_t> h_leaf_box, h_box_leaf;   // leaf -> box, box -> leaf (-1: split box)
     std::vector<int32_t> h_blevel;                 // level of every box
     DevBuf<int32_t> leaf_box, box_leaf, blevel, leaf_lev;
@@ -216,7 +216,9 @@ FmmPlan *plan_in_slot(Context &ctx, int slot);
 void build_tree(Context &ctx, FmmPlan &pl, const SumProblem &pb);
 // fmm_plan.cpp: boxes and lists from the sorted keys, then the translation
 // operators and expansion tables of order p (rebuilt when p changes)
-void build_lists(Context &ctx, FmmPlan &pl, const std::vector<uint32_t> &keys, const uint32_t *dkeys);
+// (returns false, having built nothing, when the automatic form picks the
+// adaptive tree for these points)
+bool build_lists(Context &ctx, FmmPlan &pl, const std::vector<uint32_t> &keys, const uint32_t *dkeys);
 // the adaptive tree (opt_tree 1): boxes split while they hold more than
 // leaf_size points, then 2:1 balanced; U, V, W and X lists
 void build_lists_adaptive(Context &ctx, FmmPlan &pl, const std::vector<uint32_t> &keys, const uint32_t *dkeys);

@@ -198,7 +198,7 @@ void boxes_from_codes(FmmPlan &pl, const std::vector<std::vector<uint32_t>> &cod
 void finish_tree(Context &ctx, FmmPlan &pl, const std::vector<double> &cx, const std::vector<double> &cy,
                  const uint32_t *dkeys);
 
-void build_lists(Context &ctx, FmmPlan &pl, const std::vector<uint32_t> &keys, const uint32_t *dkeys) {
+bool build_lists(Context &ctx, FmmPlan &pl, const std::vector<uint32_t> &keys, const uint32_t *dkeys) {
     const int64_t N = pl.N;
     // ---- merged Morton codes (each set's block is sorted) ----
     std::vector<uint32_t> merged = merged_codes(pl, keys);
@@ -257,6 +257,10 @@ void build_lists(Context &ctx, FmmPlan &pl, const std::vector<uint32_t> &keys, c
         const uint32_t v = merged[k] >> (2 * (kMaxLevel - L));
         if (codes[L].empty() || codes[L].back() != v) codes[L].push_back(v);
     }
+    // automatic form: points so clustered that the uniform tree's leaves are
+    // mostly near-empty (more than six times N / leaf_size of them; a uniform
+    // random set stays below four) take the adaptive tree instead
+    if (pl.opt_tree == 2 && (double)codes[L].size() > 6.0 * (double)N / (double)pl.opt_leaf) return false;
     for (int l = L - 1; l >= 0; --l) {
         codes[l].clear();
         for (uint32_t v : codes[l + 1])
@@ -284,6 +288,7 @@ void build_lists(Context &ctx, FmmPlan &pl, const std::vector<uint32_t> &keys, c
     gpu_ulists(ctx, pl, dleaf_codes);
     gpu_vlists(ctx, pl);
     finish_tree(ctx, pl, cx, cy, dkeys);
+    return true;
 }
 
 // The adaptive tree (Sec. 3.1's quad-tree refined box by box): a box is split

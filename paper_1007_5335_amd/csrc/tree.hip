@@ -280,8 +280,8 @@ void build_tree(Context &ctx, FmmPlan &pl, const SumProblem &pb) {
     YK_HIP(hipMemcpyAsync(hkeys.data(), keys, N * sizeof(uint32_t), hipMemcpyDeviceToHost, ctx.stream));
     YK_HIP(hipStreamSynchronize(ctx.stream));
     pl.adaptive = pl.opt_tree == 1;
+    if (!pl.adaptive && !build_lists(ctx, pl, hkeys, keys)) pl.adaptive = true;
     if (pl.adaptive) build_lists_adaptive(ctx, pl, hkeys, keys);
-    else build_lists(ctx, pl, hkeys, keys);
     build_tables(ctx, pl, pl.opt_p > 0 ? supported_order(pl.opt_p) : choose_order(pl.opt_tol));
     pl.build_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
 }

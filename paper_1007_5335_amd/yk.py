@@ -29,6 +29,7 @@ YK_PREC_FP32 = 2
 
 YK_TREE_UNIFORM = 0
 YK_TREE_ADAPTIVE = 1
+YK_TREE_AUTO = 2
 
 HEAT_GRID_SELF_CELL = 1
 HEAT_ZERO_GUESS = 2

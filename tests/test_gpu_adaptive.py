@@ -270,3 +270,34 @@ def test_adaptive_clustered_small_alpha_pass_vs_oracle(yk, oracle_lib):
               f"per-target relative errors {err}", flush=True)
         assert np.max(err) <= 1e-10, err
     assert infos[yk.YK_TREE_ADAPTIVE].n_leaves < infos[yk.YK_TREE_UNIFORM].n_leaves
+
+
+def test_automatic_tree_choice(yk, oracle_lib):
+    """Default options (automatic form): a dense cluster in a sparse background
+    would leave the uniform tree's leaves mostly near-empty, so the adaptive
+    tree is taken (and the pass meets 1e-10 per sampled target); uniform
+    random points keep the uniform tree."""
+    import torch
+    rng = np.random.default_rng(21)
+    n_c, n_b = 36000, 4000
+    vol = np.concatenate([0.4 + 1e-3 * rng.random((n_c, 2)), rng.random((n_b, 2))])
+    q = rng.uniform(0.5, 1.5, vol.shape[0])
+    idx = np.concatenate([rng.choice(n_c, 8, replace=False), n_c + rng.choice(n_b, 8, replace=False)])
+    ref = oracle_lib.volume_sum(vol, q, 0.01, tgt_xy=vol[idx])
+    forms = {}
+    for name, pts, qq in (("clustered", vol, q), ("uniform", rng.random((40000, 2)), q)):
+        ctx = _ctx(yk, tree=yk.YK_TREE_AUTO)
+        try:
+            out = torch.empty(pts.shape[0], dtype=torch.float64, device="cuda")
+            yk.yk_volume_potential(ctx, dev(pts), dev(qq), None, 0.01, out)
+            torch.cuda.synchronize()
+            info = yk.yk_plan_info_get(ctx, 2)
+        finally:
+            yk.yk_destroy(ctx)
+        forms[name] = info.tree
+        print(f"  {name}: tree {info.tree}, {info.n_leaves} leaves for {pts.shape[0]} points", flush=True)
+        if name == "clustered":
+            err = np.abs(host(out)[idx] - ref) / np.abs(ref)
+            print(f"  per-target relative errors {err}", flush=True)
+            assert err.max() <= 1e-10
+    assert forms == {"clustered": yk.YK_TREE_ADAPTIVE, "uniform": yk.YK_TREE_UNIFORM}

@@ -426,13 +426,15 @@ def test_clustered_small_alpha_pass_vs_oracle(yk, oracle_lib):
 def test_c4_full_size_pass_vs_oracle(yk, oracle_lib):
     """The large adaptive set at full size (about 2^24 adaptive cells refined by
     a mixture of 8 Gaussians, 20 holes x 8192 nodes, alpha = 1e-3): one FMM
-    pass at the default tolerance, sampled outputs against the oracle's direct
-    sums, each within 1e-10 relative to its own value."""
+    pass at the default tolerance (and the default, automatic tree form, which
+    takes the adaptive quad-tree here), sampled outputs against the oracle's
+    direct sums, each within 1e-10 relative to its own value."""
     c = W.config_c4()
     print("C4 full size", flush=True)
     ((info, err, l2),) = _c4_like_pass_vs_oracle(yk, oracle_lib, c, 2, 2, 41)
     print(f"  order {info.p_initial} -> {info.p}, order check {info.order_check_err:.2e}", flush=True)
-    assert info.n_leaves > 1_000_000
+    # the default (automatic) form takes the adaptive tree for this clustered set
+    assert info.tree == yk.YK_TREE_ADAPTIVE and info.n_leaves > 200_000 and info.n_wlist > 0
     assert np.max(err) <= 1e-10 and l2 <= 1e-10, err
 
 

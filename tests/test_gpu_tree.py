@@ -49,7 +49,7 @@ def test_tree_and_lists_match_reference(yk, case):
         c = W.small_fmm_case(n_vol=20000, n_nodes=512, alpha=0.02, seed=31, clustered=case != "uniform")
         alpha, leaf = 0.02, 16
     b = c["bnd"]
-    ctx = yk.yk_create(leaf_size=leaf, p=8, near_cache_mb=0)
+    ctx = yk.yk_create(leaf_size=leaf, p=8, near_cache_mb=0, tree=yk.YK_TREE_UNIFORM)
     try:
         print(f"tree {case}: {c['vol'].shape[0]} + {b.n} points", flush=True)
         if case == "clustered_targets":
