@@ -436,7 +436,7 @@ def large_step_bench(args, yk, torch, W):
     # one FMM pass over every point (volume charges a positive density times
     # the cell areas, unit-scale dipoles), tree already built
     tree = {"auto": yk.YK_TREE_AUTO, "uniform": yk.YK_TREE_UNIFORM, "adaptive": yk.YK_TREE_ADAPTIVE}[args.tree]
-    ctx = yk.yk_create(fmm_tol=1e-10, tree=tree)
+    ctx = yk.yk_create(fmm_tol=1e-10, tree=tree, leaf_size=args.large_leaf)
     try:
         rng = np.random.default_rng(5)
         q = d(rng.uniform(0.5, 1.5, volh.shape[0]) * c["vol_w"])
@@ -467,7 +467,7 @@ def large_step_bench(args, yk, torch, W):
             ("mixed_learned", yk.YK_PREC_MIXED, True))
     runs = tuple(r for r in runs if r[0] in args.large_runs.split(","))
     for name, prec, learned in runs:
-        ctx = yk.yk_create(fmm_tol=1e-10, precision=prec, tree=tree)
+        ctx = yk.yk_create(fmm_tol=1e-10, precision=prec, tree=tree, leaf_size=args.large_leaf)
         ws = None
         try:
             if learned:
@@ -556,6 +556,7 @@ def main():
     ap.add_argument("--tree", choices=("auto", "uniform", "adaptive"), default="auto",
                     help="quad-tree of the large-set runs (--large-steps; auto: adaptive for the "
                          "clustered volume set, uniform for the boundary)")
+    ap.add_argument("--large-leaf", type=int, default=64, help="leaf size of the large-set runs")
     ap.add_argument("--large-runs", default="fp64,fp64_learned,mixed_learned",
                     help="which of the large-set step runs to time (comma-separated)")
     ap.add_argument("--calib-copy", action="store_true",

@@ -62,7 +62,9 @@ typedef struct {
                                fmm_tol.  The order used is the smallest of 8, 12,
                                16, 20, 24, 28, 31 not below p (yk_plan_info.p);
                                p > 31 is rejected (YK_ERR_ARG) */
-    int leaf_size;          /* target mean number of points per leaf box */
+    int leaf_size;          /* target mean number of points per leaf box (the
+                               adaptive tree splits a box while it holds more
+                               than leaf_size / 2 points) */
     int direct;             /* 1 = all sums by O(N^2) direct summation */
     int gmres_m;            /* Krylov dimension before a restart */
     int debug_flags;        /* bit0: synchronise and check after every kernel;
@@ -97,7 +99,7 @@ typedef struct {
                                leaf at one level (the smallest level whose
                                point-weighted occupancy is <= leaf_size), U and
                                V lists.  ADAPTIVE: boxes split while they hold
-                               more than leaf_size points, then 2:1 balanced
+                               more than leaf_size / 2 points, then 2:1 balanced
                                (touching leaves differ by at most one level);
                                U, V, W (multipoles of finer boxes evaluated at a
                                leaf's points) and X (a coarser leaf's sources

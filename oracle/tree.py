@@ -21,7 +21,7 @@ build_adaptive() gives the adaptive form of Sec. 3.1's quad-tree (boxes
 refined box by box, childless boxes at any level) with the lists of the
 adaptive FMM:
 
-  * a box is split while it holds more than leaf_size points (level 15 at
+  * a box is split while it holds more than max_points points (level 15 at
     most); then, until nothing changes, a leaf is split when an existing box
     two levels finer touches it (2:1 balance: touching leaves differ by at
     most one level);
@@ -167,7 +167,7 @@ def _square_of(code, lev):
     return x0, y0, np.left_shift(np.int64(1), k)
 
 
-def build_adaptive(sets, square, leaf_size, alpha, far_cut=40.0):
+def build_adaptive(sets, square, max_points, alpha, far_cut=40.0):
     """The adaptive tree of the point sets; see the module docstring."""
     keys = keys_of(sets, square)
     n_set = [len(np.asarray(x).reshape(-1, 2)) for x in sets]
@@ -192,7 +192,7 @@ def build_adaptive(sets, square, leaf_size, alpha, far_cut=40.0):
         else:
             par = np.searchsorted(codes[lev - 1], codes[lev] >> np.uint64(2))
             exists = state[lev - 1][par] == SPLIT
-        split = (counts[lev] > leaf_size) & (lev < MAX_LEVEL)
+        split = (counts[lev] > max_points) & (lev < MAX_LEVEL)
         state.append(np.where(exists, np.where(split, SPLIT, LEAF), ABSENT).astype(np.int8))
 
     def exists_at(lev, jx, jy):

@@ -63,6 +63,8 @@ struct ActiveSet {
     DevBuf<int32_t> leaves;            // active leaves (leaf-local indices)
     int64_t n_leaves = 0;
     DevBuf<int2> leaf_items;           // {leaf, first target} work items of <= 64 targets
+    std::vector<int64_t> item_lev_begin;   // adaptive tree: items by class 2 level + (a coarser
+                                           // leaf touches it), 2 (L + 1) + 1 offsets
     int64_t n_items = 0;
     int64_t n_m2l_boxes = 0;
     // work counts (for measurement)
@@ -231,6 +233,8 @@ void gpu_point_leaves_adaptive(Context &ctx, FmmPlan &pl, const uint32_t *dkeys)
 void gpu_ulists_adaptive(Context &ctx, FmmPlan &pl);
 void gpu_wlists(Context &ctx, FmmPlan &pl, std::vector<int32_t> &woff, std::vector<int32_t> &wl);
 void build_tables(Context &ctx, FmmPlan &pl, int p);
+// terms of the near-field K0/K1 series for pairs with t = r^2/(4 alpha^2) <= tmax
+int near_series_terms(double tmax);
 ActiveSet &get_active(Context &ctx, FmmPlan &pl, int mask);
 void ensure_near_layout(Context &ctx, FmmPlan &pl, ActiveSet &as);
 // expansion orders with kernels: the smallest one >= p (at most kMaxOrder)

@@ -2398,7 +2398,14 @@ __global__ __launch_bounds__(256) void k_ad_l2p(
 LeafKernel pick_leaf_kernel(int nt, bool small_only, bool f32, bool adaptive) {
     if (adaptive) {
         if (f32) return small_only ? k_leaf<8, true, true, 16> : k_leaf<8, false, true, 16>;
-        return small_only ? k_leaf<14, true, false, 16> : k_leaf<14, false, false, 16>;
+        if (small_only) {
+            if (nt <= 5) return k_leaf<5, true, false, 16>;
+            if (nt <= 6) return k_leaf<6, true, false, 16>;
+            if (nt <= 8) return k_leaf<8, true, false, 16>;
+            if (nt <= 10) return k_leaf<10, true, false, 16>;
+            return k_leaf<14, true, false, 16>;
+        }
+        return k_leaf<14, false, false, 16>;
     }
     if (f32) return small_only ? k_leaf<8, true, true> : k_leaf<8, false, true>;
     if (small_only) {
@@ -2587,6 +2594,24 @@ void fmm_run(Context &ctx, FmmPlan &pl, const double *q, const double *dn, doubl
                                        as.item_doff.p, as.nq64.p, as.nd64.p, 0.5 * inv_alpha, outs);
                 }
                 check_launch(ctx, "k_near_apply");
+            } else if (pl.adaptive) {
+                // one launch per item class: a leaf of side s meets pairs with
+                // t = r^2/(4 alpha^2) <= 2 s^2/alpha^2 among leaves of its size
+                // or finer, 4.5 s^2/alpha^2 with a coarser one (at a corner);
+                // the fine levels take short series
+                StageTimer tl(ctx, YK_STAGE_LEAF, near_stream);
+                for (int k = 0; k < 2 * (L + 1); ++k) {
+                    const int64_t i0 = as.item_lev_begin[k], ni = as.item_lev_begin[k + 1] - i0;
+                    if (ni == 0) continue;
+                    const int l = k >> 1;
+                    const double tl_max = ((k & 1) ? 4.5 : 2.0) * pl.lev[l].side * pl.lev[l].side * inv_alpha *
+                                          inv_alpha;
+                    LeafKernel kern = pick_leaf_kernel(near_series_terms(tl_max), tl_max <= 1.0, f32, true);
+                    hipLaunchKernelGGL(kern, dim3((unsigned)ni), dim3(64), 0, near_stream, as.leaf_items.p + i0,
+                                       leaf_base, pl.lrange.p, pl.ulist_off.p, pl.ulist.p, pl.px.p, pl.py.p, qs,
+                                       dns, pl.toff[1], has_q, has_d, mask, 0.5 * inv_alpha, 0.5 * inv_alpha, outs);
+                    check_launch(ctx, "k_leaf");
+                }
             } else {
                 LeafKernel kern = pick_leaf_kernel(pl.near_terms, small_only, f32, pl.adaptive);
                 StageTimer tl(ctx, YK_STAGE_LEAF, near_stream);

@@ -198,6 +198,19 @@ void boxes_from_codes(FmmPlan &pl, const std::vector<std::vector<uint32_t>> &cod
 void finish_tree(Context &ctx, FmmPlan &pl, const std::vector<double> &cx, const std::vector<double> &cy,
                  const uint32_t *dkeys);
 
+int near_series_terms(double tmax) {
+    const double tt = std::min(1.0, tmax);
+    const double weight = 0.5 * std::fabs(std::log(tt)) + 3.0;
+    const double k0min = std::max(0.11, -0.5 * std::log(tt) - 0.58);
+    int k = 1;
+    double term = 1;
+    for (; k < YK_NSER64; ++k) {
+        term *= tt / ((double)k * (double)k);
+        if (term * weight < 0x1p-54 * k0min) break;
+    }
+    return std::min(YK_NSER64, k);
+}
+
 bool build_lists(Context &ctx, FmmPlan &pl, const std::vector<uint32_t> &keys, const uint32_t *dkeys) {
     const int64_t N = pl.N;
     // ---- merged Morton codes (each set's block is sorted) ----
@@ -292,14 +305,17 @@ bool build_lists(Context &ctx, FmmPlan &pl, const std::vector<uint32_t> &keys, c
 }
 
 // The adaptive tree (Sec. 3.1's quad-tree refined box by box): a box is split
-// while it holds more than leaf_size points (down to level 15); then, until
+// while it holds more than leaf_size / 2 points (down to level 15); then, until
 // nothing changes, a leaf touched by an existing box two levels finer is split
 // (2:1 balance, so that touching leaves differ by at most one level and a U
 // list holds at most 13 leaves).  Leaves are numbered in Morton order of their
 // first level-15 cell; the U and W lists are built on the GPU (lists.hip), X
 // is the transpose of W.
 void build_lists_adaptive(Context &ctx, FmmPlan &pl, const std::vector<uint32_t> &keys, const uint32_t *dkeys) {
-    const int64_t N = pl.N, s = pl.opt_leaf;
+    // split above half the leaf size: the leaves then hold about as many
+    // points on average as the uniform tree's (measured fastest on clustered
+    // sets: a split box's children hold a quarter of it each)
+    const int64_t N = pl.N, s = std::max(1, pl.opt_leaf / 2);
     std::vector<uint32_t> merged = merged_codes(pl, keys);
     // non-empty boxes of every level and their point counts
     std::vector<std::vector<uint32_t>> code(kMaxLevel + 1);
@@ -340,15 +356,26 @@ void build_lists_adaptive(Context &ctx, FmmPlan &pl, const std::vector<uint32_t>
             if (exists) st[l][k] = (cnt[l][k] > s && l < kMaxLevel) ? kSplitBox : kLeafBox;
         }
     }
-    auto find = [&](int l, uint32_t c) -> int64_t {
-        auto it = std::lower_bound(code[l].begin(), code[l].end(), c);
-        return (it != code[l].end() && *it == c) ? (int64_t)(it - code[l].begin()) : -1;
-    };
-    // 2:1 balance: the 20 cells two levels finer that ring a leaf touch it
+    // 2:1 balance: the 20 cells two levels finer that ring a leaf touch it.
+    // The ring is looked up among the boxes that exist at that level (far
+    // fewer than the non-empty cells there), gathered before each level's
+    // check: splits at this level and coarser ones create no boxes there.
+    std::vector<uint32_t> ex;
     for (bool changed = true; changed;) {
         changed = false;
         for (int l = 0; l + 2 <= kMaxLevel; ++l) {
             const int64_t nl = (int64_t)code[l].size();
+            bool any_leaf = false;
+            for (int8_t v : st[l])
+                if (v == kLeafBox) {
+                    any_leaf = true;
+                    break;
+                }
+            if (!any_leaf) continue;
+            ex.clear();
+            for (size_t k = 0; k < code[l + 2].size(); ++k)
+                if (st[l + 2][k] != kAbsent) ex.push_back(code[l + 2][k]);
+            if (ex.empty()) continue;
             std::vector<char> hit((size_t)nl, 0);
             const int64_t ns = (int64_t)1 << (l + 2);
             parallel_for(nl, [&](int64_t i0, int64_t i1) {
@@ -361,8 +388,7 @@ void build_lists_adaptive(Context &ctx, FmmPlan &pl, const std::vector<uint32_t>
                             if (i >= 0 && i <= 3 && j >= 0 && j <= 3) continue;
                             const int64_t X = 4 * (int64_t)bx + i, Y = 4 * (int64_t)by + j;
                             if (X < 0 || Y < 0 || X >= ns || Y >= ns) continue;
-                            const int64_t q = find(l + 2, encode((uint32_t)X, (uint32_t)Y));
-                            if (q >= 0 && st[l + 2][q] != kAbsent) {
+                            if (std::binary_search(ex.begin(), ex.end(), encode((uint32_t)X, (uint32_t)Y))) {
                                 hit[k] = 1;
                                 break;
                             }
@@ -692,19 +718,7 @@ void build_tables(Context &ctx, FmmPlan &pl, int p) {
     // weighted by the largest factor it meets ((1/2)|ln t| for A, about 3 for
     // the digamma weights of B and D), is below half an ulp of the smallest
     // K0 on the range (K0(z) > -(1/2) ln t - 0.58, and K0(2) > 0.11).
-    {
-        const double tmax = pl.near_tmax;
-        const double tt = std::min(1.0, tmax);
-        const double weight = 0.5 * std::fabs(std::log(tt)) + 3.0;
-        const double k0min = std::max(0.11, -0.5 * std::log(tt) - 0.58);
-        int k = 1;
-        double term = 1;
-        for (; k < YK_NSER64; ++k) {
-            term *= tt / ((double)k * (double)k);
-            if (term * weight < 0x1p-54 * k0min) break;
-        }
-        pl.near_terms = std::min(YK_NSER64, k);
-    }
+    pl.near_terms = near_series_terms(pl.near_tmax);
 
     const int nC = 2 * p + 1;
     std::vector<cld> C((size_t)(p + 1) * nC);
@@ -1000,6 +1014,26 @@ ActiveSet &get_active(Context &ctx, FmmPlan &pl, int mask) {
         as->h_sd = std::move(sd_leaf);
         as->h_uoff = std::move(uoff);
         as->h_ul = std::move(ul);
+    }
+    // adaptive tree: the items grouped (stably) by their leaf's level and by
+    // whether a coarser leaf touches it, class 2 l + coarser, so that each
+    // class's near field runs with the series its pair distances need
+    as->item_lev_begin.assign(2 * (L + 1) + 1, 0);
+    if (pl.adaptive) {
+        std::vector<std::vector<int2>> by(2 * (L + 1));
+        for (const int2 &it : items) {
+            const int l = pl.h_blevel[pl.h_leaf_box[it.x]];
+            int coarser = 0;
+            for (int32_t u = as->h_uoff[it.x]; u < as->h_uoff[it.x + 1]; ++u)
+                if (pl.h_blevel[pl.h_leaf_box[as->h_ul[u]]] < l) coarser = 1;
+            by[2 * l + coarser].push_back(it);
+        }
+        items.clear();
+        for (int k = 0; k < 2 * (L + 1); ++k) {
+            as->item_lev_begin[k] = (int64_t)items.size();
+            items.insert(items.end(), by[k].begin(), by[k].end());
+        }
+        as->item_lev_begin[2 * (L + 1)] = (int64_t)items.size();
     }
     as->h_items = items;
     as->h_tcnt.assign(pl.nleaf, 0);
