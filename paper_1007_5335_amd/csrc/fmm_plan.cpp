@@ -317,72 +317,68 @@ void build_lists_adaptive(Context &ctx, FmmPlan &pl, const std::vector<uint32_t>
     // sets: a split box's children hold a quarter of it each)
     const int64_t N = pl.N, s = std::max(1, pl.opt_leaf / 2);
     std::vector<uint32_t> merged = merged_codes(pl, keys);
-    // non-empty boxes of every level and their point counts
-    std::vector<std::vector<uint32_t>> code(kMaxLevel + 1);
-    std::vector<std::vector<int32_t>> cnt(kMaxLevel + 1);
-    for (int64_t k = 0; k < N; ++k) {
-        if (k == 0 || merged[k] != merged[k - 1]) {
-            code[kMaxLevel].push_back(merged[k]);
-            cnt[kMaxLevel].push_back(0);
-        }
-        cnt[kMaxLevel].back()++;
-    }
-    merged.clear();
-    merged.shrink_to_fit();
-    for (int l = kMaxLevel - 1; l >= 0; --l) {
-        const auto &c1 = code[l + 1];
-        const auto &n1 = cnt[l + 1];
-        for (size_t k = 0; k < c1.size(); ++k) {
-            const uint32_t v = c1[k] >> 2;
-            if (code[l].empty() || code[l].back() != v) {
-                code[l].push_back(v);
-                cnt[l].push_back(0);
+    // Boxes are built top down: a box of level l with code c holds the points
+    // whose level-15 codes lie in [c 4^(15-l), (c + 1) 4^(15-l)), a range of
+    // the sorted codes found by binary search; only boxes of the tree are
+    // ever formed.  Per level: codes (Morton order), point ranges, leaf flag.
+    struct Lev {
+        std::vector<uint32_t> code;
+        std::vector<int64_t> a, e;
+        std::vector<char> leaf;
+    };
+    std::vector<Lev> tl(kMaxLevel + 1);
+    auto lower = [&](uint64_t c) -> int64_t {
+        return (int64_t)(std::lower_bound(merged.begin(), merged.end(), (uint32_t)std::min<uint64_t>(c, 0xffffffffu)) -
+                         merged.begin());
+    };
+    // the non-empty children of box (l, c) with points [a, e), appended to level l + 1
+    auto children = [&](int l, uint32_t c, int64_t a, int64_t e, std::vector<uint32_t> &cc,
+                        std::vector<int64_t> &ca, std::vector<int64_t> &ce) {
+        const int sh = 2 * (kMaxLevel - l - 1);
+        int64_t lo = a;
+        for (uint32_t q = 0; q < 4; ++q) {
+            const uint32_t ch = (c << 2) | q;
+            const int64_t hi = q == 3 ? e : std::max(lo, std::min(e, lower((uint64_t)(ch + 1) << sh)));
+            if (hi > lo) {
+                cc.push_back(ch);
+                ca.push_back(lo);
+                ce.push_back(hi);
             }
-            cnt[l].back() += n1[k];
+            lo = hi;
         }
-    }
-    // state of every non-empty box: absent (inside a leaf), leaf or split
-    enum : int8_t { kAbsent = 0, kLeafBox = 1, kSplitBox = 2 };
-    std::vector<std::vector<int8_t>> st(kMaxLevel + 1);
+    };
+    tl[0].code = {0};
+    tl[0].a = {0};
+    tl[0].e = {N};
+    tl[0].leaf = {0};
     for (int l = 0; l <= kMaxLevel; ++l) {
-        st[l].assign(code[l].size(), kAbsent);
-        size_t pi = 0;
-        for (size_t k = 0; k < code[l].size(); ++k) {
-            bool exists = l == 0;
-            if (l > 0) {
-                while (code[l - 1][pi] != (code[l][k] >> 2)) ++pi;
-                exists = st[l - 1][pi] == kSplitBox;
+        Lev &L0 = tl[l];
+        L0.leaf.assign(L0.code.size(), 1);
+        if (l == kMaxLevel) break;
+        Lev &L1 = tl[l + 1];
+        for (size_t k = 0; k < L0.code.size(); ++k)
+            if (L0.e[k] - L0.a[k] > s) {
+                L0.leaf[k] = 0;
+                children(l, L0.code[k], L0.a[k], L0.e[k], L1.code, L1.a, L1.e);
             }
-            if (exists) st[l][k] = (cnt[l][k] > s && l < kMaxLevel) ? kSplitBox : kLeafBox;
-        }
+        if (L1.code.empty()) break;
     }
-    // 2:1 balance: the 20 cells two levels finer that ring a leaf touch it.
-    // The ring is looked up among the boxes that exist at that level (far
-    // fewer than the non-empty cells there), gathered before each level's
-    // check: splits at this level and coarser ones create no boxes there.
-    std::vector<uint32_t> ex;
+    // 2:1 balance: the 20 cells two levels finer that ring a leaf touch it;
+    // a leaf with a box of the tree among them is split (its children hold
+    // at most its points: leaves), until nothing changes
     for (bool changed = true; changed;) {
         changed = false;
         for (int l = 0; l + 2 <= kMaxLevel; ++l) {
-            const int64_t nl = (int64_t)code[l].size();
-            bool any_leaf = false;
-            for (int8_t v : st[l])
-                if (v == kLeafBox) {
-                    any_leaf = true;
-                    break;
-                }
-            if (!any_leaf) continue;
-            ex.clear();
-            for (size_t k = 0; k < code[l + 2].size(); ++k)
-                if (st[l + 2][k] != kAbsent) ex.push_back(code[l + 2][k]);
-            if (ex.empty()) continue;
+            const std::vector<uint32_t> &ex = tl[l + 2].code;
+            if (ex.empty() || tl[l].code.empty()) continue;
+            const int64_t nl = (int64_t)tl[l].code.size();
             std::vector<char> hit((size_t)nl, 0);
             const int64_t ns = (int64_t)1 << (l + 2);
             parallel_for(nl, [&](int64_t i0, int64_t i1) {
                 for (int64_t k = i0; k < i1; ++k) {
-                    if (st[l][k] != kLeafBox) continue;
+                    if (!tl[l].leaf[k]) continue;
                     uint32_t bx, by;
-                    decode(code[l][k], bx, by);
+                    decode(tl[l].code[k], bx, by);
                     for (int j = -1; j <= 4 && !hit[k]; ++j)
                         for (int i = -1; i <= 4; ++i) {
                             if (i >= 0 && i <= 3 && j >= 0 && j <= 3) continue;
@@ -395,37 +391,54 @@ void build_lists_adaptive(Context &ctx, FmmPlan &pl, const std::vector<uint32_t>
                         }
                 }
             });
+            std::vector<uint32_t> nc;
+            std::vector<int64_t> na, ne;
             for (int64_t k = 0; k < nl; ++k) {
                 if (!hit[k]) continue;
                 changed = true;
-                st[l][k] = kSplitBox;
-                // its children become leaves (they hold at most the parent's s points)
-                const uint32_t c0 = code[l][k] << 2;
-                auto it = std::lower_bound(code[l + 1].begin(), code[l + 1].end(), c0);
-                for (; it != code[l + 1].end() && (*it >> 2) == code[l][k]; ++it)
-                    st[l + 1][it - code[l + 1].begin()] = kLeafBox;
+                tl[l].leaf[k] = 0;
+                children(l, tl[l].code[k], tl[l].a[k], tl[l].e[k], nc, na, ne);
             }
+            if (nc.empty()) continue;
+            // merge the new leaves into the next level (both sorted)
+            Lev &L1 = tl[l + 1];
+            Lev m;
+            const size_t n1 = L1.code.size(), n2 = nc.size();
+            m.code.reserve(n1 + n2);
+            size_t x = 0, y = 0;
+            while (x < n1 || y < n2) {
+                if (y == n2 || (x < n1 && L1.code[x] < nc[y])) {
+                    m.code.push_back(L1.code[x]);
+                    m.a.push_back(L1.a[x]);
+                    m.e.push_back(L1.e[x]);
+                    m.leaf.push_back(L1.leaf[x]);
+                    ++x;
+                } else {
+                    m.code.push_back(nc[y]);
+                    m.a.push_back(na[y]);
+                    m.e.push_back(ne[y]);
+                    m.leaf.push_back(1);
+                    ++y;
+                }
+            }
+            L1 = std::move(m);
         }
     }
     int L = 0;
     for (int l = 0; l <= kMaxLevel; ++l)
-        for (int8_t v : st[l])
-            if (v != kAbsent) {
-                L = l;
-                break;
-            }
+        if (!tl[l].code.empty()) L = l;
     pl.L = L;
     std::vector<std::vector<uint32_t>> codes(L + 1);
     std::vector<std::vector<int8_t>> lst(L + 1);
-    for (int l = 0; l <= L; ++l)
-        for (size_t k = 0; k < code[l].size(); ++k)
-            if (st[l][k] != kAbsent) {
-                codes[l].push_back(code[l][k]);
-                lst[l].push_back(st[l][k]);
-            }
-    code.clear();
-    cnt.clear();
-    st.clear();
+    for (int l = 0; l <= L; ++l) {
+        codes[l] = std::move(tl[l].code);
+        lst[l].resize(codes[l].size());
+        for (size_t k = 0; k < codes[l].size(); ++k) lst[l][k] = tl[l].leaf[k] ? 1 : 2;
+    }
+    tl.clear();
+    merged.clear();
+    merged.shrink_to_fit();
+    enum : int8_t { kLeafBox = 1 };
     std::vector<double> cx, cy;
     boxes_from_codes(pl, codes, cx, cy);
     const int64_t nb = pl.nbox;
