@@ -1,0 +1,136 @@
+"""Box-code volume quadrature on a uniform grid -- TEST INFRASTRUCTURE ONLY.
+
+Only the tests may import this module; it shares no code with the GPU library.
+It follows Sec. 3.1 (eq. volume_potential and the leaf polynomials): the grid's
+cells are grouped into leaves of 4 x 4 cells; on each leaf the density is the
+least-squares cubic (ten monomials) through its 16 cell-centre values, and
+
+    V(x) = sum over leaves  int_leaf K0(|x - y| / alpha) / (2 pi) p_leaf(y) dy
+
+(the library's normalisation: U^p = V / alpha^2).  Each (target, leaf)
+integral is taken by quadrature: tensor Gauss-Legendre over the leaf when the
+target is at least a leaf side away; otherwise the leaf is written, by
+inclusion-exclusion, as signed rectangles with a corner at the target, each
+split at its diagonal into two triangles integrated in polar coordinates about
+the target (radius r = R s^2, Gauss-Legendre in s and in the angle), which
+takes the logarithmic singularity of K0 out.  U^p at a point of a leaf is its
+leaf polynomial fitted to the values of U^p at the leaf's cells.
+"""
+from __future__ import annotations
+
+import numpy as np
+from scipy.special import k0 as _k0
+
+NPOLAR = 48     # Gauss-Legendre points in s and in the angle, per triangle
+NTENSOR = 24    # per direction over a leaf (well separated targets)
+
+_gl_cache = {}
+
+
+def _gl(n):
+    if n not in _gl_cache:
+        _gl_cache[n] = np.polynomial.legendre.leggauss(n)
+    return _gl_cache[n]
+
+
+def monomials(u, v):
+    """The cubic basis 1, u, v, u^2, uv, v^2, u^3, u^2 v, u v^2, v^3 (last axis)."""
+    u = np.asarray(u, dtype=np.float64)
+    v = np.asarray(v, dtype=np.float64)
+    return np.stack([np.ones_like(u), u, v, u * u, u * v, v * v, u ** 3, u * u * v, u * v * v, v ** 3], -1)
+
+
+# the 16 cell centres of a leaf in its scaled coordinates (leaf = [-1, 1]^2)
+_OFFS = np.array([-0.75, -0.25, 0.25, 0.75])
+
+
+def fit(values, nx, ny):
+    """Per-leaf least-squares cubic coefficients [ny/4, nx/4, 10] of the cell
+    values (point j nx + i at cell (i, j))."""
+    vals = np.asarray(values, dtype=np.float64).reshape(ny, nx)
+    uu, vv = np.meshgrid(_OFFS, _OFFS, indexing="xy")      # [row j][col i]
+    Vm = monomials(uu.ravel(), vv.ravel())                  # 16 x 10, cell (i, j) at j*4 + i
+    blocks = vals.reshape(ny // 4, 4, nx // 4, 4).transpose(0, 2, 1, 3).reshape(ny // 4, nx // 4, 16)
+    coef, *_ = np.linalg.lstsq(Vm, blocks.reshape(-1, 16).T, rcond=None)
+    return coef.T.reshape(ny // 4, nx // 4, 10)
+
+
+def _corner_rect(tx, ty, X, Y, alpha, cx, cy, H):
+    """Signed integral of K0(r/alpha) m(y) over the rectangle with corners
+    (tx, ty) and (tx + X, ty + Y) (X, Y signed), m the ten monomials in the
+    leaf coordinates ((y - c) / H).  Returns [10]."""
+    if X == 0.0 or Y == 0.0:
+        return np.zeros(10)
+    sgn = np.sign(X) * np.sign(Y)
+    ax, ay = abs(X), abs(Y)
+    sx, sy = np.sign(X), np.sign(Y)
+    xs, ws = _gl(NPOLAR)
+    out = np.zeros(10)
+    # triangle 1: angle 0 .. atan(ay/ax) (bounded by x = ax); triangle 2: the rest (y = ay)
+    th_d = np.arctan2(ay, ax)
+    for lo, hi, edge in ((0.0, th_d, "x"), (th_d, np.pi / 2, "y")):
+        th = 0.5 * (hi - lo) * (xs + 1) + lo
+        wth = 0.5 * (hi - lo) * ws
+        R = ax / np.cos(th) if edge == "x" else ay / np.sin(th)
+        s = 0.5 * (xs + 1)
+        wsr = 0.5 * ws
+        # r = R s^2: dr = 2 R s ds
+        r = R[:, None] * s[None, :] ** 2
+        jac = 2.0 * R[:, None] * s[None, :]
+        px = tx + sx * r * np.cos(th)[:, None]
+        py = ty + sy * r * np.sin(th)[:, None]
+        m = monomials((px - cx) / H, (py - cy) / H)        # [nth, ns, 10]
+        f = _k0(r / alpha) * r * jac                        # [nth, ns]
+        out += np.einsum("a,b,ab,abk->k", wth, wsr, f, m)
+    return sgn * out
+
+
+def leaf_integrals(tx, ty, cx, cy, H, alpha):
+    """[10]: int over the leaf [cx - H, cx + H] x [cy - H, cy + H] of
+    K0(|t - y|/alpha) m_k((y - c)/H) dy (no 1/(2 pi))."""
+    dx = max(abs(tx - cx) - H, 0.0)
+    dy = max(abs(ty - cy) - H, 0.0)
+    if max(dx, dy) >= 2.0 * H:
+        xs, ws = _gl(NTENSOR)
+        gx, gy = cx + H * xs, cy + H * xs
+        X, Y = np.meshgrid(gx, gy, indexing="ij")
+        w = np.outer(ws, ws) * H * H
+        r = np.hypot(tx - X, ty - Y)
+        m = monomials((X - cx) / H, (Y - cy) / H)
+        return np.einsum("ab,ab,abk->k", w, _k0(r / alpha), m)
+    # inclusion-exclusion over the four corners of the leaf
+    x0, x1, y0, y1 = cx - H, cx + H, cy - H, cy + H
+    out = np.zeros(10)
+    for X, sxs in ((x1, 1.0), (x0, -1.0)):
+        for Y, sys_ in ((y1, 1.0), (y0, -1.0)):
+            out += sxs * sys_ * _corner_rect(tx, ty, X - tx, Y - ty, alpha, cx, cy, H)
+    return out
+
+
+def potential(values, grid, alpha, targets):
+    """V at the target points [m][2] of the piecewise-cubic density fitted to
+    the cell values (grid = (x0, y0, h, nx, ny))."""
+    x0, y0, h, nx, ny = grid
+    coef = fit(values, nx, ny)
+    H = 2.0 * h
+    out = np.zeros(len(targets))
+    for k, (tx, ty) in enumerate(np.asarray(targets, dtype=np.float64)):
+        acc = 0.0
+        for J in range(ny // 4):
+            for I in range(nx // 4):
+                cx, cy = x0 + (4 * I + 2) * h, y0 + (4 * J + 2) * h
+                acc += leaf_integrals(tx, ty, cx, cy, H, alpha) @ coef[J, I]
+        out[k] = acc / (2.0 * np.pi)
+    return out
+
+
+def leaf_eval(values, grid, pts):
+    """The leaf polynomial (fitted to the cell values) of the leaf holding each point."""
+    x0, y0, h, nx, ny = grid
+    coef = fit(values, nx, ny)
+    pts = np.asarray(pts, dtype=np.float64).reshape(-1, 2)
+    I = np.clip(np.floor((pts[:, 0] - x0) / (4 * h)).astype(int), 0, nx // 4 - 1)
+    J = np.clip(np.floor((pts[:, 1] - y0) / (4 * h)).astype(int), 0, ny // 4 - 1)
+    cx, cy = x0 + (4 * I + 2) * h, y0 + (4 * J + 2) * h
+    m = monomials((pts[:, 0] - cx) / (2 * h), (pts[:, 1] - cy) / (2 * h))
+    return np.einsum("nk,nk->n", m, coef[J, I])
