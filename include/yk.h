@@ -261,10 +261,12 @@ yk_status yk_heat_step(yk_ctx ctx, const yk_boundary *bnd, int64_t n_vol, const 
  *   g        = f_next - U^p on the nodes;  sigma solves A sigma = -2 alpha^2 g
  *   u_next   = U^p + DL[w sigma] / alpha^2 at the cell centres, with the
  *            near-boundary evaluation of yk_heat_step (off with flags bit2)
- * flags bit1: zero initial guess.  sigma_io, u_next, stats as for
- * yk_heat_step (stats->ms[1] is the U^p stage).  Outside the domain u_next is
- * not meaningful.  YK_ERR_ARG when a node's interpolation stencil leaves the
- * grid.
+ * flags bit1: zero initial guess.  flags bit3: the box code instead
+ * (yk_box_potential: U^p = V / alpha^2 of the leaves' cubic fits of B at the
+ * cells, and on the nodes the leaf polynomials fitted to those values; grid
+ * sides multiples of 4 cells).  sigma_io, u_next, stats as for yk_heat_step
+ * (stats->ms[1] is the U^p stage).  Outside the domain u_next is not
+ * meaningful.  YK_ERR_ARG when a node's interpolation stencil leaves the grid.
  */
 typedef struct {
     double x0, y0;      /* lower-left corner of the gridded square */
@@ -275,6 +277,27 @@ typedef struct {
 yk_status yk_heat_step_grid(yk_ctx ctx, const yk_boundary *bnd, const yk_grid *grid, const double *B, int flags,
                             const double *f_next, double alpha2, double tol, double *sigma_io, double *u_next,
                             yk_stats *stats);
+
+/*
+ * The box code of Sec. 3.1 (eq. volume_potential and the leaf polynomials) on
+ * a uniform grid whose sides are multiples of 4 cells: the cells form leaves
+ * of 4 x 4; on each leaf B is replaced by its least-squares cubic (ten
+ * monomials in the leaf's coordinates) through the 16 cell values, and
+ *   V(x) = sum over leaves int_leaf K0(|x - y|/alpha)/(2 pi) cubic(y) dy
+ * (the sums' normalisation: U^p = V / alpha^2) is evaluated at every cell --
+ * the near field (a leaf and its 3 x 3 neighbours) from tables of the
+ * monomials' integrals, the rest by the FMM with the leaves' polynomial
+ * multipoles (tables per (h, alpha), built on the first call).
+ *   grid      the cells (as for yk_heat_step_grid)
+ *   B         [nx ny] device, cell values
+ *   V         [nx ny] device, out
+ *   pts       [n_pts][2] device (optional): points inside the grid; pts_vals
+ *             [n_pts] device receives there the leaf polynomial fitted to V
+ *             (the polynomials C^i_j of Sec. 3.1)
+ * YK_ERR_ARG for sides that are not multiples of 4 (or above 2^17 cells).
+ */
+yk_status yk_box_potential(yk_ctx ctx, const yk_grid *grid, const double *B, double alpha, double *V,
+                           int64_t n_pts, const double *pts, double *pts_vals);
 
 /*
  * Introspection: number of volume points the last step evaluated with the

@@ -512,6 +512,7 @@ yk_status yk_invalidate_geometry(yk_ctx ctx) {
         c.plan_nearc.reset();
         c.near.reset();
         c.cell_nodes.reset();
+        c.box.reset();
         c.grid_nx = c.grid_ny = 0;
         c.grid_bnd_gen = 0;
         c.self_w = nullptr;
@@ -912,9 +913,6 @@ yk_status yk_heat_step_grid(yk_ctx ctx, const yk_boundary *bnd, const yk_grid *g
         const double *gxy = grid_points(c, *grid);
         grid_check_nodes(c, bd, *grid);
         auto t0 = std::chrono::steady_clock::now();
-        // U^p = (V[h^2 B] + B (C_cell + kappa h^2)) / alpha^2 at the cell centres
-        double *q = c.ws_q.ensure(n);
-        launch_axpby(c, n, h * h, B, 0.0, nullptr, q);
         SumProblem pb;
         pb.n[0] = n;
         pb.xy[0] = gxy;
@@ -923,23 +921,35 @@ yk_status yk_heat_step_grid(yk_ctx ctx, const yk_boundary *bnd, const yk_grid *g
         pb.normal = bd.normal;
         pb.alpha = alpha;
         double *up = c.grid_up.ensure(n);
-        {
-            double *outs[3] = {up, nullptr, nullptr};
-            evaluate_sums(c, SLOT_VOL, pb, q, nullptr, outs, vprec);
-        }
-        if (c.grid_w0_key[0] != h * h || c.grid_w0_key[1] != alpha || !c.grid_w0.p) {
-            double *dh2 = c.grid_w0.ensure(2);
-            const double hh = h * h;
-            YK_HIP(hipMemcpyAsync(dh2 + 1, &hh, sizeof(double), hipMemcpyHostToDevice, c.stream));
-            launch_self_weights(c, 1, dh2 + 1, alpha, dh2);
-            YK_HIP(hipStreamSynchronize(c.stream));
-            c.grid_w0_key[0] = hh;
-            c.grid_w0_key[1] = alpha;
-        }
-        launch_self_cell(c, n, nullptr, c.grid_w0.p, B, 1.0 / a2, up);
-        // U^p on the nodes by bicubic interpolation; b = -2 alpha^2 (f - U^p), g = f - U^p
         double *vb = c.ws_e.ensure(nb);
-        launch_bicubic(c, nb, bd.xy, grid->x0, grid->y0, h, grid->nx, grid->ny, up, vb);
+        if (flags & 8) {
+            // box code: U^p = V[cubic leaf fits of B] / alpha^2 at the cells,
+            // and on the nodes the leaf polynomials fitted to those values
+            box_potential(c, *grid, B, alpha, up);
+            launch_axpby(c, n, 1.0 / a2, up, 0.0, nullptr, up);
+            box_leaf_eval(c, *grid, up, nb, bd.xy, vb);
+        } else {
+            // U^p = (V[h^2 B] + B (C_cell + kappa h^2)) / alpha^2 at the cell centres
+            double *q = c.ws_q.ensure(n);
+            launch_axpby(c, n, h * h, B, 0.0, nullptr, q);
+            {
+                double *outs[3] = {up, nullptr, nullptr};
+                evaluate_sums(c, SLOT_VOL, pb, q, nullptr, outs, vprec);
+            }
+            if (c.grid_w0_key[0] != h * h || c.grid_w0_key[1] != alpha || !c.grid_w0.p) {
+                double *dh2 = c.grid_w0.ensure(2);
+                const double hh = h * h;
+                YK_HIP(hipMemcpyAsync(dh2 + 1, &hh, sizeof(double), hipMemcpyHostToDevice, c.stream));
+                launch_self_weights(c, 1, dh2 + 1, alpha, dh2);
+                YK_HIP(hipStreamSynchronize(c.stream));
+                c.grid_w0_key[0] = hh;
+                c.grid_w0_key[1] = alpha;
+            }
+            launch_self_cell(c, n, nullptr, c.grid_w0.p, B, 1.0 / a2, up);
+            // U^p on the nodes by bicubic interpolation
+            launch_bicubic(c, nb, bd.xy, grid->x0, grid->y0, h, grid->nx, grid->ny, up, vb);
+        }
+        // b = -2 alpha^2 (f - U^p), g = f - U^p
         double *b = c.ws_f.ensure(nb);
         launch_axpby(c, nb, -2.0 * a2, f_next, 2.0 * a2, vb, b);
         double *gN = c.ws_g.ensure(nb);
@@ -975,6 +985,25 @@ yk_status yk_heat_step_grid(yk_ctx ctx, const yk_boundary *bnd, const yk_grid *g
             c.last_error = "GMRES did not reach the tolerance";
             return YK_ERR_NOCONV;
         }
+        return YK_OK;
+    });
+}
+
+yk_status yk_box_potential(yk_ctx ctx, const yk_grid *grid, const double *B, double alpha, double *V,
+                           int64_t n_pts, const double *pts, double *pts_vals) {
+    return guarded(ctx, [&](Context &c) {
+        YK_REQUIRE(grid && B && V, "invalid box-code arguments");
+        YK_REQUIRE(std::isfinite(grid->x0) && std::isfinite(grid->y0) && std::isfinite(grid->h) && grid->h > 0.0,
+                   "invalid grid origin or cell size");
+        YK_REQUIRE(grid->nx >= 4 && grid->ny >= 4 && grid->nx % 4 == 0 && grid->ny % 4 == 0 &&
+                       grid->nx <= ((int64_t)1 << 17) && grid->ny <= ((int64_t)1 << 17) &&
+                       grid->nx * grid->ny < ((int64_t)1 << 31),
+                   "grid sides must be multiples of 4 cells, 4 .. 2^17");
+        YK_REQUIRE(std::isfinite(alpha) && alpha > 0.0, "alpha must be finite and > 0");
+        YK_REQUIRE(n_pts >= 0 && (n_pts == 0 || (pts && pts_vals)), "invalid evaluation points");
+        box_potential(c, *grid, B, alpha, V);
+        if (n_pts > 0) box_leaf_eval(c, *grid, V, n_pts, pts, pts_vals);
+        YK_HIP(hipStreamSynchronize(c.stream));
         return YK_OK;
     });
 }

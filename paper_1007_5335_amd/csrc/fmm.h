@@ -235,6 +235,12 @@ void gpu_wlists(Context &ctx, FmmPlan &pl, std::vector<int32_t> &woff, std::vect
 void build_tables(Context &ctx, FmmPlan &pl, int p);
 // terms of the near-field K0/K1 series for pairs with t = r^2/(4 alpha^2) <= tmax
 int near_series_terms(double tmax);
+// I_0(x) .. I_nmax(x) in extended precision
+std::vector<long double> bessel_i_seq(long double x, int nmax);
+// the stages between the leaf multipoles and the leaf local expansions
+void fmm_m2m(Context &ctx, FmmPlan &pl);
+void fmm_m2l(Context &ctx, FmmPlan &pl, ActiveSet &as, bool f32);
+void fmm_l2l(Context &ctx, FmmPlan &pl, ActiveSet &as, bool f32);
 ActiveSet &get_active(Context &ctx, FmmPlan &pl, int mask);
 void ensure_near_layout(Context &ctx, FmmPlan &pl, ActiveSet &as);
 // expansion orders with kernels: the smallest one >= p (at most kMaxOrder)

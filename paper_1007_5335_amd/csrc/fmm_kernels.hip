@@ -2431,6 +2431,103 @@ int m2l_persist_grid(Context &ctx) {
     return 3 * cus;
 }
 
+// M2M over levels L-1 .. lmin: each parent box from its children (the
+// adaptive tree's split boxes only: a leaf keeps its own multipole)
+void fmm_m2m(Context &ctx, FmmPlan &pl) {
+    const int L = pl.L, P = pl.P, Pp = pl.Pp;
+    {
+        StageTimer tmm(ctx, YK_STAGE_M2M);
+        for (int l = L - 1; l >= pl.lmin; --l) {
+            const int64_t nbl = pl.lev[l].end - pl.lev[l].begin;
+            if (pl.adaptive) {
+                // the split boxes only (a leaf keeps its P2M multipole)
+                if (pl.up_n[l] <= kSmallLevelM2M)
+                    launch_small_gemv(ctx, Pp, 4, pl.up_n[l], pl.up_boxes.p + pl.up_off[l], 0, pl.child4.p,
+                                      pl.bcode.p, pl.m2m.p + (size_t)l * 4 * Pp * Pp, pl.M.p, P, 1, pl.M.p);
+                else
+                    launch_tile_gemm<double, double>(ctx, P, Pp, pl.up_tile_count[l], pl.up_tiles.p,
+                                                     pl.up_tile_begin[l], pl.up_boxes.p, 4, pl.child4.p,
+                                                     pl.iota4.p, pl.m2m.p, (int64_t)4 * Pp * Pp, 0, pl.M.p,
+                                                     1, pl.M.p);
+            } else if (nbl <= kSmallLevelM2M) {
+                launch_small_gemv(ctx, Pp, 4, nbl, nullptr, pl.lev[l].begin, pl.child4.p, pl.bcode.p,
+                                  pl.m2m.p + (size_t)l * 4 * Pp * Pp, pl.M.p, P, 1, pl.M.p);
+            } else {
+                // M2M on matrix cores: 4 child slots, operators S[l][position]
+                launch_tile_gemm<double, double>(ctx, P, Pp, pl.up_tile_count[l], pl.up_tiles.p,
+                                                 pl.up_tile_begin[l], pl.up_boxes.p, 4, pl.child4.p,
+                                                 pl.iota4.p, pl.m2m.p, (int64_t)4 * Pp * Pp, 0, pl.M.p,
+                                                 1, pl.M.p);
+            }
+        }
+    }
+}
+
+// M2L of every level at once into the zeroed local expansions
+void fmm_m2l(Context &ctx, FmmPlan &pl, ActiveSet &as, bool f32) {
+    const int P = pl.P, Pp = pl.Pp;
+    {
+        // M2L of every level at once (levels are independent given the multipoles)
+        StageTimer tl(ctx, YK_STAGE_M2L);
+        // (FP32: 128-box tiles, two column blocks per wavefront, so each
+        // operator fragment feeds two matrix-core steps)
+        SlabPlan slab;
+        slab.buf = &as.m2l_slab;
+        slab.ntgt = as.n_csr_tgt;
+        slab.tgt = as.csr_tgt.p;
+        slab.off = as.csr_off.p;
+        slab.rows = as.csr_rows.p;
+        if (as.m2l_sparse && f32)
+            launch_tile_gemm<float, float>(ctx, P, Pp, as.n_ptiles, as.m2l_ptiles.p, 0, as.m2l_piota.p,
+                                           1, as.m2l_psrc.p, pl.iota40.p, pl.m2lf.p,
+                                           (int64_t)kNumOff * Pp * Pp, 0, pl.Mf.p, 0, pl.Lc.p,
+                                           as.m2l_ptgt.p, &slab, as.n_ptrans);
+        else if (as.m2l_sparse)
+            launch_tile_gemm<double, double>(ctx, P, Pp, as.n_ptiles, as.m2l_ptiles.p, 0,
+                                             as.m2l_piota.p, 1, as.m2l_psrc.p, pl.iota40.p, pl.m2l.p,
+                                             (int64_t)kNumOff * Pp * Pp, 0, pl.M.p, 0, pl.Lc.p,
+                                             as.m2l_ptgt.p, &slab, as.n_ptrans);
+        else if (f32)
+            launch_tile_gemm<float, float, 2>(ctx, P, Pp, as.n_tiles_w, as.m2l_tiles_w.p, 0,
+                                              as.m2l_boxes.p, kNumV, pl.vlist.p, pl.slot_oid.p,
+                                              pl.m2lf.p, (int64_t)kNumOff * Pp * Pp, 0, pl.Mf.p, 0,
+                                              pl.Lc.p, nullptr, &slab);
+        else if (Pp == 64 && P == 63 && as.n_tiles >= m2l_persist_grid(ctx)) {
+            hipLaunchKernelGGL(k_m2l_persist, dim3(m2l_persist_grid(ctx)), dim3(256), 0, ctx.stream,
+                               as.m2l_tiles.p, as.n_tiles, as.m2l_boxes.p, pl.vlist.p, pl.slot_oid.p,
+                               pl.m2l.p, (int64_t)kNumOff * Pp * Pp, pl.M.p, pl.Lc.p);
+            check_launch(ctx, "k_m2l_persist");
+        } else
+            launch_tile_gemm<double, double, 1>(ctx, P, Pp, as.n_tiles, as.m2l_tiles.p, 0,
+                                                as.m2l_boxes.p, kNumV, pl.vlist.p, pl.slot_oid.p, pl.m2l.p,
+                                                (int64_t)kNumOff * Pp * Pp, 0, pl.M.p, 0, pl.Lc.p, nullptr,
+                                                &slab);
+    }
+}
+
+// L2L top-down over levels lmin+1 .. L (each box pulls its parent's expansion)
+void fmm_l2l(Context &ctx, FmmPlan &pl, ActiveSet &as, bool f32) {
+    const int L = pl.L, P = pl.P, Pp = pl.Pp;
+    StageTimer tl2(ctx, YK_STAGE_L2L);
+    for (int l = pl.lmin + 1; l <= L; ++l) {
+        // L2L top-down: one parent slot, operator E[l-1][position]
+        if (as.l2l_count[l] <= kSmallLevelL2L) {
+            launch_small_gemv(ctx, Pp, 1, as.l2l_count[l], as.l2l_boxes.p + as.l2l_begin[l], 0,
+                              pl.bparent.p, pl.bcode.p, pl.l2l.p + (size_t)(l - 1) * 4 * Pp * Pp,
+                              pl.Lc.p, P, 0, pl.Lc.p);
+        } else if (f32)
+            launch_tile_gemm<float, double>(ctx, P, Pp, as.tile_count[l], as.m2l_tiles.p,
+                                            as.tile_begin[l], as.m2l_boxes.p, 1, pl.bparent.p,
+                                            pl.iota4.p, pl.l2lf.p, (int64_t)4 * Pp * Pp, -1, pl.Lc.p,
+                                            0, pl.Lc.p);
+        else
+            launch_tile_gemm<double, double>(ctx, P, Pp, as.tile_count[l], as.m2l_tiles.p,
+                                             as.tile_begin[l], as.m2l_boxes.p, 1, pl.bparent.p,
+                                             pl.iota4.p, pl.l2l.p, (int64_t)4 * Pp * Pp, -1, pl.Lc.p,
+                                             0, pl.Lc.p);
+    }
+}
+
 void fmm_run(Context &ctx, FmmPlan &pl, const double *q, const double *dn, double *const out[3],
              SumPrec prec, const BieFuse *bie, int keep_charge_m, int parts) {
     int mask = 0;
@@ -2740,32 +2837,7 @@ void fmm_run(Context &ctx, FmmPlan &pl, const double *q, const double *dn, doubl
         }
         }
         launch_near();
-        {
-            StageTimer tmm(ctx, YK_STAGE_M2M);
-            for (int l = L - 1; l >= pl.lmin; --l) {
-                const int64_t nbl = pl.lev[l].end - pl.lev[l].begin;
-                if (pl.adaptive) {
-                    // the split boxes only (a leaf keeps its P2M multipole)
-                    if (pl.up_n[l] <= kSmallLevelM2M)
-                        launch_small_gemv(ctx, Pp, 4, pl.up_n[l], pl.up_boxes.p + pl.up_off[l], 0, pl.child4.p,
-                                          pl.bcode.p, pl.m2m.p + (size_t)l * 4 * Pp * Pp, pl.M.p, P, 1, pl.M.p);
-                    else
-                        launch_tile_gemm<double, double>(ctx, P, Pp, pl.up_tile_count[l], pl.up_tiles.p,
-                                                         pl.up_tile_begin[l], pl.up_boxes.p, 4, pl.child4.p,
-                                                         pl.iota4.p, pl.m2m.p, (int64_t)4 * Pp * Pp, 0, pl.M.p,
-                                                         1, pl.M.p);
-                } else if (nbl <= kSmallLevelM2M) {
-                    launch_small_gemv(ctx, Pp, 4, nbl, nullptr, pl.lev[l].begin, pl.child4.p, pl.bcode.p,
-                                      pl.m2m.p + (size_t)l * 4 * Pp * Pp, pl.M.p, P, 1, pl.M.p);
-                } else {
-                    // M2M on matrix cores: 4 child slots, operators S[l][position]
-                    launch_tile_gemm<double, double>(ctx, P, Pp, pl.up_tile_count[l], pl.up_tiles.p,
-                                                     pl.up_tile_begin[l], pl.up_boxes.p, 4, pl.child4.p,
-                                                     pl.iota4.p, pl.m2m.p, (int64_t)4 * Pp * Pp, 0, pl.M.p,
-                                                     1, pl.M.p);
-                }
-            }
-        }
+        fmm_m2m(ctx, pl);
         const bool f32 = prec == SUM_FP32;
         if (f32) {
             const int64_t nm = pl.nbox * (int64_t)Pp;
@@ -2777,43 +2849,7 @@ void fmm_run(Context &ctx, FmmPlan &pl, const double *q, const double *dn, doubl
         // a fill kernel rather than a memset node: this pass may be captured in a graph
         if (!lc_clear) launch_fill(ctx, (int64_t)pl.nbox * Pp, 0.0, pl.Lc.p);
         {
-            {
-                // M2L of every level at once (levels are independent given the multipoles)
-                StageTimer tl(ctx, YK_STAGE_M2L);
-                // (FP32: 128-box tiles, two column blocks per wavefront, so each
-                // operator fragment feeds two matrix-core steps)
-                SlabPlan slab;
-                slab.buf = &as.m2l_slab;
-                slab.ntgt = as.n_csr_tgt;
-                slab.tgt = as.csr_tgt.p;
-                slab.off = as.csr_off.p;
-                slab.rows = as.csr_rows.p;
-                if (as.m2l_sparse && f32)
-                    launch_tile_gemm<float, float>(ctx, P, Pp, as.n_ptiles, as.m2l_ptiles.p, 0, as.m2l_piota.p,
-                                                   1, as.m2l_psrc.p, pl.iota40.p, pl.m2lf.p,
-                                                   (int64_t)kNumOff * Pp * Pp, 0, pl.Mf.p, 0, pl.Lc.p,
-                                                   as.m2l_ptgt.p, &slab, as.n_ptrans);
-                else if (as.m2l_sparse)
-                    launch_tile_gemm<double, double>(ctx, P, Pp, as.n_ptiles, as.m2l_ptiles.p, 0,
-                                                     as.m2l_piota.p, 1, as.m2l_psrc.p, pl.iota40.p, pl.m2l.p,
-                                                     (int64_t)kNumOff * Pp * Pp, 0, pl.M.p, 0, pl.Lc.p,
-                                                     as.m2l_ptgt.p, &slab, as.n_ptrans);
-                else if (f32)
-                    launch_tile_gemm<float, float, 2>(ctx, P, Pp, as.n_tiles_w, as.m2l_tiles_w.p, 0,
-                                                      as.m2l_boxes.p, kNumV, pl.vlist.p, pl.slot_oid.p,
-                                                      pl.m2lf.p, (int64_t)kNumOff * Pp * Pp, 0, pl.Mf.p, 0,
-                                                      pl.Lc.p, nullptr, &slab);
-                else if (Pp == 64 && P == 63 && as.n_tiles >= m2l_persist_grid(ctx)) {
-                    hipLaunchKernelGGL(k_m2l_persist, dim3(m2l_persist_grid(ctx)), dim3(256), 0, ctx.stream,
-                                       as.m2l_tiles.p, as.n_tiles, as.m2l_boxes.p, pl.vlist.p, pl.slot_oid.p,
-                                       pl.m2l.p, (int64_t)kNumOff * Pp * Pp, pl.M.p, pl.Lc.p);
-                    check_launch(ctx, "k_m2l_persist");
-                } else
-                    launch_tile_gemm<double, double, 1>(ctx, P, Pp, as.n_tiles, as.m2l_tiles.p, 0,
-                                                        as.m2l_boxes.p, kNumV, pl.vlist.p, pl.slot_oid.p, pl.m2l.p,
-                                                        (int64_t)kNumOff * Pp * Pp, 0, pl.M.p, 0, pl.Lc.p, nullptr,
-                                                        &slab);
-            }
+            fmm_m2l(ctx, pl, as, f32);
             if (pl.adaptive && pl.n_xbox > 0) {
                 // X lists: coarser leaves' sources straight into the local
                 // expansions (before L2L passes them down)
@@ -2824,24 +2860,7 @@ void fmm_run(Context &ctx, FmmPlan &pl, const double *q, const double *dn, doubl
                                    pl.py.p, qs, dns, pl.toff[1], pl.rI.p, p, Pp, inv_alpha, pl.Lc.p);
                 check_launch(ctx, "k_ad_p2l");
             }
-            StageTimer tl2(ctx, YK_STAGE_L2L);
-            for (int l = pl.lmin + 1; l <= L; ++l) {
-                // L2L top-down: one parent slot, operator E[l-1][position]
-                if (as.l2l_count[l] <= kSmallLevelL2L) {
-                    launch_small_gemv(ctx, Pp, 1, as.l2l_count[l], as.l2l_boxes.p + as.l2l_begin[l], 0,
-                                      pl.bparent.p, pl.bcode.p, pl.l2l.p + (size_t)(l - 1) * 4 * Pp * Pp,
-                                      pl.Lc.p, P, 0, pl.Lc.p);
-                } else if (f32)
-                    launch_tile_gemm<float, double>(ctx, P, Pp, as.tile_count[l], as.m2l_tiles.p,
-                                                    as.tile_begin[l], as.m2l_boxes.p, 1, pl.bparent.p,
-                                                    pl.iota4.p, pl.l2lf.p, (int64_t)4 * Pp * Pp, -1, pl.Lc.p,
-                                                    0, pl.Lc.p);
-                else
-                    launch_tile_gemm<double, double>(ctx, P, Pp, as.tile_count[l], as.m2l_tiles.p,
-                                                     as.tile_begin[l], as.m2l_boxes.p, 1, pl.bparent.p,
-                                                     pl.iota4.p, pl.l2l.p, (int64_t)4 * Pp * Pp, -1, pl.Lc.p,
-                                                     0, pl.Lc.p);
-            }
+            fmm_l2l(ctx, pl, as, f32);
         }
     }
     if (!near_done) launch_near();

@@ -198,6 +198,8 @@ void boxes_from_codes(FmmPlan &pl, const std::vector<std::vector<uint32_t>> &cod
 void finish_tree(Context &ctx, FmmPlan &pl, const std::vector<double> &cx, const std::vector<double> &cy,
                  const uint32_t *dkeys);
 
+std::vector<long double> bessel_i_seq(long double x, int nmax) { return I_seq(x, nmax); }
+
 int near_series_terms(double tmax) {
     const double tt = std::min(1.0, tmax);
     const double weight = 0.5 * std::fabs(std::log(tt)) + 3.0;

@@ -34,6 +34,9 @@ struct SumProblem {
     // multipoles and add only the dipoles' (both are hints: a pass that
     // cannot use them computes everything)
     int keep_charge_m = 0;
+    // FMM backend: a fixed bounding square {x0, y0, side} for the tree (null:
+    // the points' bounding square); every point must lie inside it
+    const double *square = nullptr;
 };
 
 enum PlanSlot { SLOT_VOL = 0, SLOT_BND = 1, SLOT_MISC = 2, SLOT_NEAR = 3, SLOT_NEARC = 4 };

@@ -247,12 +247,21 @@ void build_tree(Context &ctx, FmmPlan &pl, const SumProblem &pb) {
     }
     YK_REQUIRE(std::isfinite(mn[0]) && std::isfinite(mn[1]) && std::isfinite(mx[0]) && std::isfinite(mx[1]),
                "point coordinates are not finite");
-    double ext = std::fmax(mx[0] - mn[0], mx[1] - mn[1]);
-    if (ext <= 0) ext = 1e-6 * std::fmax(1.0, std::fabs(mn[0]) + std::fabs(mn[1]));
-    pl.size = ext * (1.0 + 1e-9);
-    const double cxm = 0.5 * (mn[0] + mx[0]), cym = 0.5 * (mn[1] + mx[1]);
-    pl.x0 = cxm - 0.5 * pl.size;
-    pl.y0 = cym - 0.5 * pl.size;
+    if (pb.square) {
+        YK_REQUIRE(pb.square[2] > 0.0 && mn[0] >= pb.square[0] && mn[1] >= pb.square[1] &&
+                       mx[0] < pb.square[0] + pb.square[2] && mx[1] < pb.square[1] + pb.square[2],
+                   "points outside the given bounding square");
+        pl.x0 = pb.square[0];
+        pl.y0 = pb.square[1];
+        pl.size = pb.square[2];
+    } else {
+        double ext = std::fmax(mx[0] - mn[0], mx[1] - mn[1]);
+        if (ext <= 0) ext = 1e-6 * std::fmax(1.0, std::fabs(mn[0]) + std::fabs(mn[1]));
+        pl.size = ext * (1.0 + 1e-9);
+        const double cxm = 0.5 * (mn[0] + mx[0]), cym = 0.5 * (mn[1] + mx[1]);
+        pl.x0 = cxm - 0.5 * pl.size;
+        pl.y0 = cym - 0.5 * pl.size;
+    }
     const double inv_cell = (double)(1 << kMaxLevel) / pl.size;
 
     // keys

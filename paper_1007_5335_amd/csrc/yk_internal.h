@@ -125,6 +125,14 @@ struct CellNodePlanDeleter {
 };
 using CellNodePtr = std::unique_ptr<CellNodePlan, CellNodePlanDeleter>;
 
+// Box code on a uniform grid (box.hip): leaves of 4 x 4 cells, their cubic
+// fits, the near-field and expansion tables, and the tree over the leaves
+struct BoxPlan;
+struct BoxPlanDeleter {
+    void operator()(BoxPlan *p) const;
+};
+using BoxPtr = std::unique_ptr<BoxPlan, BoxPlanDeleter>;
+
 struct FmmPlan;   // tree + lists + operator tables (fmm.hip)
 void destroy_plan(FmmPlan *p);
 struct PlanDeleter {
@@ -162,6 +170,7 @@ struct Context {
     PlanPtr plan_nearc;                    // nodes -> near targets (coarse rule, subtracted)
     NearPtr near;                          // near-boundary targets of the last volume set
     CellNodePtr cell_nodes;                // cells next to the nodes (heat step, flags bit0)
+    BoxPtr box;                            // box code of the last grid and alpha
 
     // own-cell weights of yk_heat_step's cell centres (flags bit0): the
     // distinct cell areas of vol_w, an index per point, the weights for alpha
@@ -347,6 +356,11 @@ void launch_grid_points(Context &ctx, int64_t n, double x0, double y0, double h,
 // out_j = tensor cubic Lagrange interpolation of the cell-centre values V at xy_j
 void launch_bicubic(Context &ctx, int64_t n, const double *xy, double x0, double y0, double h, int64_t nx,
                     int64_t ny, const double *V, double *out);
+// box.hip: the box-code volume potential V (K0/(2 pi) normalisation, U^p =
+// V / alpha^2) at the cells of a grid whose sides are multiples of 4 cells, and
+// the leaf polynomials of cell values evaluated at points inside the grid
+void box_potential(Context &ctx, const yk_grid &g, const double *B, double alpha, double *V);
+void box_leaf_eval(Context &ctx, const yk_grid &g, const double *vals, int64_t n, const double *xy, double *out);
 
 // near-boundary evaluation (near.hip): the near targets of tgt_xy for the
 // boundary (built once per boundary and target array), and one step's

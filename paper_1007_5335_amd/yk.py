@@ -34,6 +34,7 @@ YK_TREE_AUTO = 2
 HEAT_GRID_SELF_CELL = 1
 HEAT_ZERO_GUESS = 2
 HEAT_NO_NEAR = 4
+HEAT_BOX_CODE = 8
 
 SCHEME_EULER = 0
 SCHEME_GEAR = 1
@@ -49,7 +50,7 @@ EXPORTS = (
     "yk_ws_predict", "yk_set_warm_start", "yk_ws_num_params", "yk_ws_get_params",
     "yk_ws_set_params", "yk_ws_loss_grad", "yk_ws_forward", "yk_ws_adam_step",
     "yk_gmres_density_noalloc", "yk_plan_tree_export", "yk_rhs_imex", "yk_heat_step_grid",
-    "yk_near_info", "yk_plan_adaptive_export",
+    "yk_near_info", "yk_plan_adaptive_export", "yk_box_potential",
 )
 
 STAGES = ("gather", "p2m", "m2m", "m2l", "l2l", "leaf", "scatter", "direct", "l2p", "near_build")
@@ -168,6 +169,7 @@ def load_library(path: str = LIB_PATH):
         "yk_gmres_density_noalloc": (ip, [vp, P(yk_boundary), dbl, vp, vp, dbl, ip, vp, P(yk_stats)]),
         "yk_plan_tree_export": (ip, [vp, ip, P(dbl), P(i64), vp, vp, vp, vp, vp, vp, vp, vp]),
         "yk_plan_adaptive_export": (ip, [vp, ip, vp, vp, vp, vp, vp, vp, vp]),
+        "yk_box_potential": (ip, [vp, P(yk_grid), vp, dbl, vp, i64, vp, vp]),
         "yk_rhs_imex": (ip, [vp, ip, ip, i64, vp, vp, vp, vp, vp, ip, P(dbl), dbl, vp]),
         "yk_heat_step_grid": (ip, [vp, P(yk_boundary), P(yk_grid), vp, ip, vp, dbl, dbl, vp, vp, P(yk_stats)]),
         "yk_near_info": (ip, [vp, P(i64), P(dbl)]),
@@ -373,6 +375,15 @@ def yk_heat_step_grid(ctx, bnd: Boundary, grid: yk_grid, B, flags, f_next, alpha
         return st
     _check(ctx, s, st)
     return st
+
+
+def yk_box_potential(ctx, grid: yk_grid, B, alpha, V, pts=None, pts_vals=None):
+    if B.shape[0] != grid.nx * grid.ny or V.shape[0] != grid.nx * grid.ny:
+        raise ValueError("B and V need one value per grid cell")
+    n = 0 if pts is None else int(pts.shape[0])
+    _check(ctx, load_library().yk_box_potential(ctx, ctypes.byref(grid), _dev(B, "B"), float(alpha), _dev(V, "V"),
+                                                n, _dev(pts, "pts") if n else None,
+                                                _dev(pts_vals, "pts_vals") if n else None))
 
 
 def yk_near_info(ctx):

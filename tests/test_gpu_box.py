@@ -1,0 +1,105 @@
+"""The box code (Sec. 3.1, eq. volume_potential and the leaf polynomials) on
+the GPU against the oracle's box code (oracle/box.py): the volume potential of
+the leaves' cubic fits at sampled cells, element by element, on grids whose
+leaf counts are and are not powers of two, with and without a far field; the
+leaf polynomials at points; and the grid heat step run with it."""
+import numpy as np
+import pytest
+
+import workloads as W
+from gpu_util import dev, elem_err, host
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def yk():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1007_5335_amd.yk as yk
+    yk.load_library()
+    return yk
+
+
+def _cells(grid):
+    x0, y0, h, nx, ny = grid
+    i, j = np.meshgrid(np.arange(nx), np.arange(ny), indexing="xy")
+    return np.stack([x0 + (i.ravel() + 0.5) * h, y0 + (j.ravel() + 0.5) * h], 1)
+
+
+@pytest.mark.parametrize("grid,alpha", [((0.0, 0.0, 1 / 32, 32, 32), 0.1),
+                                        ((0.0, 0.0, 1 / 32, 32, 32), 0.02),
+                                        ((-0.3, 0.2, 0.025, 40, 24), 0.05),
+                                        ((0.0, 0.0, 1 / 128, 128, 128), 0.01)])
+def test_box_potential_vs_oracle(yk, grid, alpha):
+    """Rough cell values (noise of 0.3 on a smooth field), so the leaf fits
+    carry large high-order terms.  Bound 2e-10 of the largest value: the far
+    field runs at the highest order (p = 31) with no order check, and at
+    alpha = 0.02 the leaves are 6.25 alpha wide (the expansions' scaled
+    radius is 4.4), where the translations' truncation reaches about 1e-10."""
+    import torch
+    from oracle import box as X
+    c = _cells(grid)
+    rng = np.random.default_rng(7)
+    B = np.cos(3 * c[:, 0] - c[:, 1]) + 0.3 * rng.standard_normal(len(c))   # rough: the fits differ from B
+    ctx = yk.yk_create()
+    try:
+        V = torch.empty(len(c), dtype=torch.float64, device="cuda")
+        print(f"box grid {grid}, alpha {alpha}", flush=True)
+        yk.yk_box_potential(ctx, yk.make_grid(grid[0], grid[1], grid[2], grid[3], grid[4]), dev(B), alpha, V)
+        torch.cuda.synchronize()
+    finally:
+        yk.yk_destroy(ctx)
+    got = host(V)
+    idx = np.unique(np.concatenate([rng.choice(len(c), 24, replace=False), [0, len(c) - 1, grid[3] - 1]]))
+    ref = X.potential(B, grid, alpha, c[idx])
+    err = elem_err(got[idx], ref)
+    print(f"  max err / max |ref| over {len(idx)} cells: {err:.2e}", flush=True)
+    assert err <= 2e-10
+
+
+def test_box_leaf_polynomials_vs_oracle(yk):
+    import torch
+    from oracle import box as X
+    grid = (-0.3, 0.2, 0.025, 40, 24)
+    c = _cells(grid)
+    rng = np.random.default_rng(3)
+    B = np.sin(2 * c[:, 0]) * np.exp(c[:, 1]) + 0.1 * rng.standard_normal(len(c))
+    pts = np.stack([grid[0] + rng.random(500) * 40 * 0.025, grid[1] + rng.random(500) * 24 * 0.025], 1)
+    ctx = yk.yk_create()
+    try:
+        V = torch.empty(len(c), dtype=torch.float64, device="cuda")
+        pv = torch.empty(len(pts), dtype=torch.float64, device="cuda")
+        yk.yk_box_potential(ctx, yk.make_grid(*grid), dev(B), 0.05, V, dev(pts), pv)
+        torch.cuda.synchronize()
+    finally:
+        yk.yk_destroy(ctx)
+    ref = X.leaf_eval(host(V), grid, pts)
+    assert elem_err(host(pv), ref) <= 1e-12
+
+
+def test_grid_step_box_code_closed_form(yk):
+    """u = sin(3x) sin(2y) + 1 by one step of the grid form with the box code:
+    every cell inside the annulus within 1e-6, like the lattice rule."""
+    import torch
+    b = W.make_boundary([W.circle((0.0, 0.0), 0.4, 1024), W.circle((0.0, 0.0), 0.1, 512, ccw=False)])
+    grid, pts = W.grid_box(-0.5, 0.5, 512)
+    uf = lambda p: np.sin(3 * p[:, 0]) * np.sin(2 * p[:, 1]) + 1.0
+    a2 = 1e-3
+    B = (1 + 13 * a2) * uf(pts) - 13 * a2
+    inside = b.region(pts) < 0
+    ctx = yk.yk_create()
+    errs = {}
+    try:
+        bd = yk.Boundary.from_workload(b)
+        for flags in (yk.HEAT_ZERO_GUESS, yk.HEAT_ZERO_GUESS | yk.HEAT_BOX_CODE):
+            sig = torch.zeros(b.n, dtype=torch.float64, device="cuda")
+            u = torch.empty(pts.shape[0], dtype=torch.float64, device="cuda")
+            yk.yk_heat_step_grid(ctx, bd, yk.make_grid(*grid), dev(B), flags, dev(uf(b.xy)), a2, 1e-12, sig, u)
+            errs[flags] = np.max(np.abs(host(u) - uf(pts))[inside])
+    finally:
+        yk.yk_destroy(ctx)
+    print(f"closed form: max error lattice {errs[yk.HEAT_ZERO_GUESS]:.2e}, "
+          f"box code {errs[yk.HEAT_ZERO_GUESS | yk.HEAT_BOX_CODE]:.2e}", flush=True)
+    assert errs[yk.HEAT_ZERO_GUESS | yk.HEAT_BOX_CODE] < 1e-6
