@@ -31,7 +31,9 @@ def _cells(grid):
 @pytest.mark.parametrize("grid,alpha", [((0.0, 0.0, 1 / 32, 32, 32), 0.1),
                                         ((0.0, 0.0, 1 / 32, 32, 32), 0.02),
                                         ((-0.3, 0.2, 0.025, 40, 24), 0.05),
-                                        ((0.0, 0.0, 1 / 128, 128, 128), 0.01)])
+                                        ((0.0, 0.0, 1 / 128, 128, 128), 0.01),
+                                        ((0.1, -0.2, 0.05, 4, 4), 0.03),
+                                        ((0.0, 0.0, 0.05, 8, 4), 0.2)])
 def test_box_potential_vs_oracle(yk, grid, alpha):
     """Rough cell values (noise of 0.3 on a smooth field), so the leaf fits
     carry large high-order terms.  Bound 2e-10 of the largest value: the far
@@ -52,7 +54,8 @@ def test_box_potential_vs_oracle(yk, grid, alpha):
     finally:
         yk.yk_destroy(ctx)
     got = host(V)
-    idx = np.unique(np.concatenate([rng.choice(len(c), 24, replace=False), [0, len(c) - 1, grid[3] - 1]]))
+    idx = np.unique(np.concatenate([rng.choice(len(c), min(24, len(c)), replace=False),
+                                    [0, len(c) - 1, grid[3] - 1]]))
     ref = X.potential(B, grid, alpha, c[idx])
     err = elem_err(got[idx], ref)
     print(f"  max err / max |ref| over {len(idx)} cells: {err:.2e}", flush=True)
@@ -103,3 +106,16 @@ def test_grid_step_box_code_closed_form(yk):
     print(f"closed form: max error lattice {errs[yk.HEAT_ZERO_GUESS]:.2e}, "
           f"box code {errs[yk.HEAT_ZERO_GUESS | yk.HEAT_BOX_CODE]:.2e}", flush=True)
     assert errs[yk.HEAT_ZERO_GUESS | yk.HEAT_BOX_CODE] < 1e-6
+
+
+def test_box_rejects_sides_not_multiple_of_four(yk):
+    import torch
+    ctx = yk.yk_create()
+    try:
+        B = torch.zeros(30, dtype=torch.float64, device="cuda")
+        V = torch.empty(30, dtype=torch.float64, device="cuda")
+        with pytest.raises(yk.YkError) as ei:
+            yk.yk_box_potential(ctx, yk.make_grid(0.0, 0.0, 0.1, 6, 5), B, 0.1, V)
+        assert ei.value.status == yk.YK_ERR_ARG
+    finally:
+        yk.yk_destroy(ctx)
