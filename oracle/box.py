@@ -134,3 +134,111 @@ def leaf_eval(values, grid, pts):
     cx, cy = x0 + (4 * I + 2) * h, y0 + (4 * J + 2) * h
     m = monomials((pts[:, 0] - cx) / (2 * h), (pts[:, 1] - cy) / (2 * h))
     return np.einsum("nk,nk->n", m, coef[J, I])
+
+
+# ---------------------------------------------------------------------------
+# Adaptive leaves: childless boxes of a quad-tree over the square
+# [x0, x0 + side]^2, leaf k at level l_k with integer position (ix_k, iy_k),
+# each with its own 4 x 4 cell-centred grid (Sec. 3.1)
+# ---------------------------------------------------------------------------
+def leaf_cells(levels, ix, iy, root):
+    """Cell centres [n_leaves * 16][2] (cell t = jj 4 + ii of leaf k at 16 k + t)."""
+    x0, y0, side = root
+    s = side / (2.0 ** np.asarray(levels, dtype=np.float64))
+    out = np.zeros((len(s), 16, 2))
+    for t in range(16):
+        out[:, t, 0] = x0 + (np.asarray(ix) + ((t & 3) + 0.5) / 4.0) * s
+        out[:, t, 1] = y0 + (np.asarray(iy) + ((t >> 2) + 0.5) / 4.0) * s
+    return out.reshape(-1, 2)
+
+
+def fit_cells(values16):
+    """Per-leaf least-squares cubic coefficients [n][10] of 16 cell values each."""
+    uu, vv = np.meshgrid(_OFFS, _OFFS, indexing="xy")
+    Vm = monomials(uu.ravel(), vv.ravel())
+    coef, *_ = np.linalg.lstsq(Vm, np.asarray(values16, dtype=np.float64).reshape(-1, 16).T, rcond=None)
+    return coef.T
+
+
+def potential_leaves(levels, ix, iy, root, values16, alpha, targets):
+    """V at the targets of the piecewise cubic fitted on every leaf."""
+    x0, y0, side = root
+    coef = fit_cells(values16)
+    s = side / (2.0 ** np.asarray(levels, dtype=np.float64))
+    cx = x0 + (np.asarray(ix) + 0.5) * s
+    cy = y0 + (np.asarray(iy) + 0.5) * s
+    out = np.zeros(len(targets))
+    for k, (tx, ty) in enumerate(np.asarray(targets, dtype=np.float64)):
+        acc = 0.0
+        for j in range(len(s)):
+            acc += leaf_integrals(tx, ty, cx[j], cy[j], 0.5 * s[j], alpha) @ coef[j]
+        out[k] = acc / (2.0 * np.pi)
+    return out
+
+
+def refine_flags(values16, values64, tol):
+    """Sec. 3.1's refinement test: a leaf is split when its cubic fitted to the
+    16 cell values misses the values at the 64 cell centres of its four
+    children (children's 4 x 4 grids, child q = qy 2 + qx, cell t) by more
+    than tol.  Returns the flags and the errors."""
+    coef = fit_cells(values16)
+    v64 = np.asarray(values64, dtype=np.float64).reshape(-1, 4, 16)
+    err = np.zeros(len(coef))
+    for q in range(4):
+        qx, qy = q & 1, q >> 1
+        for t in range(16):
+            # child cell centre in the parent's scaled coordinates [-1, 1]
+            u = -1.0 + (qx * 4 + (t & 3) + 0.5) / 4.0
+            v = -1.0 + (qy * 4 + (t >> 2) + 0.5) / 4.0
+            e = np.abs(monomials(u, v) @ coef.T - v64[:, q, t])
+            err = np.maximum(err, e)
+    return err > tol, err
+
+
+def balanced_leaves(root, centre, depth_max, depth_min=2):
+    """A 2:1 balanced leaf set refined towards a point (test input): levels
+    from depth_min to depth_max, finer closer to `centre`.  Returns levels,
+    ix, iy."""
+    x0, y0, side = root
+    cx, cy = centre
+    leaves = {}
+
+    def want(l, i, j):
+        s = side / 2 ** l
+        bx, by = x0 + (i + 0.5) * s, y0 + (j + 0.5) * s
+        d = max(abs(bx - cx), abs(by - cy))
+        return l < depth_min or (l < depth_max and d < 1.5 * s)
+
+    def build(l, i, j):
+        if want(l, i, j):
+            for q in range(4):
+                build(l + 1, 2 * i + (q & 1), 2 * j + (q >> 1))
+        else:
+            leaves[(l, i, j)] = True
+
+    build(0, 0, 0)
+    # 2:1 balance: split a leaf touched by a leaf two or more levels finer
+    changed = True
+    while changed:
+        changed = False
+        for (l, i, j) in list(leaves):
+            if (l, i, j) not in leaves:
+                continue
+            s = 1.0 / 2 ** l
+            hit = False
+            for (l2, i2, j2) in leaves:
+                if l2 < l + 2:
+                    continue
+                s2 = 1.0 / 2 ** l2
+                if (i2 * s2 <= (i + 1) * s and i * s <= (i2 + 1) * s2 and
+                        j2 * s2 <= (j + 1) * s and j * s <= (j2 + 1) * s2):
+                    hit = True
+                    break
+            if hit:
+                del leaves[(l, i, j)]
+                for q in range(4):
+                    leaves[(l + 1, 2 * i + (q & 1), 2 * j + (q >> 1))] = True
+                changed = True
+    keys = sorted(leaves)
+    return (np.array([k[0] for k in keys], dtype=np.int32), np.array([k[1] for k in keys], dtype=np.int32),
+            np.array([k[2] for k in keys], dtype=np.int32))

@@ -81,3 +81,48 @@ def test_plane_wave_fourth_order():
         errs.append(np.max(np.abs(got - exact) / exact))
     print("plane wave errors", errs)
     assert errs[1] < 5e-6 and 12 < errs[0] / errs[1] < 70
+
+
+def test_adaptive_leaves_integrate_a_cubic_like_the_uniform_grid():
+    """A global cubic is fitted exactly on every leaf, so any leaf set over the
+    square gives the same potential: adaptive leaves (levels 2-6, refined
+    towards a point) against the uniform 64 x 64 grid."""
+    root = (0.0, 0.0, 1.0)
+    lv, ix, iy = X.balanced_leaves(root, (0.3, 0.6), 6)
+    c = X.leaf_cells(lv, ix, iy, root)
+    t = np.array([[0.31, 0.61], [0.8, 0.2], [0.05, 0.93]])
+    va = X.potential_leaves(lv, ix, iy, root, _cubic(c[:, 0], c[:, 1]), 0.05, t)
+    g = (0.0, 0.0, 1 / 64, 64, 64)
+    cu = _cells(g)
+    vu = X.potential(_cubic(cu[:, 0], cu[:, 1]), g, 0.05, t)
+    assert np.max(np.abs(va - vu) / np.abs(vu)) < 1e-10
+
+
+def test_balanced_leaves_tile_the_square_two_to_one():
+    root = (0.0, 0.0, 1.0)
+    lv, ix, iy = X.balanced_leaves(root, (0.3, 0.6), 7)
+    s = 0.5 ** lv.astype(float)
+    assert abs(np.sum(s * s) - 1.0) < 1e-12
+    x0, y0 = ix * s, iy * s
+    for a in range(len(lv)):
+        touch = ((x0 <= x0[a] + s[a]) & (x0[a] <= x0 + s) & (y0 <= y0[a] + s[a]) & (y0[a] <= y0 + s))
+        assert np.all(np.abs(lv[touch] - lv[a]) <= 1)
+
+
+def test_refinement_test_is_fourth_order_and_exact_for_cubics():
+    root = (0.0, 0.0, 1.0)
+    q = lambda x, y: x ** 4 + 0.3 * y ** 4
+    errs = []
+    for l in (3, 4, 5):
+        n = 2 ** l
+        ix, iy = np.meshgrid(np.arange(n), np.arange(n), indexing="xy")
+        lv = np.full(n * n, l)
+        c16 = X.leaf_cells(lv, ix.ravel(), iy.ravel(), root)
+        c64 = X.leaf_cells(np.full(4 * n * n, l + 1),
+                           (2 * ix.ravel()[:, None] + np.array([0, 1, 0, 1])).ravel(),
+                           (2 * iy.ravel()[:, None] + np.array([0, 0, 1, 1])).ravel(), root)
+        f16, e16 = X.refine_flags(_cubic(c16[:, 0], c16[:, 1]), _cubic(c64[:, 0], c64[:, 1]), 1e-12)
+        assert not f16.any() and e16.max() < 1e-12
+        _, e = X.refine_flags(q(c16[:, 0], c16[:, 1]), q(c64[:, 0], c64[:, 1]), 0.0)
+        errs.append(e.max())
+    assert 14 < errs[0] / errs[1] < 18 and 14 < errs[1] / errs[2] < 18, errs
