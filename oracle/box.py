@@ -9,11 +9,13 @@ least-squares cubic (ten monomials) through its 16 cell-centre values, and
 
 (the library's normalisation: U^p = V / alpha^2).  Each (target, leaf)
 integral is taken by quadrature: tensor Gauss-Legendre over the leaf when the
-target is at least a leaf side away; otherwise the leaf is written, by
+target is at least a leaf side away (on sub-squares no wider than 4 alpha);
+otherwise the leaf is written, by
 inclusion-exclusion, as signed rectangles with a corner at the target, each
 split at its diagonal into two triangles integrated in polar coordinates about
 the target (radius r = R s^2, Gauss-Legendre in s and in the angle), which
-takes the logarithmic singularity of K0 out.  U^p at a point of a leaf is its
+takes the logarithmic singularity of K0 out.  K0 is dropped beyond 40 alpha
+(below 1e-18).  U^p at a point of a leaf is its
 leaf polynomial fitted to the values of U^p at the leaf's cells.
 """
 from __future__ import annotations
@@ -21,8 +23,9 @@ from __future__ import annotations
 import numpy as np
 from scipy.special import k0 as _k0
 
-NPOLAR = 48     # Gauss-Legendre points in s and in the angle, per triangle
-NTENSOR = 24    # per direction over a leaf (well separated targets)
+NPOLAR = 96     # Gauss-Legendre points in s and in the angle, per triangle
+NTENSOR = 16    # per direction over each sub-square of a leaf (well separated targets)
+CUT = 40.0      # K0(r/alpha) is taken as zero beyond r = CUT alpha (K0(40) < 1e-18)
 
 _gl_cache = {}
 
@@ -72,6 +75,7 @@ def _corner_rect(tx, ty, X, Y, alpha, cx, cy, H):
         th = 0.5 * (hi - lo) * (xs + 1) + lo
         wth = 0.5 * (hi - lo) * ws
         R = ax / np.cos(th) if edge == "x" else ay / np.sin(th)
+        R = np.minimum(R, CUT * alpha)   # the kernel is negligible beyond
         s = 0.5 * (xs + 1)
         wsr = 0.5 * ws
         # r = R s^2: dr = 2 R s ds
@@ -90,11 +94,17 @@ def leaf_integrals(tx, ty, cx, cy, H, alpha):
     K0(|t - y|/alpha) m_k((y - c)/H) dy (no 1/(2 pi))."""
     dx = max(abs(tx - cx) - H, 0.0)
     dy = max(abs(ty - cy) - H, 0.0)
+    if np.hypot(dx, dy) > CUT * alpha:
+        return np.zeros(10)
     if max(dx, dy) >= 2.0 * H:
+        # sub-squares no wider than 4 alpha (K0 varies on the scale alpha)
+        k = int(min(16, max(1, np.ceil(2.0 * H / (4.0 * alpha)))))
         xs, ws = _gl(NTENSOR)
-        gx, gy = cx + H * xs, cy + H * xs
+        e = -H + (2.0 * H / k) * (np.arange(k)[:, None] + 0.5 * (xs[None, :] + 1))   # [k][n] nodes
+        g = (np.outer(np.ones(k), ws) * (H / k)).ravel()
+        gx, gy = cx + e.ravel(), cy + e.ravel()
         X, Y = np.meshgrid(gx, gy, indexing="ij")
-        w = np.outer(ws, ws) * H * H
+        w = np.outer(g, g)
         r = np.hypot(tx - X, ty - Y)
         m = monomials((X - cx) / H, (Y - cy) / H)
         return np.einsum("ab,ab,abk->k", w, _k0(r / alpha), m)
