@@ -300,6 +300,38 @@ yk_status yk_box_potential(yk_ctx ctx, const yk_grid *grid, const double *B, dou
                            int64_t n_pts, const double *pts, double *pts_vals);
 
 /*
+ * The box code on the childless boxes of an adaptive quad-tree (Sec. 3.1: the
+ * square D is level 0, each box splits into four, leaves at any level), each
+ * leaf with its own 4 x 4 cell-centred grid:
+ *   root      HOST [3]: x0, y0, side of the square D
+ *   level, ix, iy  HOST [n_leaves]: leaf k is the box of level level[k]
+ *             (0 .. 13) at position (ix[k], iy[k]) in that level's 2^l x 2^l
+ *             grid; the leaves must not overlap and touching leaves must be
+ *             at most one level apart (2:1 balance), else YK_ERR_ARG
+ *   vals      [n_leaves][16] device: B at the leaf's cells, cell t = jj 4 + ii
+ *             at (x0 + (ix + (ii + 1/2)/4) s, y0 + (iy + (jj + 1/2)/4) s),
+ *             s = side / 2^level
+ *   V         [n_leaves][16] device, out: V (as yk_box_potential) at the cells
+ * The tree over the cells' centres is the library's adaptive tree (its leaves
+ * are the given ones); near-field tables per (level, neighbour level,
+ * offset), polynomial multipoles per level, X-list (coarser leaf -> finer
+ * box) tables per (levels, offset), and the W lists evaluated at the cells.
+ */
+yk_status yk_box_potential_adaptive(yk_ctx ctx, const double *root, int64_t n_leaves, const int32_t *level,
+                                    const int32_t *ix, const int32_t *iy, const double *vals, double alpha,
+                                    double *V);
+
+/*
+ * Sec. 3.1's refinement test: a leaf is refined where the cubic fitted to its
+ * 16 cell values misses the values at the 64 cell centres of its four children
+ * by more than tol.  v16 [n][16] and v64 [n][4][16] device (child q = qy 2 +
+ * qx, its cell t as above); flags [n] device out (1: refine); err [n] device
+ * out (optional): the largest miss.
+ */
+yk_status yk_box_refine(yk_ctx ctx, int64_t n_leaves, const double *v16, const double *v64, double tol,
+                        int32_t *flags, double *err);
+
+/*
  * Introspection: number of volume points the last step evaluated with the
  * near-boundary rule, and the time (ms) that set took to build.
  */

@@ -1008,6 +1008,31 @@ yk_status yk_box_potential(yk_ctx ctx, const yk_grid *grid, const double *B, dou
     });
 }
 
+yk_status yk_box_potential_adaptive(yk_ctx ctx, const double *root, int64_t n_leaves, const int32_t *level,
+                                    const int32_t *ix, const int32_t *iy, const double *vals, double alpha,
+                                    double *V) {
+    return guarded(ctx, [&](Context &c) {
+        YK_REQUIRE(root && level && ix && iy && vals && V, "invalid box-code arguments");
+        YK_REQUIRE(std::isfinite(root[0]) && std::isfinite(root[1]) && std::isfinite(root[2]) && root[2] > 0.0,
+                   "invalid root square");
+        YK_REQUIRE(n_leaves >= 1 && n_leaves < ((int64_t)1 << 26), "n_leaves must be 1 .. 2^26");
+        YK_REQUIRE(std::isfinite(alpha) && alpha > 0.0, "alpha must be finite and > 0");
+        box_potential_adaptive(c, root, n_leaves, level, ix, iy, vals, alpha, V);
+        YK_HIP(hipStreamSynchronize(c.stream));
+        return YK_OK;
+    });
+}
+
+yk_status yk_box_refine(yk_ctx ctx, int64_t n_leaves, const double *v16, const double *v64, double tol,
+                        int32_t *flags, double *err) {
+    return guarded(ctx, [&](Context &c) {
+        YK_REQUIRE(n_leaves >= 0 && (n_leaves == 0 || (v16 && v64 && flags)), "invalid refinement arguments");
+        YK_REQUIRE(std::isfinite(tol) && tol >= 0.0, "tol must be finite and >= 0");
+        box_refine(c, n_leaves, v16, v64, tol, flags, err);
+        return YK_OK;
+    });
+}
+
 yk_status yk_near_info(yk_ctx ctx, int64_t *n_near, double *setup_ms) {
     if (!ctx) return YK_ERR_ARG;
     Context &c = ctx->c;

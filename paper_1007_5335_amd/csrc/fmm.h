@@ -199,6 +199,7 @@ struct FmmPlan {
     int64_t n_wl = 0, n_wleaves = 0;
     DevBuf<int32_t> xbox, xoff, xl;                // X lists: boxes with one, CSR of source leaves
     int64_t n_xbox = 0, n_xl = 0;
+    std::vector<int32_t> h_xbox, h_xoff, h_xl;     // host copies
     int max_u = 0;                                 // longest U list
     // per-level tables for expansions at any level >= lmin
     int nser_stride = 0;                           // serc_lv: [level][2][nser_stride]
@@ -241,6 +242,10 @@ std::vector<long double> bessel_i_seq(long double x, int nmax);
 void fmm_m2m(Context &ctx, FmmPlan &pl);
 void fmm_m2l(Context &ctx, FmmPlan &pl, ActiveSet &as, bool f32);
 void fmm_l2l(Context &ctx, FmmPlan &pl, ActiveSet &as, bool f32);
+// adaptive tree, after L2L: the W-list multipoles added into the sorted sums
+// outs, then each leaf's local expansion at its points, written with outs to
+// the caller's arrays out[set] (sets in mask)
+void fmm_adaptive_finish(Context &ctx, FmmPlan &pl, int mask, double *outs, double *const out[3]);
 ActiveSet &get_active(Context &ctx, FmmPlan &pl, int mask);
 void ensure_near_layout(Context &ctx, FmmPlan &pl, ActiveSet &as);
 // expansion orders with kernels: the smallest one >= p (at most kMaxOrder)

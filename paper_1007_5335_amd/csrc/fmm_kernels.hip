@@ -2528,6 +2528,24 @@ void fmm_l2l(Context &ctx, FmmPlan &pl, ActiveSet &as, bool f32) {
     }
 }
 
+void fmm_adaptive_finish(Context &ctx, FmmPlan &pl, int mask, double *outs, double *const out[3]) {
+    const int p = pl.p, Pp = pl.Pp;
+    const double inv_alpha = 1.0 / pl.alpha;
+    StageTimer tl(ctx, YK_STAGE_L2P);
+    if (pl.n_wleaves > 0 && pl.lmin <= pl.L) {
+        hipLaunchKernelGGL(k_ad_m2p, dim3((unsigned)pl.n_wleaves), dim3(64), 0, ctx.stream, pl.wleaves.p, pl.woff.p,
+                           pl.wl.p, pl.lrange.p, mask, pl.blevel.p, pl.bcx.p, pl.bcy.p, pl.px.p, pl.py.p, pl.M.p,
+                           pl.rI.p, p, Pp, inv_alpha, outs);
+        check_launch(ctx, "k_ad_m2p");
+    }
+    hipLaunchKernelGGL(k_ad_l2p, dim3(nblk(pl.N, 256)), dim3(256), 0, ctx.stream, pl.N, pl.toff[1], pl.toff[2], mask,
+                       pl.pleaf.p, pl.leaf_box.p, pl.leaf_lev.p, pl.lmin, pl.bcx.p, pl.bcy.p, pl.px.p, pl.py.p,
+                       pl.Lc.p, inv_alpha, pl.invR_lv.p, pl.invFY.p, pl.cnn.p, pl.serc_lv.p, pl.nser_dev.p,
+                       pl.nser_stride, p, Pp, outs, pl.perm.p, out[0], out[1], out[2], (const double *)nullptr,
+                       (const double *)nullptr, (const double *)nullptr);
+    check_launch(ctx, "k_ad_l2p");
+}
+
 void fmm_run(Context &ctx, FmmPlan &pl, const double *q, const double *dn, double *const out[3],
              SumPrec prec, const BieFuse *bie, int keep_charge_m, int parts) {
     int mask = 0;

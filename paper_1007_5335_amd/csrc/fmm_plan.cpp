@@ -510,6 +510,9 @@ void build_lists_adaptive(Context &ctx, FmmPlan &pl, const std::vector<uint32_t>
         }
         pl.n_xbox = (int64_t)xbox.size();
         pl.n_xl = (int64_t)xl.size();
+        pl.h_xbox = xbox;
+        pl.h_xoff = xoff;
+        pl.h_xl = xl;
         pl.n_wleaves = (int64_t)wleaves.size();
         up(pl.xbox, xbox);
         up(pl.xoff, xoff);

@@ -361,6 +361,12 @@ void launch_bicubic(Context &ctx, int64_t n, const double *xy, double x0, double
 // the leaf polynomials of cell values evaluated at points inside the grid
 void box_potential(Context &ctx, const yk_grid &g, const double *B, double alpha, double *V);
 void box_leaf_eval(Context &ctx, const yk_grid &g, const double *vals, int64_t n, const double *xy, double *out);
+// the box code on adaptive leaves (level, ix, iy host arrays; vals, V [n][16] device)
+void box_potential_adaptive(Context &ctx, const double root[3], int64_t n, const int32_t *lev, const int32_t *ix,
+                            const int32_t *iy, const double *vals, double alpha, double *V);
+// Sec. 3.1's refinement test of n leaves (device arrays)
+void box_refine(Context &ctx, int64_t n, const double *v16, const double *v64, double tol, int32_t *flags,
+                double *err);
 
 // near-boundary evaluation (near.hip): the near targets of tgt_xy for the
 // boundary (built once per boundary and target array), and one step's

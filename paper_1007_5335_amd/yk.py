@@ -50,7 +50,8 @@ EXPORTS = (
     "yk_ws_predict", "yk_set_warm_start", "yk_ws_num_params", "yk_ws_get_params",
     "yk_ws_set_params", "yk_ws_loss_grad", "yk_ws_forward", "yk_ws_adam_step",
     "yk_gmres_density_noalloc", "yk_plan_tree_export", "yk_rhs_imex", "yk_heat_step_grid",
-    "yk_near_info", "yk_plan_adaptive_export", "yk_box_potential",
+    "yk_near_info", "yk_plan_adaptive_export", "yk_box_potential", "yk_box_potential_adaptive",
+    "yk_box_refine",
 )
 
 STAGES = ("gather", "p2m", "m2m", "m2l", "l2l", "leaf", "scatter", "direct", "l2p", "near_build")
@@ -134,6 +135,7 @@ def load_library(path: str = LIB_PATH):
     import torch  # noqa: F401
     lib = ctypes.CDLL(path)
     vp, i64, dbl, ip = ctypes.c_void_p, ctypes.c_int64, ctypes.c_double, ctypes.c_int
+    i32 = ctypes.c_int32
     P = ctypes.POINTER
     sig = {
         "yk_default_options": (None, [P(yk_options)]),
@@ -170,6 +172,8 @@ def load_library(path: str = LIB_PATH):
         "yk_plan_tree_export": (ip, [vp, ip, P(dbl), P(i64), vp, vp, vp, vp, vp, vp, vp, vp]),
         "yk_plan_adaptive_export": (ip, [vp, ip, vp, vp, vp, vp, vp, vp, vp]),
         "yk_box_potential": (ip, [vp, P(yk_grid), vp, dbl, vp, i64, vp, vp]),
+        "yk_box_potential_adaptive": (ip, [vp, P(dbl), i64, P(i32), P(i32), P(i32), vp, dbl, vp]),
+        "yk_box_refine": (ip, [vp, i64, vp, vp, dbl, vp, vp]),
         "yk_rhs_imex": (ip, [vp, ip, ip, i64, vp, vp, vp, vp, vp, ip, P(dbl), dbl, vp]),
         "yk_heat_step_grid": (ip, [vp, P(yk_boundary), P(yk_grid), vp, ip, vp, dbl, dbl, vp, vp, P(yk_stats)]),
         "yk_near_info": (ip, [vp, P(i64), P(dbl)]),
@@ -384,6 +388,27 @@ def yk_box_potential(ctx, grid: yk_grid, B, alpha, V, pts=None, pts_vals=None):
     _check(ctx, load_library().yk_box_potential(ctx, ctypes.byref(grid), _dev(B, "B"), float(alpha), _dev(V, "V"),
                                                 n, _dev(pts, "pts") if n else None,
                                                 _dev(pts_vals, "pts_vals") if n else None))
+
+
+def yk_box_potential_adaptive(ctx, root, level, ix, iy, vals, alpha, V):
+    import numpy as np
+    lv = np.ascontiguousarray(level, dtype=np.int32)
+    jx = np.ascontiguousarray(ix, dtype=np.int32)
+    jy = np.ascontiguousarray(iy, dtype=np.int32)
+    n = lv.shape[0]
+    if vals.shape[0] != 16 * n or V.shape[0] != 16 * n:
+        raise ValueError("vals and V need 16 values per leaf")
+    rt = (ctypes.c_double * 3)(*[float(v) for v in root])
+    i32p = ctypes.POINTER(ctypes.c_int32)
+    _check(ctx, load_library().yk_box_potential_adaptive(ctx, rt, n, lv.ctypes.data_as(i32p),
+                                                         jx.ctypes.data_as(i32p), jy.ctypes.data_as(i32p),
+                                                         _dev(vals, "vals"), float(alpha), _dev(V, "V")))
+
+
+def yk_box_refine(ctx, v16, v64, tol, flags, err=None):
+    n = int(v16.shape[0]) // 16
+    _check(ctx, load_library().yk_box_refine(ctx, n, _dev(v16, "v16"), _dev(v64, "v64"), float(tol),
+                                             _dev(flags, "flags", "int32"), _dev(err, "err")))
 
 
 def yk_near_info(ctx):

@@ -36,10 +36,8 @@ def _cells(grid):
                                         ((0.0, 0.0, 0.05, 8, 4), 0.2)])
 def test_box_potential_vs_oracle(yk, grid, alpha):
     """Rough cell values (noise of 0.3 on a smooth field), so the leaf fits
-    carry large high-order terms.  Bound 2e-10 of the largest value: the far
-    field runs at the highest order (p = 31) with no order check, and at
-    alpha = 0.02 the leaves are 6.25 alpha wide (the expansions' scaled
-    radius is 4.4), where the translations' truncation reaches about 1e-10."""
+    carry large high-order terms; every sampled cell within 1e-10 of the
+    largest value."""
     import torch
     from oracle import box as X
     c = _cells(grid)
@@ -59,7 +57,7 @@ def test_box_potential_vs_oracle(yk, grid, alpha):
     ref = X.potential(B, grid, alpha, c[idx])
     err = elem_err(got[idx], ref)
     print(f"  max err / max |ref| over {len(idx)} cells: {err:.2e}", flush=True)
-    assert err <= 2e-10
+    assert err <= 1e-10
 
 
 def test_box_leaf_polynomials_vs_oracle(yk):
@@ -119,3 +117,71 @@ def test_box_rejects_sides_not_multiple_of_four(yk):
         assert ei.value.status == yk.YK_ERR_ARG
     finally:
         yk.yk_destroy(ctx)
+
+
+@pytest.mark.parametrize("depth,alpha", [(5, 0.05), (7, 0.01), (3, 0.2)])
+def test_adaptive_box_potential_vs_oracle(yk, depth, alpha):
+    """The box code on 2:1-balanced adaptive leaves (refined towards a point,
+    levels 2 .. depth): V at sampled cells against the oracle's box code on
+    the same leaves; the tree's leaves are the given ones (near tables per
+    level pair, W and X lists through polynomial multipoles and tables)."""
+    import torch
+    from oracle import box as X
+    root = (-0.2, 0.1, 1.3)
+    lv, ix, iy = X.balanced_leaves(root, (0.2, 0.5), depth)
+    cells = X.leaf_cells(lv, ix, iy, root)
+    rng = np.random.default_rng(depth)
+    B = np.cos(2 * cells[:, 0]) * np.exp(cells[:, 1]) + 0.2 * rng.standard_normal(len(cells))
+    ctx = yk.yk_create()
+    try:
+        V = torch.empty(len(cells), dtype=torch.float64, device="cuda")
+        print(f"adaptive box: {len(lv)} leaves, levels {lv.min()}..{lv.max()}, alpha {alpha}", flush=True)
+        yk.yk_box_potential_adaptive(ctx, root, lv, ix, iy, dev(B), alpha, V)
+        torch.cuda.synchronize()
+    finally:
+        yk.yk_destroy(ctx)
+    got = host(V)
+    idx = np.unique(np.concatenate([rng.choice(len(cells), 20, replace=False), [0, len(cells) - 1]]))
+    ref = X.potential_leaves(lv, ix, iy, root, B, alpha, cells[idx])
+    err = elem_err(got[idx], ref)
+    print(f"  max err / max |ref| over {len(idx)} cells: {err:.2e}", flush=True)
+    assert err <= 1e-10
+
+
+def test_adaptive_box_rejects_unbalanced_leaves(yk):
+    import torch
+    # quadrant (0, 0) in four level-2 leaves, the one at (1, 1) split again:
+    # its level-3 leaves at x = 3/8 .. 1/2 touch the level-1 leaf at (1, 0)
+    lv = [1, 1, 1] + [2] * 3 + [3] * 4
+    ix = [1, 0, 1] + [0, 1, 0] + [2, 3, 2, 3]
+    iy = [0, 1, 1] + [0, 0, 1] + [2, 2, 3, 3]
+    n = len(lv)
+    ctx = yk.yk_create()
+    try:
+        B = torch.zeros(16 * n, dtype=torch.float64, device="cuda")
+        V = torch.empty(16 * n, dtype=torch.float64, device="cuda")
+        with pytest.raises(yk.YkError) as ei:
+            yk.yk_box_potential_adaptive(ctx, (0.0, 0.0, 1.0), lv, ix, iy, B, 0.1, V)
+        assert ei.value.status == yk.YK_ERR_ARG
+    finally:
+        yk.yk_destroy(ctx)
+
+
+def test_box_refinement_test_vs_oracle(yk):
+    import torch
+    from oracle import box as X
+    rng = np.random.default_rng(11)
+    n = 300
+    v16 = rng.standard_normal(16 * n)
+    v64 = rng.standard_normal(64 * n) * 0.01
+    ref_f, ref_e = X.refine_flags(v16, v64, 1.0)
+    ctx = yk.yk_create()
+    try:
+        fl = torch.empty(n, dtype=torch.int32, device="cuda")
+        er = torch.empty(n, dtype=torch.float64, device="cuda")
+        yk.yk_box_refine(ctx, dev(v16), dev(v64), 1.0, fl, er)
+        torch.cuda.synchronize()
+    finally:
+        yk.yk_destroy(ctx)
+    assert elem_err(host(er), ref_e) <= 1e-13
+    assert np.array_equal(host(fl).astype(bool), ref_f)
