@@ -332,6 +332,22 @@ yk_status yk_box_refine(yk_ctx ctx, int64_t n_leaves, const double *v16, const d
                         int32_t *flags, double *err);
 
 /*
+ * One step of (1 - alpha^2 Lap) u = B, u = f_next on the curves (eq.
+ * mod_helm_forced) on adaptive leaves (Sec. 3.1 with the box code): the
+ * volume points are the cells of the leaves of yk_box_potential_adaptive
+ * (root, level, ix, iy as there), B and u_next [n_leaves][16] device in its
+ * cell order.  U^p = V / alpha^2 of the leaves' cubic fits at the cells, on
+ * the nodes the leaf polynomials fitted to those values (every node inside a
+ * leaf); then as yk_heat_step_grid: sigma from A sigma = -2 alpha^2 (f_next -
+ * U^p), u_next = U^p + DL[w sigma] / alpha^2 with the near-boundary
+ * evaluation (off with flags bit2).  flags bit1: zero initial guess.
+ */
+yk_status yk_heat_step_leaves(yk_ctx ctx, const yk_boundary *bnd, const double *root, int64_t n_leaves,
+                              const int32_t *level, const int32_t *ix, const int32_t *iy, const double *B,
+                              int flags, const double *f_next, double alpha2, double tol, double *sigma_io,
+                              double *u_next, yk_stats *stats);
+
+/*
  * Introspection: number of volume points the last step evaluated with the
  * near-boundary rule, and the time (ms) that set took to build.
  */

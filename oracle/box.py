@@ -252,3 +252,43 @@ def balanced_leaves(root, centre, depth_max, depth_min=2):
     keys = sorted(leaves)
     return (np.array([k[0] for k in keys], dtype=np.int32), np.array([k[1] for k in keys], dtype=np.int32),
             np.array([k[2] for k in keys], dtype=np.int32))
+
+
+def balanced_leaves_by(root, want, depth_max):
+    """A 2:1 balanced leaf set (test input): a box (l, i, j) is split while
+    want(l, i, j) holds (up to depth_max), then leaves touched by leaves two
+    or more levels finer are split.  Returns levels, ix, iy."""
+    leaves = set()
+
+    def build(l, i, j):
+        if l < depth_max and want(l, i, j):
+            for q in range(4):
+                build(l + 1, 2 * i + (q & 1), 2 * j + (q >> 1))
+        else:
+            leaves.add((l, i, j))
+
+    build(0, 0, 0)
+    changed = True
+    while changed:
+        changed = False
+        by_level = {}
+        for (l, i, j) in leaves:
+            by_level.setdefault(l, set()).add((i, j))
+        for (l, i, j) in sorted(leaves):
+            hit = False
+            for l2 in range(l + 2, depth_max + 1):
+                f = 2 ** (l2 - l)
+                ring = [(i * f + a, j * f + b) for a in range(-1, f + 1) for b in range(-1, f + 1)
+                        if not (0 <= a < f and 0 <= b < f)]
+                if any(c in by_level.get(l2, ()) for c in ring):
+                    hit = True
+                    break
+            if hit:
+                leaves.discard((l, i, j))
+                for q in range(4):
+                    leaves.add((l + 1, 2 * i + (q & 1), 2 * j + (q >> 1)))
+                changed = True
+                break
+    keys = sorted(leaves)
+    return (np.array([k[0] for k in keys], dtype=np.int32), np.array([k[1] for k in keys], dtype=np.int32),
+            np.array([k[2] for k in keys], dtype=np.int32))

@@ -212,6 +212,20 @@ __global__ void k_boxa_p2l(const int32_t *__restrict__ xbox, const int32_t *__re
     Lc[(int64_t)xbox[b] * Pp + o] += s;
 }
 
+// the leaf polynomial (coefficients of leaf pleaf[i]) at scaled coordinates uv[i]
+__global__ void k_boxa_eval(int64_t n, const int32_t *__restrict__ pleaf, const double *__restrict__ uv,
+                            const double *__restrict__ coef, double *__restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double m[kNB];
+    monomials(uv[2 * i], uv[2 * i + 1], m);
+    const double *c = coef + (int64_t)pleaf[i] * kNB;
+    double s = 0.0;
+#pragma unroll
+    for (int k = 0; k < kNB; ++k) s = __builtin_fma(c[k], m[k], s);
+    out[i] = s;
+}
+
 // Sec. 3.1's refinement test: the cubic fitted to a leaf's 16 cell values
 // against the values at its children's 64 cell centres (child q = qy 2 + qx)
 __global__ void k_box_refine(int64_t n, const double *__restrict__ v16, const double *__restrict__ v64,
@@ -291,6 +305,13 @@ struct BoxPlan {
     std::vector<int32_t> lev, ix, iy;
     DevBuf<double> cells, qlv, near_tab, p2l_tab;
     DevBuf<int32_t> tin, u_tab, x_tab;
+    // points evaluated through the leaf polynomials (the boundary nodes):
+    // their leaf and their scaled coordinates in it, for one point array
+    const double *pts_key = nullptr;
+    int64_t pts_n = 0;
+    uint64_t pts_gen = 0;
+    DevBuf<int32_t> pts_leaf;
+    DevBuf<double> pts_uv;
 };
 
 void BoxPlanDeleter::operator()(BoxPlan *p) const { delete p; }
@@ -825,6 +846,65 @@ void box_potential_adaptive(Context &ctx, const double root[3], int64_t n, const
     }
     double *out3[3] = {V, nullptr, nullptr};
     fmm_adaptive_finish(ctx, pl, 1, outs, out3);
+}
+
+const double *box_cells(Context &ctx) {
+    YK_REQUIRE(ctx.box && ctx.box->adaptive, "no adaptive box plan");
+    return ctx.box->cells.p;
+}
+
+void box_leaves_eval(Context &ctx, const double *vals, int64_t n, const double *xy, uint64_t gen, double *out) {
+    YK_REQUIRE(ctx.box && ctx.box->adaptive, "the leaf polynomials need the adaptive box plan (the potential first)");
+    BoxPlan &bp = *ctx.box;
+    const int64_t nl = bp.nleaf;
+    if (bp.pts_key != xy || bp.pts_n != n || bp.pts_gen != gen || gen == 0) {
+        // each point's leaf: the level-l box holding it, looked up from the
+        // coarsest level down among the leaves
+        std::vector<double> hxy(2 * n);
+        if (n > 0)
+            YK_HIP(hipMemcpyAsync(hxy.data(), xy, 2 * n * sizeof(double), hipMemcpyDeviceToHost, ctx.stream));
+        YK_HIP(hipStreamSynchronize(ctx.stream));
+        std::map<std::array<int64_t, 3>, int32_t> where;
+        int lmax = 0;
+        for (int64_t k = 0; k < nl; ++k) {
+            where[{bp.lev[k], bp.ix[k], bp.iy[k]}] = (int32_t)k;
+            lmax = std::max(lmax, bp.lev[k]);
+        }
+        std::vector<int32_t> pl(n);
+        std::vector<double> uv(2 * n);
+        for (int64_t i = 0; i < n; ++i) {
+            const double x = (hxy[2 * i] - bp.square[0]) / bp.square[2], y = (hxy[2 * i + 1] - bp.square[1]) / bp.square[2];
+            YK_REQUIRE(x >= 0.0 && x < 1.0 && y >= 0.0 && y < 1.0, "a point lies outside the leaves' square");
+            int32_t found = -1;
+            for (int l = 0; l <= lmax && found < 0; ++l) {
+                const int64_t cx = (int64_t)std::floor(std::ldexp(x, l)), cy = (int64_t)std::floor(std::ldexp(y, l));
+                auto it = where.find({l, cx, cy});
+                if (it != where.end()) found = it->second;
+            }
+            YK_REQUIRE(found >= 0, "a point lies in no leaf");
+            pl[i] = found;
+            const double s = std::ldexp(1.0, -bp.lev[found]);
+            uv[2 * i] = (x - (bp.ix[found] + 0.5) * s) / (0.5 * s);
+            uv[2 * i + 1] = (y - (bp.iy[found] + 0.5) * s) / (0.5 * s);
+        }
+        YK_HIP(hipMemcpyAsync(bp.pts_leaf.ensure(std::max<int64_t>(n, 1)), pl.data(), n * sizeof(int32_t),
+                              hipMemcpyHostToDevice, ctx.stream));
+        YK_HIP(hipMemcpyAsync(bp.pts_uv.ensure(std::max<int64_t>(2 * n, 1)), uv.data(), 2 * n * sizeof(double),
+                              hipMemcpyHostToDevice, ctx.stream));
+        bp.pts_key = xy;
+        bp.pts_n = n;
+        bp.pts_gen = gen;
+    }
+    DevBuf<double> cbuf;
+    double *coef = cbuf.ensure(nl * kNB);
+    hipLaunchKernelGGL(k_boxa_fit, dim3(nblk(nl, 128)), dim3(128), 0, ctx.stream, nl, vals, bp.pinv.p, coef);
+    check_launch(ctx, "k_boxa_fit");
+    if (n > 0) {
+        hipLaunchKernelGGL(k_boxa_eval, dim3(nblk(n, 256)), dim3(256), 0, ctx.stream, n, bp.pts_leaf.p, bp.pts_uv.p,
+                           coef, out);
+        check_launch(ctx, "k_boxa_eval");
+    }
+    YK_HIP(hipStreamSynchronize(ctx.stream));
 }
 
 void box_refine(Context &ctx, int64_t n, const double *v16, const double *v64, double tol, int32_t *flags,

@@ -1008,6 +1008,77 @@ yk_status yk_box_potential(yk_ctx ctx, const yk_grid *grid, const double *B, dou
     });
 }
 
+yk_status yk_heat_step_leaves(yk_ctx ctx, const yk_boundary *bnd, const double *root, int64_t n_leaves,
+                              const int32_t *level, const int32_t *ix, const int32_t *iy, const double *B,
+                              int flags, const double *f_next, double alpha2, double tol, double *sigma_io,
+                              double *u_next, yk_stats *stats) {
+    return guarded(ctx, [&](Context &c) {
+        YK_REQUIRE(root && level && ix && iy && B && f_next && sigma_io && u_next, "invalid leaf-step arguments");
+        YK_REQUIRE(std::isfinite(root[0]) && std::isfinite(root[1]) && std::isfinite(root[2]) && root[2] > 0.0,
+                   "invalid root square");
+        YK_REQUIRE(n_leaves >= 1 && n_leaves < ((int64_t)1 << 26), "n_leaves must be 1 .. 2^26");
+        YK_REQUIRE(std::isfinite(alpha2) && alpha2 > 0.0, "alpha2 must be finite and > 0");
+        YK_REQUIRE(std::isfinite(tol) && tol >= 0.0, "tol must be finite and >= 0");
+        if (stats) std::memset(stats, 0, sizeof(*stats));
+        BoundaryData &bd = prepare_boundary(c, bnd);
+        check_warm(c, bd);
+        const int64_t n = 16 * n_leaves, nb = bd.n;
+        const double a2 = alpha2, alpha = std::sqrt(alpha2);
+        const SumPrec vprec = c.opt.precision == YK_PREC_FP32 ? SUM_FP32 : SUM_FP64;
+        auto t0 = std::chrono::steady_clock::now();
+        // U^p = V / alpha^2 at the cells (box code on the leaves), and on the
+        // nodes the leaf polynomials fitted to those values
+        double *up = c.grid_up.ensure(n);
+        box_potential_adaptive(c, root, n_leaves, level, ix, iy, B, alpha, up);
+        launch_axpby(c, n, 1.0 / a2, up, 0.0, nullptr, up);
+        const double *cells = box_cells(c);
+        double *vb = c.ws_e.ensure(nb);
+        box_leaves_eval(c, up, nb, bd.xy, bd.gen, vb);
+        double *b = c.ws_f.ensure(nb);
+        launch_axpby(c, nb, -2.0 * a2, f_next, 2.0 * a2, vb, b);
+        double *gN = c.ws_g.ensure(nb);
+        launch_axpby(c, nb, 1.0, f_next, -1.0, vb, gN);
+        if (stats) {
+            YK_HIP(hipStreamSynchronize(c.stream));
+            stats->ms[0] = fmm_last_build_ms(c);
+            stats->ms[1] = ms_since(t0);
+        }
+        int outer = 0, guess = 0;
+        GmresResult r = step_density(c, bd, alpha, b, gN, flags, tol, sigma_io, stats, outer, guess);
+        // u = U^p + DL[w sigma] / alpha^2 at the cells
+        auto t2 = std::chrono::steady_clock::now();
+        {
+            SumProblem pr;
+            pr.n[0] = n;
+            pr.xy[0] = cells;
+            pr.n[1] = nb;
+            pr.xy[1] = bd.xy;
+            pr.normal = bd.normal;
+            pr.alpha = alpha;
+            double *outs[3] = {u_next, nullptr, nullptr};
+            BieFuse f;
+            f.w = bd.w.p;
+            f.sigma = sigma_io;
+            f.normal = bd.normal;
+            pr.bie = &f;
+            evaluate_sums(c, SLOT_VOL, pr, nullptr, nullptr, outs, vprec);
+        }
+        launch_axpby(c, n, 1.0, up, 1.0 / a2, u_next, u_next);
+        if (!(flags & 4)) {
+            NearPlan &np = near_prepare(c, bd, n, cells);
+            near_apply(c, np, bd, alpha, sigma_io, gN, up, u_next);
+        }
+        YK_HIP(hipStreamSynchronize(c.stream));
+        if (stats) stats->ms[3] = ms_since(t2);
+        fill_stats(stats, r, outer, guess);
+        if (!r.converged) {
+            c.last_error = "GMRES did not reach the tolerance";
+            return YK_ERR_NOCONV;
+        }
+        return YK_OK;
+    });
+}
+
 yk_status yk_box_potential_adaptive(yk_ctx ctx, const double *root, int64_t n_leaves, const int32_t *level,
                                     const int32_t *ix, const int32_t *iy, const double *vals, double alpha,
                                     double *V) {

@@ -364,6 +364,11 @@ void box_leaf_eval(Context &ctx, const yk_grid &g, const double *vals, int64_t n
 // the box code on adaptive leaves (level, ix, iy host arrays; vals, V [n][16] device)
 void box_potential_adaptive(Context &ctx, const double root[3], int64_t n, const int32_t *lev, const int32_t *ix,
                             const int32_t *iy, const double *vals, double alpha, double *V);
+// the adaptive box plan's cell centres [n_leaves * 16][2] (device)
+const double *box_cells(Context &ctx);
+// the leaf polynomials fitted to vals [n_leaves][16] at n points xy (device),
+// the points' leaves cached for (xy, n, gen)
+void box_leaves_eval(Context &ctx, const double *vals, int64_t n, const double *xy, uint64_t gen, double *out);
 // Sec. 3.1's refinement test of n leaves (device arrays)
 void box_refine(Context &ctx, int64_t n, const double *v16, const double *v64, double tol, int32_t *flags,
                 double *err);

@@ -51,7 +51,7 @@ EXPORTS = (
     "yk_ws_set_params", "yk_ws_loss_grad", "yk_ws_forward", "yk_ws_adam_step",
     "yk_gmres_density_noalloc", "yk_plan_tree_export", "yk_rhs_imex", "yk_heat_step_grid",
     "yk_near_info", "yk_plan_adaptive_export", "yk_box_potential", "yk_box_potential_adaptive",
-    "yk_box_refine",
+    "yk_box_refine", "yk_heat_step_leaves",
 )
 
 STAGES = ("gather", "p2m", "m2m", "m2l", "l2l", "leaf", "scatter", "direct", "l2p", "near_build")
@@ -174,6 +174,8 @@ def load_library(path: str = LIB_PATH):
         "yk_box_potential": (ip, [vp, P(yk_grid), vp, dbl, vp, i64, vp, vp]),
         "yk_box_potential_adaptive": (ip, [vp, P(dbl), i64, P(i32), P(i32), P(i32), vp, dbl, vp]),
         "yk_box_refine": (ip, [vp, i64, vp, vp, dbl, vp, vp]),
+        "yk_heat_step_leaves": (ip, [vp, P(yk_boundary), P(dbl), i64, P(i32), P(i32), P(i32), vp, ip, vp, dbl,
+                                     dbl, vp, vp, P(yk_stats)]),
         "yk_rhs_imex": (ip, [vp, ip, ip, i64, vp, vp, vp, vp, vp, ip, P(dbl), dbl, vp]),
         "yk_heat_step_grid": (ip, [vp, P(yk_boundary), P(yk_grid), vp, ip, vp, dbl, dbl, vp, vp, P(yk_stats)]),
         "yk_near_info": (ip, [vp, P(i64), P(dbl)]),
@@ -403,6 +405,25 @@ def yk_box_potential_adaptive(ctx, root, level, ix, iy, vals, alpha, V):
     _check(ctx, load_library().yk_box_potential_adaptive(ctx, rt, n, lv.ctypes.data_as(i32p),
                                                          jx.ctypes.data_as(i32p), jy.ctypes.data_as(i32p),
                                                          _dev(vals, "vals"), float(alpha), _dev(V, "V")))
+
+
+def yk_heat_step_leaves(ctx, bnd: Boundary, root, level, ix, iy, B, flags, f_next, alpha2, tol, sigma_io, u_next):
+    import numpy as np
+    lv = np.ascontiguousarray(level, dtype=np.int32)
+    jx = np.ascontiguousarray(ix, dtype=np.int32)
+    jy = np.ascontiguousarray(iy, dtype=np.int32)
+    n = lv.shape[0]
+    if B.shape[0] != 16 * n or u_next.shape[0] != 16 * n:
+        raise ValueError("B and u_next need 16 values per leaf")
+    st = yk_stats()
+    rt = (ctypes.c_double * 3)(*[float(v) for v in root])
+    i32p = ctypes.POINTER(ctypes.c_int32)
+    s = load_library().yk_heat_step_leaves(ctx, ctypes.byref(bnd.struct), rt, n, lv.ctypes.data_as(i32p),
+                                           jx.ctypes.data_as(i32p), jy.ctypes.data_as(i32p), _dev(B, "B"),
+                                           int(flags), _dev(f_next, "f_next"), float(alpha2), float(tol),
+                                           _dev(sigma_io, "sigma_io"), _dev(u_next, "u_next"), ctypes.byref(st))
+    _check(ctx, s, st)
+    return st
 
 
 def yk_box_refine(ctx, v16, v64, tol, flags, err=None):

@@ -185,3 +185,39 @@ def test_box_refinement_test_vs_oracle(yk):
         yk.yk_destroy(ctx)
     assert elem_err(host(er), ref_e) <= 1e-13
     assert np.array_equal(host(fl).astype(bool), ref_f)
+
+
+def test_heat_step_on_adaptive_leaves_closed_form(yk):
+    """One step on adaptive leaves refined towards the annulus's two circles
+    (levels 6 .. 8, 2:1 balanced): u = sin(3x) sin(2y) + 1 at every cell
+    inside, box code for U^p, leaf polynomials on the nodes, the density
+    solve and the near-boundary evaluation."""
+    import torch
+    from oracle import box as X
+    b = W.make_boundary([W.circle((0.0, 0.0), 0.4, 1024), W.circle((0.0, 0.0), 0.1, 512, ccw=False)])
+    root = (-0.5, -0.5, 1.0)
+
+    def want(l, i, j):
+        s = 2.0 ** -l
+        r = np.hypot(root[0] + (i + 0.5) * s, root[1] + (j + 0.5) * s)
+        return l < 6 or min(abs(r - 0.4), abs(r - 0.1)) < s
+
+    lv, ix, iy = X.balanced_leaves_by(root, want, 8)
+    cells = X.leaf_cells(lv, ix, iy, root)
+    uf = lambda p: np.sin(3 * p[:, 0]) * np.sin(2 * p[:, 1]) + 1.0
+    a2 = 1e-3
+    B = (1 + 13 * a2) * uf(cells) - 13 * a2
+    inside = b.region(cells) < 0
+    ctx = yk.yk_create()
+    try:
+        bd = yk.Boundary.from_workload(b)
+        sig = torch.zeros(b.n, dtype=torch.float64, device="cuda")
+        u = torch.empty(len(cells), dtype=torch.float64, device="cuda")
+        print(f"leaves {len(lv)}, cells {len(cells)}", flush=True)
+        st = yk.yk_heat_step_leaves(ctx, bd, root, lv, ix, iy, dev(B), yk.HEAT_ZERO_GUESS, dev(uf(b.xy)), a2,
+                                    1e-12, sig, u)
+    finally:
+        yk.yk_destroy(ctx)
+    err = np.max(np.abs(host(u) - uf(cells))[inside])
+    print(f"  adaptive leaves: max error inside {err:.2e}, {st.iters} iterations", flush=True)
+    assert err < 1e-6
