@@ -641,6 +641,12 @@ BoxPlan &box_plan_adaptive(Context &ctx, const double root[3], int64_t n, const 
         std::equal(iy, iy + n, ctx.box->iy.begin()))
         return *ctx.box;
     ctx.box.reset();
+    // the volume trees and near-boundary sets keyed by the cells' buffer are
+    // stale: a new plan may reuse its address for other cells
+    ctx.plan_vol.reset();
+    ctx.plan_near.reset();
+    ctx.plan_nearc.reset();
+    ctx.near.reset();
     BoxPtr bp(new BoxPlan());
     bp->adaptive = true;
     bp->alpha = alpha;
