@@ -415,6 +415,107 @@ def heat_step_bench(args, yk, torch, W):
     return out
 
 
+def box_code_bench(args, yk, torch, W):
+    """The box code (cubic fits on 4x4-cell leaves, near-field integral tables,
+    polynomial multipoles through the FMM) on the time-stepping grid: the
+    volume potential alone, and the time step of the uniform-grid entry with
+    the box code against the same entry with the lattice rule (FP64, the
+    previous-step guess).  B is a seeded mixture of eight Gaussians."""
+    cfg = W.config_c3(m=args.heat_m, n_holes=10, n_nodes=2048, dt=1e-3, seed=3)
+    m, b, alpha = args.heat_m, cfg["bnd"], cfg["alpha"]
+    d = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+    # the grid entry needs two cells between the curves and the grid's edge:
+    # the square [-1/32, 1 + 1/32]^2 around the time-stepping geometry
+    gb, vol = W.grid_box(-1.0 / 32, 1.0 + 1.0 / 32, m)
+    grid = yk.make_grid(*gb)
+    rng = np.random.default_rng(7)
+    mu, sg = rng.uniform(0.2, 0.8, (8, 2)), rng.uniform(0.03, 0.15, 8)
+    Bh = sum(np.exp(-((vol[:, 0] - mu[k, 0]) ** 2 + (vol[:, 1] - mu[k, 1]) ** 2) / (2 * sg[k] ** 2))
+             for k in range(8))
+    B, V = d(Bh), torch.empty(m * m, dtype=torch.float64, device="cuda")
+    out = {}
+    ctx = yk.yk_create(fmm_tol=1e-10, leaf_size=args.leaf)
+    try:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        yk.yk_box_potential(ctx, grid, B, alpha, V)          # tables and the leaf tree
+        torch.cuda.synchronize()
+        first = (time.perf_counter() - t0) * 1e3
+        for _ in range(args.warmup):
+            yk.yk_box_potential(ctx, grid, B, alpha, V)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(args.steps):
+            yk.yk_box_potential(ctx, grid, B, alpha, V)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / args.steps
+        yk.yk_timing_enable(ctx, True)
+        yk.yk_timing_read(ctx, reset=True)
+        for _ in range(args.steps):
+            yk.yk_box_potential(ctx, grid, B, alpha, V)
+        stg = {k: v[0] / args.steps for k, v in yk.yk_timing_read(ctx, reset=True).items() if v[1]}
+        yk.yk_timing_enable(ctx, False)
+    finally:
+        yk.yk_destroy(ctx)
+    nleaf = (m // 4) ** 2
+    roofs = {}
+    # algorithmic bytes per leaf: k_box_leaf reads the leaf's 10 coefficients
+    # and its local expansion (64 doubles) and writes its 16 cells; the fit
+    # reads 16 cells and writes 10 coefficients; the P2M reads 10 and writes 64
+    for key, kern, per_leaf in (("leaf", "k_box_leaf (near tables + local expansion at the 16 cells)",
+                                 (10 + 64 + 16) * 8),
+                                ("p2m", "k_box_p2m (polynomial multipoles)", (10 + 64) * 8)):
+        t = stg.get(key)
+        if t:
+            nbytes = nleaf * per_leaf
+            ach = nbytes / (t * 1e-3) / 1e9
+            roofs[key] = {"kernel": kern, "bound": "hbm", "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                          "frac": ach / PEAK_HBM_GBS, "traffic": None, "ms_per_call": t,
+                          "algorithmic_bytes": nbytes}
+    out["potential"] = {"ms": ms, "first_call_ms": first, "mcells_per_s": m * m / (ms * 1e-3) / 1e6,
+                        "leaves": nleaf, "stage_ms": stg, "rooflines": roofs}
+    bdy = yk.Boundary.from_workload(b)
+    f = d(cfg["f_bnd"])
+    reg_h = b.region(vol)
+    region = torch.as_tensor(reg_h, dtype=torch.int32, device="cuda")
+    finals = {}
+    for name, flags in (("lattice", 0), ("box_code", yk.HEAT_BOX_CODE)):
+        ctx = yk.yk_create(fmm_tol=1e-10, leaf_size=args.leaf)
+        try:
+            u = torch.zeros(m * m, dtype=torch.float64, device="cuda")
+            Bs, un = torch.empty_like(u), torch.empty_like(u)
+            sig = torch.zeros(b.n, dtype=torch.float64, device="cuda")
+            times, iters, first = [], [], None
+            n_steps = max(4, args.heat_steps // 5)
+            for step in range(1, n_steps + 1):
+                yk.yk_rhs_backward_euler(ctx, u, None, region, cfg["consts"], cfg["dt"], Bs)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                st = yk.yk_heat_step_grid(ctx, bdy, grid, Bs, flags, f, cfg["dt"], 1e-10, sig, un)
+                torch.cuda.synchronize()
+                dt_s = time.perf_counter() - t0
+                if step == 1:
+                    first = dt_s
+                else:
+                    times.append(dt_s)
+                    iters.append(st.iters)
+                u, un = un, u
+            finals[name] = u.cpu().numpy()
+        finally:
+            yk.yk_destroy(ctx)
+        out[name + "_grid_step"] = {"s_per_step": float(np.mean(times)), "first_step_s": first,
+                                    "gmres_iters": float(np.mean(iters)), "steps": n_steps}
+    inside = reg_h < 0
+    out["box_vs_lattice_max_diff_inside"] = float(np.max(np.abs(finals["box_code"] - finals["lattice"])[inside]))
+    out["workload"] = (f"{m}^2 cell grid of [-1/32, 1+1/32]^2, alpha=sqrt(1e-3); potential of a mixture of 8 "
+                       f"Gaussians ({nleaf} leaves of 4x4 cells); backward-Euler grid steps (dt=1e-3, u=0 at "
+                       f"t=0) on the time-stepping geometry (outer circle + 10 ellipses x 2048 nodes), GMRES "
+                       f"tol 1e-10, averages over steps 2-{max(4, args.heat_steps // 5)}")
+    return out
+
+
 def large_step_bench(args, yk, torch, W):
     """s/time-step on the large adaptive set (about 2^24 cells of an adaptive
     quadtree refined where a mixture of eight Gaussians is dense, weights the
@@ -547,6 +648,9 @@ def main():
     ap.add_argument("--heat-steps", type=int, default=100)
     ap.add_argument("--heat-m", type=int, default=1024)
     ap.add_argument("--no-heat", action="store_true")
+    ap.add_argument("--no-box", action="store_true", help="skip the box-code measurements")
+    ap.add_argument("--box-only", action="store_true",
+                    help="only the box-code measurements (profiling runs); prints their JSON object")
     ap.add_argument("--no-fp32-pass", action="store_true", help="skip the FP32 pass of the same workload")
     ap.add_argument("--heat-only", action="store_true",
                     help="only the time-stepping comparison (profiling runs); prints its JSON object")
@@ -576,6 +680,9 @@ def main():
 
     if args.heat_only:
         print(json.dumps(heat_step_bench(args, yk, torch, W)), flush=True)
+        return
+    if args.box_only:
+        print(json.dumps(box_code_bench(args, yk, torch, W)), flush=True)
         return
     if args.large_steps > 0:
         print(json.dumps(large_step_bench(args, yk, torch, W)), flush=True)
@@ -638,6 +745,7 @@ def main():
     if not args.no_cpu:
         err_oracle, cpu = oracle_baseline(args, res, idx)
     heat = None if args.no_heat else heat_step_bench(args, yk, torch, W)
+    box = None if args.no_box else box_code_bench(args, yk, torch, W)
     line = {
         "metric": METRIC, "value": value, "unit": "Mpts/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": res["ms"], "higher_is_better": True,
@@ -667,6 +775,7 @@ def main():
         "cpu_baseline": cpu,
         "fp32_pass": fp32_pass,
         "time_step": heat,
+        "box_code": box,
     }
     print(json.dumps(line), flush=True)
 

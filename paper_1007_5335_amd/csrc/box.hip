@@ -69,50 +69,88 @@ __global__ void k_box_fit(int64_t nlx, int64_t nleaf, int64_t nx, const double *
     }
 }
 
-// multipole of leaf box li (its single point is the centre of grid leaf
-// perm[lrange[li][0]]): M[o] = sum_k coef[k] Q[k][o]; one workgroup of Pp lanes
-__global__ void k_box_p2m(int64_t leaf_base, const int32_t *__restrict__ lrange, const int32_t *__restrict__ perm,
+// multipoles of 16 consecutive grid leaves g per workgroup of Pp lanes (lane
+// = coefficient o): M[tree leaf of g][o] = sum_k coef[g][k] Q[k][o]
+constexpr int kP2MLeaves = 16;
+__global__ void k_box_p2m(int64_t nl, int64_t leaf_base, const int32_t *__restrict__ g2l,
                           const double *__restrict__ coef, const double *__restrict__ Q, int Pp,
                           double *__restrict__ M) {
-    const int64_t li = blockIdx.x;
     const int o = threadIdx.x;
-    const int64_t g = perm[lrange[li * 6]];
-    double s = 0.0;
+    double q[kNB];
 #pragma unroll
-    for (int k = 0; k < kNB; ++k) s = __builtin_fma(coef[g * kNB + k], Q[k * Pp + o], s);
-    M[(leaf_base + li) * Pp + o] = s;
+    for (int k = 0; k < kNB; ++k) q[k] = Q[k * Pp + o];
+    const int64_t g0 = (int64_t)blockIdx.x * kP2MLeaves;
+#pragma unroll
+    for (int i = 0; i < kP2MLeaves; ++i) {
+        const int64_t g = g0 + i;
+        if (g < nl) {
+            double s = 0.0;
+#pragma unroll
+            for (int k = 0; k < kNB; ++k) s = __builtin_fma(coef[g * kNB + k], q[k], s);
+            M[(leaf_base + g2l[g]) * Pp + o] = s;
+        }
+    }
 }
 
-// V at the 16 cells of every leaf: near field from the U list (the leaf and
-// its existing neighbours) by the tables A[offset][cell][k], far field from
-// the leaf's local expansion by E[cell][o]; 4 leaves per 64-lane workgroup
-__global__ __launch_bounds__(64) void k_box_leaf(
-    int64_t nl, int64_t leaf_base, const int32_t *__restrict__ lrange, const int32_t *__restrict__ perm,
-    const int32_t *__restrict__ uoff, const int32_t *__restrict__ ulist, int64_t nlx, int64_t nx,
-    const double *__restrict__ coef, const double *__restrict__ A, const double *__restrict__ E,
-    const double *__restrict__ Lc, int Pp, int far, double *__restrict__ V) {
-    const int64_t li = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 4);
-    const int t = threadIdx.x & 15;
-    if (li >= nl) return;
-    const int64_t g = perm[lrange[li * 6]];
-    const int64_t I = g % nlx, J = g / nlx;
-    double acc = 0.0;
-    for (int32_t u = uoff[li]; u < uoff[li + 1]; ++u) {
-        const int64_t gs = perm[lrange[(int64_t)ulist[u] * 6]];
-        const int dI = (int)(gs % nlx - I), dJ = (int)(gs / nlx - J);
-        const double *a = A + ((size_t)((dJ + 1) * 3 + dI + 1) * kNC + t) * kNB;
-        const double *c = coef + gs * kNB;
+// V at the 16 cells of every leaf.  Per leaf this is one small dense product,
+//   V[t] = sum_o E[t][o] L[o] / (2 pi) + sum_(offset, k) A[offset][t][k] c_nb(offset)[k],
+// the far field from the leaf's local expansion L and the near field from the
+// cubics c of the leaf and its 3 x 3 neighbours (zero outside the grid), so
+// it runs on the FP64 matrix cores: a wavefront owns 16 leaves of one grid
+// row (the columns of a 16 x 16 output tile, the rows being the 16 cells),
+// and contracts over the PP far and 90 near terms in steps of four.  Lane l
+// (leaf or cell l % 16, group gq = l / 16) supplies, in far step s, term
+// gq FS + s of the local expansion (a contiguous run per lane), and in near
+// step s, term gq kNearSteps + s of the 90 near terms (offset, monomial) in
+// that order, padded with zeros to 92.  W holds the matching operator
+// fragments in lane order, W[step][lane].  The output tile's row r of lane
+// group gq is cell gq + 4 r: row r of the leaf's cells at column gq, so each
+// store instruction writes 64 consecutive cells of one grid row.
+constexpr int kNearSteps = 23;   // ceil(90 / 4)
+typedef double box_d4 __attribute__((ext_vector_type(4)));
+
+template <int PP>   // PP = 0: no far field
+__global__ __launch_bounds__(256) void k_box_leaf(
+    int64_t nlx, int64_t nly, int64_t nx, int64_t tiles_row, const int32_t *__restrict__ g2l, int64_t leaf_base,
+    const double *__restrict__ coef, const double *__restrict__ W, const double *__restrict__ Lc,
+    double *__restrict__ V) {
+    constexpr int FS = PP / 4;
+    const int lane = threadIdx.x & 63, j = lane & 15, gq = lane >> 4;
+    const int64_t tile = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (tile >= tiles_row * nly) return;   // (no barriers in this kernel)
+    const int64_t J = tile / tiles_row, I = (tile % tiles_row) * 16 + j;
+    const bool ok = I < nlx;
+    box_d4 accn = {0.0, 0.0, 0.0, 0.0}, accf = {0.0, 0.0, 0.0, 0.0};
+    if constexpr (PP > 0) {
+        const double *lp = Lc + (leaf_base + (ok ? g2l[J * nlx + I] : 0)) * PP + gq * FS;
+        double bf[FS];
 #pragma unroll
-        for (int k = 0; k < kNB; ++k) acc = __builtin_fma(a[k], c[k], acc);
+        for (int s = 0; s < FS; ++s) bf[s] = ok ? lp[s] : 0.0;
+#pragma unroll
+        for (int s = 0; s < FS; ++s) accf = __builtin_amdgcn_mfma_f64_16x16x4f64(W[s * 64 + lane], bf[s], accf, 0, 0, 0);
     }
-    if (far) {
-        const double *Lb = Lc + (leaf_base + li) * Pp;
-        const double *e = E + (size_t)t * Pp;
-        double s = 0.0;
-        for (int o = 0; o < Pp; ++o) s = __builtin_fma(e[o], Lb[o], s);
-        acc += s * kInv2Pi;
+    double bn[kNearSteps];
+#pragma unroll
+    for (int s = 0; s < kNearSteps; ++s) {
+        const int f = gq * kNearSteps + s, off = f / kNB, k = f - off * kNB;
+        const int64_t In = I + off % 3 - 1, Jn = J + off / 3 - 1;
+        const bool in = ok && f < kNOff * kNB && In >= 0 && In < nlx && Jn >= 0 && Jn < nly;
+        bn[s] = in ? coef[(Jn * nlx + In) * kNB + k] : 0.0;
     }
-    V[(4 * J + (t >> 2)) * nx + 4 * I + (t & 3)] = acc;
+#pragma unroll
+    for (int s = 0; s < kNearSteps; ++s)
+        accn = __builtin_amdgcn_mfma_f64_16x16x4f64(W[(FS + s) * 64 + lane], bn[s], accn, 0, 0, 0);
+    if (!ok) return;
+    double *out = V + 4 * J * nx + 4 * I + gq;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) out[r * nx] = accn[r] + accf[r] * kInv2Pi;
+}
+
+// g2l[g] = the tree leaf whose single point is the centre of grid leaf g
+__global__ void k_box_g2l(int64_t nl, const int32_t *__restrict__ lrange, const int32_t *__restrict__ perm,
+                          int32_t *__restrict__ g2l) {
+    const int64_t li = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (li < nl) g2l[perm[lrange[li * 6]]] = (int32_t)li;
 }
 
 // the leaf polynomial of the leaf holding each point
@@ -298,6 +336,8 @@ struct BoxPlan {
     int Pp = 0;
     bool far = false;
     DevBuf<double> centres, pinv, A, Q, E, coef;
+    DevBuf<double> W;         // the leaf kernel's operator fragments in lane order
+    DevBuf<int32_t> g2l;      // grid leaf -> tree leaf
     // adaptive leaves: the leaf set (level, ix, iy) over the root square; the
     // tree over the leaves' cell centres; per U-list entry and per X-list entry
     // the index of its table; per tree leaf its input leaf; P2M tables by level
@@ -493,8 +533,8 @@ void box_tables(Context &ctx, BoxPlan &bp) {
                               hipMemcpyHostToDevice, ctx.stream));
     }
     // near field: A[off][t][k] for the 16 cells of a leaf at each of the 9 offsets
+    std::vector<double> A((size_t)kNOff * kNC * kNB, 0.0), E;
     {
-        std::vector<double> A((size_t)kNOff * kNC * kNB, 0.0);
         host_parallel(kNOff, [&](int64_t i0, int64_t i1) {
             for (int64_t off = i0; off < i1; ++off) {
                 const int dI = (int)(off % 3) - 1, dJ = (int)(off / 3) - 1;
@@ -514,7 +554,8 @@ void box_tables(Context &ctx, BoxPlan &bp) {
         const int p = pl.p, Pp = pl.Pp;
         const long double R = pl.lev[pl.L].R;
         const std::vector<long double> IR = bessel_i_seq(R, p + 1);
-        std::vector<double> Q((size_t)kNB * Pp, 0.0), E((size_t)kNC * Pp, 0.0);
+        std::vector<double> Q((size_t)kNB * Pp, 0.0);
+        E.assign((size_t)kNC * Pp, 0.0);
         moments(H, R, al, p, Pp, Q.data());
         // E[t][o]: the weights of the stored local coefficients in the value at cell t
         for (int t = 0; t < kNC; ++t) {
@@ -531,6 +572,26 @@ void box_tables(Context &ctx, BoxPlan &bp) {
         YK_HIP(hipMemcpyAsync(bp.Q.ensure(Q.size()), Q.data(), Q.size() * sizeof(double), hipMemcpyHostToDevice,
                               ctx.stream));
         YK_HIP(hipMemcpyAsync(bp.E.ensure(E.size()), E.data(), E.size() * sizeof(double), hipMemcpyHostToDevice,
+                              ctx.stream));
+    }
+    // the uniform leaf kernel's operator fragments W[step][lane] (the term
+    // order of k_box_leaf): cell t = lane % 16, lane group gq = lane / 16
+    if (!bp.adaptive) {
+        const int FS = bp.far ? bp.Pp / 4 : 0, S = FS + kNearSteps;
+        std::vector<double> W((size_t)S * 64, 0.0);
+        for (int st = 0; st < S; ++st)
+            for (int l = 0; l < 64; ++l) {
+                const int t = l & 15, gq = l >> 4;
+                double v = 0.0;
+                if (st < FS) {
+                    v = E[(size_t)t * bp.Pp + gq * FS + st];
+                } else {
+                    const int f = gq * kNearSteps + (st - FS);
+                    if (f < kNOff * kNB) v = A[((size_t)(f / kNB) * kNC + t) * kNB + f % kNB];
+                }
+                W[(size_t)st * 64 + l] = v;
+            }
+        YK_HIP(hipMemcpyAsync(bp.W.ensure(W.size()), W.data(), W.size() * sizeof(double), hipMemcpyHostToDevice,
                               ctx.stream));
     }
     YK_HIP(hipStreamSynchronize(ctx.stream));
@@ -582,6 +643,9 @@ BoxPlan &box_plan(Context &ctx, const yk_grid &g, double alpha) {
     bp->far = fp->lmin <= fp->L;
     bp->Pp = fp->Pp;
     bp->fmm = std::move(fp);
+    hipLaunchKernelGGL(k_box_g2l, dim3(nblk(bp->nleaf, 256)), dim3(256), 0, ctx.stream, bp->nleaf,
+                       bp->fmm->lrange.p, bp->fmm->perm.p, bp->g2l.ensure(bp->nleaf));
+    check_launch(ctx, "k_box_g2l");
     box_tables(ctx, *bp);
     ctx.box = std::move(bp);
     return *ctx.box;
@@ -601,8 +665,8 @@ void box_potential(Context &ctx, const yk_grid &g, const double *B, double alpha
     if (bp.far) {
         {
             StageTimer tm(ctx, YK_STAGE_P2M);
-            hipLaunchKernelGGL(k_box_p2m, dim3((unsigned)pl.nleaf), dim3(pl.Pp), 0, ctx.stream, leaf_base,
-                               pl.lrange.p, pl.perm.p, coef, bp.Q.p, pl.Pp, pl.M.p);
+            hipLaunchKernelGGL(k_box_p2m, dim3(nblk(bp.nleaf, kP2MLeaves)), dim3(pl.Pp), 0, ctx.stream, bp.nleaf,
+                               leaf_base, bp.g2l.p, coef, bp.Q.p, pl.Pp, pl.M.p);
             check_launch(ctx, "k_box_p2m");
         }
         fmm_m2m(ctx, pl);
@@ -611,9 +675,24 @@ void box_potential(Context &ctx, const yk_grid &g, const double *B, double alpha
         fmm_l2l(ctx, pl, as, false);
     }
     StageTimer tl(ctx, YK_STAGE_LEAF);
-    hipLaunchKernelGGL(k_box_leaf, dim3(nblk(pl.nleaf, 4)), dim3(64), 0, ctx.stream, pl.nleaf, leaf_base,
-                       pl.lrange.p, pl.perm.p, pl.ulist_off.p, pl.ulist.p, bp.nlx, bp.nx, coef, bp.A.p,
-                       bp.far ? bp.E.p : nullptr, pl.Lc.p, pl.Pp, bp.far ? 1 : 0, V);
+    const int64_t tiles_row = (bp.nlx + 15) / 16;
+    const unsigned nb = nblk(tiles_row * bp.nly, 4);
+    const int pp = bp.far ? pl.Pp : 0;
+#define YK_BOX_LEAF(PPV)                                                                                   \
+    case PPV:                                                                                              \
+        hipLaunchKernelGGL(k_box_leaf<PPV>, dim3(nb), dim3(256), 0, ctx.stream, bp.nlx, bp.nly, bp.nx, tiles_row, \
+                           bp.g2l.p, leaf_base, coef, bp.W.p, pl.Lc.p, V);                                \
+        break;
+    switch (pp) {
+        YK_BOX_LEAF(0)
+        YK_BOX_LEAF(16)
+        YK_BOX_LEAF(32)
+        YK_BOX_LEAF(48)
+        YK_BOX_LEAF(64)
+        default:
+            throw Error{YK_ERR_INTERNAL, "no box leaf kernel for this padded order"};
+    }
+#undef YK_BOX_LEAF
     check_launch(ctx, "k_box_leaf");
 }
 
