@@ -109,41 +109,50 @@ __global__ void k_box_p2m(int64_t nl, int64_t leaf_base, const int32_t *__restri
 constexpr int kNearSteps = 23;   // ceil(90 / 4)
 typedef double box_d4 __attribute__((ext_vector_type(4)));
 
+constexpr int kLeafTiles = 4;    // tiles per wavefront (the operator fragments stay in registers)
+
 template <int PP>   // PP = 0: no far field
 __global__ __launch_bounds__(256) void k_box_leaf(
     int64_t nlx, int64_t nly, int64_t nx, int64_t tiles_row, const int32_t *__restrict__ g2l, int64_t leaf_base,
     const double *__restrict__ coef, const double *__restrict__ W, const double *__restrict__ Lc,
     double *__restrict__ V) {
-    constexpr int FS = PP / 4;
+    constexpr int FS = PP / 4, S = FS + kNearSteps;
     const int lane = threadIdx.x & 63, j = lane & 15, gq = lane >> 4;
-    const int64_t tile = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (tile >= tiles_row * nly) return;   // (no barriers in this kernel)
-    const int64_t J = tile / tiles_row, I = (tile % tiles_row) * 16 + j;
-    const bool ok = I < nlx;
-    box_d4 accn = {0.0, 0.0, 0.0, 0.0}, accf = {0.0, 0.0, 0.0, 0.0};
-    if constexpr (PP > 0) {
-        const double *lp = Lc + (leaf_base + (ok ? g2l[J * nlx + I] : 0)) * PP + gq * FS;
-        double bf[FS];
+    const int64_t ntiles = tiles_row * nly;
+    const int64_t tile0 = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * kLeafTiles;
+    if (tile0 >= ntiles) return;   // (no barriers in this kernel)
+    double w[S];
 #pragma unroll
-        for (int s = 0; s < FS; ++s) bf[s] = ok ? lp[s] : 0.0;
+    for (int s = 0; s < S; ++s) w[s] = W[s * 64 + lane];
+    for (int64_t tile = tile0; tile < tile0 + kLeafTiles && tile < ntiles; ++tile) {
+        const int64_t J = tile / tiles_row, I = (tile % tiles_row) * 16 + j;
+        const bool ok = I < nlx;
+        box_d4 accn = {0.0, 0.0, 0.0, 0.0}, accf = {0.0, 0.0, 0.0, 0.0};
+        if constexpr (PP > 0) {
+            const double *lp = Lc + (leaf_base + (ok ? g2l[J * nlx + I] : 0)) * PP + gq * FS;
+            double bf[FS];
 #pragma unroll
-        for (int s = 0; s < FS; ++s) accf = __builtin_amdgcn_mfma_f64_16x16x4f64(W[s * 64 + lane], bf[s], accf, 0, 0, 0);
+            for (int s = 0; s < FS; ++s) bf[s] = ok ? lp[s] : 0.0;
+#pragma unroll
+            for (int s = 0; s < FS; ++s) accf = __builtin_amdgcn_mfma_f64_16x16x4f64(w[s], bf[s], accf, 0, 0, 0);
+        }
+        double bn[kNearSteps];
+#pragma unroll
+        for (int s = 0; s < kNearSteps; ++s) {
+            const int f = gq * kNearSteps + s, off = f / kNB, k = f - off * kNB;
+            const int64_t In = I + off % 3 - 1, Jn = J + off / 3 - 1;
+            const bool in = ok && f < kNOff * kNB && In >= 0 && In < nlx && Jn >= 0 && Jn < nly;
+            bn[s] = in ? coef[(Jn * nlx + In) * kNB + k] : 0.0;
+        }
+#pragma unroll
+        for (int s = 0; s < kNearSteps; ++s)
+            accn = __builtin_amdgcn_mfma_f64_16x16x4f64(w[FS + s], bn[s], accn, 0, 0, 0);
+        if (ok) {
+            double *out = V + 4 * J * nx + 4 * I + gq;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) out[r * nx] = accn[r] + accf[r] * kInv2Pi;
+        }
     }
-    double bn[kNearSteps];
-#pragma unroll
-    for (int s = 0; s < kNearSteps; ++s) {
-        const int f = gq * kNearSteps + s, off = f / kNB, k = f - off * kNB;
-        const int64_t In = I + off % 3 - 1, Jn = J + off / 3 - 1;
-        const bool in = ok && f < kNOff * kNB && In >= 0 && In < nlx && Jn >= 0 && Jn < nly;
-        bn[s] = in ? coef[(Jn * nlx + In) * kNB + k] : 0.0;
-    }
-#pragma unroll
-    for (int s = 0; s < kNearSteps; ++s)
-        accn = __builtin_amdgcn_mfma_f64_16x16x4f64(W[(FS + s) * 64 + lane], bn[s], accn, 0, 0, 0);
-    if (!ok) return;
-    double *out = V + 4 * J * nx + 4 * I + gq;
-#pragma unroll
-    for (int r = 0; r < 4; ++r) out[r * nx] = accn[r] + accf[r] * kInv2Pi;
 }
 
 // g2l[g] = the tree leaf whose single point is the centre of grid leaf g
@@ -676,7 +685,7 @@ void box_potential(Context &ctx, const yk_grid &g, const double *B, double alpha
     }
     StageTimer tl(ctx, YK_STAGE_LEAF);
     const int64_t tiles_row = (bp.nlx + 15) / 16;
-    const unsigned nb = nblk(tiles_row * bp.nly, 4);
+    const unsigned nb = nblk(tiles_row * bp.nly, 4 * kLeafTiles);
     const int pp = bp.far ? pl.Pp : 0;
 #define YK_BOX_LEAF(PPV)                                                                                   \
     case PPV:                                                                                              \
