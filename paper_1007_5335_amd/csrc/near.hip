@@ -72,6 +72,7 @@ struct NearPlan {
     };
     std::vector<std::unique_ptr<FftGroup>> fft;
     DevBuf<int8_t> fft_curve;        // [n_curves]: 1 when the curve takes the FFTs
+    DevBuf<double> tw;               // [kTwHalf][2] butterfly factors
     bool any_direct = false;
     double setup_ms = 0;
 };
@@ -273,13 +274,66 @@ __global__ void k_fine_dipoles(int64_t nf, int n_curves, const int64_t *__restri
     fdn[2 * i + 1] = s * fnrm[2 * i + 1];
 }
 
+constexpr int kFftMinLog = 4, kFftMaxLog = 13;
+constexpr int kTwHalf = 1 << (kFftMaxLog - 1);   // twiddles of the largest transform
+
+// tw[k] = (cos, sin)(pi k / kTwHalf), k < kTwHalf: the butterflies' factors
+// for every size, e^{-+ i pi k / half} = tw[k kTwHalf / half] (read, not
+// recomputed per butterfly: an FP64 sincos costs far more than the butterfly)
+__global__ void k_fft_twiddles(double *__restrict__ tw) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= kTwHalf) return;
+    double sn, cs;
+    sincospi((double)k / (double)kTwHalf, &sn, &cs);
+    tw[2 * k] = cs;
+    tw[2 * k + 1] = sn;
+}
+
+// threads per workgroup of the LDS FFTs: the large transforms are the few
+// long ones (one workgroup per curve), so they take more threads per stage
+constexpr int fft_threads(int logn) { return logn >= 11 ? 1024 : 256; }
+
+// The radix-2 stages of an in-place FFT of N = 2^LOGN points in LDS (input in
+// bit-reversed order, decimation in time) by NT threads, factors
+// e^{SIGN i pi k / half} from tw; each thread issues the loads of its
+// butterflies' factors of a stage together, before their LDS work
+template <int LOGN, int SIGN>
+__device__ __forceinline__ void fft_stages(double *re, double *im, const double *__restrict__ tw) {
+    constexpr int NT = fft_threads(LOGN), NBF = (1 << LOGN) / 2, BPT = (NBF + NT - 1) / NT;
+    for (int s = 1; s <= LOGN; ++s) {
+        const int half = 1 << (s - 1);
+        double cs[BPT], sn[BPT];
+#pragma unroll
+        for (int u = 0; u < BPT; ++u) {
+            // (k < half, so e < kTwHalf for every thread)
+            const int e = ((threadIdx.x + NT * u) & (half - 1)) << (kFftMaxLog - s);
+            cs[u] = tw[2 * e];
+            sn[u] = SIGN * tw[2 * e + 1];
+        }
+#pragma unroll
+        for (int u = 0; u < BPT; ++u) {
+            const int t = threadIdx.x + NT * u;
+            if (NBF % NT == 0 || t < NBF) {
+                const int k = t & (half - 1), i = ((t >> (s - 1)) << s) + k, j = i + half;
+                const double tr = re[j] * cs[u] - im[j] * sn[u], ti = re[j] * sn[u] + im[j] * cs[u];
+                re[j] = re[i] - tr;
+                im[j] = im[i] - ti;
+                re[i] += tr;
+                im[i] += ti;
+            }
+        }
+        __syncthreads();
+    }
+}
+
 // Fourier coefficients c_k = (1/N) sum_j v_j e^{-2 pi i j k / N} of a curve
 // whose N = 2^LOGN, by an in-place radix-2 FFT in LDS (input in bit-reversed
 // order, decimation in time); one workgroup per (curve, field)
 template <int LOGN>
-__global__ __launch_bounds__(256) void k_fft_coef(const int32_t *__restrict__ curves, const int64_t *__restrict__ off,
+__global__ __launch_bounds__(1024) void k_fft_coef(const int32_t *__restrict__ curves, const int64_t *__restrict__ off,
                                                   const double *__restrict__ v0, const double *__restrict__ v1,
-                                                  double *__restrict__ c0, double *__restrict__ c1) {
+                                                  const double *__restrict__ tw, double *__restrict__ c0,
+                                                  double *__restrict__ c1) {
     constexpr int N = 1 << LOGN;
     __shared__ double re[N], im[N];
     const int64_t base = off[curves[blockIdx.x]];
@@ -291,20 +345,7 @@ __global__ __launch_bounds__(256) void k_fft_coef(const int32_t *__restrict__ cu
         im[j] = 0.0;
     }
     __syncthreads();
-    for (int s = 1; s <= LOGN; ++s) {
-        const int half = 1 << (s - 1);
-        for (int t = threadIdx.x; t < N / 2; t += blockDim.x) {
-            const int k = t & (half - 1), i = ((t >> (s - 1)) << s) + k, j = i + half;
-            double sn, cs;
-            sincospi(-(double)k / (double)half, &sn, &cs);
-            const double tr = re[j] * cs - im[j] * sn, ti = re[j] * sn + im[j] * cs;
-            re[j] = re[i] - tr;
-            im[j] = im[i] - ti;
-            re[i] += tr;
-            im[i] += ti;
-        }
-        __syncthreads();
-    }
+    fft_stages<LOGN, -1>(re, im, tw);
     for (int i = threadIdx.x; i < N; i += blockDim.x) {
         cf[2 * (base + i)] = re[i] * (1.0 / N);
         cf[2 * (base + i) + 1] = im[i] * (1.0 / N);
@@ -317,9 +358,10 @@ __global__ __launch_bounds__(256) void k_fft_coef(const int32_t *__restrict__ cu
 // contributes c_{N/2} cos(N theta / 2)); one workgroup per (curve, r); writes
 // the finer rule's dipole vectors w sigma n
 template <int LOGN>
-__global__ __launch_bounds__(256) void k_fft_fine(const int32_t *__restrict__ curves, const int64_t *__restrict__ off,
+__global__ __launch_bounds__(1024) void k_fft_fine(const int32_t *__restrict__ curves, const int64_t *__restrict__ off,
                                                   const double *__restrict__ coef, const double *__restrict__ fnrm,
-                                                  const double *__restrict__ fw, double *__restrict__ fdn) {
+                                                  const double *__restrict__ fw, const double *__restrict__ tw,
+                                                  double *__restrict__ fdn) {
     constexpr int N = 1 << LOGN;
     constexpr int M = kNearM * N;
     __shared__ double re[N], im[N];
@@ -340,20 +382,7 @@ __global__ __launch_bounds__(256) void k_fft_fine(const int32_t *__restrict__ cu
         }
     }
     __syncthreads();
-    for (int s = 1; s <= LOGN; ++s) {
-        const int half = 1 << (s - 1);
-        for (int t = threadIdx.x; t < N / 2; t += blockDim.x) {
-            const int k = t & (half - 1), i = ((t >> (s - 1)) << s) + k, j = i + half;
-            double sn, cs;
-            sincospi((double)k / (double)half, &sn, &cs);
-            const double tr = re[j] * cs - im[j] * sn, ti = re[j] * sn + im[j] * cs;
-            re[j] = re[i] - tr;
-            im[j] = im[i] - ti;
-            re[i] += tr;
-            im[i] += ti;
-        }
-        __syncthreads();
-    }
+    fft_stages<LOGN, 1>(re, im, tw);
     for (int j = threadIdx.x; j < N; j += blockDim.x) {
         const int64_t f = kNearM * base + (int64_t)kNearM * j + r;
         const double sgm = fw[f] * re[j];
@@ -424,10 +453,10 @@ __global__ void k_near_finish(int64_t nn, const int64_t *__restrict__ idx, const
     out[p] = basev + uh;
 }
 
-using FftCoefKernel = void (*)(const int32_t *, const int64_t *, const double *, const double *, double *, double *);
+using FftCoefKernel = void (*)(const int32_t *, const int64_t *, const double *, const double *, const double *,
+                               double *, double *);
 using FftFineKernel = void (*)(const int32_t *, const int64_t *, const double *, const double *, const double *,
-                               double *);
-constexpr int kFftMinLog = 4, kFftMaxLog = 13;
+                               const double *, double *);
 
 FftCoefKernel fft_coef_kernel(int logn) {
     switch (logn) {
@@ -685,6 +714,11 @@ NearPlan &near_prepare(Context &ctx, BoundaryData &bd, int64_t n_tgt, const doub
             np->fft.push_back(std::move(gr));
         }
         YK_HIP(hipMemcpyAsync(np->fft_curve.ensure(nc), flag.data(), nc, hipMemcpyHostToDevice, ctx.stream));
+        if (!np->fft.empty()) {
+            hipLaunchKernelGGL(k_fft_twiddles, dim3(nblk(kTwHalf, 256)), dim3(256), 0, ctx.stream,
+                               np->tw.ensure(2 * (size_t)kTwHalf));
+            check_launch(ctx, "k_fft_twiddles");
+        }
     }
     YK_HIP(hipStreamSynchronize(ctx.stream));
     np->setup_ms = ms_since(t0);
@@ -703,11 +737,11 @@ void near_apply(Context &ctx, NearPlan &np, BoundaryData &bd, double alpha, cons
     // LDS FFTs for power-of-two curves, direct sums for the others
     for (const auto &gp : np.fft) {
         const NearPlan::FftGroup &gr = *gp;
-        hipLaunchKernelGGL(fft_coef_kernel(gr.logn), dim3(gr.count, 2), dim3(256), 0, ctx.stream, gr.ids.p,
-                           np.doff.p, sigma, g, sc, gc);
+        hipLaunchKernelGGL(fft_coef_kernel(gr.logn), dim3(gr.count, 2), dim3(fft_threads(gr.logn)), 0, ctx.stream,
+                           gr.ids.p, np.doff.p, sigma, g, np.tw.p, sc, gc);
         check_launch(ctx, "k_fft_coef");
-        hipLaunchKernelGGL(fft_fine_kernel(gr.logn), dim3(gr.count * kNearM), dim3(256), 0, ctx.stream, gr.ids.p,
-                           np.doff.p, sc, np.fnrm.p, np.fw.p, fdn);
+        hipLaunchKernelGGL(fft_fine_kernel(gr.logn), dim3(gr.count * kNearM), dim3(fft_threads(gr.logn)), 0,
+                           ctx.stream, gr.ids.p, np.doff.p, sc, np.fnrm.p, np.fw.p, np.tw.p, fdn);
         check_launch(ctx, "k_fft_fine");
     }
     if (np.any_direct) {
