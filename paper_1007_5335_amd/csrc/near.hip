@@ -391,9 +391,10 @@ __global__ __launch_bounds__(1024) void k_fft_fine(const int32_t *__restrict__ c
     }
 }
 
-// g(theta*) at the near targets, one wavefront per target: the lanes split the
-// modes in contiguous runs (e^{ik theta} by recurrence, re-seeded every 32),
-// and the partial sums meet in a fixed shuffle tree
+// g(theta*) at the near targets, one wavefront per target: lane l takes the
+// modes k = 1 + l + 64 m (consecutive lanes read consecutive coefficients),
+// e^{ik theta} by the recurrence of stride 64 re-seeded every 16 of a lane's
+// modes, and the partial sums meet in a fixed shuffle tree
 __global__ __launch_bounds__(256) void k_near_g(int64_t nn, const int32_t *__restrict__ cur,
                                                 const double *__restrict__ th, const int64_t *__restrict__ off,
                                                 const double *__restrict__ gcoef, double *__restrict__ gstar) {
@@ -404,18 +405,17 @@ __global__ __launch_bounds__(256) void k_near_g(int64_t nn, const int32_t *__res
     const int64_t base = off[c], N = off[c + 1] - base, kmax = (N - 1) / 2;
     const double t = th[w];
     const double *cf = gcoef + 2 * base;
-    const int64_t chunk = (kmax + 63) / 64, k0 = 1 + lane * chunk, k1 = min(kmax, k0 + chunk - 1);
     double acc = 0.0;
-    if (k0 <= k1) {
-        double s1, c1, ei, er;
-        sincos(t, &s1, &c1);
-        sincos((double)k0 * t, &ei, &er);
-        for (int64_t k = k0; k <= k1; ++k) {
-            if (k > k0 && (k & 31) == 0) {
+    if (1 + lane <= kmax) {
+        double s64, c64, ei = 0.0, er = 1.0;
+        sincos(64.0 * t, &s64, &c64);
+        int m = 0;
+        for (int64_t k = 1 + lane; k <= kmax; k += 64, ++m) {
+            if ((m & 15) == 0) {
                 sincos((double)k * t, &ei, &er);
-            } else if (k > k0) {
-                const double nr = er * c1 - ei * s1;
-                ei = er * s1 + ei * c1;
+            } else {
+                const double nr = er * c64 - ei * s64;
+                ei = er * s64 + ei * c64;
                 er = nr;
             }
             acc += 2.0 * (cf[2 * k] * er - cf[2 * k + 1] * ei);
