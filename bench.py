@@ -476,6 +476,40 @@ def box_code_bench(args, yk, torch, W):
                           "algorithmic_bytes": nbytes}
     out["potential"] = {"ms": ms, "first_call_ms": first, "mcells_per_s": m * m / (ms * 1e-3) / 1e6,
                         "leaves": nleaf, "stage_ms": stg, "rooflines": roofs}
+    # the same density on adaptive leaves (levels 6-10, refined towards a circle)
+    lv, lx, ly = W.graded_leaves(centre=(0.5, 0.5), radius=0.3, lo=6, hi=10)
+    cells = W.leaf_cell_centres(lv, lx, ly)
+    Ba = d(sum(np.exp(-((cells[:, 0] - mu[k, 0]) ** 2 + (cells[:, 1] - mu[k, 1]) ** 2) / (2 * sg[k] ** 2))
+               for k in range(8)))
+    Va = torch.empty_like(Ba)
+    ctx = yk.yk_create(fmm_tol=1e-10)
+    try:
+        root = (0.0, 0.0, 1.0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        yk.yk_box_potential_adaptive(ctx, root, lv, lx, ly, Ba, alpha, Va)   # tables and the tree
+        torch.cuda.synchronize()
+        first_a = (time.perf_counter() - t0) * 1e3
+        for _ in range(args.warmup):
+            yk.yk_box_potential_adaptive(ctx, root, lv, lx, ly, Ba, alpha, Va)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(args.steps):
+            yk.yk_box_potential_adaptive(ctx, root, lv, lx, ly, Ba, alpha, Va)
+        e1.record()
+        torch.cuda.synchronize()
+        ms_a = e0.elapsed_time(e1) / args.steps
+        yk.yk_timing_enable(ctx, True)
+        yk.yk_timing_read(ctx, reset=True)
+        for _ in range(args.steps):
+            yk.yk_box_potential_adaptive(ctx, root, lv, lx, ly, Ba, alpha, Va)
+        stg_a = {k: v[0] / args.steps for k, v in yk.yk_timing_read(ctx, reset=True).items() if v[1]}
+        yk.yk_timing_enable(ctx, False)
+    finally:
+        yk.yk_destroy(ctx)
+    out["adaptive_potential"] = {"ms": ms_a, "first_call_ms": first_a, "leaves": int(lv.size),
+                                 "cells": int(cells.shape[0]), "levels": [int(lv.min()), int(lv.max())],
+                                 "mcells_per_s": cells.shape[0] / (ms_a * 1e-3) / 1e6, "stage_ms": stg_a}
     bdy = yk.Boundary.from_workload(b)
     f = d(cfg["f_bnd"])
     reg_h = b.region(vol)
@@ -510,7 +544,9 @@ def box_code_bench(args, yk, torch, W):
     inside = reg_h < 0
     out["box_vs_lattice_max_diff_inside"] = float(np.max(np.abs(finals["box_code"] - finals["lattice"])[inside]))
     out["workload"] = (f"{m}^2 cell grid of [-1/32, 1+1/32]^2, alpha=sqrt(1e-3); potential of a mixture of 8 "
-                       f"Gaussians ({nleaf} leaves of 4x4 cells); backward-Euler grid steps (dt=1e-3, u=0 at "
+                       f"Gaussians ({nleaf} leaves of 4x4 cells), and of the same density on {lv.size} adaptive "
+                       f"leaves of levels 6-10 of the unit square refined towards the circle of radius 0.3 about "
+                       f"its centre; backward-Euler grid steps (dt=1e-3, u=0 at "
                        f"t=0) on the time-stepping geometry (outer circle + 10 ellipses x 2048 nodes), GMRES "
                        f"tol 1e-10, averages over steps 2-{max(4, args.heat_steps // 5)}")
     return out

@@ -299,6 +299,47 @@ def adaptive_cells(target, density, max_level=16, refine=None):
     return np.concatenate(ox), np.concatenate(oy), np.concatenate(oh)
 
 
+def graded_leaves(centre=(0.5, 0.5), radius=0.3, lo=6, hi=10, K=2.0):
+    """Leaves (level, ix, iy) of a quadtree over the unit square refined towards
+    a circle: a box of level l splits while l < lo, or while l < hi and its
+    distance to the circle is below K times its side.  With K >= sqrt(2) two
+    touching leaves differ by at most one level (a split box of level l + 1
+    touching a leaf of level l would bring the circle within K/2 + sqrt(2)/2
+    sides of level l of the leaf), so the set is 2:1 balanced."""
+    cx, cy = centre
+    ix, iy = np.zeros(1, dtype=np.int64), np.zeros(1, dtype=np.int64)
+    out_l, out_x, out_y = [], [], []
+    for level in range(hi + 1):
+        s = 2.0 ** -level
+        x0, y0 = ix * s, iy * s
+        dx = np.maximum(np.maximum(x0 - cx, cx - (x0 + s)), 0.0)
+        dy = np.maximum(np.maximum(y0 - cy, cy - (y0 + s)), 0.0)
+        dmin = np.hypot(dx, dy)
+        dmax = np.hypot(np.maximum(np.abs(x0 - cx), np.abs(x0 + s - cx)),
+                        np.maximum(np.abs(y0 - cy), np.abs(y0 + s - cy)))
+        dist = np.where(radius < dmin, dmin - radius, np.where(radius > dmax, radius - dmax, 0.0))
+        split = (level < lo) | ((level < hi) & (dist < K * s))
+        out_l.append(np.full(int((~split).sum()), level, dtype=np.int32))
+        out_x.append(ix[~split].astype(np.int32))
+        out_y.append(iy[~split].astype(np.int32))
+        sx, sy = ix[split], iy[split]
+        ix = np.concatenate([2 * sx, 2 * sx + 1, 2 * sx, 2 * sx + 1])
+        iy = np.concatenate([2 * sy, 2 * sy, 2 * sy + 1, 2 * sy + 1])
+        if ix.size == 0:
+            break
+    return np.concatenate(out_l), np.concatenate(out_x), np.concatenate(out_y)
+
+
+def leaf_cell_centres(level, ix, iy):
+    """The 16 cell centres of every leaf (cell t = jj 4 + ii), [n_leaves * 16][2]."""
+    s = 2.0 ** -level.astype(np.float64)
+    t = np.arange(16)
+    u, v = (t & 3) + 0.5, (t >> 2) + 0.5
+    x = (ix[:, None] + u[None, :] / 4.0) * s[:, None]
+    y = (iy[:, None] + v[None, :] / 4.0) * s[:, None]
+    return np.stack([x.ravel(), y.ravel()], axis=1)
+
+
 def config_c4(n_vol=1 << 24, n_holes=20, n_nodes=8192, alpha=1e-3, seed=4, n_gauss=8):
     """Large adaptive set: the centres of about n_vol square cells of an
     adaptive quadtree over the unit square, refined where a mixture of n_gauss
