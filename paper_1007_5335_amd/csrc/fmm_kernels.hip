@@ -2205,38 +2205,48 @@ __global__ __launch_bounds__(64) void k_ad_m2p(
         rn[st] = (mask >> st) & 1 ? lrange[li * 6 + 2 * st + 1] - rs[st] : 0;
         ntot += rn[st];
     }
-    for (int k = threadIdx.x; k < ntot; k += 64) {
-        int t = -1, r = k;
-        for (int st = 0; st < 3; ++st) {
-            if (t < 0 && r < rn[st]) t = rs[st] + r;
-            r -= rn[st];
-        }
-        const double x = px[t], y = py[t];
+    // a leaf with few targets (at most 16 or 32) splits its W list among 4 or
+    // 2 lane groups, whose partial sums meet in a fixed shuffle order
+    const int G = ntot <= 16 ? 4 : ntot <= 32 ? 2 : 1, T = 64 / G;
+    const int g = threadIdx.x / T, kl = threadIdx.x - g * T;
+    for (int kb = 0; kb < ntot; kb += T) {
+        const int k = kb + kl;
+        int t = -1;
         double acc = 0.0;
-        for (int w = w0; w < w1; ++w) {
-            const int32_t d = wl[w];
-            const double *Md = M + (int64_t)d * Pp;
-            const double *ri = rI + (int64_t)blevel[d] * (p + 3);
-            const double wx = (x - bcx[d]) * inv_alpha, wy = (y - bcy[d]) * inv_alpha;
-            const double rho = sqrt(wx * wx + wy * wy), ir = 1.0 / rho;
-            if (rho > kFarRho) continue;          // below 1e-250 of the box's sources
-            const double c = wx * ir, sn = wy * ir;
-            const double k0v = k0(rho);
-            double rk = k1(rho) / k0v;            // K_1 / K_0
-            double T = ri[0] * k0v;               // I_0(R) K_0(rho)
-            double sum = Md[0] * T;
-            double er = c, ei = sn;               // e^{i n theta}
-            for (int n = 1; n <= p; ++n) {
-                T *= ri[n] * rk;                  // I_n(R) K_n(rho)
-                sum += 2.0 * T * (Md[2 * n - 1] * er - Md[2 * n] * ei);
-                rk = 1.0 / rk + 2.0 * n * ir;     // K_{n+1} / K_n
-                const double nr = er * c - ei * sn;
-                ei = er * sn + ei * c;
-                er = nr;
+        if (k < ntot) {
+            int r = k;
+            for (int st = 0; st < 3; ++st) {
+                if (t < 0 && r < rn[st]) t = rs[st] + r;
+                r -= rn[st];
             }
-            acc += sum;
+            const double x = px[t], y = py[t];
+            for (int w = w0 + g; w < w1; w += G) {
+                const int32_t d = wl[w];
+                const double *Md = M + (int64_t)d * Pp;
+                const double *ri = rI + (int64_t)blevel[d] * (p + 3);
+                const double wx = (x - bcx[d]) * inv_alpha, wy = (y - bcy[d]) * inv_alpha;
+                const double rho = sqrt(wx * wx + wy * wy), ir = 1.0 / rho;
+                if (rho > kFarRho) continue;          // below 1e-250 of the box's sources
+                const double c = wx * ir, sn = wy * ir;
+                const double k0v = k0(rho);
+                double rk = k1(rho) / k0v;            // K_1 / K_0
+                double T0 = ri[0] * k0v;              // I_0(R) K_0(rho)
+                double sum = Md[0] * T0;
+                double er = c, ei = sn;               // e^{i n theta}
+                for (int n = 1; n <= p; ++n) {
+                    T0 *= ri[n] * rk;                 // I_n(R) K_n(rho)
+                    sum += 2.0 * T0 * (Md[2 * n - 1] * er - Md[2 * n] * ei);
+                    rk = 1.0 / rk + 2.0 * n * ir;     // K_{n+1} / K_n
+                    const double nr = er * c - ei * sn;
+                    ei = er * sn + ei * c;
+                    er = nr;
+                }
+                acc += sum;
+            }
         }
-        outs[t] += acc * kInv2Pi;
+        if (G == 4) acc += __shfl_xor(acc, 16, 64);
+        if (G >= 2) acc += __shfl_xor(acc, 32, 64);
+        if (t >= 0 && g == 0) outs[t] += acc * kInv2Pi;
     }
 }
 
