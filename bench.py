@@ -304,7 +304,34 @@ def oracle_baseline(args, res, idx):
                        "pairs_per_s": len(sub1) * n_src / t1, "sample": f"{len(sub1)} of the sampled targets"}
     if not args.no_cpu_steps:
         cpu["oracle_steps"] = oracle_step_timings(oracle)
+        try:
+            cpu["c4_direct"] = oracle_c4_rate(oracle)
+        except (MemoryError, RuntimeError, ValueError) as e:   # reported, not fatal
+            cpu["c4_direct"] = {"error": repr(e)}
     return err, cpu
+
+
+def oracle_c4_rate(oracle):
+    """Direct-sum throughput of the oracle on the large clustered set: one
+    sampled target against all its charges and dipoles (the set's generation
+    is not timed).  The oracle hands targets to its threads in chunks of 16,
+    so one target runs on one core."""
+    import workloads as W
+    c = W.config_c4()
+    b = c["bnd"]
+    rng = np.random.default_rng(4)
+    n_vol = c["vol"].shape[0]
+    nt = 1
+    tgt = c["vol"][rng.integers(0, n_vol, nt)]
+    q = rng.uniform(0.5, 1.5, n_vol) * c["vol_w"]
+    dip = rng.standard_normal(b.n) * 1e-3
+    t0 = time.perf_counter()
+    oracle.volume_sum(c["vol"], q, c["alpha"], tgt_xy=tgt)
+    oracle.dl_sum(b.xy, b.normal, dip, c["alpha"], tgt)
+    t = time.perf_counter() - t0
+    n_src = n_vol + b.n
+    return {"targets": nt, "cores": 1, "sources": int(n_src), "s": t, "pairs_per_s": nt * n_src / t,
+            "full_pass_s_extrapolated_one_core": t * n_src / nt}
 
 
 def oracle_step_timings(oracle):
